@@ -1,0 +1,258 @@
+"""Model description and the semi-implicit stochastic time step (oracle; tests only).
+
+A model is a set of real fields phi_f on a periodic lattice, each obeying
+(Sec. "What cuPSS calculates", eq:basereal and eq:basefourier)
+
+    d/dt phi_f = L_f(q) phi_f + sum_t M_t(q) F[ prod_k u_{g_k}^{p_k} ] + noise_f
+
+where L_f is the implicit self-linear operator, each explicit term t has an
+operator M_t acting on the whole product (the paragraph on explicit terms in
+Sec. "Writing models"), and the noise has Fourier variance 2 D_f(q)
+(eq:noise_eq; Sec. "Adding noise").
+
+One step from phi^n to phi^{n+1} follows the six-step list after
+eq:timeupdate:
+
+1. (intermediate fields: none in this oracle model; every factor is a field)
+2. de-alias each factor field according to the highest-order term it enters
+   (Sec. "De-aliasing");
+3. transform the de-aliased factors to real space and multiply;
+4. transform each product back to Fourier space;
+5. draw Fourier-space Gaussian noise for every noisy field and scale it;
+6. advance every dynamic field with eq:timeupdate,
+       phi^{n+1} = (phi^n + dt sum_t M_t N_t + sqrt(dt) eta) / (1 - dt L(q)).
+
+Readings of points the paper leaves open:
+
+* Sign convention of terms: every term, implicit or explicit, is written on
+  the right-hand side of d/dt phi (eq:basereal).  The equation-string form
+  "dt phi + lhs = rhs" of Sec. "Writing models" maps to implicit operators
+  equal to minus the lhs prefactor.
+* An explicit term with a single factor of power 1 is linear; it needs neither
+  de-aliasing nor a real-space round trip, so its Fourier value is the
+  factor's own spectrum (the round trip is the identity).
+* Multi-field update order: all explicit terms are evaluated from the step-n
+  state, then every field is advanced (Jacobi), as the list orders
+  "calculate each N_ij" before "advance each field".
+* Noise normalisation (eq:noise_eq uses continuum delta functions): lattice
+  white noise with <xi_x xi_x'> = delta_xx'/dV, so the Fourier amplitude of the
+  increment is sigma(q) xi_hat(k) with sigma = sqrt(2 D(q) dt / dV) and
+  <|xi_hat|^2> = N; the sqrt(dt) of eq:timeupdate is inside sigma.
+* Real fields: xi_hat is Hermitian.  A mode k and its partner -k share one
+  Philox draw, keyed by the smaller of their linear indices c(k); the owner
+  (linear index == c) takes sqrt(N/2)(g1 + i g2), the partner its conjugate,
+  and a self-conjugate mode takes sqrt(N) g1.  The Philox counter is
+  (c(k), step, field, 0) with the 64-bit seed as key.
+* Real space is the real part of the inverse transform.
+* Initial fields "uniform in [lo, hi)" take u0 of Philox counter
+  (site, 0, field, 1) and set phi = float32(lo + (hi - lo) u0), i.e. the FP64
+  value rounded once to binary32, so FP32 and FP64 runs start identically.
+"""
+
+import numpy as np
+
+from . import philox
+from .spectral import (Lattice, Mono, fftn, ifftn, DEALIAS_TWO_THIRDS,
+                       DEALIAS_PAPER_ORDER, DEALIAS_NONE, SHAPE_RADIAL)
+
+
+class Term:
+    def __init__(self, target, implicit, op, factors):
+        self.target = int(target)
+        self.implicit = bool(implicit)
+        self.op = [m if isinstance(m, Mono) else Mono(*m) for m in op]
+        self.factors = [(int(g), int(p)) for g, p in factors]
+
+    @property
+    def order(self):
+        return sum(p for _, p in self.factors)
+
+    @property
+    def is_direct(self):
+        """Single factor to the first power: applied directly in Fourier space."""
+        return len(self.factors) == 1 and self.factors[0][1] == 1
+
+
+class Model:
+    """Fields, terms and noise on a lattice; state kept as full complex spectra."""
+
+    def __init__(self, lattice, dt, seed=0, dealias=DEALIAS_TWO_THIRDS,
+                 shape=SHAPE_RADIAL):
+        self.lat = lattice
+        self.dt = float(dt)
+        self.seed = int(seed)
+        self.dealias = dealias
+        self.mask_shape = shape
+        self.names = []
+        self.terms = []
+        self.noise = {}
+        self.state = []
+        self.step_index = 0
+        self._cache = None
+
+    # -- construction ---------------------------------------------------
+    def add_field(self, name):
+        self.names.append(name)
+        self.state.append(np.zeros(self.lat.shape, dtype=np.complex128))
+        self._cache = None
+        return len(self.names) - 1
+
+    def add_term(self, target, op, factors, implicit=False):
+        t = Term(target, implicit, op, factors)
+        if implicit and not (t.factors == [(t.target, 1)]):
+            raise ValueError("an implicit term must be linear in its own field")
+        self.terms.append(t)
+        self._cache = None
+        return len(self.terms) - 1
+
+    def set_noise(self, field, op):
+        self.noise[int(field)] = [m if isinstance(m, Mono) else Mono(*m) for m in op]
+        self._cache = None
+
+    # -- state ----------------------------------------------------------
+    def set_real(self, field, values):
+        values = np.asarray(values, dtype=np.float64).reshape(self.lat.shape)
+        self.state[field] = fftn(values.astype(np.complex128))
+
+    def init_uniform(self, field, lo, hi):
+        """phi_0 = float32(lo + (hi - lo) u0) at every site (see module notes)."""
+        u0 = philox.uniform_site(self.lat.lin, field, self.seed)
+        vals = (lo + (hi - lo) * u0).astype(np.float32).astype(np.float64)
+        self.set_real(field, vals)
+        return vals
+
+    def real(self, field):
+        return ifftn(self.state[field]).real
+
+    # -- per-plan quantities (computed once, like a plan) ----------------
+    def _prepare(self):
+        if self._cache is not None:
+            return self._cache
+        lat = self.lat
+        nf = len(self.names)
+        lam = [np.zeros(lat.shape, dtype=np.complex128) for _ in range(nf)]
+        for t in self.terms:
+            if t.implicit:
+                lam[t.target] = lam[t.target] + lat.operator(t.op)
+        denom = [1.0 - self.dt * l for l in lam]
+        ops = [lat.operator(t.op) for t in self.terms]
+        # highest order among the nonlinear terms that contain each field
+        order = [0] * nf
+        for t in self.terms:
+            if t.implicit or t.is_direct:
+                continue
+            for g, _ in t.factors:
+                order[g] = max(order[g], t.order)
+        masks = []
+        for g in range(nf):
+            if order[g] == 0 or self.dealias == DEALIAS_NONE:
+                masks.append(None)
+            elif self.dealias == DEALIAS_TWO_THIRDS:
+                masks.append(lat.mask(2, 3, self.mask_shape))
+            elif self.dealias == DEALIAS_PAPER_ORDER:
+                masks.append(lat.mask(2, order[g] + 1, self.mask_shape))
+            else:
+                raise ValueError("unknown dealias rule")
+        sigma = {}
+        for f, op in self.noise.items():
+            D = lat.operator(op)
+            if np.any(np.abs(D.imag) > 0) or np.any(D.real < 0):
+                raise ValueError("noise operator must be real and non-negative")
+            sigma[f] = np.sqrt(2.0 * D.real * self.dt / lat.dV)
+        self._cache = dict(denom=denom, ops=ops, masks=masks, sigma=sigma)
+        return self._cache
+
+    # -- noise (step 5) ---------------------------------------------------
+    def noise_hat(self, field, step):
+        """Unit-variance Hermitian white noise xi_hat(k) for (step, field)."""
+        lat = self.lat
+        c = np.minimum(lat.lin, lat.lin_neg)
+        g1, g2 = philox.gaussian_pair(c, step, field, self.seed)
+        own = lat.lin == c
+        selfc = lat.lin == lat.lin_neg
+        half = np.sqrt(lat.N / 2.0)
+        xi = np.where(own, half * (g1 + 1j * g2), half * (g1 - 1j * g2))
+        xi = np.where(selfc, np.sqrt(float(lat.N)) * g1 + 0j, xi)
+        return xi
+
+    # -- one step ----------------------------------------------------------
+    def nonlinear_hat(self, t_index):
+        """Fourier transform of term t's product of de-aliased factors (steps 2-4)."""
+        c = self._prepare()
+        t = self.terms[t_index]
+        if t.is_direct:
+            return self.state[t.factors[0][0]]
+        prod = np.ones(self.lat.shape, dtype=np.float64)
+        for g, p in t.factors:
+            spec = self.state[g]
+            if c["masks"][g] is not None:
+                spec = spec * c["masks"][g]
+            u = ifftn(spec).real
+            prod = prod * u ** p
+        return fftn(prod.astype(np.complex128))
+
+    def step(self, nsteps=1):
+        c = self._prepare()
+        for _ in range(int(nsteps)):
+            n = self.step_index
+            rhs = [np.zeros(self.lat.shape, dtype=np.complex128) for _ in self.names]
+            for i, t in enumerate(self.terms):
+                if t.implicit:
+                    continue
+                rhs[t.target] += c["ops"][i] * self.nonlinear_hat(i)
+            new = []
+            for f in range(len(self.names)):
+                acc = self.state[f] + self.dt * rhs[f]
+                if f in c["sigma"]:
+                    acc = acc + c["sigma"][f] * self.noise_hat(f, n)
+                new.append(acc / c["denom"][f])
+            self.state = new
+            self.step_index += 1
+
+    # -- convenience ------------------------------------------------------
+    def copy(self):
+        m = Model(self.lat, self.dt, self.seed, self.dealias, self.mask_shape)
+        m.names = list(self.names)
+        m.terms = list(self.terms)
+        m.noise = dict(self.noise)
+        m.state = [s.copy() for s in self.state]
+        m.step_index = self.step_index
+        return m
+
+
+def model_b(lattice, dt, a=-1.0, b=1.0, k=1.0, D=0.01, seed=1,
+            dealias=DEALIAS_TWO_THIRDS, shape=SHAPE_RADIAL):
+    """Model B (Cahn-Hilliard with conserved noise), Sec. "Example":
+    d/dt phi_hat = -q^2 (a + k q^2) phi_hat - b q^2 F[u^3] + conserved noise D q^2.
+    """
+    m = Model(lattice, dt, seed=seed, dealias=dealias, shape=shape)
+    f = m.add_field("phi")
+    m.add_term(f, [Mono(-a, q2=1), Mono(-k, q2=2)], [(f, 1)], implicit=True)
+    m.add_term(f, [Mono(-b, q2=1)], [(f, 3)])
+    if D:
+        m.set_noise(f, [Mono(D, q2=1)])
+    return m
+
+
+def two_field_3d(lattice, dt, a=-1.0, b=1.0, k=1.0, c=-0.5, g=0.3, D=0.005,
+                 seed=1, dealias=DEALIAS_TWO_THIRDS, shape=SHAPE_RADIAL):
+    """Model B field phi coupled to a Model A field psi.
+
+    d/dt phi = lap(a phi + b phi^3 - k lap phi + (g/2) phi psi^2) + conserved noise D q^2
+    d/dt psi = -(c psi + psi^3 - lap psi) - g phi psi + noise D
+    (the literal coupling reading: (g/2) phi psi^2 inside phi's chemical
+    potential and -g phi psi in psi's equation; no single free energy gives both).
+    """
+    m = Model(lattice, dt, seed=seed, dealias=dealias, shape=shape)
+    phi = m.add_field("phi")
+    psi = m.add_field("psi")
+    m.add_term(phi, [Mono(-a, q2=1), Mono(-k, q2=2)], [(phi, 1)], implicit=True)
+    m.add_term(phi, [Mono(-b, q2=1)], [(phi, 3)])
+    m.add_term(phi, [Mono(-0.5 * g, q2=1)], [(phi, 1), (psi, 2)])
+    m.add_term(psi, [Mono(-c), Mono(-1.0, q2=1)], [(psi, 1)], implicit=True)
+    m.add_term(psi, [Mono(-1.0)], [(psi, 3)])
+    m.add_term(psi, [Mono(-g)], [(phi, 1), (psi, 1)])
+    if D:
+        m.set_noise(phi, [Mono(D, q2=1)])
+        m.set_noise(psi, [Mono(D)])
+    return m

@@ -1,0 +1,36 @@
+"""Pins of the oracle's observables (CPU only): a single Fourier mode has its
+whole structure factor in one shell and a domain length of one wavelength;
+the mass is the spatial sum."""
+
+import numpy as np
+
+from oracle import observables as ob
+from oracle.spectral import Lattice, fftn
+
+
+def test_single_mode_shell_and_length():
+    lat = Lattice(64, 64, 1, dx=0.5, dy=0.5)
+    x = np.arange(64) * 0.5
+    k0 = 6
+    f = np.broadcast_to(np.cos(2 * np.pi * k0 * x / 32.0), lat.shape)
+    fh = fftn(f + 0j)
+    sj, nj = ob.shell_average(lat, ob.structure_factor(lat, fh))
+    assert np.argmax(sj * nj) + 1 == k0
+    assert np.isclose(np.sum(sj * nj), np.sum(ob.structure_factor(lat, fh)))
+    assert np.isclose(ob.domain_length(lat, fh), 32.0 / k0)
+
+
+def test_mass_is_sum():
+    lat = Lattice(8, 16)
+    rng = np.random.default_rng(0)
+    f = rng.standard_normal(lat.shape)
+    assert np.isclose(ob.mass(fftn(f + 0j)), f.sum())
+
+
+def test_shell_populations():
+    lat = Lattice(32, 32)
+    j = ob.shell_index(lat)
+    # shell 1 holds exactly the 4 nearest modes plus the 4 diagonal ones with |k|=sqrt2 -> round 1
+    assert np.sum(j == 1) == 8
+    _, nj = ob.shell_average(lat, np.ones(lat.shape))
+    assert nj.sum() == np.sum((j >= 1) & (j < 16))
