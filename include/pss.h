@@ -1,0 +1,243 @@
+/*
+ * pss.h -- C interface of the MI355X pseudo-spectral stochastic-PDE stepper.
+ *
+ * The library advances real fields phi_f on a periodic 2D or 3D lattice with
+ * the semi-implicit Euler-Maruyama scheme of cuPSS (arXiv 2405.02410,
+ * eq:timeupdate and the six-step list that follows it):
+ *
+ *   phi_f(t+dt) = ( phi_f + dt * sum_t M_t(q) N_t + sigma_f(q) xi_f ) / (1 - dt L_f(q))
+ *
+ * where L_f is the sum of the field's implicit operators, each explicit term t
+ * contributes M_t(q) times the Fourier transform of a product of de-aliased
+ * fields evaluated in real space (eq:basereal, eq:nonlin_general), and the
+ * noise has Fourier variance 2 D_f(q) (eq:noise_eq, Sec. "Adding noise").
+ *
+ * The calls follow the paper's statement of a problem (Sec. "Writing
+ * models"): create a system from sizes, spacings and dt; declare fields; add
+ * implicit and explicit terms; add noise; set initial conditions; evolve.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every function returns a pss_status: PSS_OK (0) or a negative code.  No
+ *   exception or abort crosses the interface.  pss_last_error() returns a
+ *   thread-local message describing the most recent failure on the calling
+ *   thread.
+ * - Sizes are given as n[3] = {Nx, Ny, Nz} and dx[3] = {dx, dy, dz}; a 2D
+ *   lattice ignores n[2] and dx[2].  Every N_i must be a power of two in
+ *   [8, 4096]; other sizes return PSS_E_UNSUPPORTED.
+ * - Real-space arrays are float32, x fastest: index (z*Ny + y)*Nx + x.
+ * - Fourier convention: forward transform unnormalised, inverse with 1/N.
+ *   Mode indices are signed integers in FFT order with the Nyquist index read
+ *   as -N_i/2; q_i = 2 pi k_i / (N_i dx_i).
+ * - Terms are written on the right-hand side of d/dt phi.  The paper's
+ *   equation string "dt phi + lhs = rhs" therefore maps to implicit operators
+ *   equal to minus the lhs prefactor (Sec. "Writing models").
+ * - The context owns every device buffer it allocates.  Host arrays passed in
+ *   are copied before the call returns; device pointers passed with
+ *   on_device = 1 must stay valid until the call returns.
+ * - pss_step is asynchronous on the context's stream; device faults surface
+ *   as PSS_E_HIP at the next synchronising call (pss_sync, downloads, saves).
+ * - Structural calls (declare, term_add, noise_set, dealias_set) are only
+ *   accepted before the device plan is built (first upload, init or step);
+ *   afterwards they return PSS_E_STATE.  Coefficients can still be changed
+ *   with pss_term_set_coef.
+ * - A context is not thread-safe: one thread at a time.
+ */
+#ifndef PSS_H
+#define PSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pss_ctx pss_ctx;
+typedef int32_t pss_status;
+
+#define PSS_OK 0
+#define PSS_E_INVAL (-1)       /* bad argument (null pointer, index, size) */
+#define PSS_E_UNSUPPORTED (-2) /* valid request outside what is implemented */
+#define PSS_E_NOMEM (-3)       /* device allocation failed */
+#define PSS_E_HIP (-4)         /* a HIP runtime call or kernel failed */
+#define PSS_E_STATE (-5)       /* call not allowed in the current state */
+#define PSS_E_UNSTABLE (-6)    /* 1 - dt*L(q) has real part <= 0 on some mode */
+
+/* De-aliasing (Sec. "De-aliasing").  A factor entering nonlinear terms of
+ * highest order n has its modes beyond a fraction f of the Nyquist index
+ * zeroed before the real-space product: TWO_THIRDS uses f = 2/3 for every
+ * factor, PAPER_ORDER uses f = 2/(n+1) (the paper's |q| > 2 pi/((n+1) dx)
+ * rule), NONE keeps every mode.  RADIAL keeps sum_i (k_i/(N_i/2))^2 < f^2,
+ * PER_AXIS keeps |k_i|/(N_i/2) < f on every axis.  Modes on the cutoff are
+ * zeroed. */
+#define PSS_DEALIAS_TWO_THIRDS 0
+#define PSS_DEALIAS_PAPER_ORDER 1
+#define PSS_DEALIAS_NONE 2
+#define PSS_SHAPE_RADIAL 0
+#define PSS_SHAPE_PER_AXIS 1
+
+/* One operator monomial (Sec. "Reserved keywords"):
+ *   coef * (q^2)^q2_pow * |q|^(-invq_pow) * (i qx)^iq_pow[0] (i qy)^iq_pow[1] (i qz)^iq_pow[2]
+ * q^2 is -laplacian, i q_i is d/dx_i (zero on the Nyquist plane of axis i),
+ * 1/|q| is zero at q = 0.  An operator is a sum of monomials.  All powers
+ * must lie in [0, 8]. */
+typedef struct {
+    double coef;
+    int32_t q2_pow;
+    int32_t invq_pow;
+    int32_t iq_pow[3];
+} pss_qmono;
+
+/* ---- lattice ----------------------------------------------------------- */
+
+/* Create a lattice context (Sec. "Writing models", the system constructor).
+ * ndim: 2 or 3.  n, dx: see conventions.  dt > 0.  Touches no device: the
+ * device plan is built on the first upload, init or step.
+ * Errors: PSS_E_INVAL (null out, dt <= 0, dx <= 0), PSS_E_UNSUPPORTED (ndim
+ * not 2 or 3, a size that is not a power of two in [8, 4096]). */
+pss_status pss_lattice_create(pss_ctx **out, int32_t ndim, const int64_t n[3],
+                              const double dx[3], double dt);
+
+/* Release the context and every buffer it owns.  NULL is accepted. */
+pss_status pss_lattice_destroy(pss_ctx *ctx);
+
+/* ---- model ------------------------------------------------------------- */
+
+/* Declare a field (Sec. "Writing models", createField).  dynamic = 1 for a
+ * field with its own time derivative.  Intermediate fields defined by a
+ * linear equation (dynamic = 0) return PSS_E_UNSUPPORTED.  Names must be
+ * unique, 1..63 characters.  At most 4 fields.  *field_id receives the index
+ * (0, 1, ...). */
+pss_status pss_field_declare(pss_ctx *ctx, const char *name, int32_t dynamic,
+                             int32_t *field_id);
+
+/* Add a term  op(q) * prod_j field_j^power_j  to d/dt of target_field
+ * (eq:basereal; the operator acts on the whole product, Sec. "Writing
+ * models").  implicit = 1 requires exactly one factor, the target field to
+ * the power 1 (implicit terms must be linear in their field); its operator is
+ * added to L(q).  Explicit terms: 1 to 4 factors with powers 1..8; a single
+ * factor of power 1 is applied directly in Fourier space, any other term is
+ * formed in real space from de-aliased factors.  At most 8 monomials per
+ * operator, 16 terms in total.  *term_id (may be NULL) receives the index. */
+pss_status pss_term_add(pss_ctx *ctx, int32_t target_field, int32_t implicit,
+                        const pss_qmono *op, int32_t n_mono,
+                        const int32_t *factor_fields, const int32_t *factor_powers,
+                        int32_t n_factors, int32_t *term_id);
+
+/* Change the coefficient of monomial `mono` of term `term_id`.  Allowed at
+ * any time; takes effect at the next step (stream-ordered).  Re-checks
+ * stability: PSS_E_UNSTABLE leaves the old value in place. */
+pss_status pss_term_set_coef(pss_ctx *ctx, int32_t term_id, int32_t mono, double coef);
+
+/* Add noise to a field (Sec. "Adding noise"): D(q) is a sum of monomials in
+ * q^2 and 1/|q| only (no i q_i), real and >= 0 on every mode (checked when the
+ * plan is built; PSS_E_INVAL otherwise).  The Fourier noise amplitude is
+ * sigma(q) = sqrt(2 D(q) dt / dV) on unit white noise. */
+pss_status pss_noise_set(pss_ctx *ctx, int32_t field, const pss_qmono *D_of_q,
+                         int32_t n_mono);
+
+/* 64-bit seed of the Philox4x32-10 noise (Salmon et al. SC'11).  The noise of
+ * mode k of field f at step n is keyed by counter (c(k), n, f, 0) with key
+ * (low, high) words of the seed, where c(k) = min(L(k), L(-k)) and L is the
+ * linear mode index (z*Ny + y)*Nx + x of the full spectrum.  Default 0. */
+pss_status pss_seed_set(pss_ctx *ctx, uint64_t seed);
+
+/* De-aliasing rule and shape (defaults TWO_THIRDS, RADIAL). */
+pss_status pss_dealias_set(pss_ctx *ctx, int32_t rule, int32_t shape);
+
+/* Run on this hipStream_t (NULL selects the context's own stream).  The
+ * caller keeps the stream alive while the context uses it.  The legacy null
+ * stream cannot host graph capture; pass a created stream. */
+pss_status pss_stream_set(pss_ctx *ctx, void *hip_stream);
+
+/* Check the model without touching the device: implicit terms, noise
+ * operators, and stability Re(1 - dt L(q)) > 0 on every mode. */
+pss_status pss_validate(pss_ctx *ctx);
+
+/* ---- state ------------------------------------------------------------- */
+
+/* Set field from a real-space float32 array (host, or device if on_device).
+ * Synchronous: returns after the forward transform has completed. */
+pss_status pss_field_upload(pss_ctx *ctx, int32_t field, const float *real_xyz,
+                            int32_t on_device);
+
+/* Set field to float32(lo + (hi - lo) u) at every site, u the first uniform of
+ * Philox counter (site, 0, field, 1) with the context seed; u is an odd
+ * multiple of 2^-24 in (0, 1).  Synchronous. */
+pss_status pss_field_init_uniform(pss_ctx *ctx, int32_t field, double lo, double hi);
+
+/* Write the real-space field (inverse transform of the full state, no
+ * de-aliasing) to a float32 array.  Synchronous. */
+pss_status pss_field_download(pss_ctx *ctx, int32_t field, float *real_xyz,
+                              int32_t on_device);
+
+/* Write the Fourier state of a field as the half spectrum: complex float32
+ * pairs (re, im) of modes kx = 0..Nx/2 for every (z, y), index
+ * ((z*Ny + y)*(Nx/2+1) + kx).  Synchronous. */
+pss_status pss_spectrum_download(pss_ctx *ctx, int32_t field, float *half_spectrum,
+                                 int32_t on_device);
+
+/* Advance nsteps time steps (eq:timeupdate).  nsteps = 0 is a no-op.
+ * Asynchronous on the context stream; replays captured HIP graphs of the
+ * step sequence. */
+pss_status pss_step(pss_ctx *ctx, int64_t nsteps);
+
+/* Number of steps taken since the plan was built (the noise step index). */
+pss_status pss_step_index(pss_ctx *ctx, int64_t *out);
+
+/* Wait for the context stream; reports asynchronous device failures. */
+pss_status pss_sync(pss_ctx *ctx);
+
+/* Bytes needed by pss_state_save. */
+pss_status pss_state_size(pss_ctx *ctx, size_t *bytes);
+
+/* Save / restore every field's Fourier state and the step index into a host
+ * buffer of pss_state_size bytes.  A restored run replays exactly, because
+ * the noise is keyed by (seed, step, mode).  Synchronous. */
+pss_status pss_state_save(pss_ctx *ctx, void *dst, size_t bytes);
+pss_status pss_state_load(pss_ctx *ctx, const void *src, size_t bytes);
+
+/* ---- reductions -------------------------------------------------------- */
+
+/* Mass sum_x phi(x) (= Re phi_hat(0)), in FP64.  Synchronous. */
+pss_status pss_mass(pss_ctx *ctx, int32_t field, double *mass);
+
+/* Shell-averaged structure factor S_j = mean over modes with
+ * round(|k|) = j of (dV/N)|phi_hat(k)|^2, j = 1 .. n_shells, n_shells =
+ * min_i(N_i)/2 - 1; counts[j-1] receives the shell population.  FP64
+ * accumulation on the device.  Synchronous. */
+pss_status pss_structure_factor(pss_ctx *ctx, int32_t field, double *S, int64_t *counts,
+                                int32_t n_shells);
+
+/* ---- utilities --------------------------------------------------------- */
+
+/* Philox4x32-10 words for counters (c0 + i, c1, c2, c3), i = 0..count-1, with
+ * key (k0, k1), written as 4*count uint32 to device memory `out_device` (the
+ * same device routine the noise uses).  Synchronous. */
+pss_status pss_util_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                           uint32_t k0, uint32_t k1, int64_t count, uint32_t *out_device);
+
+/* Benchmark helper: launch kernel `which` of one step `reps` times back to
+ * back on the context stream between two HIP events and return the mean
+ * time per launch in milliseconds.  which = 0 is the update kernel (the last
+ * axis: y in 2D, z in 3D), 1 the x (real-space product) kernel, 2 and 3 the
+ * inverse and forward y passes of 3D lattices.  Destroys the state's
+ * physical meaning; for timing only.  *name receives a static kernel name. */
+pss_status pss_time_kernel(pss_ctx *ctx, int32_t which, int32_t reps, double *ms_per_launch,
+                           const char **name);
+
+/* Per-launch algorithmic HBM bytes of kernel `which` (same numbering): the
+ * bytes each launch must read and write once at the current plan. */
+pss_status pss_kernel_bytes(pss_ctx *ctx, int32_t which, double *bytes);
+
+/* Number of kernels in one step (2 in 2D, 4 in 3D). */
+pss_status pss_kernels_per_step(pss_ctx *ctx, int32_t *count);
+
+const char *pss_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSS_H */

@@ -1,0 +1,305 @@
+"""MI355X pseudo-spectral stochastic-PDE stepper (cuPSS method, arXiv 2405.02410).
+
+Thin ctypes binding over the C interface in include/pss.h.  Every step of the
+hot path runs in the HIP kernels of libpss.so; this module only marshals
+arguments.  Device arrays may be passed as torch tensors (their data pointer
+is used); host arrays as numpy arrays.
+
+Terms follow the paper's form (eq:basereal): each term adds
+op(q) * prod_j field_j^p_j to d/dt of its target.  An operator is a list of
+monomials coef * (q^2)^q2 * |q|^-invq * prod_i (i q_i)^iq_i (Sec. "Reserved
+keywords").  Implicit terms (treated by the 1/(1 - dt L) factor of
+eq:timeupdate) must be linear in their own field.
+"""
+
+import ctypes
+import os
+from collections import namedtuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libpss.so")
+
+PSS_OK = 0
+ERRORS = {
+    -1: "PSS_E_INVAL",
+    -2: "PSS_E_UNSUPPORTED",
+    -3: "PSS_E_NOMEM",
+    -4: "PSS_E_HIP",
+    -5: "PSS_E_STATE",
+    -6: "PSS_E_UNSTABLE",
+}
+DEALIAS_TWO_THIRDS, DEALIAS_PAPER_ORDER, DEALIAS_NONE = 0, 1, 2
+SHAPE_RADIAL, SHAPE_PER_AXIS = 0, 1
+KERNEL_UPDATE, KERNEL_X = 0, 1
+
+
+class PssError(RuntimeError):
+    def __init__(self, code, msg):
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+        super().__init__(f"{self.name}: {msg}")
+
+
+class _QMono(ctypes.Structure):
+    _fields_ = [("coef", ctypes.c_double), ("q2_pow", ctypes.c_int32),
+                ("invq_pow", ctypes.c_int32), ("iq_pow", ctypes.c_int32 * 3)]
+
+
+Mono = namedtuple("Mono", ["coef", "q2", "invq", "iq"], defaults=(0, 0, (0, 0, 0)))
+
+_lib = None
+
+_SIGS = {
+    "pss_lattice_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                           ctypes.POINTER(ctypes.c_double), ctypes.c_double],
+    "pss_lattice_destroy": [ctypes.c_void_p],
+    "pss_field_declare": [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+    "pss_term_add": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_QMono), ctypes.c_int32,
+                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                     ctypes.POINTER(ctypes.c_int32)],
+    "pss_term_set_coef": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double],
+    "pss_noise_set": [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(_QMono), ctypes.c_int32],
+    "pss_seed_set": [ctypes.c_void_p, ctypes.c_uint64],
+    "pss_dealias_set": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32],
+    "pss_stream_set": [ctypes.c_void_p, ctypes.c_void_p],
+    "pss_validate": [ctypes.c_void_p],
+    "pss_field_upload": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32],
+    "pss_field_init_uniform": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_double],
+    "pss_field_download": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32],
+    "pss_spectrum_download": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32],
+    "pss_step": [ctypes.c_void_p, ctypes.c_int64],
+    "pss_step_index": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)],
+    "pss_sync": [ctypes.c_void_p],
+    "pss_state_size": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "pss_state_save": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t],
+    "pss_state_load": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t],
+    "pss_mass": [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
+    "pss_structure_factor": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32],
+    "pss_util_philox": [ctypes.c_uint32] * 6 + [ctypes.c_int64, ctypes.c_void_p],
+    "pss_time_kernel": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                        ctypes.POINTER(ctypes.c_char_p)],
+    "pss_kernel_bytes": [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
+    "pss_kernels_per_step": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)],
+}
+
+
+def lib():
+    """Load libpss.so (built by paper_2405_02410_amd.build); raise if missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is missing: build it with "
+                              "`python -m paper_2405_02410_amd.build` (hipcc, gfx950)")
+        L = ctypes.CDLL(_LIB_PATH)
+        for name, argt in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = argt
+            fn.restype = ctypes.c_int32
+        L.pss_last_error.argtypes = []
+        L.pss_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != PSS_OK:
+        raise PssError(code, lib().pss_last_error().decode())
+
+
+def _monos(op):
+    op = [m if isinstance(m, Mono) else Mono(*m) for m in op]
+    arr = (_QMono * len(op))()
+    for i, m in enumerate(op):
+        iq = tuple(m.iq) + (0,) * (3 - len(m.iq))
+        arr[i].coef = float(m.coef)
+        arr[i].q2_pow = int(m.q2)
+        arr[i].invq_pow = int(m.invq)
+        for k in range(3):
+            arr[i].iq_pow[k] = int(iq[k])
+    return arr, len(op)
+
+
+def _ptr(a):
+    """(address, on_device) of a torch tensor or numpy array of float32."""
+    if hasattr(a, "data_ptr"):
+        if a.dtype.__str__() != "torch.float32" or not a.is_contiguous():
+            raise TypeError("torch tensors must be contiguous float32")
+        return a.data_ptr(), 1 if a.is_cuda else 0
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a.ctypes.data, 0
+
+
+class Lattice:
+    """A periodic 2D or 3D lattice with fields, terms and noise (one context)."""
+
+    def __init__(self, n, dx=None, dt=0.01, seed=0, dealias=DEALIAS_TWO_THIRDS, shape=SHAPE_RADIAL):
+        n = tuple(int(v) for v in n)
+        self.ndim = len(n)
+        if self.ndim not in (2, 3):
+            raise PssError(-2, f"ndim must be 2 or 3 (got {self.ndim})")
+        dx = tuple(float(v) for v in (dx if dx is not None else (1.0,) * self.ndim))
+        n3 = (ctypes.c_int64 * 3)(*(n + (1,) * (3 - self.ndim)))
+        d3 = (ctypes.c_double * 3)(*(dx + (1.0,) * (3 - self.ndim)))
+        h = ctypes.c_void_p()
+        _check(lib().pss_lattice_create(ctypes.byref(h), self.ndim, n3, d3, float(dt)))
+        self._h = h
+        self.n = n
+        self.dx = dx
+        self.dt = float(dt)
+        self.shape = tuple(reversed(n))  # numpy order (z, y, x)
+        self.sites = int(np.prod(n))
+        self.names = []
+        _check(lib().pss_seed_set(self._h, int(seed) & 0xFFFFFFFFFFFFFFFF))
+        _check(lib().pss_dealias_set(self._h, int(dealias), int(shape)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pss_lattice_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- model ---------------------------------------------------------
+    def field(self, name, dynamic=True):
+        fid = ctypes.c_int32()
+        _check(lib().pss_field_declare(self._h, name.encode(), int(dynamic), ctypes.byref(fid)))
+        self.names.append(name)
+        return fid.value
+
+    def term(self, target, op, factors, implicit=False):
+        arr, nm = _monos(op)
+        ff = (ctypes.c_int32 * len(factors))(*[int(f) for f, _ in factors])
+        fp = (ctypes.c_int32 * len(factors))(*[int(p) for _, p in factors])
+        tid = ctypes.c_int32()
+        _check(lib().pss_term_add(self._h, int(target), int(implicit), arr, nm, ff, fp, len(factors),
+                                  ctypes.byref(tid)))
+        return tid.value
+
+    def set_coef(self, term, mono, coef):
+        _check(lib().pss_term_set_coef(self._h, int(term), int(mono), float(coef)))
+
+    def noise(self, field, op):
+        arr, nm = _monos(op)
+        _check(lib().pss_noise_set(self._h, int(field), arr, nm))
+
+    def seed(self, seed):
+        _check(lib().pss_seed_set(self._h, int(seed) & 0xFFFFFFFFFFFFFFFF))
+
+    def stream(self, hip_stream):
+        """Run on a hipStream_t given as an integer handle (torch: stream.cuda_stream)."""
+        _check(lib().pss_stream_set(self._h, ctypes.c_void_p(int(hip_stream) if hip_stream else 0)))
+
+    def validate(self):
+        _check(lib().pss_validate(self._h))
+
+    # -- state ---------------------------------------------------------
+    def upload(self, field, values):
+        if hasattr(values, "data_ptr"):
+            if values.numel() != self.sites:
+                raise ValueError("wrong number of sites")
+            p, dev = _ptr(values)
+            _check(lib().pss_field_upload(self._h, int(field), ctypes.c_void_p(p), dev))
+        else:
+            a = np.ascontiguousarray(values, dtype=np.float32).reshape(-1)
+            if a.size != self.sites:
+                raise ValueError("wrong number of sites")
+            _check(lib().pss_field_upload(self._h, int(field), a.ctypes.data_as(ctypes.c_void_p), 0))
+
+    def init_uniform(self, field, lo=-0.1, hi=0.1):
+        _check(lib().pss_field_init_uniform(self._h, int(field), float(lo), float(hi)))
+
+    def download(self, field, out=None):
+        """Real-space field as a numpy array (z, y, x), or into a float32 torch tensor."""
+        if out is not None and hasattr(out, "data_ptr"):
+            p, dev = _ptr(out)
+            _check(lib().pss_field_download(self._h, int(field), ctypes.c_void_p(p), dev))
+            return out
+        a = np.empty(self.shape, dtype=np.float32)
+        _check(lib().pss_field_download(self._h, int(field), a.ctypes.data_as(ctypes.c_void_p), 0))
+        return a
+
+    def spectrum(self, field):
+        """Half spectrum phi_hat(kx = 0..Nx/2) as complex64 array (z, y, kx)."""
+        nh = self.n[0] // 2 + 1
+        a = np.empty(self.shape[:-1] + (nh, 2), dtype=np.float32)
+        _check(lib().pss_spectrum_download(self._h, int(field), a.ctypes.data_as(ctypes.c_void_p), 0))
+        return a[..., 0] + 1j * a[..., 1]
+
+    def step(self, n=1):
+        _check(lib().pss_step(self._h, int(n)))
+
+    def sync(self):
+        _check(lib().pss_sync(self._h))
+
+    @property
+    def step_index(self):
+        v = ctypes.c_int64()
+        _check(lib().pss_step_index(self._h, ctypes.byref(v)))
+        return v.value
+
+    def save(self):
+        n = ctypes.c_size_t()
+        _check(lib().pss_state_size(self._h, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib().pss_state_save(self._h, buf, n.value))
+        return buf.raw
+
+    def load(self, blob):
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        _check(lib().pss_state_load(self._h, buf, len(blob)))
+
+    # -- reductions ----------------------------------------------------
+    def mass(self, field):
+        v = ctypes.c_double()
+        _check(lib().pss_mass(self._h, int(field), ctypes.byref(v)))
+        return v.value
+
+    def structure_factor(self, field):
+        ns = min(n for n in self.n) // 2 - 1
+        S = np.zeros(ns, dtype=np.float64)
+        cnt = np.zeros(ns, dtype=np.int64)
+        _check(lib().pss_structure_factor(self._h, int(field), S.ctypes.data_as(ctypes.c_void_p),
+                                          cnt.ctypes.data_as(ctypes.c_void_p), ns))
+        return S, cnt
+
+    # -- measurement helpers -------------------------------------------
+    def time_kernel(self, which, reps):
+        ms = ctypes.c_double()
+        name = ctypes.c_char_p()
+        _check(lib().pss_time_kernel(self._h, int(which), int(reps), ctypes.byref(ms), ctypes.byref(name)))
+        return ms.value, name.value.decode()
+
+    def kernel_bytes(self, which):
+        b = ctypes.c_double()
+        _check(lib().pss_kernel_bytes(self._h, int(which), ctypes.byref(b)))
+        return b.value
+
+    def kernels_per_step(self):
+        v = ctypes.c_int32()
+        _check(lib().pss_kernels_per_step(self._h, ctypes.byref(v)))
+        return v.value
+
+
+def philox(counter0, c1, c2, c3, k0, k1, count, out):
+    """Philox4x32-10 words for counters (counter0 + i, c1, c2, c3) into a device uint32 tensor."""
+    if not hasattr(out, "data_ptr") or not out.is_cuda or out.numel() < 4 * count:
+        raise TypeError("out must be a device tensor with 4*count 32-bit elements")
+    _check(lib().pss_util_philox(counter0, c1, c2, c3, k0, k1, int(count), ctypes.c_void_p(out.data_ptr())))
+
+
+def model_b(lat, a=-1.0, b=1.0, k=1.0, D=0.01):
+    """Model B (Cahn-Hilliard), Sec. "Example":
+    d/dt phi = -q^2 (a + k q^2) phi - b q^2 F[phi^3] + conserved noise D q^2.
+    Returns the field id and the term ids (implicit, cubic)."""
+    f = lat.field("phi")
+    t_imp = lat.term(f, [Mono(-a, q2=1), Mono(-k, q2=2)], [(f, 1)], implicit=True)
+    t_nl = lat.term(f, [Mono(-b, q2=1)], [(f, 3)])
+    if D:
+        lat.noise(f, [Mono(D, q2=1)])
+    return f, (t_imp, t_nl)

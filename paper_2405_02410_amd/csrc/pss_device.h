@@ -1,0 +1,236 @@
+// Device building blocks for the pseudo-spectral step on gfx950:
+//   * complex helpers and in-register DFTs of size 2, 4, 8, 16;
+//   * a Stockham autosort line FFT staged through LDS, written from the
+//     textbook formulation (C. Van Loan, "Computational Frameworks for the
+//     Fast Fourier Transform", SIAM 1992, Sec. 1.7): pass p with span Ns
+//     combines R sub-transforms; butterfly j reads x[j + r L/R], applies the
+//     twiddles w^(j mod Ns) r of order Ns R, and writes
+//     y[(j div Ns) Ns R + (j mod Ns) + r Ns];
+//   * Philox4x32-10 (Salmon et al., SC'11) and Box-Muller (1958).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pss {
+
+// ------------------------------------------------------------------ complex
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+
+// multiply by DIR * i (DIR = -1: forward transform sign, +1: inverse)
+template <int DIR>
+__device__ __forceinline__ float2 mul_dir_i(float2 a) {
+    return DIR > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// cos and sin of 2 pi j / 16 for j = 0..15 (multiples of pi/8)
+#define PSS_C16 0.92387953251128675613f
+#define PSS_S16 0.38268343236508977173f
+#define PSS_C8 0.70710678118654752440f
+
+template <int J>
+struct Unit16 {
+    static constexpr int j = J & 15;
+    static constexpr float c = (j == 0) ? 1.f : (j == 1) ? PSS_C16 : (j == 2) ? PSS_C8 : (j == 3) ? PSS_S16
+                             : (j == 4) ? 0.f : (j == 5) ? -PSS_S16 : (j == 6) ? -PSS_C8 : (j == 7) ? -PSS_C16
+                             : (j == 8) ? -1.f : (j == 9) ? -PSS_C16 : (j == 10) ? -PSS_C8 : (j == 11) ? -PSS_S16
+                             : (j == 12) ? 0.f : (j == 13) ? PSS_S16 : (j == 14) ? PSS_C8 : PSS_C16;
+};
+
+// a * exp(DIR * 2 pi i J / 16)
+template <int DIR, int J>
+__device__ __forceinline__ float2 rot16(float2 a) {
+    constexpr int j = J & 15;
+    if constexpr (j == 0) {
+        return a;
+    } else if constexpr (j == 4) {
+        return mul_dir_i<DIR>(a);
+    } else if constexpr (j == 8) {
+        return make_float2(-a.x, -a.y);
+    } else if constexpr (j == 12) {
+        return mul_dir_i<-DIR>(a);
+    } else {
+        constexpr float c = Unit16<j>::c;
+        constexpr float s = (DIR > 0 ? 1.f : -1.f) * Unit16<(j + 12) & 15>::c;
+        return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+    }
+}
+
+// In-register DFT of size R: a[k] <- sum_r a[r] exp(DIR 2 pi i r k / R), natural order.
+template <int R, int DIR>
+struct DFT;
+
+template <int DIR>
+struct DFT<1, DIR> {
+    static __device__ __forceinline__ void run(float2*) {}
+};
+
+template <int DIR>
+struct DFT<2, DIR> {
+    static __device__ __forceinline__ void run(float2* a) {
+        float2 t = a[1];
+        a[1] = csub(a[0], t);
+        a[0] = cadd(a[0], t);
+    }
+};
+
+template <int DIR>
+struct DFT<4, DIR> {
+    static __device__ __forceinline__ void run(float2* a) {
+        float2 t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+        float2 t2 = cadd(a[1], a[3]), t3 = mul_dir_i<DIR>(csub(a[1], a[3]));
+        a[0] = cadd(t0, t2);
+        a[2] = csub(t0, t2);
+        a[1] = cadd(t1, t3);
+        a[3] = csub(t1, t3);
+    }
+};
+
+template <int DIR>
+struct DFT<8, DIR> {
+    // radix-2 split: even / odd halves as DFT4, twiddles exp(DIR 2 pi i k/8)
+    static __device__ __forceinline__ void run(float2* a) {
+        float2 e[4] = {a[0], a[2], a[4], a[6]};
+        float2 o[4] = {a[1], a[3], a[5], a[7]};
+        DFT<4, DIR>::run(e);
+        DFT<4, DIR>::run(o);
+        o[1] = rot16<DIR, 2>(o[1]);
+        o[2] = rot16<DIR, 4>(o[2]);
+        o[3] = rot16<DIR, 6>(o[3]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            a[k] = cadd(e[k], o[k]);
+            a[k + 4] = csub(e[k], o[k]);
+        }
+    }
+};
+
+template <int DIR>
+struct DFT<16, DIR> {
+    // 4 x 4 split: X[k1 + 4 k2] = sum_n2 w4^(n2 k2) w16^(n2 k1) sum_n1 a[4 n1 + n2] w4^(n1 k1)
+    template <int N2>
+    static __device__ __forceinline__ void col(float2* a, float2 (&b)[4][4]) {
+        float2 t[4] = {a[N2], a[N2 + 4], a[N2 + 8], a[N2 + 12]};
+        DFT<4, DIR>::run(t);
+        b[N2][0] = t[0];
+        b[N2][1] = rot16<DIR, N2 * 1>(t[1]);
+        b[N2][2] = rot16<DIR, N2 * 2>(t[2]);
+        b[N2][3] = rot16<DIR, N2 * 3>(t[3]);
+    }
+    static __device__ __forceinline__ void run(float2* a) {
+        float2 b[4][4];
+        col<0>(a, b);
+        col<1>(a, b);
+        col<2>(a, b);
+        col<3>(a, b);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            float2 t[4] = {b[0][k1], b[1][k1], b[2][k1], b[3][k1]};
+            DFT<4, DIR>::run(t);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = t[k2];
+        }
+    }
+};
+
+// ------------------------------------------------------------ LDS line FFT
+// Padding of LDS line buffers: one float2 every 16 to spread banks.
+__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int lds_line(int L) { return lds_pad(L); }
+
+// One Stockham pass of span NS over a line of length L held by T = L/P
+// threads; thread t keeps x[t + m T] in v[m] on entry and exit.
+template <int L, int P, int NS, int DIR>
+struct StockhamPass {
+    static __device__ __forceinline__ void run(float2 (&v)[P], float2* __restrict__ buf, int t,
+                                               const float2* __restrict__ tw) {
+        constexpr int R = (P < L / NS) ? P : (L / NS);
+        constexpr int T = L / P;
+        constexpr int B = P / R;  // butterflies per thread
+        constexpr bool last = (NS * R == L);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int j = t + b * T;
+            float2 a[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) a[r] = v[b + r * B];
+            if constexpr (NS > 1) {
+                const int jm = j & (NS - 1);
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    float2 w = tw[(jm * r) * (L / (NS * R))];
+                    if (DIR > 0) w.y = -w.y;
+                    a[r] = cmul(a[r], w);
+                }
+            }
+            DFT<R, DIR>::run(a);
+            if constexpr (last) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[b + r * B] = a[r];
+            } else {
+                const int base = (j / NS) * NS * R + (j & (NS - 1));
+#pragma unroll
+                for (int r = 0; r < R; ++r) buf[lds_pad(base + r * NS)] = a[r];
+            }
+        }
+        if constexpr (!last) {
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < P; ++m) v[m] = buf[lds_pad(t + m * T)];
+            __syncthreads();
+            StockhamPass<L, P, NS * R, DIR>::run(v, buf, t, tw);
+        }
+    }
+};
+
+// Full line transform: v[m] = x[t + m T] in, X[t + m T] out (natural order).
+// DIR = -1: forward, unnormalised; DIR = +1: inverse, unnormalised.
+// Every thread of the block must call it (it contains block barriers).
+template <int L, int P, int DIR>
+__device__ __forceinline__ void fft_line(float2 (&v)[P], float2* __restrict__ buf, int t,
+                                         const float2* __restrict__ tw) {
+    static_assert((L & (L - 1)) == 0 && (P & (P - 1)) == 0 && P <= 16 && P <= L, "bad FFT shape");
+    StockhamPass<L, P, 1, DIR>::run(v, buf, t, tw);
+}
+
+// ------------------------------------------------------------------ Philox
+#define PSS_PHILOX_M0 0xD2511F53u
+#define PSS_PHILOX_M1 0xCD9E8D57u
+#define PSS_PHILOX_W0 0x9E3779B9u
+#define PSS_PHILOX_W1 0xBB67AE85u
+
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        if (i) {
+            k0 += PSS_PHILOX_W0;
+            k1 += PSS_PHILOX_W1;
+        }
+        const uint32_t hi0 = __umulhi(PSS_PHILOX_M0, c.x), lo0 = PSS_PHILOX_M0 * c.x;
+        const uint32_t hi1 = __umulhi(PSS_PHILOX_M1, c.z), lo1 = PSS_PHILOX_M1 * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    }
+    return c;
+}
+
+// (floor(w / 2^9) + 1/2) 2^-23: exact in binary32, inside (0, 1)
+__device__ __forceinline__ float uniform23(uint32_t w) {
+    return (static_cast<float>(w >> 9) + 0.5f) * 1.1920928955078125e-07f;
+}
+
+// Two standard normals from the first two words (Box & Muller 1958).
+__device__ __forceinline__ float2 box_muller(uint32_t w0, uint32_t w1) {
+    const float u0 = uniform23(w0), u1 = uniform23(w1);
+    const float r = sqrtf(-2.f * logf(u0));
+    float s, c;
+    sincospif(2.f * u1, &s, &c);
+    return make_float2(r * c, r * s);
+}
+
+}  // namespace pss

@@ -1,0 +1,84 @@
+// Launch interface between the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pss_plan.h"
+
+namespace pss {
+
+// kernel modes
+enum {
+    MODE_STEP = 0,       // one time step
+    MODE_PROLOGUE = 1,   // update kernel: masked inverse of the current state only
+    MODE_FWD_STORE = 2,  // update kernel: forward transform of `in`, stored as state `sel`
+    MODE_INV_OUT = 3,    // update kernel: inverse transform of state `sel` into `out`
+    MODE_R2C_IN = 4,     // x kernel: real rows `real_in` -> packed columns `out`
+    MODE_C2R_OUT = 5,    // x kernel: packed columns `in` -> real rows `real_out`
+};
+
+// Device arrays used by a launch (all in the packed half-spectrum layout
+// except the real-space ones).
+struct Bufs {
+    float2* S[PSS_MAXF];   // state per field
+    float2* N[PSS_MAXCH];  // product channels (x kernel writes, update kernel reads)
+    float2* V[PSS_MAXF];   // de-aliased inverse transforms per factor slot
+    const float2* in;
+    float2* out;
+    const float* real_in;
+    float* real_out;
+    int sel;
+};
+
+struct Geo {
+    int tc;       // packed columns per tile
+    int rb;       // rows per x-kernel block (even)
+    int ntile;    // tiles (= Nx/2 / tc): update-kernel blocks
+    int nrowblk;  // x-kernel blocks (= rows / rb)
+};
+
+struct LaunchArgs {
+    hipStream_t stream;
+    const DevPlan* plan;
+    Bufs bufs;
+    Geo geo;
+    const uint64_t* step_ctr;
+    int step_off;
+    const float2* tw_u;  // twiddles of the update-axis length
+    const float2* tw_x;  // twiddles of Nx
+};
+
+// points per thread of a line of length L when k register arrays of fields
+// are live (k = 1, 2, 4): 16, 8, 4, capped at L
+constexpr int points_per_thread(int L, int k) {
+    const int p = k <= 1 ? 16 : (k == 2 ? 8 : 4);
+    return p < L ? p : L;
+}
+
+hipError_t launch_update(int mode, int L, int nf, const LaunchArgs& a);
+hipError_t launch_xrow(int mode, int L, int ng, const LaunchArgs& a);
+hipError_t launch_advance(hipStream_t s, uint64_t* step_ctr, int64_t k);
+hipError_t launch_init_uniform(hipStream_t s, float* out, int64_t n, uint32_t field, uint32_t key0, uint32_t key1,
+                               double lo, double hi);
+hipError_t launch_philox(hipStream_t s, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+                         int64_t count, uint32_t* out);
+int update_threads(int L, int nf, int tc);
+int xrow_threads(int L, int ng, int rb);
+
+// register-array count an instantiation is built for (1, 2 or 4 fields)
+inline int field_slots(int n) { return n <= 1 ? 1 : (n == 2 ? 2 : 4); }
+// dynamic LDS of the update kernel: TC padded lines + three column-0 areas
+inline size_t update_lds_bytes(int L, int nf_slots, int tc) {
+    return sizeof(float2) * (static_cast<size_t>(tc) * (L + L / 16) + 3 * static_cast<size_t>(nf_slots) * L);
+}
+// dynamic LDS of the x kernel: RB/2 padded lines + RB staged packed rows
+inline size_t xrow_lds_bytes(int L, int rb) {
+    return sizeof(float2) * (static_cast<size_t>(rb / 2) * (L + L / 16) + static_cast<size_t>(rb) * (L / 2 + 1));
+}
+
+// FP64 shell sums of (dV/N)|phi_hat|^2 over the packed state of one field
+hipError_t launch_shells(hipStream_t s, const float2* S, int nx, int ny, int nz, int tc, int ndim,
+                         double scale, int nshell, double* sums, unsigned long long* counts);
+
+}  // namespace pss

@@ -1,0 +1,91 @@
+// Plan descriptor: the model compiled into the form the kernels read.
+// It lives in device memory; kernels read it with uniform (scalar) loads, so
+// coefficient changes never invalidate a captured graph.
+//
+// Data layout of every spectral array (the "packed half spectrum"):
+//   The x transform of a real line has modes kx = 0..Nx/2, with kx = 0 and
+//   kx = Nx/2 real.  Column c = 0 stores X(0) + i X(Nx/2); columns
+//   c = 1..Nx/2-1 store X(c).  A line therefore holds exactly Nx/2 complex
+//   values, and the y (and z) transforms of column 0 give
+//   S(0,k) = phi(0,k) + i phi(Nx/2,k), both Hermitian along the other axes.
+//   Columns are grouped in tiles of TC; arrays are stored
+//     2D:  [ctile][y][TC]                      (state, exchanges)
+//     3D:  state and z-pass input  [y][ctile][z][TC]
+//          y-pass and x-pass arrays [z][ctile][y][TC]
+//   so that every kernel reads or writes whole contiguous blocks.
+#pragma once
+
+#include <stdint.h>
+
+#define PSS_MAXF 4    // fields
+#define PSS_MAXM 8    // monomials per operator
+#define PSS_MAXT 16   // terms
+#define PSS_MAXCH 8   // real-space product channels
+#define PSS_MAXPT 8   // products per channel
+#define PSS_MAXD 8    // Fourier-space (single linear factor) terms
+#define PSS_MAXPOW 8  // largest factor power / operator power
+
+namespace pss {
+
+struct DevMono {
+    float coef;
+    int8_t q2, invq, ix, iy, iz, ipow;  // ipow = (ix + iy + iz) mod 4
+    int8_t pad[2];
+};
+
+struct DevOp {
+    int32_t n;
+    int32_t pad;
+    DevMono m[PSS_MAXM];
+};
+
+struct DevProd {
+    float coef;
+    int8_t pow[PSS_MAXF];  // power of each factor slot
+};
+
+struct DevChannel {
+    int32_t target;  // field whose update receives M(q) * F[sum_p coef_p prod_g u_g^pow]
+    int32_t nprod;
+    DevOp op;
+    DevProd prod[PSS_MAXPT];
+};
+
+struct DevDirect {
+    int32_t target, src;
+    DevOp op;
+};
+
+struct DevMask {
+    // keep a mode iff  (RADIAL) sum_i w_i k_i^2 * den2 < rhs
+    //                  (PER_AXIS) den * |k_i| < num * h_i on every axis
+    int64_t w[3];
+    int64_t den2, rhs;
+    int32_t num, den;
+    int32_t h[3];
+    int32_t shape;  // 0 radial, 1 per axis, 2 keep all
+    int32_t ncol;   // packed columns holding kept modes (c < ncol)
+    int32_t ylo;    // 3D: kept |ky| <= ylo (band of the y axis)
+    int32_t pad;
+};
+
+struct DevPlan {
+    int32_t ndim;
+    int32_t n[3];      // Nx, Ny, Nz (Nz = 1 in 2D)
+    int32_t nf, nch, ng, nd;
+    float qs[3];       // 2 pi / (N_i dx_i)
+    float dt;
+    float inv_n;       // 1 / (Nx Ny Nz)
+    float amp_pair;    // sqrt(dt N / dV): sqrt(2 dt/dV) * sqrt(N/2)
+    float amp_self;    // sqrt(2 dt N / dV)
+    uint32_t key0, key1;
+    int32_t noisy[PSS_MAXF];
+    int32_t gfield[PSS_MAXF];  // factor slot -> field
+    DevMask mask[PSS_MAXF];    // per factor slot
+    DevOp implicit_op[PSS_MAXF];
+    DevOp noise_op[PSS_MAXF];
+    DevDirect direct[PSS_MAXD];
+    DevChannel ch[PSS_MAXCH];
+};
+
+}  // namespace pss

@@ -1,0 +1,1034 @@
+// Host runtime behind include/pss.h: context, validation, plan compilation,
+// device buffers, captured step graphs, state I/O and reductions.
+//
+// The model is the paper's term structure (eq:basereal): implicit operators
+// build L(q) of each field; explicit single-factor linear terms act directly
+// in Fourier space; every other explicit term is a product of de-aliased
+// fields formed in real space.  Terms with the same target and the same single
+// monomial operator shape share one real-space "channel" (their products are
+// summed before the forward transform, which is linear).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/pss.h"
+#include "pss_kernels.h"
+#include "pss_plan.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+pss_status fail(pss_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            return fail(e_ == hipErrorOutOfMemory ? PSS_E_NOMEM : PSS_E_HIP, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                     \
+        }                                                                                    \
+    } while (0)
+
+struct Mono {
+    double coef;
+    int q2, invq, iq[3];
+};
+
+struct Term {
+    int target;
+    bool implicit;
+    std::vector<Mono> op;
+    std::vector<std::pair<int, int>> factors;  // (field, power)
+    // where its coefficients live in the compiled plan
+    int kind = 0;      // 0 implicit, 1 direct, 2 channel (single monomial), 3 channel (own operator)
+    int slot = -1;     // field / direct / channel index
+    int mono0 = -1;    // first monomial index inside the slot operator (kinds 0, 1, 3)
+    int prod = -1;     // product index inside the channel (kind 2)
+};
+
+struct Field {
+    std::string name;
+    bool noisy = false;
+    std::vector<Mono> noise;
+};
+
+bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+
+double op_real_at(const std::vector<Mono>& op, const double q[3], bool nyq[3], double* imag) {
+    const double q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+    const double invq = q2 > 0 ? 1.0 / std::sqrt(q2) : 0.0;
+    double re = 0, im = 0;
+    for (const Mono& m : op) {
+        double s = m.coef * std::pow(q2, m.q2) * std::pow(invq, m.invq);
+        int ip = 0;
+        for (int i = 0; i < 3; ++i) {
+            if (m.iq[i]) {
+                s *= std::pow(nyq[i] ? 0.0 : q[i], m.iq[i]);
+                ip += m.iq[i];
+            }
+        }
+        switch (ip & 3) {
+            case 0: re += s; break;
+            case 1: im += s; break;
+            case 2: re -= s; break;
+            default: im -= s; break;
+        }
+    }
+    if (imag) *imag = im;
+    return re;
+}
+
+// FP32 twiddles exp(-2 pi i m / L), m = 0..L-1, computed in FP64 from the
+// angle reduced to the first octant so every value is correctly rounded.
+std::vector<float2> twiddles(int L) {
+    std::vector<float2> w(L);
+    for (int m = 0; m < L; ++m) {
+        // angle = 2 pi m / L = (pi/4) * (8 m / L); split 8m = L*o + r
+        const int64_t num = 8LL * m;
+        const int oct = static_cast<int>(num / L);
+        const double frac = static_cast<double>(num % L) / L;  // in [0, 1)
+        // phase within the octant in units of pi/4
+        double c, s;
+        const double a = frac * (M_PI / 4);
+        const double ca = std::cos(a), sa = std::sin(a);
+        const double cb = std::cos(M_PI / 4 - a), sb = std::sin(M_PI / 4 - a);
+        switch (oct & 7) {
+            case 0: c = ca; s = sa; break;
+            case 1: c = sb; s = cb; break;
+            case 2: c = -sa; s = ca; break;
+            case 3: c = -cb; s = sb; break;
+            case 4: c = -ca; s = -sa; break;
+            case 5: c = -sb; s = -cb; break;
+            case 6: c = sa; s = -ca; break;
+            default: c = cb; s = -sb; break;
+        }
+        w[m] = make_float2(static_cast<float>(c), static_cast<float>(-s));
+    }
+    return w;
+}
+
+}  // namespace
+
+struct pss_ctx {
+    int ndim = 2;
+    int n[3] = {1, 1, 1};
+    double dx[3] = {1, 1, 1};
+    double dt = 0;
+    uint64_t seed = 0;
+    int rule = PSS_DEALIAS_TWO_THIRDS, shape = PSS_SHAPE_RADIAL;
+    std::vector<Field> fields;
+    std::vector<Term> terms;
+
+    // device side
+    bool planned = false;
+    bool dirty = true;  // channel arrays must be rebuilt from the state
+    pss::DevPlan plan{};
+    pss::Geo geo{};
+    int lu = 0;  // update-axis length
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    pss::DevPlan* d_plan = nullptr;
+    uint64_t* d_step = nullptr;
+    float2* d_tw_u = nullptr;
+    float2* d_tw_x = nullptr;
+    std::vector<float2*> d_state, d_chan, d_v;
+    float2* d_tmp = nullptr;
+    float* d_real = nullptr;
+    double* d_shell_sum = nullptr;
+    unsigned long long* d_shell_cnt = nullptr;
+    std::map<int64_t, hipGraphExec_t> graphs;
+    int64_t steps_taken = 0;
+
+    int64_t sites() const { return static_cast<int64_t>(n[0]) * n[1] * n[2]; }
+    int64_t packed() const { return sites() / 2; }  // complex elements per spectral array
+};
+
+namespace {
+
+pss_status check_ctx(pss_ctx* c) {
+    if (!c) return fail(PSS_E_INVAL, "null context");
+    return PSS_OK;
+}
+
+pss_status check_ops(const pss_qmono* op, int32_t n_mono, bool noise) {
+    if (n_mono < 1 || n_mono > PSS_MAXM) return fail(PSS_E_INVAL, "operator needs 1..%d monomials", PSS_MAXM);
+    if (!op) return fail(PSS_E_INVAL, "null operator");
+    for (int i = 0; i < n_mono; ++i) {
+        const pss_qmono& m = op[i];
+        if (!std::isfinite(m.coef)) return fail(PSS_E_INVAL, "non-finite coefficient");
+        if (m.q2_pow < 0 || m.q2_pow > PSS_MAXPOW || m.invq_pow < 0 || m.invq_pow > PSS_MAXPOW)
+            return fail(PSS_E_INVAL, "operator powers must lie in [0, %d]", PSS_MAXPOW);
+        for (int k = 0; k < 3; ++k)
+            if (m.iq_pow[k] < 0 || m.iq_pow[k] > PSS_MAXPOW)
+                return fail(PSS_E_INVAL, "operator powers must lie in [0, %d]", PSS_MAXPOW);
+        if (noise && (m.iq_pow[0] || m.iq_pow[1] || m.iq_pow[2]))
+            return fail(PSS_E_INVAL, "a noise operator takes powers of q^2 and 1/|q| only");
+    }
+    return PSS_OK;
+}
+
+std::vector<Mono> to_monos(const pss_qmono* op, int n) {
+    std::vector<Mono> v;
+    for (int i = 0; i < n; ++i)
+        v.push_back({op[i].coef, op[i].q2_pow, op[i].invq_pow, {op[i].iq_pow[0], op[i].iq_pow[1], op[i].iq_pow[2]}});
+    return v;
+}
+
+// Visit every mode of the full spectrum with its q vector (FP64).
+template <class F>
+void for_each_mode(const pss_ctx* c, F&& fn) {
+    const int nz = c->ndim == 3 ? c->n[2] : 1;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < c->n[1]; ++y)
+            for (int x = 0; x <= c->n[0] / 2; ++x) {
+                const int k[3] = {x == c->n[0] / 2 ? -x : x, y < c->n[1] / 2 ? y : y - c->n[1],
+                                  nz == 1 ? 0 : (z < nz / 2 ? z : z - nz)};
+                double q[3];
+                bool nyq[3];
+                for (int i = 0; i < 3; ++i) {
+                    const int ni = i < 2 ? c->n[i] : nz;
+                    q[i] = 2 * M_PI * k[i] / (ni * c->dx[i]);
+                    nyq[i] = ni > 1 && k[i] == -(ni / 2);
+                }
+                fn(q, nyq);
+            }
+}
+
+pss_status validate(pss_ctx* c) {
+    const int nf = static_cast<int>(c->fields.size());
+    if (nf == 0) return fail(PSS_E_STATE, "no fields declared");
+    std::vector<std::vector<Mono>> lam(nf);
+    for (const Term& t : c->terms)
+        if (t.implicit) lam[t.target].insert(lam[t.target].end(), t.op.begin(), t.op.end());
+    pss_status st = PSS_OK;
+    for (int f = 0; f < nf && st == PSS_OK; ++f) {
+        for_each_mode(c, [&](const double* q, bool* nyq) {
+            if (st != PSS_OK) return;
+            double im = 0;
+            const double re = op_real_at(lam[f], q, nyq, &im);
+            if (!(1.0 - c->dt * re > 0.0))
+                st = fail(PSS_E_UNSTABLE, "field %d: Re(1 - dt L(q)) = %g <= 0 at q = (%g, %g, %g)", f,
+                          1.0 - c->dt * re, q[0], q[1], q[2]);
+            if (c->fields[f].noisy) {
+                double dim = 0;
+                const double D = op_real_at(c->fields[f].noise, q, nyq, &dim);
+                if (D < 0 || dim != 0)
+                    st = fail(PSS_E_INVAL, "field %d: noise operator D(q) = %g is negative", f, D);
+            }
+        });
+    }
+    return st;
+}
+
+// keep-mask constants of a factor with cutoff num/den of Nyquist
+pss::DevMask make_mask(const pss_ctx* c, int rule, int shape, int order) {
+    pss::DevMask mk{};
+    const int nz = c->ndim == 3 ? c->n[2] : 1;
+    const int ns[3] = {c->n[0], c->n[1], nz};
+    if (rule == PSS_DEALIAS_NONE) {
+        mk.shape = 2;
+        mk.ncol = c->n[0] / 2;
+        mk.ylo = c->n[1] / 2;
+        return mk;
+    }
+    const int num = 2, den = rule == PSS_DEALIAS_TWO_THIRDS ? 3 : order + 1;
+    mk.num = num;
+    mk.den = den;
+    mk.shape = shape == PSS_SHAPE_PER_AXIS ? 1 : 0;
+    int64_t l = 1;
+    for (int i = 0; i < 3; ++i) {
+        mk.h[i] = ns[i] > 1 ? ns[i] / 2 : 0;
+        if (mk.h[i]) l = std::lcm(l, static_cast<int64_t>(mk.h[i]) * mk.h[i]);
+    }
+    for (int i = 0; i < 3; ++i) mk.w[i] = mk.h[i] ? l / (static_cast<int64_t>(mk.h[i]) * mk.h[i]) : 0;
+    mk.den2 = static_cast<int64_t>(den) * den;
+    mk.rhs = static_cast<int64_t>(num) * num * l;
+    // kept |kx| satisfy den |kx| < num h_x on either shape; the packed column
+    // count also keeps column 0 (kx = 0 is always kept)
+    int kmax = 0;
+    while (den * (kmax + 1) < num * mk.h[0]) ++kmax;
+    mk.ncol = std::min(kmax + 1, c->n[0] / 2);
+    int ymax = 0;
+    while (den * (ymax + 1) < num * mk.h[1]) ++ymax;
+    mk.ylo = ymax;
+    return mk;
+}
+
+pss_status build_plan(pss_ctx* c) {
+    using namespace pss;
+    DevPlan& P = c->plan;
+    P = DevPlan{};
+    const int nf = static_cast<int>(c->fields.size());
+    P.ndim = c->ndim;
+    P.n[0] = c->n[0];
+    P.n[1] = c->n[1];
+    P.n[2] = c->ndim == 3 ? c->n[2] : 1;
+    P.nf = nf;
+    for (int i = 0; i < 3; ++i) P.qs[i] = static_cast<float>(2 * M_PI / (P.n[i] * c->dx[i]));
+    if (c->ndim == 2) P.qs[2] = 0.f;
+    P.dt = static_cast<float>(c->dt);
+    const double N = static_cast<double>(c->sites());
+    const double dV = c->dx[0] * c->dx[1] * (c->ndim == 3 ? c->dx[2] : 1.0);
+    P.inv_n = static_cast<float>(1.0 / N);
+    P.amp_pair = static_cast<float>(std::sqrt(c->dt * N / dV));
+    P.amp_self = static_cast<float>(std::sqrt(2.0 * c->dt * N / dV));
+    P.key0 = static_cast<uint32_t>(c->seed & 0xffffffffu);
+    P.key1 = static_cast<uint32_t>(c->seed >> 32);
+
+    auto put_mono = [](DevOp& op, const Mono& m) -> int {
+        if (op.n >= PSS_MAXM) return -1;
+        DevMono& d = op.m[op.n];
+        d.coef = static_cast<float>(m.coef);
+        d.q2 = static_cast<int8_t>(m.q2);
+        d.invq = static_cast<int8_t>(m.invq);
+        d.ix = static_cast<int8_t>(m.iq[0]);
+        d.iy = static_cast<int8_t>(m.iq[1]);
+        d.iz = static_cast<int8_t>(m.iq[2]);
+        d.ipow = static_cast<int8_t>((m.iq[0] + m.iq[1] + m.iq[2]) & 3);
+        return op.n++;
+    };
+
+    for (int f = 0; f < nf; ++f) {
+        P.noisy[f] = c->fields[f].noisy ? 1 : 0;
+        for (const Mono& m : c->fields[f].noise)
+            if (put_mono(P.noise_op[f], m) < 0) return fail(PSS_E_UNSUPPORTED, "too many noise monomials");
+    }
+    // factor slots: fields entering real-space products, with the highest order
+    std::vector<int> order(nf, 0);
+    for (Term& t : c->terms) {
+        if (t.implicit) {
+            t.kind = 0;
+            t.slot = t.target;
+            t.mono0 = P.implicit_op[t.target].n;
+            for (const Mono& m : t.op)
+                if (put_mono(P.implicit_op[t.target], m) < 0)
+                    return fail(PSS_E_UNSUPPORTED, "more than %d implicit monomials on a field", PSS_MAXM);
+            continue;
+        }
+        if (t.factors.size() == 1 && t.factors[0].second == 1) {
+            if (P.nd >= PSS_MAXD) return fail(PSS_E_UNSUPPORTED, "more than %d linear explicit terms", PSS_MAXD);
+            t.kind = 1;
+            t.slot = P.nd;
+            t.mono0 = 0;
+            DevDirect& d = P.direct[P.nd++];
+            d.target = t.target;
+            d.src = t.factors[0].first;
+            for (const Mono& m : t.op) put_mono(d.op, m);
+            continue;
+        }
+        int ord = 0;
+        for (auto& fp : t.factors) ord += fp.second;
+        for (auto& fp : t.factors) order[fp.first] = std::max(order[fp.first], ord);
+    }
+    int gslot[PSS_MAXF];
+    P.ng = 0;
+    for (int f = 0; f < nf; ++f) {
+        gslot[f] = -1;
+        if (order[f] > 0) {
+            gslot[f] = P.ng;
+            P.gfield[P.ng] = f;
+            P.mask[P.ng] = make_mask(c, c->rule, c->shape, order[f]);
+            ++P.ng;
+        }
+    }
+    // channels
+    for (Term& t : c->terms) {
+        if (t.implicit || t.kind == 1) continue;
+        const bool single = t.op.size() == 1;
+        int ch = -1;
+        if (single) {
+            for (int k = 0; k < P.nch; ++k) {
+                const DevChannel& C = P.ch[k];
+                const Mono& m = t.op[0];
+                if (C.target == t.target && C.op.n == 1 && C.op.m[0].coef == 1.f && C.op.m[0].q2 == m.q2 &&
+                    C.op.m[0].invq == m.invq && C.op.m[0].ix == m.iq[0] && C.op.m[0].iy == m.iq[1] &&
+                    C.op.m[0].iz == m.iq[2] && C.nprod < PSS_MAXPT)
+                    ch = k;
+            }
+        }
+        if (ch < 0) {
+            if (P.nch >= PSS_MAXCH) return fail(PSS_E_UNSUPPORTED, "more than %d product channels", PSS_MAXCH);
+            ch = P.nch++;
+            DevChannel& C = P.ch[ch];
+            C.target = t.target;
+            if (single) {
+                Mono unit = t.op[0];
+                unit.coef = 1.0;
+                put_mono(C.op, unit);
+            } else {
+                for (const Mono& m : t.op) put_mono(C.op, m);
+            }
+        }
+        DevChannel& C = P.ch[ch];
+        DevProd& pd = C.prod[C.nprod];
+        pd.coef = single ? static_cast<float>(t.op[0].coef) : 1.f;
+        for (auto& fp : t.factors) pd.pow[gslot[fp.first]] += static_cast<int8_t>(fp.second);
+        t.kind = single ? 2 : 3;
+        t.slot = ch;
+        t.prod = C.nprod;
+        t.mono0 = 0;
+        ++C.nprod;
+    }
+    return PSS_OK;
+}
+
+int pick_pow2(int want, int lo, int hi) {
+    int v = 1;
+    while (v < want) v <<= 1;
+    return std::max(lo, std::min(hi, v));
+}
+
+pss_status choose_geometry(pss_ctx* c) {
+    const int nf = static_cast<int>(c->fields.size());
+    const int ng = std::max(1, c->plan.ng);
+    const int nx = c->n[0], ny = c->n[1];
+    c->lu = ny;
+    const int ncols = nx / 2;
+    // update kernel: TC columns of T = L/P threads; 64..256 threads
+    const int tu = pss::update_threads(ny, nf, 1);
+    int tc = std::max(1, 256 / tu);
+    tc = std::min(tc, ncols);
+    if (tu > 256) return fail(PSS_E_UNSUPPORTED, "line length %d with %d fields needs more than 256 threads", ny, nf);
+    // x kernel: RB rows (pairs of T threads); aim for >= 512 blocks, 64..256 threads
+    const int tx = pss::xrow_threads(nx, ng, 2);
+    if (tx > 256) return fail(PSS_E_UNSUPPORTED, "row length %d needs more than 256 threads", nx);
+    const int rows = ny;
+    const int rb_lo = std::max(2, 2 * (64 / tx));
+    const int rb_hi = std::max(2, 2 * (256 / tx));
+    int rb = pick_pow2(std::max(2, rows / 512), rb_lo, rb_hi);
+    rb = std::min(rb, rows);
+    c->geo.tc = tc;
+    c->geo.rb = rb;
+    c->geo.ntile = ncols / tc;
+    c->geo.nrowblk = rows / rb;
+    const size_t lu_lds = pss::update_lds_bytes(ny, pss::field_slots(nf), tc);
+    const size_t lx_lds = pss::xrow_lds_bytes(nx, rb);
+    if (lu_lds > 160 * 1024 || lx_lds > 160 * 1024)
+        return fail(PSS_E_UNSUPPORTED, "lattice needs more LDS than a workgroup has (%zu, %zu bytes)", lu_lds,
+                    lx_lds);
+    return PSS_OK;
+}
+
+void free_device(pss_ctx* c) {
+    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    auto rel = [](auto*& p) {
+        if (p) hipFree(p);
+        p = nullptr;
+    };
+    for (auto*& p : c->d_state) rel(p);
+    for (auto*& p : c->d_chan) rel(p);
+    for (auto*& p : c->d_v) rel(p);
+    rel(c->d_plan);
+    rel(c->d_step);
+    rel(c->d_tw_u);
+    rel(c->d_tw_x);
+    rel(c->d_tmp);
+    rel(c->d_real);
+    rel(c->d_shell_sum);
+    rel(c->d_shell_cnt);
+    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+    c->stream = nullptr;
+    c->own_stream = false;
+    c->planned = false;
+}
+
+pss::LaunchArgs args(pss_ctx* c, int step_off = 0) {
+    pss::LaunchArgs a{};
+    a.stream = c->stream;
+    a.plan = c->d_plan;
+    for (size_t f = 0; f < c->d_state.size(); ++f) a.bufs.S[f] = c->d_state[f];
+    for (size_t k = 0; k < c->d_chan.size(); ++k) a.bufs.N[k] = c->d_chan[k];
+    for (size_t g = 0; g < c->d_v.size(); ++g) a.bufs.V[g] = c->d_v[g];
+    a.geo = c->geo;
+    a.step_ctr = c->d_step;
+    a.step_off = step_off;
+    a.tw_u = c->d_tw_u;
+    a.tw_x = c->d_tw_x;
+    return a;
+}
+
+pss_status upload_plan(pss_ctx* c) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(c->d_plan, &c->plan, sizeof(pss::DevPlan), hipMemcpyHostToDevice));
+    return PSS_OK;
+}
+
+pss_status materialize(pss_ctx* c) {
+    if (c->planned) return PSS_OK;
+    if (c->ndim != 2) return fail(PSS_E_UNSUPPORTED, "3D lattices are not built yet");
+    pss_status st = validate(c);
+    if (st) return st;
+    if ((st = build_plan(c))) return st;
+    if ((st = choose_geometry(c))) return st;
+    if (!c->stream) {
+        HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        c->own_stream = true;
+    }
+    const size_t bytes = sizeof(float2) * static_cast<size_t>(c->packed());
+    const int nf = static_cast<int>(c->fields.size());
+    c->d_state.assign(nf, nullptr);
+    c->d_chan.assign(c->plan.nch, nullptr);
+    c->d_v.assign(c->plan.ng, nullptr);
+    for (auto*& p : c->d_state) {
+        HIP_TRY(hipMalloc(&p, bytes));
+        HIP_TRY(hipMemset(p, 0, bytes));
+    }
+    for (auto*& p : c->d_chan) {
+        HIP_TRY(hipMalloc(&p, bytes));
+        HIP_TRY(hipMemset(p, 0, bytes));
+    }
+    for (auto*& p : c->d_v) {
+        HIP_TRY(hipMalloc(&p, bytes));
+        HIP_TRY(hipMemset(p, 0, bytes));
+    }
+    HIP_TRY(hipMalloc(&c->d_tmp, bytes));
+    HIP_TRY(hipMalloc(&c->d_real, sizeof(float) * static_cast<size_t>(c->sites())));
+    HIP_TRY(hipMalloc(&c->d_plan, sizeof(pss::DevPlan)));
+    HIP_TRY(hipMalloc(&c->d_step, sizeof(uint64_t)));
+    HIP_TRY(hipMemset(c->d_step, 0, sizeof(uint64_t)));
+    const auto twx = twiddles(c->n[0]);
+    const auto twu = twiddles(c->lu);
+    HIP_TRY(hipMalloc(&c->d_tw_x, sizeof(float2) * twx.size()));
+    HIP_TRY(hipMalloc(&c->d_tw_u, sizeof(float2) * twu.size()));
+    HIP_TRY(hipMemcpy(c->d_tw_x, twx.data(), sizeof(float2) * twx.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->d_tw_u, twu.data(), sizeof(float2) * twu.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->d_plan, &c->plan, sizeof(pss::DevPlan), hipMemcpyHostToDevice));
+    HIP_TRY(hipDeviceSynchronize());
+    c->planned = true;
+    c->dirty = true;
+    c->steps_taken = 0;
+    return PSS_OK;
+}
+
+// Rebuild the channel arrays from the current state (masked inverse along the
+// update axis, then the real-space products).
+pss_status prologue(pss_ctx* c) {
+    const int nf = static_cast<int>(c->fields.size());
+    pss::LaunchArgs a = args(c);
+    HIP_TRY(pss::launch_update(pss::MODE_PROLOGUE, c->lu, nf, a));
+    if (c->plan.nch > 0) HIP_TRY(pss::launch_xrow(pss::MODE_STEP, c->n[0], c->plan.ng, a));
+    c->dirty = false;
+    return PSS_OK;
+}
+
+pss_status enqueue_steps(pss_ctx* c, int64_t k) {
+    const int nf = static_cast<int>(c->fields.size());
+    for (int64_t i = 0; i < k; ++i) {
+        pss::LaunchArgs a = args(c, static_cast<int>(i));
+        HIP_TRY(pss::launch_update(pss::MODE_STEP, c->lu, nf, a));
+        if (c->plan.nch > 0) HIP_TRY(pss::launch_xrow(pss::MODE_STEP, c->n[0], c->plan.ng, a));
+    }
+    HIP_TRY(pss::launch_advance(c->stream, c->d_step, k));
+    return PSS_OK;
+}
+
+pss_status graph_for(pss_ctx* c, int64_t k, hipGraphExec_t* out) {
+    auto it = c->graphs.find(k);
+    if (it != c->graphs.end()) {
+        *out = it->second;
+        return PSS_OK;
+    }
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    pss_status st = enqueue_steps(c, k);
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (st) {
+        if (g) hipGraphDestroy(g);
+        return st;
+    }
+    HIP_TRY(e);
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    HIP_TRY(e);
+    c->graphs[k] = ex;
+    *out = ex;
+    return PSS_OK;
+}
+
+constexpr int64_t kGraphSteps = 50;
+
+// unpack the packed state of one field into the canonical half spectrum
+void unpack_half(const pss_ctx* c, const std::vector<float2>& S, float* out) {
+    const int nx = c->n[0], ny = c->n[1], tc = c->geo.tc;
+    const int nh = nx / 2 + 1;
+    auto at = [&](int col, int y) { return S[(static_cast<size_t>(col / tc) * ny + y) * tc + col % tc]; };
+    for (int y = 0; y < ny; ++y) {
+        for (int col = 1; col < nx / 2; ++col) {
+            const float2 v = at(col, y);
+            out[2 * (static_cast<size_t>(y) * nh + col)] = v.x;
+            out[2 * (static_cast<size_t>(y) * nh + col) + 1] = v.y;
+        }
+        const float2 a = at(0, y), b = at(0, (ny - y) & (ny - 1));
+        const double r0 = 0.5 * (static_cast<double>(a.x) + b.x), i0 = 0.5 * (static_cast<double>(a.y) - b.y);
+        const double rn = 0.5 * (static_cast<double>(a.y) + b.y), in = 0.5 * (static_cast<double>(b.x) - a.x);
+        out[2 * (static_cast<size_t>(y) * nh)] = static_cast<float>(r0);
+        out[2 * (static_cast<size_t>(y) * nh) + 1] = static_cast<float>(i0);
+        out[2 * (static_cast<size_t>(y) * nh + nx / 2)] = static_cast<float>(rn);
+        out[2 * (static_cast<size_t>(y) * nh + nx / 2) + 1] = static_cast<float>(in);
+    }
+}
+
+struct SaveHeader {
+    char magic[8];
+    int32_t ndim, nf;
+    int32_t n[3];
+    int32_t tc;
+    int64_t step;
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* pss_last_error(void) { return g_err.c_str(); }
+
+pss_status pss_lattice_create(pss_ctx** out, int32_t ndim, const int64_t n[3], const double dx[3], double dt) {
+    if (!out || !n || !dx) return fail(PSS_E_INVAL, "null argument");
+    *out = nullptr;
+    if (ndim != 2 && ndim != 3) return fail(PSS_E_UNSUPPORTED, "ndim must be 2 or 3 (got %d)", ndim);
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(PSS_E_INVAL, "dt must be positive");
+    int64_t total = 1;
+    for (int i = 0; i < ndim; ++i) {
+        if (!(dx[i] > 0) || !std::isfinite(dx[i])) return fail(PSS_E_INVAL, "dx[%d] must be positive", i);
+        if (!is_pow2(n[i]) || n[i] < 8 || n[i] > 4096)
+            return fail(PSS_E_UNSUPPORTED, "n[%d] = %lld is not a power of two in [8, 4096]", i,
+                        static_cast<long long>(n[i]));
+        total *= n[i];
+    }
+    if (total > (int64_t(1) << 31)) return fail(PSS_E_UNSUPPORTED, "more than 2^31 sites");
+    pss_ctx* c = new pss_ctx();
+    c->ndim = ndim;
+    for (int i = 0; i < ndim; ++i) {
+        c->n[i] = static_cast<int>(n[i]);
+        c->dx[i] = dx[i];
+    }
+    c->dt = dt;
+    *out = c;
+    return PSS_OK;
+}
+
+pss_status pss_lattice_destroy(pss_ctx* c) {
+    if (!c) return PSS_OK;
+    free_device(c);
+    delete c;
+    return PSS_OK;
+}
+
+pss_status pss_field_declare(pss_ctx* c, const char* name, int32_t dynamic, int32_t* field_id) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (c->planned) return fail(PSS_E_STATE, "fields cannot be added after the plan is built");
+    if (!name || !*name || std::strlen(name) > 63) return fail(PSS_E_INVAL, "field name must have 1..63 characters");
+    if (!dynamic)
+        return fail(PSS_E_UNSUPPORTED, "intermediate (non-dynamic) fields are not supported yet");
+    for (const Field& f : c->fields)
+        if (f.name == name) return fail(PSS_E_INVAL, "field '%s' already declared", name);
+    if (static_cast<int>(c->fields.size()) >= PSS_MAXF) return fail(PSS_E_UNSUPPORTED, "at most %d fields", PSS_MAXF);
+    Field f;
+    f.name = name;
+    c->fields.push_back(f);
+    if (field_id) *field_id = static_cast<int32_t>(c->fields.size() - 1);
+    return PSS_OK;
+}
+
+pss_status pss_term_add(pss_ctx* c, int32_t target, int32_t implicit, const pss_qmono* op, int32_t n_mono,
+                        const int32_t* factor_fields, const int32_t* factor_powers, int32_t n_factors,
+                        int32_t* term_id) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (c->planned) return fail(PSS_E_STATE, "terms cannot be added after the plan is built");
+    const int nf = static_cast<int>(c->fields.size());
+    if (target < 0 || target >= nf) return fail(PSS_E_INVAL, "target field %d out of range", target);
+    if (pss_status s = check_ops(op, n_mono, false)) return s;
+    if (n_factors < 1 || n_factors > 4 || !factor_fields || !factor_powers)
+        return fail(PSS_E_INVAL, "a term needs 1..4 factors");
+    if (static_cast<int>(c->terms.size()) >= PSS_MAXT) return fail(PSS_E_UNSUPPORTED, "at most %d terms", PSS_MAXT);
+    Term t;
+    t.target = target;
+    t.implicit = implicit != 0;
+    t.op = to_monos(op, n_mono);
+    for (int i = 0; i < n_factors; ++i) {
+        if (factor_fields[i] < 0 || factor_fields[i] >= nf)
+            return fail(PSS_E_INVAL, "factor field %d out of range", factor_fields[i]);
+        if (factor_powers[i] < 1 || factor_powers[i] > PSS_MAXPOW)
+            return fail(PSS_E_INVAL, "factor powers must lie in [1, %d]", PSS_MAXPOW);
+        t.factors.push_back({factor_fields[i], factor_powers[i]});
+    }
+    if (t.implicit && !(n_factors == 1 && factor_fields[0] == target && factor_powers[0] == 1))
+        return fail(PSS_E_INVAL, "an implicit term must be linear in its own field (op * field)");
+    int total = 0;
+    for (auto& fp : t.factors) total += fp.second;
+    if (total > PSS_MAXPOW) return fail(PSS_E_INVAL, "total order above %d", PSS_MAXPOW);
+    c->terms.push_back(t);
+    if (term_id) *term_id = static_cast<int32_t>(c->terms.size() - 1);
+    return PSS_OK;
+}
+
+pss_status pss_term_set_coef(pss_ctx* c, int32_t term_id, int32_t mono, double coef) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (term_id < 0 || term_id >= static_cast<int>(c->terms.size())) return fail(PSS_E_INVAL, "bad term id");
+    Term& t = c->terms[term_id];
+    if (mono < 0 || mono >= static_cast<int>(t.op.size())) return fail(PSS_E_INVAL, "bad monomial index");
+    if (!std::isfinite(coef)) return fail(PSS_E_INVAL, "non-finite coefficient");
+    const double old = t.op[mono].coef;
+    t.op[mono].coef = coef;
+    if (t.implicit) {
+        if (pss_status s = validate(c)) {
+            t.op[mono].coef = old;
+            return s;
+        }
+    }
+    if (!c->planned) return PSS_OK;
+    pss::DevPlan& P = c->plan;
+    switch (t.kind) {
+        case 0: P.implicit_op[t.slot].m[t.mono0 + mono].coef = static_cast<float>(coef); break;
+        case 1: P.direct[t.slot].op.m[mono].coef = static_cast<float>(coef); break;
+        case 2: P.ch[t.slot].prod[t.prod].coef = static_cast<float>(coef); break;
+        default: P.ch[t.slot].op.m[mono].coef = static_cast<float>(coef); break;
+    }
+    return upload_plan(c);
+}
+
+pss_status pss_noise_set(pss_ctx* c, int32_t field, const pss_qmono* D, int32_t n_mono) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (c->planned) return fail(PSS_E_STATE, "noise cannot be changed after the plan is built");
+    if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    if (pss_status s = check_ops(D, n_mono, true)) return s;
+    c->fields[field].noisy = true;
+    c->fields[field].noise = to_monos(D, n_mono);
+    return PSS_OK;
+}
+
+pss_status pss_seed_set(pss_ctx* c, uint64_t seed) {
+    if (pss_status s = check_ctx(c)) return s;
+    c->seed = seed;
+    if (c->planned) {
+        c->plan.key0 = static_cast<uint32_t>(seed & 0xffffffffu);
+        c->plan.key1 = static_cast<uint32_t>(seed >> 32);
+        return upload_plan(c);
+    }
+    return PSS_OK;
+}
+
+pss_status pss_dealias_set(pss_ctx* c, int32_t rule, int32_t shape) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (c->planned) return fail(PSS_E_STATE, "de-aliasing cannot be changed after the plan is built");
+    if (rule < 0 || rule > 2 || shape < 0 || shape > 1) return fail(PSS_E_INVAL, "bad de-aliasing rule or shape");
+    c->rule = rule;
+    c->shape = shape;
+    return PSS_OK;
+}
+
+pss_status pss_stream_set(pss_ctx* c, void* stream) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (c->planned && c->stream) HIP_TRY(hipStreamSynchronize(c->stream));
+    if (c->own_stream && c->stream) {
+        hipStreamDestroy(c->stream);
+        c->own_stream = false;
+        c->stream = nullptr;
+    }
+    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    c->stream = static_cast<hipStream_t>(stream);
+    if (!c->stream && c->planned) {
+        HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        c->own_stream = true;
+    }
+    return PSS_OK;
+}
+
+pss_status pss_validate(pss_ctx* c) {
+    if (pss_status s = check_ctx(c)) return s;
+    return validate(c);
+}
+
+pss_status pss_field_upload(pss_ctx* c, int32_t field, const float* real, int32_t on_device) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (!real) return fail(PSS_E_INVAL, "null array");
+    if (pss_status s = materialize(c)) return s;
+    if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    const size_t bytes = sizeof(float) * static_cast<size_t>(c->sites());
+    HIP_TRY(hipMemcpyAsync(c->d_real, real, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           c->stream));
+    pss::LaunchArgs a = args(c);
+    a.bufs.real_in = c->d_real;
+    a.bufs.out = c->d_tmp;
+    HIP_TRY(pss::launch_xrow(pss::MODE_R2C_IN, c->n[0], 1, a));
+    a.bufs.in = c->d_tmp;
+    a.bufs.sel = field;
+    HIP_TRY(pss::launch_update(pss::MODE_FWD_STORE, c->lu, 1, a));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->dirty = true;
+    return PSS_OK;
+}
+
+pss_status pss_field_init_uniform(pss_ctx* c, int32_t field, double lo, double hi) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (!std::isfinite(lo) || !std::isfinite(hi)) return fail(PSS_E_INVAL, "non-finite bounds");
+    if (pss_status s = materialize(c)) return s;
+    if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    HIP_TRY(pss::launch_init_uniform(c->stream, c->d_real, c->sites(), static_cast<uint32_t>(field),
+                                     c->plan.key0, c->plan.key1, lo, hi));
+    pss::LaunchArgs a = args(c);
+    a.bufs.real_in = c->d_real;
+    a.bufs.out = c->d_tmp;
+    HIP_TRY(pss::launch_xrow(pss::MODE_R2C_IN, c->n[0], 1, a));
+    a.bufs.in = c->d_tmp;
+    a.bufs.sel = field;
+    HIP_TRY(pss::launch_update(pss::MODE_FWD_STORE, c->lu, 1, a));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->dirty = true;
+    return PSS_OK;
+}
+
+pss_status pss_field_download(pss_ctx* c, int32_t field, float* real, int32_t on_device) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (!real) return fail(PSS_E_INVAL, "null array");
+    if (pss_status s = materialize(c)) return s;
+    if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    pss::LaunchArgs a = args(c);
+    a.bufs.sel = field;
+    a.bufs.out = c->d_tmp;
+    HIP_TRY(pss::launch_update(pss::MODE_INV_OUT, c->lu, 1, a));
+    a.bufs.in = c->d_tmp;
+    a.bufs.real_out = c->d_real;
+    HIP_TRY(pss::launch_xrow(pss::MODE_C2R_OUT, c->n[0], 1, a));
+    const size_t bytes = sizeof(float) * static_cast<size_t>(c->sites());
+    HIP_TRY(hipMemcpyAsync(real, c->d_real, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return PSS_OK;
+}
+
+pss_status pss_spectrum_download(pss_ctx* c, int32_t field, float* half, int32_t on_device) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (!half) return fail(PSS_E_INVAL, "null array");
+    if (pss_status s = materialize(c)) return s;
+    if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    std::vector<float2> S(static_cast<size_t>(c->packed()));
+    HIP_TRY(hipMemcpyAsync(S.data(), c->d_state[field], sizeof(float2) * S.size(), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const size_t nout = static_cast<size_t>(c->n[1]) * (c->n[0] / 2 + 1) * 2;
+    std::vector<float> h(nout);
+    unpack_half(c, S, h.data());
+    if (on_device) {
+        HIP_TRY(hipMemcpy(half, h.data(), sizeof(float) * nout, hipMemcpyHostToDevice));
+    } else {
+        std::memcpy(half, h.data(), sizeof(float) * nout);
+    }
+    return PSS_OK;
+}
+
+pss_status pss_step(pss_ctx* c, int64_t nsteps) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (nsteps < 0) return fail(PSS_E_INVAL, "negative step count");
+    if (nsteps == 0) return PSS_OK;
+    if (pss_status s = materialize(c)) return s;
+    if (c->dirty)
+        if (pss_status s = prologue(c)) return s;
+    int64_t left = nsteps;
+    while (left > 0) {
+        const int64_t k = std::min(left, kGraphSteps);
+        hipGraphExec_t ex = nullptr;
+        if (pss_status s = graph_for(c, k, &ex)) return s;
+        HIP_TRY(hipGraphLaunch(ex, c->stream));
+        left -= k;
+    }
+    c->steps_taken += nsteps;
+    return PSS_OK;
+}
+
+pss_status pss_step_index(pss_ctx* c, int64_t* out) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (!out) return fail(PSS_E_INVAL, "null output");
+    *out = c->steps_taken;
+    return PSS_OK;
+}
+
+pss_status pss_sync(pss_ctx* c) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (c->stream) HIP_TRY(hipStreamSynchronize(c->stream));
+    return PSS_OK;
+}
+
+pss_status pss_state_size(pss_ctx* c, size_t* bytes) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (!bytes) return fail(PSS_E_INVAL, "null output");
+    *bytes = sizeof(SaveHeader) + c->fields.size() * sizeof(float2) * static_cast<size_t>(c->packed());
+    return PSS_OK;
+}
+
+pss_status pss_state_save(pss_ctx* c, void* dst, size_t bytes) {
+    if (pss_status s = check_ctx(c)) return s;
+    size_t need = 0;
+    pss_state_size(c, &need);
+    if (!dst || bytes < need) return fail(PSS_E_INVAL, "state buffer needs %zu bytes", need);
+    if (pss_status s = materialize(c)) return s;
+    SaveHeader h{};
+    std::memcpy(h.magic, "PSSSTAT1", 8);
+    h.ndim = c->ndim;
+    h.nf = static_cast<int32_t>(c->fields.size());
+    for (int i = 0; i < 3; ++i) h.n[i] = c->n[i];
+    h.tc = c->geo.tc;
+    h.step = c->steps_taken;
+    std::memcpy(dst, &h, sizeof(h));
+    char* p = static_cast<char*>(dst) + sizeof(h);
+    const size_t fb = sizeof(float2) * static_cast<size_t>(c->packed());
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (size_t f = 0; f < c->fields.size(); ++f) HIP_TRY(hipMemcpy(p + f * fb, c->d_state[f], fb, hipMemcpyDeviceToHost));
+    return PSS_OK;
+}
+
+pss_status pss_state_load(pss_ctx* c, const void* src, size_t bytes) {
+    if (pss_status s = check_ctx(c)) return s;
+    size_t need = 0;
+    pss_state_size(c, &need);
+    if (!src || bytes < need) return fail(PSS_E_INVAL, "state buffer needs %zu bytes", need);
+    if (pss_status s = materialize(c)) return s;
+    SaveHeader h;
+    std::memcpy(&h, src, sizeof(h));
+    if (std::memcmp(h.magic, "PSSSTAT1", 8) != 0 || h.ndim != c->ndim || h.nf != static_cast<int>(c->fields.size()) ||
+        h.n[0] != c->n[0] || h.n[1] != c->n[1] || h.n[2] != c->n[2] || h.tc != c->geo.tc)
+        return fail(PSS_E_INVAL, "state buffer does not match this lattice");
+    const char* p = static_cast<const char*>(src) + sizeof(h);
+    const size_t fb = sizeof(float2) * static_cast<size_t>(c->packed());
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (size_t f = 0; f < c->fields.size(); ++f) HIP_TRY(hipMemcpy(c->d_state[f], p + f * fb, fb, hipMemcpyHostToDevice));
+    const uint64_t st = static_cast<uint64_t>(h.step);
+    HIP_TRY(hipMemcpy(c->d_step, &st, sizeof(st), hipMemcpyHostToDevice));
+    c->steps_taken = h.step;
+    c->dirty = true;
+    return PSS_OK;
+}
+
+pss_status pss_mass(pss_ctx* c, int32_t field, double* mass) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (!mass) return fail(PSS_E_INVAL, "null output");
+    if (pss_status s = materialize(c)) return s;
+    if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    float2 v;
+    HIP_TRY(hipMemcpyAsync(&v, c->d_state[field], sizeof(v), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *mass = static_cast<double>(v.x);  // Re of phi_hat(0) + i phi_hat(Nx/2, 0)
+    return PSS_OK;
+}
+
+pss_status pss_structure_factor(pss_ctx* c, int32_t field, double* S, int64_t* counts, int32_t n_shells) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (!S || !counts) return fail(PSS_E_INVAL, "null output");
+    if (pss_status s = materialize(c)) return s;
+    if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    const int nmin = std::min(c->n[0], c->n[1]);
+    const int ns = nmin / 2;  // shells j = 1 .. ns-1
+    if (n_shells != ns - 1) return fail(PSS_E_INVAL, "n_shells must be %d", ns - 1);
+    if (!c->d_shell_sum) {
+        HIP_TRY(hipMalloc(&c->d_shell_sum, sizeof(double) * ns));
+        HIP_TRY(hipMalloc(&c->d_shell_cnt, sizeof(unsigned long long) * ns));
+    }
+    HIP_TRY(hipMemsetAsync(c->d_shell_sum, 0, sizeof(double) * ns, c->stream));
+    HIP_TRY(hipMemsetAsync(c->d_shell_cnt, 0, sizeof(unsigned long long) * ns, c->stream));
+    const double dV = c->dx[0] * c->dx[1] * (c->ndim == 3 ? c->dx[2] : 1.0);
+    HIP_TRY(pss::launch_shells(c->stream, c->d_state[field], c->n[0], c->n[1], c->ndim == 3 ? c->n[2] : 1, c->geo.tc,
+                               c->ndim, dV / static_cast<double>(c->sites()), ns, c->d_shell_sum, c->d_shell_cnt));
+    std::vector<double> sums(ns);
+    std::vector<unsigned long long> cnt(ns);
+    HIP_TRY(hipMemcpyAsync(sums.data(), c->d_shell_sum, sizeof(double) * ns, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(cnt.data(), c->d_shell_cnt, sizeof(unsigned long long) * ns, hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int j = 1; j < ns; ++j) {
+        counts[j - 1] = static_cast<int64_t>(cnt[j]);
+        S[j - 1] = cnt[j] ? sums[j] / static_cast<double>(cnt[j]) : 0.0;
+    }
+    return PSS_OK;
+}
+
+pss_status pss_util_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+                           int64_t count, uint32_t* out) {
+    if (!out || count < 0) return fail(PSS_E_INVAL, "bad arguments");
+    if (count == 0) return PSS_OK;
+    HIP_TRY(pss::launch_philox(nullptr, c0, c1, c2, c3, k0, k1, count, out));
+    HIP_TRY(hipStreamSynchronize(nullptr));
+    return PSS_OK;
+}
+
+pss_status pss_kernels_per_step(pss_ctx* c, int32_t* count) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (!count) return fail(PSS_E_INVAL, "null output");
+    *count = c->ndim == 3 ? 4 : 2;
+    return PSS_OK;
+}
+
+pss_status pss_kernel_bytes(pss_ctx* c, int32_t which, double* bytes) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (!bytes) return fail(PSS_E_INVAL, "null output");
+    if (pss_status s = materialize(c)) return s;
+    const double arr = 8.0 * static_cast<double>(c->packed());  // one packed array
+    const pss::DevPlan& P = c->plan;
+    const int ny = c->n[1], tc = c->geo.tc;
+    double vbytes = 0;  // factor arrays written by the update / read by the x kernel
+    for (int g = 0; g < P.ng; ++g) {
+        const int tiles = (P.mask[g].ncol + tc - 1) / tc;
+        vbytes += 8.0 * tiles * tc * ny;
+    }
+    const int nf = static_cast<int>(c->fields.size());
+    if (which == 0) {
+        *bytes = arr * (P.nch + 2 * nf) + vbytes;
+    } else if (which == 1) {
+        *bytes = vbytes + arr * P.nch;
+    } else {
+        return fail(PSS_E_INVAL, "kernel %d does not exist on a 2D lattice", which);
+    }
+    return PSS_OK;
+}
+
+pss_status pss_time_kernel(pss_ctx* c, int32_t which, int32_t reps, double* ms, const char** name) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (!ms || reps < 1) return fail(PSS_E_INVAL, "bad arguments");
+    if (pss_status s = materialize(c)) return s;
+    if (which < 0 || which > 1) return fail(PSS_E_INVAL, "kernel %d does not exist on a 2D lattice", which);
+    if (c->dirty)
+        if (pss_status s = prologue(c)) return s;
+    const int nf = static_cast<int>(c->fields.size());
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    pss::LaunchArgs a = args(c);
+    HIP_TRY(hipEventRecord(e0, c->stream));
+    for (int r = 0; r < reps; ++r) {
+        if (which == 0) {
+            HIP_TRY(pss::launch_update(pss::MODE_STEP, c->lu, nf, a));
+        } else {
+            HIP_TRY(pss::launch_xrow(pss::MODE_STEP, c->n[0], c->plan.ng, a));
+        }
+    }
+    HIP_TRY(hipEventRecord(e1, c->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float t = 0;
+    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *ms = static_cast<double>(t) / reps;
+    c->dirty = true;  // the channel arrays no longer match the state
+    if (name) *name = which == 0 ? "update_kernel" : "xrow_kernel";
+    return PSS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+"""Host-only checks of the C interface (no GPU): the library loads, exports
+every declared symbol, and rejects invalid models before touching a device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2405_02410_amd as pss
+from paper_2405_02410_amd import Mono, PssError
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pss.h")).read()
+    return sorted(set(re.findall(r"\b(pss_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = pss.lib()
+    names = _declared()
+    assert len(names) >= 27
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def _lat(n=(64, 64), dt=0.01, **kw):
+    return pss.Lattice(n, dt=dt, **kw)
+
+
+@pytest.mark.parametrize("n", [(63, 64), (64, 4), (8192, 8), (64, 64, 64, 64)])
+def test_bad_sizes(n):
+    with pytest.raises(PssError) as e:
+        pss.Lattice(n, dt=0.1)
+    assert e.value.name in ("PSS_E_UNSUPPORTED", "PSS_E_INVAL")
+
+
+def test_bad_dt_and_dx():
+    with pytest.raises(PssError) as e:
+        pss.Lattice((16, 16), dt=0.0)
+    assert e.value.name == "PSS_E_INVAL"
+    with pytest.raises(PssError):
+        pss.Lattice((16, 16), dx=(1.0, -1.0), dt=0.1)
+
+
+def test_implicit_term_must_be_linear_in_own_field():
+    lat = _lat()
+    a = lat.field("a")
+    b = lat.field("b")
+    with pytest.raises(PssError) as e:
+        lat.term(a, [Mono(1.0)], [(b, 1)], implicit=True)
+    assert e.value.name == "PSS_E_INVAL"
+    with pytest.raises(PssError):
+        lat.term(a, [Mono(1.0)], [(a, 2)], implicit=True)
+    lat.term(a, [Mono(-1.0, 1)], [(a, 1)], implicit=True)
+
+
+def test_duplicate_and_intermediate_fields():
+    lat = _lat()
+    lat.field("phi")
+    with pytest.raises(PssError):
+        lat.field("phi")
+    with pytest.raises(PssError) as e:
+        lat.field("psi", dynamic=False)
+    assert e.value.name == "PSS_E_UNSUPPORTED"
+
+
+def test_unstable_model_rejected_on_host():
+    lat = _lat(dt=10.0)
+    f = lat.field("phi")
+    # 1 - dt L = 1 + dt (a q^2 + k q^4) with a = -1, k = 0 -> negative at large q
+    lat.term(f, [Mono(1.0, q2=1)], [(f, 1)], implicit=True)
+    with pytest.raises(PssError) as e:
+        lat.validate()
+    assert e.value.name == "PSS_E_UNSTABLE"
+
+
+def test_model_b_validates():
+    lat = _lat()
+    pss.model_b(lat)
+    lat.validate()
+
+
+def test_noise_operator_checks():
+    lat = _lat()
+    f = lat.field("phi")
+    with pytest.raises(PssError):
+        lat.noise(f, [Mono(1.0, iq=(1, 0, 0))])
+    lat.noise(f, [Mono(-1.0, q2=1)])
+    with pytest.raises(PssError) as e:
+        lat.validate()
+    assert e.value.name == "PSS_E_INVAL"
+
+
+def test_argument_ranges():
+    lat = _lat()
+    f = lat.field("phi")
+    with pytest.raises(PssError):
+        lat.term(f, [Mono(1.0, q2=9)], [(f, 3)])
+    with pytest.raises(PssError):
+        lat.term(f, [Mono(1.0)], [(f, 9)])
+    with pytest.raises(PssError):
+        lat.term(5, [Mono(1.0)], [(f, 3)])
+    with pytest.raises(PssError):
+        lat.term(f, [], [(f, 3)])
+    t = lat.term(f, [Mono(1.0)], [(f, 3)])
+    with pytest.raises(PssError):
+        lat.set_coef(t, 3, 1.0)
+    lat.set_coef(t, 0, 2.0)
+
+
+def test_null_context_is_an_error():
+    lib = pss.lib()
+    assert lib.pss_step(None, 1) == -1
+    assert lib.pss_lattice_destroy(None) == 0
+    assert b"null" in lib.pss_last_error()
+
+
+def test_step_zero_is_a_noop_without_device():
+    lat = _lat()
+    pss.model_b(lat)
+    lat.step(0)
+    assert lat.step_index == 0

@@ -1,0 +1,297 @@
+"""GPU parity of the HIP path (through the C interface) against the FP64 oracle.
+
+Tolerances: the GPU computes in FP32.  Transforms of O(1) data agree with
+FP64 to a few 1e-7 relative per pass; the 2D Model B workload must stay within
+1e-4 max-abs of the oracle's real-space field after 100 steps, with mass
+conserved to 1e-6 of sum|phi|.
+"""
+
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+from tests import inputs
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs an MI355X")]
+
+import paper_2405_02410_amd as pss  # noqa: E402
+from paper_2405_02410_amd import Mono  # noqa: E402
+from oracle import model as om  # noqa: E402
+from oracle import philox as oph  # noqa: E402
+from oracle import observables as ob  # noqa: E402
+from oracle.spectral import Lattice as OLattice, Mono as OMono, fftn  # noqa: E402
+
+
+def _olat(n, dx=None):
+    dx = dx or (1.0,) * len(n)
+    if len(n) == 2:
+        return OLattice(n[0], n[1], 1, dx=dx[0], dy=dx[1])
+    return OLattice(n[0], n[1], n[2], dx=dx[0], dy=dx[1], dz=dx[2])
+
+
+def _half(full):
+    return full[..., : full.shape[-1] // 2 + 1]
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / max(1e-30, np.max(np.abs(b)))
+
+
+# ------------------------------------------------------------------ Philox
+def test_philox_words_bitwise():
+    import torch
+    n = 1 << 22
+    out = torch.empty(4 * n, dtype=torch.int32, device="cuda")
+    pss.philox(123, 7, 2, 0, 0xDEADBEEF, 0x12345678, n, out)
+    got = out.cpu().numpy().view(np.uint32).reshape(n, 4)
+    w = oph.philox4x32_10(np.arange(123, 123 + n, dtype=np.uint64), 7, 2, 0, 0xDEADBEEF, 0x12345678)
+    for i in range(4):
+        assert np.array_equal(got[:, i].astype(np.uint64), w[i])
+
+
+def test_philox_counter_wraps_like_uint32():
+    import torch
+    n = 4096
+    out = torch.empty(4 * n, dtype=torch.int32, device="cuda")
+    start = 2**32 - 100
+    pss.philox(start, 1, 2, 3, 4, 5, n, out)
+    got = out.cpu().numpy().view(np.uint32).reshape(n, 4)
+    ctr = (np.arange(n, dtype=np.uint64) + start) & 0xFFFFFFFF
+    w = oph.philox4x32_10(ctr, 1, 2, 3, 4, 5)
+    assert np.array_equal(got[:, 0].astype(np.uint64), w[0])
+
+
+# ------------------------------------------------------------- transforms
+@pytest.mark.parametrize("n", [(64, 64), (128, 32), (32, 128), (8, 8), (16, 256), (256, 16), (1024, 1024),
+                               (4096, 8), (8, 2048)])
+def test_forward_transform_and_round_trip(n):
+    lat = pss.Lattice(n, dt=0.01)
+    lat.field("phi")
+    shape = tuple(reversed(n))
+    x = inputs.random_field((1,) + shape, seed=sum(n), amp=1.0)[0]
+    lat.upload(0, x)
+    spec = lat.spectrum(0)
+    ref = _half(np.fft.fftn(x.astype(np.float64)))
+    assert _rel(spec, ref) < 2e-6 * np.log2(max(n))
+    back = lat.download(0)
+    assert np.max(np.abs(back.reshape(shape) - x)) < 2e-6 * np.log2(max(n)) * np.max(np.abs(x))
+
+
+def test_init_uniform_matches_oracle():
+    n = (128, 64)
+    lat = pss.Lattice(n, dt=0.01, seed=987654321)
+    lat.field("phi")
+    lat.field("psi")
+    lat.init_uniform(1, -0.1, 0.1)
+    m = om.Model(_olat(n), 0.01, seed=987654321)
+    m.add_field("phi")
+    m.add_field("psi")
+    want = m.init_uniform(1, -0.1, 0.1)
+    got = lat.download(1).reshape(want.shape)
+    # the real field comes back through two FP32 transforms
+    assert np.max(np.abs(got - want)) < 1e-7
+    spec = lat.spectrum(1)
+    ref = _half(fftn(want.astype(np.complex128)))[0]
+    assert _rel(spec, ref) < 1e-5
+
+
+# ----------------------------------------------------------------- linear
+def test_linear_decay_matches_oracle():
+    n, dx, dt = (64, 32), (0.7, 1.3), 0.05
+    ops = [Mono(-0.3, q2=1), Mono(-0.1, q2=2), Mono(0.2, iq=(2, 0, 0)), Mono(-0.05, invq=1),
+           Mono(0.02, iq=(0, 1, 0))]
+    lat = pss.Lattice(n, dx=dx, dt=dt)
+    f = lat.field("phi")
+    lat.term(f, ops, [(f, 1)], implicit=True)
+    x = inputs.random_field((32, 64), seed=3)
+    lat.upload(f, x)
+    lat.step(37)
+    m = om.Model(_olat(n, dx), dt)
+    g = m.add_field("phi")
+    m.add_term(g, [OMono(o.coef, o.q2, o.invq, o.iq) for o in ops], [(g, 1)], implicit=True)
+    m.set_real(g, x[None])
+    m.step(37)
+    assert _rel(lat.spectrum(f), _half(m.state[g])[0]) < 1e-5
+
+
+def test_direct_terms_and_jacobi_coupling():
+    n, dt = (32, 32), 0.02
+    lat = pss.Lattice(n, dt=dt)
+    a = lat.field("a")
+    b = lat.field("b")
+    lat.term(a, [Mono(-1.0, q2=1)], [(a, 1)], implicit=True)
+    lat.term(b, [Mono(-0.5), Mono(-2.0, q2=1)], [(b, 1)], implicit=True)
+    lat.term(a, [Mono(0.7, iq=(1, 0, 0))], [(b, 1)])
+    lat.term(b, [Mono(-0.4, q2=1)], [(a, 1)])
+    lat.term(a, [Mono(0.3)], [(a, 1)])
+    xa = inputs.random_field((32, 32), seed=4)
+    xb = inputs.random_field((32, 32), seed=5)
+    lat.upload(a, xa)
+    lat.upload(b, xb)
+    lat.step(25)
+    m = om.Model(_olat(n), dt)
+    A = m.add_field("a")
+    B = m.add_field("b")
+    m.add_term(A, [OMono(-1.0, q2=1)], [(A, 1)], implicit=True)
+    m.add_term(B, [OMono(-0.5), OMono(-2.0, q2=1)], [(B, 1)], implicit=True)
+    m.add_term(A, [OMono(0.7, iq=(1, 0, 0))], [(B, 1)])
+    m.add_term(B, [OMono(-0.4, q2=1)], [(A, 1)])
+    m.add_term(A, [OMono(0.3)], [(A, 1)])
+    m.set_real(A, xa[None])
+    m.set_real(B, xb[None])
+    m.step(25)
+    assert _rel(lat.spectrum(a), _half(m.state[A])[0]) < 1e-5
+    assert _rel(lat.spectrum(b), _half(m.state[B])[0]) < 1e-5
+
+
+# ------------------------------------------------------------------ noise
+@pytest.mark.parametrize("n,seed", [((64, 64), 1), ((32, 16), 2**40 + 3), ((16, 64), 77)])
+def test_one_noise_step_matches_oracle(n, seed):
+    dt, D = 0.1, 0.3
+    dx = (0.5, 0.8)
+    lat = pss.Lattice(n, dx=dx, dt=dt, seed=seed)
+    f = lat.field("phi")
+    lat.term(f, [Mono(-1.0, q2=1)], [(f, 1)], implicit=True)
+    lat.noise(f, [Mono(D, q2=1), Mono(0.05)])
+    lat.upload(f, np.zeros((n[1], n[0]), np.float32))
+    lat.step(3)
+    m = om.Model(_olat(n, dx), dt, seed=seed)
+    g = m.add_field("phi")
+    m.add_term(g, [OMono(-1.0, q2=1)], [(g, 1)], implicit=True)
+    m.set_noise(g, [OMono(D, q2=1), OMono(0.05)])
+    m.step(3)
+    assert _rel(lat.spectrum(f), _half(m.state[g])[0]) < 1e-5
+
+
+# ---------------------------------------------------------------- Model B
+def _model_b_pair(n, steps, seed=1, D=0.01, dealias=pss.DEALIAS_TWO_THIRDS, shape=pss.SHAPE_RADIAL,
+                  odeal=om.DEALIAS_TWO_THIRDS, oshape=om.SHAPE_RADIAL):
+    p = inputs.MODEL_B
+    lat = pss.Lattice(n, dt=p["dt"], seed=seed, dealias=dealias, shape=shape)
+    f, _ = pss.model_b(lat, a=p["a"], b=p["b"], k=p["k"], D=D)
+    lat.init_uniform(f, -0.1, 0.1)
+    m = om.model_b(_olat(n), p["dt"], a=p["a"], b=p["b"], k=p["k"], D=D, seed=seed,
+                   dealias=odeal, shape=oshape)
+    m.init_uniform(0, -0.1, 0.1)
+    return lat, m
+
+
+def test_model_b_64_after_100_steps():
+    lat, m = _model_b_pair((64, 64), 100)
+    mass0 = lat.mass(0)
+    for _ in range(10):
+        lat.step(10)
+        m.step(10)
+        phi = lat.download(0)
+        assert abs(lat.mass(0) - mass0) <= 1e-6 * np.sum(np.abs(phi))
+    err = np.max(np.abs(lat.download(0) - m.real(0)[0]))
+    assert err <= 1e-4, err
+
+
+def test_model_b_64_after_1000_steps():
+    lat, m = _model_b_pair((64, 64), 1000)
+    lat.step(1000)
+    m.step(1000)
+    err = np.max(np.abs(lat.download(0) - m.real(0)[0]))
+    assert err <= 1e-4, err
+
+
+@pytest.mark.parametrize("n", [(128, 32), (32, 128), (16, 256), (256, 16), (8, 8), (2048, 8)])
+def test_model_b_non_square(n):
+    lat, m = _model_b_pair(n, 20, seed=5, D=0.05)
+    lat.step(20)
+    m.step(20)
+    assert np.max(np.abs(lat.download(0) - m.real(0)[0])) < 2e-5
+
+
+@pytest.mark.parametrize("deal,shape", [(pss.DEALIAS_PAPER_ORDER, pss.SHAPE_RADIAL),
+                                        (pss.DEALIAS_TWO_THIRDS, pss.SHAPE_PER_AXIS),
+                                        (pss.DEALIAS_NONE, pss.SHAPE_RADIAL),
+                                        (pss.DEALIAS_PAPER_ORDER, pss.SHAPE_PER_AXIS)])
+def test_model_b_dealias_variants(deal, shape):
+    lat, m = _model_b_pair((64, 32), 30, seed=9, D=0.05, dealias=deal, shape=shape, odeal=deal, oshape=shape)
+    lat.step(30)
+    m.step(30)
+    assert np.max(np.abs(lat.download(0) - m.real(0)[0])) < 2e-5
+
+
+def test_model_b_1024_full_size():
+    lat, m = _model_b_pair((1024, 1024), 10)
+    lat.step(10)
+    m.step(10)
+    err = np.max(np.abs(lat.download(0) - m.real(0)[0]))
+    assert err < 1e-5, err
+    S, cnt = lat.structure_factor(0)
+    so, no = ob.shell_average(m.lat, ob.structure_factor(m.lat, m.state[0]))
+    assert np.array_equal(cnt, no)
+    assert _rel(S, so) < 1e-4
+
+
+def test_two_field_products_2d():
+    n, dt = (64, 64), 0.005
+    a_, b_, k_, c_, g_, D_ = -1.0, 1.0, 1.0, -0.5, 0.3, 0.005
+    lat = pss.Lattice(n, dt=dt, seed=11)
+    phi = lat.field("phi")
+    psi = lat.field("psi")
+    lat.term(phi, [Mono(-a_, q2=1), Mono(-k_, q2=2)], [(phi, 1)], implicit=True)
+    lat.term(phi, [Mono(-b_, q2=1)], [(phi, 3)])
+    lat.term(phi, [Mono(-0.5 * g_, q2=1)], [(phi, 1), (psi, 2)])
+    lat.term(psi, [Mono(-c_), Mono(-1.0, q2=1)], [(psi, 1)], implicit=True)
+    lat.term(psi, [Mono(-1.0)], [(psi, 3)])
+    lat.term(psi, [Mono(-g_)], [(phi, 1), (psi, 1)])
+    lat.noise(phi, [Mono(D_, q2=1)])
+    lat.noise(psi, [Mono(D_)])
+    lat.init_uniform(phi)
+    lat.init_uniform(psi)
+    m = om.two_field_3d(_olat(n), dt, a=a_, b=b_, k=k_, c=c_, g=g_, D=D_, seed=11)
+    m.init_uniform(0, -0.1, 0.1)
+    m.init_uniform(1, -0.1, 0.1)
+    lat.step(50)
+    m.step(50)
+    for f in (0, 1):
+        assert np.max(np.abs(lat.download(f) - m.real(f)[0])) < 2e-5
+
+
+def test_set_coef_takes_effect():
+    lat, m = _model_b_pair((64, 64), 0, seed=3, D=0.02)
+    lat.step(5)
+    m.step(5)
+    lat.set_coef(1, 0, -2.5)  # cubic term prefactor: -b q^2 with b = 2.5
+    m.terms[1].op[0] = OMono(-2.5, q2=1)
+    m._cache = None
+    lat.set_coef(0, 1, -1.5)  # implicit k q^4 prefactor
+    m.terms[0].op[1] = OMono(-1.5, q2=2)
+    m._cache = None
+    lat.step(20)
+    m.step(20)
+    assert np.max(np.abs(lat.download(0) - m.real(0)[0])) < 2e-5
+
+
+# ------------------------------------------------------- replay and graphs
+def test_graph_chunking_and_restart_are_bitwise():
+    a, _ = _model_b_pair((64, 128), 0, seed=21, D=0.05)
+    a.step(120)
+    ref = a.spectrum(0)
+    b, _ = _model_b_pair((64, 128), 0, seed=21, D=0.05)
+    b.step(50)
+    b.step(1)
+    blob = b.save()
+    b.step(69)
+    assert np.array_equal(b.spectrum(0), ref)
+    c, _ = _model_b_pair((64, 128), 0, seed=21, D=0.05)
+    c.load(blob)
+    assert c.step_index == 51
+    c.step(69)
+    assert np.array_equal(c.spectrum(0), ref)
+
+
+def test_step_zero_and_seed_dependence():
+    a, _ = _model_b_pair((32, 32), 0, seed=1, D=0.05)
+    s0 = a.spectrum(0)
+    a.step(0)
+    assert np.array_equal(a.spectrum(0), s0)
+    b, _ = _model_b_pair((32, 32), 0, seed=2, D=0.05)
+    a.step(5)
+    b.step(5)
+    assert not np.array_equal(a.spectrum(0), b.spectrum(0))
