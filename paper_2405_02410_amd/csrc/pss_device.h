@@ -212,8 +212,11 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
             k0 += PSS_PHILOX_W0;
             k1 += PSS_PHILOX_W1;
         }
-        const uint32_t hi0 = __umulhi(PSS_PHILOX_M0, c.x), lo0 = PSS_PHILOX_M0 * c.x;
-        const uint32_t hi1 = __umulhi(PSS_PHILOX_M1, c.z), lo1 = PSS_PHILOX_M1 * c.z;
+        // 32 x 32 -> 64-bit products: one multiply gives both halves
+        const uint64_t p0 = static_cast<uint64_t>(PSS_PHILOX_M0) * c.x;
+        const uint64_t p1 = static_cast<uint64_t>(PSS_PHILOX_M1) * c.z;
+        const uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
+        const uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
         c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
     }
     return c;

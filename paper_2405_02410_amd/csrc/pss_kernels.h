@@ -16,6 +16,8 @@ enum {
     MODE_INV_OUT = 3,    // update kernel: inverse transform of state `sel` into `out`
     MODE_R2C_IN = 4,     // x kernel: real rows `real_in` -> packed columns `out`
     MODE_C2R_OUT = 5,    // x kernel: packed columns `in` -> real rows `real_out`
+    MODE_YINV = 6,       // y pass (3D): inverse transform, column-0 slots -> packed
+    MODE_YFWD = 7,       // y pass (3D): forward transform, column-0 packed -> slots
 };
 
 // Device arrays used by a launch (all in the packed half-spectrum layout
@@ -34,8 +36,21 @@ struct Bufs {
 struct Geo {
     int tc;       // packed columns per tile
     int rb;       // rows per x-kernel block (even)
-    int ntile;    // tiles (= Nx/2 / tc): update-kernel blocks
+    int ntile;    // tiles (= Nx/2 / tc)
     int nrowblk;  // x-kernel blocks (= rows / rb)
+    int to;       // update kernel: other-index lines per block (3D: y values; 2D: 1)
+    int nublk;    // update-kernel blocks (= ntile * Ny/to in 3D, ntile in 2D)
+    int tz;       // y pass: z values per block
+    int nyblk;    // y-pass blocks (= ntile * Nz/tz)
+    int nz;       // Nz (1 in 2D)
+};
+
+// arrays handled by one y-pass launch
+struct YArgs {
+    const float2* src[PSS_MAXCH];
+    float2* dst[PSS_MAXCH];
+    int ncol[PSS_MAXCH];  // only tiles with columns below ncol are transformed
+    int n;
 };
 
 struct LaunchArgs {
@@ -47,6 +62,8 @@ struct LaunchArgs {
     int step_off;
     const float2* tw_u;  // twiddles of the update-axis length
     const float2* tw_x;  // twiddles of Nx
+    const float2* tw_y;  // twiddles of Ny (3D y passes)
+    int dim;             // 2 or 3
 };
 
 // points per thread of a line of length L when k register arrays of fields
@@ -58,6 +75,7 @@ constexpr int points_per_thread(int L, int k) {
 
 hipError_t launch_update(int mode, int L, int nf, const LaunchArgs& a);
 hipError_t launch_xrow(int mode, int L, int ng, const LaunchArgs& a);
+hipError_t launch_ypass(int mode, int L, const YArgs& ya, const LaunchArgs& a);
 hipError_t launch_advance(hipStream_t s, uint64_t* step_ctr, int64_t k);
 hipError_t launch_init_uniform(hipStream_t s, float* out, int64_t n, uint32_t field, uint32_t key0, uint32_t key1,
                                double lo, double hi);
@@ -68,10 +86,16 @@ int xrow_threads(int L, int ng, int rb);
 
 // register-array count an instantiation is built for (1, 2 or 4 fields)
 inline int field_slots(int n) { return n <= 1 ? 1 : (n == 2 ? 2 : 4); }
-// dynamic LDS of the update kernel: TC padded lines + three column-0 areas
-inline size_t update_lds_bytes(int L, int nf_slots, int tc) {
-    return sizeof(float2) * (static_cast<size_t>(tc) * (L + L / 16) + 3 * static_cast<size_t>(nf_slots) * L);
+// dynamic LDS of the update kernel: TC*TO padded lines + one exchange line
+inline size_t update_lds_bytes(int L, int nf_slots, int tc, int to) {
+    (void)nf_slots;
+    return sizeof(float2) * (static_cast<size_t>(tc) * to * (L + L / 16) + static_cast<size_t>(L));
 }
+// dynamic LDS of the y pass: TC*TZ padded lines + one exchange line per z
+inline size_t ypass_lds_bytes(int L, int tc, int tz) {
+    return sizeof(float2) * (static_cast<size_t>(tc) * tz * (L + L / 16) + static_cast<size_t>(tz) * L);
+}
+int ypass_threads(int L, int tc, int tz);
 // dynamic LDS of the x kernel: RB/2 padded lines + RB staged packed rows
 inline size_t xrow_lds_bytes(int L, int rb) {
     return sizeof(float2) * (static_cast<size_t>(rb / 2) * (L + L / 16) + static_cast<size_t>(rb) * (L / 2 + 1));
@@ -80,5 +104,8 @@ inline size_t xrow_lds_bytes(int L, int rb) {
 // FP64 shell sums of (dV/N)|phi_hat|^2 over the packed state of one field
 hipError_t launch_shells(hipStream_t s, const float2* S, int nx, int ny, int nz, int tc, int ndim,
                          double scale, int nshell, double* sums, unsigned long long* counts);
+
+// points per thread of the y pass
+constexpr int ypass_points(int L) { return L < 16 ? L : 16; }
 
 }  // namespace pss

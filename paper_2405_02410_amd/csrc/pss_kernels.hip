@@ -23,7 +23,7 @@ namespace pss {
 
 // ----------------------------------------------------------------- modes
 struct ModeQ {
-    float q2, invq;
+    float q2;
     float iq[3];
 };
 
@@ -36,24 +36,25 @@ __device__ __forceinline__ ModeQ mode_q(const DevPlan& p, int kx, int ky, int kz
     const float qy = static_cast<float>(ky) * p.qs[1];
     const float qz = static_cast<float>(kz) * p.qs[2];
     m.q2 = qx * qx + qy * qy + qz * qz;
-    m.invq = m.q2 > 0.f ? 1.f / sqrtf(m.q2) : 0.f;
     m.iq[0] = (kx == -(p.n[0] >> 1)) ? 0.f : qx;
     m.iq[1] = (ky == -(p.n[1] >> 1)) ? 0.f : qy;
     m.iq[2] = (p.n[2] > 1 && kz == -(p.n[2] >> 1)) ? 0.f : qz;
     return m;
 }
 
-// sum_m coef (q^2)^a |q|^-b (i qx)^cx (i qy)^cy (i qz)^cz
-__device__ __forceinline__ float2 eval_op(const DevOp& op, const ModeQ& q) {
+// monomials with 1/|q| or i q_i factors (rare): kept out of line so the common
+// pure-q^2 path stays a short Horner loop
+__device__ __noinline__ float2 eval_general(const DevOp& op, float q2, float iqx, float iqy, float iqz) {
+    const float invq = q2 > 0.f ? 1.f / sqrtf(q2) : 0.f;
     float re = 0.f, im = 0.f;
     for (int i = 0; i < op.n; ++i) {
         const DevMono mo = op.m[i];
         float s = mo.coef;
-        for (int e = 0; e < mo.q2; ++e) s *= q.q2;
-        for (int e = 0; e < mo.invq; ++e) s *= q.invq;
-        for (int e = 0; e < mo.ix; ++e) s *= q.iq[0];
-        for (int e = 0; e < mo.iy; ++e) s *= q.iq[1];
-        for (int e = 0; e < mo.iz; ++e) s *= q.iq[2];
+        for (int e = 0; e < mo.q2; ++e) s *= q2;
+        for (int e = 0; e < mo.invq; ++e) s *= invq;
+        for (int e = 0; e < mo.ix; ++e) s *= iqx;
+        for (int e = 0; e < mo.iy; ++e) s *= iqy;
+        for (int e = 0; e < mo.iz; ++e) s *= iqz;
         switch (mo.ipow) {
             case 0: re += s; break;
             case 1: im += s; break;
@@ -62,6 +63,17 @@ __device__ __forceinline__ float2 eval_op(const DevOp& op, const ModeQ& q) {
         }
     }
     return make_float2(re, im);
+}
+
+// sum_m coef (q^2)^a |q|^-b (i qx)^cx (i qy)^cy (i qz)^cz: Horner over the
+// pure q^2 part, then the listed general monomials (none for most models)
+__device__ __forceinline__ float2 eval_op(const DevOp& op, const ModeQ& q) {
+    float re = op.poly[PSS_MAXPOW];
+#pragma unroll
+    for (int j = PSS_MAXPOW - 1; j >= 0; --j) re = fmaf(re, q.q2, op.poly[j]);
+    if (op.n == 0) return make_float2(re, 0.f);
+    const float2 g = eval_general(op, q.q2, q.iq[0], q.iq[1], q.iq[2]);
+    return make_float2(re + g.x, g.y);
 }
 
 // 1 / (1 - dt L(q))
@@ -126,45 +138,188 @@ __device__ __forceinline__ void add_to(float2 (&a)[NF][P], int f, int m, float2 
 }
 
 // ------------------------------------------------------------ update kernel
-// Lines along the last axis u (y in 2D).  Block = one tile of TC packed
-// columns; thread (cc, t) holds u = t + m*T of column ct*TC + cc in v[m].
-// Array element (column c, u) of the tile is at  tile_base + u*TC + cc  with
-// tile_base = ct * (L*TC).
+// Lines along the last axis u (y in 2D, z in 3D).  A block holds TC packed
+// columns x TO values of the other index o (y in 3D; none in 2D); thread
+// (cc, lo, t) keeps u = t + m*T of line (c, o) in v[m].  The state and the
+// channel inputs are [o][ctile][u][TC]; the factor outputs V go to
+// [ctile][u][TC] in 2D and to [u][ctile][o][TC] (the y-pass layout) in 3D.
 //
-// Column 0 holds S = phi(0,k) + i phi(Nx/2,k) with both parts Hermitian along
-// u; its threads unpack with the partner value at -u, which they exchange
-// through LDS (tile 0 only, block-uniform barriers).  LDS layout:
-//   TC line buffers | acc0[NF*L] | accn[NF*L] | old[NF*L] (= channel exchange)
-template <int L, int P, int NF, int MODE>
+// Which modes a line holds (signed indices):
+//   c >= 1           : (c, u, -) in 2D, (c, o, u) in 3D
+//   c = 0, 0<o<Ny/2  : (0, o, u)                          (3D)
+//   c = 0, o>Ny/2    : (-Nx/2, Ny-o, u)                   (3D)
+//   packed line (c = 0 in 2D; c = 0, o in {0, Ny/2} in 3D), slot form:
+//     slot u in (0, L/2)  : kx = 0 at u
+//     slot u in (L/2, L)  : kx = -Nx/2 at L - u
+//     slots 0 and L/2     : (Re of kx = 0, Re of kx = -Nx/2), both real
+// Transforms of a packed line see S(u) = phi(0,u) + i phi(Nx/2,u); the slot
+// form is converted to and from it through one LDS line (block-uniform
+// barriers; a block holds at most one packed line, at (cc, lo) = (0, 0)).
+// LDS: TC*TO padded line buffers | one exchange line of L.
+
+// mode of slot u of a line; `pair` marks the two real modes of slots 0, L/2
+template <int DIM>
+__device__ __forceinline__ void slot_mode(bool packed, int kx_l, int ky_l, int u, int L, int nx, int& kx, int& ky,
+                                          int& kz, bool& pair) {
+    int w = signed_mode(u, L);  // signed index along the line
+    pair = false;
+    if (packed) {
+        const int h = L >> 1;
+        if (u == 0 || u == h) {
+            pair = true;
+            kx = 0;
+        } else if (u < h) {
+            kx = 0;
+        } else {
+            kx = -(nx >> 1);
+            w = L - u;
+        }
+    } else {
+        kx = kx_l;
+    }
+    if (DIM == 2) {
+        ky = w;
+        kz = 0;
+    } else {
+        ky = ky_l;
+        kz = w;
+    }
+}
+
+// full-spectrum linear index and its negative for signed mode indices
+__device__ __forceinline__ void mode_lin(const DevPlan& p, int kx, int ky, int kz, uint32_t& lin, uint32_t& lneg) {
+    const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
+    const int ux = kx & (nx - 1), uy = ky & (ny - 1), uz = kz & (nz - 1);
+    lin = lin_index(p, ux, uy, uz);
+    lneg = lin_index(p, (nx - ux) & (nx - 1), (ny - uy) & (ny - 1), (nz - uz) & (nz - 1));
+}
+
+// packed line: S(u), S(L-u) -> slot value of u (the forward direction)
+template <int L>
+__device__ __forceinline__ float2 to_slot(int u, float2 a, float2 b) {
+    if (u == 0 || u == (L >> 1)) return a;
+    return u < (L >> 1) ? make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y))   // phi(0, u)
+                        : make_float2(0.5f * (a.y + b.y), 0.5f * (a.x - b.x));  // phi(Nx/2, L-u)
+}
+
+// packed line: slot values of u and L-u -> S(u) = phi(0,u) + i phi(Nx/2,u)
+template <int L>
+__device__ __forceinline__ float2 from_slot(int u, float2 s1, float2 s2) {
+    if (u == 0 || u == (L >> 1)) return s1;
+    return u < (L >> 1) ? make_float2(s1.x - s2.y, s1.y + s2.x)   // phi0(u) + i phiN(u)
+                        : make_float2(s2.x + s1.y, s1.x - s2.y);  // conj phi0(L-u) + i conj phiN(L-u)
+}
+
+// the two real self-conjugate modes (kx = 0 and kx = -Nx/2) of slot u in
+// {0, L/2} of a packed line: signed index w of the line axis
+template <int DIM>
+__device__ __forceinline__ void pair_modes(int ky_l, int u, int L, int& ky, int& kz) {
+    const int w = u == 0 ? 0 : -(L >> 1);
+    if (DIM == 2) {
+        ky = w;
+        kz = 0;
+    } else {
+        ky = ky_l;
+        kz = w;
+    }
+}
+
+// op applied to a pair slot (re: kx = 0 mode, im: kx = -Nx/2 mode)
+template <int DIM>
+__device__ __forceinline__ float2 pair_op_d(const DevPlan& p, const DevOp& op, int ky_l, int u, int L, float2 a) {
+    int ky, kz;
+    pair_modes<DIM>(ky_l, u, L, ky, kz);
+    return make_float2(eval_op(op, mode_q(p, 0, ky, kz)).x * a.x,
+                       eval_op(op, mode_q(p, -(p.n[0] >> 1), ky, kz)).x * a.y);
+}
+
+// semi-implicit update of a pair slot
+template <int DIM>
+__device__ __forceinline__ float2 pair_update_d(const DevPlan& p, int f, uint32_t step, int ky_l, int u, int L,
+                                                float2 old, float2 acc, bool noisy) {
+    int ky, kz;
+    pair_modes<DIM>(ky_l, u, L, ky, kz);
+    const int kn = -(p.n[0] >> 1);
+    const ModeQ q0 = mode_q(p, 0, ky, kz), qn = mode_q(p, kn, ky, kz);
+    float2 r = cadd(old, cscale(acc, p.dt));
+    if (noisy) {
+        uint32_t lin, lneg;
+        mode_lin(p, 0, ky, kz, lin, lneg);
+        r.x += noise_mode(p, f, step, lin, lneg, q0).x;
+        mode_lin(p, kn, ky, kz, lin, lneg);
+        r.y += noise_mode(p, f, step, lin, lneg, qn).x;
+    }
+    return make_float2(r.x * implicit_inv(p, f, q0).x, r.y * implicit_inv(p, f, qn).x);
+}
+
+template <int L, int P, int NF, int MODE, int DIM>
 __global__ void __launch_bounds__(256) update_kernel(const DevPlan* __restrict__ plan, Bufs bufs, Geo geo,
                                                       const uint64_t* __restrict__ step_ctr,
                                                       int step_off, const float2* __restrict__ tw) {
     constexpr int T = L / P;
     extern __shared__ float2 smem[];
     const DevPlan& p = *plan;
-    const int tc = geo.tc;
+    const int tc = geo.tc, to = geo.to;
+    const int ntile = geo.ntile;
     const int tid = threadIdx.x;
     const int cc = tid % tc;
-    const int t = tid / tc;
-    const int ct = blockIdx.x;    // tile index
-    const int c = ct * tc + cc;   // packed column
-    const size_t base = static_cast<size_t>(ct) * (L * tc) + cc;
-    float2* line = smem + cc * lds_line(L);
-    float2* acc0 = smem + tc * lds_line(L);  // kx = 0 accumulators, then new phi(0,k)
-    float2* accn = acc0 + NF * L;            // kx = Nx/2 accumulators, then new phi(Nx/2,k)
-    float2* oldb = accn + NF * L;            // old column-0 state
-    float2* xbuf = oldb;                     // channel exchange; done before oldb is written
-    const bool col0 = (c == 0);
-    const bool tile0 = (ct == 0);
-    const int nx = p.n[0];
+    const int lo = (tid / tc) % to;
+    const int t = tid / (tc * to);
+    const int ct = blockIdx.x % ntile;  // tile index
+    const int og = blockIdx.x / ntile;  // group of `to` other-index lines
+    const int o = og * to + lo;
+    const int c = ct * tc + cc;         // packed column
+    const int nx = p.n[0], ny = p.n[1];
+    const size_t base = (static_cast<size_t>(o) * ntile + ct) * L * tc + cc;
+    const size_t vbase = DIM == 2 ? base : (static_cast<size_t>(ct) * ny + o) * tc + cc;
+    const size_t vstride = DIM == 2 ? static_cast<size_t>(tc) : static_cast<size_t>(ntile) * ny * tc;
+    float2* line = smem + (lo * tc + cc) * lds_line(L);
+    float2* xbuf = smem + tc * to * lds_line(L);  // packed-line exchange
+    // block holds a packed line (block-uniform); this thread is on it
+    const bool blk_packed = ct == 0 && (DIM == 2 || og * to == 0 || og * to == (ny >> 1));
+    const bool packed = blk_packed && cc == 0 && lo == 0;
+    // fixed mode indices of a plain line
+    int kx_l = c, ky_l = 0;
+    if (DIM == 3) {
+        ky_l = signed_mode(o, ny);
+        if (c == 0 && !packed) {
+            if (o < (ny >> 1)) {
+                kx_l = 0;
+                ky_l = o;
+            } else {
+                kx_l = -(nx >> 1);
+                ky_l = ny - o;
+            }
+        }
+    }
     const int nf = p.nf;
 
+    // packed line only: exchange v with the partner -u and map it (block-uniform)
+    auto exchange = [&](float2 (&v)[P], bool forward) {
+        if (!blk_packed) return;
+        if (packed) {
+#pragma unroll
+            for (int m = 0; m < P; ++m) xbuf[t + m * T] = v[m];
+        }
+        __syncthreads();
+        if (packed) {
+#pragma unroll
+            for (int m = 0; m < P; ++m) {
+                const int u = t + m * T;
+                const float2 b = xbuf[(L - u) & (L - 1)];
+                v[m] = forward ? to_slot<L>(u, v[m], b) : from_slot<L>(u, v[m], b);
+            }
+        }
+        __syncthreads();
+    };
+
     if constexpr (MODE == MODE_FWD_STORE) {
-        // forward transform of an x-transformed array, stored as the state
+        // forward transform of an array in the state layout, stored as the state
         float2 v[P];
 #pragma unroll
         for (int m = 0; m < P; ++m) v[m] = bufs.in[base + (t + m * T) * tc];
         fft_line<L, P, -1>(v, line, t, tw);
+        exchange(v, true);
 #pragma unroll
         for (int m = 0; m < P; ++m) bufs.S[bufs.sel][base + (t + m * T) * tc] = v[m];
         return;
@@ -173,69 +328,15 @@ __global__ void __launch_bounds__(256) update_kernel(const DevPlan* __restrict__
         float2 v[P];
 #pragma unroll
         for (int m = 0; m < P; ++m) v[m] = bufs.S[bufs.sel][base + (t + m * T) * tc];
+        exchange(v, false);
         fft_line<L, P, 1>(v, line, t, tw);
 #pragma unroll
-        for (int m = 0; m < P; ++m) bufs.out[base + (t + m * T) * tc] = v[m];
+        for (int m = 0; m < P; ++m) bufs.out[vbase + (t + m * T) * vstride] = v[m];
         return;
     }
 
     // ---- MODE_STEP or MODE_PROLOGUE
-    // Column-0 threads keep everything in LDS and loop over their modes at run
-    // time; the other threads keep register arrays indexed by constants.
-    const uint32_t step = static_cast<uint32_t>(*step_ctr) + static_cast<uint32_t>(step_off);
-    float2 s[NF][P];    // state, then new state
-    float2 acc[NF][P];  // explicit contributions at kx = c
-#pragma unroll
-    for (int f = 0; f < NF; ++f)
-#pragma unroll
-        for (int m = 0; m < P; ++m) acc[f][m] = make_float2(0.f, 0.f);
-
-    if constexpr (MODE == MODE_STEP) {
-        if (col0)
-            for (int i = t; i < NF * L; i += T) {
-                acc0[i] = make_float2(0.f, 0.f);
-                accn[i] = make_float2(0.f, 0.f);
-            }
-        // explicit real-space channels
-        for (int ch = 0; ch < p.nch; ++ch) {
-            const DevChannel& C = p.ch[ch];
-            float2 v[P];
-#pragma unroll
-            for (int m = 0; m < P; ++m) v[m] = bufs.N[ch][base + (t + m * T) * tc];
-            fft_line<L, P, -1>(v, line, t, tw);
-            if (tile0) {
-                if (col0) {
-#pragma unroll
-                    for (int m = 0; m < P; ++m) xbuf[t + m * T] = v[m];
-                }
-                __syncthreads();
-                if (col0) {
-#pragma unroll 1
-                    for (int m = 0; m < P; ++m) {
-                        const int u = t + m * T;
-                        const float2 a = xbuf[u], b = xbuf[(L - u) & (L - 1)];
-                        // unpack the kx = 0 and kx = Nx/2 parts
-                        const float2 n0 = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
-                        const float2 nn = make_float2(0.5f * (a.y + b.y), 0.5f * (b.x - a.x));
-                        const int ku = signed_mode(u, L);
-                        const int o = C.target * L + u;
-                        acc0[o] = cadd(acc0[o], cmul(eval_op(C.op, mode_q(p, 0, ku, 0)), n0));
-                        accn[o] = cadd(accn[o], cmul(eval_op(C.op, mode_q(p, -(nx >> 1), ku, 0)), nn));
-                    }
-                }
-                __syncthreads();
-            }
-            if (!col0) {
-#pragma unroll
-                for (int m = 0; m < P; ++m) {
-                    const ModeQ q = mode_q(p, c, signed_mode(t + m * T, L), 0);
-                    add_to(acc, C.target, m, cmul(eval_op(C.op, q), v[m]));
-                }
-            }
-        }
-    }
-
-    // old state; column 0 parks it in LDS for the partner reads
+    float2 s[NF][P];  // state, then new state (slot form on a packed line)
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         if (f < nf) {
@@ -245,111 +346,185 @@ __global__ void __launch_bounds__(256) update_kernel(const DevPlan* __restrict__
 #pragma unroll
             for (int m = 0; m < P; ++m) s[f][m] = make_float2(0.f, 0.f);
         }
-        if (col0) {
-#pragma unroll
-            for (int m = 0; m < P; ++m) oldb[f * L + t + m * T] = s[f][m];
-        }
     }
-    if (tile0) __syncthreads();
 
-    if (!col0) {
-        if constexpr (MODE == MODE_STEP) {
-            // Fourier-space terms with a single linear factor
-            for (int d = 0; d < p.nd; ++d) {
-                const DevDirect& Dd = p.direct[d];
+    if constexpr (MODE == MODE_STEP) {
+        const uint32_t step = static_cast<uint32_t>(*step_ctr) + static_cast<uint32_t>(step_off);
+        float2 acc[NF][P];  // explicit contributions
 #pragma unroll
-                for (int m = 0; m < P; ++m) {
-                    const ModeQ q = mode_q(p, c, signed_mode(t + m * T, L), 0);
-                    add_to(acc, Dd.target, m, cmul(eval_op(Dd.op, q), pick(s, Dd.src, m)));
-                }
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int m = 0; m < P; ++m) acc[f][m] = make_float2(0.f, 0.f);
+        // explicit real-space channels: forward transform, then M(q) per mode
+        for (int ch = 0; ch < p.nch; ++ch) {
+            const DevChannel& C = p.ch[ch];
+            float2 v[P];
+#pragma unroll
+            for (int m = 0; m < P; ++m) v[m] = bufs.N[ch][base + (t + m * T) * tc];
+            fft_line<L, P, -1>(v, line, t, tw);
+            exchange(v, true);
+#pragma unroll
+            for (int m = 0; m < P; ++m) {
+                int kx, ky, kz;
+                bool pair;
+                slot_mode<DIM>(packed, kx_l, ky_l, t + m * T, L, nx, kx, ky, kz, pair);
+                if (!pair) add_to(acc, C.target, m, cmul(eval_op(C.op, mode_q(p, kx, ky, kz)), v[m]));
             }
-            // semi-implicit update with noise
-#pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                if (f >= nf) continue;
-                const bool noisy = p.noisy[f] != 0;
-#pragma unroll
-                for (int m = 0; m < P; ++m) {
-                    const int u = t + m * T;
-                    const ModeQ q = mode_q(p, c, signed_mode(u, L), 0);
-                    float2 r = cadd(s[f][m], cscale(acc[f][m], p.dt));
-                    if (noisy) r = cadd(r, noise_mode(p, f, step, lin_index(p, c, u, 0), lin_neg(p, c, u, 0), q));
-                    s[f][m] = cmul(r, implicit_inv(p, f, q));
-                    bufs.S[f][base + u * tc] = s[f][m];
-                }
-            }
-        }
-    } else {
-        // column 0: unpack S = phi(0,k) + i phi(Nx/2,k) with the partner -u
-        if constexpr (MODE == MODE_STEP) {
-            for (int d = 0; d < p.nd; ++d) {
-                const DevDirect& Dd = p.direct[d];
-#pragma unroll 1
-                for (int m = 0; m < P; ++m) {
-                    const int u = t + m * T;
-                    const int ku = signed_mode(u, L);
-                    const float2 a = oldb[Dd.src * L + u], b = oldb[Dd.src * L + ((L - u) & (L - 1))];
-                    const float2 n0 = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
-                    const float2 nn = make_float2(0.5f * (a.y + b.y), 0.5f * (b.x - a.x));
-                    const int o = Dd.target * L + u;
-                    acc0[o] = cadd(acc0[o], cmul(eval_op(Dd.op, mode_q(p, 0, ku, 0)), n0));
-                    accn[o] = cadd(accn[o], cmul(eval_op(Dd.op, mode_q(p, -(nx >> 1), ku, 0)), nn));
-                }
+            if (packed && t == 0) {
+                // slots 0 and L/2: two real modes (operators are real on them)
+                add_to(acc, C.target, 0, pair_op_d<DIM>(p, C.op, ky_l, 0, L, v[0]));
+                add_to(acc, C.target, P / 2, pair_op_d<DIM>(p, C.op, ky_l, L >> 1, L, v[P / 2]));
             }
         }
-        for (int f = 0; f < nf; ++f) {
+        // Fourier-space terms with a single linear factor
+        for (int d = 0; d < p.nd; ++d) {
+            const DevDirect& Dd = p.direct[d];
+#pragma unroll
+            for (int m = 0; m < P; ++m) {
+                int kx, ky, kz;
+                bool pair;
+                slot_mode<DIM>(packed, kx_l, ky_l, t + m * T, L, nx, kx, ky, kz, pair);
+                if (!pair) add_to(acc, Dd.target, m, cmul(eval_op(Dd.op, mode_q(p, kx, ky, kz)), pick(s, Dd.src, m)));
+            }
+            if (packed && t == 0) {
+                add_to(acc, Dd.target, 0, pair_op_d<DIM>(p, Dd.op, ky_l, 0, L, pick(s, Dd.src, 0)));
+                add_to(acc, Dd.target, P / 2, pair_op_d<DIM>(p, Dd.op, ky_l, L >> 1, L, pick(s, Dd.src, P / 2)));
+            }
+        }
+        // semi-implicit update (eq:timeupdate) with in-register noise
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if (f >= nf) continue;
             const bool noisy = p.noisy[f] != 0;
-#pragma unroll 1
+            const float2 old0 = s[f][0], oldh = s[f][P / 2];
+#pragma unroll
             for (int m = 0; m < P; ++m) {
                 const int u = t + m * T;
-                const int ku = signed_mode(u, L);
-                const float2 a = oldb[f * L + u], b = oldb[f * L + ((L - u) & (L - 1))];
-                float2 s0 = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
-                float2 sn = make_float2(0.5f * (a.y + b.y), 0.5f * (b.x - a.x));
-                if constexpr (MODE == MODE_STEP) {
-                    const ModeQ q0 = mode_q(p, 0, ku, 0);
-                    const ModeQ qn = mode_q(p, -(nx >> 1), ku, 0);
-                    s0 = cadd(s0, cscale(acc0[f * L + u], p.dt));
-                    sn = cadd(sn, cscale(accn[f * L + u], p.dt));
-                    if (noisy) {
-                        s0 = cadd(s0, noise_mode(p, f, step, lin_index(p, 0, u, 0), lin_neg(p, 0, u, 0), q0));
-                        sn = cadd(sn, noise_mode(p, f, step, lin_index(p, nx >> 1, u, 0),
-                                                 lin_neg(p, nx >> 1, u, 0), qn));
-                    }
-                    s0 = cmul(s0, implicit_inv(p, f, q0));
-                    sn = cmul(sn, implicit_inv(p, f, qn));
-                    bufs.S[f][base + u * tc] = make_float2(s0.x - sn.y, s0.y + sn.x);  // s0 + i sn
+                int kx, ky, kz;
+                bool pair;
+                slot_mode<DIM>(packed, kx_l, ky_l, u, L, nx, kx, ky, kz, pair);
+                const ModeQ q = mode_q(p, kx, ky, kz);
+                float2 r = cadd(s[f][m], cscale(acc[f][m], p.dt));
+                if (noisy) {
+                    uint32_t lin, lneg;
+                    mode_lin(p, kx, ky, kz, lin, lneg);
+                    r = cadd(r, noise_mode(p, f, step, lin, lneg, q));
                 }
-                // own slots only: the new halves for the inverse transforms
-                acc0[f * L + u] = s0;
-                accn[f * L + u] = sn;
+                s[f][m] = cmul(r, implicit_inv(p, f, q));
             }
+            if (packed && t == 0) {
+                // slots 0 and L/2 hold two real modes each
+                s[f][0] = pair_update_d<DIM>(p, f, step, ky_l, 0, L, old0, acc[f][0], noisy);
+                s[f][P / 2] = pair_update_d<DIM>(p, f, step, ky_l, L >> 1, L, oldh, acc[f][P / 2], noisy);
+            }
+#pragma unroll
+            for (int m = 0; m < P; ++m) bufs.S[f][base + (t + m * T) * tc] = s[f][m];
         }
     }
 
-    // de-aliased inverse transforms of every factor field
+    // de-aliased inverse transforms of every factor field (eq:cubicexampledealiased)
     for (int g = 0; g < p.ng; ++g) {
         const DevMask& mk = p.mask[g];
-        if (ct * tc >= mk.ncol) continue;  // whole tile masked: never read
+        if (ct * tc >= mk.ncol) continue;  // whole tile masked: never read (block-uniform)
         const int fg = p.gfield[g];
         float2 v[P];
-        if (!col0) {
 #pragma unroll
-            for (int m = 0; m < P; ++m)
-                v[m] = mask_keep(mk, c, signed_mode(t + m * T, L), 0) ? pick(s, fg, m) : make_float2(0.f, 0.f);
-        } else {
-#pragma unroll
-            for (int m = 0; m < P; ++m) {
-                const int u = t + m * T;
-                const int ku = signed_mode(u, L);
-                const float2 z0 = mask_keep(mk, 0, ku, 0) ? acc0[fg * L + u] : make_float2(0.f, 0.f);
-                const float2 zn = mask_keep(mk, -(nx >> 1), ku, 0) ? accn[fg * L + u] : make_float2(0.f, 0.f);
-                v[m] = make_float2(z0.x - zn.y, z0.y + zn.x);
+        for (int m = 0; m < P; ++m) {
+            int kx, ky, kz;
+            bool pair;
+            slot_mode<DIM>(packed, kx_l, ky_l, t + m * T, L, nx, kx, ky, kz, pair);
+            const float2 a = pick(s, fg, m);
+            if (!pair) {
+                v[m] = mask_keep(mk, kx, ky, kz) ? a : make_float2(0.f, 0.f);
+            } else {
+                v[m] = make_float2(mask_keep(mk, 0, ky, kz) ? a.x : 0.f,
+                                   mask_keep(mk, -(nx >> 1), ky, kz) ? a.y : 0.f);
             }
         }
+        exchange(v, false);
         fft_line<L, P, 1>(v, line, t, tw);
 #pragma unroll
-        for (int m = 0; m < P; ++m) bufs.V[g][base + (t + m * T) * tc] = v[m];
+        for (int m = 0; m < P; ++m) bufs.V[g][vbase + (t + m * T) * vstride] = v[m];
+    }
+}
+
+// ----------------------------------------------------------------- y pass
+// 3D only: lines along y for fixed (c, z); block = TC columns x TZ values of
+// z.  Input [z][ctile][y][TC].  The inverse pass writes the same layout, the
+// forward pass writes the state layout [y][ctile][z][TC].
+//
+// Column 0 arrives from the x pass as X(0) + i X(Nx/2), both real; after the
+// forward y transform it is Y(ky) = Y0(ky) + i YN(ky) with Y0, YN Hermitian
+// in ky.  The forward pass re-packs it so that every z line of column 0
+// except ky = 0, Ny/2 holds single modes:
+//   slot ky in (0, Ny/2)   : Y0(ky)          (modes kx = 0)
+//   slot Ny-ky             : YN(ky)          (modes kx = Nx/2)
+//   slots 0 and Ny/2       : Y unchanged     (packed, Hermitian along z)
+// and the inverse pass undoes it before transforming.
+template <int L, int P, int MODE>
+__global__ void __launch_bounds__(256) ypass_kernel(YArgs ya, Geo geo, const float2* __restrict__ tw) {
+    constexpr int T = L / P;
+    extern __shared__ float2 smem[];
+    const int tc = geo.tc, tz = geo.tz;
+    const int ntile = geo.ntile;
+    const int nz = geo.nz;
+    const int tid = threadIdx.x;
+    const int cc = tid % tc;
+    const int lz = (tid / tc) % tz;
+    const int t = tid / (tc * tz);
+    const int ct = blockIdx.x % ntile;
+    const int z = (blockIdx.x / ntile) * tz + lz;
+    const int c = ct * tc + cc;
+    float2* line = smem + (lz * tc + cc) * lds_line(L);
+    float2* xb = smem + tc * tz * lds_line(L) + lz * L;  // column-0 exchange, one line per z
+    const size_t ibase = (static_cast<size_t>(z) * ntile + ct) * L * tc + cc;
+    const size_t obase = MODE == MODE_YFWD ? (static_cast<size_t>(ct) * nz + z) * tc + cc : ibase;
+    const size_t ostride = MODE == MODE_YFWD ? static_cast<size_t>(ntile) * nz * tc : static_cast<size_t>(tc);
+
+    for (int a = 0; a < ya.n; ++a) {
+        if (ct * tc >= ya.ncol[a]) continue;  // tile holds no kept column (block-uniform)
+        const float2* __restrict__ src = ya.src[a];
+        float2* __restrict__ dst = ya.dst[a];
+        float2 v[P];
+        if constexpr (MODE == MODE_YINV) {
+#pragma unroll
+            for (int m = 0; m < P; ++m) {
+                const int y = t + m * T;
+                const float2 s1 = src[ibase + y * tc];
+                if (c == 0 && y != 0 && y != (L >> 1)) {
+                    const float2 s2 = src[ibase + (L - y) * tc];
+                    v[m] = y < (L >> 1) ? make_float2(s1.x - s2.y, s1.y + s2.x)   // Y0 + i YN
+                                        : make_float2(s2.x + s1.y, s1.x - s2.y);  // conj(Y0) + i conj(YN)
+                } else {
+                    v[m] = s1;
+                }
+            }
+            fft_line<L, P, 1>(v, line, t, tw);
+        } else {
+#pragma unroll
+            for (int m = 0; m < P; ++m) v[m] = src[ibase + (t + m * T) * tc];
+            fft_line<L, P, -1>(v, line, t, tw);
+            if (ct == 0) {
+                if (c == 0) {
+#pragma unroll
+                    for (int m = 0; m < P; ++m) xb[t + m * T] = v[m];
+                }
+                __syncthreads();
+                if (c == 0) {
+#pragma unroll
+                    for (int m = 0; m < P; ++m) {
+                        const int y = t + m * T;
+                        if (y == 0 || y == (L >> 1)) continue;
+                        const float2 a0 = v[m], b0 = xb[L - y];
+                        v[m] = y < (L >> 1) ? make_float2(0.5f * (a0.x + b0.x), 0.5f * (a0.y - b0.y))   // Y0(y)
+                                            : make_float2(0.5f * (a0.y + b0.y), 0.5f * (a0.x - b0.x));  // YN(L-y)
+                    }
+                }
+                __syncthreads();
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < P; ++m) dst[obase + (t + m * T) * ostride] = v[m];
     }
 }
 
@@ -370,8 +545,10 @@ __global__ void __launch_bounds__(256) xrow_kernel(const DevPlan* __restrict__ p
     const int nthr = blockDim.x;
     const int pr = tid / T;  // pair within the block
     const int t = tid % T;
-    const int y0 = blockIdx.x * rb;  // first row (2D: y)
+    const int r0 = blockIdx.x * rb;  // first row; row index = z*Ny + y
     const int ny = p.n[1];
+    const int zr = r0 / ny;          // z of the block (0 in 2D)
+    const int y0 = r0 - zr * ny;     // first y of the block
     float2* line = smem + pr * lds_line(L);
     float2* stage = smem + (rb / 2) * lds_line(L);  // rb x NC (+pad)
     const int spitch = NC + 1;
@@ -383,25 +560,25 @@ __global__ void __launch_bounds__(256) xrow_kernel(const DevPlan* __restrict__ p
         for (int i = tid; i < nt * per; i += nthr) {
             const int tl = i / per, rem = i - tl * per;
             const int r = rem / tc, cc = rem - r * tc;
-            stage[r * spitch + tl * tc + cc] = src[(static_cast<size_t>(tl) * ny + y0 + r) * tc + cc];
+            stage[r * spitch + tl * tc + cc] = src[((static_cast<size_t>(zr) * ntile + tl) * ny + y0 + r) * tc + cc];
         }
     };
     // build the packed complex input Z[k] = X_row0[k] + i X_row1[k] of pair pr
     auto build_z = [&](float2 (&v)[P], int ncol) {
-        const float2* r0 = stage + (2 * pr) * spitch;
-        const float2* r1 = r0 + spitch;
+        const float2* row0 = stage + (2 * pr) * spitch;
+        const float2* row1 = row0 + spitch;
 #pragma unroll
         for (int m = 0; m < P; ++m) {
             const int k = t + m * T;
             float2 z;
             if (k == 0) {
-                z = make_float2(r0[0].x, r1[0].x);
+                z = make_float2(row0[0].x, row1[0].x);
             } else if (k == NC) {
-                z = make_float2(r0[0].y, r1[0].y);
+                z = make_float2(row0[0].y, row1[0].y);
             } else {
                 const int kk = k < NC ? k : L - k;
-                const float2 a = kk < ncol ? r0[kk] : make_float2(0.f, 0.f);
-                const float2 b = kk < ncol ? r1[kk] : make_float2(0.f, 0.f);
+                const float2 a = kk < ncol ? row0[kk] : make_float2(0.f, 0.f);
+                const float2 b = kk < ncol ? row1[kk] : make_float2(0.f, 0.f);
                 z = k < NC ? make_float2(a.x - b.y, a.y + b.x) : make_float2(a.x + b.y, b.x - a.y);
             }
             v[m] = z;
@@ -424,7 +601,7 @@ __global__ void __launch_bounds__(256) xrow_kernel(const DevPlan* __restrict__ p
                 o = (r & 1) ? make_float2(0.5f * (a.y + b.y), 0.5f * (b.x - a.x))
                             : make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
             }
-            dst[(static_cast<size_t>(tl) * ny + y0 + r) * tc + cc] = o;
+            dst[((static_cast<size_t>(zr) * ntile + tl) * ny + y0 + r) * tc + cc] = o;
         }
     };
 
@@ -435,8 +612,8 @@ __global__ void __launch_bounds__(256) xrow_kernel(const DevPlan* __restrict__ p
 #pragma unroll
         for (int m = 0; m < P; ++m) {
             const int x = t + m * T;
-            v[m] = make_float2(src[static_cast<size_t>(y0 + 2 * pr) * L + x],
-                               src[static_cast<size_t>(y0 + 2 * pr + 1) * L + x]);
+            v[m] = make_float2(src[static_cast<size_t>(r0 + 2 * pr) * L + x],
+                               src[static_cast<size_t>(r0 + 2 * pr + 1) * L + x]);
         }
         fft_line<L, P, -1>(v, line, t, tw);
 #pragma unroll
@@ -455,8 +632,8 @@ __global__ void __launch_bounds__(256) xrow_kernel(const DevPlan* __restrict__ p
 #pragma unroll
         for (int m = 0; m < P; ++m) {
             const int x = t + m * T;
-            dst[static_cast<size_t>(y0 + 2 * pr) * L + x] = v[m].x * p.inv_n;
-            dst[static_cast<size_t>(y0 + 2 * pr + 1) * L + x] = v[m].y * p.inv_n;
+            dst[static_cast<size_t>(r0 + 2 * pr) * L + x] = v[m].x * p.inv_n;
+            dst[static_cast<size_t>(r0 + 2 * pr + 1) * L + x] = v[m].y * p.inv_n;
         }
         return;
     }
@@ -543,8 +720,8 @@ __device__ __forceinline__ void shell_add(double* sums, unsigned int* cnt, int n
     }
 }
 
-__global__ void shells_kernel(const float2* __restrict__ S, int nx, int ny, int tc, double scale, int nshell,
-                              double* __restrict__ gsum, unsigned long long* __restrict__ gcnt) {
+__global__ void shells_kernel(const float2* __restrict__ S, int nx, int ny, int nz, int tc, int dim, double scale,
+                              int nshell, double* __restrict__ gsum, unsigned long long* __restrict__ gcnt) {
     extern __shared__ double lsum[];
     unsigned int* lcnt = reinterpret_cast<unsigned int*>(lsum + nshell);
     for (int i = threadIdx.x; i < nshell; i += blockDim.x) {
@@ -553,25 +730,55 @@ __global__ void shells_kernel(const float2* __restrict__ S, int nx, int ny, int 
     }
     __syncthreads();
     const int ncols = nx / 2;
-    const int64_t total = static_cast<int64_t>(ncols) * ny;
+    const int ntile = ncols / tc;
+    const int64_t total = static_cast<int64_t>(ncols) * ny * nz;
+    auto mag = [](float2 v) { return static_cast<double>(v.x) * v.x + static_cast<double>(v.y) * v.y; };
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
          e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int cc = static_cast<int>(e % tc);
         const int64_t r = e / tc;
-        const int y = static_cast<int>(r % ny);
-        const int ct = static_cast<int>(r / ny);
-        const int c = ct * tc + cc;
+        int c, y, z;
+        if (dim == 2) {
+            y = static_cast<int>(r % ny);
+            c = static_cast<int>(r / ny) * tc + cc;
+            z = 0;
+        } else {
+            z = static_cast<int>(r % nz);
+            const int64_t r2 = r / nz;
+            c = static_cast<int>(r2 % ntile) * tc + cc;
+            y = static_cast<int>(r2 / ntile);
+        }
         const int ky = y < ny / 2 ? y : y - ny;
+        const int kz = nz == 1 ? 0 : (z < nz / 2 ? z : z - nz);
         const float2 a = S[e];
         if (c > 0) {
-            const double v = scale * (static_cast<double>(a.x) * a.x + static_cast<double>(a.y) * a.y);
-            shell_add(lsum, lcnt, nshell, c, ky, 0, v, 2u);
+            shell_add(lsum, lcnt, nshell, c, ky, kz, scale * mag(a), 2u);
+            continue;
+        }
+        // column 0: slot form along the update axis on packed lines
+        const bool packed = dim == 2 || y == 0 || y == ny / 2;
+        if (!packed) {
+            if (y < ny / 2)
+                shell_add(lsum, lcnt, nshell, 0, y, kz, scale * mag(a), 2u);
+            else
+                shell_add(lsum, lcnt, nshell, -(nx / 2), ny - y, kz, scale * mag(a), 2u);
+            continue;
+        }
+        const int L = dim == 2 ? ny : nz;
+        const int u = dim == 2 ? y : z;
+        const int ky0 = dim == 2 ? 0 : ky;
+        auto at = [&](int w) { return dim == 2 ? make_int2(w, 0) : make_int2(ky0, w); };  // (ky, kz) of index w
+        if (u == 0 || u == L / 2) {
+            const int w = u == 0 ? 0 : -(L / 2);
+            const int2 yz = at(w);
+            shell_add(lsum, lcnt, nshell, 0, yz.x, yz.y, scale * static_cast<double>(a.x) * a.x, 1u);
+            shell_add(lsum, lcnt, nshell, -(nx / 2), yz.x, yz.y, scale * static_cast<double>(a.y) * a.y, 1u);
+        } else if (u < L / 2) {
+            const int2 yz = at(u);
+            shell_add(lsum, lcnt, nshell, 0, yz.x, yz.y, scale * mag(a), 2u);
         } else {
-            const float2 b = S[static_cast<int64_t>((ny - y) & (ny - 1)) * tc];
-            const double r0 = 0.5 * (static_cast<double>(a.x) + b.x), i0 = 0.5 * (static_cast<double>(a.y) - b.y);
-            const double rn = 0.5 * (static_cast<double>(a.y) + b.y), in = 0.5 * (static_cast<double>(b.x) - a.x);
-            shell_add(lsum, lcnt, nshell, 0, ky, 0, scale * (r0 * r0 + i0 * i0), 1u);
-            shell_add(lsum, lcnt, nshell, -(nx / 2), ky, 0, scale * (rn * rn + in * in), 1u);
+            const int2 yz = at(L - u);
+            shell_add(lsum, lcnt, nshell, -(nx / 2), yz.x, yz.y, scale * mag(a), 2u);
         }
     }
     __syncthreads();
@@ -589,32 +796,37 @@ __global__ void shells_kernel(const float2* __restrict__ S, int nx, int ny, int 
 // kernels of that length) and once with -DPSS_COMMON (utilities and the
 // length dispatch), so the instantiations build in parallel.
 #if defined(PSS_LINE_LEN)
-template <int L, int P, int NF>
-static hipError_t launch_update_t(int mode, const LaunchArgs& a) {
-    const int threads = a.geo.tc * (L / P);
-    const size_t lds = update_lds_bytes(L, NF, a.geo.tc);
-    dim3 grid(a.geo.ntile), block(threads);
+template <int L, int P, int NF, int DIM>
+static hipError_t launch_update_d(int mode, const LaunchArgs& a) {
+    const int threads = a.geo.tc * a.geo.to * (L / P);
+    const size_t lds = update_lds_bytes(L, NF, a.geo.tc, a.geo.to);
+    dim3 grid(a.geo.nublk), block(threads);
     switch (mode) {
         case MODE_STEP:
-            hipLaunchKernelGGL((update_kernel<L, P, NF, MODE_STEP>), grid, block, lds, a.stream, a.plan, a.bufs,
-                               a.geo, a.step_ctr, a.step_off, a.tw_u);
+            hipLaunchKernelGGL((update_kernel<L, P, NF, MODE_STEP, DIM>), grid, block, lds, a.stream, a.plan,
+                               a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
             break;
         case MODE_PROLOGUE:
-            hipLaunchKernelGGL((update_kernel<L, P, NF, MODE_PROLOGUE>), grid, block, lds, a.stream, a.plan,
+            hipLaunchKernelGGL((update_kernel<L, P, NF, MODE_PROLOGUE, DIM>), grid, block, lds, a.stream, a.plan,
                                a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
             break;
         case MODE_FWD_STORE:
-            hipLaunchKernelGGL((update_kernel<L, P, 1, MODE_FWD_STORE>), grid, block, lds, a.stream, a.plan,
+            hipLaunchKernelGGL((update_kernel<L, P, 1, MODE_FWD_STORE, DIM>), grid, block, lds, a.stream, a.plan,
                                a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
             break;
         case MODE_INV_OUT:
-            hipLaunchKernelGGL((update_kernel<L, P, 1, MODE_INV_OUT>), grid, block, lds, a.stream, a.plan,
+            hipLaunchKernelGGL((update_kernel<L, P, 1, MODE_INV_OUT, DIM>), grid, block, lds, a.stream, a.plan,
                                a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
             break;
         default:
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int L, int P, int NF>
+static hipError_t launch_update_t(int mode, const LaunchArgs& a) {
+    return a.dim == 3 ? launch_update_d<L, P, NF, 3>(mode, a) : launch_update_d<L, P, NF, 2>(mode, a);
 }
 
 template <int L, int P, int NG>
@@ -657,6 +869,22 @@ hipError_t PSS_CAT(launch_update_L, PSS_LINE_LEN)(int mode, int nf, const Launch
     }
 }
 
+hipError_t PSS_CAT(launch_ypass_L, PSS_LINE_LEN)(int mode, const YArgs& ya, const LaunchArgs& a) {
+    constexpr int L = PSS_LINE_LEN;
+    constexpr int P = ypass_points(L);
+    const int threads = a.geo.tc * a.geo.tz * (L / P);
+    const size_t lds = ypass_lds_bytes(L, a.geo.tc, a.geo.tz);
+    dim3 grid(a.geo.nyblk), block(threads);
+    if (mode == MODE_YINV) {
+        hipLaunchKernelGGL((ypass_kernel<L, P, MODE_YINV>), grid, block, lds, a.stream, ya, a.geo, a.tw_y);
+    } else if (mode == MODE_YFWD) {
+        hipLaunchKernelGGL((ypass_kernel<L, P, MODE_YFWD>), grid, block, lds, a.stream, ya, a.geo, a.tw_y);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t PSS_CAT(launch_xrow_L, PSS_LINE_LEN)(int mode, int ng, const LaunchArgs& a) {
     constexpr int L = PSS_LINE_LEN;
     constexpr int P = points_per_thread(L, 1);
@@ -673,8 +901,9 @@ hipError_t PSS_CAT(launch_xrow_L, PSS_LINE_LEN)(int mode, int ng, const LaunchAr
 #endif  // PSS_LINE_LEN
 
 #if defined(PSS_COMMON)
-#define PSS_DECL_L(L)                                                         \
-    hipError_t launch_update_L##L(int mode, int nf, const LaunchArgs& a);    \
+#define PSS_DECL_L(L)                                                               \
+    hipError_t launch_update_L##L(int mode, int nf, const LaunchArgs& a);          \
+    hipError_t launch_ypass_L##L(int mode, const YArgs& ya, const LaunchArgs& a);  \
     hipError_t launch_xrow_L##L(int mode, int ng, const LaunchArgs& a);
 PSS_DECL_L(8)
 PSS_DECL_L(16)
@@ -713,6 +942,24 @@ hipError_t launch_update(int mode, int L, int nf, const LaunchArgs& a) {
     }
 }
 
+int ypass_threads(int L, int tc, int tz) { return tc * tz * (L / ypass_points(L)); }
+
+hipError_t launch_ypass(int mode, int L, const YArgs& ya, const LaunchArgs& a) {
+    switch (L) {
+        case 8: return launch_ypass_L8(mode, ya, a);
+        case 16: return launch_ypass_L16(mode, ya, a);
+        case 32: return launch_ypass_L32(mode, ya, a);
+        case 64: return launch_ypass_L64(mode, ya, a);
+        case 128: return launch_ypass_L128(mode, ya, a);
+        case 256: return launch_ypass_L256(mode, ya, a);
+        case 512: return launch_ypass_L512(mode, ya, a);
+        case 1024: return launch_ypass_L1024(mode, ya, a);
+        case 2048: return launch_ypass_L2048(mode, ya, a);
+        case 4096: return launch_ypass_L4096(mode, ya, a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_xrow(int mode, int L, int ng, const LaunchArgs& a) {
     switch (L) {
         case 8: return launch_xrow_L8(mode, ng, a);
@@ -744,9 +991,9 @@ hipError_t launch_init_uniform(hipStream_t s, float* out, int64_t n, uint32_t fi
 
 hipError_t launch_shells(hipStream_t s, const float2* S, int nx, int ny, int nz, int tc, int ndim, double scale,
                          int nshell, double* sums, unsigned long long* counts) {
-    if (ndim != 2 || nz != 1) return hipErrorInvalidValue;
     const size_t lds = nshell * (sizeof(double) + sizeof(unsigned int));
-    hipLaunchKernelGGL(shells_kernel, dim3(256), dim3(256), lds, s, S, nx, ny, tc, scale, nshell, sums, counts);
+    hipLaunchKernelGGL(shells_kernel, dim3(256), dim3(256), lds, s, S, nx, ny, nz, tc, ndim, scale, nshell, sums,
+                       counts);
     return hipGetLastError();
 }
 

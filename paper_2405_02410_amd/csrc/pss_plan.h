@@ -8,6 +8,11 @@
 //   c = 1..Nx/2-1 store X(c).  A line therefore holds exactly Nx/2 complex
 //   values, and the y (and z) transforms of column 0 give
 //   S(0,k) = phi(0,k) + i phi(Nx/2,k), both Hermitian along the other axes.
+//   Along the update axis u (y in 2D, z in 3D) a "packed" line (column 0 in
+//   2D; column 0 with ky = 0 or Ny/2 in 3D) is kept in slot form: slot u in
+//   (0, L/2) holds the kx = 0 mode, slot u in (L/2, L) the kx = Nx/2 mode at
+//   index L - u, and slots 0 and L/2 hold the two real self-conjugate modes as
+//   (re of kx = 0, re of kx = Nx/2).  Every slot is then one update.
 //   Columns are grouped in tiles of TC; arrays are stored
 //     2D:  [ctile][y][TC]                      (state, exchanges)
 //     3D:  state and z-pass input  [y][ctile][z][TC]
@@ -33,8 +38,11 @@ struct DevMono {
     int8_t pad[2];
 };
 
+// An operator: the pure (q^2)^j monomials folded into dense Horner
+// coefficients, plus the monomials with 1/|q| or i q_i factors listed apart.
 struct DevOp {
-    int32_t n;
+    float poly[PSS_MAXPOW + 1];  // coefficient of (q^2)^j, j = 0..8
+    int32_t n;                   // monomials with 1/|q| or i q_i factors
     int32_t pad;
     DevMono m[PSS_MAXM];
 };

@@ -11,12 +11,14 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <map>
 #include <numeric>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/pss.h"
@@ -148,8 +150,12 @@ struct pss_ctx {
     uint64_t* d_step = nullptr;
     float2* d_tw_u = nullptr;
     float2* d_tw_x = nullptr;
-    std::vector<float2*> d_state, d_chan, d_v;
+    float2* d_tw_y = nullptr;
+    // d_chan: channel inputs of the update kernel; d_chan_x: x-kernel outputs
+    // (the same arrays in 2D; in 3D the forward y pass maps one to the other)
+    std::vector<float2*> d_state, d_chan, d_chan_x, d_v;
     float2* d_tmp = nullptr;
+    float2* d_tmp2 = nullptr;
     float* d_real = nullptr;
     double* d_shell_sum = nullptr;
     unsigned long long* d_shell_cnt = nullptr;
@@ -292,7 +298,13 @@ pss_status build_plan(pss_ctx* c) {
     P.key0 = static_cast<uint32_t>(c->seed & 0xffffffffu);
     P.key1 = static_cast<uint32_t>(c->seed >> 32);
 
+    // pure (q^2)^j monomials go into the Horner coefficients, the others into
+    // the general list
     auto put_mono = [](DevOp& op, const Mono& m) -> int {
+        if (m.invq == 0 && m.iq[0] == 0 && m.iq[1] == 0 && m.iq[2] == 0) {
+            op.poly[m.q2] += static_cast<float>(m.coef);
+            return 0;
+        }
         if (op.n >= PSS_MAXM) return -1;
         DevMono& d = op.m[op.n];
         d.coef = static_cast<float>(m.coef);
@@ -302,7 +314,7 @@ pss_status build_plan(pss_ctx* c) {
         d.iy = static_cast<int8_t>(m.iq[1]);
         d.iz = static_cast<int8_t>(m.iq[2]);
         d.ipow = static_cast<int8_t>((m.iq[0] + m.iq[1] + m.iq[2]) & 3);
-        return op.n++;
+        return ++op.n;
     };
 
     for (int f = 0; f < nf; ++f) {
@@ -348,24 +360,25 @@ pss_status build_plan(pss_ctx* c) {
             ++P.ng;
         }
     }
-    // channels
+    // channels; single-monomial terms with the same target and shape share one
+    std::tuple<int, int, int, int, int, int> chan_key[PSS_MAXCH];
     for (Term& t : c->terms) {
         if (t.implicit || t.kind == 1) continue;
         const bool single = t.op.size() == 1;
         int ch = -1;
         if (single) {
-            for (int k = 0; k < P.nch; ++k) {
-                const DevChannel& C = P.ch[k];
-                const Mono& m = t.op[0];
-                if (C.target == t.target && C.op.n == 1 && C.op.m[0].coef == 1.f && C.op.m[0].q2 == m.q2 &&
-                    C.op.m[0].invq == m.invq && C.op.m[0].ix == m.iq[0] && C.op.m[0].iy == m.iq[1] &&
-                    C.op.m[0].iz == m.iq[2] && C.nprod < PSS_MAXPT)
+            for (int k = 0; k < P.nch; ++k)
+                if (chan_key[k] == std::make_tuple(t.target, t.op[0].q2, t.op[0].invq, t.op[0].iq[0], t.op[0].iq[1],
+                                                   t.op[0].iq[2]) &&
+                    P.ch[k].nprod < PSS_MAXPT)
                     ch = k;
-            }
         }
         if (ch < 0) {
             if (P.nch >= PSS_MAXCH) return fail(PSS_E_UNSUPPORTED, "more than %d product channels", PSS_MAXCH);
             ch = P.nch++;
+            chan_key[ch] = single ? std::make_tuple(t.target, t.op[0].q2, t.op[0].invq, t.op[0].iq[0], t.op[0].iq[1],
+                                                    t.op[0].iq[2])
+                                  : std::make_tuple(-1, 0, 0, 0, 0, 0);
             DevChannel& C = P.ch[ch];
             C.target = t.target;
             if (single) {
@@ -399,26 +412,48 @@ pss_status choose_geometry(pss_ctx* c) {
     const int nf = static_cast<int>(c->fields.size());
     const int ng = std::max(1, c->plan.ng);
     const int nx = c->n[0], ny = c->n[1];
-    c->lu = ny;
+    const int nz = c->ndim == 3 ? c->n[2] : 1;
     const int ncols = nx / 2;
-    // update kernel: TC columns of T = L/P threads; 64..256 threads
-    const int tu = pss::update_threads(ny, nf, 1);
-    int tc = std::max(1, 256 / tu);
-    tc = std::min(tc, ncols);
-    if (tu > 256) return fail(PSS_E_UNSUPPORTED, "line length %d with %d fields needs more than 256 threads", ny, nf);
+    pss::Geo& g = c->geo;
+    g = pss::Geo{};
+    g.nz = nz;
+    if (c->ndim == 2) {
+        c->lu = ny;
+        // update kernel: TC columns of T = L/P threads; up to 256 threads
+        const int tu = pss::update_threads(ny, nf, 1);
+        if (tu > 256)
+            return fail(PSS_E_UNSUPPORTED, "line length %d with %d fields needs more than 256 threads", ny, nf);
+        g.tc = std::min(std::max(1, 256 / tu), ncols);
+        g.to = 1;
+        g.ntile = ncols / g.tc;
+        g.nublk = g.ntile;
+    } else {
+        c->lu = nz;
+        const int tu = pss::update_threads(nz, nf, 1);
+        if (tu > 256)
+            return fail(PSS_E_UNSUPPORTED, "line length %d with %d fields needs more than 256 threads", nz, nf);
+        g.tc = std::min(4, ncols);
+        g.to = std::max(1, std::min(256 / (g.tc * tu), ny / 2));
+        g.ntile = ncols / g.tc;
+        g.nublk = g.ntile * (ny / g.to);
+        const int ty = pss::ypass_threads(ny, g.tc, 1);
+        if (ty > 256) return fail(PSS_E_UNSUPPORTED, "y line length %d needs more than 256 threads", ny);
+        g.tz = std::max(1, std::min(256 / ty, nz));
+        g.nyblk = g.ntile * (nz / g.tz);
+        if (pss::ypass_lds_bytes(ny, g.tc, g.tz) > 160 * 1024)
+            return fail(PSS_E_UNSUPPORTED, "y pass needs more LDS than a workgroup has");
+    }
     // x kernel: RB rows (pairs of T threads); aim for >= 512 blocks, 64..256 threads
     const int tx = pss::xrow_threads(nx, ng, 2);
     if (tx > 256) return fail(PSS_E_UNSUPPORTED, "row length %d needs more than 256 threads", nx);
-    const int rows = ny;
+    const int rows = ny * nz;
     const int rb_lo = std::max(2, 2 * (64 / tx));
     const int rb_hi = std::max(2, 2 * (256 / tx));
     int rb = pick_pow2(std::max(2, rows / 512), rb_lo, rb_hi);
-    rb = std::min(rb, rows);
-    c->geo.tc = tc;
-    c->geo.rb = rb;
-    c->geo.ntile = ncols / tc;
-    c->geo.nrowblk = rows / rb;
-    const size_t lu_lds = pss::update_lds_bytes(ny, pss::field_slots(nf), tc);
+    rb = std::min(rb, ny);  // a block's rows share z
+    g.rb = rb;
+    g.nrowblk = rows / rb;
+    const size_t lu_lds = pss::update_lds_bytes(c->lu, pss::field_slots(nf), g.tc, g.to);
     const size_t lx_lds = pss::xrow_lds_bytes(nx, rb);
     if (lu_lds > 160 * 1024 || lx_lds > 160 * 1024)
         return fail(PSS_E_UNSUPPORTED, "lattice needs more LDS than a workgroup has (%zu, %zu bytes)", lu_lds,
@@ -434,13 +469,18 @@ void free_device(pss_ctx* c) {
         p = nullptr;
     };
     for (auto*& p : c->d_state) rel(p);
+    for (size_t k = 0; k < c->d_chan_x.size(); ++k)
+        if (c->d_chan_x[k] != c->d_chan[k]) rel(c->d_chan_x[k]);
+    c->d_chan_x.clear();
     for (auto*& p : c->d_chan) rel(p);
     for (auto*& p : c->d_v) rel(p);
     rel(c->d_plan);
     rel(c->d_step);
     rel(c->d_tw_u);
     rel(c->d_tw_x);
+    rel(c->d_tw_y);
     rel(c->d_tmp);
+    rel(c->d_tmp2);
     rel(c->d_real);
     rel(c->d_shell_sum);
     rel(c->d_shell_cnt);
@@ -462,7 +502,38 @@ pss::LaunchArgs args(pss_ctx* c, int step_off = 0) {
     a.step_off = step_off;
     a.tw_u = c->d_tw_u;
     a.tw_x = c->d_tw_x;
+    a.tw_y = c->d_tw_y;
+    a.dim = c->ndim;
     return a;
+}
+
+// x-kernel arguments: channel outputs go to the y-pass layout in 3D
+pss::LaunchArgs xargs(pss_ctx* c) {
+    pss::LaunchArgs a = args(c);
+    for (size_t k = 0; k < c->d_chan_x.size(); ++k) a.bufs.N[k] = c->d_chan_x[k];
+    return a;
+}
+
+hipError_t y_inverse_factors(pss_ctx* c) {
+    pss::YArgs ya{};
+    ya.n = c->plan.ng;
+    for (int g = 0; g < ya.n; ++g) {
+        ya.src[g] = c->d_v[g];
+        ya.dst[g] = c->d_v[g];  // in place: each line is read whole before it is written
+        ya.ncol[g] = c->plan.mask[g].ncol;
+    }
+    return pss::launch_ypass(pss::MODE_YINV, c->n[1], ya, args(c));
+}
+
+hipError_t y_forward_channels(pss_ctx* c) {
+    pss::YArgs ya{};
+    ya.n = c->plan.nch;
+    for (int k = 0; k < ya.n; ++k) {
+        ya.src[k] = c->d_chan_x[k];
+        ya.dst[k] = c->d_chan[k];
+        ya.ncol[k] = c->n[0] / 2;
+    }
+    return pss::launch_ypass(pss::MODE_YFWD, c->n[1], ya, args(c));
 }
 
 pss_status upload_plan(pss_ctx* c) {
@@ -473,7 +544,6 @@ pss_status upload_plan(pss_ctx* c) {
 
 pss_status materialize(pss_ctx* c) {
     if (c->planned) return PSS_OK;
-    if (c->ndim != 2) return fail(PSS_E_UNSUPPORTED, "3D lattices are not built yet");
     pss_status st = validate(c);
     if (st) return st;
     if ((st = build_plan(c))) return st;
@@ -495,11 +565,19 @@ pss_status materialize(pss_ctx* c) {
         HIP_TRY(hipMalloc(&p, bytes));
         HIP_TRY(hipMemset(p, 0, bytes));
     }
+    c->d_chan_x = c->d_chan;
+    if (c->ndim == 3) {
+        for (auto*& p : c->d_chan_x) {
+            HIP_TRY(hipMalloc(&p, bytes));
+            HIP_TRY(hipMemset(p, 0, bytes));
+        }
+    }
     for (auto*& p : c->d_v) {
         HIP_TRY(hipMalloc(&p, bytes));
         HIP_TRY(hipMemset(p, 0, bytes));
     }
     HIP_TRY(hipMalloc(&c->d_tmp, bytes));
+    HIP_TRY(hipMalloc(&c->d_tmp2, bytes));
     HIP_TRY(hipMalloc(&c->d_real, sizeof(float) * static_cast<size_t>(c->sites())));
     HIP_TRY(hipMalloc(&c->d_plan, sizeof(pss::DevPlan)));
     HIP_TRY(hipMalloc(&c->d_step, sizeof(uint64_t)));
@@ -510,6 +588,9 @@ pss_status materialize(pss_ctx* c) {
     HIP_TRY(hipMalloc(&c->d_tw_u, sizeof(float2) * twu.size()));
     HIP_TRY(hipMemcpy(c->d_tw_x, twx.data(), sizeof(float2) * twx.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->d_tw_u, twu.data(), sizeof(float2) * twu.size(), hipMemcpyHostToDevice));
+    const auto twy = twiddles(c->n[1]);
+    HIP_TRY(hipMalloc(&c->d_tw_y, sizeof(float2) * twy.size()));
+    HIP_TRY(hipMemcpy(c->d_tw_y, twy.data(), sizeof(float2) * twy.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->d_plan, &c->plan, sizeof(pss::DevPlan), hipMemcpyHostToDevice));
     HIP_TRY(hipDeviceSynchronize());
     c->planned = true;
@@ -524,19 +605,70 @@ pss_status prologue(pss_ctx* c) {
     const int nf = static_cast<int>(c->fields.size());
     pss::LaunchArgs a = args(c);
     HIP_TRY(pss::launch_update(pss::MODE_PROLOGUE, c->lu, nf, a));
-    if (c->plan.nch > 0) HIP_TRY(pss::launch_xrow(pss::MODE_STEP, c->n[0], c->plan.ng, a));
+    if (c->plan.nch > 0) {
+        if (c->ndim == 3) HIP_TRY(y_inverse_factors(c));
+        HIP_TRY(pss::launch_xrow(pss::MODE_STEP, c->n[0], c->plan.ng, xargs(c)));
+        if (c->ndim == 3) HIP_TRY(y_forward_channels(c));
+    }
     c->dirty = false;
     return PSS_OK;
 }
 
 pss_status enqueue_steps(pss_ctx* c, int64_t k) {
     const int nf = static_cast<int>(c->fields.size());
+    const pss::LaunchArgs ax = xargs(c);
     for (int64_t i = 0; i < k; ++i) {
         pss::LaunchArgs a = args(c, static_cast<int>(i));
         HIP_TRY(pss::launch_update(pss::MODE_STEP, c->lu, nf, a));
-        if (c->plan.nch > 0) HIP_TRY(pss::launch_xrow(pss::MODE_STEP, c->n[0], c->plan.ng, a));
+        if (c->plan.nch > 0) {
+            if (c->ndim == 3) HIP_TRY(y_inverse_factors(c));
+            HIP_TRY(pss::launch_xrow(pss::MODE_STEP, c->n[0], c->plan.ng, ax));
+            if (c->ndim == 3) HIP_TRY(y_forward_channels(c));
+        }
     }
     HIP_TRY(pss::launch_advance(c->stream, c->d_step, k));
+    return PSS_OK;
+}
+
+// real-space array on the device (d_real) -> Fourier state of `field`
+pss_status forward_to_state(pss_ctx* c, int field) {
+    pss::LaunchArgs a = args(c);
+    a.bufs.real_in = c->d_real;
+    a.bufs.out = c->d_tmp;
+    HIP_TRY(pss::launch_xrow(pss::MODE_R2C_IN, c->n[0], 1, a));
+    const float2* in = c->d_tmp;
+    if (c->ndim == 3) {
+        pss::YArgs ya{};
+        ya.n = 1;
+        ya.src[0] = c->d_tmp;
+        ya.dst[0] = c->d_tmp2;
+        ya.ncol[0] = c->n[0] / 2;
+        HIP_TRY(pss::launch_ypass(pss::MODE_YFWD, c->n[1], ya, a));
+        in = c->d_tmp2;
+    }
+    a.bufs.in = in;
+    a.bufs.sel = field;
+    HIP_TRY(pss::launch_update(pss::MODE_FWD_STORE, c->lu, 1, a));
+    return PSS_OK;
+}
+
+// Fourier state of `field` -> real-space array on the device (d_real)
+pss_status state_to_real(pss_ctx* c, int field) {
+    pss::LaunchArgs a = args(c);
+    a.bufs.sel = field;
+    a.bufs.out = c->d_tmp;
+    HIP_TRY(pss::launch_update(pss::MODE_INV_OUT, c->lu, 1, a));
+    if (c->ndim == 3) {
+        pss::YArgs ya{};
+        ya.n = 1;
+        ya.src[0] = c->d_tmp;
+        ya.dst[0] = c->d_tmp;
+        ya.ncol[0] = c->n[0] / 2;
+        HIP_TRY(pss::launch_ypass(pss::MODE_YINV, c->n[1], ya, a));
+    }
+    a.bufs.in = c->d_tmp;
+    a.bufs.real_out = c->d_real;
+    HIP_TRY(pss::launch_xrow(pss::MODE_C2R_OUT, c->n[0], 1, a));
     return PSS_OK;
 }
 
@@ -566,25 +698,80 @@ pss_status graph_for(pss_ctx* c, int64_t k, hipGraphExec_t* out) {
 
 constexpr int64_t kGraphSteps = 50;
 
-// unpack the packed state of one field into the canonical half spectrum
+// unpack the state of one field (packed columns, slot form on packed lines)
+// into the canonical half spectrum
 void unpack_half(const pss_ctx* c, const std::vector<float2>& S, float* out) {
-    const int nx = c->n[0], ny = c->n[1], tc = c->geo.tc;
+    const int nx = c->n[0], ny = c->n[1], tc = c->geo.tc, ntile = c->geo.ntile;
+    const int nz = c->ndim == 3 ? c->n[2] : 1;
     const int nh = nx / 2 + 1;
-    auto at = [&](int col, int y) { return S[(static_cast<size_t>(col / tc) * ny + y) * tc + col % tc]; };
-    for (int y = 0; y < ny; ++y) {
-        for (int col = 1; col < nx / 2; ++col) {
-            const float2 v = at(col, y);
-            out[2 * (static_cast<size_t>(y) * nh + col)] = v.x;
-            out[2 * (static_cast<size_t>(y) * nh + col) + 1] = v.y;
+    auto put = [&](int z, int y, int kx, double re, double im) {
+        const size_t i = 2 * ((static_cast<size_t>(z) * ny + y) * nh + kx);
+        out[i] = static_cast<float>(re);
+        out[i + 1] = static_cast<float>(im);
+    };
+    auto at = [&](int col, int y, int z) {
+        if (c->ndim == 2) return S[(static_cast<size_t>(col / tc) * ny + y) * tc + col % tc];
+        return S[((static_cast<size_t>(y) * ntile + col / tc) * nz + z) * tc + col % tc];
+    };
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int col = 1; col < nx / 2; ++col) {
+                const float2 v = at(col, y, z);
+                put(z, y, col, v.x, v.y);
+            }
+    // planes kx = 0 and kx = Nx/2: collect what is stored, then fill the rest
+    // by Hermitian symmetry phi(kx0, -y, -z) = conj phi(kx0, y, z)
+    const size_t np = static_cast<size_t>(ny) * nz;
+    std::vector<std::complex<double>> P0(np), PN(np);
+    std::vector<char> k0(np, 0), kn(np, 0);
+    auto idx = [&](int y, int z) { return static_cast<size_t>(z) * ny + y; };
+    auto slots = [&](int L, auto get, auto set0, auto setn) {  // packed line of length L
+        for (int u = 0; u < L; ++u) {
+            const float2 v = get(u);
+            if (u == 0 || u == L / 2) {
+                set0(u, std::complex<double>(v.x, 0));
+                setn(u, std::complex<double>(v.y, 0));
+            } else if (u < L / 2) {
+                set0(u, std::complex<double>(v.x, v.y));
+            } else {
+                setn(L - u, std::complex<double>(v.x, v.y));
+            }
         }
-        const float2 a = at(0, y), b = at(0, (ny - y) & (ny - 1));
-        const double r0 = 0.5 * (static_cast<double>(a.x) + b.x), i0 = 0.5 * (static_cast<double>(a.y) - b.y);
-        const double rn = 0.5 * (static_cast<double>(a.y) + b.y), in = 0.5 * (static_cast<double>(b.x) - a.x);
-        out[2 * (static_cast<size_t>(y) * nh)] = static_cast<float>(r0);
-        out[2 * (static_cast<size_t>(y) * nh) + 1] = static_cast<float>(i0);
-        out[2 * (static_cast<size_t>(y) * nh + nx / 2)] = static_cast<float>(rn);
-        out[2 * (static_cast<size_t>(y) * nh + nx / 2) + 1] = static_cast<float>(in);
+    };
+    if (c->ndim == 2) {
+        slots(
+            ny, [&](int u) { return at(0, u, 0); },
+            [&](int y, std::complex<double> v) { P0[idx(y, 0)] = v; k0[idx(y, 0)] = 1; },
+            [&](int y, std::complex<double> v) { PN[idx(y, 0)] = v; kn[idx(y, 0)] = 1; });
+    } else {
+        for (int o = 0; o < ny; ++o) {
+            if (o == 0 || o == ny / 2) {
+                slots(
+                    nz, [&](int u) { return at(0, o, u); },
+                    [&](int z, std::complex<double> v) { P0[idx(o, z)] = v; k0[idx(o, z)] = 1; },
+                    [&](int z, std::complex<double> v) { PN[idx(o, z)] = v; kn[idx(o, z)] = 1; });
+            } else {
+                for (int z = 0; z < nz; ++z) {
+                    const float2 v = at(0, o, z);
+                    if (o < ny / 2) {
+                        P0[idx(o, z)] = {v.x, v.y};
+                        k0[idx(o, z)] = 1;
+                    } else {
+                        PN[idx(ny - o, z)] = {v.x, v.y};
+                        kn[idx(ny - o, z)] = 1;
+                    }
+                }
+            }
+        }
     }
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y) {
+            const size_t i = idx(y, z), j = idx((ny - y) & (ny - 1), (nz - z) & (nz - 1));
+            const std::complex<double> a = k0[i] ? P0[i] : std::conj(P0[j]);
+            const std::complex<double> b = kn[i] ? PN[i] : std::conj(PN[j]);
+            put(z, y, 0, a.real(), a.imag());
+            put(z, y, nx / 2, b.real(), b.imag());
+        }
 }
 
 struct SaveHeader {
@@ -696,13 +883,15 @@ pss_status pss_term_set_coef(pss_ctx* c, int32_t term_id, int32_t mono, double c
         }
     }
     if (!c->planned) return PSS_OK;
-    pss::DevPlan& P = c->plan;
-    switch (t.kind) {
-        case 0: P.implicit_op[t.slot].m[t.mono0 + mono].coef = static_cast<float>(coef); break;
-        case 1: P.direct[t.slot].op.m[mono].coef = static_cast<float>(coef); break;
-        case 2: P.ch[t.slot].prod[t.prod].coef = static_cast<float>(coef); break;
-        default: P.ch[t.slot].op.m[mono].coef = static_cast<float>(coef); break;
+    // recompile the coefficients (the structure is unchanged), and rebuild the
+    // channel arrays of the next step from the current state
+    const pss::DevPlan keep = c->plan;
+    if (pss_status s = build_plan(c)) {
+        t.op[mono].coef = old;
+        c->plan = keep;
+        return s;
     }
+    c->dirty = true;
     return upload_plan(c);
 }
 
@@ -767,13 +956,7 @@ pss_status pss_field_upload(pss_ctx* c, int32_t field, const float* real, int32_
     const size_t bytes = sizeof(float) * static_cast<size_t>(c->sites());
     HIP_TRY(hipMemcpyAsync(c->d_real, real, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                            c->stream));
-    pss::LaunchArgs a = args(c);
-    a.bufs.real_in = c->d_real;
-    a.bufs.out = c->d_tmp;
-    HIP_TRY(pss::launch_xrow(pss::MODE_R2C_IN, c->n[0], 1, a));
-    a.bufs.in = c->d_tmp;
-    a.bufs.sel = field;
-    HIP_TRY(pss::launch_update(pss::MODE_FWD_STORE, c->lu, 1, a));
+    if (pss_status s = forward_to_state(c, field)) return s;
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->dirty = true;
     return PSS_OK;
@@ -786,13 +969,7 @@ pss_status pss_field_init_uniform(pss_ctx* c, int32_t field, double lo, double h
     if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
     HIP_TRY(pss::launch_init_uniform(c->stream, c->d_real, c->sites(), static_cast<uint32_t>(field),
                                      c->plan.key0, c->plan.key1, lo, hi));
-    pss::LaunchArgs a = args(c);
-    a.bufs.real_in = c->d_real;
-    a.bufs.out = c->d_tmp;
-    HIP_TRY(pss::launch_xrow(pss::MODE_R2C_IN, c->n[0], 1, a));
-    a.bufs.in = c->d_tmp;
-    a.bufs.sel = field;
-    HIP_TRY(pss::launch_update(pss::MODE_FWD_STORE, c->lu, 1, a));
+    if (pss_status s = forward_to_state(c, field)) return s;
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->dirty = true;
     return PSS_OK;
@@ -803,13 +980,7 @@ pss_status pss_field_download(pss_ctx* c, int32_t field, float* real, int32_t on
     if (!real) return fail(PSS_E_INVAL, "null array");
     if (pss_status s = materialize(c)) return s;
     if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
-    pss::LaunchArgs a = args(c);
-    a.bufs.sel = field;
-    a.bufs.out = c->d_tmp;
-    HIP_TRY(pss::launch_update(pss::MODE_INV_OUT, c->lu, 1, a));
-    a.bufs.in = c->d_tmp;
-    a.bufs.real_out = c->d_real;
-    HIP_TRY(pss::launch_xrow(pss::MODE_C2R_OUT, c->n[0], 1, a));
+    if (pss_status s = state_to_real(c, field)) return s;
     const size_t bytes = sizeof(float) * static_cast<size_t>(c->sites());
     HIP_TRY(hipMemcpyAsync(real, c->d_real, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                            c->stream));
@@ -825,7 +996,7 @@ pss_status pss_spectrum_download(pss_ctx* c, int32_t field, float* half, int32_t
     std::vector<float2> S(static_cast<size_t>(c->packed()));
     HIP_TRY(hipMemcpyAsync(S.data(), c->d_state[field], sizeof(float2) * S.size(), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    const size_t nout = static_cast<size_t>(c->n[1]) * (c->n[0] / 2 + 1) * 2;
+    const size_t nout = static_cast<size_t>(c->n[1]) * (c->ndim == 3 ? c->n[2] : 1) * (c->n[0] / 2 + 1) * 2;
     std::vector<float> h(nout);
     unpack_half(c, S, h.data());
     if (on_device) {
@@ -935,7 +1106,7 @@ pss_status pss_structure_factor(pss_ctx* c, int32_t field, double* S, int64_t* c
     if (!S || !counts) return fail(PSS_E_INVAL, "null output");
     if (pss_status s = materialize(c)) return s;
     if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
-    const int nmin = std::min(c->n[0], c->n[1]);
+    const int nmin = c->ndim == 3 ? std::min(std::min(c->n[0], c->n[1]), c->n[2]) : std::min(c->n[0], c->n[1]);
     const int ns = nmin / 2;  // shells j = 1 .. ns-1
     if (n_shells != ns - 1) return fail(PSS_E_INVAL, "n_shells must be %d", ns - 1);
     if (!c->d_shell_sum) {
@@ -982,19 +1153,21 @@ pss_status pss_kernel_bytes(pss_ctx* c, int32_t which, double* bytes) {
     if (pss_status s = materialize(c)) return s;
     const double arr = 8.0 * static_cast<double>(c->packed());  // one packed array
     const pss::DevPlan& P = c->plan;
-    const int ny = c->n[1], tc = c->geo.tc;
-    double vbytes = 0;  // factor arrays written by the update / read by the x kernel
+    const int tc = c->geo.tc;
+    const double lines = static_cast<double>(c->n[1]) * (c->ndim == 3 ? c->n[2] : 1);
+    double vbytes = 0;  // factor arrays: only tiles holding kept columns move
     for (int g = 0; g < P.ng; ++g) {
         const int tiles = (P.mask[g].ncol + tc - 1) / tc;
-        vbytes += 8.0 * tiles * tc * ny;
+        vbytes += 8.0 * tiles * tc * lines;
     }
     const int nf = static_cast<int>(c->fields.size());
-    if (which == 0) {
-        *bytes = arr * (P.nch + 2 * nf) + vbytes;
-    } else if (which == 1) {
-        *bytes = vbytes + arr * P.nch;
-    } else {
-        return fail(PSS_E_INVAL, "kernel %d does not exist on a 2D lattice", which);
+    const int nk = c->ndim == 3 ? 4 : 2;
+    if (which < 0 || which >= nk) return fail(PSS_E_INVAL, "kernel %d does not exist on this lattice", which);
+    switch (which) {
+        case 0: *bytes = arr * (P.nch + 2 * nf) + vbytes; break;  // channels in, state in/out, factors out
+        case 1: *bytes = vbytes + arr * P.nch; break;             // factors in, channels out
+        case 2: *bytes = 2 * vbytes; break;                       // factors in place
+        default: *bytes = 2 * arr * P.nch; break;                 // channels re-laid out
     }
     return PSS_OK;
 }
@@ -1003,7 +1176,8 @@ pss_status pss_time_kernel(pss_ctx* c, int32_t which, int32_t reps, double* ms, 
     if (pss_status s = check_ctx(c)) return s;
     if (!ms || reps < 1) return fail(PSS_E_INVAL, "bad arguments");
     if (pss_status s = materialize(c)) return s;
-    if (which < 0 || which > 1) return fail(PSS_E_INVAL, "kernel %d does not exist on a 2D lattice", which);
+    const int nk = c->ndim == 3 ? 4 : 2;
+    if (which < 0 || which >= nk) return fail(PSS_E_INVAL, "kernel %d does not exist on this lattice", which);
     if (c->dirty)
         if (pss_status s = prologue(c)) return s;
     const int nf = static_cast<int>(c->fields.size());
@@ -1011,12 +1185,14 @@ pss_status pss_time_kernel(pss_ctx* c, int32_t which, int32_t reps, double* ms, 
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     pss::LaunchArgs a = args(c);
+    const pss::LaunchArgs ax = xargs(c);
     HIP_TRY(hipEventRecord(e0, c->stream));
     for (int r = 0; r < reps; ++r) {
-        if (which == 0) {
-            HIP_TRY(pss::launch_update(pss::MODE_STEP, c->lu, nf, a));
-        } else {
-            HIP_TRY(pss::launch_xrow(pss::MODE_STEP, c->n[0], c->plan.ng, a));
+        switch (which) {
+            case 0: HIP_TRY(pss::launch_update(pss::MODE_STEP, c->lu, nf, a)); break;
+            case 1: HIP_TRY(pss::launch_xrow(pss::MODE_STEP, c->n[0], c->plan.ng, ax)); break;
+            case 2: HIP_TRY(y_inverse_factors(c)); break;
+            default: HIP_TRY(y_forward_channels(c)); break;
         }
     }
     HIP_TRY(hipEventRecord(e1, c->stream));
@@ -1027,7 +1203,8 @@ pss_status pss_time_kernel(pss_ctx* c, int32_t which, int32_t reps, double* ms, 
     hipEventDestroy(e1);
     *ms = static_cast<double>(t) / reps;
     c->dirty = true;  // the channel arrays no longer match the state
-    if (name) *name = which == 0 ? "update_kernel" : "xrow_kernel";
+    static const char* names[4] = {"update_kernel", "xrow_kernel", "ypass_kernel(inverse)", "ypass_kernel(forward)"};
+    if (name) *name = names[which];
     return PSS_OK;
 }
 
