@@ -151,6 +151,17 @@ pss_status pss_dealias_set(pss_ctx *ctx, int32_t rule, int32_t shape);
  * stream cannot host graph capture; pass a created stream. */
 pss_status pss_stream_set(pss_ctx *ctx, void *hip_stream);
 
+/* Launch-geometry override, before the plan is built (PSS_E_STATE after).
+ * Keys: "tc" (packed columns per tile; also the array layout), "to" (3D:
+ * y lines per update block), "tz" (3D: z lines per y-pass block), "rb" (rows
+ * per x-kernel block), "pu", "px", "py" (points per thread of the update,
+ * x and y kernels: 4, 8 or 16).  value <= 0 restores the default.  Invalid
+ * combinations are reported as PSS_E_UNSUPPORTED when the plan is built. */
+pss_status pss_tuning_set(pss_ctx *ctx, const char *key, int64_t value);
+
+/* The geometry value in use for a key (builds the plan if needed). */
+pss_status pss_tuning_get(pss_ctx *ctx, const char *key, int64_t *value);
+
 /* Check the model without touching the device: implicit terms, noise
  * operators, and stability Re(1 - dt L(q)) > 0 on every mode. */
 pss_status pss_validate(pss_ctx *ctx);

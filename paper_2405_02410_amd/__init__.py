@@ -82,6 +82,8 @@ _SIGS = {
                         ctypes.POINTER(ctypes.c_char_p)],
     "pss_kernel_bytes": [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
     "pss_kernels_per_step": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)],
+    "pss_tuning_set": [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64],
+    "pss_tuning_get": [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)],
 }
 
 
@@ -194,6 +196,19 @@ class Lattice:
     def stream(self, hip_stream):
         """Run on a hipStream_t given as an integer handle (torch: stream.cuda_stream)."""
         _check(lib().pss_stream_set(self._h, ctypes.c_void_p(int(hip_stream) if hip_stream else 0)))
+
+    def tune(self, **kw):
+        """Force launch-geometry values (tc, to, tz, rb, pu, px, py) before the plan is built."""
+        for k, v in kw.items():
+            _check(lib().pss_tuning_set(self._h, k.encode(), int(v)))
+
+    def geometry(self):
+        out = {}
+        for k in ("tc", "to", "tz", "rb", "pu", "px", "py"):
+            v = ctypes.c_int64()
+            _check(lib().pss_tuning_get(self._h, k.encode(), ctypes.byref(v)))
+            out[k] = v.value
+        return out
 
     def validate(self):
         _check(lib().pss_validate(self._h))

@@ -227,13 +227,14 @@ __device__ __forceinline__ float uniform23(uint32_t w) {
     return (static_cast<float>(w >> 9) + 0.5f) * 1.1920928955078125e-07f;
 }
 
-// Two standard normals from the first two words (Box & Muller 1958).
+// Two standard normals from the first two words (Box & Muller 1958), with
+// the hardware transcendentals: v_log_f32 (log2), v_sqrt_f32, and
+// v_sin_f32 / v_cos_f32, whose argument is in revolutions (sin(2 pi u)).
 __device__ __forceinline__ float2 box_muller(uint32_t w0, uint32_t w1) {
     const float u0 = uniform23(w0), u1 = uniform23(w1);
-    const float r = sqrtf(-2.f * logf(u0));
-    float s, c;
-    sincospif(2.f * u1, &s, &c);
-    return make_float2(r * c, r * s);
+    // -2 ln u0 = -2 ln2 log2 u0 >= 0; clamp the rounding of log2 near u0 = 1
+    const float r = __builtin_amdgcn_sqrtf(fmaxf(-1.3862943611198906f * __builtin_amdgcn_logf(u0), 0.f));
+    return make_float2(r * __builtin_amdgcn_cosf(u1), r * __builtin_amdgcn_sinf(u1));
 }
 
 }  // namespace pss

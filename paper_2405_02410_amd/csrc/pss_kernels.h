@@ -43,6 +43,10 @@ struct Geo {
     int tz;       // y pass: z values per block
     int nyblk;    // y-pass blocks (= ntile * Nz/tz)
     int nz;       // Nz (1 in 2D)
+    int tc_log2;  // log2(tc)
+    int pu;       // points per thread: update kernel
+    int px;       // points per thread: x kernel
+    int py;       // points per thread: y pass
 };
 
 // arrays handled by one y-pass launch
@@ -66,12 +70,9 @@ struct LaunchArgs {
     int dim;             // 2 or 3
 };
 
-// points per thread of a line of length L when k register arrays of fields
-// are live (k = 1, 2, 4): 16, 8, 4, capped at L
-constexpr int points_per_thread(int L, int k) {
-    const int p = k <= 1 ? 16 : (k == 2 ? 8 : 4);
-    return p < L ? p : L;
-}
+// largest points per thread a kernel is built for with `nregs` register
+// arrays of fields (1, 2 or 4 and more): 16, 8, 4, capped at L
+int max_points(int L, int nregs);
 
 hipError_t launch_update(int mode, int L, int nf, const LaunchArgs& a);
 hipError_t launch_xrow(int mode, int L, int ng, const LaunchArgs& a);
@@ -81,31 +82,28 @@ hipError_t launch_init_uniform(hipStream_t s, float* out, int64_t n, uint32_t fi
                                double lo, double hi);
 hipError_t launch_philox(hipStream_t s, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
                          int64_t count, uint32_t* out);
-int update_threads(int L, int nf, int tc);
-int xrow_threads(int L, int ng, int rb);
 
 // register-array count an instantiation is built for (1, 2 or 4 fields)
 inline int field_slots(int n) { return n <= 1 ? 1 : (n == 2 ? 2 : 4); }
-// dynamic LDS of the update kernel: TC*TO padded lines + one exchange line
+// dynamic LDS of the update kernel: TC*TO padded lines, one exchange line and
+// the staged twiddle table (L entries), in that order
 inline size_t update_lds_bytes(int L, int nf_slots, int tc, int to) {
     (void)nf_slots;
-    return sizeof(float2) * (static_cast<size_t>(tc) * to * (L + L / 16) + static_cast<size_t>(L));
+    return sizeof(float2) * (static_cast<size_t>(tc) * to * (L + L / 16) + 2 * static_cast<size_t>(L));
 }
-// dynamic LDS of the y pass: TC*TZ padded lines + one exchange line per z
+// dynamic LDS of the y pass: TC*TZ padded lines, one exchange line per z and
+// the staged twiddle table (L entries), in that order
 inline size_t ypass_lds_bytes(int L, int tc, int tz) {
-    return sizeof(float2) * (static_cast<size_t>(tc) * tz * (L + L / 16) + static_cast<size_t>(tz) * L);
+    return sizeof(float2) * (static_cast<size_t>(tc) * tz * (L + L / 16) + static_cast<size_t>(tz + 1) * L);
 }
-int ypass_threads(int L, int tc, int tz);
-// dynamic LDS of the x kernel: RB/2 padded lines + RB staged packed rows
+// dynamic LDS of the x kernel: RB/2 padded lines + the staged twiddle table
 inline size_t xrow_lds_bytes(int L, int rb) {
-    return sizeof(float2) * (static_cast<size_t>(rb / 2) * (L + L / 16) + static_cast<size_t>(rb) * (L / 2 + 1));
+    return sizeof(float2) * (static_cast<size_t>(rb / 2) * (L + L / 16) + static_cast<size_t>(L));
 }
 
 // FP64 shell sums of (dV/N)|phi_hat|^2 over the packed state of one field
 hipError_t launch_shells(hipStream_t s, const float2* S, int nx, int ny, int nz, int tc, int ndim,
                          double scale, int nshell, double* sums, unsigned long long* counts);
 
-// points per thread of the y pass
-constexpr int ypass_points(int L) { return L < 16 ? L : 16; }
 
 }  // namespace pss

@@ -15,11 +15,25 @@
 // pss_plan.h: column 0 holds X(kx=0) + i X(kx=Nx/2).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "pss_device.h"
 #include "pss_kernels.h"
 #include "pss_plan.h"
 
 namespace pss {
+
+// ----------------------------------------------------------------- twiddles
+// Copy the twiddle table of a line length into LDS once per block; the copy
+// loop is unrolled so its loads are in flight together.  Returns the LDS copy
+// (the first transform's barriers order it before any use).
+template <int L>
+__device__ __forceinline__ const float2* stage_twiddles(float2* dst, const float2* __restrict__ src, int tid,
+                                                        int nthr) {
+#pragma unroll 8
+    for (int i = tid; i < L; i += nthr) dst[i] = src[i];
+    return dst;
+}
 
 // ----------------------------------------------------------------- modes
 struct ModeQ {
@@ -155,7 +169,7 @@ __device__ __forceinline__ void add_to(float2 (&a)[NF][P], int f, int m, float2 
 // Transforms of a packed line see S(u) = phi(0,u) + i phi(Nx/2,u); the slot
 // form is converted to and from it through one LDS line (block-uniform
 // barriers; a block holds at most one packed line, at (cc, lo) = (0, 0)).
-// LDS: TC*TO padded line buffers | one exchange line of L.
+// LDS: TC*TO padded line buffers | one exchange line of L | twiddles of L.
 
 // mode of slot u of a line; `pair` marks the two real modes of slots 0, L/2
 template <int DIM>
@@ -255,7 +269,7 @@ __device__ __forceinline__ float2 pair_update_d(const DevPlan& p, int f, uint32_
 template <int L, int P, int NF, int MODE, int DIM>
 __global__ void __launch_bounds__(256) update_kernel(const DevPlan* __restrict__ plan, Bufs bufs, Geo geo,
                                                       const uint64_t* __restrict__ step_ctr,
-                                                      int step_off, const float2* __restrict__ tw) {
+                                                      int step_off, const float2* __restrict__ tw_g) {
     constexpr int T = L / P;
     extern __shared__ float2 smem[];
     const DevPlan& p = *plan;
@@ -275,6 +289,7 @@ __global__ void __launch_bounds__(256) update_kernel(const DevPlan* __restrict__
     const size_t vstride = DIM == 2 ? static_cast<size_t>(tc) : static_cast<size_t>(ntile) * ny * tc;
     float2* line = smem + (lo * tc + cc) * lds_line(L);
     float2* xbuf = smem + tc * to * lds_line(L);  // packed-line exchange
+    const float2* tw = stage_twiddles<L>(xbuf + L, tw_g, tid, tc * to * T);
     // block holds a packed line (block-uniform); this thread is on it
     const bool blk_packed = ct == 0 && (DIM == 2 || og * to == 0 || og * to == (ny >> 1));
     const bool packed = blk_packed && cc == 0 && lo == 0;
@@ -462,7 +477,7 @@ __global__ void __launch_bounds__(256) update_kernel(const DevPlan* __restrict__
 //   slots 0 and Ny/2       : Y unchanged     (packed, Hermitian along z)
 // and the inverse pass undoes it before transforming.
 template <int L, int P, int MODE>
-__global__ void __launch_bounds__(256) ypass_kernel(YArgs ya, Geo geo, const float2* __restrict__ tw) {
+__global__ void __launch_bounds__(256) ypass_kernel(YArgs ya, Geo geo, const float2* __restrict__ tw_g) {
     constexpr int T = L / P;
     extern __shared__ float2 smem[];
     const int tc = geo.tc, tz = geo.tz;
@@ -477,6 +492,7 @@ __global__ void __launch_bounds__(256) ypass_kernel(YArgs ya, Geo geo, const flo
     const int c = ct * tc + cc;
     float2* line = smem + (lz * tc + cc) * lds_line(L);
     float2* xb = smem + tc * tz * lds_line(L) + lz * L;  // column-0 exchange, one line per z
+    const float2* tw = stage_twiddles<L>(smem + tc * tz * lds_line(L) + tz * L, tw_g, tid, tc * tz * T);
     const size_t ibase = (static_cast<size_t>(z) * ntile + ct) * L * tc + cc;
     const size_t obase = MODE == MODE_YFWD ? (static_cast<size_t>(ct) * nz + z) * tc + cc : ibase;
     const size_t ostride = MODE == MODE_YFWD ? static_cast<size_t>(ntile) * nz * tc : static_cast<size_t>(tc);
@@ -534,7 +550,7 @@ __global__ void __launch_bounds__(256) ypass_kernel(YArgs ya, Geo geo, const flo
 // whole tile blocks of RB*TC contiguous elements.
 template <int L, int P, int NG, int MODE>
 __global__ void __launch_bounds__(256) xrow_kernel(const DevPlan* __restrict__ plan, Bufs bufs, Geo geo,
-                                                    const float2* __restrict__ tw) {
+                                                    const float2* __restrict__ tw_g) {
     constexpr int T = L / P;
     constexpr int NC = L / 2;  // packed columns
     extern __shared__ float2 smem[];
@@ -549,36 +565,32 @@ __global__ void __launch_bounds__(256) xrow_kernel(const DevPlan* __restrict__ p
     const int ny = p.n[1];
     const int zr = r0 / ny;          // z of the block (0 in 2D)
     const int y0 = r0 - zr * ny;     // first y of the block
+    const int lt = geo.tc_log2;
     float2* line = smem + pr * lds_line(L);
-    float2* stage = smem + (rb / 2) * lds_line(L);  // rb x NC (+pad)
-    const int spitch = NC + 1;
+    const float2* tw = stage_twiddles<L>(smem + (rb / 2) * lds_line(L), tw_g, tid, nthr);
 
-    // load packed columns [0, ncol) of rows y0..y0+rb-1 into stage
-    auto stage_rows = [&](const float2* __restrict__ src, int ncol) {
-        const int nt = (ncol + tc - 1) / tc;
-        const int per = rb * tc;
-        for (int i = tid; i < nt * per; i += nthr) {
-            const int tl = i / per, rem = i - tl * per;
-            const int r = rem / tc, cc = rem - r * tc;
-            stage[r * spitch + tl * tc + cc] = src[((static_cast<size_t>(zr) * ntile + tl) * ny + y0 + r) * tc + cc];
-        }
-    };
-    // build the packed complex input Z[k] = X_row0[k] + i X_row1[k] of pair pr
-    auto build_z = [&](float2 (&v)[P], int ncol) {
-        const float2* row0 = stage + (2 * pr) * spitch;
-        const float2* row1 = row0 + spitch;
+    // Gather the packed complex input Z[k] = X_row0[k] + i X_row1[k] of pair
+    // pr straight from the packed-column array (columns [0, ncol) are stored;
+    // the others are zero); all loads are issued together.
+    const size_t row0 = (static_cast<size_t>(zr) * ntile * ny + y0 + 2 * pr) * tc;
+    const size_t tstride = static_cast<size_t>(ny) * tc;  // one column tile
+    auto build_z = [&](float2 (&v)[P], const float2* __restrict__ src, int ncol) {
 #pragma unroll
         for (int m = 0; m < P; ++m) {
             const int k = t + m * T;
+            const int kk = (k == NC) ? 0 : (k < NC ? k : L - k);
+            float2 a = make_float2(0.f, 0.f), b = a;
+            if (kk < ncol) {
+                const size_t off = row0 + (kk >> lt) * tstride + (kk & (tc - 1));
+                a = src[off];
+                b = src[off + tc];
+            }
             float2 z;
             if (k == 0) {
-                z = make_float2(row0[0].x, row1[0].x);
+                z = make_float2(a.x, b.x);
             } else if (k == NC) {
-                z = make_float2(row0[0].y, row1[0].y);
+                z = make_float2(a.y, b.y);
             } else {
-                const int kk = k < NC ? k : L - k;
-                const float2 a = kk < ncol ? row0[kk] : make_float2(0.f, 0.f);
-                const float2 b = kk < ncol ? row1[kk] : make_float2(0.f, 0.f);
                 z = k < NC ? make_float2(a.x - b.y, a.y + b.x) : make_float2(a.x + b.y, b.x - a.y);
             }
             v[m] = z;
@@ -587,6 +599,7 @@ __global__ void __launch_bounds__(256) xrow_kernel(const DevPlan* __restrict__ p
     // unpack the forward transform W of each pair and store packed columns
     auto store_rows = [&](float2* __restrict__ dst) {
         const int per = rb * tc;
+#pragma unroll 4
         for (int i = tid; i < ntile * per; i += nthr) {
             const int tl = i / per, rem = i - tl * per;
             const int r = rem / tc, cc = rem - r * tc;
@@ -623,10 +636,8 @@ __global__ void __launch_bounds__(256) xrow_kernel(const DevPlan* __restrict__ p
         return;
     }
     if constexpr (MODE == MODE_C2R_OUT) {
-        stage_rows(bufs.in, NC);
-        __syncthreads();
         float2 v[P];
-        build_z(v, NC);
+        build_z(v, bufs.in, NC);
         fft_line<L, P, 1>(v, line, t, tw);
         float* __restrict__ dst = bufs.real_out;
 #pragma unroll
@@ -642,12 +653,8 @@ __global__ void __launch_bounds__(256) xrow_kernel(const DevPlan* __restrict__ p
     float2 z[NG][P];
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
-        const int ncol = p.mask[g].ncol;
-        stage_rows(bufs.V[g], ncol);
-        __syncthreads();
         float2 v[P];
-        build_z(v, ncol);
-        __syncthreads();  // stage is reused by the next factor
+        build_z(v, bufs.V[g], p.mask[g].ncol);
         fft_line<L, P, 1>(v, line, t, tw);
 #pragma unroll
         for (int m = 0; m < P; ++m) z[g][m] = cscale(v[m], p.inv_n);
@@ -856,47 +863,67 @@ static hipError_t launch_xrow_t(int mode, const LaunchArgs& a) {
 #define PSS_CAT2(a, b) a##b
 #define PSS_CAT(a, b) PSS_CAT2(a, b)
 
+// points-per-thread variants: P = geo.pu (update) or geo.px (x kernel), any
+// of 16, 8, 4 not above the cap for the number of register arrays
+template <int L, int CAP, class F>
+static hipError_t with_points(int want, F&& f) {
+    if constexpr (L >= 16 && CAP >= 16) {
+        if (want == 16) return f(std::integral_constant<int, 16>{});
+    }
+    if constexpr (L >= 8 && CAP >= 8) {
+        if (want == 8) return f(std::integral_constant<int, 8>{});
+    }
+    if constexpr (L >= 4 && CAP >= 4) {
+        if (want == 4) return f(std::integral_constant<int, 4>{});
+    }
+    if constexpr (L < 4) {
+        if (want == L) return f(std::integral_constant<int, L>{});
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t PSS_CAT(launch_update_L, PSS_LINE_LEN)(int mode, int nf, const LaunchArgs& a) {
     constexpr int L = PSS_LINE_LEN;
-    constexpr int P = points_per_thread(L, 1);
-    if (mode == MODE_FWD_STORE || mode == MODE_INV_OUT) return launch_update_t<L, P, 1>(mode, a);
-    switch (nf) {
-        case 1: return launch_update_t<L, P, 1>(mode, a);
-        case 2: return launch_update_t<L, points_per_thread(L, 2), 2>(mode, a);
-        case 3:
-        case 4: return launch_update_t<L, points_per_thread(L, 4), 4>(mode, a);
-        default: return hipErrorInvalidValue;
-    }
+    const int pu = a.geo.pu;
+    if (mode == MODE_FWD_STORE || mode == MODE_INV_OUT || nf <= 1)
+        return with_points<L, 16>(pu, [&](auto P) { return launch_update_t<L, decltype(P)::value, 1>(mode, a); });
+    if (nf == 2)
+        return with_points<L, 8>(pu, [&](auto P) { return launch_update_t<L, decltype(P)::value, 2>(mode, a); });
+    if (nf <= 4)
+        return with_points<L, 4>(pu, [&](auto P) { return launch_update_t<L, decltype(P)::value, 4>(mode, a); });
+    return hipErrorInvalidValue;
 }
 
 hipError_t PSS_CAT(launch_ypass_L, PSS_LINE_LEN)(int mode, const YArgs& ya, const LaunchArgs& a) {
     constexpr int L = PSS_LINE_LEN;
-    constexpr int P = ypass_points(L);
-    const int threads = a.geo.tc * a.geo.tz * (L / P);
-    const size_t lds = ypass_lds_bytes(L, a.geo.tc, a.geo.tz);
-    dim3 grid(a.geo.nyblk), block(threads);
-    if (mode == MODE_YINV) {
-        hipLaunchKernelGGL((ypass_kernel<L, P, MODE_YINV>), grid, block, lds, a.stream, ya, a.geo, a.tw_y);
-    } else if (mode == MODE_YFWD) {
-        hipLaunchKernelGGL((ypass_kernel<L, P, MODE_YFWD>), grid, block, lds, a.stream, ya, a.geo, a.tw_y);
-    } else {
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return with_points<L, 16>(a.geo.py, [&](auto PP) {
+        constexpr int P = decltype(PP)::value;
+        const int threads = a.geo.tc * a.geo.tz * (L / P);
+        const size_t lds = ypass_lds_bytes(L, a.geo.tc, a.geo.tz);
+        dim3 grid(a.geo.nyblk), block(threads);
+        if (mode == MODE_YINV) {
+            hipLaunchKernelGGL((ypass_kernel<L, P, MODE_YINV>), grid, block, lds, a.stream, ya, a.geo, a.tw_y);
+        } else if (mode == MODE_YFWD) {
+            hipLaunchKernelGGL((ypass_kernel<L, P, MODE_YFWD>), grid, block, lds, a.stream, ya, a.geo, a.tw_y);
+        } else {
+            return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    });
 }
 
 hipError_t PSS_CAT(launch_xrow_L, PSS_LINE_LEN)(int mode, int ng, const LaunchArgs& a) {
     constexpr int L = PSS_LINE_LEN;
-    constexpr int P = points_per_thread(L, 1);
-    if (mode != MODE_STEP) return launch_xrow_t<L, P, 1>(mode, a);
-    switch (ng) {
-        case 0:
-        case 1: return launch_xrow_t<L, P, 1>(mode, a);
-        case 2: return launch_xrow_t<L, points_per_thread(L, 2), 2>(mode, a);
-        case 3: return launch_xrow_t<L, points_per_thread(L, 4), 3>(mode, a);
-        case 4: return launch_xrow_t<L, points_per_thread(L, 4), 4>(mode, a);
-        default: return hipErrorInvalidValue;
-    }
+    const int px = a.geo.px;
+    if (mode != MODE_STEP || ng <= 1)
+        return with_points<L, 16>(px, [&](auto P) { return launch_xrow_t<L, decltype(P)::value, 1>(mode, a); });
+    if (ng == 2)
+        return with_points<L, 8>(px, [&](auto P) { return launch_xrow_t<L, decltype(P)::value, 2>(mode, a); });
+    if (ng == 3)
+        return with_points<L, 4>(px, [&](auto P) { return launch_xrow_t<L, decltype(P)::value, 3>(mode, a); });
+    if (ng == 4)
+        return with_points<L, 4>(px, [&](auto P) { return launch_xrow_t<L, decltype(P)::value, 4>(mode, a); });
+    return hipErrorInvalidValue;
 }
 #endif  // PSS_LINE_LEN
 
@@ -916,14 +943,9 @@ PSS_DECL_L(1024)
 PSS_DECL_L(2048)
 PSS_DECL_L(4096)
 
-int update_threads(int L, int nf, int tc) {
-    const int k = nf <= 1 ? 1 : (nf == 2 ? 2 : 4);
-    return tc * (L / points_per_thread(L, k));
-}
-
-int xrow_threads(int L, int ng, int rb) {
-    const int k = ng <= 1 ? 1 : (ng == 2 ? 2 : 4);
-    return (rb / 2) * (L / points_per_thread(L, k));
+int max_points(int L, int nregs) {
+    const int cap = nregs <= 1 ? 16 : (nregs == 2 ? 8 : 4);
+    return cap < L ? cap : L;
 }
 
 hipError_t launch_update(int mode, int L, int nf, const LaunchArgs& a) {
@@ -941,8 +963,6 @@ hipError_t launch_update(int mode, int L, int nf, const LaunchArgs& a) {
         default: return hipErrorInvalidValue;
     }
 }
-
-int ypass_threads(int L, int tc, int tz) { return tc * tz * (L / ypass_points(L)); }
 
 hipError_t launch_ypass(int mode, int L, const YArgs& ya, const LaunchArgs& a) {
     switch (L) {

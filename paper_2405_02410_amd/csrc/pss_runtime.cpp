@@ -160,6 +160,7 @@ struct pss_ctx {
     double* d_shell_sum = nullptr;
     unsigned long long* d_shell_cnt = nullptr;
     std::map<int64_t, hipGraphExec_t> graphs;
+    std::map<std::string, int64_t> tune;  // launch-geometry overrides
     int64_t steps_taken = 0;
 
     int64_t sites() const { return static_cast<int64_t>(n[0]) * n[1] * n[2]; }
@@ -408,6 +409,9 @@ int pick_pow2(int want, int lo, int hi) {
     return std::max(lo, std::min(hi, v));
 }
 
+// Launch geometry.  Defaults come from the sizes; pss_tuning_set can force any
+// of tc, to, tz, rb (powers of two) and pu, px, py (points per thread: 4, 8 or
+// 16) before the plan is built.
 pss_status choose_geometry(pss_ctx* c) {
     const int nf = static_cast<int>(c->fields.size());
     const int ng = std::max(1, c->plan.ng);
@@ -417,43 +421,58 @@ pss_status choose_geometry(pss_ctx* c) {
     pss::Geo& g = c->geo;
     g = pss::Geo{};
     g.nz = nz;
+    auto tuned = [&](const char* key, int def) {
+        auto it = c->tune.find(key);
+        return it == c->tune.end() ? def : static_cast<int>(it->second);
+    };
+    auto pow2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };
+    c->lu = c->ndim == 2 ? ny : nz;
+    const int lu = c->lu;
+    g.pu = tuned("pu", pss::max_points(lu, pss::field_slots(nf)));
+    g.px = tuned("px", pss::max_points(nx, pss::field_slots(ng)));
+    g.py = tuned("py", pss::max_points(ny, 1));
+    if (!pow2(g.pu) || g.pu > pss::max_points(lu, pss::field_slots(nf)) || !pow2(g.px) ||
+        g.px > pss::max_points(nx, pss::field_slots(ng)) || !pow2(g.py) || g.py > pss::max_points(ny, 1))
+        return fail(PSS_E_UNSUPPORTED, "points per thread must be a power of two up to the variant limit");
+    const int tu = lu / g.pu;
     if (c->ndim == 2) {
-        c->lu = ny;
-        // update kernel: TC columns of T = L/P threads; up to 256 threads
-        const int tu = pss::update_threads(ny, nf, 1);
-        if (tu > 256)
-            return fail(PSS_E_UNSUPPORTED, "line length %d with %d fields needs more than 256 threads", ny, nf);
-        g.tc = std::min(std::max(1, 256 / tu), ncols);
+        g.tc = tuned("tc", std::min(std::max(1, 256 / tu), ncols));
         g.to = 1;
-        g.ntile = ncols / g.tc;
-        g.nublk = g.ntile;
     } else {
-        c->lu = nz;
-        const int tu = pss::update_threads(nz, nf, 1);
-        if (tu > 256)
-            return fail(PSS_E_UNSUPPORTED, "line length %d with %d fields needs more than 256 threads", nz, nf);
-        g.tc = std::min(4, ncols);
-        g.to = std::max(1, std::min(256 / (g.tc * tu), ny / 2));
-        g.ntile = ncols / g.tc;
-        g.nublk = g.ntile * (ny / g.to);
-        const int ty = pss::ypass_threads(ny, g.tc, 1);
+        g.tc = tuned("tc", std::min(4, ncols));
+        g.to = tuned("to", std::max(1, std::min(256 / (g.tc * tu), ny / 2)));
+    }
+    if (!pow2(g.tc) || g.tc > ncols || !pow2(g.to) || g.to > std::max(1, ny / 2))
+        return fail(PSS_E_UNSUPPORTED, "tile width tc must be a power of two up to Nx/2, to up to Ny/2");
+    if (g.tc * g.to * tu > 256)
+        return fail(PSS_E_UNSUPPORTED, "update kernel block of %d threads exceeds 256", g.tc * g.to * tu);
+    g.ntile = ncols / g.tc;
+    g.nublk = c->ndim == 2 ? g.ntile : g.ntile * (ny / g.to);
+    if (c->ndim == 3) {
+        const int ty = g.tc * (ny / g.py);
         if (ty > 256) return fail(PSS_E_UNSUPPORTED, "y line length %d needs more than 256 threads", ny);
-        g.tz = std::max(1, std::min(256 / ty, nz));
+        g.tz = tuned("tz", std::max(1, std::min(256 / ty, nz)));
+        if (!pow2(g.tz) || g.tz > nz || g.tz * ty > 256)
+            return fail(PSS_E_UNSUPPORTED, "y-pass block (tz = %d) is too large", g.tz);
         g.nyblk = g.ntile * (nz / g.tz);
         if (pss::ypass_lds_bytes(ny, g.tc, g.tz) > 160 * 1024)
             return fail(PSS_E_UNSUPPORTED, "y pass needs more LDS than a workgroup has");
     }
     // x kernel: RB rows (pairs of T threads); aim for >= 512 blocks, 64..256 threads
-    const int tx = pss::xrow_threads(nx, ng, 2);
+    const int tx = nx / g.px;
     if (tx > 256) return fail(PSS_E_UNSUPPORTED, "row length %d needs more than 256 threads", nx);
     const int rows = ny * nz;
     const int rb_lo = std::max(2, 2 * (64 / tx));
     const int rb_hi = std::max(2, 2 * (256 / tx));
     int rb = pick_pow2(std::max(2, rows / 512), rb_lo, rb_hi);
-    rb = std::min(rb, ny);  // a block's rows share z
+    rb = tuned("rb", std::min(rb, ny));  // a block's rows share z
+    if (!pow2(rb) || rb < 2 || rb > ny || (rb / 2) * tx > 256)
+        return fail(PSS_E_UNSUPPORTED, "x-kernel block of %d rows is not valid", rb);
     g.rb = rb;
     g.nrowblk = rows / rb;
-    const size_t lu_lds = pss::update_lds_bytes(c->lu, pss::field_slots(nf), g.tc, g.to);
+    g.tc_log2 = 0;
+    while ((1 << g.tc_log2) < g.tc) ++g.tc_log2;
+    const size_t lu_lds = pss::update_lds_bytes(lu, pss::field_slots(nf), g.tc, g.to);
     const size_t lx_lds = pss::xrow_lds_bytes(nx, rb);
     if (lu_lds > 160 * 1024 || lx_lds > 160 * 1024)
         return fail(PSS_E_UNSUPPORTED, "lattice needs more LDS than a workgroup has (%zu, %zu bytes)", lu_lds,
@@ -941,6 +960,38 @@ pss_status pss_stream_set(pss_ctx* c, void* stream) {
         c->own_stream = true;
     }
     return PSS_OK;
+}
+
+pss_status pss_tuning_set(pss_ctx* c, const char* key, int64_t value) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (c->planned) return fail(PSS_E_STATE, "the launch geometry is fixed once the plan is built");
+    static const char* keys[] = {"tc", "to", "tz", "rb", "pu", "px", "py"};
+    if (!key) return fail(PSS_E_INVAL, "null key");
+    for (const char* k : keys)
+        if (std::strcmp(k, key) == 0) {
+            if (value <= 0) {
+                c->tune.erase(key);
+            } else {
+                c->tune[key] = value;
+            }
+            return PSS_OK;
+        }
+    return fail(PSS_E_INVAL, "unknown tuning key '%s'", key);
+}
+
+pss_status pss_tuning_get(pss_ctx* c, const char* key, int64_t* value) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (!key || !value) return fail(PSS_E_INVAL, "null argument");
+    if (pss_status s = materialize(c)) return s;
+    const pss::Geo& g = c->geo;
+    const std::pair<const char*, int> vals[] = {{"tc", g.tc}, {"to", g.to}, {"tz", g.tz}, {"rb", g.rb},
+                                                {"pu", g.pu}, {"px", g.px}, {"py", g.py}};
+    for (auto& kv : vals)
+        if (std::strcmp(kv.first, key) == 0) {
+            *value = kv.second;
+            return PSS_OK;
+        }
+    return fail(PSS_E_INVAL, "unknown tuning key '%s'", key);
 }
 
 pss_status pss_validate(pss_ctx* c) {
