@@ -21,12 +21,42 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+# Summary of the FETCH_SIZE / WRITE_SIZE counter runs of the update kernel on
+# this workload; its traffic figure is reported only while the kernel sources
+# and the launch geometry are the ones the counters were taken with.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_update_kernel_modelb_1024.txt")
+KERNEL_SOURCES = ("pss_kernels.hip", "pss_device.h", "pss_kernels.h", "pss_plan.h")
 N = (1024, 1024)
 A, B, K, D, DT, SEED = -1.0, 1.0, 1.0, 0.01, 0.01, 1
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2405_02410_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(geometry):
+    """HBM bytes per update-kernel launch from the committed counter summary,
+    or None if it is missing or was taken on other kernel code or geometry."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(l.split(":", 1) for l in f.read().splitlines() if ":" in l)
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("source_sha256") != kernel_source_hash():
+        return None
+    if kv.get("geometry") != json.dumps(geometry, sort_keys=True):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(steps):
@@ -55,6 +85,9 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=2000)
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB three times with a plain device "
+                         "copy (a known-size reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the lattice is not sharded.",
@@ -94,10 +127,20 @@ def main():
         f"{xname} {ms_x * 1e3:.2f} us/launch, {xb / 1e6:.2f} MB -> {xb / (ms_x * 1e-3) / 1e9:.0f} GB/s")
     step_bytes = kb + xb
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(lat.geometry()),
                 "kernel": kname, "bytes_per_launch": kb, "us_per_launch": round(ms_k * 1e3, 3),
                 "step_bytes": step_bytes,
                 "step_GBs": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1)}
+
+    if args.copy_mib > 0:
+        nbytes = args.copy_mib << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copied {args.copy_mib} MiB three times")
+        del src, dst
 
     cpu = None
     if not args.no_cpu:

@@ -139,6 +139,19 @@ struct DFT<16, DIR> {
     }
 };
 
+// ------------------------------------------------------------ block order
+// The hardware hands out the blocks of a grid round-robin over the 8 XCDs
+// (block b starts on XCD b mod 8), and each XCD has its own L2.  Renumber
+// the blocks so that every XCD works on one contiguous range of logical
+// blocks: neighbouring rows or lines that share cache lines then share an
+// L2.  A bijection on [0, n) for any n.
+__device__ __forceinline__ int xcd_block(int b, int n) {
+    constexpr int X = 8;
+    const int per = n / X, rem = n % X;
+    const int x = b % X, k = b / X;
+    return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + k;
+}
+
 // ------------------------------------------------------------ LDS line FFT
 // Padding of LDS line buffers: one float2 every 16 to spread banks.
 __host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }

@@ -279,8 +279,9 @@ __global__ void __launch_bounds__(256) update_kernel(const DevPlan* __restrict__
     const int cc = tid % tc;
     const int lo = (tid / tc) % to;
     const int t = tid / (tc * to);
-    const int ct = blockIdx.x % ntile;  // tile index
-    const int og = blockIdx.x / ntile;  // group of `to` other-index lines
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int ct = blk % ntile;  // tile index
+    const int og = blk / ntile;  // group of `to` other-index lines
     const int o = og * to + lo;
     const int c = ct * tc + cc;         // packed column
     const int nx = p.n[0], ny = p.n[1];
@@ -487,8 +488,9 @@ __global__ void __launch_bounds__(256) ypass_kernel(YArgs ya, Geo geo, const flo
     const int cc = tid % tc;
     const int lz = (tid / tc) % tz;
     const int t = tid / (tc * tz);
-    const int ct = blockIdx.x % ntile;
-    const int z = (blockIdx.x / ntile) * tz + lz;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int ct = blk % ntile;
+    const int z = (blk / ntile) * tz + lz;
     const int c = ct * tc + cc;
     float2* line = smem + (lz * tc + cc) * lds_line(L);
     float2* xb = smem + tc * tz * lds_line(L) + lz * L;  // column-0 exchange, one line per z
@@ -561,7 +563,7 @@ __global__ void __launch_bounds__(256) xrow_kernel(const DevPlan* __restrict__ p
     const int nthr = blockDim.x;
     const int pr = tid / T;  // pair within the block
     const int t = tid % T;
-    const int r0 = blockIdx.x * rb;  // first row; row index = z*Ny + y
+    const int r0 = xcd_block(blockIdx.x, gridDim.x) * rb;  // first row; row index = z*Ny + y
     const int ny = p.n[1];
     const int zr = r0 / ny;          // z of the block (0 in 2D)
     const int y0 = r0 - zr * ny;     // first y of the block

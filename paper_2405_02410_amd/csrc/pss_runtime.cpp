@@ -428,11 +428,14 @@ pss_status choose_geometry(pss_ctx* c) {
     auto pow2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };
     c->lu = c->ndim == 2 ? ny : nz;
     const int lu = c->lu;
-    g.pu = tuned("pu", pss::max_points(lu, pss::field_slots(nf)));
-    g.px = tuned("px", pss::max_points(nx, pss::field_slots(ng)));
-    g.py = tuned("py", pss::max_points(ny, 1));
+    // default: the fewest points per thread (most threads per line) that keep
+    // a line within one 256-thread block; fewer points per thread measured
+    // faster for every kernel (lower register use, more waves in flight)
+    auto few_points = [](int L, int cap) { return std::min(cap, std::max(std::min(4, L), L / 256)); };
+    g.pu = tuned("pu", few_points(lu, pss::max_points(lu, pss::field_slots(nf))));
+    g.px = tuned("px", few_points(nx, pss::max_points(nx, pss::field_slots(ng))));
     if (!pow2(g.pu) || g.pu > pss::max_points(lu, pss::field_slots(nf)) || !pow2(g.px) ||
-        g.px > pss::max_points(nx, pss::field_slots(ng)) || !pow2(g.py) || g.py > pss::max_points(ny, 1))
+        g.px > pss::max_points(nx, pss::field_slots(ng)))
         return fail(PSS_E_UNSUPPORTED, "points per thread must be a power of two up to the variant limit");
     const int tu = lu / g.pu;
     if (c->ndim == 2) {
@@ -449,6 +452,11 @@ pss_status choose_geometry(pss_ctx* c) {
     g.ntile = ncols / g.tc;
     g.nublk = c->ndim == 2 ? g.ntile : g.ntile * (ny / g.to);
     if (c->ndim == 3) {
+        // y pass: TC lines of Ny points per z share a block of <= 256 threads
+        g.py = tuned("py", std::min(pss::max_points(ny, 1),
+                                    std::max(few_points(ny, pss::max_points(ny, 1)), pick_pow2(g.tc * ny / 256, 1, 16))));
+        if (!pow2(g.py) || g.py > pss::max_points(ny, 1))
+            return fail(PSS_E_UNSUPPORTED, "points per thread must be a power of two up to the variant limit");
         const int ty = g.tc * (ny / g.py);
         if (ty > 256) return fail(PSS_E_UNSUPPORTED, "y line length %d needs more than 256 threads", ny);
         g.tz = tuned("tz", std::max(1, std::min(256 / ty, nz)));
