@@ -295,3 +295,51 @@ def test_step_zero_and_seed_dependence():
     a.step(5)
     b.step(5)
     assert not np.array_equal(a.spectrum(0), b.spectrum(0))
+
+
+def _tuned_model_b(n, steps, **kw):
+    p = inputs.MODEL_B
+    lat = pss.Lattice(n, dt=p["dt"], seed=5)
+    f, _ = pss.model_b(lat, a=p["a"], b=p["b"], k=p["k"], D=0.01)
+    lat.tune(**kw)
+    lat.init_uniform(f, -0.1, 0.1)
+    lat.step(steps)
+    return lat
+
+
+# Tiling (tc, to, tz, rb) regroups the same per-line arithmetic: bitwise equal.
+# Points per thread (pu, px, py) change the FFT radix and so the rounding:
+# equal to FP32 accuracy, and still on the oracle.
+@pytest.mark.parametrize("kw", [dict(tc=1), dict(tc=2), dict(rb=8), dict(tc=2, rb=4),
+                                dict(pu=8), dict(pu=16, tc=16), dict(px=8, rb=16), dict(px=16, rb=32)])
+def test_launch_geometry_leaves_the_result(kw):
+    n, steps = (256, 256), 20
+    ref = _tuned_model_b(n, steps)
+    lat = _tuned_model_b(n, steps, **kw)
+    g0, g1 = ref.geometry(), lat.geometry()
+    for k, v in kw.items():
+        assert g1[k] == v
+    a, b = lat.spectrum(0), ref.spectrum(0)
+    if (g0["pu"], g0["px"]) == (g1["pu"], g1["px"]):
+        assert np.array_equal(a, b)
+    else:
+        assert _rel(a, b) < 1e-5
+        p = inputs.MODEL_B
+        m = om.model_b(_olat(n), p["dt"], a=p["a"], b=p["b"], k=p["k"], D=0.01, seed=5)
+        m.init_uniform(0, -0.1, 0.1)
+        m.step(steps)
+        assert np.max(np.abs(lat.download(0) - m.real(0)[0])) < 2e-5
+
+
+@pytest.mark.parametrize("kw", [dict(tc=2, to=2, tz=2), dict(tc=1, to=4, tz=4), dict(tc=8, to=1, tz=1)])
+def test_launch_geometry_3d_is_bitwise(kw):
+    n = (32, 32, 32)
+    out = []
+    for t in ({}, kw):
+        lat = pss.Lattice(n, dt=0.01, seed=9)
+        f, _ = pss.model_b(lat, D=0.02)
+        lat.tune(**t)
+        lat.init_uniform(f)
+        lat.step(10)
+        out.append(lat.spectrum(f))
+    assert np.array_equal(out[0], out[1])
