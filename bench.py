@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=2000)
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", choices=("modelb1024", "ensemble"), default="modelb1024",
+                    help="modelb1024: one 1024^2 lattice (default); ensemble: 256x128^2 + 64x256^2 + "
+                         "16x512^2 independent lattices in one batch, also timed one lattice per launch")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times with a plain device "
                          "copy (a known-size reference for hardware byte counters)")
@@ -100,6 +103,8 @@ def main():
         log("no GPU visible")
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.workload == "ensemble":
+        return ensemble(args, pss)
 
     lat = pss.Lattice(N, dt=DT, seed=SEED)
     f, _ = pss.model_b(lat, a=A, b=B, k=K, D=D)
@@ -160,6 +165,107 @@ def main():
         "mass_after": mass,
     }
     print(json.dumps(out), flush=True)
+
+
+ENSEMBLE = ((256, 128), (64, 256), (16, 512))  # (members, side)
+
+
+def ensemble_cpu_baseline(steps):
+    """The FP64 oracle on `steps` steps of one 512^2 member (after one warm-up)."""
+    from oracle import model as om
+    from oracle import spectral
+    cores = os.cpu_count() or 1
+    spectral.WORKERS = cores
+    m = om.model_b(spectral.Lattice(512, 512), DT, a=A, b=B, k=K, D=D, seed=SEED)
+    m.init_uniform(0, -0.1, 0.1)
+    m.step(1)
+    t0 = time.perf_counter()
+    m.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": 512 * 512 * steps / dt, "unit": "site-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} steps of one 512x512 member of the ensemble after 1 warm-up step "
+                      f"(numpy FP64, scipy.fft with {cores} workers); members are independent, so the "
+                      f"site-step rate carries over to the whole ensemble"}
+
+
+def ensemble(args, pss):
+    """Batched ensemble: every member in one batch (one update and one x launch
+    per size class and step) against the same members stepped one lattice per
+    launch sequence (pss_step on each, each on its own stream)."""
+    def build():
+        lats, seed = [], 1000
+        for count, side in ENSEMBLE:
+            for _ in range(count):
+                lat = pss.Lattice((side, side), dt=DT, seed=seed)
+                f, _ = pss.model_b(lat, a=A, b=B, k=K, D=D)
+                lat.init_uniform(f, -0.1, 0.1)
+                lats.append(lat)
+                seed += 1
+        return lats
+    lats = build()
+    sites = sum(c * s * s for c, s in ENSEMBLE)
+    batch = pss.Batch(lats)
+    log(f"bench: ensemble of {len(lats)} lattices, {sites} sites, {batch.classes()[0]} classes")
+    batch.step(args.warmup)
+    batch.sync()
+    t0 = time.perf_counter()
+    batch.step(args.steps)
+    batch.sync()
+    el = time.perf_counter() - t0
+    value = sites * args.steps / el
+    ms_per_step = 1e3 * el / args.steps
+    log(f"bench: batched {ms_per_step * 1e3:.1f} us/step, {value:.4e} site-steps/s")
+
+    # one lattice per launch sequence: the same members, pss_step on each
+    plain_steps = max(1, args.steps // 10)
+    for lat in lats:
+        lat.step(args.warmup)
+    for lat in lats:
+        lat.sync()
+    t0 = time.perf_counter()
+    for lat in lats:
+        lat.step(plain_steps)
+    for lat in lats:
+        lat.sync()
+    pel = time.perf_counter() - t0
+    plain = sites * plain_steps / pel
+    log(f"bench: plain {1e6 * pel / plain_steps:.1f} us/step, {plain:.4e} site-steps/s")
+
+    # roofline of the kernel with the largest share of the batched step
+    best = None
+    for cls in range(batch.classes()[0]):
+        for which in (pss.KERNEL_UPDATE, pss.KERNEL_X):
+            ms, nbytes = batch.time_kernel(cls, which, args.kernel_reps)
+            log(f"bench: class {cls} kernel {which}: {ms * 1e3:.2f} us/launch, {nbytes / 1e6:.2f} MB")
+            if best is None or ms > best[0]:
+                best = (ms, nbytes, cls, which)
+    ms, nbytes, cls, which = best
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"{'update_kernel' if which == 0 else 'xrow_kernel'} (batched, size class {cls})",
+                "bytes_per_launch": nbytes, "us_per_launch": round(ms * 1e3, 3)}
+    cpu = None
+    if not args.no_cpu:
+        log("bench: timing the oracle on 10 steps of one 512^2 member")
+        cpu = ensemble_cpu_baseline(10)
+    out = {
+        "metric": "site-steps/s", "value": value, "unit": "site-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "ensemble of 2D Model B lattices, 256x128^2 + 64x256^2 + 16x512^2 FP32, "
+                               "a=-1 b=1 k=1, D=0.01 q^2, dt=0.01, 2/3 radial de-aliasing, independent seeds, "
+                               "one batch",
+                   "members": len(lats), "sites": sites, "parallelism": "single GPU"},
+        "plain": {"value": plain, "steps": plain_steps,
+                  "form": "pss_step on each lattice in turn, each on its own stream"},
+        "vs_plain": round(value / plain, 2),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    batch.close()
 
 
 if __name__ == "__main__":

@@ -54,6 +54,7 @@ extern "C" {
 #endif
 
 typedef struct pss_ctx pss_ctx;
+typedef struct pss_batch pss_batch;
 typedef int32_t pss_status;
 
 #define PSS_OK 0
@@ -244,6 +245,53 @@ pss_status pss_kernel_bytes(pss_ctx *ctx, int32_t which, double *bytes);
 
 /* Number of kernels in one step (2 in 2D, 4 in 3D). */
 pss_status pss_kernels_per_step(pss_ctx *ctx, int32_t *count);
+
+/* ------------------------------------------------------------------ batches
+ * Many independent 2D lattices advanced together.  The paper finds small
+ * lattices overhead-bound on the GPU (its benchmarks: the CPU version wins
+ * below 128^2, Sec. "Benchmarks"); a batch runs every lattice of one size
+ * class in the same launches, so the per-launch cost is paid once per class
+ * and the launches hold enough blocks to fill the chip.
+ *
+ * Lattices with equal sizes, field count, factor and channel counts and launch
+ * geometry form one class: per time step, one update launch and one x launch
+ * each, with the lattice picked by blockIdx.y from a table of its plan,
+ * buffers and step counter.  Every lattice keeps its own model, coefficients,
+ * seed (noise keys), de-aliasing, state and step counter; a batch step gives,
+ * bit for bit, the state that pss_step gives on that lattice alone. */
+
+/* Make a batch of n >= 1 distinct 2D lattices (3D lattices: PSS_E_UNSUPPORTED;
+ * a lattice listed twice or a null entry: PSS_E_INVAL).  The lattices are
+ * planned (as by pss_validate) if they were not.  seeds may be NULL; else
+ * seeds[i] is set on lattices[i] as by pss_seed_set.  The batch borrows the
+ * lattices: pss_lattice_destroy of a member fails with PSS_E_STATE until every
+ * batch holding it is destroyed.  Members stay usable on their own (state I/O,
+ * pss_step, pss_term_set_coef, pss_state_load); work on a member's stream is
+ * ordered against the batch's steps.  The batch runs on the first lattice's
+ * stream. */
+pss_status pss_batch_create(pss_batch **batch, pss_ctx *const *lattices, int32_t n, const uint64_t *seeds);
+
+/* Wait for the batch's work and free the batch (not its lattices). NULL is a no-op. */
+pss_status pss_batch_destroy(pss_batch *batch);
+
+/* Advance every member by nsteps >= 0 steps (asynchronous, like pss_step;
+ * captured HIP graphs of up to 50 steps). */
+pss_status pss_batch_step(pss_batch *batch, int64_t nsteps);
+
+/* Block until the batch's stream is idle. */
+pss_status pss_batch_sync(pss_batch *batch);
+
+/* Number of size classes; class_of (may be NULL, else n entries) receives the
+ * class of each member in creation order. */
+pss_status pss_batch_info(pss_batch *batch, int32_t *n_classes, int32_t *class_of);
+
+/* Time `reps` back-to-back launches of one class's update kernel (which = 0)
+ * or x kernel (which = 1) with HIP events on the batch stream: *ms per launch;
+ * *bytes (may be NULL) the launch's algorithmic HBM bytes (the first member's
+ * per-lattice figure times the class size).  Leaves the members' channel
+ * arrays stale, so the next step rebuilds them; for timing only. */
+pss_status pss_batch_time_kernel(pss_batch *batch, int32_t cls, int32_t which, int32_t reps, double *ms,
+                                 double *bytes);
 
 const char *pss_last_error(void);
 

@@ -84,6 +84,14 @@ _SIGS = {
     "pss_kernels_per_step": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)],
     "pss_tuning_set": [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64],
     "pss_tuning_get": [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)],
+    "pss_batch_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                         ctypes.POINTER(ctypes.c_uint64)],
+    "pss_batch_destroy": [ctypes.c_void_p],
+    "pss_batch_step": [ctypes.c_void_p, ctypes.c_int64],
+    "pss_batch_sync": [ctypes.c_void_p],
+    "pss_batch_info": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+    "pss_batch_time_kernel": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
 }
 
 
@@ -158,7 +166,7 @@ class Lattice:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().pss_lattice_destroy(self._h)
+            _check(lib().pss_lattice_destroy(self._h))  # fails while a batch holds it
             self._h = None
 
     def __del__(self):
@@ -299,6 +307,52 @@ class Lattice:
         v = ctypes.c_int32()
         _check(lib().pss_kernels_per_step(self._h, ctypes.byref(v)))
         return v.value
+
+
+class Batch:
+    """Independent 2D lattices advanced together (pss_batch_*): one update and
+    one x launch per size class and step.  Holds references to its lattices;
+    close() (or garbage collection) frees the batch, not the lattices."""
+
+    def __init__(self, lattices, seeds=None):
+        self.lattices = list(lattices)
+        n = len(self.lattices)
+        hs = (ctypes.c_void_p * max(n, 1))(*[l._h for l in self.lattices])
+        sd = None if seeds is None else (ctypes.c_uint64 * n)(*[int(v) for v in seeds])
+        h = ctypes.c_void_p()
+        _check(lib().pss_batch_create(ctypes.byref(h), hs, n, sd))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().pss_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, nsteps=1):
+        _check(lib().pss_batch_step(self._h, int(nsteps)))
+
+    def sync(self):
+        _check(lib().pss_batch_sync(self._h))
+
+    def classes(self):
+        """(number of size classes, class of each member)."""
+        nc = ctypes.c_int32()
+        of = (ctypes.c_int32 * len(self.lattices))()
+        _check(lib().pss_batch_info(self._h, ctypes.byref(nc), of))
+        return nc.value, list(of)
+
+    def time_kernel(self, cls, which=KERNEL_UPDATE, reps=100):
+        """(ms per launch, algorithmic bytes per launch) of one class's kernel."""
+        ms, b = ctypes.c_double(), ctypes.c_double()
+        _check(lib().pss_batch_time_kernel(self._h, int(cls), int(which), int(reps), ctypes.byref(ms),
+                                           ctypes.byref(b)))
+        return ms.value, b.value
 
 
 def philox(counter0, c1, c2, c3, k0, k1, count, out):

@@ -57,12 +57,24 @@ struct YArgs {
     int n;
 };
 
+// One lattice of a step launch.  The step kernels (update STEP / PROLOGUE,
+// x STEP) read plan, buffers and step counter of lattice blockIdx.y from a
+// table of these in device memory; the lattices of one launch share the
+// geometry (sizes, fields, factors, channels, tiling) and the twiddles.
+struct Member {
+    const DevPlan* plan;
+    Bufs bufs;
+    const uint64_t* step_ctr;
+};
+
 struct LaunchArgs {
     hipStream_t stream;
     const DevPlan* plan;
     Bufs bufs;
     Geo geo;
     const uint64_t* step_ctr;
+    const Member* members;  // step modes: table of nmem lattices (device memory)
+    int nmem;
     int step_off;
     const float2* tw_u;  // twiddles of the update-axis length
     const float2* tw_x;  // twiddles of Nx
@@ -78,6 +90,8 @@ hipError_t launch_update(int mode, int L, int nf, const LaunchArgs& a);
 hipError_t launch_xrow(int mode, int L, int ng, const LaunchArgs& a);
 hipError_t launch_ypass(int mode, int L, const YArgs& ya, const LaunchArgs& a);
 hipError_t launch_advance(hipStream_t s, uint64_t* step_ctr, int64_t k);
+// *ctrs[i] += k for i < n (the step counters of a batch)
+hipError_t launch_advance_many(hipStream_t s, uint64_t* const* ctrs, int n, int64_t k);
 hipError_t launch_init_uniform(hipStream_t s, float* out, int64_t n, uint32_t field, uint32_t key0, uint32_t key1,
                                double lo, double hi);
 hipError_t launch_philox(hipStream_t s, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,

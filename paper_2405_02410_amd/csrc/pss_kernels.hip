@@ -267,19 +267,29 @@ __device__ __forceinline__ float2 pair_update_d(const DevPlan& p, int f, uint32_
 }
 
 template <int L, int P, int NF, int MODE, int DIM>
-__global__ void __launch_bounds__(256) update_kernel(const DevPlan* __restrict__ plan, Bufs bufs, Geo geo,
-                                                      const uint64_t* __restrict__ step_ctr,
+__global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ members,
+                                                      const DevPlan* __restrict__ plan_a, Bufs bufs_a, Geo geo,
+                                                      const uint64_t* __restrict__ step_ctr_a,
                                                       int step_off, const float2* __restrict__ tw_g) {
     constexpr int T = L / P;
     extern __shared__ float2 smem[];
-    const DevPlan& p = *plan;
+    // step modes: lattice blockIdx.y of the member table; the transform
+    // modes act on the single lattice of the arguments (gridDim.y = 1)
+    constexpr bool TAB = MODE == MODE_STEP || MODE == MODE_PROLOGUE;
+    const int nb = gridDim.x;
+    const int lin = xcd_block(blockIdx.y * nb + blockIdx.x, nb * gridDim.y);
+    const int mi = lin / nb;
+    const int blk = lin - mi * nb;
+    const Member* mem = members + mi;  // dereferenced in the step modes only
+    const DevPlan& p = TAB ? *mem->plan : *plan_a;
+    const Bufs& bufs = TAB ? mem->bufs : bufs_a;
+    const uint64_t* __restrict__ step_ctr = TAB ? mem->step_ctr : step_ctr_a;
     const int tc = geo.tc, to = geo.to;
     const int ntile = geo.ntile;
     const int tid = threadIdx.x;
     const int cc = tid % tc;
     const int lo = (tid / tc) % to;
     const int t = tid / (tc * to);
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int ct = blk % ntile;  // tile index
     const int og = blk / ntile;  // group of `to` other-index lines
     const int o = og * to + lo;
@@ -551,19 +561,26 @@ __global__ void __launch_bounds__(256) ypass_kernel(YArgs ya, Geo geo, const flo
 // packed as one complex line.  Packed-column arrays are read and written in
 // whole tile blocks of RB*TC contiguous elements.
 template <int L, int P, int NG, int MODE>
-__global__ void __launch_bounds__(256) xrow_kernel(const DevPlan* __restrict__ plan, Bufs bufs, Geo geo,
+__global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ members,
+                                                    const DevPlan* __restrict__ plan_a, Bufs bufs_a, Geo geo,
                                                     const float2* __restrict__ tw_g) {
     constexpr int T = L / P;
     constexpr int NC = L / 2;  // packed columns
     extern __shared__ float2 smem[];
-    const DevPlan& p = *plan;
+    constexpr bool TAB = MODE == MODE_STEP;  // as in the update kernel
+    const int nb = gridDim.x;
+    const int lin = xcd_block(blockIdx.y * nb + blockIdx.x, nb * gridDim.y);
+    const int mi = lin / nb;
+    const Member* mem = members + mi;
+    const DevPlan& p = TAB ? *mem->plan : *plan_a;
+    const Bufs& bufs = TAB ? mem->bufs : bufs_a;
     const int tc = geo.tc, rb = geo.rb;
     const int ntile = NC / tc;
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
     const int pr = tid / T;  // pair within the block
     const int t = tid % T;
-    const int r0 = xcd_block(blockIdx.x, gridDim.x) * rb;  // first row; row index = z*Ny + y
+    const int r0 = (lin - mi * nb) * rb;  // first row; row index = z*Ny + y
     const int ny = p.n[1];
     const int zr = r0 / ny;          // z of the block (0 in 2D)
     const int y0 = r0 - zr * ny;     // first y of the block
@@ -697,6 +714,11 @@ __global__ void advance_kernel(uint64_t* step_ctr, int64_t k) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *step_ctr += static_cast<uint64_t>(k);
 }
 
+__global__ void advance_many_kernel(uint64_t* const* __restrict__ ctrs, int n, int64_t k) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) *ctrs[i] += static_cast<uint64_t>(k);
+}
+
 __global__ void init_uniform_kernel(float* __restrict__ out, int64_t n, uint32_t field, uint32_t key0,
                                     uint32_t key1, double lo, double hi) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -809,23 +831,25 @@ template <int L, int P, int NF, int DIM>
 static hipError_t launch_update_d(int mode, const LaunchArgs& a) {
     const int threads = a.geo.tc * a.geo.to * (L / P);
     const size_t lds = update_lds_bytes(L, NF, a.geo.tc, a.geo.to);
-    dim3 grid(a.geo.nublk), block(threads);
+    const bool tab = mode == MODE_STEP || mode == MODE_PROLOGUE;
+    if (tab && (!a.members || a.nmem < 1)) return hipErrorInvalidValue;
+    dim3 grid(a.geo.nublk, tab ? a.nmem : 1), block(threads);
     switch (mode) {
         case MODE_STEP:
-            hipLaunchKernelGGL((update_kernel<L, P, NF, MODE_STEP, DIM>), grid, block, lds, a.stream, a.plan,
-                               a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
+            hipLaunchKernelGGL((update_kernel<L, P, NF, MODE_STEP, DIM>), grid, block, lds, a.stream, a.members,
+                               a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
             break;
         case MODE_PROLOGUE:
-            hipLaunchKernelGGL((update_kernel<L, P, NF, MODE_PROLOGUE, DIM>), grid, block, lds, a.stream, a.plan,
-                               a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
+            hipLaunchKernelGGL((update_kernel<L, P, NF, MODE_PROLOGUE, DIM>), grid, block, lds, a.stream,
+                               a.members, a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
             break;
         case MODE_FWD_STORE:
-            hipLaunchKernelGGL((update_kernel<L, P, 1, MODE_FWD_STORE, DIM>), grid, block, lds, a.stream, a.plan,
-                               a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
+            hipLaunchKernelGGL((update_kernel<L, P, 1, MODE_FWD_STORE, DIM>), grid, block, lds, a.stream,
+                               a.members, a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
             break;
         case MODE_INV_OUT:
-            hipLaunchKernelGGL((update_kernel<L, P, 1, MODE_INV_OUT, DIM>), grid, block, lds, a.stream, a.plan,
-                               a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
+            hipLaunchKernelGGL((update_kernel<L, P, 1, MODE_INV_OUT, DIM>), grid, block, lds, a.stream, a.members,
+                               a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
             break;
         default:
             return hipErrorInvalidValue;
@@ -842,19 +866,21 @@ template <int L, int P, int NG>
 static hipError_t launch_xrow_t(int mode, const LaunchArgs& a) {
     const int threads = (a.geo.rb / 2) * (L / P);
     const size_t lds = xrow_lds_bytes(L, a.geo.rb);
-    dim3 grid(a.geo.nrowblk), block(threads);
+    const bool tab = mode == MODE_STEP;
+    if (tab && (!a.members || a.nmem < 1)) return hipErrorInvalidValue;
+    dim3 grid(a.geo.nrowblk, tab ? a.nmem : 1), block(threads);
     switch (mode) {
         case MODE_STEP:
-            hipLaunchKernelGGL((xrow_kernel<L, P, NG, MODE_STEP>), grid, block, lds, a.stream, a.plan, a.bufs,
-                               a.geo, a.tw_x);
+            hipLaunchKernelGGL((xrow_kernel<L, P, NG, MODE_STEP>), grid, block, lds, a.stream, a.members, a.plan,
+                               a.bufs, a.geo, a.tw_x);
             break;
         case MODE_R2C_IN:
-            hipLaunchKernelGGL((xrow_kernel<L, P, 1, MODE_R2C_IN>), grid, block, lds, a.stream, a.plan, a.bufs,
-                               a.geo, a.tw_x);
+            hipLaunchKernelGGL((xrow_kernel<L, P, 1, MODE_R2C_IN>), grid, block, lds, a.stream, a.members, a.plan,
+                               a.bufs, a.geo, a.tw_x);
             break;
         case MODE_C2R_OUT:
-            hipLaunchKernelGGL((xrow_kernel<L, P, 1, MODE_C2R_OUT>), grid, block, lds, a.stream, a.plan, a.bufs,
-                               a.geo, a.tw_x);
+            hipLaunchKernelGGL((xrow_kernel<L, P, 1, MODE_C2R_OUT>), grid, block, lds, a.stream, a.members, a.plan,
+                               a.bufs, a.geo, a.tw_x);
             break;
         default:
             return hipErrorInvalidValue;
@@ -1000,6 +1026,12 @@ hipError_t launch_xrow(int mode, int L, int ng, const LaunchArgs& a) {
 
 hipError_t launch_advance(hipStream_t s, uint64_t* step_ctr, int64_t k) {
     hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, step_ctr, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_many(hipStream_t s, uint64_t* const* ctrs, int n, int64_t k) {
+    if (n < 1) return hipSuccess;
+    hipLaunchKernelGGL(advance_many_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ctrs, n, k);
     return hipGetLastError();
 }
 

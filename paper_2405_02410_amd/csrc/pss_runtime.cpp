@@ -159,12 +159,36 @@ struct pss_ctx {
     float* d_real = nullptr;
     double* d_shell_sum = nullptr;
     unsigned long long* d_shell_cnt = nullptr;
+    // one-entry member tables of the step kernels (update kernel, x kernel)
+    pss::Member* d_member_u = nullptr;
+    pss::Member* d_member_x = nullptr;
+    int batches = 0;  // live batches holding this context
     std::map<int64_t, hipGraphExec_t> graphs;
     std::map<std::string, int64_t> tune;  // launch-geometry overrides
     int64_t steps_taken = 0;
 
     int64_t sites() const { return static_cast<int64_t>(n[0]) * n[1] * n[2]; }
     int64_t packed() const { return sites() / 2; }  // complex elements per spectral array
+};
+
+// A set of 2D lattices stepped together.  Lattices with the same sizes,
+// field / factor / channel counts and launch geometry form a class; each
+// class runs as one update launch and one x launch per step, with the
+// lattice picked by blockIdx.y from a device table of its plan, buffers and
+// step counter.
+struct pss_batch {
+    struct Class {
+        std::vector<int> idx;          // members of the class
+        pss_ctx* rep = nullptr;        // first member: geometry and twiddles
+        pss::Member* d_u = nullptr;    // member tables of the update and x kernels
+        pss::Member* d_x = nullptr;
+    };
+    std::vector<pss_ctx*> mem;
+    std::vector<Class> cls;
+    uint64_t** d_ctrs = nullptr;       // step counter of every member
+    hipStream_t stream = nullptr;      // the first member's stream
+    hipEvent_t ev = nullptr;
+    std::map<int64_t, hipGraphExec_t> graphs;
 };
 
 namespace {
@@ -511,6 +535,8 @@ void free_device(pss_ctx* c) {
     rel(c->d_real);
     rel(c->d_shell_sum);
     rel(c->d_shell_cnt);
+    rel(c->d_member_u);
+    rel(c->d_member_x);
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
     c->stream = nullptr;
     c->own_stream = false;
@@ -526,6 +552,8 @@ pss::LaunchArgs args(pss_ctx* c, int step_off = 0) {
     for (size_t g = 0; g < c->d_v.size(); ++g) a.bufs.V[g] = c->d_v[g];
     a.geo = c->geo;
     a.step_ctr = c->d_step;
+    a.members = c->d_member_u;
+    a.nmem = 1;
     a.step_off = step_off;
     a.tw_u = c->d_tw_u;
     a.tw_x = c->d_tw_x;
@@ -538,7 +566,18 @@ pss::LaunchArgs args(pss_ctx* c, int step_off = 0) {
 pss::LaunchArgs xargs(pss_ctx* c) {
     pss::LaunchArgs a = args(c);
     for (size_t k = 0; k < c->d_chan_x.size(); ++k) a.bufs.N[k] = c->d_chan_x[k];
+    a.members = c->d_member_x;
     return a;
+}
+
+// member-table entries of the update kernel and the x kernel of a context
+pss::Member member_u(pss_ctx* c) {
+    const pss::LaunchArgs a = args(c);
+    return pss::Member{c->d_plan, a.bufs, c->d_step};
+}
+pss::Member member_x(pss_ctx* c) {
+    const pss::LaunchArgs a = xargs(c);
+    return pss::Member{c->d_plan, a.bufs, c->d_step};
 }
 
 hipError_t y_inverse_factors(pss_ctx* c) {
@@ -619,6 +658,11 @@ pss_status materialize(pss_ctx* c) {
     HIP_TRY(hipMalloc(&c->d_tw_y, sizeof(float2) * twy.size()));
     HIP_TRY(hipMemcpy(c->d_tw_y, twy.data(), sizeof(float2) * twy.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->d_plan, &c->plan, sizeof(pss::DevPlan), hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&c->d_member_u, sizeof(pss::Member)));
+    HIP_TRY(hipMalloc(&c->d_member_x, sizeof(pss::Member)));
+    const pss::Member mu = member_u(c), mx = member_x(c);
+    HIP_TRY(hipMemcpy(c->d_member_u, &mu, sizeof(mu), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->d_member_x, &mx, sizeof(mx), hipMemcpyHostToDevice));
     HIP_TRY(hipDeviceSynchronize());
     c->planned = true;
     c->dirty = true;
@@ -724,6 +768,72 @@ pss_status graph_for(pss_ctx* c, int64_t k, hipGraphExec_t* out) {
 }
 
 constexpr int64_t kGraphSteps = 50;
+
+bool same_class(const pss_ctx* a, const pss_ctx* b) {
+    return a->n[0] == b->n[0] && a->n[1] == b->n[1] && a->fields.size() == b->fields.size() &&
+           a->plan.ng == b->plan.ng && a->plan.nch == b->plan.nch &&
+           std::memcmp(&a->geo, &b->geo, sizeof(pss::Geo)) == 0;
+}
+
+void free_batch(pss_batch* b) {
+    for (auto& kv : b->graphs) hipGraphExecDestroy(kv.second);
+    b->graphs.clear();
+    for (auto& cl : b->cls) {
+        if (cl.d_u) hipFree(cl.d_u);
+        if (cl.d_x) hipFree(cl.d_x);
+        cl.d_u = cl.d_x = nullptr;
+    }
+    if (b->d_ctrs) hipFree(b->d_ctrs);
+    b->d_ctrs = nullptr;
+    if (b->ev) hipEventDestroy(b->ev);
+    b->ev = nullptr;
+}
+
+pss_status batch_enqueue(pss_batch* b, int64_t k) {
+    for (int64_t i = 0; i < k; ++i) {
+        for (auto& cl : b->cls) {
+            pss_ctx* r = cl.rep;
+            pss::LaunchArgs a = args(r, static_cast<int>(i));
+            a.stream = b->stream;
+            a.members = cl.d_u;
+            a.nmem = static_cast<int>(cl.idx.size());
+            HIP_TRY(pss::launch_update(pss::MODE_STEP, r->lu, static_cast<int>(r->fields.size()), a));
+            if (r->plan.nch > 0) {
+                pss::LaunchArgs ax = xargs(r);
+                ax.stream = b->stream;
+                ax.members = cl.d_x;
+                ax.nmem = a.nmem;
+                HIP_TRY(pss::launch_xrow(pss::MODE_STEP, r->n[0], r->plan.ng, ax));
+            }
+        }
+    }
+    HIP_TRY(pss::launch_advance_many(b->stream, b->d_ctrs, static_cast<int>(b->mem.size()), k));
+    return PSS_OK;
+}
+
+pss_status batch_graph_for(pss_batch* b, int64_t k, hipGraphExec_t* out) {
+    auto it = b->graphs.find(k);
+    if (it != b->graphs.end()) {
+        *out = it->second;
+        return PSS_OK;
+    }
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    pss_status st = batch_enqueue(b, k);
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (st) {
+        if (g) hipGraphDestroy(g);
+        return st;
+    }
+    HIP_TRY(e);
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    HIP_TRY(e);
+    b->graphs[k] = ex;
+    *out = ex;
+    return PSS_OK;
+}
 
 // unpack the state of one field (packed columns, slot form on packed lines)
 // into the canonical half spectrum
@@ -842,6 +952,7 @@ pss_status pss_lattice_create(pss_ctx** out, int32_t ndim, const int64_t n[3], c
 
 pss_status pss_lattice_destroy(pss_ctx* c) {
     if (!c) return PSS_OK;
+    if (c->batches > 0) return fail(PSS_E_STATE, "lattice is held by %d batch(es); destroy them first", c->batches);
     free_device(c);
     delete c;
     return PSS_OK;
@@ -1264,6 +1375,165 @@ pss_status pss_time_kernel(pss_ctx* c, int32_t which, int32_t reps, double* ms, 
     c->dirty = true;  // the channel arrays no longer match the state
     static const char* names[4] = {"update_kernel", "xrow_kernel", "ypass_kernel(inverse)", "ypass_kernel(forward)"};
     if (name) *name = names[which];
+    return PSS_OK;
+}
+
+pss_status pss_batch_create(pss_batch** out, pss_ctx* const* lattices, int32_t n, const uint64_t* seeds) {
+    if (!out) return fail(PSS_E_INVAL, "null output");
+    *out = nullptr;
+    if (!lattices || n < 1) return fail(PSS_E_INVAL, "a batch needs at least one lattice");
+    for (int32_t i = 0; i < n; ++i) {
+        if (!lattices[i]) return fail(PSS_E_INVAL, "lattice %d is null", i);
+        if (lattices[i]->ndim != 2) return fail(PSS_E_UNSUPPORTED, "lattice %d: batches hold 2D lattices only", i);
+        for (int32_t j = 0; j < i; ++j)
+            if (lattices[j] == lattices[i]) return fail(PSS_E_INVAL, "lattice %d appears twice", i);
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        if (seeds)
+            if (pss_status s = pss_seed_set(lattices[i], seeds[i])) return s;
+        if (pss_status s = materialize(lattices[i])) return s;
+    }
+    auto* b = new pss_batch();
+    b->mem.assign(lattices, lattices + n);
+    for (int32_t i = 0; i < n; ++i) {
+        auto it = std::find_if(b->cls.begin(), b->cls.end(),
+                               [&](const pss_batch::Class& cl) { return same_class(cl.rep, lattices[i]); });
+        if (it == b->cls.end()) {
+            b->cls.emplace_back();
+            b->cls.back().rep = lattices[i];
+            it = b->cls.end() - 1;
+        }
+        it->idx.push_back(i);
+    }
+    auto bail = [&](pss_status s) {
+        free_batch(b);
+        delete b;
+        return s;
+    };
+    std::vector<uint64_t*> ctrs;
+    for (pss_ctx* c : b->mem) ctrs.push_back(c->d_step);
+    hipError_t e = hipMalloc(&b->d_ctrs, sizeof(uint64_t*) * ctrs.size());
+    if (e == hipSuccess) e = hipMemcpy(b->d_ctrs, ctrs.data(), sizeof(uint64_t*) * ctrs.size(), hipMemcpyHostToDevice);
+    for (auto& cl : b->cls) {
+        std::vector<pss::Member> tu, tx;
+        for (int i : cl.idx) {
+            tu.push_back(member_u(b->mem[i]));
+            tx.push_back(member_x(b->mem[i]));
+        }
+        const size_t bytes = sizeof(pss::Member) * tu.size();
+        if (e == hipSuccess) e = hipMalloc(&cl.d_u, bytes);
+        if (e == hipSuccess) e = hipMalloc(&cl.d_x, bytes);
+        if (e == hipSuccess) e = hipMemcpy(cl.d_u, tu.data(), bytes, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(cl.d_x, tx.data(), bytes, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
+    if (e != hipSuccess)
+        return bail(fail(e == hipErrorOutOfMemory ? PSS_E_NOMEM : PSS_E_HIP, "batch set-up: %s", hipGetErrorString(e)));
+    b->stream = b->mem[0]->stream;
+    for (pss_ctx* c : b->mem) ++c->batches;
+    *out = b;
+    return PSS_OK;
+}
+
+pss_status pss_batch_destroy(pss_batch* b) {
+    if (!b) return PSS_OK;
+    if (b->stream) hipStreamSynchronize(b->stream);
+    for (pss_ctx* c : b->mem) --c->batches;
+    free_batch(b);
+    delete b;
+    return PSS_OK;
+}
+
+pss_status pss_batch_step(pss_batch* b, int64_t nsteps) {
+    if (!b) return fail(PSS_E_INVAL, "null batch");
+    if (nsteps < 0) return fail(PSS_E_INVAL, "negative step count");
+    if (nsteps == 0) return PSS_OK;
+    // channel arrays of every member must match its state; then order the
+    // batch stream after every member's stream
+    for (pss_ctx* c : b->mem) {
+        if (c->dirty)
+            if (pss_status s = prologue(c)) return s;
+        if (c->stream != b->stream) {
+            HIP_TRY(hipEventRecord(b->ev, c->stream));
+            HIP_TRY(hipStreamWaitEvent(b->stream, b->ev, 0));
+        }
+    }
+    int64_t left = nsteps;
+    while (left > 0) {
+        const int64_t k = std::min(left, kGraphSteps);
+        hipGraphExec_t ex = nullptr;
+        if (pss_status s = batch_graph_for(b, k, &ex)) return s;
+        HIP_TRY(hipGraphLaunch(ex, b->stream));
+        left -= k;
+    }
+    // later work on any member's stream comes after the batch
+    HIP_TRY(hipEventRecord(b->ev, b->stream));
+    for (pss_ctx* c : b->mem) {
+        if (c->stream != b->stream) HIP_TRY(hipStreamWaitEvent(c->stream, b->ev, 0));
+        c->steps_taken += nsteps;
+    }
+    return PSS_OK;
+}
+
+pss_status pss_batch_sync(pss_batch* b) {
+    if (!b) return fail(PSS_E_INVAL, "null batch");
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return PSS_OK;
+}
+
+pss_status pss_batch_info(pss_batch* b, int32_t* n_classes, int32_t* class_of) {
+    if (!b) return fail(PSS_E_INVAL, "null batch");
+    if (n_classes) *n_classes = static_cast<int32_t>(b->cls.size());
+    if (class_of)
+        for (size_t k = 0; k < b->cls.size(); ++k)
+            for (int i : b->cls[k].idx) class_of[i] = static_cast<int32_t>(k);
+    return PSS_OK;
+}
+
+pss_status pss_batch_time_kernel(pss_batch* b, int32_t cls, int32_t which, int32_t reps, double* ms,
+                                 double* bytes) {
+    if (!b) return fail(PSS_E_INVAL, "null batch");
+    if (cls < 0 || cls >= static_cast<int32_t>(b->cls.size())) return fail(PSS_E_INVAL, "no class %d", cls);
+    if ((which != 0 && which != 1) || reps < 1 || !ms) return fail(PSS_E_INVAL, "bad kernel timing request");
+    const auto& cl = b->cls[cls];
+    pss_ctx* r = cl.rep;
+    if (which == 1 && r->plan.nch == 0) return fail(PSS_E_INVAL, "class %d has no x kernel", cls);
+    for (int i : cl.idx) {
+        pss_ctx* c = b->mem[i];
+        if (c->dirty)
+            if (pss_status s = prologue(c)) return s;
+        if (c->stream != b->stream) {
+            HIP_TRY(hipEventRecord(b->ev, c->stream));
+            HIP_TRY(hipStreamWaitEvent(b->stream, b->ev, 0));
+        }
+    }
+    pss::LaunchArgs a = which == 0 ? args(r) : xargs(r);
+    a.stream = b->stream;
+    a.members = which == 0 ? cl.d_u : cl.d_x;
+    a.nmem = static_cast<int>(cl.idx.size());
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, b->stream));
+    for (int k = 0; k < reps; ++k) {
+        if (which == 0)
+            HIP_TRY(pss::launch_update(pss::MODE_STEP, r->lu, static_cast<int>(r->fields.size()), a));
+        else
+            HIP_TRY(pss::launch_xrow(pss::MODE_STEP, r->n[0], r->plan.ng, a));
+    }
+    HIP_TRY(hipEventRecord(e1, b->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float t = 0;
+    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *ms = static_cast<double>(t) / reps;
+    if (bytes) {
+        double one = 0;
+        if (pss_status s = pss_kernel_bytes(r, which, &one)) return s;
+        *bytes = one * static_cast<double>(cl.idx.size());
+    }
+    for (int i : cl.idx) b->mem[i]->dirty = true;  // repeated launches leave the channels stale
     return PSS_OK;
 }
 

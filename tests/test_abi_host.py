@@ -123,3 +123,24 @@ def test_step_zero_is_a_noop_without_device():
     pss.model_b(lat)
     lat.step(0)
     assert lat.step_index == 0
+
+
+def test_batch_arguments_are_checked_before_any_device_work():
+    a = _lat()
+    pss.model_b(a)
+    with pytest.raises(PssError) as e:
+        pss.Batch([])
+    assert e.value.name == "PSS_E_INVAL"
+    with pytest.raises(PssError) as e:
+        pss.Batch([a, a])
+    assert e.value.name == "PSS_E_INVAL"
+    c = pss.Lattice((16, 16, 16), dt=0.01)
+    pss.model_b(c)
+    with pytest.raises(PssError) as e:
+        pss.Batch([a, c])
+    assert e.value.name == "PSS_E_UNSUPPORTED"
+    lib = pss.lib()
+    assert lib.pss_batch_step(None, 1) == -1
+    assert lib.pss_batch_sync(None) == -1
+    assert lib.pss_batch_info(None, None, None) == -1
+    assert lib.pss_batch_destroy(None) == 0

@@ -1,0 +1,161 @@
+"""GPU parity of batched stepping (pss_batch_*): every member of a batch must
+end bit for bit where the same lattice stepped alone ends, and a member must
+stay on the FP64 oracle."""
+
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+from tests import inputs
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs an MI355X")]
+
+import paper_2405_02410_amd as pss  # noqa: E402
+from paper_2405_02410_amd import Mono, PssError  # noqa: E402
+from oracle import model as om  # noqa: E402
+from oracle.spectral import Lattice as OLattice  # noqa: E402
+
+
+def _model_b(n, seed, D=0.01, dt=0.01, a=-1.0):
+    lat = pss.Lattice(n, dt=dt, seed=seed)
+    f, _ = pss.model_b(lat, a=a, D=D)
+    lat.init_uniform(f, -0.1, 0.1)
+    return lat
+
+
+def _two_field(n, seed):
+    lat = pss.Lattice(n, dt=0.005, seed=seed)
+    phi = lat.field("phi")
+    psi = lat.field("psi")
+    lat.term(phi, [Mono(1.0, q2=1), Mono(-1.0, q2=2)], [(phi, 1)], implicit=True)
+    lat.term(phi, [Mono(-1.0, q2=1)], [(phi, 3)])
+    lat.term(phi, [Mono(-0.15, q2=1)], [(phi, 1), (psi, 2)])
+    lat.term(psi, [Mono(0.5), Mono(-1.0, q2=1)], [(psi, 1)], implicit=True)
+    lat.term(psi, [Mono(-1.0)], [(psi, 3)])
+    lat.term(psi, [Mono(-0.3)], [(phi, 1), (psi, 1)])
+    lat.noise(phi, [Mono(0.005, q2=1)])
+    lat.noise(psi, [Mono(0.005)])
+    lat.init_uniform(phi)
+    lat.init_uniform(psi)
+    return lat
+
+
+# members of uneven size and model; the builder of each is called twice
+MEMBERS = [
+    lambda: _model_b((64, 64), 1),
+    lambda: _model_b((64, 64), 2),
+    lambda: _model_b((64, 64), 2**40 + 7),
+    lambda: _model_b((64, 64), 4, D=0.0),      # noiseless, same class
+    lambda: _model_b((128, 128), 10),
+    lambda: _model_b((128, 128), 11, a=-0.5),  # other coefficients, same class
+    lambda: _model_b((32, 128), 12),
+    lambda: _model_b((256, 16), 13),
+    lambda: _two_field((64, 64), 14),
+]
+
+
+def _fields(lat):
+    return range(len(lat.names))
+
+
+def test_batch_is_bitwise_the_single_lattice_path():
+    mem = [b() for b in MEMBERS]
+    twins = [b() for b in MEMBERS]
+    batch = pss.Batch(mem)
+    nc, of = batch.classes()
+    assert nc == 5 and of[:4] == [0, 0, 0, 0] and of[4] == of[5] != of[0]
+    batch.step(7)
+    batch.step(60)  # crosses a graph chunk
+    batch.sync()
+    for lat, tw in zip(mem, twins):
+        tw.step(67)
+        assert lat.step_index == 67
+        for f in _fields(lat):
+            assert np.array_equal(lat.spectrum(f), tw.spectrum(f)), (lat.n, f)
+    batch.close()
+
+
+def test_batch_member_on_the_oracle():
+    p = inputs.MODEL_B
+    mem = [_model_b((64, 64), s) for s in (3, 5, 8)]
+    batch = pss.Batch(mem)
+    mass0 = mem[1].mass(0)
+    batch.step(100)
+    m = om.model_b(OLattice(64, 64, 1), p["dt"], a=p["a"], b=p["b"], k=p["k"], D=0.01, seed=5)
+    m.init_uniform(0, -0.1, 0.1)
+    m.step(100)
+    phi = mem[1].download(0)
+    assert np.max(np.abs(phi - m.real(0)[0])) <= 1e-4
+    assert abs(mem[1].mass(0) - mass0) <= 1e-6 * np.sum(np.abs(phi))
+    batch.close()
+
+
+def test_batch_seeds_and_interleaving_with_own_steps():
+    mem = [_model_b((64, 64), 0) for _ in range(3)]  # same initial field, noise keys set by the batch
+    twins = [_model_b((64, 64), 0) for _ in range(3)]
+    for tw, s in zip(twins, (21, 22, 23)):
+        tw.seed(s)
+    batch = pss.Batch(mem, seeds=[21, 22, 23])
+    mem[0].step(5)          # alone first
+    batch.step(10)
+    mem[2].set_coef(1, 0, -2.0)   # coefficient change between batch steps
+    twins[2].step(10)
+    twins[2].set_coef(1, 0, -2.0)
+    batch.step(6)
+    mem[1].step(3)          # alone after
+    twins[0].step(16 + 5)
+    twins[1].step(16 + 3)
+    twins[2].step(6)
+    for i, (lat, tw) in enumerate(zip(mem, twins)):
+        assert lat.step_index == tw.step_index, i
+        assert np.array_equal(lat.spectrum(0), tw.spectrum(0)), i
+    batch.close()
+
+
+def test_batch_restores_after_state_load():
+    a = _model_b((128, 64), 31)
+    b = _model_b((128, 64), 32)
+    batch = pss.Batch([a, b])
+    batch.step(20)
+    blob = a.save()
+    ref = _model_b((128, 64), 31)
+    ref.step(20)
+    batch.step(5)
+    a.load(blob)             # back to step 20: channels rebuilt before the next batch step
+    batch.step(5)
+    ref.step(5)
+    assert np.array_equal(a.spectrum(0), ref.spectrum(0))
+    batch.close()
+
+
+def test_member_outlives_its_batch():
+    a = _model_b((64, 64), 1)
+    batch = pss.Batch([a])
+    batch.step(2)
+    with pytest.raises(PssError) as e:
+        a.close()
+    assert e.value.name == "PSS_E_STATE"
+    batch.close()
+    a.step(1)
+    a.close()
+
+
+def test_batch_kernel_timing_and_bytes():
+    mem = [_model_b((128, 128), s) for s in range(4)]
+    single = _model_b((128, 128), 9)
+    batch = pss.Batch(mem)
+    blobs = [lat.save() for lat in mem]  # timing launches overwrite the state
+    ms, nbytes = batch.time_kernel(0, pss.KERNEL_UPDATE, 20)
+    assert ms > 0 and nbytes == 4 * single.kernel_bytes(pss.KERNEL_UPDATE)
+    ms, nbytes = batch.time_kernel(0, pss.KERNEL_X, 20)
+    assert ms > 0 and nbytes == 4 * single.kernel_bytes(pss.KERNEL_X)
+    # restore the states; the next batch step must rebuild the stale channels
+    twins = [_model_b((128, 128), s) for s in range(4)]
+    for lat, blob in zip(mem, blobs):
+        lat.load(blob)
+    batch.step(3)
+    for lat, tw in zip(mem, twins):
+        tw.step(3)
+        assert np.array_equal(lat.spectrum(0), tw.spectrum(0))
+    batch.close()
