@@ -40,7 +40,7 @@
  * - Structural calls (declare, term_add, noise_set, dealias_set) are only
  *   accepted before the device plan is built (first upload, init or step);
  *   afterwards they return PSS_E_STATE.  Coefficients can still be changed
- *   with pss_term_set_coef.
+ *   with pss_term_set_coef, and pss_noise_set with the monomials unchanged.
  * - A context is not thread-safe: one thread at a time.
  */
 #ifndef PSS_H
@@ -134,7 +134,10 @@ pss_status pss_term_set_coef(pss_ctx *ctx, int32_t term_id, int32_t mono, double
 /* Add noise to a field (Sec. "Adding noise"): D(q) is a sum of monomials in
  * q^2 and 1/|q| only (no i q_i), real and >= 0 on every mode (checked when the
  * plan is built; PSS_E_INVAL otherwise).  The Fourier noise amplitude is
- * sigma(q) = sqrt(2 D(q) dt / dV) on unit white noise. */
+ * sigma(q) = sqrt(2 D(q) dt / dV) on unit white noise.  After the plan is
+ * built, a call that repeats the field's monomials with new coefficients is a
+ * coefficient change (takes effect at the next step); any other call then
+ * returns PSS_E_STATE. */
 pss_status pss_noise_set(pss_ctx *ctx, int32_t field, const pss_qmono *D_of_q,
                          int32_t n_mono);
 
@@ -245,6 +248,34 @@ pss_status pss_kernel_bytes(pss_ctx *ctx, int32_t which, double *bytes);
 
 /* Number of kernels in one step (2 in 2D, 4 in 3D). */
 pss_status pss_kernels_per_step(pss_ctx *ctx, int32_t *count);
+
+/* ------------------------------------------------------------------ adjoint
+ * Reverse-mode gradient of a structure-factor loss through a 2D Model B
+ * trajectory (Sec. "Example": the model; eq:timeupdate: the step that is
+ * differentiated; the paper itself has no adjoint).  The lattice must hold
+ * exactly the Model B terms: one field, an implicit operator with q^2 and q^4
+ * monomials -(a q^2 + k q^4), one explicit term -b q^2 F[phi^3], and either
+ * no noise or D(q) = D q^2 (anything else: PSS_E_UNSUPPORTED).
+ *
+ * From the current state phi_0 at step n0 the call runs nsteps forward steps
+ * (noise keyed by steps n0 .. n0+nsteps-1, as pss_step would), keeping a
+ * checkpoint of the state every ckpt_every steps.  It evaluates
+ *   L = sum_{j=1}^{n_shells} (S_j - S_target[j-1])^2,
+ * S_j the shell averages of pss_structure_factor at the final step
+ * (n_shells = min(Nx, Ny)/2 - 1), and sweeps back through the steps,
+ * recomputing each segment from its checkpoint, with the adjoint recursion
+ *   r = g_{n+1} / A,   g_n = r + b m F[3 u_n^2 N F^-1[-dt q^2 r]] / N,
+ *   u_n = F^-1[m phi_n],   A = 1 + dt q^2 (a + k q^2),
+ * where m is the de-aliasing mask and the noise of each step is regenerated
+ * from its Philox counter (it does not depend on the coefficients other than
+ * through D).  Outputs: *loss; grad[4] = dL/d(a, b, k, D) (FP64 sums of FP32
+ * terms; dL/dD = 0 when D = 0); grad_phi0 (may be NULL; else Nx*Ny floats,
+ * host or device memory per on_device) = dL/dphi_0(x) for the real initial
+ * field.  The lattice is left at step n0 + nsteps with the forward final
+ * state.  Device workspace: (ceil(nsteps/ckpt_every) + min(ckpt_every,
+ * nsteps) + 8) arrays of Nx*Ny*4 bytes, allocated for the call. */
+pss_status pss_adjoint_model_b(pss_ctx *ctx, int64_t nsteps, int32_t ckpt_every, const double *S_target,
+                               int32_t n_shells, double *loss, double *grad, float *grad_phi0, int32_t on_device);
 
 /* ------------------------------------------------------------------ batches
  * Many independent 2D lattices advanced together.  The paper finds small

@@ -84,6 +84,9 @@ _SIGS = {
     "pss_kernels_per_step": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)],
     "pss_tuning_set": [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64],
     "pss_tuning_get": [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)],
+    "pss_adjoint_model_b": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                            ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                            ctypes.c_void_p, ctypes.c_int32],
     "pss_batch_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
                          ctypes.POINTER(ctypes.c_uint64)],
     "pss_batch_destroy": [ctypes.c_void_p],
@@ -302,6 +305,20 @@ class Lattice:
         b = ctypes.c_double()
         _check(lib().pss_kernel_bytes(self._h, int(which), ctypes.byref(b)))
         return b.value
+
+    def adjoint_model_b(self, nsteps, S_target, ckpt_every=45, grad_phi0=True):
+        """(loss, dL/d(a, b, k, D), dL/dphi_0 or None) of the structure-factor
+        loss after nsteps Model B steps from the current state (pss_adjoint_model_b).
+        Leaves the lattice at the end of the forward run."""
+        S = np.ascontiguousarray(S_target, dtype=np.float64)
+        loss = ctypes.c_double()
+        grad = (ctypes.c_double * 4)()
+        out = np.empty(self.shape, dtype=np.float32) if grad_phi0 else None
+        _check(lib().pss_adjoint_model_b(self._h, int(nsteps), int(ckpt_every),
+                                         S.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(S.size),
+                                         ctypes.byref(loss), grad,
+                                         None if out is None else out.ctypes.data, 0))
+        return loss.value, np.array(list(grad)), out
 
     def kernels_per_step(self):
         v = ctypes.c_int32()

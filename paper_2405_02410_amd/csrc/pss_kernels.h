@@ -18,6 +18,9 @@ enum {
     MODE_C2R_OUT = 5,    // x kernel: packed columns `in` -> real rows `real_out`
     MODE_YINV = 6,       // y pass (3D): inverse transform, column-0 slots -> packed
     MODE_YFWD = 7,       // y pass (3D): forward transform, column-0 packed -> slots
+    MODE_ADJROW = 8,     // x kernel: adjoint row pass (Model B), see AdjArgs
+    MODE_ADJCOL = 9,     // adjoint column kernel: one reverse step
+    MODE_ADJFIN = 10,    // adjoint column kernel: g_0 from the last reverse step
 };
 
 // Device arrays used by a launch (all in the packed half-spectrum layout
@@ -30,7 +33,35 @@ struct Bufs {
     float2* out;
     const float* real_in;
     float* real_out;
+    double* acc;  // adjoint row pass: FP64 accumulator of sum_x u^3 w
     int sel;
+};
+
+// Reverse step of 2D Model B (phi_{n+1} = (phi_n + dt M F[u_n^3] + eta_n) / A,
+// u_n = Re F^-1[m phi_n], M = -b q^2, A = 1 + dt q^2 (a + k q^2)), adjoint
+// column kernel.  All spectral arrays are packed, in the 2D state layout.
+//   g_{n+1} = first ? G : Rin + b m F_y[X] / N    (X: x-forward of 3 u^2 w, row pass)
+//   r_n = g_{n+1} / A                             -> Rout
+//   acc[0] -= <r, dt q^2 phi1>, acc[2] -= <r, dt q^4 phi1>, acc[3] += <r, eta_n>/(2D)
+//   W = F_y^-1[-dt q^2 r_n],  U = F_y^-1[m phi0]
+// The row pass (x kernel, MODE_ADJROW) forms w = N F^-1[-dt q^2 r_n] and
+// u_n in real space and adds <r, -dt q^2 F[u_n^3]> = sum_x u^3 w to acc[1].
+// with <x, y> = Re sum over all modes of conj(x) y.  MODE_ADJFIN stops after
+// g_{n+1} and stores it in Rout.
+struct AdjArgs {
+    const DevPlan* plan;  // forward plan: masks, noise operator, q scales, keys
+    const float2* G;
+    const float2* Rin;
+    const float2* X;
+    const float2* phi1;   // phi_{n+1}
+    const float2* phi0;   // phi_n
+    float2* Rout;
+    float2* W;
+    float2* U;
+    double* acc;          // [4]: dL/da, dL/db (row pass), dL/dk, dL/dD
+    float a, b, k, D;
+    uint32_t step;        // n: the noise counter of the forward step
+    int first;
 };
 
 struct Geo {
@@ -90,6 +121,12 @@ hipError_t launch_update(int mode, int L, int nf, const LaunchArgs& a);
 hipError_t launch_xrow(int mode, int L, int ng, const LaunchArgs& a);
 hipError_t launch_ypass(int mode, int L, const YArgs& ya, const LaunchArgs& a);
 hipError_t launch_advance(hipStream_t s, uint64_t* step_ctr, int64_t k);
+// adjoint column kernel (2D, one field) and its launch
+hipError_t launch_adjcol(int mode, int L, const AdjArgs& aa, const LaunchArgs& a);
+// terminal seed g = coef[shell(k)] * phi (2D packed state layout)
+hipError_t launch_adjseed(hipStream_t s, const float2* phi, float2* g, const float* coef, int nshell, int nx, int ny,
+                          int tc);
+
 // *ctrs[i] += k for i < n (the step counters of a batch)
 hipError_t launch_advance_many(hipStream_t s, uint64_t* const* ctrs, int n, int64_t k);
 hipError_t launch_init_uniform(hipStream_t s, float* out, int64_t n, uint32_t field, uint32_t key0, uint32_t key1,

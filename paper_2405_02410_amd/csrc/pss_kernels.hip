@@ -35,6 +35,25 @@ __device__ __forceinline__ const float2* stage_twiddles(float2* dst, const float
     return dst;
 }
 
+// FP64 atomic add of NV per-thread values into dst[0..NV): one atomic per
+// wave after a shuffle reduction when the block is whole waves, else one per
+// thread (tiny lattices)
+template <int NV>
+__device__ __forceinline__ void block_atomic_add(double (&v)[NV], double* dst) {
+    if ((blockDim.x & 63) == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o, 64);
+        if ((threadIdx.x & 63) == 0)
+#pragma unroll
+            for (int i = 0; i < NV; ++i) atomicAdd(dst + i, v[i]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) atomicAdd(dst + i, v[i]);
+    }
+}
+
 // ----------------------------------------------------------------- modes
 struct ModeQ {
     float q2;
@@ -474,6 +493,179 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
     }
 }
 
+// ------------------------------------------------------ adjoint column kernel
+// One reverse step of 2D Model B along y lines (AdjArgs).  Same block shape,
+// slot form and LDS layout as the 2D update kernel: TC column lines per
+// block, thread (cc, t) holds slots u = t + m*T.  Inner products over all
+// modes become sums over the stored slots with weight 2 (a mode and its
+// conjugate), and weight 1 for each real component of the pair slots.
+template <int L, int P, int MODE>
+__global__ void __launch_bounds__(256) adjcol_kernel(AdjArgs aa, Geo geo, const float2* __restrict__ tw_g) {
+    constexpr int T = L / P;
+    extern __shared__ float2 smem[];
+    const DevPlan& p = *aa.plan;
+    const int tc = geo.tc;
+    const int tid = threadIdx.x;
+    const int cc = tid % tc;
+    const int t = tid / tc;
+    const int ct = xcd_block(blockIdx.x, gridDim.x);
+    const int c = ct * tc + cc;
+    const int nx = p.n[0];
+    const int kn = -(nx >> 1);
+    const size_t base = static_cast<size_t>(ct) * L * tc + cc;
+    float2* line = smem + cc * lds_line(L);
+    float2* xbuf = smem + tc * lds_line(L);
+    const float2* tw = stage_twiddles<L>(xbuf + L, tw_g, tid, tc * T);
+    const bool blk_packed = ct == 0;
+    const bool packed = blk_packed && cc == 0;
+    const DevMask& mk = p.mask[0];
+
+    auto exchange = [&](float2 (&v)[P], bool forward) {  // as in the update kernel
+        if (!blk_packed) return;
+        if (packed) {
+#pragma unroll
+            for (int m = 0; m < P; ++m) xbuf[t + m * T] = v[m];
+        }
+        __syncthreads();
+        if (packed) {
+#pragma unroll
+            for (int m = 0; m < P; ++m) {
+                const int u = t + m * T;
+                const float2 b = xbuf[(L - u) & (L - 1)];
+                v[m] = forward ? to_slot<L>(u, v[m], b) : from_slot<L>(u, v[m], b);
+            }
+        }
+        __syncthreads();
+    };
+
+    // g_{n+1}
+    float2 g[P];
+    if (aa.first) {
+#pragma unroll
+        for (int m = 0; m < P; ++m) g[m] = aa.G[base + (t + m * T) * tc];
+    } else {
+        float2 v[P];
+#pragma unroll
+        for (int m = 0; m < P; ++m) v[m] = aa.X[base + (t + m * T) * tc];
+        fft_line<L, P, -1>(v, line, t, tw);
+        exchange(v, true);
+#pragma unroll
+        for (int m = 0; m < P; ++m) {
+            int kx, ky, kz;
+            bool pair;
+            slot_mode<2>(packed, c, 0, t + m * T, L, nx, kx, ky, kz, pair);
+            float2 y = cscale(v[m], p.inv_n * aa.b);
+            if (!pair) {
+                if (!mask_keep(mk, kx, ky, 0)) y = make_float2(0.f, 0.f);
+            } else {
+                if (!mask_keep(mk, 0, ky, 0)) y.x = 0.f;
+                if (!mask_keep(mk, kn, ky, 0)) y.y = 0.f;
+            }
+            g[m] = cadd(aa.Rin[base + (t + m * T) * tc], y);
+        }
+    }
+    if constexpr (MODE == MODE_ADJFIN) {
+#pragma unroll
+        for (int m = 0; m < P; ++m) aa.Rout[base + (t + m * T) * tc] = g[m];
+        return;
+    }
+
+    // r_n = g_{n+1} / A, the coefficient sums, -dt q^2 r_n and m phi_n
+    const float dt = p.dt;
+    const bool noisy = p.noisy[0] != 0;
+    double part[3] = {0.0, 0.0, 0.0};  // d/da, d/dk, <r, eta>
+    float2 wr[P], um[P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+        const int u = t + m * T;
+        const size_t e = base + u * tc;
+        int kx, ky, kz;
+        bool pair;
+        slot_mode<2>(packed, c, 0, u, L, nx, kx, ky, kz, pair);
+        const float2 f1 = aa.phi1[e], f0 = aa.phi0[e];
+        float2 r;
+        if (!pair) {
+            const ModeQ q = mode_q(p, kx, ky, 0);
+            r = cscale(g[m], 1.f / (1.f + dt * q.q2 * (aa.a + aa.k * q.q2)));
+            const double re1 = static_cast<double>(r.x) * f1.x + static_cast<double>(r.y) * f1.y;
+            part[0] -= 2.0 * dt * q.q2 * re1;
+            part[1] -= 2.0 * dt * static_cast<double>(q.q2) * q.q2 * re1;
+            if (noisy) {
+                uint32_t lin, lneg;
+                mode_lin(p, kx, ky, 0, lin, lneg);
+                const float2 eta = noise_mode(p, 0, aa.step, lin, lneg, q);
+                part[2] += 2.0 * (static_cast<double>(r.x) * eta.x + static_cast<double>(r.y) * eta.y);
+            }
+            wr[m] = cscale(r, -dt * q.q2);
+            um[m] = mask_keep(mk, kx, ky, 0) ? f0 : make_float2(0.f, 0.f);
+        } else {
+            // two real modes: re part kx = 0, im part kx = -Nx/2
+            const ModeQ q0 = mode_q(p, 0, ky, 0), qn = mode_q(p, kn, ky, 0);
+            r = make_float2(g[m].x / (1.f + dt * q0.q2 * (aa.a + aa.k * q0.q2)),
+                            g[m].y / (1.f + dt * qn.q2 * (aa.a + aa.k * qn.q2)));
+            const double e0 = static_cast<double>(r.x) * f1.x, en = static_cast<double>(r.y) * f1.y;
+            part[0] -= dt * (q0.q2 * e0 + qn.q2 * en);
+            part[1] -= dt * (static_cast<double>(q0.q2) * q0.q2 * e0 + static_cast<double>(qn.q2) * qn.q2 * en);
+            if (noisy) {
+                uint32_t lin, lneg;
+                mode_lin(p, 0, ky, 0, lin, lneg);
+                const float eta0 = noise_mode(p, 0, aa.step, lin, lneg, q0).x;
+                mode_lin(p, kn, ky, 0, lin, lneg);
+                const float etan = noise_mode(p, 0, aa.step, lin, lneg, qn).x;
+                part[2] += static_cast<double>(r.x) * eta0 + static_cast<double>(r.y) * etan;
+            }
+            wr[m] = make_float2(-dt * q0.q2 * r.x, -dt * qn.q2 * r.y);
+            um[m] = make_float2(mask_keep(mk, 0, ky, 0) ? f0.x : 0.f, mask_keep(mk, kn, ky, 0) ? f0.y : 0.f);
+        }
+        aa.Rout[e] = r;
+    }
+    exchange(wr, false);
+    fft_line<L, P, 1>(wr, line, t, tw);
+#pragma unroll
+    for (int m = 0; m < P; ++m) aa.W[base + (t + m * T) * tc] = wr[m];
+    exchange(um, false);
+    fft_line<L, P, 1>(um, line, t, tw);
+#pragma unroll
+    for (int m = 0; m < P; ++m) aa.U[base + (t + m * T) * tc] = um[m];
+    if (aa.D > 0.f) part[2] /= 2.0 * aa.D;
+    double out[4] = {part[0], 0.0, part[1], part[2]};
+    block_atomic_add(out, aa.acc);
+}
+
+#if defined(PSS_COMMON)
+// terminal seed of the adjoint: g(k) = coef[shell(k)] phi(k) on the 2D packed
+// state layout (slot form on column 0), shell(k) = rint(|k|)
+__global__ void adjseed_kernel(const float2* __restrict__ phi, float2* __restrict__ g, const float* __restrict__ coef,
+                               int nshell, int nx, int ny, int tc) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t total = static_cast<int64_t>(nx / 2) * ny;
+    if (e >= total) return;
+    const int cc = static_cast<int>(e % tc);
+    const int y = static_cast<int>((e / tc) % ny);
+    const int col = static_cast<int>(e / (static_cast<int64_t>(tc) * ny)) * tc + cc;
+    auto cf = [&](int kx, int ky) {
+        const int j = static_cast<int>(rintf(sqrtf(static_cast<float>(kx * kx + ky * ky))));
+        return (j >= 1 && j < nshell) ? coef[j] : 0.f;
+    };
+    const float2 v = phi[e];
+    float2 o;
+    if (col > 0) {
+        const float s = cf(col, y < ny / 2 ? y : y - ny);
+        o = make_float2(s * v.x, s * v.y);
+    } else if (y == 0 || y == ny / 2) {
+        const int w = y == 0 ? 0 : -(ny / 2);
+        o = make_float2(cf(0, w) * v.x, cf(-(nx / 2), w) * v.y);
+    } else if (y < ny / 2) {
+        const float s = cf(0, y);
+        o = make_float2(s * v.x, s * v.y);
+    } else {
+        const float s = cf(-(nx / 2), ny - y);
+        o = make_float2(s * v.x, s * v.y);
+    }
+    g[e] = o;
+}
+#endif  // PSS_COMMON
+
 // ----------------------------------------------------------------- y pass
 // 3D only: lines along y for fixed (c, z); block = TC columns x TZ values of
 // z.  Input [z][ctile][y][TC].  The inverse pass writes the same layout, the
@@ -665,6 +857,33 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
             dst[static_cast<size_t>(r0 + 2 * pr) * L + x] = v[m].x * p.inv_n;
             dst[static_cast<size_t>(r0 + 2 * pr + 1) * L + x] = v[m].y * p.inv_n;
         }
+        return;
+    }
+
+    if constexpr (MODE == MODE_ADJROW) {
+        // reverse step, real space: u = F^-1[m phi_n] (rows of V[0], kept
+        // columns only), w = N F^-1[-dt q^2 r] (rows of V[1], unnormalised),
+        // 3 u^2 w -> forward x transform into N[0] (the column kernel applies
+        // the factor b); and the FP64 sum of u^3 w, which is
+        // <r, -dt q^2 F[u^3]> = dL/db of the step, by Parseval
+        float2 u[P], w[P];
+        build_z(u, bufs.V[0], p.mask[0].ncol);
+        fft_line<L, P, 1>(u, line, t, tw);
+        build_z(w, bufs.V[1], p.mask[1].ncol);
+        fft_line<L, P, 1>(w, line, t, tw);
+        double part[1] = {0.0};
+#pragma unroll
+        for (int m = 0; m < P; ++m) {
+            const float ux = u[m].x * p.inv_n, uy = u[m].y * p.inv_n;
+            part[0] += static_cast<double>(ux) * ux * ux * w[m].x + static_cast<double>(uy) * uy * uy * w[m].y;
+            u[m] = make_float2(3.f * ux * ux * w[m].x, 3.f * uy * uy * w[m].y);
+        }
+        fft_line<L, P, -1>(u, line, t, tw);
+#pragma unroll
+        for (int m = 0; m < P; ++m) line[lds_pad(t + m * T)] = u[m];
+        __syncthreads();
+        store_rows(bufs.N[0]);
+        block_atomic_add(part, bufs.acc);
         return;
     }
 
@@ -882,6 +1101,13 @@ static hipError_t launch_xrow_t(int mode, const LaunchArgs& a) {
             hipLaunchKernelGGL((xrow_kernel<L, P, 1, MODE_C2R_OUT>), grid, block, lds, a.stream, a.members, a.plan,
                                a.bufs, a.geo, a.tw_x);
             break;
+        case MODE_ADJROW:
+            if constexpr (NG == 2) {
+                hipLaunchKernelGGL((xrow_kernel<L, P, 2, MODE_ADJROW>), grid, block, lds, a.stream, a.members,
+                                   a.plan, a.bufs, a.geo, a.tw_x);
+                break;
+            }
+            return hipErrorInvalidValue;
         default:
             return hipErrorInvalidValue;
     }
@@ -940,10 +1166,29 @@ hipError_t PSS_CAT(launch_ypass_L, PSS_LINE_LEN)(int mode, const YArgs& ya, cons
     });
 }
 
+hipError_t PSS_CAT(launch_adjcol_L, PSS_LINE_LEN)(int mode, const AdjArgs& aa, const LaunchArgs& a) {
+    constexpr int L = PSS_LINE_LEN;
+    return with_points<L, 16>(a.geo.pu, [&](auto PP) {
+        constexpr int P = decltype(PP)::value;
+        const int threads = a.geo.tc * (L / P);
+        const size_t lds = update_lds_bytes(L, 1, a.geo.tc, 1);
+        dim3 grid(a.geo.nublk), block(threads);
+        if (a.dim != 2 || a.geo.to != 1) return hipErrorInvalidValue;
+        if (mode == MODE_ADJCOL) {
+            hipLaunchKernelGGL((adjcol_kernel<L, P, MODE_ADJCOL>), grid, block, lds, a.stream, aa, a.geo, a.tw_u);
+        } else if (mode == MODE_ADJFIN) {
+            hipLaunchKernelGGL((adjcol_kernel<L, P, MODE_ADJFIN>), grid, block, lds, a.stream, aa, a.geo, a.tw_u);
+        } else {
+            return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    });
+}
+
 hipError_t PSS_CAT(launch_xrow_L, PSS_LINE_LEN)(int mode, int ng, const LaunchArgs& a) {
     constexpr int L = PSS_LINE_LEN;
     const int px = a.geo.px;
-    if (mode != MODE_STEP || ng <= 1)
+    if ((mode != MODE_STEP && mode != MODE_ADJROW) || ng <= 1)
         return with_points<L, 16>(px, [&](auto P) { return launch_xrow_t<L, decltype(P)::value, 1>(mode, a); });
     if (ng == 2)
         return with_points<L, 8>(px, [&](auto P) { return launch_xrow_t<L, decltype(P)::value, 2>(mode, a); });
@@ -959,7 +1204,8 @@ hipError_t PSS_CAT(launch_xrow_L, PSS_LINE_LEN)(int mode, int ng, const LaunchAr
 #define PSS_DECL_L(L)                                                               \
     hipError_t launch_update_L##L(int mode, int nf, const LaunchArgs& a);          \
     hipError_t launch_ypass_L##L(int mode, const YArgs& ya, const LaunchArgs& a);  \
-    hipError_t launch_xrow_L##L(int mode, int ng, const LaunchArgs& a);
+    hipError_t launch_xrow_L##L(int mode, int ng, const LaunchArgs& a);            \
+    hipError_t launch_adjcol_L##L(int mode, const AdjArgs& aa, const LaunchArgs& a);
 PSS_DECL_L(8)
 PSS_DECL_L(16)
 PSS_DECL_L(32)
@@ -1022,6 +1268,30 @@ hipError_t launch_xrow(int mode, int L, int ng, const LaunchArgs& a) {
         case 4096: return launch_xrow_L4096(mode, ng, a);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_adjcol(int mode, int L, const AdjArgs& aa, const LaunchArgs& a) {
+    switch (L) {
+        case 8: return launch_adjcol_L8(mode, aa, a);
+        case 16: return launch_adjcol_L16(mode, aa, a);
+        case 32: return launch_adjcol_L32(mode, aa, a);
+        case 64: return launch_adjcol_L64(mode, aa, a);
+        case 128: return launch_adjcol_L128(mode, aa, a);
+        case 256: return launch_adjcol_L256(mode, aa, a);
+        case 512: return launch_adjcol_L512(mode, aa, a);
+        case 1024: return launch_adjcol_L1024(mode, aa, a);
+        case 2048: return launch_adjcol_L2048(mode, aa, a);
+        case 4096: return launch_adjcol_L4096(mode, aa, a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_adjseed(hipStream_t s, const float2* phi, float2* g, const float* coef, int nshell, int nx, int ny,
+                          int tc) {
+    const int64_t total = static_cast<int64_t>(nx / 2) * ny;
+    hipLaunchKernelGGL(adjseed_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s, phi, g, coef,
+                       nshell, nx, ny, tc);
+    return hipGetLastError();
 }
 
 hipError_t launch_advance(hipStream_t s, uint64_t* step_ctr, int64_t k) {

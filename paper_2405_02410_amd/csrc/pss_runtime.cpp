@@ -1035,12 +1035,32 @@ pss_status pss_term_set_coef(pss_ctx* c, int32_t term_id, int32_t mono, double c
 
 pss_status pss_noise_set(pss_ctx* c, int32_t field, const pss_qmono* D, int32_t n_mono) {
     if (pss_status s = check_ctx(c)) return s;
-    if (c->planned) return fail(PSS_E_STATE, "noise cannot be changed after the plan is built");
     if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
     if (pss_status s = check_ops(D, n_mono, true)) return s;
-    c->fields[field].noisy = true;
-    c->fields[field].noise = to_monos(D, n_mono);
-    return PSS_OK;
+    std::vector<Mono> nm = to_monos(D, n_mono);
+    Field& fl = c->fields[field];
+    if (!c->planned) {
+        fl.noisy = true;
+        fl.noise = nm;
+        return PSS_OK;
+    }
+    // after planning: new coefficients of the same monomials only
+    bool same = fl.noisy && fl.noise.size() == nm.size();
+    for (size_t i = 0; same && i < nm.size(); ++i)
+        same = fl.noise[i].q2 == nm[i].q2 && fl.noise[i].invq == nm[i].invq && fl.noise[i].iq[0] == nm[i].iq[0] &&
+               fl.noise[i].iq[1] == nm[i].iq[1] && fl.noise[i].iq[2] == nm[i].iq[2];
+    if (!same) return fail(PSS_E_STATE, "after the plan is built only the coefficients of a noise operator can change");
+    const std::vector<Mono> old = fl.noise;
+    const pss::DevPlan keep = c->plan;
+    fl.noise = nm;
+    pss_status st = validate(c);
+    if (!st) st = build_plan(c);
+    if (st) {
+        fl.noise = old;
+        c->plan = keep;
+        return st;
+    }
+    return upload_plan(c);
 }
 
 pss_status pss_seed_set(pss_ctx* c, uint64_t seed) {
@@ -1375,6 +1395,217 @@ pss_status pss_time_kernel(pss_ctx* c, int32_t which, int32_t reps, double* ms, 
     c->dirty = true;  // the channel arrays no longer match the state
     static const char* names[4] = {"update_kernel", "xrow_kernel", "ypass_kernel(inverse)", "ypass_kernel(forward)"};
     if (name) *name = names[which];
+    return PSS_OK;
+}
+
+pss_status pss_adjoint_model_b(pss_ctx* c, int64_t nsteps, int32_t ckpt_every, const double* S_target,
+                               int32_t n_shells, double* loss, double* grad, float* grad_phi0, int32_t on_device) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (nsteps < 1 || ckpt_every < 1) return fail(PSS_E_INVAL, "need nsteps >= 1 and ckpt_every >= 1");
+    if (!S_target || !loss || !grad) return fail(PSS_E_INVAL, "null argument");
+    if (c->ndim != 2) return fail(PSS_E_UNSUPPORTED, "the adjoint is implemented for 2D lattices");
+    // recognise Model B: one field; implicit -(a q^2 + k q^4); explicit -b q^2 F[phi^3]; noise D q^2
+    double a = 0, b = 0, k = 0, D = 0;
+    {
+        bool ok = c->fields.size() == 1 && c->terms.size() == 2;
+        int nimp = 0, ncub = 0;
+        for (const Term& t : c->terms) {
+            if (!ok) break;
+            if (t.implicit) {
+                ++nimp;
+                for (const Mono& m : t.op) {
+                    if (m.invq || m.iq[0] || m.iq[1] || m.iq[2] || (m.q2 != 1 && m.q2 != 2)) ok = false;
+                    (m.q2 == 1 ? a : k) -= m.coef;
+                }
+            } else {
+                ++ncub;
+                ok = ok && t.factors.size() == 1 && t.factors[0].first == 0 && t.factors[0].second == 3 &&
+                     t.op.size() == 1 && t.op[0].q2 == 1 && !t.op[0].invq && !t.op[0].iq[0] && !t.op[0].iq[1] &&
+                     !t.op[0].iq[2];
+                if (ok) b = -t.op[0].coef;
+            }
+        }
+        const Field& f = c->fields.empty() ? Field{} : c->fields[0];
+        if (f.noisy) {
+            ok = ok && f.noise.size() == 1 && f.noise[0].q2 == 1 && !f.noise[0].invq && !f.noise[0].iq[0] &&
+                 !f.noise[0].iq[1] && !f.noise[0].iq[2];
+            if (ok) D = f.noise[0].coef;
+        }
+        if (!ok || nimp != 1 || ncub != 1)
+            return fail(PSS_E_UNSUPPORTED, "the adjoint needs a Model B lattice (implicit a q^2 + k q^4, "
+                                           "explicit -b q^2 phi^3, noise D q^2)");
+    }
+    if (pss_status s = materialize(c)) return s;
+    const int nx = c->n[0], ny = c->n[1];
+    const int ns = std::min(nx, ny) / 2;
+    if (n_shells != ns - 1) return fail(PSS_E_INVAL, "n_shells must be %d", ns - 1);
+    const int64_t nck = (nsteps + ckpt_every - 1) / ckpt_every;
+    const int64_t seglen = std::min<int64_t>(ckpt_every, nsteps);
+    const size_t fb = sizeof(float2) * static_cast<size_t>(c->packed());
+
+    // workspace: checkpoints, one recomputed segment, adjoint arrays
+    std::vector<void*> mem;
+    auto alloc = [&](size_t bytes) -> void* {
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        mem.push_back(p);
+        return p;
+    };
+    auto release = [&]() {
+        hipStreamSynchronize(c->stream);
+        for (void* p : mem) hipFree(p);
+        mem.clear();
+    };
+    auto* ck = static_cast<char*>(alloc(fb * static_cast<size_t>(nck)));
+    auto* seg = static_cast<char*>(alloc(fb * static_cast<size_t>(seglen + 1)));
+    auto* fT = static_cast<float2*>(alloc(fb));
+    auto* G = static_cast<float2*>(alloc(fb));
+    auto* R0 = static_cast<float2*>(alloc(fb));
+    auto* R1 = static_cast<float2*>(alloc(fb));
+    auto* X = static_cast<float2*>(alloc(fb));
+    auto* W = static_cast<float2*>(alloc(fb));
+    auto* U = static_cast<float2*>(alloc(fb));
+    auto* acc = static_cast<double*>(alloc(4 * sizeof(double)));
+    auto* coef = static_cast<float*>(alloc(sizeof(float) * ns));
+    auto* plan_row = static_cast<pss::DevPlan*>(alloc(sizeof(pss::DevPlan)));
+    auto* plan_raw = static_cast<pss::DevPlan*>(alloc(sizeof(pss::DevPlan)));
+    if (mem.size() != 13) {
+        release();
+        return fail(PSS_E_NOMEM, "adjoint workspace of %zu bytes does not fit", fb * (nck + seglen + 8));
+    }
+    auto at = [&](char* base, int64_t i) { return reinterpret_cast<float2*>(base + fb * static_cast<size_t>(i)); };
+#define ADJ_TRY(expr)            \
+    do {                         \
+        pss_status s_ = (expr);  \
+        if (s_) {                \
+            release();           \
+            return s_;           \
+        }                        \
+    } while (0)
+#define ADJ_HIP(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) {                                                                    \
+            release();                                                                             \
+            return fail(PSS_E_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+        }                                                                                          \
+    } while (0)
+
+    // plans of the row pass (u from the kept columns, w from all) and of the
+    // unnormalised inverse transform of g_0
+    pss::DevPlan pr = c->plan;
+    pr.mask[1] = pr.mask[0];
+    pr.mask[1].ncol = nx / 2;
+    pr.ng = 2;
+    pss::DevPlan pu = c->plan;
+    pu.inv_n = 1.f;
+    ADJ_HIP(hipMemcpy(plan_row, &pr, sizeof(pr), hipMemcpyHostToDevice));
+    ADJ_HIP(hipMemcpy(plan_raw, &pu, sizeof(pu), hipMemcpyHostToDevice));
+
+    // forward run with a checkpoint every ckpt_every steps
+    const int64_t n0 = c->steps_taken;
+    for (int64_t sgi = 0; sgi < nck; ++sgi) {
+        if (c->dirty) ADJ_TRY(prologue(c));
+        ADJ_HIP(hipMemcpyAsync(at(ck, sgi), c->d_state[0], fb, hipMemcpyDeviceToDevice, c->stream));
+        ADJ_TRY(pss_step(c, std::min<int64_t>(ckpt_every, nsteps - sgi * ckpt_every)));
+    }
+    ADJ_HIP(hipMemcpyAsync(fT, c->d_state[0], fb, hipMemcpyDeviceToDevice, c->stream));
+
+    // loss and terminal seed from the shell averages of the final spectrum
+    std::vector<double> S(ns - 1);
+    std::vector<int64_t> cnt(ns - 1);
+    ADJ_TRY(pss_structure_factor(c, 0, S.data(), cnt.data(), ns - 1));
+    const double dV = c->dx[0] * c->dx[1];
+    const double N = static_cast<double>(c->sites());
+    double L = 0;
+    std::vector<float> cf(ns, 0.f);
+    for (int j = 1; j < ns; ++j) {
+        const double d = S[j - 1] - S_target[j - 1];
+        L += d * d;
+        cf[j] = static_cast<float>(2.0 * d / std::max<int64_t>(cnt[j - 1], 1) * (dV / N) * 2.0);
+    }
+    ADJ_HIP(hipMemcpy(coef, cf.data(), sizeof(float) * ns, hipMemcpyHostToDevice));
+    ADJ_HIP(pss::launch_adjseed(c->stream, fT, G, coef, ns, nx, ny, c->geo.tc));
+    ADJ_HIP(hipMemsetAsync(acc, 0, 4 * sizeof(double), c->stream));
+
+    // reverse sweep: recompute each segment from its checkpoint, then step back
+    pss::AdjArgs aa{};
+    aa.plan = c->d_plan;
+    aa.G = G;
+    aa.X = X;
+    aa.W = W;
+    aa.U = U;
+    aa.acc = acc;
+    aa.a = static_cast<float>(a);
+    aa.b = static_cast<float>(b);
+    aa.k = static_cast<float>(k);
+    aa.D = static_cast<float>(D);
+    aa.first = 1;
+    float2* Rcur = R0;
+    float2* Rnxt = R1;
+    pss::LaunchArgs ax = args(c);
+    ax.plan = plan_row;
+    ax.bufs = pss::Bufs{};
+    ax.bufs.V[0] = U;
+    ax.bufs.V[1] = W;
+    ax.bufs.N[0] = X;
+    ax.bufs.acc = acc + 1;
+    for (int64_t sgi = nck - 1; sgi >= 0; --sgi) {
+        const int64_t start = sgi * ckpt_every;
+        const int64_t len = std::min<int64_t>(ckpt_every, nsteps - start);
+        const uint64_t st = static_cast<uint64_t>(n0 + start);
+        ADJ_HIP(hipStreamSynchronize(c->stream));
+        ADJ_HIP(hipMemcpy(c->d_step, &st, sizeof(st), hipMemcpyHostToDevice));
+        ADJ_HIP(hipMemcpyAsync(c->d_state[0], at(ck, sgi), fb, hipMemcpyDeviceToDevice, c->stream));
+        ADJ_HIP(hipMemcpyAsync(at(seg, 0), at(ck, sgi), fb, hipMemcpyDeviceToDevice, c->stream));
+        ADJ_TRY(prologue(c));
+        for (int64_t i = 1; i <= len; ++i) {
+            ADJ_TRY(enqueue_steps(c, 1));
+            ADJ_HIP(hipMemcpyAsync(at(seg, i), c->d_state[0], fb, hipMemcpyDeviceToDevice, c->stream));
+        }
+        for (int64_t i = len - 1; i >= 0; --i) {
+            aa.Rin = Rcur;
+            aa.Rout = Rnxt;
+            aa.phi1 = at(seg, i + 1);
+            aa.phi0 = at(seg, i);
+            aa.step = static_cast<uint32_t>(n0 + start + i);
+            ADJ_HIP(pss::launch_adjcol(pss::MODE_ADJCOL, ny, aa, args(c)));
+            ADJ_HIP(pss::launch_xrow(pss::MODE_ADJROW, nx, 2, ax));
+            std::swap(Rcur, Rnxt);
+            aa.first = 0;
+        }
+    }
+    // g_0, and the gradient for the real initial field: N F^-1[g_0]
+    aa.Rin = Rcur;
+    aa.Rout = G;
+    ADJ_HIP(pss::launch_adjcol(pss::MODE_ADJFIN, ny, aa, args(c)));
+    std::vector<double> gh(4);
+    ADJ_HIP(hipMemcpyAsync(gh.data(), acc, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (grad_phi0) {
+        pss::LaunchArgs a1 = args(c);
+        a1.plan = plan_raw;
+        a1.bufs.S[0] = G;
+        a1.bufs.sel = 0;
+        a1.bufs.out = c->d_tmp;
+        ADJ_HIP(pss::launch_update(pss::MODE_INV_OUT, c->lu, 1, a1));
+        a1.bufs.in = c->d_tmp;
+        a1.bufs.real_out = c->d_real;
+        ADJ_HIP(pss::launch_xrow(pss::MODE_C2R_OUT, nx, 1, a1));
+        ADJ_HIP(hipMemcpyAsync(grad_phi0, c->d_real, sizeof(float) * static_cast<size_t>(c->sites()),
+                               on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    }
+    // leave the lattice at the end of the forward run
+    const uint64_t fin = static_cast<uint64_t>(n0 + nsteps);
+    ADJ_HIP(hipStreamSynchronize(c->stream));
+    ADJ_HIP(hipMemcpy(c->d_step, &fin, sizeof(fin), hipMemcpyHostToDevice));
+    ADJ_HIP(hipMemcpy(c->d_state[0], fT, fb, hipMemcpyDeviceToDevice));
+    c->steps_taken = n0 + nsteps;
+    c->dirty = true;
+    release();
+#undef ADJ_TRY
+#undef ADJ_HIP
+    *loss = L;
+    for (int i = 0; i < 4; ++i) grad[i] = gh[i];
     return PSS_OK;
 }
 
