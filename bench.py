@@ -85,9 +85,10 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=2000)
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=("modelb1024", "ensemble"), default="modelb1024",
+    ap.add_argument("--workload", choices=("modelb1024", "ensemble", "adjoint"), default="modelb1024",
                     help="modelb1024: one 1024^2 lattice (default); ensemble: 256x128^2 + 64x256^2 + "
-                         "16x512^2 independent lattices in one batch, also timed one lattice per launch")
+                         "16x512^2 independent lattices in one batch, also timed one lattice per launch; "
+                         "adjoint: gradient of the structure-factor loss through 2000 steps at 256^2")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times with a plain device "
                          "copy (a known-size reference for hardware byte counters)")
@@ -105,6 +106,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "ensemble":
         return ensemble(args, pss)
+    if args.workload == "adjoint":
+        return adjoint(args, pss)
 
     lat = pss.Lattice(N, dt=DT, seed=SEED)
     f, _ = pss.model_b(lat, a=A, b=B, k=K, D=D)
@@ -266,6 +269,57 @@ def ensemble(args, pss):
     }
     print(json.dumps(out), flush=True)
     batch.close()
+
+
+def adjoint(args, pss):
+    """Adjoint workload: dL/d(a, b, k, D) and dL/dphi_0 of the shell
+    structure-factor loss after 2000 steps of 256^2 Model B, checkpoints every
+    45 steps; the target spectrum comes from a forward run at (a, b, k, D) =
+    (-1, 1, 1, 0.01), the gradient is taken at (-0.9, 1.1, 0.9, 0.012) with
+    the same seed and initial field.  Compared with the plain forward run."""
+    n, nsteps, ckpt = (256, 256), 2000, 45
+
+    def make(theta):
+        lat = pss.Lattice(n, dt=DT, seed=SEED)
+        f, _ = pss.model_b(lat, a=theta[0], b=theta[1], k=theta[2], D=theta[3])
+        lat.init_uniform(f, -0.1, 0.1)
+        return lat
+    ref = make((-1.0, 1.0, 1.0, 0.01))
+    ref.step(nsteps)
+    S_target, _ = ref.structure_factor(0)
+    fwd = make((-0.9, 1.1, 0.9, 0.012))
+    fwd.step(20)
+    fwd.sync()
+    t0 = time.perf_counter()
+    fwd.step(nsteps)
+    fwd.sync()
+    t_fwd = time.perf_counter() - t0
+    times = []
+    for _ in range(3):
+        lat = make((-0.9, 1.1, 0.9, 0.012))
+        lat.sync()
+        t0 = time.perf_counter()
+        loss, grad, _ = lat.adjoint_model_b(nsteps, S_target, ckpt_every=ckpt)
+        times.append(time.perf_counter() - t0)
+    t_adj = min(times)
+    sites = n[0] * n[1]
+    log(f"bench: adjoint {t_adj * 1e3:.1f} ms for {nsteps} steps (forward alone {t_fwd * 1e3:.1f} ms); "
+        f"loss {loss:.6g}, grad {grad}")
+    out = {
+        "metric": "site-steps/s", "value": sites * nsteps / t_adj, "unit": "site-steps/s", "n_gpus": 1,
+        "steps": nsteps, "warmup": 20, "ms_per_step": 1e3 * t_adj / nsteps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "adjoint of 2D Model B 256x256 FP32 through 2000 steps, checkpoints every 45 "
+                               "steps, structure-factor loss, gradients in (a, b, k, D) and phi_0",
+                   "lattice": list(n), "parallelism": "single GPU"},
+        "plain": {"value": sites * nsteps / t_fwd, "form": "the forward run alone (pss_step)"},
+        "vs_plain": round(t_fwd / t_adj, 3),
+        "loss": loss, "grad": list(grad),
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

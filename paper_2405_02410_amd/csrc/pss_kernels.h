@@ -89,11 +89,12 @@ struct YArgs {
 };
 
 // One lattice of a step launch.  The step kernels (update STEP / PROLOGUE,
-// x STEP) read plan, buffers and step counter of lattice blockIdx.y from a
-// table of these in device memory; the lattices of one launch share the
-// geometry (sizes, fields, factors, channels, tiling) and the twiddles.
+// x STEP) read buffers and step counter of lattice blockIdx.y from a table of
+// these in device memory, and its plan from a parallel array of plans (a
+// kernel argument of its own, so that the plan reads are scalar loads); the
+// lattices of one launch share the geometry (sizes, fields, factors,
+// channels, tiling) and the twiddles.
 struct Member {
-    const DevPlan* plan;
     Bufs bufs;
     const uint64_t* step_ctr;
 };
@@ -105,6 +106,7 @@ struct LaunchArgs {
     Geo geo;
     const uint64_t* step_ctr;
     const Member* members;  // step modes: table of nmem lattices (device memory)
+    const DevPlan* plans;   // step modes: their nmem plans (device memory)
     int nmem;
     int step_off;
     const float2* tw_u;  // twiddles of the update-axis length

@@ -287,20 +287,22 @@ __device__ __forceinline__ float2 pair_update_d(const DevPlan& p, int f, uint32_
 
 template <int L, int P, int NF, int MODE, int DIM>
 __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ members,
+                                                      const DevPlan* __restrict__ plans,
                                                       const DevPlan* __restrict__ plan_a, Bufs bufs_a, Geo geo,
                                                       const uint64_t* __restrict__ step_ctr_a,
                                                       int step_off, const float2* __restrict__ tw_g) {
     constexpr int T = L / P;
     extern __shared__ float2 smem[];
-    // step modes: lattice blockIdx.y of the member table; the transform
-    // modes act on the single lattice of the arguments (gridDim.y = 1)
+    // step modes: lattice blockIdx.y of the member table and of the plan
+    // array (both kernel arguments, so the plan reads stay scalar loads); the
+    // transform modes act on the single lattice of the arguments (gridDim.y = 1)
     constexpr bool TAB = MODE == MODE_STEP || MODE == MODE_PROLOGUE;
     const int nb = gridDim.x;
     const int lin = xcd_block(blockIdx.y * nb + blockIdx.x, nb * gridDim.y);
     const int mi = lin / nb;
     const int blk = lin - mi * nb;
     const Member* mem = members + mi;  // dereferenced in the step modes only
-    const DevPlan& p = TAB ? *mem->plan : *plan_a;
+    const DevPlan& p = TAB ? plans[mi] : *plan_a;
     const Bufs& bufs = TAB ? mem->bufs : bufs_a;
     const uint64_t* __restrict__ step_ctr = TAB ? mem->step_ctr : step_ctr_a;
     const int tc = geo.tc, to = geo.to;
@@ -754,6 +756,7 @@ __global__ void __launch_bounds__(256) ypass_kernel(YArgs ya, Geo geo, const flo
 // whole tile blocks of RB*TC contiguous elements.
 template <int L, int P, int NG, int MODE>
 __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ members,
+                                                    const DevPlan* __restrict__ plans,
                                                     const DevPlan* __restrict__ plan_a, Bufs bufs_a, Geo geo,
                                                     const float2* __restrict__ tw_g) {
     constexpr int T = L / P;
@@ -764,7 +767,7 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
     const int lin = xcd_block(blockIdx.y * nb + blockIdx.x, nb * gridDim.y);
     const int mi = lin / nb;
     const Member* mem = members + mi;
-    const DevPlan& p = TAB ? *mem->plan : *plan_a;
+    const DevPlan& p = TAB ? plans[mi] : *plan_a;
     const Bufs& bufs = TAB ? mem->bufs : bufs_a;
     const int tc = geo.tc, rb = geo.rb;
     const int ntile = NC / tc;
@@ -1051,23 +1054,23 @@ static hipError_t launch_update_d(int mode, const LaunchArgs& a) {
     const int threads = a.geo.tc * a.geo.to * (L / P);
     const size_t lds = update_lds_bytes(L, NF, a.geo.tc, a.geo.to);
     const bool tab = mode == MODE_STEP || mode == MODE_PROLOGUE;
-    if (tab && (!a.members || a.nmem < 1)) return hipErrorInvalidValue;
+    if (tab && (!a.members || !a.plans || a.nmem < 1)) return hipErrorInvalidValue;
     dim3 grid(a.geo.nublk, tab ? a.nmem : 1), block(threads);
     switch (mode) {
         case MODE_STEP:
-            hipLaunchKernelGGL((update_kernel<L, P, NF, MODE_STEP, DIM>), grid, block, lds, a.stream, a.members,
+            hipLaunchKernelGGL((update_kernel<L, P, NF, MODE_STEP, DIM>), grid, block, lds, a.stream, a.members, a.plans,
                                a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
             break;
         case MODE_PROLOGUE:
             hipLaunchKernelGGL((update_kernel<L, P, NF, MODE_PROLOGUE, DIM>), grid, block, lds, a.stream,
-                               a.members, a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
+                               a.members, a.plans, a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
             break;
         case MODE_FWD_STORE:
             hipLaunchKernelGGL((update_kernel<L, P, 1, MODE_FWD_STORE, DIM>), grid, block, lds, a.stream,
-                               a.members, a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
+                               a.members, a.plans, a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
             break;
         case MODE_INV_OUT:
-            hipLaunchKernelGGL((update_kernel<L, P, 1, MODE_INV_OUT, DIM>), grid, block, lds, a.stream, a.members,
+            hipLaunchKernelGGL((update_kernel<L, P, 1, MODE_INV_OUT, DIM>), grid, block, lds, a.stream, a.members, a.plans,
                                a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
             break;
         default:
@@ -1086,24 +1089,24 @@ static hipError_t launch_xrow_t(int mode, const LaunchArgs& a) {
     const int threads = (a.geo.rb / 2) * (L / P);
     const size_t lds = xrow_lds_bytes(L, a.geo.rb);
     const bool tab = mode == MODE_STEP;
-    if (tab && (!a.members || a.nmem < 1)) return hipErrorInvalidValue;
+    if (tab && (!a.members || !a.plans || a.nmem < 1)) return hipErrorInvalidValue;
     dim3 grid(a.geo.nrowblk, tab ? a.nmem : 1), block(threads);
     switch (mode) {
         case MODE_STEP:
-            hipLaunchKernelGGL((xrow_kernel<L, P, NG, MODE_STEP>), grid, block, lds, a.stream, a.members, a.plan,
+            hipLaunchKernelGGL((xrow_kernel<L, P, NG, MODE_STEP>), grid, block, lds, a.stream, a.members, a.plans, a.plan,
                                a.bufs, a.geo, a.tw_x);
             break;
         case MODE_R2C_IN:
-            hipLaunchKernelGGL((xrow_kernel<L, P, 1, MODE_R2C_IN>), grid, block, lds, a.stream, a.members, a.plan,
+            hipLaunchKernelGGL((xrow_kernel<L, P, 1, MODE_R2C_IN>), grid, block, lds, a.stream, a.members, a.plans, a.plan,
                                a.bufs, a.geo, a.tw_x);
             break;
         case MODE_C2R_OUT:
-            hipLaunchKernelGGL((xrow_kernel<L, P, 1, MODE_C2R_OUT>), grid, block, lds, a.stream, a.members, a.plan,
+            hipLaunchKernelGGL((xrow_kernel<L, P, 1, MODE_C2R_OUT>), grid, block, lds, a.stream, a.members, a.plans, a.plan,
                                a.bufs, a.geo, a.tw_x);
             break;
         case MODE_ADJROW:
             if constexpr (NG == 2) {
-                hipLaunchKernelGGL((xrow_kernel<L, P, 2, MODE_ADJROW>), grid, block, lds, a.stream, a.members,
+                hipLaunchKernelGGL((xrow_kernel<L, P, 2, MODE_ADJROW>), grid, block, lds, a.stream, a.members, a.plans,
                                    a.plan, a.bufs, a.geo, a.tw_x);
                 break;
             }

@@ -162,7 +162,8 @@ struct pss_ctx {
     // one-entry member tables of the step kernels (update kernel, x kernel)
     pss::Member* d_member_u = nullptr;
     pss::Member* d_member_x = nullptr;
-    int batches = 0;  // live batches holding this context
+    int batches = 0;        // live batches holding this context
+    uint64_t plan_gen = 0;  // bumped at every upload of the plan
     std::map<int64_t, hipGraphExec_t> graphs;
     std::map<std::string, int64_t> tune;  // launch-geometry overrides
     int64_t steps_taken = 0;
@@ -182,6 +183,8 @@ struct pss_batch {
         pss_ctx* rep = nullptr;        // first member: geometry and twiddles
         pss::Member* d_u = nullptr;    // member tables of the update and x kernels
         pss::Member* d_x = nullptr;
+        pss::DevPlan* d_plans = nullptr;  // copies of the members' plans
+        std::vector<uint64_t> gen;        // plan generation of each copy
     };
     std::vector<pss_ctx*> mem;
     std::vector<Class> cls;
@@ -553,6 +556,7 @@ pss::LaunchArgs args(pss_ctx* c, int step_off = 0) {
     a.geo = c->geo;
     a.step_ctr = c->d_step;
     a.members = c->d_member_u;
+    a.plans = c->d_plan;
     a.nmem = 1;
     a.step_off = step_off;
     a.tw_u = c->d_tw_u;
@@ -573,11 +577,11 @@ pss::LaunchArgs xargs(pss_ctx* c) {
 // member-table entries of the update kernel and the x kernel of a context
 pss::Member member_u(pss_ctx* c) {
     const pss::LaunchArgs a = args(c);
-    return pss::Member{c->d_plan, a.bufs, c->d_step};
+    return pss::Member{a.bufs, c->d_step};
 }
 pss::Member member_x(pss_ctx* c) {
     const pss::LaunchArgs a = xargs(c);
-    return pss::Member{c->d_plan, a.bufs, c->d_step};
+    return pss::Member{a.bufs, c->d_step};
 }
 
 hipError_t y_inverse_factors(pss_ctx* c) {
@@ -605,6 +609,7 @@ hipError_t y_forward_channels(pss_ctx* c) {
 pss_status upload_plan(pss_ctx* c) {
     HIP_TRY(hipStreamSynchronize(c->stream));
     HIP_TRY(hipMemcpy(c->d_plan, &c->plan, sizeof(pss::DevPlan), hipMemcpyHostToDevice));
+    ++c->plan_gen;
     return PSS_OK;
 }
 
@@ -781,12 +786,27 @@ void free_batch(pss_batch* b) {
     for (auto& cl : b->cls) {
         if (cl.d_u) hipFree(cl.d_u);
         if (cl.d_x) hipFree(cl.d_x);
+        if (cl.d_plans) hipFree(cl.d_plans);
         cl.d_u = cl.d_x = nullptr;
+        cl.d_plans = nullptr;
     }
     if (b->d_ctrs) hipFree(b->d_ctrs);
     b->d_ctrs = nullptr;
     if (b->ev) hipEventDestroy(b->ev);
     b->ev = nullptr;
+}
+
+// copy the plans of members whose coefficients changed since the last step
+pss_status batch_refresh_plans(pss_batch* b) {
+    for (auto& cl : b->cls)
+        for (size_t j = 0; j < cl.idx.size(); ++j) {
+            pss_ctx* m = b->mem[cl.idx[j]];
+            if (cl.gen[j] == m->plan_gen) continue;
+            HIP_TRY(hipMemcpyAsync(cl.d_plans + j, m->d_plan, sizeof(pss::DevPlan), hipMemcpyDeviceToDevice,
+                                   b->stream));
+            cl.gen[j] = m->plan_gen;
+        }
+    return PSS_OK;
 }
 
 pss_status batch_enqueue(pss_batch* b, int64_t k) {
@@ -796,12 +816,14 @@ pss_status batch_enqueue(pss_batch* b, int64_t k) {
             pss::LaunchArgs a = args(r, static_cast<int>(i));
             a.stream = b->stream;
             a.members = cl.d_u;
+            a.plans = cl.d_plans;
             a.nmem = static_cast<int>(cl.idx.size());
             HIP_TRY(pss::launch_update(pss::MODE_STEP, r->lu, static_cast<int>(r->fields.size()), a));
             if (r->plan.nch > 0) {
                 pss::LaunchArgs ax = xargs(r);
                 ax.stream = b->stream;
                 ax.members = cl.d_x;
+                ax.plans = cl.d_plans;
                 ax.nmem = a.nmem;
                 HIP_TRY(pss::launch_xrow(pss::MODE_STEP, r->n[0], r->plan.ng, ax));
             }
@@ -1654,8 +1676,14 @@ pss_status pss_batch_create(pss_batch** out, pss_ctx* const* lattices, int32_t n
         const size_t bytes = sizeof(pss::Member) * tu.size();
         if (e == hipSuccess) e = hipMalloc(&cl.d_u, bytes);
         if (e == hipSuccess) e = hipMalloc(&cl.d_x, bytes);
+        if (e == hipSuccess) e = hipMalloc(&cl.d_plans, sizeof(pss::DevPlan) * tu.size());
         if (e == hipSuccess) e = hipMemcpy(cl.d_u, tu.data(), bytes, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(cl.d_x, tx.data(), bytes, hipMemcpyHostToDevice);
+        for (size_t j = 0; j < cl.idx.size() && e == hipSuccess; ++j) {
+            pss_ctx* m = b->mem[cl.idx[j]];
+            e = hipMemcpy(cl.d_plans + j, m->d_plan, sizeof(pss::DevPlan), hipMemcpyDeviceToDevice);
+            cl.gen.push_back(m->plan_gen);
+        }
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
     if (e != hipSuccess)
@@ -1689,6 +1717,7 @@ pss_status pss_batch_step(pss_batch* b, int64_t nsteps) {
             HIP_TRY(hipStreamWaitEvent(b->stream, b->ev, 0));
         }
     }
+    if (pss_status s = batch_refresh_plans(b)) return s;
     int64_t left = nsteps;
     while (left > 0) {
         const int64_t k = std::min(left, kGraphSteps);
@@ -1738,9 +1767,11 @@ pss_status pss_batch_time_kernel(pss_batch* b, int32_t cls, int32_t which, int32
             HIP_TRY(hipStreamWaitEvent(b->stream, b->ev, 0));
         }
     }
+    if (pss_status s = batch_refresh_plans(b)) return s;
     pss::LaunchArgs a = which == 0 ? args(r) : xargs(r);
     a.stream = b->stream;
     a.members = which == 0 ? cl.d_u : cl.d_x;
+    a.plans = cl.d_plans;
     a.nmem = static_cast<int>(cl.idx.size());
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
