@@ -242,6 +242,18 @@ pss_status pss_util_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
 pss_status pss_time_kernel(pss_ctx *ctx, int32_t which, int32_t reps, double *ms_per_launch,
                            const char **name);
 
+/* Pick the launch geometry by timing: before the plan is built, try points
+ * per thread and tile widths of the update kernel (pu, tc; 3D: to), then of
+ * the x kernel (px, rb), then (3D) of the y passes (py, tz), each on a scratch
+ * copy of the model with `reps` back-to-back launches per kernel (HIP
+ * events), and keep the fastest as if set by pss_tuning_set.  Keys the
+ * caller already set are kept.  The choice is cached for the process per
+ * lattice shape, term structure and forced keys.  *us_per_step (may be NULL)
+ * receives the summed kernel time of one step at the choice.  Tiling keys
+ * leave results bitwise unchanged; points per thread change the FFT radix
+ * and so the FP32 rounding.  PSS_E_STATE after the plan is built. */
+pss_status pss_autotune(pss_ctx *ctx, int32_t reps, double *us_per_step);
+
 /* Per-launch algorithmic HBM bytes of kernel `which` (same numbering): the
  * bytes each launch must read and write once at the current plan. */
 pss_status pss_kernel_bytes(pss_ctx *ctx, int32_t which, double *bytes);

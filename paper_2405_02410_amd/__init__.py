@@ -84,6 +84,7 @@ _SIGS = {
     "pss_kernels_per_step": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)],
     "pss_tuning_set": [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64],
     "pss_tuning_get": [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)],
+    "pss_autotune": [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
     "pss_adjoint_model_b": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                             ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                             ctypes.c_void_p, ctypes.c_int32],
@@ -212,6 +213,13 @@ class Lattice:
         """Force launch-geometry values (tc, to, tz, rb, pu, px, py) before the plan is built."""
         for k, v in kw.items():
             _check(lib().pss_tuning_set(self._h, k.encode(), int(v)))
+
+    def autotune(self, reps=30):
+        """Time candidate launch geometries and keep the fastest (pss_autotune);
+        returns the summed kernel time of one step in microseconds."""
+        us = ctypes.c_double()
+        _check(lib().pss_autotune(self._h, int(reps), ctypes.byref(us)))
+        return us.value
 
     def geometry(self):
         out = {}

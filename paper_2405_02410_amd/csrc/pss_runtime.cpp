@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <tuple>
@@ -1417,6 +1418,97 @@ pss_status pss_time_kernel(pss_ctx* c, int32_t which, int32_t reps, double* ms, 
     c->dirty = true;  // the channel arrays no longer match the state
     static const char* names[4] = {"update_kernel", "xrow_kernel", "ypass_kernel(inverse)", "ypass_kernel(forward)"};
     if (name) *name = names[which];
+    return PSS_OK;
+}
+
+pss_status pss_autotune(pss_ctx* c, int32_t reps, double* us_per_step) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (c->planned) return fail(PSS_E_STATE, "autotune before the plan is built (first upload, init or step)");
+    if (reps < 1) return fail(PSS_E_INVAL, "reps must be >= 1");
+    if (pss_status s = validate(c)) return s;
+    using Tune = std::map<std::string, int64_t>;
+    // one process-wide cache entry per lattice shape and term structure
+    static std::map<std::string, std::pair<Tune, double>> cache;
+    static std::mutex cache_mu;
+    std::lock_guard<std::mutex> lock(cache_mu);
+    std::string key = std::to_string(c->ndim);
+    for (int i = 0; i < c->ndim; ++i) key += "x" + std::to_string(c->n[i]);
+    key += "/f" + std::to_string(c->fields.size()) + "/t";
+    for (const Term& t : c->terms) {
+        key += t.implicit ? "i" : "e";
+        for (auto& fp : t.factors) key += std::to_string(fp.first) + "^" + std::to_string(fp.second);
+        key += ",";
+    }
+    for (const auto& kv : c->tune) key += kv.first + "=" + std::to_string(kv.second);  // forced keys stay
+    auto hit = cache.find(key);
+    if (hit != cache.end()) {
+        c->tune = hit->second.first;
+        if (us_per_step) *us_per_step = hit->second.second;
+        return PSS_OK;
+    }
+    // time the kernels of one step on a scratch copy of the model; +inf if
+    // the geometry is not valid for this lattice
+    const int nk = c->ndim == 3 ? 4 : 2;
+    auto trial = [&](const Tune& tn) -> double {
+        pss_ctx* t = new pss_ctx();
+        t->ndim = c->ndim;
+        for (int i = 0; i < 3; ++i) {
+            t->n[i] = c->n[i];
+            t->dx[i] = c->dx[i];
+        }
+        t->dt = c->dt;
+        t->seed = c->seed;
+        t->rule = c->rule;
+        t->shape = c->shape;
+        t->fields = c->fields;
+        t->terms = c->terms;
+        t->tune = tn;
+        double total = 0;
+        if (materialize(t) != PSS_OK) total = HUGE_VAL;
+        for (int w = 0; w < nk && std::isfinite(total); ++w) {
+            if ((w == 1 || w == 3) && t->plan.nch == 0) continue;
+            if (w == 2 && t->plan.ng == 0) continue;
+            double ms = 0;
+            if (pss_time_kernel(t, w, reps, &ms, nullptr) != PSS_OK) {
+                total = HUGE_VAL;
+                break;
+            }
+            total += ms;
+        }
+        pss_lattice_destroy(t);
+        return total;
+    };
+    const std::string err_keep = g_err;
+    Tune best = c->tune;
+    double tbest = trial(best);
+    auto improve = [&](const char* k1, std::vector<int> v1, const char* k2, std::vector<int> v2) {
+        const Tune base = best;
+        // a key the caller set keeps its value
+        if (c->tune.count(k1)) v1 = {static_cast<int>(c->tune.at(k1))};
+        if (k2 && c->tune.count(k2)) v2 = {static_cast<int>(c->tune.at(k2))};
+        for (int a : v1)
+            for (int b : v2) {
+                Tune tn = base;
+                tn[k1] = a;
+                if (k2) tn[k2] = b;
+                const double tt = trial(tn);
+                if (tt < tbest) {
+                    tbest = tt;
+                    best = tn;
+                }
+            }
+    };
+    // update kernel (and the tile width the x kernel shares), then x kernel,
+    // then (3D) the y pass
+    improve("pu", {4, 8, 16}, "tc", {1, 2, 4, 8, 16, 32});
+    if (c->ndim == 3) improve("to", {1, 2, 4, 8}, nullptr, {0});
+    improve("px", {4, 8, 16}, "rb", {2, 4, 8, 16, 32});
+    if (c->ndim == 3) improve("py", {4, 8, 16}, "tz", {1, 2, 4, 8});
+    g_err = err_keep;
+    if (!std::isfinite(tbest)) return fail(PSS_E_UNSUPPORTED, "no launch geometry works for this lattice");
+    c->tune = best;
+    cache[key] = {best, tbest * 1e3};
+    if (us_per_step) *us_per_step = tbest * 1e3;
     return PSS_OK;
 }
 

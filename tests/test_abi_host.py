@@ -144,3 +144,11 @@ def test_batch_arguments_are_checked_before_any_device_work():
     assert lib.pss_batch_sync(None) == -1
     assert lib.pss_batch_info(None, None, None) == -1
     assert lib.pss_batch_destroy(None) == 0
+
+
+def test_autotune_arguments():
+    lat = _lat()
+    pss.model_b(lat)
+    with pytest.raises(PssError) as e:
+        lat.autotune(reps=0)
+    assert e.value.name == "PSS_E_INVAL"
