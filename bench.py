@@ -89,6 +89,8 @@ def main():
                     help="modelb1024: one 1024^2 lattice (default); ensemble: 256x128^2 + 64x256^2 + "
                          "16x512^2 independent lattices in one batch, also timed one lattice per launch; "
                          "adjoint: gradient of the structure-factor loss through 2000 steps at 256^2")
+    ap.add_argument("--autotune", action="store_true",
+                    help="ensemble: pick each lattice size's launch geometry with pss_autotune first")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times with a plain device "
                          "copy (a known-size reference for hardware byte counters)")
@@ -201,6 +203,8 @@ def ensemble(args, pss):
             for _ in range(count):
                 lat = pss.Lattice((side, side), dt=DT, seed=seed)
                 f, _ = pss.model_b(lat, a=A, b=B, k=K, D=D)
+                if args.autotune:
+                    lat.autotune(reps=20)  # measured once per size, then cached
                 lat.init_uniform(f, -0.1, 0.1)
                 lats.append(lat)
                 seed += 1
@@ -260,7 +264,8 @@ def ensemble(args, pss):
         "config": {"workload": "ensemble of 2D Model B lattices, 256x128^2 + 64x256^2 + 16x512^2 FP32, "
                                "a=-1 b=1 k=1, D=0.01 q^2, dt=0.01, 2/3 radial de-aliasing, independent seeds, "
                                "one batch",
-                   "members": len(lats), "sites": sites, "parallelism": "single GPU"},
+                   "members": len(lats), "sites": sites, "parallelism": "single GPU",
+                   "geometry": "autotuned per size" if args.autotune else "default"},
         "plain": {"value": plain, "steps": plain_steps,
                   "form": "pss_step on each lattice in turn, each on its own stream"},
         "vs_plain": round(value / plain, 2),
