@@ -59,22 +59,29 @@ def measured_traffic(geometry):
     return float(kv["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(steps):
-    """The FP64 oracle on `steps` steps of the same workload (after one warm-up)."""
+def cpu_baseline(steps, steps_1core=5):
+    """The FP64 oracle on `steps` steps of the same workload (after one warm-up),
+    on all host cores, and on `steps_1core` steps with one FFT worker."""
     from oracle import model as om
     from oracle import spectral
     cores = os.cpu_count() or 1
-    spectral.WORKERS = cores
-    m = om.model_b(spectral.Lattice(*N), DT, a=A, b=B, k=K, D=D, seed=SEED)
-    m.init_uniform(0, -0.1, 0.1)
-    m.step(1)
-    t0 = time.perf_counter()
-    m.step(steps)
-    dt = time.perf_counter() - t0
     sites = N[0] * N[1]
-    return {"value": sites * steps / dt, "unit": "site-steps/s", "cores": cores, "kind": "oracle",
+
+    def rate(workers, k):
+        spectral.WORKERS = workers
+        m = om.model_b(spectral.Lattice(*N), DT, a=A, b=B, k=K, D=D, seed=SEED)
+        m.init_uniform(0, -0.1, 0.1)
+        m.step(1)
+        t0 = time.perf_counter()
+        m.step(k)
+        return sites * k / (time.perf_counter() - t0)
+    value = rate(cores, steps)
+    one = rate(1, steps_1core)
+    return {"value": value, "unit": "site-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"{steps} steps of the 1024x1024 Model B workload after 1 warm-up step "
-                      f"(numpy FP64, scipy.fft with {cores} workers)"}
+                      f"(numpy FP64; the FFTs run on scipy.fft with {cores} workers, the elementwise "
+                      f"steps are single-threaded numpy)",
+            "single_core": {"value": one, "sample": f"{steps_1core} steps, scipy.fft with 1 worker"}}
 
 
 def main():
