@@ -159,3 +159,18 @@ def test_batch_kernel_timing_and_bytes():
         tw.step(3)
         assert np.array_equal(lat.spectrum(0), tw.spectrum(0))
     batch.close()
+
+
+def test_full_ensemble_configuration_sampled():
+    # the batched ensemble exactly as bench.py runs it (256 x 128^2 + 64 x 256^2
+    # + 16 x 512^2, seeds 1000 + i); two members of each size re-run alone
+    sizes = [128] * 256 + [256] * 64 + [512] * 16
+    mem = [_model_b((s, s), 1000 + i) for i, s in enumerate(sizes)]
+    batch = pss.Batch(mem)
+    assert batch.classes()[0] == 3
+    batch.step(25)
+    for i in (0, 255, 256, 319, 320, 335):
+        twin = _model_b((sizes[i], sizes[i]), 1000 + i)
+        twin.step(25)
+        assert np.array_equal(mem[i].spectrum(0), twin.spectrum(0)), i
+    batch.close()

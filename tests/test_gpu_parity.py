@@ -197,7 +197,8 @@ def test_model_b_64_after_1000_steps():
     assert err <= 1e-4, err
 
 
-@pytest.mark.parametrize("n", [(128, 32), (32, 128), (16, 256), (256, 16), (8, 8), (2048, 8)])
+@pytest.mark.parametrize("n", [(128, 32), (32, 128), (16, 256), (256, 16), (8, 8), (2048, 8), (4096, 16),
+                               (16, 4096)])
 def test_model_b_non_square(n):
     lat, m = _model_b_pair(n, 20, seed=5, D=0.05)
     lat.step(20)
@@ -214,6 +215,16 @@ def test_model_b_dealias_variants(deal, shape):
     lat.step(30)
     m.step(30)
     assert np.max(np.abs(lat.download(0) - m.real(0)[0])) < 2e-5
+
+
+def test_model_b_4096_largest_lattice():
+    # the largest 2D lattice the library takes (4096 per axis), 2 noisy steps
+    lat, m = _model_b_pair((4096, 4096), 2)
+    lat.step(2)
+    m.step(2)
+    err = np.max(np.abs(lat.download(0) - m.real(0)[0]))
+    assert err < 1e-5, err
+    assert abs(lat.mass(0) - np.sum(m.real(0))) <= 1e-6 * np.sum(np.abs(m.real(0)))
 
 
 def test_model_b_1024_full_size():
