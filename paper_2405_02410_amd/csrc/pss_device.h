@@ -156,13 +156,18 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
 // Padding of LDS line buffers: one float2 every 16 to spread banks.
 __host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int lds_line(int L) { return lds_pad(L); }
+// LDS of one line transform: two padded lines, written by alternate passes
+__host__ __device__ constexpr int lds_fft(int L) { return 2 * lds_line(L); }
 
 // One Stockham pass of span NS over a line of length L held by T = L/P
-// threads; thread t keeps x[t + m T] in v[m] on entry and exit.
+// threads; thread t keeps x[t + m T] in v[m] on entry and exit.  Passes
+// exchange through `buf` and hand `alt` to the next pass: a buffer is written
+// again only two passes later, after a barrier that every thread reaches once
+// it has read the older data, so one barrier per exchange suffices.
 template <int L, int P, int NS, int DIR>
 struct StockhamPass {
-    static __device__ __forceinline__ void run(float2 (&v)[P], float2* __restrict__ buf, int t,
-                                               const float2* __restrict__ tw) {
+    static __device__ __forceinline__ void run(float2 (&v)[P], float2* __restrict__ buf, float2* __restrict__ alt,
+                                               int t, const float2* __restrict__ tw) {
         constexpr int R = (P < L / NS) ? P : (L / NS);
         constexpr int T = L / P;
         constexpr int B = P / R;  // butterflies per thread
@@ -196,20 +201,22 @@ struct StockhamPass {
             __syncthreads();
 #pragma unroll
             for (int m = 0; m < P; ++m) v[m] = buf[lds_pad(t + m * T)];
-            __syncthreads();
-            StockhamPass<L, P, NS * R, DIR>::run(v, buf, t, tw);
+            StockhamPass<L, P, NS * R, DIR>::run(v, alt, buf, t, tw);
         }
     }
 };
 
 // Full line transform: v[m] = x[t + m T] in, X[t + m T] out (natural order).
 // DIR = -1: forward, unnormalised; DIR = +1: inverse, unnormalised.
-// Every thread of the block must call it (it contains block barriers).
+// buf holds lds_fft(L) elements (two padded lines).  Every thread of the
+// block must call it (it contains block barriers); on return every thread
+// has finished with buf, which the caller may reuse at once.
 template <int L, int P, int DIR>
 __device__ __forceinline__ void fft_line(float2 (&v)[P], float2* __restrict__ buf, int t,
                                          const float2* __restrict__ tw) {
     static_assert((L & (L - 1)) == 0 && (P & (P - 1)) == 0 && P <= 16 && P <= L, "bad FFT shape");
-    StockhamPass<L, P, 1, DIR>::run(v, buf, t, tw);
+    StockhamPass<L, P, 1, DIR>::run(v, buf, buf + lds_line(L), t, tw);
+    if constexpr (L > P) __syncthreads();
 }
 
 // ------------------------------------------------------------------ Philox

@@ -138,20 +138,21 @@ hipError_t launch_philox(hipStream_t s, uint32_t c0, uint32_t c1, uint32_t c2, u
 
 // register-array count an instantiation is built for (1, 2 or 4 fields)
 inline int field_slots(int n) { return n <= 1 ? 1 : (n == 2 ? 2 : 4); }
-// dynamic LDS of the update kernel: TC*TO padded lines, one exchange line and
-// the staged twiddle table (L entries), in that order
+// dynamic LDS of the update kernel: TC*TO line transforms (two padded lines
+// each), one exchange line and the staged twiddle table (L entries), in that order
 inline size_t update_lds_bytes(int L, int nf_slots, int tc, int to) {
     (void)nf_slots;
-    return sizeof(float2) * (static_cast<size_t>(tc) * to * (L + L / 16) + 2 * static_cast<size_t>(L));
+    return sizeof(float2) * (static_cast<size_t>(tc) * to * 2 * (L + L / 16) + 2 * static_cast<size_t>(L));
 }
-// dynamic LDS of the y pass: TC*TZ padded lines, one exchange line per z and
-// the staged twiddle table (L entries), in that order
+// dynamic LDS of the y pass: TC*TZ line transforms (two padded lines each),
+// one exchange line per z and the staged twiddle table (L entries), in that order
 inline size_t ypass_lds_bytes(int L, int tc, int tz) {
-    return sizeof(float2) * (static_cast<size_t>(tc) * tz * (L + L / 16) + static_cast<size_t>(tz + 1) * L);
+    return sizeof(float2) * (static_cast<size_t>(tc) * tz * 2 * (L + L / 16) + static_cast<size_t>(tz + 1) * L);
 }
-// dynamic LDS of the x kernel: RB/2 padded lines + the staged twiddle table
+// dynamic LDS of the x kernel: RB/2 line transforms (two padded lines each)
+// + the staged twiddle table
 inline size_t xrow_lds_bytes(int L, int rb) {
-    return sizeof(float2) * (static_cast<size_t>(rb / 2) * (L + L / 16) + static_cast<size_t>(L));
+    return sizeof(float2) * (static_cast<size_t>(rb / 2) * 2 * (L + L / 16) + static_cast<size_t>(L));
 }
 
 // FP64 shell sums of (dV/N)|phi_hat|^2 over the packed state of one field

@@ -319,8 +319,8 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
     const size_t base = (static_cast<size_t>(o) * ntile + ct) * L * tc + cc;
     const size_t vbase = DIM == 2 ? base : (static_cast<size_t>(ct) * ny + o) * tc + cc;
     const size_t vstride = DIM == 2 ? static_cast<size_t>(tc) : static_cast<size_t>(ntile) * ny * tc;
-    float2* line = smem + (lo * tc + cc) * lds_line(L);
-    float2* xbuf = smem + tc * to * lds_line(L);  // packed-line exchange
+    float2* line = smem + (lo * tc + cc) * lds_fft(L);
+    float2* xbuf = smem + tc * to * lds_fft(L);  // packed-line exchange
     const float2* tw = stage_twiddles<L>(xbuf + L, tw_g, tid, tc * to * T);
     // block holds a packed line (block-uniform); this thread is on it
     const bool blk_packed = ct == 0 && (DIM == 2 || og * to == 0 || og * to == (ny >> 1));
@@ -515,8 +515,8 @@ __global__ void __launch_bounds__(256) adjcol_kernel(AdjArgs aa, Geo geo, const 
     const int nx = p.n[0];
     const int kn = -(nx >> 1);
     const size_t base = static_cast<size_t>(ct) * L * tc + cc;
-    float2* line = smem + cc * lds_line(L);
-    float2* xbuf = smem + tc * lds_line(L);
+    float2* line = smem + cc * lds_fft(L);
+    float2* xbuf = smem + tc * lds_fft(L);
     const float2* tw = stage_twiddles<L>(xbuf + L, tw_g, tid, tc * T);
     const bool blk_packed = ct == 0;
     const bool packed = blk_packed && cc == 0;
@@ -696,9 +696,9 @@ __global__ void __launch_bounds__(256) ypass_kernel(YArgs ya, Geo geo, const flo
     const int ct = blk % ntile;
     const int z = (blk / ntile) * tz + lz;
     const int c = ct * tc + cc;
-    float2* line = smem + (lz * tc + cc) * lds_line(L);
-    float2* xb = smem + tc * tz * lds_line(L) + lz * L;  // column-0 exchange, one line per z
-    const float2* tw = stage_twiddles<L>(smem + tc * tz * lds_line(L) + tz * L, tw_g, tid, tc * tz * T);
+    float2* line = smem + (lz * tc + cc) * lds_fft(L);
+    float2* xb = smem + tc * tz * lds_fft(L) + lz * L;  // column-0 exchange, one line per z
+    const float2* tw = stage_twiddles<L>(smem + tc * tz * lds_fft(L) + tz * L, tw_g, tid, tc * tz * T);
     const size_t ibase = (static_cast<size_t>(z) * ntile + ct) * L * tc + cc;
     const size_t obase = MODE == MODE_YFWD ? (static_cast<size_t>(ct) * nz + z) * tc + cc : ibase;
     const size_t ostride = MODE == MODE_YFWD ? static_cast<size_t>(ntile) * nz * tc : static_cast<size_t>(tc);
@@ -780,8 +780,8 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
     const int zr = r0 / ny;          // z of the block (0 in 2D)
     const int y0 = r0 - zr * ny;     // first y of the block
     const int lt = geo.tc_log2;
-    float2* line = smem + pr * lds_line(L);
-    const float2* tw = stage_twiddles<L>(smem + (rb / 2) * lds_line(L), tw_g, tid, nthr);
+    float2* line = smem + pr * lds_fft(L);
+    const float2* tw = stage_twiddles<L>(smem + (rb / 2) * lds_fft(L), tw_g, tid, nthr);
 
     // Gather the packed complex input Z[k] = X_row0[k] + i X_row1[k] of pair
     // pr straight from the packed-column array (columns [0, ncol) are stored;
@@ -818,7 +818,7 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
             const int tl = i / per, rem = i - tl * per;
             const int r = rem / tc, cc = rem - r * tc;
             const int c = tl * tc + cc;
-            const float2* W = smem + (r >> 1) * lds_line(L);
+            const float2* W = smem + (r >> 1) * lds_fft(L);
             float2 o;
             if (c == 0) {
                 const float2 a = W[lds_pad(0)], b = W[lds_pad(NC)];
