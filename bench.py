@@ -97,8 +97,8 @@ def main():
                          "16x512^2 independent lattices in one batch, also timed one lattice per launch; "
                          "adjoint: gradient of the structure-factor loss through 2000 steps at 256^2; "
                          "3d: the two-field 256^3 system (Model B phi coupled to Model A psi)")
-    ap.add_argument("--autotune", action="store_true",
-                    help="ensemble: pick each lattice size's launch geometry with pss_autotune first")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="ensemble: keep the default launch geometry instead of pss_autotune's choice per size")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times with a plain device "
                          "copy (a known-size reference for hardware byte counters)")
