@@ -30,7 +30,7 @@ def test_mass_is_sum():
 def test_shell_populations():
     lat = Lattice(32, 32)
     j = ob.shell_index(lat)
-    # shell 1 holds exactly the 4 nearest modes plus the 4 diagonal ones with |k|=sqrt2 -> round 1
+    # shell 1 holds exactly the 4 nearest modes plus the 4 diagonal ones with |k|=sqrt2 (rounds to 1)
     assert np.sum(j == 1) == 8
     _, nj = ob.shell_average(lat, np.ones(lat.shape))
     assert nj.sum() == np.sum((j >= 1) & (j < 16))
