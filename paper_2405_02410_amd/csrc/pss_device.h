@@ -139,6 +139,23 @@ struct DFT<16, DIR> {
     }
 };
 
+// ------------------------------------------------------------ global access
+// The step kernels read their array pointers from a table in device memory,
+// so the compiler sees generic pointers and would emit FLAT loads and stores
+// (which also hold the LDS counter).  Every such array is device memory:
+// access it through global (address space 1) pointers, 8 bytes at a time.
+typedef __attribute__((address_space(1))) double pss_gdouble;
+typedef __attribute__((address_space(1))) uint64_t pss_gu64;
+__device__ __forceinline__ float2 gload(const float2* p) {
+    const pss_gdouble* q = (const pss_gdouble*)(p);
+    return __builtin_bit_cast(float2, *q);
+}
+__device__ __forceinline__ void gstore(float2* p, float2 v) {
+    pss_gdouble* q = (pss_gdouble*)(p);
+    *q = __builtin_bit_cast(double, v);
+}
+__device__ __forceinline__ uint64_t gload_u64(const uint64_t* p) { return *(const pss_gu64*)(p); }
+
 // ------------------------------------------------------------ block order
 // The hardware hands out the blocks of a grid round-robin over the 8 XCDs
 // (block b starts on XCD b mod 8), and each XCD has its own L2.  Renumber

@@ -108,6 +108,7 @@ struct LaunchArgs {
     const Member* members;  // step modes: table of nmem lattices (device memory)
     const DevPlan* plans;   // step modes: their nmem plans (device memory)
     int nmem;
+    bool general;           // the plans need the general-monomial operator code
     int step_off;
     const float2* tw_u;  // twiddles of the update-axis length
     const float2* tw_x;  // twiddles of Nx

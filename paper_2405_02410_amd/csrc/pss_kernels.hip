@@ -27,11 +27,25 @@ namespace pss {
 // Copy the twiddle table of a line length into LDS once per block; the copy
 // loop is unrolled so its loads are in flight together.  Returns the LDS copy
 // (the first transform's barriers order it before any use).
-template <int L>
-__device__ __forceinline__ const float2* stage_twiddles(float2* dst, const float2* __restrict__ src, int tid,
-                                                        int nthr) {
-#pragma unroll 8
-    for (int i = tid; i < L; i += nthr) dst[i] = src[i];
+// Copy of the twiddle table into LDS, in two halves so that the caller can
+// issue its own loads in between: every thread loads its (at most P) entries
+// at once, then stores them.  The blocks hold at least L/P threads, so P
+// entries per thread cover the table.
+template <int L, int P>
+__device__ __forceinline__ void load_twiddles(float2 (&w)[P], const float2* __restrict__ src, int tid, int nthr) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const int i = tid + k * nthr;
+        w[k] = i < L ? src[i] : make_float2(0.f, 0.f);
+    }
+}
+template <int L, int P>
+__device__ __forceinline__ const float2* store_twiddles(float2* dst, const float2 (&w)[P], int tid, int nthr) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const int i = tid + k * nthr;
+        if (i < L) dst[i] = w[k];
+    }
     return dst;
 }
 
@@ -100,18 +114,27 @@ __device__ __noinline__ float2 eval_general(const DevOp& op, float q2, float iqx
 
 // sum_m coef (q^2)^a |q|^-b (i qx)^cx (i qy)^cy (i qz)^cz: Horner over the
 // pure q^2 part, then the listed general monomials (none for most models)
+// GEN = false: the plan has no general monomials (DevPlan::general), and the
+// kernel is built without the out-of-line call, which would split the
+// unrolled mode loops into separately scheduled pieces
+template <bool GEN>
 __device__ __forceinline__ float2 eval_op(const DevOp& op, const ModeQ& q) {
     float re = op.poly[PSS_MAXPOW];
 #pragma unroll
     for (int j = PSS_MAXPOW - 1; j >= 0; --j) re = fmaf(re, q.q2, op.poly[j]);
-    if (op.n == 0) return make_float2(re, 0.f);
-    const float2 g = eval_general(op, q.q2, q.iq[0], q.iq[1], q.iq[2]);
-    return make_float2(re + g.x, g.y);
+    if constexpr (GEN) {
+        if (op.n != 0) {
+            const float2 g = eval_general(op, q.q2, q.iq[0], q.iq[1], q.iq[2]);
+            return make_float2(re + g.x, g.y);
+        }
+    }
+    return make_float2(re, 0.f);
 }
 
 // 1 / (1 - dt L(q))
+template <bool GEN>
 __device__ __forceinline__ float2 implicit_inv(const DevPlan& p, int f, const ModeQ& q) {
-    const float2 L = eval_op(p.implicit_op[f], q);
+    const float2 L = eval_op<GEN>(p.implicit_op[f], q);
     const float ar = 1.f - p.dt * L.x, ai = -p.dt * L.y;
     const float d = 1.f / (ar * ar + ai * ai);
     return make_float2(ar * d, -ai * d);
@@ -132,9 +155,10 @@ __device__ __forceinline__ bool mask_keep(const DevMask& mk, int kx, int ky, int
 
 // Scaled unit white noise sigma(q) xi_hat(k) of field f at step `step` for a
 // mode with full-spectrum linear index lin and negative-mode index lneg.
+template <bool GEN>
 __device__ __forceinline__ float2 noise_mode(const DevPlan& p, int f, uint32_t step, uint32_t lin,
                                              uint32_t lneg, const ModeQ& q) {
-    const float D = eval_op(p.noise_op[f], q).x;
+    const float D = eval_op<GEN>(p.noise_op[f], q).x;
     const uint32_t c = lin < lneg ? lin : lneg;
     const uint4 w = philox4x32_10(make_uint4(c, step, static_cast<uint32_t>(f), 0u), p.key0, p.key1);
     const float2 g = box_muller(w.x, w.y);
@@ -258,16 +282,16 @@ __device__ __forceinline__ void pair_modes(int ky_l, int u, int L, int& ky, int&
 }
 
 // op applied to a pair slot (re: kx = 0 mode, im: kx = -Nx/2 mode)
-template <int DIM>
+template <int DIM, bool GEN>
 __device__ __forceinline__ float2 pair_op_d(const DevPlan& p, const DevOp& op, int ky_l, int u, int L, float2 a) {
     int ky, kz;
     pair_modes<DIM>(ky_l, u, L, ky, kz);
-    return make_float2(eval_op(op, mode_q(p, 0, ky, kz)).x * a.x,
-                       eval_op(op, mode_q(p, -(p.n[0] >> 1), ky, kz)).x * a.y);
+    return make_float2(eval_op<GEN>(op, mode_q(p, 0, ky, kz)).x * a.x,
+                       eval_op<GEN>(op, mode_q(p, -(p.n[0] >> 1), ky, kz)).x * a.y);
 }
 
 // semi-implicit update of a pair slot
-template <int DIM>
+template <int DIM, bool GEN>
 __device__ __forceinline__ float2 pair_update_d(const DevPlan& p, int f, uint32_t step, int ky_l, int u, int L,
                                                 float2 old, float2 acc, bool noisy) {
     int ky, kz;
@@ -278,14 +302,14 @@ __device__ __forceinline__ float2 pair_update_d(const DevPlan& p, int f, uint32_
     if (noisy) {
         uint32_t lin, lneg;
         mode_lin(p, 0, ky, kz, lin, lneg);
-        r.x += noise_mode(p, f, step, lin, lneg, q0).x;
+        r.x += noise_mode<GEN>(p, f, step, lin, lneg, q0).x;
         mode_lin(p, kn, ky, kz, lin, lneg);
-        r.y += noise_mode(p, f, step, lin, lneg, qn).x;
+        r.y += noise_mode<GEN>(p, f, step, lin, lneg, qn).x;
     }
-    return make_float2(r.x * implicit_inv(p, f, q0).x, r.y * implicit_inv(p, f, qn).x);
+    return make_float2(r.x * implicit_inv<GEN>(p, f, q0).x, r.y * implicit_inv<GEN>(p, f, qn).x);
 }
 
-template <int L, int P, int NF, int MODE, int DIM>
+template <int L, int P, int NF, int MODE, int DIM, bool GEN>
 __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ members,
                                                       const DevPlan* __restrict__ plans,
                                                       const DevPlan* __restrict__ plan_a, Bufs bufs_a, Geo geo,
@@ -321,7 +345,10 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
     const size_t vstride = DIM == 2 ? static_cast<size_t>(tc) : static_cast<size_t>(ntile) * ny * tc;
     float2* line = smem + (lo * tc + cc) * lds_fft(L);
     float2* xbuf = smem + tc * to * lds_fft(L);  // packed-line exchange
-    const float2* tw = stage_twiddles<L>(xbuf + L, tw_g, tid, tc * to * T);
+    // twiddles: loaded now, stored to LDS after each mode's first loads
+    float2 twr[P];
+    load_twiddles<L, P>(twr, tw_g, tid, tc * to * T);
+    const float2* tw = xbuf + L;
     // block holds a packed line (block-uniform); this thread is on it
     const bool blk_packed = ct == 0 && (DIM == 2 || og * to == 0 || og * to == (ny >> 1));
     const bool packed = blk_packed && cc == 0 && lo == 0;
@@ -364,21 +391,23 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
         // forward transform of an array in the state layout, stored as the state
         float2 v[P];
 #pragma unroll
-        for (int m = 0; m < P; ++m) v[m] = bufs.in[base + (t + m * T) * tc];
+        for (int m = 0; m < P; ++m) v[m] = gload(bufs.in + base + (t + m * T) * tc);
+        store_twiddles<L, P>(xbuf + L, twr, tid, tc * to * T);
         fft_line<L, P, -1>(v, line, t, tw);
         exchange(v, true);
 #pragma unroll
-        for (int m = 0; m < P; ++m) bufs.S[bufs.sel][base + (t + m * T) * tc] = v[m];
+        for (int m = 0; m < P; ++m) gstore(bufs.S[bufs.sel] + base + (t + m * T) * tc, v[m]);
         return;
     }
     if constexpr (MODE == MODE_INV_OUT) {
         float2 v[P];
 #pragma unroll
-        for (int m = 0; m < P; ++m) v[m] = bufs.S[bufs.sel][base + (t + m * T) * tc];
+        for (int m = 0; m < P; ++m) v[m] = gload(bufs.S[bufs.sel] + base + (t + m * T) * tc);
+        store_twiddles<L, P>(xbuf + L, twr, tid, tc * to * T);
         exchange(v, false);
         fft_line<L, P, 1>(v, line, t, tw);
 #pragma unroll
-        for (int m = 0; m < P; ++m) bufs.out[vbase + (t + m * T) * vstride] = v[m];
+        for (int m = 0; m < P; ++m) gstore(bufs.out + vbase + (t + m * T) * vstride, v[m]);
         return;
     }
 
@@ -388,15 +417,23 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
     for (int f = 0; f < NF; ++f) {
         if (f < nf) {
 #pragma unroll
-            for (int m = 0; m < P; ++m) s[f][m] = bufs.S[f][base + (t + m * T) * tc];
+            for (int m = 0; m < P; ++m) s[f][m] = gload(bufs.S[f] + base + (t + m * T) * tc);
         } else {
 #pragma unroll
             for (int m = 0; m < P; ++m) s[f][m] = make_float2(0.f, 0.f);
         }
     }
 
+    if constexpr (MODE == MODE_PROLOGUE) store_twiddles<L, P>(xbuf + L, twr, tid, tc * to * T);
     if constexpr (MODE == MODE_STEP) {
-        const uint32_t step = static_cast<uint32_t>(*step_ctr) + static_cast<uint32_t>(step_off);
+        const uint32_t step = static_cast<uint32_t>(gload_u64(step_ctr)) + static_cast<uint32_t>(step_off);
+        // the first channel's loads go out before the twiddles are stored
+        float2 nxt[P];
+        if (p.nch > 0) {
+#pragma unroll
+            for (int m = 0; m < P; ++m) nxt[m] = gload(bufs.N[0] + base + (t + m * T) * tc);
+        }
+        store_twiddles<L, P>(xbuf + L, twr, tid, tc * to * T);
         float2 acc[NF][P];  // explicit contributions
 #pragma unroll
         for (int f = 0; f < NF; ++f)
@@ -407,7 +444,11 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
             const DevChannel& C = p.ch[ch];
             float2 v[P];
 #pragma unroll
-            for (int m = 0; m < P; ++m) v[m] = bufs.N[ch][base + (t + m * T) * tc];
+            for (int m = 0; m < P; ++m) v[m] = nxt[m];
+            if (ch + 1 < p.nch) {
+#pragma unroll
+                for (int m = 0; m < P; ++m) nxt[m] = gload(bufs.N[ch + 1] + base + (t + m * T) * tc);
+            }
             fft_line<L, P, -1>(v, line, t, tw);
             exchange(v, true);
 #pragma unroll
@@ -415,12 +456,12 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
                 int kx, ky, kz;
                 bool pair;
                 slot_mode<DIM>(packed, kx_l, ky_l, t + m * T, L, nx, kx, ky, kz, pair);
-                if (!pair) add_to(acc, C.target, m, cmul(eval_op(C.op, mode_q(p, kx, ky, kz)), v[m]));
+                if (!pair) add_to(acc, C.target, m, cmul(eval_op<GEN>(C.op, mode_q(p, kx, ky, kz)), v[m]));
             }
             if (packed && t == 0) {
                 // slots 0 and L/2: two real modes (operators are real on them)
-                add_to(acc, C.target, 0, pair_op_d<DIM>(p, C.op, ky_l, 0, L, v[0]));
-                add_to(acc, C.target, P / 2, pair_op_d<DIM>(p, C.op, ky_l, L >> 1, L, v[P / 2]));
+                add_to(acc, C.target, 0, pair_op_d<DIM, GEN>(p, C.op, ky_l, 0, L, v[0]));
+                add_to(acc, C.target, P / 2, pair_op_d<DIM, GEN>(p, C.op, ky_l, L >> 1, L, v[P / 2]));
             }
         }
         // Fourier-space terms with a single linear factor
@@ -431,11 +472,11 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
                 int kx, ky, kz;
                 bool pair;
                 slot_mode<DIM>(packed, kx_l, ky_l, t + m * T, L, nx, kx, ky, kz, pair);
-                if (!pair) add_to(acc, Dd.target, m, cmul(eval_op(Dd.op, mode_q(p, kx, ky, kz)), pick(s, Dd.src, m)));
+                if (!pair) add_to(acc, Dd.target, m, cmul(eval_op<GEN>(Dd.op, mode_q(p, kx, ky, kz)), pick(s, Dd.src, m)));
             }
             if (packed && t == 0) {
-                add_to(acc, Dd.target, 0, pair_op_d<DIM>(p, Dd.op, ky_l, 0, L, pick(s, Dd.src, 0)));
-                add_to(acc, Dd.target, P / 2, pair_op_d<DIM>(p, Dd.op, ky_l, L >> 1, L, pick(s, Dd.src, P / 2)));
+                add_to(acc, Dd.target, 0, pair_op_d<DIM, GEN>(p, Dd.op, ky_l, 0, L, pick(s, Dd.src, 0)));
+                add_to(acc, Dd.target, P / 2, pair_op_d<DIM, GEN>(p, Dd.op, ky_l, L >> 1, L, pick(s, Dd.src, P / 2)));
             }
         }
         // semi-implicit update (eq:timeupdate) with in-register noise
@@ -455,17 +496,17 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
                 if (noisy) {
                     uint32_t lin, lneg;
                     mode_lin(p, kx, ky, kz, lin, lneg);
-                    r = cadd(r, noise_mode(p, f, step, lin, lneg, q));
+                    r = cadd(r, noise_mode<GEN>(p, f, step, lin, lneg, q));
                 }
-                s[f][m] = cmul(r, implicit_inv(p, f, q));
+                s[f][m] = cmul(r, implicit_inv<GEN>(p, f, q));
             }
             if (packed && t == 0) {
                 // slots 0 and L/2 hold two real modes each
-                s[f][0] = pair_update_d<DIM>(p, f, step, ky_l, 0, L, old0, acc[f][0], noisy);
-                s[f][P / 2] = pair_update_d<DIM>(p, f, step, ky_l, L >> 1, L, oldh, acc[f][P / 2], noisy);
+                s[f][0] = pair_update_d<DIM, GEN>(p, f, step, ky_l, 0, L, old0, acc[f][0], noisy);
+                s[f][P / 2] = pair_update_d<DIM, GEN>(p, f, step, ky_l, L >> 1, L, oldh, acc[f][P / 2], noisy);
             }
 #pragma unroll
-            for (int m = 0; m < P; ++m) bufs.S[f][base + (t + m * T) * tc] = s[f][m];
+            for (int m = 0; m < P; ++m) gstore(bufs.S[f] + base + (t + m * T) * tc, s[f][m]);
         }
     }
 
@@ -491,7 +532,7 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
         exchange(v, false);
         fft_line<L, P, 1>(v, line, t, tw);
 #pragma unroll
-        for (int m = 0; m < P; ++m) bufs.V[g][vbase + (t + m * T) * vstride] = v[m];
+        for (int m = 0; m < P; ++m) gstore(bufs.V[g] + vbase + (t + m * T) * vstride, v[m]);
     }
 }
 
@@ -517,7 +558,9 @@ __global__ void __launch_bounds__(256) adjcol_kernel(AdjArgs aa, Geo geo, const 
     const size_t base = static_cast<size_t>(ct) * L * tc + cc;
     float2* line = smem + cc * lds_fft(L);
     float2* xbuf = smem + tc * lds_fft(L);
-    const float2* tw = stage_twiddles<L>(xbuf + L, tw_g, tid, tc * T);
+    float2 twr[P];
+    load_twiddles<L, P>(twr, tw_g, tid, tc * T);
+    const float2* tw = xbuf + L;
     const bool blk_packed = ct == 0;
     const bool packed = blk_packed && cc == 0;
     const DevMask& mk = p.mask[0];
@@ -545,10 +588,12 @@ __global__ void __launch_bounds__(256) adjcol_kernel(AdjArgs aa, Geo geo, const 
     if (aa.first) {
 #pragma unroll
         for (int m = 0; m < P; ++m) g[m] = aa.G[base + (t + m * T) * tc];
+        store_twiddles<L, P>(xbuf + L, twr, tid, tc * T);
     } else {
         float2 v[P];
 #pragma unroll
         for (int m = 0; m < P; ++m) v[m] = aa.X[base + (t + m * T) * tc];
+        store_twiddles<L, P>(xbuf + L, twr, tid, tc * T);
         fft_line<L, P, -1>(v, line, t, tw);
         exchange(v, true);
 #pragma unroll
@@ -595,7 +640,7 @@ __global__ void __launch_bounds__(256) adjcol_kernel(AdjArgs aa, Geo geo, const 
             if (noisy) {
                 uint32_t lin, lneg;
                 mode_lin(p, kx, ky, 0, lin, lneg);
-                const float2 eta = noise_mode(p, 0, aa.step, lin, lneg, q);
+                const float2 eta = noise_mode<false>(p, 0, aa.step, lin, lneg, q);
                 part[2] += 2.0 * (static_cast<double>(r.x) * eta.x + static_cast<double>(r.y) * eta.y);
             }
             wr[m] = cscale(r, -dt * q.q2);
@@ -611,9 +656,9 @@ __global__ void __launch_bounds__(256) adjcol_kernel(AdjArgs aa, Geo geo, const 
             if (noisy) {
                 uint32_t lin, lneg;
                 mode_lin(p, 0, ky, 0, lin, lneg);
-                const float eta0 = noise_mode(p, 0, aa.step, lin, lneg, q0).x;
+                const float eta0 = noise_mode<false>(p, 0, aa.step, lin, lneg, q0).x;
                 mode_lin(p, kn, ky, 0, lin, lneg);
-                const float etan = noise_mode(p, 0, aa.step, lin, lneg, qn).x;
+                const float etan = noise_mode<false>(p, 0, aa.step, lin, lneg, qn).x;
                 part[2] += static_cast<double>(r.x) * eta0 + static_cast<double>(r.y) * etan;
             }
             wr[m] = make_float2(-dt * q0.q2 * r.x, -dt * qn.q2 * r.y);
@@ -698,7 +743,9 @@ __global__ void __launch_bounds__(256) ypass_kernel(YArgs ya, Geo geo, const flo
     const int c = ct * tc + cc;
     float2* line = smem + (lz * tc + cc) * lds_fft(L);
     float2* xb = smem + tc * tz * lds_fft(L) + lz * L;  // column-0 exchange, one line per z
-    const float2* tw = stage_twiddles<L>(smem + tc * tz * lds_fft(L) + tz * L, tw_g, tid, tc * tz * T);
+    float2 twr[P];
+    load_twiddles<L, P>(twr, tw_g, tid, tc * tz * T);
+    const float2* tw = store_twiddles<L, P>(smem + tc * tz * lds_fft(L) + tz * L, twr, tid, tc * tz * T);
     const size_t ibase = (static_cast<size_t>(z) * ntile + ct) * L * tc + cc;
     const size_t obase = MODE == MODE_YFWD ? (static_cast<size_t>(ct) * nz + z) * tc + cc : ibase;
     const size_t ostride = MODE == MODE_YFWD ? static_cast<size_t>(ntile) * nz * tc : static_cast<size_t>(tc);
@@ -781,7 +828,11 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
     const int y0 = r0 - zr * ny;     // first y of the block
     const int lt = geo.tc_log2;
     float2* line = smem + pr * lds_fft(L);
-    const float2* tw = stage_twiddles<L>(smem + (rb / 2) * lds_fft(L), tw_g, tid, nthr);
+    // twiddles: loaded now, stored to LDS after each mode's first loads
+    float2 twr[P];
+    load_twiddles<L, P>(twr, tw_g, tid, nthr);
+    float2* const twl = smem + (rb / 2) * lds_fft(L);
+    const float2* tw = twl;
 
     // Gather the packed complex input Z[k] = X_row0[k] + i X_row1[k] of pair
     // pr straight from the packed-column array (columns [0, ncol) are stored;
@@ -796,8 +847,8 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
             float2 a = make_float2(0.f, 0.f), b = a;
             if (kk < ncol) {
                 const size_t off = row0 + (kk >> lt) * tstride + (kk & (tc - 1));
-                a = src[off];
-                b = src[off + tc];
+                a = gload(src + off);
+                b = gload(src + off + tc);
             }
             float2 z;
             if (k == 0) {
@@ -828,7 +879,7 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
                 o = (r & 1) ? make_float2(0.5f * (a.y + b.y), 0.5f * (b.x - a.x))
                             : make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
             }
-            dst[((static_cast<size_t>(zr) * ntile + tl) * ny + y0 + r) * tc + cc] = o;
+            gstore(dst + ((static_cast<size_t>(zr) * ntile + tl) * ny + y0 + r) * tc + cc, o);
         }
     };
 
@@ -842,6 +893,7 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
             v[m] = make_float2(src[static_cast<size_t>(r0 + 2 * pr) * L + x],
                                src[static_cast<size_t>(r0 + 2 * pr + 1) * L + x]);
         }
+        store_twiddles<L, P>(twl, twr, tid, nthr);
         fft_line<L, P, -1>(v, line, t, tw);
 #pragma unroll
         for (int m = 0; m < P; ++m) line[lds_pad(t + m * T)] = v[m];
@@ -852,6 +904,7 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
     if constexpr (MODE == MODE_C2R_OUT) {
         float2 v[P];
         build_z(v, bufs.in, NC);
+        store_twiddles<L, P>(twl, twr, tid, nthr);
         fft_line<L, P, 1>(v, line, t, tw);
         float* __restrict__ dst = bufs.real_out;
 #pragma unroll
@@ -871,8 +924,9 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
         // <r, -dt q^2 F[u^3]> = dL/db of the step, by Parseval
         float2 u[P], w[P];
         build_z(u, bufs.V[0], p.mask[0].ncol);
-        fft_line<L, P, 1>(u, line, t, tw);
         build_z(w, bufs.V[1], p.mask[1].ncol);
+        store_twiddles<L, P>(twl, twr, tid, nthr);
+        fft_line<L, P, 1>(u, line, t, tw);
         fft_line<L, P, 1>(w, line, t, tw);
         double part[1] = {0.0};
 #pragma unroll
@@ -896,6 +950,7 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
     for (int g = 0; g < NG; ++g) {
         float2 v[P];
         build_z(v, bufs.V[g], p.mask[g].ncol);
+        if (g == 0) store_twiddles<L, P>(twl, twr, tid, nthr);
         fft_line<L, P, 1>(v, line, t, tw);
 #pragma unroll
         for (int m = 0; m < P; ++m) z[g][m] = cscale(v[m], p.inv_n);
@@ -1058,20 +1113,24 @@ static hipError_t launch_update_d(int mode, const LaunchArgs& a) {
     dim3 grid(a.geo.nublk, tab ? a.nmem : 1), block(threads);
     switch (mode) {
         case MODE_STEP:
-            hipLaunchKernelGGL((update_kernel<L, P, NF, MODE_STEP, DIM>), grid, block, lds, a.stream, a.members, a.plans,
-                               a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
+            if (a.general)
+                hipLaunchKernelGGL((update_kernel<L, P, NF, MODE_STEP, DIM, true>), grid, block, lds, a.stream,
+                                   a.members, a.plans, a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
+            else
+                hipLaunchKernelGGL((update_kernel<L, P, NF, MODE_STEP, DIM, false>), grid, block, lds, a.stream,
+                                   a.members, a.plans, a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
             break;
         case MODE_PROLOGUE:
-            hipLaunchKernelGGL((update_kernel<L, P, NF, MODE_PROLOGUE, DIM>), grid, block, lds, a.stream,
+            hipLaunchKernelGGL((update_kernel<L, P, NF, MODE_PROLOGUE, DIM, false>), grid, block, lds, a.stream,
                                a.members, a.plans, a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
             break;
         case MODE_FWD_STORE:
-            hipLaunchKernelGGL((update_kernel<L, P, 1, MODE_FWD_STORE, DIM>), grid, block, lds, a.stream,
+            hipLaunchKernelGGL((update_kernel<L, P, 1, MODE_FWD_STORE, DIM, false>), grid, block, lds, a.stream,
                                a.members, a.plans, a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
             break;
         case MODE_INV_OUT:
-            hipLaunchKernelGGL((update_kernel<L, P, 1, MODE_INV_OUT, DIM>), grid, block, lds, a.stream, a.members, a.plans,
-                               a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
+            hipLaunchKernelGGL((update_kernel<L, P, 1, MODE_INV_OUT, DIM, false>), grid, block, lds, a.stream,
+                               a.members, a.plans, a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
             break;
         default:
             return hipErrorInvalidValue;

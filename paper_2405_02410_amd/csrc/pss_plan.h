@@ -94,6 +94,7 @@ struct DevPlan {
     DevOp noise_op[PSS_MAXF];
     DevDirect direct[PSS_MAXD];
     DevChannel ch[PSS_MAXCH];
+    int32_t general;  // some operator has 1/|q| or i q_i monomials (general list)
 };
 
 }  // namespace pss

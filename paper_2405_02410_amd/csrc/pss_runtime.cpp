@@ -428,6 +428,11 @@ pss_status build_plan(pss_ctx* c) {
         t.mono0 = 0;
         ++C.nprod;
     }
+    // kernels without the general-monomial code unless some operator needs it
+    P.general = 0;
+    for (int f = 0; f < nf; ++f) P.general |= (P.implicit_op[f].n > 0) | (P.noise_op[f].n > 0);
+    for (int d = 0; d < P.nd; ++d) P.general |= P.direct[d].op.n > 0;
+    for (int k = 0; k < P.nch; ++k) P.general |= P.ch[k].op.n > 0;
     return PSS_OK;
 }
 
@@ -559,6 +564,7 @@ pss::LaunchArgs args(pss_ctx* c, int step_off = 0) {
     a.members = c->d_member_u;
     a.plans = c->d_plan;
     a.nmem = 1;
+    a.general = c->plan.general != 0;
     a.step_off = step_off;
     a.tw_u = c->d_tw_u;
     a.tw_x = c->d_tw_x;
@@ -777,7 +783,7 @@ constexpr int64_t kGraphSteps = 50;
 
 bool same_class(const pss_ctx* a, const pss_ctx* b) {
     return a->n[0] == b->n[0] && a->n[1] == b->n[1] && a->fields.size() == b->fields.size() &&
-           a->plan.ng == b->plan.ng && a->plan.nch == b->plan.nch &&
+           a->plan.ng == b->plan.ng && a->plan.nch == b->plan.nch && a->plan.general == b->plan.general &&
            std::memcmp(&a->geo, &b->geo, sizeof(pss::Geo)) == 0;
 }
 
