@@ -33,11 +33,10 @@ namespace pss {
 // entries per thread cover the table.
 template <int L, int P>
 __device__ __forceinline__ void load_twiddles(float2 (&w)[P], const float2* __restrict__ src, int tid, int nthr) {
+    // unconditional loads (the index wraps, L is a power of two) keep the
+    // memory counter exact for the loads the caller issues next
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        const int i = tid + k * nthr;
-        w[k] = i < L ? src[i] : make_float2(0.f, 0.f);
-    }
+    for (int k = 0; k < P; ++k) w[k] = src[(tid + k * nthr) & (L - 1)];
 }
 template <int L, int P>
 __device__ __forceinline__ const float2* store_twiddles(float2* dst, const float2 (&w)[P], int tid, int nthr) {
