@@ -839,23 +839,31 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
     const size_t row0 = (static_cast<size_t>(zr) * ntile * ny + y0 + 2 * pr) * tc;
     const size_t tstride = static_cast<size_t>(ny) * tc;  // one column tile
     auto build_z = [&](float2 (&v)[P], const float2* __restrict__ src, int ncol) {
+        // all loads first, without control flow between them; a dropped
+        // column reads column 0 and then counts as zero
+        float2 a[P], b[P];
 #pragma unroll
         for (int m = 0; m < P; ++m) {
             const int k = t + m * T;
             const int kk = (k == NC) ? 0 : (k < NC ? k : L - k);
-            float2 a = make_float2(0.f, 0.f), b = a;
-            if (kk < ncol) {
-                const size_t off = row0 + (kk >> lt) * tstride + (kk & (tc - 1));
-                a = gload(src + off);
-                b = gload(src + off + tc);
-            }
+            const int kc = kk < ncol ? kk : 0;
+            const size_t off = row0 + (kc >> lt) * tstride + (kc & (tc - 1));
+            a[m] = gload(src + off);
+            b[m] = gload(src + off + tc);
+        }
+#pragma unroll
+        for (int m = 0; m < P; ++m) {
+            const int k = t + m * T;
+            const int kk = (k == NC) ? 0 : (k < NC ? k : L - k);
+            const float2 zero = make_float2(0.f, 0.f);
+            const float2 am = kk < ncol ? a[m] : zero, bm = kk < ncol ? b[m] : zero;
             float2 z;
             if (k == 0) {
-                z = make_float2(a.x, b.x);
+                z = make_float2(am.x, bm.x);
             } else if (k == NC) {
-                z = make_float2(a.y, b.y);
+                z = make_float2(am.y, bm.y);
             } else {
-                z = k < NC ? make_float2(a.x - b.y, a.y + b.x) : make_float2(a.x + b.y, b.x - a.y);
+                z = k < NC ? make_float2(am.x - bm.y, am.y + bm.x) : make_float2(am.x + bm.y, bm.x - am.y);
             }
             v[m] = z;
         }
@@ -961,16 +969,21 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
 #pragma unroll
         for (int m = 0; m < P; ++m) w[m] = make_float2(0.f, 0.f);
         for (int k = 0; k < C.nprod; ++k) {
-            const DevProd pd = C.prod[k];
+            const DevProd& pd = C.prod[k];
+            // the factor powers read as one 32-bit word (a scalar load)
+            static_assert(sizeof(pd.pow) == 4, "four factor slots");
+            const uint32_t pw = *reinterpret_cast<const uint32_t*>(pd.pow);
 #pragma unroll
             for (int m = 0; m < P; ++m) {
                 float a = pd.coef, b = pd.coef;
 #pragma unroll
-                for (int g = 0; g < NG; ++g)
-                    for (int e = 0; e < pd.pow[g]; ++e) {
+                for (int g = 0; g < NG; ++g) {
+                    const int pg = static_cast<int>((pw >> (8 * g)) & 0xffu);
+                    for (int e = 0; e < pg; ++e) {
                         a *= z[g][m].x;
                         b *= z[g][m].y;
                     }
+                }
                 w[m].x += a;
                 w[m].y += b;
             }
