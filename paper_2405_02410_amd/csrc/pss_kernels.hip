@@ -972,7 +972,8 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
             const DevProd& pd = C.prod[k];
             // the factor powers read as one 32-bit word (a scalar load)
             static_assert(sizeof(pd.pow) == 4, "four factor slots");
-            const uint32_t pw = *reinterpret_cast<const uint32_t*>(pd.pow);
+            uint32_t pw;
+            __builtin_memcpy(&pw, pd.pow, sizeof(pw));
 #pragma unroll
             for (int m = 0; m < P; ++m) {
                 float a = pd.coef, b = pd.coef;
