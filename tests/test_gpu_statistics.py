@@ -1,0 +1,66 @@
+"""Statistical parity of long Model B coarsening runs (256x256, up to 5000 steps).
+
+FP32 and FP64 trajectories separate in the linearly unstable band long before
+t = 50, so long runs are compared as ensembles, not pointwise: 8 GPU
+realisations (seeds 101..108, independent of the oracle's) against the FP64
+oracle's 8 realisations (seeds 1..8) stored in tests/golden/sq_stats_256.json
+by tests/golden/make_sq_stats_256.py.  At t = 10, 20 and 50 the shell-averaged
+structure factor S_j and the domain length L must agree within 4 combined
+standard errors, in at least 99% of the shells and in L.  For a correct
+integrator a shell fails by chance with probability about 6e-5.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs an MI355X")]
+
+import paper_2405_02410_amd as pss  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sq_stats_256.json")
+GPU_SEEDS = tuple(range(101, 109))
+
+
+def _domain_length(S, nj, n, dx=1.0):
+    j = np.arange(1, len(S) + 1)
+    qj = 2 * np.pi * j / (n * dx)
+    return float(2 * np.pi * np.sum(nj * S) / np.sum(nj * qj * S))
+
+
+def test_coarsening_statistics_match_the_oracle():
+    with open(GOLDEN) as f:
+        ref = json.load(f)
+    n = tuple(ref["lattice"])
+    c = ref["coef"]
+    snaps = ref["snapshots"]
+    S = np.zeros((len(snaps), len(GPU_SEEDS), n[0] // 2 - 1))
+    L = np.zeros((len(snaps), len(GPU_SEEDS)))
+    for r, seed in enumerate(GPU_SEEDS):
+        lat = pss.Lattice(n, dt=ref["dt"], seed=seed)
+        f, _ = pss.model_b(lat, a=c["a"], b=c["b"], k=c["k"], D=c["D"])
+        lat.init_uniform(f, -0.1, 0.1)
+        done = 0
+        for i, sn in enumerate(snaps):
+            lat.step(sn["step"] - done)
+            done = sn["step"]
+            s, cnt = lat.structure_factor(f)
+            assert np.array_equal(cnt, sn["n_j"])
+            S[i, r] = s
+            L[i, r] = _domain_length(s, cnt, n[0])
+    k = len(GPU_SEEDS)
+    for i, sn in enumerate(snaps):
+        mg, sg = S[i].mean(axis=0), S[i].std(axis=0, ddof=1) / np.sqrt(k)
+        mo, so = np.asarray(sn["S_mean"]), np.asarray(sn["S_se"])
+        z = np.abs(mg - mo) / np.sqrt(sg ** 2 + so ** 2)
+        frac_ok = float(np.mean(z < 4.0))
+        zl = abs(L[i].mean() - sn["L_mean"]) / np.hypot(L[i].std(ddof=1) / np.sqrt(k), sn["L_se"])
+        print(f"t={sn['t']}: shells within 4 SE {frac_ok:.3f} (max z {z.max():.2f}); "
+              f"L gpu {L[i].mean():.3f} oracle {sn['L_mean']:.3f} (z {zl:.2f})", flush=True)
+        assert frac_ok >= 0.99, (sn["t"], frac_ok, int(np.argmax(z)) + 1, z.max())
+        assert zl < 4.0, (sn["t"], zl)

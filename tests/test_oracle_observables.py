@@ -34,3 +34,24 @@ def test_shell_populations():
     assert np.sum(j == 1) == 8
     _, nj = ob.shell_average(lat, np.ones(lat.shape))
     assert nj.sum() == np.sum((j >= 1) & (j < 16))
+
+
+def test_stored_coarsening_statistics_coarsen():
+    """The stored 256^2 oracle ensemble (tests/golden/make_sq_stats_256.py)
+    shows Model B coarsening: the domain length grows and the structure-factor
+    peak moves to smaller shells between t = 10, 20 and 50; the shell
+    populations are those of the 256^2 lattice."""
+    import json
+    import os
+    from oracle import observables as ob
+    from oracle.spectral import Lattice
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sq_stats_256.json")
+    with open(path) as f:
+        snaps = json.load(f)["snapshots"]
+    L = [s["L_mean"] for s in snaps]
+    peaks = [int(np.argmax(s["S_mean"])) for s in snaps]
+    assert all(b > a for a, b in zip(L, L[1:])), L
+    assert all(b < a for a, b in zip(peaks, peaks[1:])), peaks
+    _, nj = ob.shell_average(Lattice(256, 256), np.ones((256, 256)))
+    for s in snaps:
+        assert s["n_j"] == nj.tolist()
