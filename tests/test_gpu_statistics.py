@@ -1,17 +1,14 @@
-"""Statistical parity of long Model B coarsening runs (256x256, up to 5000 steps).
+"""Statistical parity of long Model B coarsening runs (256x256, up to 10000 steps).
 
 FP32 and FP64 trajectories separate in the linearly unstable band long before
-t = 50, so long runs are compared as ensembles, not pointwise: 8 GPU
-realisations (seeds 101..108, independent of the oracle's) against the FP64
-oracle's 8 realisations (seeds 1..8) stored in tests/golden/sq_stats_256.json
-by tests/golden/make_sq_stats_256.py.  At t = 10, 20 and 50 the shell-averaged
-structure factor S_j and the domain length L must agree within 4 combined
-standard errors, in at least 98% of the shells (all but 2 of 127) and in L.
-With 8 samples a side the per-shell statistic is heavy-tailed near the
-structure-factor peak: the oracle run with seeds 101..108 against the stored
-seeds 1..8 passes every shell at t = 10 and 20 but puts the peak shell (j = 21)
-at 5.4 standard errors at t = 50, with every other shell below 2.8.  A dropped
-term or a wrong coefficient shifts many shells by many standard errors.
+t = 50, so long runs are compared as ensembles, not pointwise: 16 GPU
+realisations (seeds 101..116, independent of the oracle's) against the FP64
+oracle's 16 realisations (seeds 1..16) stored in tests/golden/sq_stats_256.json
+by tests/golden/make_sq_stats_256.py.  At t = 10, 20, 50 and 100 the
+shell-averaged structure factor S_j and the domain length L must agree within
+4 combined standard errors, in at least 99% of the shells (all but one of
+127) and in L.  A dropped term or a wrong coefficient shifts many shells by
+many standard errors.
 """
 
 import json
@@ -28,7 +25,7 @@ pytestmark = [pytest.mark.gpu,
 import paper_2405_02410_amd as pss  # noqa: E402
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sq_stats_256.json")
-GPU_SEEDS = tuple(range(101, 109))
+GPU_SEEDS = tuple(range(101, 117))
 
 
 def _domain_length(S, nj, n, dx=1.0):
@@ -66,5 +63,5 @@ def test_coarsening_statistics_match_the_oracle():
         zl = abs(L[i].mean() - sn["L_mean"]) / np.hypot(L[i].std(ddof=1) / np.sqrt(k), sn["L_se"])
         print(f"t={sn['t']}: shells within 4 SE {frac_ok:.3f} (max z {z.max():.2f}); "
               f"L gpu {L[i].mean():.3f} oracle {sn['L_mean']:.3f} (z {zl:.2f})", flush=True)
-        assert frac_ok >= 0.98, (sn["t"], frac_ok, int(np.argmax(z)) + 1, z.max())
+        assert frac_ok >= 0.99, (sn["t"], frac_ok, int(np.argmax(z)) + 1, z.max())
         assert zl < 4.0, (sn["t"], zl)

@@ -39,7 +39,7 @@ def test_shell_populations():
 def test_stored_coarsening_statistics_coarsen():
     """The stored 256^2 oracle ensemble (tests/golden/make_sq_stats_256.py)
     shows Model B coarsening: the domain length grows and the structure-factor
-    peak moves to smaller shells between t = 10, 20 and 50; the shell
+    peak moves to smaller shells between t = 10, 20, 50 and 100; the shell
     populations are those of the 256^2 lattice."""
     import json
     import os
