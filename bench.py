@@ -4,15 +4,28 @@
 One "step" is one full time step of the pseudo-spectral integrator (forward
 and inverse transforms, real-space cubic, Philox noise, semi-implicit update)
 over the whole lattice.  Prints one JSON line with site-steps/s, the roofline
-position of the dominant kernel (the update kernel, HBM-bound) and the FP64
-CPU oracle timed on a bounded sample of the same workload.
+position of the dominant kernel (the update kernel, HBM-bound), the FP64 CPU
+oracle timed on a bounded sample of the same workload, and the two
+training-system workloads measured against their plain forms:
+
+* "ensemble": 256 x 128^2 + 64 x 256^2 + 16 x 512^2 independent lattices in
+  one batch, against the same lattices stepped one lattice per launch;
+* "adjoint": the gradient of a structure-factor loss through 2000 steps of
+  256^2 Model B (checkpoints every 45), against the forward run alone.
+
+Timing: the step graphs are built before any timed region (pss_step_prepare);
+the lattice runs on a torch stream, and HIP events recorded on that stream
+bracket each timed run of K steps, with a device synchronisation on both
+sides; `value` is the median of 5 such runs.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+       [--workload modelb1024|ensemble|adjoint|3d] [--no-extras]
 """
 
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -25,9 +38,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # this workload; its traffic figure is reported only while the kernel sources
 # and the launch geometry are the ones the counters were taken with.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_update_kernel_modelb_1024.txt")
-KERNEL_SOURCES = ("pss_kernels.hip", "pss_device.h", "pss_kernels.h", "pss_plan.h")
+KERNEL_SOURCES = ("pss_kernels.hip", "pss_device.h", "pss_fft.h", "pss_kernels.h", "pss_plan.h")
 N = (1024, 1024)
 A, B, K, D, DT, SEED = -1.0, 1.0, 1.0, 0.01, 0.01, 1
+REPEATS = 5
 
 
 def log(*a):
@@ -38,8 +52,10 @@ def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2405_02410_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        path = os.path.join(ROOT, "paper_2405_02410_amd", "csrc", name)
+        if os.path.exists(path):
+            with open(path, "rb") as f:
+                h.update(f.read())
     return h.hexdigest()
 
 
@@ -57,6 +73,22 @@ def measured_traffic(geometry):
     if kv.get("geometry") != json.dumps(geometry, sort_keys=True):
         return None
     return float(kv["traffic_bytes_per_launch"])
+
+
+def timed_runs(torch, stream, run, repeats=REPEATS):
+    """Seconds of each of `repeats` calls of run(), measured with HIP events on
+    `stream` and bracketed by device synchronisations."""
+    out = []
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1) * 1e-3)
+    return out
 
 
 def cpu_baseline(steps, steps_1core=5):
@@ -84,57 +116,24 @@ def cpu_baseline(steps, steps_1core=5):
             "single_core": {"value": one, "sample": f"{steps_1core} steps, scipy.fft with 1 worker"}}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--kernel-reps", type=int, default=2000)
-    ap.add_argument("--cpu-steps", type=int, default=40)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=("modelb1024", "ensemble", "adjoint", "3d"), default="modelb1024",
-                    help="modelb1024: one 1024^2 lattice (default); ensemble: 256x128^2 + 64x256^2 + "
-                         "16x512^2 independent lattices in one batch, also timed one lattice per launch; "
-                         "adjoint: gradient of the structure-factor loss through 2000 steps at 256^2; "
-                         "3d: the two-field 256^3 system (Model B phi coupled to Model A psi)")
-    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
-                    help="ensemble: keep the default launch geometry instead of pss_autotune's choice per size")
-    ap.add_argument("--copy-mib", type=int, default=0,
-                    help="after the run, copy a buffer of this many MiB three times with a plain device "
-                         "copy (a known-size reference for hardware byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the lattice is not sharded.",
-              file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    import paper_2405_02410_amd as pss
-    if not torch.cuda.is_available():
-        log("no GPU visible")
-        sys.exit(1)
-    torch.cuda.set_device(0)
-    if args.workload == "ensemble":
-        return ensemble(args, pss)
-    if args.workload == "adjoint":
-        return adjoint(args, pss)
-    if args.workload == "3d":
-        return three_d(args, pss)
-
+def modelb1024(args, pss, torch):
+    stream = torch.cuda.Stream()
     lat = pss.Lattice(N, dt=DT, seed=SEED)
+    lat.stream(stream.cuda_stream)
     f, _ = pss.model_b(lat, a=A, b=B, k=K, D=D)
     lat.init_uniform(f, -0.1, 0.1)
-    log(f"bench: 2D Model B {N[0]}x{N[1]}, warmup {args.warmup}, steps {args.steps}")
+    lat.prepare(args.warmup)
+    lat.prepare(args.steps)
+    log(f"bench: 2D Model B {N[0]}x{N[1]}, warmup {args.warmup}, {REPEATS} x {args.steps} steps")
     lat.step(args.warmup)
     lat.sync()
-    t0 = time.perf_counter()
-    lat.step(args.steps)
-    lat.sync()
-    el = time.perf_counter() - t0
+    times = timed_runs(torch, stream, lambda: lat.step(args.steps))
+    el = statistics.median(times)
     sites = N[0] * N[1]
     value = sites * args.steps / el
     ms_per_step = 1e3 * el / args.steps
-    log(f"bench: {ms_per_step * 1e3:.2f} us/step, {value:.4e} site-steps/s")
+    log(f"bench: {ms_per_step * 1e3:.2f} us/step (runs: {', '.join(f'{1e6 * t / args.steps:.2f}' for t in times)}), "
+        f"{value:.4e} site-steps/s")
     mass = lat.mass(f)
 
     # roofline of the dominant kernel: HIP events around back-to-back launches
@@ -149,37 +148,12 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(lat.geometry()),
                 "kernel": kname, "bytes_per_launch": kb, "us_per_launch": round(ms_k * 1e3, 3),
+                "x_kernel": {"kernel": xname, "bytes_per_launch": xb, "us_per_launch": round(ms_x * 1e3, 3),
+                             "frac": round(xb / (ms_x * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
                 "step_bytes": step_bytes,
                 "step_GBs": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1)}
-
-    if args.copy_mib > 0:
-        nbytes = args.copy_mib << 20
-        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"bench: copied {args.copy_mib} MiB three times")
-        del src, dst
-
-    cpu = None
-    if not args.no_cpu:
-        log(f"bench: timing the oracle on {args.cpu_steps} steps")
-        cpu = cpu_baseline(args.cpu_steps)
-
-    out = {
-        "metric": "site-steps/s", "value": value, "unit": "site-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "2D Model B 1024x1024 FP32, a=-1 b=1 k=1, conserved noise D=0.01 q^2, "
-                               "dt=0.01, 2/3 radial de-aliasing, uniform[-0.1,0.1] initial field, seed 1",
-                   "lattice": list(N), "parallelism": "single GPU"},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "mass_after": mass,
-    }
-    print(json.dumps(out), flush=True)
+    return {"value": value, "ms_per_step": ms_per_step, "runs_ms_per_step": [1e3 * t / args.steps for t in times],
+            "roofline": roofline, "mass_after": mass, "geometry": lat.geometry()}
 
 
 ENSEMBLE = ((256, 128), (64, 256), (16, 512))  # (members, side)
@@ -203,56 +177,67 @@ def ensemble_cpu_baseline(steps):
                       f"site-step rate carries over to the whole ensemble"}
 
 
-def ensemble(args, pss):
-    """Batched ensemble: every member in one batch (one update and one x launch
-    per size class and step) against the same members stepped one lattice per
-    launch sequence (pss_step on each, each on its own stream)."""
-    def build():
-        lats, seed = [], 1000
-        for count, side in ENSEMBLE:
-            for _ in range(count):
-                lat = pss.Lattice((side, side), dt=DT, seed=seed)
-                f, _ = pss.model_b(lat, a=A, b=B, k=K, D=D)
-                if args.autotune:
-                    lat.autotune(reps=20)  # measured once per size, then cached
-                lat.init_uniform(f, -0.1, 0.1)
-                lats.append(lat)
-                seed += 1
-        return lats
-    lats = build()
+def ensemble(args, pss, torch, steps):
+    """Batched ensemble: every member in one batch against the same members
+    stepped one lattice per launch sequence (pss_step on each, each on its own
+    stream).  Both forms replay graphs built before the timed region."""
+    lats, seed = [], 1000
+    for count, side in ENSEMBLE:
+        for _ in range(count):
+            lat = pss.Lattice((side, side), dt=DT, seed=seed)
+            f, _ = pss.model_b(lat, a=A, b=B, k=K, D=D)
+            if args.autotune:
+                lat.autotune(reps=20)  # measured once per size, then cached
+            lat.init_uniform(f, -0.1, 0.1)
+            lats.append(lat)
+            seed += 1
     sites = sum(c * s * s for c, s in ENSEMBLE)
     batch = pss.Batch(lats)
-    log(f"bench: ensemble of {len(lats)} lattices, {sites} sites, {batch.classes()[0]} classes")
-    batch.step(args.warmup)
+    ncls = batch.classes()[0]
+    log(f"bench: ensemble of {len(lats)} lattices, {sites} sites, {ncls} classes")
+    batch.step(steps)  # warm-up; builds the graphs of this chunk length
     batch.sync()
-    t0 = time.perf_counter()
-    batch.step(args.steps)
-    batch.sync()
-    el = time.perf_counter() - t0
-    value = sites * args.steps / el
-    ms_per_step = 1e3 * el / args.steps
-    log(f"bench: batched {ms_per_step * 1e3:.1f} us/step, {value:.4e} site-steps/s")
 
-    # one lattice per launch sequence: the same members, pss_step on each
-    plain_steps = max(1, args.steps // 10)
+    def run_batch():
+        batch.step(steps)
+        batch.sync()
+
+    def wall(run):
+        out = []
+        for _ in range(REPEATS):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run()
+            torch.cuda.synchronize()
+            out.append(time.perf_counter() - t0)
+        return out
+    tb = wall(run_batch)
+    el = statistics.median(tb)
+    value = sites * steps / el
+    log(f"bench: batched {1e6 * el / steps:.1f} us/step, {value:.4e} site-steps/s")
+
+    plain_steps = steps
     for lat in lats:
-        lat.step(args.warmup)
+        lat.prepare(plain_steps)
+        lat.step(plain_steps)  # warm-up
     for lat in lats:
         lat.sync()
-    t0 = time.perf_counter()
-    for lat in lats:
-        lat.step(plain_steps)
-    for lat in lats:
-        lat.sync()
-    pel = time.perf_counter() - t0
+
+    def run_plain():
+        for lat in lats:
+            lat.step(plain_steps)
+        for lat in lats:
+            lat.sync()
+    tp = wall(run_plain)
+    pel = statistics.median(tp)
     plain = sites * plain_steps / pel
     log(f"bench: plain {1e6 * pel / plain_steps:.1f} us/step, {plain:.4e} site-steps/s")
 
     # roofline of the kernel with the largest share of the batched step
     best = None
-    for cls in range(batch.classes()[0]):
+    for cls in range(ncls):
         for which in (pss.KERNEL_UPDATE, pss.KERNEL_X):
-            ms, nbytes = batch.time_kernel(cls, which, args.kernel_reps)
+            ms, nbytes = batch.time_kernel(cls, which, max(50, args.kernel_reps // 10))
             log(f"bench: class {cls} kernel {which}: {ms * 1e3:.2f} us/launch, {nbytes / 1e6:.2f} MB")
             if best is None or ms > best[0]:
                 best = (ms, nbytes, cls, which)
@@ -262,31 +247,19 @@ def ensemble(args, pss):
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "kernel": f"{'update_kernel' if which == 0 else 'xrow_kernel'} (batched, size class {cls})",
                 "bytes_per_launch": nbytes, "us_per_launch": round(ms * 1e3, 3)}
-    cpu = None
-    if not args.no_cpu:
-        log("bench: timing the oracle on 10 steps of one 512^2 member")
-        cpu = ensemble_cpu_baseline(10)
-    out = {
-        "metric": "site-steps/s", "value": value, "unit": "site-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "ensemble of 2D Model B lattices, 256x128^2 + 64x256^2 + 16x512^2 FP32, "
-                               "a=-1 b=1 k=1, D=0.01 q^2, dt=0.01, 2/3 radial de-aliasing, independent seeds, "
-                               "one batch",
-                   "members": len(lats), "sites": sites, "parallelism": "single GPU",
-                   "geometry": "autotuned per size" if args.autotune else "default"},
-        "plain": {"value": plain, "steps": plain_steps,
-                  "form": "pss_step on each lattice in turn, each on its own stream"},
-        "vs_plain": round(value / plain, 2),
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
+    out = {"value": value, "unit": "site-steps/s", "steps": steps, "ms_per_step": 1e3 * el / steps,
+           "members": len(lats), "sites": sites, "classes": ncls,
+           "plain": {"value": plain, "steps": plain_steps, "ms_per_step": 1e3 * pel / plain_steps,
+                     "form": "pss_step on each lattice in turn, each on its own stream"},
+           "vs_plain": round(value / plain, 2), "roofline": roofline,
+           "geometry": "autotuned per size" if args.autotune else "default"}
     batch.close()
+    for lat in lats:
+        lat.close()
+    return out
 
 
-def adjoint(args, pss):
+def adjoint(args, pss, torch):
     """Adjoint workload: dL/d(a, b, k, D) and dL/dphi_0 of the shell
     structure-factor loss after 2000 steps of 256^2 Model B, checkpoints every
     45 steps; the target spectrum comes from a forward run at (a, b, k, D) =
@@ -302,42 +275,40 @@ def adjoint(args, pss):
     ref = make((-1.0, 1.0, 1.0, 0.01))
     ref.step(nsteps)
     S_target, _ = ref.structure_factor(0)
-    fwd = make((-0.9, 1.1, 0.9, 0.012))
-    fwd.step(20)
-    fwd.sync()
-    t0 = time.perf_counter()
-    fwd.step(nsteps)
-    fwd.sync()
-    t_fwd = time.perf_counter() - t0
-    times = []
+    t_fwd, t_adj, t_rec = [], [], []
     for _ in range(3):
+        fwd = make((-0.9, 1.1, 0.9, 0.012))
+        fwd.prepare(nsteps)
+        fwd.sync()
+        t0 = time.perf_counter()
+        fwd.step(nsteps)
+        fwd.sync()
+        t_fwd.append(time.perf_counter() - t0)
         lat = make((-0.9, 1.1, 0.9, 0.012))
+        lat.prepare(ckpt)
+        lat.prepare(nsteps % ckpt)
         lat.sync()
         t0 = time.perf_counter()
-        loss, grad, _ = lat.adjoint_model_b(nsteps, S_target, ckpt_every=ckpt)
-        times.append(time.perf_counter() - t0)
-    t_adj = min(times)
+        loss, tape = lat.adjoint_forward(nsteps, S_target, ckpt_every=ckpt)
+        lat.sync()
+        t1 = time.perf_counter()
+        grad = tape.backward()
+        t2 = time.perf_counter()
+        tape.close()
+        t_rec.append(t1 - t0)
+        t_adj.append(t2 - t0)
+    tf, ta, tr = min(t_fwd), min(t_adj), min(t_rec)
+    log(f"bench: adjoint {ta * 1e3:.1f} ms for {nsteps} steps (forward alone {tf * 1e3:.1f} ms, "
+        f"checkpointed forward {tr * 1e3:.1f} ms); loss {loss:.6g}, grad {grad}")
     sites = n[0] * n[1]
-    log(f"bench: adjoint {t_adj * 1e3:.1f} ms for {nsteps} steps (forward alone {t_fwd * 1e3:.1f} ms); "
-        f"loss {loss:.6g}, grad {grad}")
-    out = {
-        "metric": "site-steps/s", "value": sites * nsteps / t_adj, "unit": "site-steps/s", "n_gpus": 1,
-        "steps": nsteps, "warmup": 20, "ms_per_step": 1e3 * t_adj / nsteps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "adjoint of 2D Model B 256x256 FP32 through 2000 steps, checkpoints every 45 "
-                               "steps, structure-factor loss, gradients in (a, b, k, D) and phi_0",
-                   "lattice": list(n), "parallelism": "single GPU"},
-        "plain": {"value": sites * nsteps / t_fwd, "form": "the forward run alone (pss_step)"},
-        "vs_plain": round(t_fwd / t_adj, 3),
-        "loss": loss, "grad": list(grad),
-        "roofline": None,
-        "cpu_baseline": None,
-    }
-    print(json.dumps(out), flush=True)
+    return {"value": sites * nsteps / ta, "unit": "site-steps/s", "steps": nsteps, "ckpt_every": ckpt,
+            "ms": ta * 1e3, "forward_ms": tf * 1e3, "checkpointed_forward_ms": tr * 1e3,
+            "plain": {"value": sites * nsteps / tf, "form": "the forward run alone (pss_step)"},
+            "cost_vs_plain": round(ta / tf, 3), "vs_plain": round(tf / ta, 3),
+            "loss": loss, "grad": list(grad)}
 
 
-def three_d(args, pss):
+def three_d(args, pss, torch):
     """3D two-field system, 256^3 FP32: Model B phi (a, b, k = -1, 1, 1, conserved
     noise 0.005 q^2) coupled to non-conserved psi with
     d/dt psi = -(c psi + psi^3 - lap psi) - g phi psi + noise 0.005, and
@@ -345,7 +316,9 @@ def three_d(args, pss):
     dt = 0.005; launch geometry picked by pss_autotune."""
     from paper_2405_02410_amd import Mono
     n, dt, c, g, Dn = (256, 256, 256), 0.005, -0.5, 0.3, 0.005
+    stream = torch.cuda.Stream()
     lat = pss.Lattice(n, dt=dt, seed=SEED)
+    lat.stream(stream.cuda_stream)
     phi = lat.field("phi")
     psi = lat.field("psi")
     lat.term(phi, [Mono(-A, q2=1), Mono(-K, q2=2)], [(phi, 1)], implicit=True)
@@ -359,13 +332,13 @@ def three_d(args, pss):
     us_tuned = lat.autotune(reps=20)
     lat.init_uniform(phi, -0.1, 0.1)
     lat.init_uniform(psi, -0.1, 0.1)
-    steps = min(args.steps, 2000)
+    steps = min(args.steps, 400)
+    lat.prepare(args.warmup)
+    lat.prepare(steps)
     lat.step(args.warmup)
     lat.sync()
-    t0 = time.perf_counter()
-    lat.step(steps)
-    lat.sync()
-    el = time.perf_counter() - t0
+    times = timed_runs(torch, stream, lambda: lat.step(steps))
+    el = statistics.median(times)
     sites = n[0] * n[1] * n[2]
     names = ("update_kernel", "xrow_kernel", "ypass_kernel(inverse)", "ypass_kernel(forward)")
     best = None
@@ -378,7 +351,7 @@ def three_d(args, pss):
     ms, nb, kname = best
     achieved = nb / (ms * 1e-3) / 1e9
     log(f"bench: 3d {1e6 * el / steps:.1f} us/step, {sites * steps / el:.4e} site-steps/s")
-    out = {
+    return {
         "metric": "site-steps/s", "value": sites * steps / el, "unit": "site-steps/s", "n_gpus": 1,
         "steps": steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -391,6 +364,107 @@ def three_d(args, pss):
                      "bytes_per_launch": nb, "us_per_launch": round(ms * 1e3, 3)},
         "cpu_baseline": None,
     }
+
+
+def line(workload, value, steps, warmup, ms_per_step, extra):
+    out = {"metric": "site-steps/s", "value": value, "unit": "site-steps/s", "n_gpus": 1,
+           "steps": steps, "warmup": warmup, "ms_per_step": ms_per_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic", "config": workload}
+    out.update(extra)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--kernel-reps", type=int, default=2000)
+    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload: leave out the ensemble and adjoint measurements")
+    ap.add_argument("--workload", choices=("modelb1024", "ensemble", "adjoint", "3d"), default="modelb1024",
+                    help="modelb1024: one 1024^2 lattice, with the ensemble and adjoint measurements "
+                         "(default); ensemble: 256x128^2 + 64x256^2 + 16x512^2 independent lattices in one "
+                         "batch, also timed one lattice per launch; adjoint: gradient of the structure-factor "
+                         "loss through 2000 steps at 256^2; 3d: the two-field 256^3 system")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="ensemble: keep the default launch geometry instead of pss_autotune's choice per size")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB three times with a plain device "
+                         "copy (a known-size reference for hardware byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the lattice is not sharded.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2405_02410_amd as pss
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    ens_steps = 200  # per timed run; both forms replay whole step graphs
+
+    if args.workload == "ensemble":
+        e = ensemble(args, pss, torch, ens_steps)
+        cpu = None if args.no_cpu else ensemble_cpu_baseline(10)
+        cfg = {"workload": "ensemble of 2D Model B lattices, 256x128^2 + 64x256^2 + 16x512^2 FP32, a=-1 b=1 "
+                           "k=1, D=0.01 q^2, dt=0.01, 2/3 radial de-aliasing, independent seeds, one batch",
+               "members": e["members"], "sites": e["sites"], "parallelism": "single GPU",
+               "geometry": e["geometry"]}
+        print(json.dumps(line(cfg, e["value"], ens_steps, ens_steps, e["ms_per_step"],
+                              {"plain": e["plain"], "vs_plain": e["vs_plain"], "roofline": e["roofline"],
+                               "cpu_baseline": cpu})), flush=True)
+        return
+    if args.workload == "adjoint":
+        a = adjoint(args, pss, torch)
+        cfg = {"workload": "adjoint of 2D Model B 256x256 FP32 through 2000 steps, checkpoints every 45 "
+                           "steps, structure-factor loss, gradients in (a, b, k, D) and phi_0",
+               "lattice": [256, 256], "parallelism": "single GPU"}
+        print(json.dumps(line(cfg, a["value"], a["steps"], 0, a["ms"] / a["steps"],
+                              {"plain": a["plain"], "vs_plain": a["vs_plain"], "cost_vs_plain": a["cost_vs_plain"],
+                               "loss": a["loss"], "grad": a["grad"], "roofline": None,
+                               "cpu_baseline": None})), flush=True)
+        return
+    if args.workload == "3d":
+        print(json.dumps(three_d(args, pss, torch)), flush=True)
+        return
+
+    m = modelb1024(args, pss, torch)
+    extras = {}
+    if not args.no_extras:
+        log(f"bench: ensemble workload, {ens_steps} steps per timed run")
+        extras["ensemble"] = ensemble(args, pss, torch, ens_steps)
+        log("bench: adjoint workload")
+        extras["adjoint"] = adjoint(args, pss, torch)
+
+    if args.copy_mib > 0:
+        nbytes = args.copy_mib << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copied {args.copy_mib} MiB three times")
+        del src, dst
+
+    cpu = None
+    if not args.no_cpu:
+        log(f"bench: timing the oracle on {args.cpu_steps} steps")
+        cpu = cpu_baseline(args.cpu_steps)
+
+    cfg = {"workload": "2D Model B 1024x1024 FP32, a=-1 b=1 k=1, conserved noise D=0.01 q^2, "
+                       "dt=0.01, 2/3 radial de-aliasing, uniform[-0.1,0.1] initial field, seed 1",
+           "lattice": list(N), "parallelism": "single GPU", "geometry": m["geometry"]}
+    out = line(cfg, m["value"], args.steps, args.warmup, m["ms_per_step"],
+               {"timing": f"median of {REPEATS} runs of {args.steps} steps, HIP events on the lattice stream",
+                "runs_ms_per_step": m["runs_ms_per_step"], "roofline": m["roofline"], "cpu_baseline": cpu,
+                "mass_after": m["mass_after"]})
+    out.update(extras)
     print(json.dumps(out), flush=True)
 
 

@@ -55,6 +55,7 @@ extern "C" {
 
 typedef struct pss_ctx pss_ctx;
 typedef struct pss_batch pss_batch;
+typedef struct pss_tape pss_tape;
 typedef int32_t pss_status;
 
 #define PSS_OK 0
@@ -64,6 +65,7 @@ typedef int32_t pss_status;
 #define PSS_E_HIP (-4)         /* a HIP runtime call or kernel failed */
 #define PSS_E_STATE (-5)       /* call not allowed in the current state */
 #define PSS_E_UNSTABLE (-6)    /* 1 - dt*L(q) has real part <= 0 on some mode */
+#define PSS_E_NONFINITE (-7)   /* a NaN or infinity appeared in the state (reported by pss_sync) */
 
 /* De-aliasing (Sec. "De-aliasing").  A factor entering nonlinear terms of
  * highest order n has its modes beyond a fraction f of the Nyquist index
@@ -152,7 +154,9 @@ pss_status pss_dealias_set(pss_ctx *ctx, int32_t rule, int32_t shape);
 
 /* Run on this hipStream_t (NULL selects the context's own stream).  The
  * caller keeps the stream alive while the context uses it.  The legacy null
- * stream cannot host graph capture; pass a created stream. */
+ * stream cannot host graph capture; pass a created stream.  PSS_E_STATE while
+ * a batch or an adjoint tape holds the context (they order their work on the
+ * streams the members had when they were made). */
 pss_status pss_stream_set(pss_ctx *ctx, void *hip_stream);
 
 /* Launch-geometry override, before the plan is built (PSS_E_STATE after).
@@ -198,10 +202,21 @@ pss_status pss_spectrum_download(pss_ctx *ctx, int32_t field, float *half_spectr
  * step sequence. */
 pss_status pss_step(pss_ctx *ctx, int64_t nsteps);
 
+/* Build the plan (if needed) and capture and instantiate the HIP graphs that
+ * pss_step(ctx, nsteps) replays (chunks of up to 50 steps and the remainder),
+ * without running them.  The state is unchanged.  For callers that time or
+ * capture pss_step and want no graph construction inside that region.
+ * Errors: PSS_E_INVAL (nsteps < 0), plan errors as for pss_step. */
+pss_status pss_step_prepare(pss_ctx *ctx, int64_t nsteps);
+
 /* Number of steps taken since the plan was built (the noise step index). */
 pss_status pss_step_index(pss_ctx *ctx, int64_t *out);
 
-/* Wait for the context stream; reports asynchronous device failures. */
+/* Wait for the context stream; reports asynchronous device failures.  The
+ * update kernel raises a device flag when a new state value is NaN or
+ * infinite (a blown-up run); pss_sync then returns PSS_E_NONFINITE once, with
+ * the mask of the affected fields in the message, and clears the flag.
+ * Uploads, uniform initialisation and state loads also clear it. */
 pss_status pss_sync(pss_ctx *ctx);
 
 /* Bytes needed by pss_state_save. */
@@ -289,6 +304,25 @@ pss_status pss_kernels_per_step(pss_ctx *ctx, int32_t *count);
 pss_status pss_adjoint_model_b(pss_ctx *ctx, int64_t nsteps, int32_t ckpt_every, const double *S_target,
                                int32_t n_shells, double *loss, double *grad, float *grad_phi0, int32_t on_device);
 
+/* The same gradient in two phases, for callers that need the loss before
+ * deciding on the gradient (an autograd forward followed, or not, by a
+ * backward).  pss_adjoint_model_b_forward runs the checkpointed forward run
+ * and returns the loss and a tape that owns the checkpoints and the reverse
+ * workspace (the device memory listed above; PSS_E_NOMEM if it does not fit).
+ * pss_adjoint_model_b_backward runs the reverse sweep once and writes grad and
+ * grad_phi0 as pss_adjoint_model_b does; it fails with PSS_E_STATE if the
+ * lattice's coefficients, seed or state changed after the forward phase, or
+ * if the sweep already ran.  pss_tape_destroy frees the tape (NULL accepted).
+ * While a tape exists its lattice refuses pss_lattice_destroy,
+ * pss_stream_set and a second tape (PSS_E_STATE).  After the forward phase
+ * the lattice is at step n0 + nsteps with the forward final state, as after
+ * the backward phase. */
+pss_status pss_adjoint_model_b_forward(pss_ctx *ctx, int64_t nsteps, int32_t ckpt_every,
+                                       const double *S_target, int32_t n_shells, double *loss,
+                                       pss_tape **tape);
+pss_status pss_adjoint_model_b_backward(pss_tape *tape, double *grad, float *grad_phi0, int32_t on_device);
+pss_status pss_tape_destroy(pss_tape *tape);
+
 /* ------------------------------------------------------------------ batches
  * Many independent 2D lattices advanced together.  The paper finds small
  * lattices overhead-bound on the GPU (its benchmarks: the CPU version wins
@@ -321,7 +355,8 @@ pss_status pss_batch_destroy(pss_batch *batch);
  * captured HIP graphs of up to 50 steps). */
 pss_status pss_batch_step(pss_batch *batch, int64_t nsteps);
 
-/* Block until the batch's stream is idle. */
+/* Block until the batch's stream is idle; PSS_E_NONFINITE (as pss_sync) if
+ * any member's flag is raised (every member's flag is cleared). */
 pss_status pss_batch_sync(pss_batch *batch);
 
 /* Number of size classes; class_of (may be NULL, else n entries) receives the

@@ -29,6 +29,7 @@ ERRORS = {
     -4: "PSS_E_HIP",
     -5: "PSS_E_STATE",
     -6: "PSS_E_UNSTABLE",
+    -7: "PSS_E_NONFINITE",
 }
 DEALIAS_TWO_THIRDS, DEALIAS_PAPER_ORDER, DEALIAS_NONE = 0, 1, 2
 SHAPE_RADIAL, SHAPE_PER_AXIS = 0, 1
@@ -88,6 +89,13 @@ _SIGS = {
     "pss_adjoint_model_b": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                             ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                             ctypes.c_void_p, ctypes.c_int32],
+    "pss_adjoint_model_b_forward": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_void_p)],
+    "pss_adjoint_model_b_backward": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
+                                     ctypes.c_int32],
+    "pss_tape_destroy": [ctypes.c_void_p],
+    "pss_step_prepare": [ctypes.c_void_p, ctypes.c_int64],
     "pss_batch_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
                          ctypes.POINTER(ctypes.c_uint64)],
     "pss_batch_destroy": [ctypes.c_void_p],
@@ -268,6 +276,10 @@ class Lattice:
     def step(self, n=1):
         _check(lib().pss_step(self._h, int(n)))
 
+    def prepare(self, n):
+        """Build the plan and the step graphs that step(n) replays, without stepping."""
+        _check(lib().pss_step_prepare(self._h, int(n)))
+
     def sync(self):
         _check(lib().pss_sync(self._h))
 
@@ -328,10 +340,59 @@ class Lattice:
                                          None if out is None else out.ctypes.data, 0))
         return loss.value, np.array(list(grad)), out
 
+    def adjoint_forward(self, nsteps, S_target, ckpt_every=45):
+        """Checkpointed forward phase of the Model B adjoint
+        (pss_adjoint_model_b_forward): (loss, Tape)."""
+        S = np.ascontiguousarray(S_target, dtype=np.float64)
+        loss = ctypes.c_double()
+        h = ctypes.c_void_p()
+        _check(lib().pss_adjoint_model_b_forward(self._h, int(nsteps), int(ckpt_every),
+                                                 S.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(S.size),
+                                                 ctypes.byref(loss), ctypes.byref(h)))
+        return loss.value, Tape(h, self)
+
     def kernels_per_step(self):
         v = ctypes.c_int32()
         _check(lib().pss_kernels_per_step(self._h, ctypes.byref(v)))
         return v.value
+
+
+class Tape:
+    """Recorded forward run of the Model B adjoint (pss_tape); backward() runs
+    the reverse sweep once.  close() (or garbage collection) frees it."""
+
+    def __init__(self, handle, lattice):
+        self._h = handle
+        self.lattice = lattice  # kept alive while the tape exists
+
+    def backward(self, grad_phi0=None):
+        """dL/d(a, b, k, D) as a numpy array; dL/dphi_0 into grad_phi0 (a float32
+        torch tensor on the device, or a numpy array) when given."""
+        grad = (ctypes.c_double * 4)()
+        if grad_phi0 is None:
+            _check(lib().pss_adjoint_model_b_backward(self._h, grad, None, 0))
+        elif hasattr(grad_phi0, "data_ptr"):
+            if grad_phi0.numel() != self.lattice.sites:
+                raise ValueError("wrong number of sites")
+            p, dev = _ptr(grad_phi0)
+            _check(lib().pss_adjoint_model_b_backward(self._h, grad, ctypes.c_void_p(p), dev))
+        else:
+            if grad_phi0.size != self.lattice.sites or grad_phi0.dtype != np.float32 or \
+                    not grad_phi0.flags.c_contiguous:
+                raise ValueError("grad_phi0 must be a contiguous float32 array of every site")
+            _check(lib().pss_adjoint_model_b_backward(self._h, grad, grad_phi0.ctypes.data, 0))
+        return np.array(list(grad))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().pss_tape_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:

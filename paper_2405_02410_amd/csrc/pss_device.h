@@ -1,11 +1,7 @@
 // Device building blocks for the pseudo-spectral step on gfx950:
-//   * complex helpers and in-register DFTs of size 2, 4, 8, 16;
-//   * a Stockham autosort line FFT staged through LDS, written from the
-//     textbook formulation (C. Van Loan, "Computational Frameworks for the
-//     Fast Fourier Transform", SIAM 1992, Sec. 1.7): pass p with span Ns
-//     combines R sub-transforms; butterfly j reads x[j + r L/R], applies the
-//     twiddles w^(j mod Ns) r of order Ns R, and writes
-//     y[(j div Ns) Ns R + (j mod Ns) + r Ns];
+//   * complex helpers and in-register DFTs of size 2, 4, 8, 16 (the line
+//     transforms built from them are in pss_fft.h);
+//   * global-memory access helpers and the XCD-aware block order;
 //   * Philox4x32-10 (Salmon et al., SC'11) and Box-Muller (1958).
 #pragma once
 
@@ -167,73 +163,6 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
     const int per = n / X, rem = n % X;
     const int x = b % X, k = b / X;
     return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + k;
-}
-
-// ------------------------------------------------------------ LDS line FFT
-// Padding of LDS line buffers: one float2 every 16 to spread banks.
-__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
-__host__ __device__ constexpr int lds_line(int L) { return lds_pad(L); }
-// LDS of one line transform: two padded lines, written by alternate passes
-__host__ __device__ constexpr int lds_fft(int L) { return 2 * lds_line(L); }
-
-// One Stockham pass of span NS over a line of length L held by T = L/P
-// threads; thread t keeps x[t + m T] in v[m] on entry and exit.  Passes
-// exchange through `buf` and hand `alt` to the next pass: a buffer is written
-// again only two passes later, after a barrier that every thread reaches once
-// it has read the older data, so one barrier per exchange suffices.
-template <int L, int P, int NS, int DIR>
-struct StockhamPass {
-    static __device__ __forceinline__ void run(float2 (&v)[P], float2* __restrict__ buf, float2* __restrict__ alt,
-                                               int t, const float2* __restrict__ tw) {
-        constexpr int R = (P < L / NS) ? P : (L / NS);
-        constexpr int T = L / P;
-        constexpr int B = P / R;  // butterflies per thread
-        constexpr bool last = (NS * R == L);
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            const int j = t + b * T;
-            float2 a[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) a[r] = v[b + r * B];
-            if constexpr (NS > 1) {
-                const int jm = j & (NS - 1);
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    float2 w = tw[(jm * r) * (L / (NS * R))];
-                    if (DIR > 0) w.y = -w.y;
-                    a[r] = cmul(a[r], w);
-                }
-            }
-            DFT<R, DIR>::run(a);
-            if constexpr (last) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) v[b + r * B] = a[r];
-            } else {
-                const int base = (j / NS) * NS * R + (j & (NS - 1));
-#pragma unroll
-                for (int r = 0; r < R; ++r) buf[lds_pad(base + r * NS)] = a[r];
-            }
-        }
-        if constexpr (!last) {
-            __syncthreads();
-#pragma unroll
-            for (int m = 0; m < P; ++m) v[m] = buf[lds_pad(t + m * T)];
-            StockhamPass<L, P, NS * R, DIR>::run(v, alt, buf, t, tw);
-        }
-    }
-};
-
-// Full line transform: v[m] = x[t + m T] in, X[t + m T] out (natural order).
-// DIR = -1: forward, unnormalised; DIR = +1: inverse, unnormalised.
-// buf holds lds_fft(L) elements (two padded lines).  Every thread of the
-// block must call it (it contains block barriers); on return every thread
-// has finished with buf, which the caller may reuse at once.
-template <int L, int P, int DIR>
-__device__ __forceinline__ void fft_line(float2 (&v)[P], float2* __restrict__ buf, int t,
-                                         const float2* __restrict__ tw) {
-    static_assert((L & (L - 1)) == 0 && (P & (P - 1)) == 0 && P <= 16 && P <= L, "bad FFT shape");
-    StockhamPass<L, P, 1, DIR>::run(v, buf, buf + lds_line(L), t, tw);
-    if constexpr (L > P) __syncthreads();
 }
 
 // ------------------------------------------------------------------ Philox

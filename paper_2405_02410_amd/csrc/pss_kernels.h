@@ -75,6 +75,7 @@ struct Geo {
     int nyblk;    // y-pass blocks (= ntile * Nz/tz)
     int nz;       // Nz (1 in 2D)
     int tc_log2;  // log2(tc)
+    int rb_log2;  // log2(rb)
     int pu;       // points per thread: update kernel
     int px;       // points per thread: x kernel
     int py;       // points per thread: y pass
@@ -96,7 +97,8 @@ struct YArgs {
 // channels, tiling) and the twiddles.
 struct Member {
     Bufs bufs;
-    const uint64_t* step_ctr;
+    uint64_t* step_ctr;
+    uint32_t* flag;  // bit f set when a non-finite value appears in field f's new state
 };
 
 struct LaunchArgs {
@@ -105,11 +107,13 @@ struct LaunchArgs {
     Bufs bufs;
     Geo geo;
     const uint64_t* step_ctr;
+    uint32_t* flag;         // the non-finite flag of the single lattice (transform modes)
     const Member* members;  // step modes: table of nmem lattices (device memory)
     const DevPlan* plans;   // step modes: their nmem plans (device memory)
     int nmem;
     bool general;           // the plans need the general-monomial operator code
     int step_off;
+    int64_t advance;     // x kernel, step modes: add this to every member's step counter (0: none)
     const float2* tw_u;  // twiddles of the update-axis length
     const float2* tw_x;  // twiddles of Nx
     const float2* tw_y;  // twiddles of Ny (3D y passes)
@@ -139,21 +143,25 @@ hipError_t launch_philox(hipStream_t s, uint32_t c0, uint32_t c1, uint32_t c2, u
 
 // register-array count an instantiation is built for (1, 2 or 4 fields)
 inline int field_slots(int n) { return n <= 1 ? 1 : (n == 2 ? 2 : 4); }
-// dynamic LDS of the update kernel: TC*TO line transforms (two padded lines
-// each), one exchange line and the staged twiddle table (L entries), in that order
-inline size_t update_lds_bytes(int L, int nf_slots, int tc, int to) {
-    (void)nf_slots;
-    return sizeof(float2) * (static_cast<size_t>(tc) * to * 2 * (L + L / 16) + 2 * static_cast<size_t>(L));
+// LDS elements of the line transforms of `lines` lines of length L held with
+// P points per thread: one in-wave region per line, plus two block-exchange
+// buffers per line when a line spans more than one wave (pss_fft.h)
+inline size_t fft_lds(int L, int P, int lines) {
+    return static_cast<size_t>(lines) * ((L / P > 64) ? 3 : 1) * static_cast<size_t>(L);
 }
-// dynamic LDS of the y pass: TC*TZ line transforms (two padded lines each),
-// one exchange line per z and the staged twiddle table (L entries), in that order
-inline size_t ypass_lds_bytes(int L, int tc, int tz) {
-    return sizeof(float2) * (static_cast<size_t>(tc) * tz * 2 * (L + L / 16) + static_cast<size_t>(tz + 1) * L);
+// dynamic LDS of the update kernel: TC*TO line transforms, one exchange line
+// and the staged twiddle table (L entries), in that order
+inline size_t update_lds_bytes(int L, int P, int tc, int to) {
+    return sizeof(float2) * (fft_lds(L, P, tc * to) + 2 * static_cast<size_t>(L));
 }
-// dynamic LDS of the x kernel: RB/2 line transforms (two padded lines each)
-// + the staged twiddle table
-inline size_t xrow_lds_bytes(int L, int rb) {
-    return sizeof(float2) * (static_cast<size_t>(rb / 2) * 2 * (L + L / 16) + static_cast<size_t>(L));
+// dynamic LDS of the y pass: TC*TZ line transforms, one exchange line per z
+// and the staged twiddle table (L entries), in that order
+inline size_t ypass_lds_bytes(int L, int P, int tc, int tz) {
+    return sizeof(float2) * (fft_lds(L, P, tc * tz) + static_cast<size_t>(tz + 1) * L);
+}
+// dynamic LDS of the x kernel: RB/2 line transforms + the staged twiddle table
+inline size_t xrow_lds_bytes(int L, int P, int rb) {
+    return sizeof(float2) * (fft_lds(L, P, rb / 2) + static_cast<size_t>(L));
 }
 
 // FP64 shell sums of (dV/N)|phi_hat|^2 over the packed state of one field

@@ -2,7 +2,7 @@
 //
 // One 2D step (eq:timeupdate and the six-step list after it) is two kernels:
 //
-//   update kernel (lines along y, one tile of TC packed columns per block)
+//   update kernel (lines along y, one or more packed columns per block)
 //     forward y-FFT of every product channel  -> N_hat(kx, ky)       (step 4)
 //     Philox4x32-10 + Box-Muller noise per mode, in registers        (step 5)
 //     phi <- (phi + dt sum M N_hat + sigma xi) / (1 - dt L)          (step 6)
@@ -12,25 +12,29 @@
 //     forward x-FFT (R2C) -> channel arrays for the next step        (step 4)
 //
 // The spectral arrays use the packed half-spectrum layout described in
-// pss_plan.h: column 0 holds X(kx=0) + i X(kx=Nx/2).
+// pss_plan.h: column 0 holds X(kx=0) + i X(kx=Nx/2).  Line transforms are the
+// register/LDS transforms of pss_fft.h: a forward transform gathers its input
+// at the digit-reversed positions and returns natural order (dit), an inverse
+// transform takes natural order and its output is scattered to the
+// digit-reversed positions (dif), so every per-mode computation sees natural
+// mode order.  A line is held by consecutive threads.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
 
 #include "pss_device.h"
+#include "pss_fft.h"
 #include "pss_kernels.h"
 #include "pss_plan.h"
 
 namespace pss {
 
 // ----------------------------------------------------------------- twiddles
-// Copy the twiddle table of a line length into LDS once per block; the copy
-// loop is unrolled so its loads are in flight together.  Returns the LDS copy
-// (the first transform's barriers order it before any use).
 // Copy of the twiddle table into LDS, in two halves so that the caller can
 // issue its own loads in between: every thread loads its (at most P) entries
 // at once, then stores them.  The blocks hold at least L/P threads, so P
-// entries per thread cover the table.
+// entries per thread cover the table.  The caller puts a block barrier
+// between the store and the first transform.
 template <int L, int P>
 __device__ __forceinline__ void load_twiddles(float2 (&w)[P], const float2* __restrict__ src, int tid, int nthr) {
     // unconditional loads (the index wraps, L is a power of two) keep the
@@ -111,16 +115,34 @@ __device__ __noinline__ float2 eval_general(const DevOp& op, float q2, float iqx
     return make_float2(re, im);
 }
 
+// sum_j poly[j] (q^2)^j up to the operator's degree
+__device__ __forceinline__ float horner(const DevOp& op, float q2) {
+    const int deg = op.deg;
+    float r = op.poly[deg];
+    for (int j = deg - 1; j >= 0; --j) r = fmaf(r, q2, op.poly[j]);
+    return r;
+}
+// the same for P modes at once: one loop per operator
+template <int P>
+__device__ __forceinline__ void horner_p(const DevOp& op, const float (&q2)[P], float (&out)[P]) {
+    const int deg = op.deg;
+    const float top = op.poly[deg];
+#pragma unroll
+    for (int m = 0; m < P; ++m) out[m] = top;
+    for (int j = deg - 1; j >= 0; --j) {
+        const float c = op.poly[j];
+#pragma unroll
+        for (int m = 0; m < P; ++m) out[m] = fmaf(out[m], q2[m], c);
+    }
+}
+
 // sum_m coef (q^2)^a |q|^-b (i qx)^cx (i qy)^cy (i qz)^cz: Horner over the
-// pure q^2 part, then the listed general monomials (none for most models)
-// GEN = false: the plan has no general monomials (DevPlan::general), and the
-// kernel is built without the out-of-line call, which would split the
-// unrolled mode loops into separately scheduled pieces
+// pure q^2 part, then the listed general monomials (GEN: the plan has some;
+// without them the kernel is built without the out-of-line call, which would
+// split the unrolled mode loops into separately scheduled pieces)
 template <bool GEN>
 __device__ __forceinline__ float2 eval_op(const DevOp& op, const ModeQ& q) {
-    float re = op.poly[PSS_MAXPOW];
-#pragma unroll
-    for (int j = PSS_MAXPOW - 1; j >= 0; --j) re = fmaf(re, q.q2, op.poly[j]);
+    const float re = horner(op, q.q2);
     if constexpr (GEN) {
         if (op.n != 0) {
             const float2 g = eval_general(op, q.q2, q.iq[0], q.iq[1], q.iq[2]);
@@ -130,11 +152,9 @@ __device__ __forceinline__ float2 eval_op(const DevOp& op, const ModeQ& q) {
     return make_float2(re, 0.f);
 }
 
-// 1 / (1 - dt L(q))
-template <bool GEN>
-__device__ __forceinline__ float2 implicit_inv(const DevPlan& p, int f, const ModeQ& q) {
-    const float2 L = eval_op<GEN>(p.implicit_op[f], q);
-    const float ar = 1.f - p.dt * L.x, ai = -p.dt * L.y;
+// 1 / (1 - dt L(q)), complex (operators with odd i q_i powers)
+__device__ __forceinline__ float2 cinv_implicit(float dt, float2 L) {
+    const float ar = 1.f - dt * L.x, ai = -dt * L.y;
     const float d = 1.f / (ar * ar + ai * ai);
     return make_float2(ar * d, -ai * d);
 }
@@ -152,28 +172,65 @@ __device__ __forceinline__ bool mask_keep(const DevMask& mk, int kx, int ky, int
     return s * mk.den2 < mk.rhs;
 }
 
+// Largest w^2 kept by mask mk along a line whose other indices are fixed at
+// (kx, ky) (2D: kz is the line index; 3D lines run along z, 2D lines along
+// y with kz absent): a mode of the line with index w is kept iff w*w <= lim.
+// -1: the whole line is masked.  Decided once per line, exactly as
+// mask_keep decides each mode.
+template <int DIM>
+__device__ __forceinline__ int line_lim(const DevMask& mk, int kx, int ky, int L) {
+    const int hmax = (L >> 1) * (L >> 1);  // the largest w^2 on the line
+    if (mk.shape == 2) return hmax;
+    const int ia = DIM == 2 ? 1 : 2;  // axis of the line
+    if (mk.shape == 1) {
+        bool k = true;
+        if (mk.h[0]) k = k && (mk.den * abs(kx) < mk.num * mk.h[0]);
+        if (DIM == 3 && mk.h[1]) k = k && (mk.den * abs(ky) < mk.num * mk.h[1]);
+        if (!k) return -1;
+        if (!mk.h[ia]) return hmax;
+        // den |w| < num h  <=>  |w| <= (num h - 1) / den
+        const int wmax = (mk.num * mk.h[ia] - 1) / mk.den;
+        return wmax * wmax;
+    }
+    // radial: (P0 + w_a w^2) den2 < rhs  <=>  w^2 <= (floor((rhs - 1)/den2) - P0) / w_a
+    const int64_t p0 = mk.w[0] * kx * kx + (DIM == 3 ? mk.w[1] * ky * ky : 0);
+    const int64_t room = (mk.rhs - 1) / mk.den2 - p0;
+    if (room < 0) return -1;
+    const int64_t wa = mk.w[ia];
+    const int64_t lim = wa > 0 ? room / wa : hmax;
+    return lim > hmax ? hmax : static_cast<int>(lim);
+}
+
 // Scaled unit white noise sigma(q) xi_hat(k) of field f at step `step` for a
-// mode with full-spectrum linear index lin and negative-mode index lneg.
-template <bool GEN>
-__device__ __forceinline__ float2 noise_mode(const DevPlan& p, int f, uint32_t step, uint32_t lin,
-                                             uint32_t lneg, const ModeQ& q) {
-    const float D = eval_op<GEN>(p.noise_op[f], q).x;
+// mode with full-spectrum linear index lin and negative-mode index lneg, and
+// noise strength D(q) (Sec. "Adding noise").
+__device__ __forceinline__ float2 noise_value(const DevPlan& p, int f, uint32_t step, uint32_t lin, uint32_t lneg,
+                                              float D) {
     const uint32_t c = lin < lneg ? lin : lneg;
     const uint4 w = philox4x32_10(make_uint4(c, step, static_cast<uint32_t>(f), 0u), p.key0, p.key1);
     const float2 g = box_muller(w.x, w.y);
-    const float sd = sqrtf(fmaxf(D, 0.f));
+    const float sd = __builtin_amdgcn_sqrtf(fmaxf(D, 0.f));
     if (lin == lneg) return make_float2(p.amp_self * sd * g.x, 0.f);
     const float a = p.amp_pair * sd;
     return lin == c ? make_float2(a * g.x, a * g.y) : make_float2(a * g.x, -a * g.y);
+}
+template <bool GEN>
+__device__ __forceinline__ float2 noise_mode(const DevPlan& p, int f, uint32_t step, uint32_t lin, uint32_t lneg,
+                                             const ModeQ& q) {
+    return noise_value(p, f, step, lin, lneg, eval_op<GEN>(p.noise_op[f], q).x);
 }
 
 // full-spectrum linear index of mode (kx, ky, kz), each in [0, n_i)
 __device__ __forceinline__ uint32_t lin_index(const DevPlan& p, int kx, int ky, int kz) {
     return (static_cast<uint32_t>(kz) * p.n[1] + ky) * p.n[0] + kx;
 }
-__device__ __forceinline__ uint32_t lin_neg(const DevPlan& p, int kx, int ky, int kz) {
+
+// full-spectrum linear index and its negative for signed mode indices
+__device__ __forceinline__ void mode_lin(const DevPlan& p, int kx, int ky, int kz, uint32_t& lin, uint32_t& lneg) {
     const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
-    return lin_index(p, (nx - kx) & (nx - 1), (ny - ky) & (ny - 1), (nz - kz) & (nz - 1));
+    const int ux = kx & (nx - 1), uy = ky & (ny - 1), uz = kz & (nz - 1);
+    lin = lin_index(p, ux, uy, uz);
+    lneg = lin_index(p, (nx - ux) & (nx - 1), (ny - uy) & (ny - 1), (nz - uz) & (nz - 1));
 }
 
 // select element F of a register array with a runtime index (unrolled)
@@ -195,10 +252,11 @@ __device__ __forceinline__ void add_to(float2 (&a)[NF][P], int f, int m, float2 
 
 // ------------------------------------------------------------ update kernel
 // Lines along the last axis u (y in 2D, z in 3D).  A block holds TC packed
-// columns x TO values of the other index o (y in 3D; none in 2D); thread
-// (cc, lo, t) keeps u = t + m*T of line (c, o) in v[m].  The state and the
-// channel inputs are [o][ctile][u][TC]; the factor outputs V go to
-// [ctile][u][TC] in 2D and to [u][ctile][o][TC] (the y-pass layout) in 3D.
+// columns x TO values of the other index o (y in 3D; none in 2D); the T
+// threads of line (cc, lo) are consecutive, thread t keeps slot u = t + m*T
+// of the line in v[m].  The state and the channel inputs are
+// [o][ctile][u][TC]; the factor outputs V go to [ctile][u][TC] in 2D and to
+// [u][ctile][o][TC] (the y-pass layout) in 3D.
 //
 // Which modes a line holds (signed indices):
 //   c >= 1           : (c, u, -) in 2D, (c, o, u) in 3D
@@ -210,45 +268,8 @@ __device__ __forceinline__ void add_to(float2 (&a)[NF][P], int f, int m, float2 
 //     slots 0 and L/2     : (Re of kx = 0, Re of kx = -Nx/2), both real
 // Transforms of a packed line see S(u) = phi(0,u) + i phi(Nx/2,u); the slot
 // form is converted to and from it through one LDS line (block-uniform
-// barriers; a block holds at most one packed line, at (cc, lo) = (0, 0)).
-// LDS: TC*TO padded line buffers | one exchange line of L | twiddles of L.
-
-// mode of slot u of a line; `pair` marks the two real modes of slots 0, L/2
-template <int DIM>
-__device__ __forceinline__ void slot_mode(bool packed, int kx_l, int ky_l, int u, int L, int nx, int& kx, int& ky,
-                                          int& kz, bool& pair) {
-    int w = signed_mode(u, L);  // signed index along the line
-    pair = false;
-    if (packed) {
-        const int h = L >> 1;
-        if (u == 0 || u == h) {
-            pair = true;
-            kx = 0;
-        } else if (u < h) {
-            kx = 0;
-        } else {
-            kx = -(nx >> 1);
-            w = L - u;
-        }
-    } else {
-        kx = kx_l;
-    }
-    if (DIM == 2) {
-        ky = w;
-        kz = 0;
-    } else {
-        ky = ky_l;
-        kz = w;
-    }
-}
-
-// full-spectrum linear index and its negative for signed mode indices
-__device__ __forceinline__ void mode_lin(const DevPlan& p, int kx, int ky, int kz, uint32_t& lin, uint32_t& lneg) {
-    const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
-    const int ux = kx & (nx - 1), uy = ky & (ny - 1), uz = kz & (nz - 1);
-    lin = lin_index(p, ux, uy, uz);
-    lneg = lin_index(p, (nx - ux) & (nx - 1), (ny - uy) & (ny - 1), (nz - uz) & (nz - 1));
-}
+// barriers; a block holds at most one packed line, its first).
+// LDS: TC*TO line-transform regions | one exchange line of L | twiddles of L.
 
 // packed line: S(u), S(L-u) -> slot value of u (the forward direction)
 template <int L>
@@ -264,6 +285,60 @@ __device__ __forceinline__ float2 from_slot(int u, float2 s1, float2 s2) {
     if (u == 0 || u == (L >> 1)) return s1;
     return u < (L >> 1) ? make_float2(s1.x - s2.y, s1.y + s2.x)   // phi0(u) + i phiN(u)
                         : make_float2(s2.x + s1.y, s1.x - s2.y);  // conj phi0(L-u) + i conj phiN(L-u)
+}
+
+// The modes of one line, decided once per thread: for slot u the signed
+// index along the line is w(u), the fixed indices are those of the line
+// (plain) or of the slot's half (packed: kx = 0 below L/2, -Nx/2 above).
+struct LineModes {
+    bool packed;
+    int kx, ky;        // fixed indices of a plain line (3D: ky; 2D: ky unused)
+    float qq;          // q_x^2 (+ q_y^2 in 3D) of a plain line
+    float qqN;         // packed line: the same with kx = -Nx/2 (kx = 0 gives qq0)
+    float qq0;
+    float qs;          // q scale of the line axis
+    uint32_t lstride;  // linear-index stride of the line axis
+    uint32_t yx, yxn;  // linear-index parts of the fixed indices and of their negatives
+    uint32_t yx0, yxN; // packed line: the same for kx = 0 and kx = -Nx/2 (negation keeps them)
+
+    // slot u (not a pair slot) -> w, q^2, lin, lneg
+    template <int L>
+    __device__ __forceinline__ void at(int u, int& w, float& q2, uint32_t& lin, uint32_t& lneg, bool& upper) const {
+        upper = packed && u > (L >> 1);
+        w = packed ? (upper ? L - u : u) : (u < (L >> 1) ? u : u - L);
+        const float ql = static_cast<float>(w) * qs;
+        q2 = fmaf(ql, ql, packed ? (upper ? qqN : qq0) : qq);
+        const uint32_t uw = static_cast<uint32_t>(w) & (L - 1), un = static_cast<uint32_t>(-w) & (L - 1);
+        lin = uw * lstride + (packed ? (upper ? yxN : yx0) : yx);
+        lneg = un * lstride + (packed ? (upper ? yxN : yx0) : yxn);
+    }
+};
+
+template <int L, int DIM>
+__device__ __forceinline__ LineModes line_modes(const DevPlan& p, bool packed, int kx_l, int ky_l) {
+    LineModes lm;
+    const int nx = p.n[0], ny = p.n[1];
+    lm.packed = packed;
+    lm.kx = kx_l;
+    lm.ky = ky_l;
+    const float qx = static_cast<float>(kx_l) * p.qs[0];
+    const float qy = DIM == 3 ? static_cast<float>(ky_l) * p.qs[1] : 0.f;
+    const float qxN = static_cast<float>(nx >> 1) * p.qs[0];
+    lm.qq = fmaf(qx, qx, qy * qy);
+    lm.qq0 = qy * qy;
+    lm.qqN = fmaf(qxN, qxN, qy * qy);
+    lm.qs = p.qs[DIM == 2 ? 1 : 2];
+    lm.lstride = DIM == 2 ? static_cast<uint32_t>(nx) : static_cast<uint32_t>(nx) * ny;
+    const uint32_t ux = static_cast<uint32_t>(kx_l) & (nx - 1), uxn = static_cast<uint32_t>(-kx_l) & (nx - 1);
+    const uint32_t uy = DIM == 3 ? (static_cast<uint32_t>(ky_l) & (ny - 1)) : 0u;
+    const uint32_t uyn = DIM == 3 ? (static_cast<uint32_t>(-ky_l) & (ny - 1)) : 0u;
+    lm.yx = uy * nx + ux;
+    lm.yxn = uyn * nx + uxn;
+    // packed lines: kx = 0 or Nx/2 are their own negatives (mod Nx); in 3D
+    // the packed lines have ky = 0 or -Ny/2, also their own negatives
+    lm.yx0 = uy * nx;
+    lm.yxN = uy * nx + (nx >> 1);
+    return lm;
 }
 
 // the two real self-conjugate modes (kx = 0 and kx = -Nx/2) of slot u in
@@ -305,7 +380,25 @@ __device__ __forceinline__ float2 pair_update_d(const DevPlan& p, int f, uint32_
         mode_lin(p, kn, ky, kz, lin, lneg);
         r.y += noise_mode<GEN>(p, f, step, lin, lneg, qn).x;
     }
-    return make_float2(r.x * implicit_inv<GEN>(p, f, q0).x, r.y * implicit_inv<GEN>(p, f, qn).x);
+    return make_float2(r.x * cinv_implicit(p.dt, eval_op<GEN>(p.implicit_op[f], q0)).x,
+                       r.y * cinv_implicit(p.dt, eval_op<GEN>(p.implicit_op[f], qn)).x);
+}
+
+// mode q of slot u of a line, for the general-monomial operators
+template <int L, int DIM>
+__device__ __forceinline__ ModeQ slot_q(const DevPlan& p, const LineModes& lm, int u) {
+    const bool upper = lm.packed && u > (L >> 1);
+    const int w = lm.packed ? (upper ? L - u : u) : (u < (L >> 1) ? u : u - L);
+    const int kx = lm.packed ? (upper ? -(p.n[0] >> 1) : 0) : lm.kx;
+    return DIM == 2 ? mode_q(p, kx, w, 0) : mode_q(p, kx, lm.ky, w);
+}
+
+// slots 0 and L/2 of a packed line: op applied to their two real modes each
+template <int DIM, bool GEN, int NF, int P>
+__device__ __forceinline__ void pair_accumulate(float2 (&acc)[NF][P], int target, const float2 (&v)[P],
+                                                const DevPlan& p, const DevOp& op, int ky_l, int L) {
+    add_to(acc, target, 0, pair_op_d<DIM, GEN>(p, op, ky_l, 0, L, v[0]));
+    add_to(acc, target, P / 2, pair_op_d<DIM, GEN>(p, op, ky_l, L >> 1, L, v[P / 2]));
 }
 
 template <int L, int P, int NF, int MODE, int DIM, bool GEN>
@@ -314,16 +407,17 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
                                                       const DevPlan* __restrict__ plan_a, Bufs bufs_a, Geo geo,
                                                       const uint64_t* __restrict__ step_ctr_a,
                                                       int step_off, const float2* __restrict__ tw_g) {
-    constexpr int T = L / P;
+    using FFT = LineFFT<L, P>;
+    constexpr int T = FFT::T;
     extern __shared__ float2 smem[];
     // step modes: lattice blockIdx.y of the member table and of the plan
     // array (both kernel arguments, so the plan reads stay scalar loads); the
     // transform modes act on the single lattice of the arguments (gridDim.y = 1)
     constexpr bool TAB = MODE == MODE_STEP || MODE == MODE_PROLOGUE;
     const int nb = gridDim.x;
-    const int lin = xcd_block(blockIdx.y * nb + blockIdx.x, nb * gridDim.y);
-    const int mi = lin / nb;
-    const int blk = lin - mi * nb;
+    const int lin_b = xcd_block(blockIdx.y * nb + blockIdx.x, nb * gridDim.y);
+    const int mi = lin_b / nb;
+    const int blk = lin_b - mi * nb;
     const Member* mem = members + mi;  // dereferenced in the step modes only
     const DevPlan& p = TAB ? plans[mi] : *plan_a;
     const Bufs& bufs = TAB ? mem->bufs : bufs_a;
@@ -331,26 +425,35 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
     const int tc = geo.tc, to = geo.to;
     const int ntile = geo.ntile;
     const int tid = threadIdx.x;
-    const int cc = tid % tc;
-    const int lo = (tid / tc) % to;
-    const int t = tid / (tc * to);
+    const int nthr = tc * to * T;
+    const int t = tid & (T - 1);
+    const int li = tid / T;  // line of the block
+    const int cc = li & (tc - 1);
+    const int lo = li >> geo.tc_log2;
     const int ct = blk % ntile;  // tile index
     const int og = blk / ntile;  // group of `to` other-index lines
     const int o = og * to + lo;
-    const int c = ct * tc + cc;         // packed column
+    const int c = ct * tc + cc;  // packed column
     const int nx = p.n[0], ny = p.n[1];
     const size_t base = (static_cast<size_t>(o) * ntile + ct) * L * tc + cc;
     const size_t vbase = DIM == 2 ? base : (static_cast<size_t>(ct) * ny + o) * tc + cc;
     const size_t vstride = DIM == 2 ? static_cast<size_t>(tc) : static_cast<size_t>(ntile) * ny * tc;
-    float2* line = smem + (lo * tc + cc) * lds_fft(L);
-    float2* xbuf = smem + tc * to * lds_fft(L);  // packed-line exchange
+    LdsLine ld;
+    ld.wl = smem + li * FFT::kLds;
+    ld.blk0 = ld.wl + L;
+    ld.blk1 = ld.wl + 2 * L;
+    ld.par = 0;
+    float2* xbuf = smem + tc * to * FFT::kLds;  // packed-line exchange
+    float2* twl = xbuf + L;
+    const int dr = FFT::drev(t);  // gathered / scattered positions dr + m*T
     // twiddles: loaded now, stored to LDS after each mode's first loads
     float2 twr[P];
-    load_twiddles<L, P>(twr, tw_g, tid, tc * to * T);
-    const float2* tw = xbuf + L;
+    load_twiddles<L, P>(twr, tw_g, tid, nthr);
+    const float2* tw = twl;
     // block holds a packed line (block-uniform); this thread is on it
     const bool blk_packed = ct == 0 && (DIM == 2 || og * to == 0 || og * to == (ny >> 1));
     const bool packed = blk_packed && cc == 0 && lo == 0;
+    const bool pair_lane = packed && t == 0;  // holds slots 0 and L/2: two real modes each
     // fixed mode indices of a plain line
     int kx_l = c, ky_l = 0;
     if (DIM == 3) {
@@ -367,7 +470,8 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
     }
     const int nf = p.nf;
 
-    // packed line only: exchange v with the partner -u and map it (block-uniform)
+    // packed line only: exchange v (natural order) with the partner slot -u
+    // and map it (block-uniform)
     auto exchange = [&](float2 (&v)[P], bool forward) {
         if (!blk_packed) return;
         if (packed) {
@@ -390,9 +494,10 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
         // forward transform of an array in the state layout, stored as the state
         float2 v[P];
 #pragma unroll
-        for (int m = 0; m < P; ++m) v[m] = gload(bufs.in + base + (t + m * T) * tc);
-        store_twiddles<L, P>(xbuf + L, twr, tid, tc * to * T);
-        fft_line<L, P, -1>(v, line, t, tw);
+        for (int m = 0; m < P; ++m) v[m] = gload(bufs.in + base + (dr + m * T) * tc);
+        store_twiddles<L, P>(twl, twr, tid, nthr);
+        __syncthreads();
+        FFT::template dit<-1>(v, ld, t, tw);
         exchange(v, true);
 #pragma unroll
         for (int m = 0; m < P; ++m) gstore(bufs.S[bufs.sel] + base + (t + m * T) * tc, v[m]);
@@ -402,15 +507,17 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
         float2 v[P];
 #pragma unroll
         for (int m = 0; m < P; ++m) v[m] = gload(bufs.S[bufs.sel] + base + (t + m * T) * tc);
-        store_twiddles<L, P>(xbuf + L, twr, tid, tc * to * T);
+        store_twiddles<L, P>(twl, twr, tid, nthr);
+        __syncthreads();
         exchange(v, false);
-        fft_line<L, P, 1>(v, line, t, tw);
+        FFT::template dif<1>(v, ld, t, tw);
 #pragma unroll
-        for (int m = 0; m < P; ++m) gstore(bufs.out + vbase + (t + m * T) * vstride, v[m]);
+        for (int m = 0; m < P; ++m) gstore(bufs.out + vbase + (dr + m * T) * vstride, v[m]);
         return;
     }
 
     // ---- MODE_STEP or MODE_PROLOGUE
+    const LineModes lmode = line_modes<L, DIM>(p, packed, kx_l, ky_l);
     float2 s[NF][P];  // state, then new state (slot form on a packed line)
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
@@ -423,16 +530,29 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
         }
     }
 
-    if constexpr (MODE == MODE_PROLOGUE) store_twiddles<L, P>(xbuf + L, twr, tid, tc * to * T);
+    if constexpr (MODE == MODE_PROLOGUE) {
+        store_twiddles<L, P>(twl, twr, tid, nthr);
+        __syncthreads();
+    }
     if constexpr (MODE == MODE_STEP) {
         const uint32_t step = static_cast<uint32_t>(gload_u64(step_ctr)) + static_cast<uint32_t>(step_off);
         // the first channel's loads go out before the twiddles are stored
         float2 nxt[P];
         if (p.nch > 0) {
 #pragma unroll
-            for (int m = 0; m < P; ++m) nxt[m] = gload(bufs.N[0] + base + (t + m * T) * tc);
+            for (int m = 0; m < P; ++m) nxt[m] = gload(bufs.N[0] + base + (dr + m * T) * tc);
         }
-        store_twiddles<L, P>(xbuf + L, twr, tid, tc * to * T);
+        store_twiddles<L, P>(twl, twr, tid, nthr);
+        // per-slot modes of the line (slot form on a packed line)
+        float q2[P];
+        uint32_t lin[P], lneg[P];
+#pragma unroll
+        for (int m = 0; m < P; ++m) {
+            int w;
+            bool up;
+            lmode.at<L>(t + m * T, w, q2[m], lin[m], lneg[m], up);
+        }
+        __syncthreads();  // twiddles in LDS
         float2 acc[NF][P];  // explicit contributions
 #pragma unroll
         for (int f = 0; f < NF; ++f)
@@ -446,67 +566,83 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
             for (int m = 0; m < P; ++m) v[m] = nxt[m];
             if (ch + 1 < p.nch) {
 #pragma unroll
-                for (int m = 0; m < P; ++m) nxt[m] = gload(bufs.N[ch + 1] + base + (t + m * T) * tc);
+                for (int m = 0; m < P; ++m) nxt[m] = gload(bufs.N[ch + 1] + base + (dr + m * T) * tc);
             }
-            fft_line<L, P, -1>(v, line, t, tw);
+            FFT::template dit<-1>(v, ld, t, tw);
             exchange(v, true);
+            if constexpr (GEN) {
 #pragma unroll
-            for (int m = 0; m < P; ++m) {
-                int kx, ky, kz;
-                bool pair;
-                slot_mode<DIM>(packed, kx_l, ky_l, t + m * T, L, nx, kx, ky, kz, pair);
-                if (!pair) add_to(acc, C.target, m, cmul(eval_op<GEN>(C.op, mode_q(p, kx, ky, kz)), v[m]));
+                for (int m = 0; m < P; ++m)
+                    if (!(pair_lane && (m == 0 || m == P / 2)))
+                        add_to(acc, C.target, m, cmul(eval_op<GEN>(C.op, slot_q<L, DIM>(p, lmode, t + m * T)), v[m]));
+            } else {
+                float M[P];
+                horner_p(C.op, q2, M);
+#pragma unroll
+                for (int m = 0; m < P; ++m)
+                    if (!(pair_lane && (m == 0 || m == P / 2))) add_to(acc, C.target, m, cscale(v[m], M[m]));
             }
-            if (packed && t == 0) {
-                // slots 0 and L/2: two real modes (operators are real on them)
-                add_to(acc, C.target, 0, pair_op_d<DIM, GEN>(p, C.op, ky_l, 0, L, v[0]));
-                add_to(acc, C.target, P / 2, pair_op_d<DIM, GEN>(p, C.op, ky_l, L >> 1, L, v[P / 2]));
-            }
+            // slots 0 and L/2 of a packed line: two real modes (operators are real on them)
+            if (pair_lane) pair_accumulate<DIM, GEN>(acc, C.target, v, p, C.op, ky_l, L);
         }
         // Fourier-space terms with a single linear factor
         for (int d = 0; d < p.nd; ++d) {
             const DevDirect& Dd = p.direct[d];
+            float2 src[P];
 #pragma unroll
-            for (int m = 0; m < P; ++m) {
-                int kx, ky, kz;
-                bool pair;
-                slot_mode<DIM>(packed, kx_l, ky_l, t + m * T, L, nx, kx, ky, kz, pair);
-                if (!pair) add_to(acc, Dd.target, m, cmul(eval_op<GEN>(Dd.op, mode_q(p, kx, ky, kz)), pick(s, Dd.src, m)));
+            for (int m = 0; m < P; ++m) src[m] = pick(s, Dd.src, m);
+            if constexpr (GEN) {
+#pragma unroll
+                for (int m = 0; m < P; ++m)
+                    if (!(pair_lane && (m == 0 || m == P / 2)))
+                        add_to(acc, Dd.target, m, cmul(eval_op<GEN>(Dd.op, slot_q<L, DIM>(p, lmode, t + m * T)), src[m]));
+            } else {
+                float M[P];
+                horner_p(Dd.op, q2, M);
+#pragma unroll
+                for (int m = 0; m < P; ++m)
+                    if (!(pair_lane && (m == 0 || m == P / 2))) add_to(acc, Dd.target, m, cscale(src[m], M[m]));
             }
-            if (packed && t == 0) {
-                add_to(acc, Dd.target, 0, pair_op_d<DIM, GEN>(p, Dd.op, ky_l, 0, L, pick(s, Dd.src, 0)));
-                add_to(acc, Dd.target, P / 2, pair_op_d<DIM, GEN>(p, Dd.op, ky_l, L >> 1, L, pick(s, Dd.src, P / 2)));
-            }
+            if (pair_lane) pair_accumulate<DIM, GEN>(acc, Dd.target, src, p, Dd.op, ky_l, L);
         }
         // semi-implicit update (eq:timeupdate) with in-register noise
+        uint32_t bad = 0;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             if (f >= nf) continue;
             const bool noisy = p.noisy[f] != 0;
             const float2 old0 = s[f][0], oldh = s[f][P / 2];
+            float Ar[P], Dn[P];
+            if constexpr (!GEN) {
+                horner_p(p.implicit_op[f], q2, Ar);
+                if (noisy) horner_p(p.noise_op[f], q2, Dn);
+            }
 #pragma unroll
             for (int m = 0; m < P; ++m) {
-                const int u = t + m * T;
-                int kx, ky, kz;
-                bool pair;
-                slot_mode<DIM>(packed, kx_l, ky_l, u, L, nx, kx, ky, kz, pair);
-                const ModeQ q = mode_q(p, kx, ky, kz);
                 float2 r = cadd(s[f][m], cscale(acc[f][m], p.dt));
-                if (noisy) {
-                    uint32_t lin, lneg;
-                    mode_lin(p, kx, ky, kz, lin, lneg);
-                    r = cadd(r, noise_mode<GEN>(p, f, step, lin, lneg, q));
+                if constexpr (GEN) {
+                    const ModeQ q = slot_q<L, DIM>(p, lmode, t + m * T);
+                    if (noisy) r = cadd(r, noise_mode<GEN>(p, f, step, lin[m], lneg[m], q));
+                    s[f][m] = cmul(r, cinv_implicit(p.dt, eval_op<GEN>(p.implicit_op[f], q)));
+                } else {
+                    if (noisy) r = cadd(r, noise_value(p, f, step, lin[m], lneg[m], Dn[m]));
+                    s[f][m] = cscale(r, __builtin_amdgcn_rcpf(fmaf(-p.dt, Ar[m], 1.f)));
                 }
-                s[f][m] = cmul(r, implicit_inv<GEN>(p, f, q));
             }
-            if (packed && t == 0) {
+            if (pair_lane) {
                 // slots 0 and L/2 hold two real modes each
                 s[f][0] = pair_update_d<DIM, GEN>(p, f, step, ky_l, 0, L, old0, acc[f][0], noisy);
                 s[f][P / 2] = pair_update_d<DIM, GEN>(p, f, step, ky_l, L >> 1, L, oldh, acc[f][P / 2], noisy);
             }
+            bool fin = true;
 #pragma unroll
-            for (int m = 0; m < P; ++m) gstore(bufs.S[f] + base + (t + m * T) * tc, s[f][m]);
+            for (int m = 0; m < P; ++m) {
+                gstore(bufs.S[f] + base + (t + m * T) * tc, s[f][m]);
+                fin = fin && __builtin_isfinite(s[f][m].x) && __builtin_isfinite(s[f][m].y);
+            }
+            if (!fin) bad |= 1u << f;  // a NaN or infinity in the new state
         }
+        if (bad) atomicOr(mem->flag, bad);
     }
 
     // de-aliased inverse transforms of every factor field (eq:cubicexampledealiased)
@@ -514,52 +650,66 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
         const DevMask& mk = p.mask[g];
         if (ct * tc >= mk.ncol) continue;  // whole tile masked: never read (block-uniform)
         const int fg = p.gfield[g];
+        // the largest kept w^2 of this line (packed: of each half)
+        const int lim = line_lim<DIM>(mk, lmode.packed ? 0 : kx_l, ky_l, L);
+        const int limN = line_lim<DIM>(mk, -(nx >> 1), ky_l, L);
         float2 v[P];
 #pragma unroll
         for (int m = 0; m < P; ++m) {
-            int kx, ky, kz;
-            bool pair;
-            slot_mode<DIM>(packed, kx_l, ky_l, t + m * T, L, nx, kx, ky, kz, pair);
+            const int u = t + m * T;
             const float2 a = pick(s, fg, m);
-            if (!pair) {
-                v[m] = mask_keep(mk, kx, ky, kz) ? a : make_float2(0.f, 0.f);
-            } else {
-                v[m] = make_float2(mask_keep(mk, 0, ky, kz) ? a.x : 0.f,
-                                   mask_keep(mk, -(nx >> 1), ky, kz) ? a.y : 0.f);
-            }
+            const bool upper = packed && u > (L >> 1);
+            const int w = packed ? (upper ? L - u : u) : (u < (L >> 1) ? u : u - L);
+            v[m] = w * w <= (upper ? limN : lim) ? a : make_float2(0.f, 0.f);
+        }
+        if (pair_lane) {
+            // slots 0 and L/2: kx = 0 (re) and kx = -Nx/2 (im) at w = 0, -L/2
+            const int wh = (L >> 1) * (L >> 1);
+            const float2 a0 = pick(s, fg, 0), ah = pick(s, fg, P / 2);
+            v[0] = make_float2(0 <= lim ? a0.x : 0.f, 0 <= limN ? a0.y : 0.f);
+            v[P / 2] = make_float2(wh <= lim ? ah.x : 0.f, wh <= limN ? ah.y : 0.f);
         }
         exchange(v, false);
-        fft_line<L, P, 1>(v, line, t, tw);
+        FFT::template dif<1>(v, ld, t, tw);
 #pragma unroll
-        for (int m = 0; m < P; ++m) gstore(bufs.V[g] + vbase + (t + m * T) * vstride, v[m]);
+        for (int m = 0; m < P; ++m) gstore(bufs.V[g] + vbase + (dr + m * T) * vstride, v[m]);
     }
 }
 
 // ------------------------------------------------------ adjoint column kernel
 // One reverse step of 2D Model B along y lines (AdjArgs).  Same block shape,
 // slot form and LDS layout as the 2D update kernel: TC column lines per
-// block, thread (cc, t) holds slots u = t + m*T.  Inner products over all
-// modes become sums over the stored slots with weight 2 (a mode and its
-// conjugate), and weight 1 for each real component of the pair slots.
+// block, the T threads of a line consecutive, thread t holds slots
+// u = t + m*T.  Inner products over all modes become sums over the stored
+// slots with weight 2 (a mode and its conjugate), and weight 1 for each real
+// component of the pair slots.
 template <int L, int P, int MODE>
 __global__ void __launch_bounds__(256) adjcol_kernel(AdjArgs aa, Geo geo, const float2* __restrict__ tw_g) {
-    constexpr int T = L / P;
+    using FFT = LineFFT<L, P>;
+    constexpr int T = FFT::T;
     extern __shared__ float2 smem[];
     const DevPlan& p = *aa.plan;
     const int tc = geo.tc;
     const int tid = threadIdx.x;
-    const int cc = tid % tc;
-    const int t = tid / tc;
+    const int nthr = tc * T;
+    const int t = tid & (T - 1);
+    const int cc = tid / T;
     const int ct = xcd_block(blockIdx.x, gridDim.x);
     const int c = ct * tc + cc;
     const int nx = p.n[0];
     const int kn = -(nx >> 1);
     const size_t base = static_cast<size_t>(ct) * L * tc + cc;
-    float2* line = smem + cc * lds_fft(L);
-    float2* xbuf = smem + tc * lds_fft(L);
+    LdsLine ld;
+    ld.wl = smem + cc * FFT::kLds;
+    ld.blk0 = ld.wl + L;
+    ld.blk1 = ld.wl + 2 * L;
+    ld.par = 0;
+    float2* xbuf = smem + tc * FFT::kLds;
+    float2* twl = xbuf + L;
+    const int dr = FFT::drev(t);
     float2 twr[P];
-    load_twiddles<L, P>(twr, tw_g, tid, tc * T);
-    const float2* tw = xbuf + L;
+    load_twiddles<L, P>(twr, tw_g, tid, nthr);
+    const float2* tw = twl;
     const bool blk_packed = ct == 0;
     const bool packed = blk_packed && cc == 0;
     const DevMask& mk = p.mask[0];
@@ -581,25 +731,45 @@ __global__ void __launch_bounds__(256) adjcol_kernel(AdjArgs aa, Geo geo, const 
         }
         __syncthreads();
     };
+    // modes of slot u: (kx, ky) of a plain slot, or pair = the two real modes
+    auto slot = [&](int u, int& kx, int& ky, bool& pair) {
+        pair = false;
+        if (!packed) {
+            kx = c;
+            ky = signed_mode(u, L);
+        } else if (u == 0 || u == (L >> 1)) {
+            pair = true;
+            kx = 0;
+            ky = u == 0 ? 0 : -(L >> 1);
+        } else if (u < (L >> 1)) {
+            kx = 0;
+            ky = u;
+        } else {
+            kx = kn;
+            ky = L - u;
+        }
+    };
 
     // g_{n+1}
     float2 g[P];
     if (aa.first) {
 #pragma unroll
         for (int m = 0; m < P; ++m) g[m] = aa.G[base + (t + m * T) * tc];
-        store_twiddles<L, P>(xbuf + L, twr, tid, tc * T);
+        store_twiddles<L, P>(twl, twr, tid, nthr);
+        __syncthreads();
     } else {
         float2 v[P];
 #pragma unroll
-        for (int m = 0; m < P; ++m) v[m] = aa.X[base + (t + m * T) * tc];
-        store_twiddles<L, P>(xbuf + L, twr, tid, tc * T);
-        fft_line<L, P, -1>(v, line, t, tw);
+        for (int m = 0; m < P; ++m) v[m] = aa.X[base + (dr + m * T) * tc];
+        store_twiddles<L, P>(twl, twr, tid, nthr);
+        __syncthreads();
+        FFT::template dit<-1>(v, ld, t, tw);
         exchange(v, true);
 #pragma unroll
         for (int m = 0; m < P; ++m) {
-            int kx, ky, kz;
+            int kx, ky;
             bool pair;
-            slot_mode<2>(packed, c, 0, t + m * T, L, nx, kx, ky, kz, pair);
+            slot(t + m * T, kx, ky, pair);
             float2 y = cscale(v[m], p.inv_n * aa.b);
             if (!pair) {
                 if (!mask_keep(mk, kx, ky, 0)) y = make_float2(0.f, 0.f);
@@ -625,9 +795,9 @@ __global__ void __launch_bounds__(256) adjcol_kernel(AdjArgs aa, Geo geo, const 
     for (int m = 0; m < P; ++m) {
         const int u = t + m * T;
         const size_t e = base + u * tc;
-        int kx, ky, kz;
+        int kx, ky;
         bool pair;
-        slot_mode<2>(packed, c, 0, u, L, nx, kx, ky, kz, pair);
+        slot(u, kx, ky, pair);
         const float2 f1 = aa.phi1[e], f0 = aa.phi0[e];
         float2 r;
         if (!pair) {
@@ -666,13 +836,13 @@ __global__ void __launch_bounds__(256) adjcol_kernel(AdjArgs aa, Geo geo, const 
         aa.Rout[e] = r;
     }
     exchange(wr, false);
-    fft_line<L, P, 1>(wr, line, t, tw);
+    FFT::template dif<1>(wr, ld, t, tw);
 #pragma unroll
-    for (int m = 0; m < P; ++m) aa.W[base + (t + m * T) * tc] = wr[m];
+    for (int m = 0; m < P; ++m) aa.W[base + (dr + m * T) * tc] = wr[m];
     exchange(um, false);
-    fft_line<L, P, 1>(um, line, t, tw);
+    FFT::template dif<1>(um, ld, t, tw);
 #pragma unroll
-    for (int m = 0; m < P; ++m) aa.U[base + (t + m * T) * tc] = um[m];
+    for (int m = 0; m < P; ++m) aa.U[base + (dr + m * T) * tc] = um[m];
     if (aa.D > 0.f) part[2] /= 2.0 * aa.D;
     double out[4] = {part[0], 0.0, part[1], part[2]};
     block_atomic_add(out, aa.acc);
@@ -714,8 +884,9 @@ __global__ void adjseed_kernel(const float2* __restrict__ phi, float2* __restric
 
 // ----------------------------------------------------------------- y pass
 // 3D only: lines along y for fixed (c, z); block = TC columns x TZ values of
-// z.  Input [z][ctile][y][TC].  The inverse pass writes the same layout, the
-// forward pass writes the state layout [y][ctile][z][TC].
+// z, the T threads of a line consecutive.  Input [z][ctile][y][TC].  The
+// inverse pass writes the same layout, the forward pass writes the state
+// layout [y][ctile][z][TC].
 //
 // Column 0 arrives from the x pass as X(0) + i X(Nx/2), both real; after the
 // forward y transform it is Y(ky) = Y0(ky) + i YN(ky) with Y0, YN Hermitian
@@ -727,24 +898,33 @@ __global__ void adjseed_kernel(const float2* __restrict__ phi, float2* __restric
 // and the inverse pass undoes it before transforming.
 template <int L, int P, int MODE>
 __global__ void __launch_bounds__(256) ypass_kernel(YArgs ya, Geo geo, const float2* __restrict__ tw_g) {
-    constexpr int T = L / P;
+    using FFT = LineFFT<L, P>;
+    constexpr int T = FFT::T;
     extern __shared__ float2 smem[];
     const int tc = geo.tc, tz = geo.tz;
     const int ntile = geo.ntile;
     const int nz = geo.nz;
     const int tid = threadIdx.x;
-    const int cc = tid % tc;
-    const int lz = (tid / tc) % tz;
-    const int t = tid / (tc * tz);
+    const int nthr = tc * tz * T;
+    const int t = tid & (T - 1);
+    const int li = tid / T;
+    const int cc = li & (tc - 1);
+    const int lz = li >> geo.tc_log2;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int ct = blk % ntile;
     const int z = (blk / ntile) * tz + lz;
     const int c = ct * tc + cc;
-    float2* line = smem + (lz * tc + cc) * lds_fft(L);
-    float2* xb = smem + tc * tz * lds_fft(L) + lz * L;  // column-0 exchange, one line per z
+    LdsLine ld;
+    ld.wl = smem + li * FFT::kLds;
+    ld.blk0 = ld.wl + L;
+    ld.blk1 = ld.wl + 2 * L;
+    ld.par = 0;
+    float2* xb = smem + tc * tz * FFT::kLds + lz * L;  // column-0 exchange, one line per z
+    const int dr = FFT::drev(t);
     float2 twr[P];
-    load_twiddles<L, P>(twr, tw_g, tid, tc * tz * T);
-    const float2* tw = store_twiddles<L, P>(smem + tc * tz * lds_fft(L) + tz * L, twr, tid, tc * tz * T);
+    load_twiddles<L, P>(twr, tw_g, tid, nthr);
+    const float2* tw = store_twiddles<L, P>(smem + tc * tz * FFT::kLds + tz * L, twr, tid, nthr);
+    __syncthreads();
     const size_t ibase = (static_cast<size_t>(z) * ntile + ct) * L * tc + cc;
     const size_t obase = MODE == MODE_YFWD ? (static_cast<size_t>(ct) * nz + z) * tc + cc : ibase;
     const size_t ostride = MODE == MODE_YFWD ? static_cast<size_t>(ntile) * nz * tc : static_cast<size_t>(tc);
@@ -755,9 +935,10 @@ __global__ void __launch_bounds__(256) ypass_kernel(YArgs ya, Geo geo, const flo
         float2* __restrict__ dst = ya.dst[a];
         float2 v[P];
         if constexpr (MODE == MODE_YINV) {
+            // gathered at the digit-reversed positions, natural order out
 #pragma unroll
             for (int m = 0; m < P; ++m) {
-                const int y = t + m * T;
+                const int y = dr + m * T;
                 const float2 s1 = src[ibase + y * tc];
                 if (c == 0 && y != 0 && y != (L >> 1)) {
                     const float2 s2 = src[ibase + (L - y) * tc];
@@ -767,21 +948,26 @@ __global__ void __launch_bounds__(256) ypass_kernel(YArgs ya, Geo geo, const flo
                     v[m] = s1;
                 }
             }
-            fft_line<L, P, 1>(v, line, t, tw);
+            // in place (src == dst) is safe: a line is read whole before any of
+            // it is written, within one wave or across the transform's barrier
+            FFT::template dit<1>(v, ld, t, tw);
+#pragma unroll
+            for (int m = 0; m < P; ++m) dst[obase + (t + m * T) * ostride] = v[m];
         } else {
 #pragma unroll
             for (int m = 0; m < P; ++m) v[m] = src[ibase + (t + m * T) * tc];
-            fft_line<L, P, -1>(v, line, t, tw);
+            FFT::template dif<-1>(v, ld, t, tw);
             if (ct == 0) {
+                // column 0: the partner of ky is L - ky, exchanged by natural position
                 if (c == 0) {
 #pragma unroll
-                    for (int m = 0; m < P; ++m) xb[t + m * T] = v[m];
+                    for (int m = 0; m < P; ++m) xb[dr + m * T] = v[m];
                 }
                 __syncthreads();
                 if (c == 0) {
 #pragma unroll
                     for (int m = 0; m < P; ++m) {
-                        const int y = t + m * T;
+                        const int y = dr + m * T;
                         if (y == 0 || y == (L >> 1)) continue;
                         const float2 a0 = v[m], b0 = xb[L - y];
                         v[m] = y < (L >> 1) ? make_float2(0.5f * (a0.x + b0.x), 0.5f * (a0.y - b0.y))   // Y0(y)
@@ -790,52 +976,59 @@ __global__ void __launch_bounds__(256) ypass_kernel(YArgs ya, Geo geo, const flo
                 }
                 __syncthreads();
             }
-        }
 #pragma unroll
-        for (int m = 0; m < P; ++m) dst[obase + (t + m * T) * ostride] = v[m];
+            for (int m = 0; m < P; ++m) dst[obase + (dr + m * T) * ostride] = v[m];
+        }
     }
 }
 
 // ----------------------------------------------------------------- x kernel
-// Rows of length L = Nx; block = RB consecutive rows, pair p = rows (2p, 2p+1)
-// packed as one complex line.  Packed-column arrays are read and written in
-// whole tile blocks of RB*TC contiguous elements.
+// Rows of length L = Nx; block = RB consecutive rows, pair pr = rows
+// (2 pr, 2 pr + 1) packed as one complex line held by T consecutive threads.
+// Packed-column arrays are read and written in whole tile blocks of RB*TC
+// contiguous elements.
 template <int L, int P, int NG, int MODE>
 __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ members,
                                                     const DevPlan* __restrict__ plans,
                                                     const DevPlan* __restrict__ plan_a, Bufs bufs_a, Geo geo,
-                                                    const float2* __restrict__ tw_g) {
-    constexpr int T = L / P;
+                                                    const float2* __restrict__ tw_g, int64_t advance) {
+    using FFT = LineFFT<L, P>;
+    constexpr int T = FFT::T;
     constexpr int NC = L / 2;  // packed columns
     extern __shared__ float2 smem[];
     constexpr bool TAB = MODE == MODE_STEP;  // as in the update kernel
     const int nb = gridDim.x;
-    const int lin = xcd_block(blockIdx.y * nb + blockIdx.x, nb * gridDim.y);
-    const int mi = lin / nb;
+    const int lin_b = xcd_block(blockIdx.y * nb + blockIdx.x, nb * gridDim.y);
+    const int mi = lin_b / nb;
     const Member* mem = members + mi;
     const DevPlan& p = TAB ? plans[mi] : *plan_a;
     const Bufs& bufs = TAB ? mem->bufs : bufs_a;
     const int tc = geo.tc, rb = geo.rb;
     const int ntile = NC / tc;
     const int tid = threadIdx.x;
-    const int nthr = blockDim.x;
+    const int nthr = (rb >> 1) * T;
     const int pr = tid / T;  // pair within the block
-    const int t = tid % T;
-    const int r0 = (lin - mi * nb) * rb;  // first row; row index = z*Ny + y
+    const int t = tid & (T - 1);
+    const int r0 = (lin_b - mi * nb) * rb;  // first row; row index = z*Ny + y
     const int ny = p.n[1];
     const int zr = r0 / ny;          // z of the block (0 in 2D)
     const int y0 = r0 - zr * ny;     // first y of the block
     const int lt = geo.tc_log2;
-    float2* line = smem + pr * lds_fft(L);
+    LdsLine ld;
+    ld.wl = smem + pr * FFT::kLds;
+    ld.blk0 = ld.wl + L;
+    ld.blk1 = ld.wl + 2 * L;
+    ld.par = 0;
+    const int dr = FFT::drev(t);
     // twiddles: loaded now, stored to LDS after each mode's first loads
     float2 twr[P];
     load_twiddles<L, P>(twr, tw_g, tid, nthr);
-    float2* const twl = smem + (rb / 2) * lds_fft(L);
+    float2* const twl = smem + (rb >> 1) * FFT::kLds;
     const float2* tw = twl;
 
     // Gather the packed complex input Z[k] = X_row0[k] + i X_row1[k] of pair
-    // pr straight from the packed-column array (columns [0, ncol) are stored;
-    // the others are zero); all loads are issued together.
+    // pr at k = dr + m T straight from the packed-column array (columns
+    // [0, ncol) are stored; the others are zero); all loads are issued together.
     const size_t row0 = (static_cast<size_t>(zr) * ntile * ny + y0 + 2 * pr) * tc;
     const size_t tstride = static_cast<size_t>(ny) * tc;  // one column tile
     auto build_z = [&](float2 (&v)[P], const float2* __restrict__ src, int ncol) {
@@ -844,7 +1037,7 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
         float2 a[P], b[P];
 #pragma unroll
         for (int m = 0; m < P; ++m) {
-            const int k = t + m * T;
+            const int k = dr + m * T;
             const int kk = (k == NC) ? 0 : (k < NC ? k : L - k);
             const int kc = kk < ncol ? kk : 0;
             const size_t off = row0 + (kc >> lt) * tstride + (kc & (tc - 1));
@@ -853,7 +1046,7 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
         }
 #pragma unroll
         for (int m = 0; m < P; ++m) {
-            const int k = t + m * T;
+            const int k = dr + m * T;
             const int kk = (k == NC) ? 0 : (k < NC ? k : L - k);
             const float2 zero = make_float2(0.f, 0.f);
             const float2 am = kk < ncol ? a[m] : zero, bm = kk < ncol ? b[m] : zero;
@@ -868,25 +1061,37 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
             v[m] = z;
         }
     };
-    // unpack the forward transform W of each pair and store packed columns
-    auto store_rows = [&](float2* __restrict__ dst) {
-        const int per = rb * tc;
+    // Stage the forward transform W (held at k = dr + m T) of every pair in
+    // LDS at its natural positions, then unpack the two real rows of each
+    // pair and store whole packed-column tiles.  A line wider than a wave
+    // stages in its next block buffer; a narrower one in its own region
+    // (its wave is done with it).  The caller separates consecutive calls by
+    // a block barrier when the staging region is the in-wave one.
+    auto store_rows = [&](const float2 (&w)[P], float2* __restrict__ dst) {
+        float2* stage = FFT::kCross ? ld.next_blk() : ld.wl;
+        if constexpr (!FFT::kCross) wave_lds_sync();  // after the transform's last in-wave reads
+#pragma unroll
+        for (int m = 0; m < P; ++m) stage[dr + m * T] = w[m];
+        __syncthreads();
+        const int lp = geo.rb_log2 + lt;  // log2(rb * tc)
+        const int total = ntile << lp;
+        const size_t sbase = (static_cast<size_t>(zr) * ntile) * ny + y0;
 #pragma unroll 4
-        for (int i = tid; i < ntile * per; i += nthr) {
-            const int tl = i / per, rem = i - tl * per;
-            const int r = rem / tc, cc = rem - r * tc;
-            const int c = tl * tc + cc;
-            const float2* W = smem + (r >> 1) * lds_fft(L);
+        for (int i = tid; i < total; i += nthr) {
+            const int tl = i >> lp, rem = i & ((1 << lp) - 1);
+            const int r = rem >> lt, cc = rem & (tc - 1);
+            const int c = (tl << lt) + cc;
+            const float2* W = smem + (r >> 1) * FFT::kLds + (FFT::kCross ? (stage - ld.wl) : 0);
             float2 o;
             if (c == 0) {
-                const float2 a = W[lds_pad(0)], b = W[lds_pad(NC)];
+                const float2 a = W[0], b = W[NC];
                 o = (r & 1) ? make_float2(a.y, b.y) : make_float2(a.x, b.x);
             } else {
-                const float2 a = W[lds_pad(c)], b = W[lds_pad(L - c)];
+                const float2 a = W[c], b = W[L - c];
                 o = (r & 1) ? make_float2(0.5f * (a.y + b.y), 0.5f * (b.x - a.x))
                             : make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
             }
-            gstore(dst + ((static_cast<size_t>(zr) * ntile + tl) * ny + y0 + r) * tc + cc, o);
+            gstore(dst + ((sbase + static_cast<size_t>(tl) * ny + r) << lt) + cc, o);
         }
     };
 
@@ -901,18 +1106,17 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
                                src[static_cast<size_t>(r0 + 2 * pr + 1) * L + x]);
         }
         store_twiddles<L, P>(twl, twr, tid, nthr);
-        fft_line<L, P, -1>(v, line, t, tw);
-#pragma unroll
-        for (int m = 0; m < P; ++m) line[lds_pad(t + m * T)] = v[m];
         __syncthreads();
-        store_rows(bufs.out);
+        FFT::template dif<-1>(v, ld, t, tw);
+        store_rows(v, bufs.out);
         return;
     }
     if constexpr (MODE == MODE_C2R_OUT) {
         float2 v[P];
         build_z(v, bufs.in, NC);
         store_twiddles<L, P>(twl, twr, tid, nthr);
-        fft_line<L, P, 1>(v, line, t, tw);
+        __syncthreads();
+        FFT::template dit<1>(v, ld, t, tw);
         float* __restrict__ dst = bufs.real_out;
 #pragma unroll
         for (int m = 0; m < P; ++m) {
@@ -933,8 +1137,9 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
         build_z(u, bufs.V[0], p.mask[0].ncol);
         build_z(w, bufs.V[1], p.mask[1].ncol);
         store_twiddles<L, P>(twl, twr, tid, nthr);
-        fft_line<L, P, 1>(u, line, t, tw);
-        fft_line<L, P, 1>(w, line, t, tw);
+        __syncthreads();
+        FFT::template dit<1>(u, ld, t, tw);
+        FFT::template dit<1>(w, ld, t, tw);
         double part[1] = {0.0};
 #pragma unroll
         for (int m = 0; m < P; ++m) {
@@ -942,23 +1147,26 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
             part[0] += static_cast<double>(ux) * ux * ux * w[m].x + static_cast<double>(uy) * uy * uy * w[m].y;
             u[m] = make_float2(3.f * ux * ux * w[m].x, 3.f * uy * uy * w[m].y);
         }
-        fft_line<L, P, -1>(u, line, t, tw);
-#pragma unroll
-        for (int m = 0; m < P; ++m) line[lds_pad(t + m * T)] = u[m];
-        __syncthreads();
-        store_rows(bufs.N[0]);
+        FFT::template dif<-1>(u, ld, t, tw);
+        store_rows(u, bufs.N[0]);
         block_atomic_add(part, bufs.acc);
         return;
     }
 
-    // MODE_STEP: real-space values of every factor field
+    // MODE_STEP: the last step of a replayed chunk moves the member's step
+    // counter on (no later kernel of the chunk reads it)
+    if (advance != 0 && r0 == 0 && tid == 0) *mem->step_ctr += static_cast<uint64_t>(advance);
+    // real-space values of every factor field
     float2 z[NG][P];
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
         float2 v[P];
         build_z(v, bufs.V[g], p.mask[g].ncol);
-        if (g == 0) store_twiddles<L, P>(twl, twr, tid, nthr);
-        fft_line<L, P, 1>(v, line, t, tw);
+        if (g == 0) {
+            store_twiddles<L, P>(twl, twr, tid, nthr);
+            __syncthreads();
+        }
+        FFT::template dit<1>(v, ld, t, tw);
 #pragma unroll
         for (int m = 0; m < P; ++m) z[g][m] = cscale(v[m], p.inv_n);
     }
@@ -989,12 +1197,9 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
                 w[m].y += b;
             }
         }
-        fft_line<L, P, -1>(w, line, t, tw);
-#pragma unroll
-        for (int m = 0; m < P; ++m) line[lds_pad(t + m * T)] = w[m];
-        __syncthreads();
-        store_rows(bufs.N[ch]);
-        __syncthreads();
+        if (!FFT::kCross && ch > 0) __syncthreads();  // the previous channel's rows are stored
+        FFT::template dif<-1>(w, ld, t, tw);
+        store_rows(w, bufs.N[ch]);
     }
 }
 
@@ -1120,7 +1325,7 @@ __global__ void shells_kernel(const float2* __restrict__ S, int nx, int ny, int 
 template <int L, int P, int NF, int DIM>
 static hipError_t launch_update_d(int mode, const LaunchArgs& a) {
     const int threads = a.geo.tc * a.geo.to * (L / P);
-    const size_t lds = update_lds_bytes(L, NF, a.geo.tc, a.geo.to);
+    const size_t lds = update_lds_bytes(L, P, a.geo.tc, a.geo.to);
     const bool tab = mode == MODE_STEP || mode == MODE_PROLOGUE;
     if (tab && (!a.members || !a.plans || a.nmem < 1)) return hipErrorInvalidValue;
     dim3 grid(a.geo.nublk, tab ? a.nmem : 1), block(threads);
@@ -1159,27 +1364,27 @@ static hipError_t launch_update_t(int mode, const LaunchArgs& a) {
 template <int L, int P, int NG>
 static hipError_t launch_xrow_t(int mode, const LaunchArgs& a) {
     const int threads = (a.geo.rb / 2) * (L / P);
-    const size_t lds = xrow_lds_bytes(L, a.geo.rb);
+    const size_t lds = xrow_lds_bytes(L, P, a.geo.rb);
     const bool tab = mode == MODE_STEP;
     if (tab && (!a.members || !a.plans || a.nmem < 1)) return hipErrorInvalidValue;
     dim3 grid(a.geo.nrowblk, tab ? a.nmem : 1), block(threads);
     switch (mode) {
         case MODE_STEP:
             hipLaunchKernelGGL((xrow_kernel<L, P, NG, MODE_STEP>), grid, block, lds, a.stream, a.members, a.plans, a.plan,
-                               a.bufs, a.geo, a.tw_x);
+                               a.bufs, a.geo, a.tw_x, a.advance);
             break;
         case MODE_R2C_IN:
             hipLaunchKernelGGL((xrow_kernel<L, P, 1, MODE_R2C_IN>), grid, block, lds, a.stream, a.members, a.plans, a.plan,
-                               a.bufs, a.geo, a.tw_x);
+                               a.bufs, a.geo, a.tw_x, int64_t{0});
             break;
         case MODE_C2R_OUT:
             hipLaunchKernelGGL((xrow_kernel<L, P, 1, MODE_C2R_OUT>), grid, block, lds, a.stream, a.members, a.plans, a.plan,
-                               a.bufs, a.geo, a.tw_x);
+                               a.bufs, a.geo, a.tw_x, int64_t{0});
             break;
         case MODE_ADJROW:
             if constexpr (NG == 2) {
                 hipLaunchKernelGGL((xrow_kernel<L, P, 2, MODE_ADJROW>), grid, block, lds, a.stream, a.members, a.plans,
-                                   a.plan, a.bufs, a.geo, a.tw_x);
+                                   a.plan, a.bufs, a.geo, a.tw_x, int64_t{0});
                 break;
             }
             return hipErrorInvalidValue;
@@ -1228,7 +1433,7 @@ hipError_t PSS_CAT(launch_ypass_L, PSS_LINE_LEN)(int mode, const YArgs& ya, cons
     return with_points<L, 16>(a.geo.py, [&](auto PP) {
         constexpr int P = decltype(PP)::value;
         const int threads = a.geo.tc * a.geo.tz * (L / P);
-        const size_t lds = ypass_lds_bytes(L, a.geo.tc, a.geo.tz);
+        const size_t lds = ypass_lds_bytes(L, P, a.geo.tc, a.geo.tz);
         dim3 grid(a.geo.nyblk), block(threads);
         if (mode == MODE_YINV) {
             hipLaunchKernelGGL((ypass_kernel<L, P, MODE_YINV>), grid, block, lds, a.stream, ya, a.geo, a.tw_y);
@@ -1246,7 +1451,7 @@ hipError_t PSS_CAT(launch_adjcol_L, PSS_LINE_LEN)(int mode, const AdjArgs& aa, c
     return with_points<L, 16>(a.geo.pu, [&](auto PP) {
         constexpr int P = decltype(PP)::value;
         const int threads = a.geo.tc * (L / P);
-        const size_t lds = update_lds_bytes(L, 1, a.geo.tc, 1);
+        const size_t lds = update_lds_bytes(L, P, a.geo.tc, 1);
         dim3 grid(a.geo.nublk), block(threads);
         if (a.dim != 2 || a.geo.to != 1) return hipErrorInvalidValue;
         if (mode == MODE_ADJCOL) {

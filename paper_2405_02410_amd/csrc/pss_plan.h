@@ -43,7 +43,7 @@ struct DevMono {
 struct DevOp {
     float poly[PSS_MAXPOW + 1];  // coefficient of (q^2)^j, j = 0..8
     int32_t n;                   // monomials with 1/|q| or i q_i factors
-    int32_t pad;
+    int32_t deg;                 // highest j with poly[j] != 0 (0 if none)
     DevMono m[PSS_MAXM];
 };
 

@@ -164,6 +164,10 @@ struct pss_ctx {
     pss::Member* d_member_u = nullptr;
     pss::Member* d_member_x = nullptr;
     int batches = 0;        // live batches holding this context
+    int tapes = 0;          // live adjoint tapes recorded on this context
+    uint64_t state_gen = 0; // bumped by every change of the state (steps, uploads, loads)
+    uint64_t enq_gen = 0;   // bumped whenever the context enqueues work on its own stream
+    hipEvent_t after_batch = nullptr;  // the context's own work must wait for this batch event
     uint64_t plan_gen = 0;  // bumped at every upload of the plan
     std::map<int64_t, hipGraphExec_t> graphs;
     std::map<std::string, int64_t> tune;  // launch-geometry overrides
@@ -188,6 +192,8 @@ struct pss_batch {
         std::vector<uint64_t> gen;        // plan generation of each copy
     };
     std::vector<pss_ctx*> mem;
+    std::vector<uint64_t> seen;        // members' enq_gen when the batch last ordered itself after them
+    std::vector<int> all;              // 0 .. n-1
     std::vector<Class> cls;
     uint64_t** d_ctrs = nullptr;       // step counter of every member
     hipStream_t stream = nullptr;      // the first member's stream
@@ -195,11 +201,49 @@ struct pss_batch {
     std::map<int64_t, hipGraphExec_t> graphs;
 };
 
+// Recorded forward run of the Model B adjoint: checkpoints of the state,
+// the final state, the terminal-seed coefficients and the workspace of the
+// reverse sweep, all owned by the tape until pss_tape_destroy.
+struct pss_tape {
+    pss_ctx* ctx = nullptr;
+    std::vector<void*> mem;  // device allocations
+    int64_t n0 = 0, nsteps = 0, nck = 0, seglen = 0;
+    int32_t ckpt = 0, ns = 0;
+    size_t fb = 0;  // bytes of one packed spectrum
+    double a = 0, b = 0, k = 0, D = 0, loss = 0;
+    uint64_t plan_gen = 0, state_gen = 0;
+    bool done = false;  // the reverse sweep has run
+    char* ck = nullptr;
+    char* seg = nullptr;
+    float2 *fT = nullptr, *G = nullptr, *R0 = nullptr, *R1 = nullptr, *X = nullptr, *W = nullptr, *U = nullptr;
+    double* acc = nullptr;
+    float* coef = nullptr;
+    pss::DevPlan* plan_row = nullptr;
+    pss::DevPlan* plan_raw = nullptr;
+};
+
 namespace {
 
 pss_status check_ctx(pss_ctx* c) {
     if (!c) return fail(PSS_E_INVAL, "null context");
     return PSS_OK;
+}
+
+void* tape_alloc(pss_tape* tp, size_t bytes) {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    tp->mem.push_back(p);
+    return p;
+}
+
+void tape_free(pss_tape* tp) {
+    if (tp->ctx && tp->ctx->stream) hipStreamSynchronize(tp->ctx->stream);
+    for (void* p : tp->mem) hipFree(p);
+    tp->mem.clear();
+}
+
+float2* tape_at(const pss_tape* tp, char* base, int64_t i) {
+    return reinterpret_cast<float2*>(base + tp->fb * static_cast<size_t>(i));
 }
 
 pss_status check_ops(const pss_qmono* op, int32_t n_mono, bool noise) {
@@ -428,6 +472,21 @@ pss_status build_plan(pss_ctx* c) {
         t.mono0 = 0;
         ++C.nprod;
     }
+    // Horner degree of every operator
+    auto set_deg = [](DevOp& op) {
+        op.deg = 0;
+        for (int j = PSS_MAXPOW; j > 0; --j)
+            if (op.poly[j] != 0.f) {
+                op.deg = j;
+                break;
+            }
+    };
+    for (int f = 0; f < nf; ++f) {
+        set_deg(P.implicit_op[f]);
+        set_deg(P.noise_op[f]);
+    }
+    for (int d = 0; d < P.nd; ++d) set_deg(P.direct[d].op);
+    for (int k = 0; k < P.nch; ++k) set_deg(P.ch[k].op);
     // kernels without the general-monomial code unless some operator needs it
     P.general = 0;
     for (int f = 0; f < nf; ++f) P.general |= (P.implicit_op[f].n > 0) | (P.noise_op[f].n > 0);
@@ -496,7 +555,7 @@ pss_status choose_geometry(pss_ctx* c) {
         if (!pow2(g.tz) || g.tz > nz || g.tz * ty > 256)
             return fail(PSS_E_UNSUPPORTED, "y-pass block (tz = %d) is too large", g.tz);
         g.nyblk = g.ntile * (nz / g.tz);
-        if (pss::ypass_lds_bytes(ny, g.tc, g.tz) > 160 * 1024)
+        if (pss::ypass_lds_bytes(ny, g.py, g.tc, g.tz) > 160 * 1024)
             return fail(PSS_E_UNSUPPORTED, "y pass needs more LDS than a workgroup has");
     }
     // x kernel: RB rows (pairs of T threads); aim for >= 512 blocks, 64..256 threads
@@ -513,8 +572,10 @@ pss_status choose_geometry(pss_ctx* c) {
     g.nrowblk = rows / rb;
     g.tc_log2 = 0;
     while ((1 << g.tc_log2) < g.tc) ++g.tc_log2;
-    const size_t lu_lds = pss::update_lds_bytes(lu, pss::field_slots(nf), g.tc, g.to);
-    const size_t lx_lds = pss::xrow_lds_bytes(nx, rb);
+    g.rb_log2 = 0;
+    while ((1 << g.rb_log2) < g.rb) ++g.rb_log2;
+    const size_t lu_lds = pss::update_lds_bytes(lu, g.pu, g.tc, g.to);
+    const size_t lx_lds = pss::xrow_lds_bytes(nx, g.px, rb);
     if (lu_lds > 160 * 1024 || lx_lds > 160 * 1024)
         return fail(PSS_E_UNSUPPORTED, "lattice needs more LDS than a workgroup has (%zu, %zu bytes)", lu_lds,
                     lx_lds);
@@ -552,6 +613,8 @@ void free_device(pss_ctx* c) {
     c->planned = false;
 }
 
+uint32_t* flag_of(pss_ctx* c) { return c->d_step ? reinterpret_cast<uint32_t*>(c->d_step + 1) : nullptr; }
+
 pss::LaunchArgs args(pss_ctx* c, int step_off = 0) {
     pss::LaunchArgs a{};
     a.stream = c->stream;
@@ -561,6 +624,7 @@ pss::LaunchArgs args(pss_ctx* c, int step_off = 0) {
     for (size_t g = 0; g < c->d_v.size(); ++g) a.bufs.V[g] = c->d_v[g];
     a.geo = c->geo;
     a.step_ctr = c->d_step;
+    a.flag = flag_of(c);
     a.members = c->d_member_u;
     a.plans = c->d_plan;
     a.nmem = 1;
@@ -584,11 +648,11 @@ pss::LaunchArgs xargs(pss_ctx* c) {
 // member-table entries of the update kernel and the x kernel of a context
 pss::Member member_u(pss_ctx* c) {
     const pss::LaunchArgs a = args(c);
-    return pss::Member{a.bufs, c->d_step};
+    return pss::Member{a.bufs, c->d_step, flag_of(c)};
 }
 pss::Member member_x(pss_ctx* c) {
     const pss::LaunchArgs a = xargs(c);
-    return pss::Member{a.bufs, c->d_step};
+    return pss::Member{a.bufs, c->d_step, flag_of(c)};
 }
 
 hipError_t y_inverse_factors(pss_ctx* c) {
@@ -658,8 +722,9 @@ pss_status materialize(pss_ctx* c) {
     HIP_TRY(hipMalloc(&c->d_tmp2, bytes));
     HIP_TRY(hipMalloc(&c->d_real, sizeof(float) * static_cast<size_t>(c->sites())));
     HIP_TRY(hipMalloc(&c->d_plan, sizeof(pss::DevPlan)));
-    HIP_TRY(hipMalloc(&c->d_step, sizeof(uint64_t)));
-    HIP_TRY(hipMemset(c->d_step, 0, sizeof(uint64_t)));
+    // the step counter and, in the next word, the non-finite flag
+    HIP_TRY(hipMalloc(&c->d_step, 2 * sizeof(uint64_t)));
+    HIP_TRY(hipMemset(c->d_step, 0, 2 * sizeof(uint64_t)));
     const auto twx = twiddles(c->n[0]);
     const auto twu = twiddles(c->lu);
     HIP_TRY(hipMalloc(&c->d_tw_x, sizeof(float2) * twx.size()));
@@ -697,19 +762,85 @@ pss_status prologue(pss_ctx* c) {
     return PSS_OK;
 }
 
+// Report (and clear) the non-finite flag that the update kernel raises when
+// a new state value is NaN or infinite.  The caller has synchronised.
+pss_status take_nonfinite(pss_ctx* c) {
+    if (!c->planned) return PSS_OK;
+    uint32_t f = 0;
+    HIP_TRY(hipMemcpy(&f, flag_of(c), sizeof(f), hipMemcpyDeviceToHost));
+    if (!f) return PSS_OK;
+    const uint32_t zero = 0;
+    HIP_TRY(hipMemcpy(flag_of(c), &zero, sizeof(zero), hipMemcpyHostToDevice));
+    return fail(PSS_E_NONFINITE, "a non-finite value appeared in the state (field mask 0x%x) at or before step %lld",
+                f, static_cast<long long>(c->steps_taken));
+}
+
+// Before the context enqueues work on its own stream: wait for the last batch
+// step that touched it, and note that its stream has new work (a batch then
+// orders itself after it).  Batches order themselves lazily, so that a batch
+// step costs no per-member API calls while the members are left alone.
+pss_status begin_work(pss_ctx* c) {
+    if (c->after_batch) {
+        HIP_TRY(hipStreamWaitEvent(c->stream, c->after_batch, 0));
+        c->after_batch = nullptr;
+    }
+    ++c->enq_gen;
+    return PSS_OK;
+}
+
+// Order the batch stream after the members' own work and after other batches
+// holding them; rebuild stale channel arrays first.
+pss_status batch_order_before(pss_batch* b, const std::vector<int>& which) {
+    for (int i : which) {
+        pss_ctx* c = b->mem[i];
+        if (c->dirty) {
+            if (pss_status s = begin_work(c)) return s;
+            if (pss_status s = prologue(c)) return s;
+        }
+        if (c->stream == b->stream) continue;
+        if (c->after_batch && c->after_batch != b->ev) HIP_TRY(hipStreamWaitEvent(b->stream, c->after_batch, 0));
+        if (c->enq_gen != b->seen[i]) {
+            HIP_TRY(hipEventRecord(b->ev, c->stream));
+            HIP_TRY(hipStreamWaitEvent(b->stream, b->ev, 0));
+            b->seen[i] = c->enq_gen;
+        }
+    }
+    return PSS_OK;
+}
+
+// after batch work: the members' own later work waits for it
+pss_status batch_order_after(pss_batch* b, const std::vector<int>& which) {
+    HIP_TRY(hipEventRecord(b->ev, b->stream));
+    for (int i : which) {
+        pss_ctx* c = b->mem[i];
+        if (c->stream != b->stream) c->after_batch = b->ev;
+    }
+    return PSS_OK;
+}
+
+// clear the flag when the state is replaced (uploads, loads)
+pss_status clear_nonfinite(pss_ctx* c) {
+    const uint32_t zero = 0;
+    HIP_TRY(hipMemcpy(flag_of(c), &zero, sizeof(zero), hipMemcpyHostToDevice));
+    return PSS_OK;
+}
+
 pss_status enqueue_steps(pss_ctx* c, int64_t k) {
     const int nf = static_cast<int>(c->fields.size());
-    const pss::LaunchArgs ax = xargs(c);
+    // in 2D the last x kernel of the sequence moves the step counter on
+    const bool x_advances = c->ndim == 2 && c->plan.nch > 0;
     for (int64_t i = 0; i < k; ++i) {
         pss::LaunchArgs a = args(c, static_cast<int>(i));
         HIP_TRY(pss::launch_update(pss::MODE_STEP, c->lu, nf, a));
         if (c->plan.nch > 0) {
             if (c->ndim == 3) HIP_TRY(y_inverse_factors(c));
+            pss::LaunchArgs ax = xargs(c);
+            ax.advance = (x_advances && i == k - 1) ? k : 0;
             HIP_TRY(pss::launch_xrow(pss::MODE_STEP, c->n[0], c->plan.ng, ax));
             if (c->ndim == 3) HIP_TRY(y_forward_channels(c));
         }
     }
-    HIP_TRY(pss::launch_advance(c->stream, c->d_step, k));
+    if (!x_advances) HIP_TRY(pss::launch_advance(c->stream, c->d_step, k));
     return PSS_OK;
 }
 
@@ -817,6 +948,10 @@ pss_status batch_refresh_plans(pss_batch* b) {
 }
 
 pss_status batch_enqueue(pss_batch* b, int64_t k) {
+    // classes with an x kernel move their members' counters on in the last
+    // step's x launch; the others need the counter kernel
+    bool all_x = true;
+    for (auto& cl : b->cls) all_x = all_x && cl.rep->plan.nch > 0;
     for (int64_t i = 0; i < k; ++i) {
         for (auto& cl : b->cls) {
             pss_ctx* r = cl.rep;
@@ -832,11 +967,12 @@ pss_status batch_enqueue(pss_batch* b, int64_t k) {
                 ax.members = cl.d_x;
                 ax.plans = cl.d_plans;
                 ax.nmem = a.nmem;
+                ax.advance = (all_x && i == k - 1) ? k : 0;
                 HIP_TRY(pss::launch_xrow(pss::MODE_STEP, r->n[0], r->plan.ng, ax));
             }
         }
     }
-    HIP_TRY(pss::launch_advance_many(b->stream, b->d_ctrs, static_cast<int>(b->mem.size()), k));
+    if (!all_x) HIP_TRY(pss::launch_advance_many(b->stream, b->d_ctrs, static_cast<int>(b->mem.size()), k));
     return PSS_OK;
 }
 
@@ -982,6 +1118,7 @@ pss_status pss_lattice_create(pss_ctx** out, int32_t ndim, const int64_t n[3], c
 pss_status pss_lattice_destroy(pss_ctx* c) {
     if (!c) return PSS_OK;
     if (c->batches > 0) return fail(PSS_E_STATE, "lattice is held by %d batch(es); destroy them first", c->batches);
+    if (c->tapes > 0) return fail(PSS_E_STATE, "an adjoint tape holds this lattice; destroy it first");
     free_device(c);
     delete c;
     return PSS_OK;
@@ -1114,6 +1251,12 @@ pss_status pss_dealias_set(pss_ctx* c, int32_t rule, int32_t shape) {
 
 pss_status pss_stream_set(pss_ctx* c, void* stream) {
     if (pss_status s = check_ctx(c)) return s;
+    // a batch launches on its first member's stream and orders itself
+    // against the others' streams: they must stay what they were
+    if (c->batches > 0)
+        return fail(PSS_E_STATE, "lattice is held by %d batch(es); destroy them before changing its stream",
+                    c->batches);
+    if (c->tapes > 0) return fail(PSS_E_STATE, "an adjoint tape holds this lattice; destroy it first");
     if (c->planned && c->stream) HIP_TRY(hipStreamSynchronize(c->stream));
     if (c->own_stream && c->stream) {
         hipStreamDestroy(c->stream);
@@ -1172,13 +1315,15 @@ pss_status pss_field_upload(pss_ctx* c, int32_t field, const float* real, int32_
     if (!real) return fail(PSS_E_INVAL, "null array");
     if (pss_status s = materialize(c)) return s;
     if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    if (pss_status s_bw = begin_work(c)) return s_bw;
     const size_t bytes = sizeof(float) * static_cast<size_t>(c->sites());
     HIP_TRY(hipMemcpyAsync(c->d_real, real, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                            c->stream));
     if (pss_status s = forward_to_state(c, field)) return s;
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->dirty = true;
-    return PSS_OK;
+    ++c->state_gen;
+    return clear_nonfinite(c);
 }
 
 pss_status pss_field_init_uniform(pss_ctx* c, int32_t field, double lo, double hi) {
@@ -1186,12 +1331,14 @@ pss_status pss_field_init_uniform(pss_ctx* c, int32_t field, double lo, double h
     if (!std::isfinite(lo) || !std::isfinite(hi)) return fail(PSS_E_INVAL, "non-finite bounds");
     if (pss_status s = materialize(c)) return s;
     if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    if (pss_status s_bw = begin_work(c)) return s_bw;
     HIP_TRY(pss::launch_init_uniform(c->stream, c->d_real, c->sites(), static_cast<uint32_t>(field),
                                      c->plan.key0, c->plan.key1, lo, hi));
     if (pss_status s = forward_to_state(c, field)) return s;
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->dirty = true;
-    return PSS_OK;
+    ++c->state_gen;
+    return clear_nonfinite(c);
 }
 
 pss_status pss_field_download(pss_ctx* c, int32_t field, float* real, int32_t on_device) {
@@ -1199,6 +1346,7 @@ pss_status pss_field_download(pss_ctx* c, int32_t field, float* real, int32_t on
     if (!real) return fail(PSS_E_INVAL, "null array");
     if (pss_status s = materialize(c)) return s;
     if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    if (pss_status s_bw = begin_work(c)) return s_bw;
     if (pss_status s = state_to_real(c, field)) return s;
     const size_t bytes = sizeof(float) * static_cast<size_t>(c->sites());
     HIP_TRY(hipMemcpyAsync(real, c->d_real, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
@@ -1212,6 +1360,7 @@ pss_status pss_spectrum_download(pss_ctx* c, int32_t field, float* half, int32_t
     if (!half) return fail(PSS_E_INVAL, "null array");
     if (pss_status s = materialize(c)) return s;
     if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    if (pss_status s_bw = begin_work(c)) return s_bw;
     std::vector<float2> S(static_cast<size_t>(c->packed()));
     HIP_TRY(hipMemcpyAsync(S.data(), c->d_state[field], sizeof(float2) * S.size(), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -1231,6 +1380,7 @@ pss_status pss_step(pss_ctx* c, int64_t nsteps) {
     if (nsteps < 0) return fail(PSS_E_INVAL, "negative step count");
     if (nsteps == 0) return PSS_OK;
     if (pss_status s = materialize(c)) return s;
+    if (pss_status s_bw = begin_work(c)) return s_bw;
     if (c->dirty)
         if (pss_status s = prologue(c)) return s;
     int64_t left = nsteps;
@@ -1242,6 +1392,21 @@ pss_status pss_step(pss_ctx* c, int64_t nsteps) {
         left -= k;
     }
     c->steps_taken += nsteps;
+    ++c->state_gen;
+    return PSS_OK;
+}
+
+pss_status pss_step_prepare(pss_ctx* c, int64_t nsteps) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (nsteps < 0) return fail(PSS_E_INVAL, "negative step count");
+    if (pss_status s = materialize(c)) return s;
+    // the chunk lengths pss_step(nsteps) replays: full chunks and the remainder
+    const int64_t lens[2] = {std::min(nsteps, kGraphSteps), nsteps % kGraphSteps};
+    for (int64_t k : lens) {
+        if (k <= 0) continue;
+        hipGraphExec_t ex = nullptr;
+        if (pss_status s = graph_for(c, k, &ex)) return s;
+    }
     return PSS_OK;
 }
 
@@ -1254,8 +1419,10 @@ pss_status pss_step_index(pss_ctx* c, int64_t* out) {
 
 pss_status pss_sync(pss_ctx* c) {
     if (pss_status s = check_ctx(c)) return s;
+    if (c->planned)
+        if (pss_status s = begin_work(c)) return s;
     if (c->stream) HIP_TRY(hipStreamSynchronize(c->stream));
-    return PSS_OK;
+    return take_nonfinite(c);
 }
 
 pss_status pss_state_size(pss_ctx* c, size_t* bytes) {
@@ -1271,6 +1438,7 @@ pss_status pss_state_save(pss_ctx* c, void* dst, size_t bytes) {
     pss_state_size(c, &need);
     if (!dst || bytes < need) return fail(PSS_E_INVAL, "state buffer needs %zu bytes", need);
     if (pss_status s = materialize(c)) return s;
+    if (pss_status s_bw = begin_work(c)) return s_bw;
     SaveHeader h{};
     std::memcpy(h.magic, "PSSSTAT1", 8);
     h.ndim = c->ndim;
@@ -1292,6 +1460,7 @@ pss_status pss_state_load(pss_ctx* c, const void* src, size_t bytes) {
     pss_state_size(c, &need);
     if (!src || bytes < need) return fail(PSS_E_INVAL, "state buffer needs %zu bytes", need);
     if (pss_status s = materialize(c)) return s;
+    if (pss_status s_bw = begin_work(c)) return s_bw;
     SaveHeader h;
     std::memcpy(&h, src, sizeof(h));
     if (std::memcmp(h.magic, "PSSSTAT1", 8) != 0 || h.ndim != c->ndim || h.nf != static_cast<int>(c->fields.size()) ||
@@ -1305,6 +1474,8 @@ pss_status pss_state_load(pss_ctx* c, const void* src, size_t bytes) {
     HIP_TRY(hipMemcpy(c->d_step, &st, sizeof(st), hipMemcpyHostToDevice));
     c->steps_taken = h.step;
     c->dirty = true;
+    ++c->state_gen;
+    if (pss_status s = clear_nonfinite(c)) return s;
     return PSS_OK;
 }
 
@@ -1313,6 +1484,7 @@ pss_status pss_mass(pss_ctx* c, int32_t field, double* mass) {
     if (!mass) return fail(PSS_E_INVAL, "null output");
     if (pss_status s = materialize(c)) return s;
     if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    if (pss_status s_bw = begin_work(c)) return s_bw;
     float2 v;
     HIP_TRY(hipMemcpyAsync(&v, c->d_state[field], sizeof(v), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -1325,6 +1497,7 @@ pss_status pss_structure_factor(pss_ctx* c, int32_t field, double* S, int64_t* c
     if (!S || !counts) return fail(PSS_E_INVAL, "null output");
     if (pss_status s = materialize(c)) return s;
     if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    if (pss_status s_bw = begin_work(c)) return s_bw;
     const int nmin = c->ndim == 3 ? std::min(std::min(c->n[0], c->n[1]), c->n[2]) : std::min(c->n[0], c->n[1]);
     const int ns = nmin / 2;  // shells j = 1 .. ns-1
     if (n_shells != ns - 1) return fail(PSS_E_INVAL, "n_shells must be %d", ns - 1);
@@ -1395,6 +1568,7 @@ pss_status pss_time_kernel(pss_ctx* c, int32_t which, int32_t reps, double* ms, 
     if (pss_status s = check_ctx(c)) return s;
     if (!ms || reps < 1) return fail(PSS_E_INVAL, "bad arguments");
     if (pss_status s = materialize(c)) return s;
+    if (pss_status s_bw = begin_work(c)) return s_bw;
     const int nk = c->ndim == 3 ? 4 : 2;
     if (which < 0 || which >= nk) return fail(PSS_E_INVAL, "kernel %d does not exist on this lattice", which);
     if (c->dirty)
@@ -1422,6 +1596,7 @@ pss_status pss_time_kernel(pss_ctx* c, int32_t which, int32_t reps, double* ms, 
     hipEventDestroy(e1);
     *ms = static_cast<double>(t) / reps;
     c->dirty = true;  // the channel arrays no longer match the state
+    ++c->state_gen;   // repeated step launches changed the state
     static const char* names[4] = {"update_kernel", "xrow_kernel", "ypass_kernel(inverse)", "ypass_kernel(forward)"};
     if (name) *name = names[which];
     return PSS_OK;
@@ -1518,12 +1693,15 @@ pss_status pss_autotune(pss_ctx* c, int32_t reps, double* us_per_step) {
     return PSS_OK;
 }
 
-pss_status pss_adjoint_model_b(pss_ctx* c, int64_t nsteps, int32_t ckpt_every, const double* S_target,
-                               int32_t n_shells, double* loss, double* grad, float* grad_phi0, int32_t on_device) {
+pss_status pss_adjoint_model_b_forward(pss_ctx* c, int64_t nsteps, int32_t ckpt_every, const double* S_target,
+                                       int32_t n_shells, double* loss, pss_tape** out) {
+    if (!out) return fail(PSS_E_INVAL, "null tape output");
+    *out = nullptr;
     if (pss_status s = check_ctx(c)) return s;
     if (nsteps < 1 || ckpt_every < 1) return fail(PSS_E_INVAL, "need nsteps >= 1 and ckpt_every >= 1");
-    if (!S_target || !loss || !grad) return fail(PSS_E_INVAL, "null argument");
+    if (!S_target || !loss) return fail(PSS_E_INVAL, "null argument");
     if (c->ndim != 2) return fail(PSS_E_UNSUPPORTED, "the adjoint is implemented for 2D lattices");
+    if (c->tapes > 0) return fail(PSS_E_STATE, "this lattice already holds an adjoint tape");
     // recognise Model B: one field; implicit -(a q^2 + k q^4); explicit -b q^2 F[phi^3]; noise D q^2
     double a = 0, b = 0, k = 0, D = 0;
     {
@@ -1556,59 +1734,56 @@ pss_status pss_adjoint_model_b(pss_ctx* c, int64_t nsteps, int32_t ckpt_every, c
                                            "explicit -b q^2 phi^3, noise D q^2)");
     }
     if (pss_status s = materialize(c)) return s;
+    if (pss_status s_bw = begin_work(c)) return s_bw;
     const int nx = c->n[0], ny = c->n[1];
     const int ns = std::min(nx, ny) / 2;
     if (n_shells != ns - 1) return fail(PSS_E_INVAL, "n_shells must be %d", ns - 1);
-    const int64_t nck = (nsteps + ckpt_every - 1) / ckpt_every;
-    const int64_t seglen = std::min<int64_t>(ckpt_every, nsteps);
-    const size_t fb = sizeof(float2) * static_cast<size_t>(c->packed());
 
+    auto* tp = new pss_tape();
+    tp->ctx = c;
+    tp->nsteps = nsteps;
+    tp->ckpt = ckpt_every;
+    tp->nck = (nsteps + ckpt_every - 1) / ckpt_every;
+    tp->seglen = std::min<int64_t>(ckpt_every, nsteps);
+    tp->fb = sizeof(float2) * static_cast<size_t>(c->packed());
+    tp->ns = ns;
+    tp->a = a;
+    tp->b = b;
+    tp->k = k;
+    tp->D = D;
+    auto bail = [&](pss_status st) {
+        tape_free(tp);
+        delete tp;
+        return st;
+    };
     // workspace: checkpoints, one recomputed segment, adjoint arrays
-    std::vector<void*> mem;
-    auto alloc = [&](size_t bytes) -> void* {
-        void* p = nullptr;
-        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
-        mem.push_back(p);
-        return p;
-    };
-    auto release = [&]() {
-        hipStreamSynchronize(c->stream);
-        for (void* p : mem) hipFree(p);
-        mem.clear();
-    };
-    auto* ck = static_cast<char*>(alloc(fb * static_cast<size_t>(nck)));
-    auto* seg = static_cast<char*>(alloc(fb * static_cast<size_t>(seglen + 1)));
-    auto* fT = static_cast<float2*>(alloc(fb));
-    auto* G = static_cast<float2*>(alloc(fb));
-    auto* R0 = static_cast<float2*>(alloc(fb));
-    auto* R1 = static_cast<float2*>(alloc(fb));
-    auto* X = static_cast<float2*>(alloc(fb));
-    auto* W = static_cast<float2*>(alloc(fb));
-    auto* U = static_cast<float2*>(alloc(fb));
-    auto* acc = static_cast<double*>(alloc(4 * sizeof(double)));
-    auto* coef = static_cast<float*>(alloc(sizeof(float) * ns));
-    auto* plan_row = static_cast<pss::DevPlan*>(alloc(sizeof(pss::DevPlan)));
-    auto* plan_raw = static_cast<pss::DevPlan*>(alloc(sizeof(pss::DevPlan)));
-    if (mem.size() != 13) {
-        release();
-        return fail(PSS_E_NOMEM, "adjoint workspace of %zu bytes does not fit", fb * (nck + seglen + 8));
-    }
-    auto at = [&](char* base, int64_t i) { return reinterpret_cast<float2*>(base + fb * static_cast<size_t>(i)); };
-#define ADJ_TRY(expr)            \
-    do {                         \
-        pss_status s_ = (expr);  \
-        if (s_) {                \
-            release();           \
-            return s_;           \
-        }                        \
+    const size_t fb = tp->fb;
+    tp->ck = static_cast<char*>(tape_alloc(tp, fb * static_cast<size_t>(tp->nck)));
+    tp->seg = static_cast<char*>(tape_alloc(tp, fb * static_cast<size_t>(tp->seglen + 1)));
+    tp->fT = static_cast<float2*>(tape_alloc(tp, fb));
+    tp->G = static_cast<float2*>(tape_alloc(tp, fb));
+    tp->R0 = static_cast<float2*>(tape_alloc(tp, fb));
+    tp->R1 = static_cast<float2*>(tape_alloc(tp, fb));
+    tp->X = static_cast<float2*>(tape_alloc(tp, fb));
+    tp->W = static_cast<float2*>(tape_alloc(tp, fb));
+    tp->U = static_cast<float2*>(tape_alloc(tp, fb));
+    tp->acc = static_cast<double*>(tape_alloc(tp, 4 * sizeof(double)));
+    tp->coef = static_cast<float*>(tape_alloc(tp, sizeof(float) * ns));
+    tp->plan_row = static_cast<pss::DevPlan*>(tape_alloc(tp, sizeof(pss::DevPlan)));
+    tp->plan_raw = static_cast<pss::DevPlan*>(tape_alloc(tp, sizeof(pss::DevPlan)));
+    if (tp->mem.size() != 13)
+        return bail(fail(PSS_E_NOMEM, "adjoint workspace of %zu bytes does not fit",
+                         fb * static_cast<size_t>(tp->nck + tp->seglen + 8)));
+#define TAPE_HIP(expr)                                                                                      \
+    do {                                                                                                    \
+        hipError_t e_ = (expr);                                                                             \
+        if (e_ != hipSuccess)                                                                               \
+            return bail(fail(PSS_E_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__)); \
     } while (0)
-#define ADJ_HIP(expr)                                                                              \
-    do {                                                                                           \
-        hipError_t e_ = (expr);                                                                    \
-        if (e_ != hipSuccess) {                                                                    \
-            release();                                                                             \
-            return fail(PSS_E_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
-        }                                                                                          \
+#define TAPE_TRY(expr)          \
+    do {                        \
+        pss_status s_ = (expr); \
+        if (s_) return bail(s_); \
     } while (0)
 
     // plans of the row pass (u from the kept columns, w from all) and of the
@@ -1619,22 +1794,22 @@ pss_status pss_adjoint_model_b(pss_ctx* c, int64_t nsteps, int32_t ckpt_every, c
     pr.ng = 2;
     pss::DevPlan pu = c->plan;
     pu.inv_n = 1.f;
-    ADJ_HIP(hipMemcpy(plan_row, &pr, sizeof(pr), hipMemcpyHostToDevice));
-    ADJ_HIP(hipMemcpy(plan_raw, &pu, sizeof(pu), hipMemcpyHostToDevice));
+    TAPE_HIP(hipMemcpy(tp->plan_row, &pr, sizeof(pr), hipMemcpyHostToDevice));
+    TAPE_HIP(hipMemcpy(tp->plan_raw, &pu, sizeof(pu), hipMemcpyHostToDevice));
 
     // forward run with a checkpoint every ckpt_every steps
-    const int64_t n0 = c->steps_taken;
-    for (int64_t sgi = 0; sgi < nck; ++sgi) {
-        if (c->dirty) ADJ_TRY(prologue(c));
-        ADJ_HIP(hipMemcpyAsync(at(ck, sgi), c->d_state[0], fb, hipMemcpyDeviceToDevice, c->stream));
-        ADJ_TRY(pss_step(c, std::min<int64_t>(ckpt_every, nsteps - sgi * ckpt_every)));
+    tp->n0 = c->steps_taken;
+    for (int64_t sgi = 0; sgi < tp->nck; ++sgi) {
+        if (c->dirty) TAPE_TRY(prologue(c));
+        TAPE_HIP(hipMemcpyAsync(tape_at(tp, tp->ck, sgi), c->d_state[0], fb, hipMemcpyDeviceToDevice, c->stream));
+        TAPE_TRY(pss_step(c, std::min<int64_t>(ckpt_every, nsteps - sgi * ckpt_every)));
     }
-    ADJ_HIP(hipMemcpyAsync(fT, c->d_state[0], fb, hipMemcpyDeviceToDevice, c->stream));
+    TAPE_HIP(hipMemcpyAsync(tp->fT, c->d_state[0], fb, hipMemcpyDeviceToDevice, c->stream));
 
     // loss and terminal seed from the shell averages of the final spectrum
     std::vector<double> S(ns - 1);
     std::vector<int64_t> cnt(ns - 1);
-    ADJ_TRY(pss_structure_factor(c, 0, S.data(), cnt.data(), ns - 1));
+    TAPE_TRY(pss_structure_factor(c, 0, S.data(), cnt.data(), ns - 1));
     const double dV = c->dx[0] * c->dx[1];
     const double N = static_cast<double>(c->sites());
     double L = 0;
@@ -1644,50 +1819,80 @@ pss_status pss_adjoint_model_b(pss_ctx* c, int64_t nsteps, int32_t ckpt_every, c
         L += d * d;
         cf[j] = static_cast<float>(2.0 * d / std::max<int64_t>(cnt[j - 1], 1) * (dV / N) * 2.0);
     }
-    ADJ_HIP(hipMemcpy(coef, cf.data(), sizeof(float) * ns, hipMemcpyHostToDevice));
-    ADJ_HIP(pss::launch_adjseed(c->stream, fT, G, coef, ns, nx, ny, c->geo.tc));
-    ADJ_HIP(hipMemsetAsync(acc, 0, 4 * sizeof(double), c->stream));
+    TAPE_HIP(hipMemcpy(tp->coef, cf.data(), sizeof(float) * ns, hipMemcpyHostToDevice));
+#undef TAPE_HIP
+#undef TAPE_TRY
+    tp->loss = L;
+    tp->plan_gen = c->plan_gen;
+    tp->state_gen = c->state_gen;
+    ++c->tapes;
+    *loss = L;
+    *out = tp;
+    return PSS_OK;
+}
+
+pss_status pss_adjoint_model_b_backward(pss_tape* tp, double* grad, float* grad_phi0, int32_t on_device) {
+    if (!tp) return fail(PSS_E_INVAL, "null tape");
+    if (!grad) return fail(PSS_E_INVAL, "null gradient output");
+    if (tp->done) return fail(PSS_E_STATE, "the reverse sweep of this tape has already run");
+    pss_ctx* c = tp->ctx;
+    if (c->plan_gen != tp->plan_gen || c->state_gen != tp->state_gen)
+        return fail(PSS_E_STATE, "the lattice changed (coefficients, seed or state) after the forward run");
+    if (pss_status s = begin_work(c)) return s;
+    const int nx = c->n[0], ny = c->n[1];
+    const size_t fb = tp->fb;
+#define ADJ_HIP(expr)                                                                                \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess)                                                                        \
+            return fail(PSS_E_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+    } while (0)
+    tp->done = true;
+    ADJ_HIP(pss::launch_adjseed(c->stream, tp->fT, tp->G, tp->coef, tp->ns, nx, ny, c->geo.tc));
+    ADJ_HIP(hipMemsetAsync(tp->acc, 0, 4 * sizeof(double), c->stream));
 
     // reverse sweep: recompute each segment from its checkpoint, then step back
     pss::AdjArgs aa{};
     aa.plan = c->d_plan;
-    aa.G = G;
-    aa.X = X;
-    aa.W = W;
-    aa.U = U;
-    aa.acc = acc;
-    aa.a = static_cast<float>(a);
-    aa.b = static_cast<float>(b);
-    aa.k = static_cast<float>(k);
-    aa.D = static_cast<float>(D);
+    aa.G = tp->G;
+    aa.X = tp->X;
+    aa.W = tp->W;
+    aa.U = tp->U;
+    aa.acc = tp->acc;
+    aa.a = static_cast<float>(tp->a);
+    aa.b = static_cast<float>(tp->b);
+    aa.k = static_cast<float>(tp->k);
+    aa.D = static_cast<float>(tp->D);
     aa.first = 1;
-    float2* Rcur = R0;
-    float2* Rnxt = R1;
+    float2* Rcur = tp->R0;
+    float2* Rnxt = tp->R1;
     pss::LaunchArgs ax = args(c);
-    ax.plan = plan_row;
+    ax.plan = tp->plan_row;
     ax.bufs = pss::Bufs{};
-    ax.bufs.V[0] = U;
-    ax.bufs.V[1] = W;
-    ax.bufs.N[0] = X;
-    ax.bufs.acc = acc + 1;
-    for (int64_t sgi = nck - 1; sgi >= 0; --sgi) {
-        const int64_t start = sgi * ckpt_every;
-        const int64_t len = std::min<int64_t>(ckpt_every, nsteps - start);
+    ax.bufs.V[0] = tp->U;
+    ax.bufs.V[1] = tp->W;
+    ax.bufs.N[0] = tp->X;
+    ax.bufs.acc = tp->acc + 1;
+    const int64_t n0 = tp->n0, nsteps = tp->nsteps;
+    for (int64_t sgi = tp->nck - 1; sgi >= 0; --sgi) {
+        const int64_t start = sgi * tp->ckpt;
+        const int64_t len = std::min<int64_t>(tp->ckpt, nsteps - start);
         const uint64_t st = static_cast<uint64_t>(n0 + start);
         ADJ_HIP(hipStreamSynchronize(c->stream));
         ADJ_HIP(hipMemcpy(c->d_step, &st, sizeof(st), hipMemcpyHostToDevice));
-        ADJ_HIP(hipMemcpyAsync(c->d_state[0], at(ck, sgi), fb, hipMemcpyDeviceToDevice, c->stream));
-        ADJ_HIP(hipMemcpyAsync(at(seg, 0), at(ck, sgi), fb, hipMemcpyDeviceToDevice, c->stream));
-        ADJ_TRY(prologue(c));
+        ADJ_HIP(hipMemcpyAsync(c->d_state[0], tape_at(tp, tp->ck, sgi), fb, hipMemcpyDeviceToDevice, c->stream));
+        ADJ_HIP(hipMemcpyAsync(tape_at(tp, tp->seg, 0), tape_at(tp, tp->ck, sgi), fb, hipMemcpyDeviceToDevice,
+                               c->stream));
+        if (pss_status s = prologue(c)) return s;
         for (int64_t i = 1; i <= len; ++i) {
-            ADJ_TRY(enqueue_steps(c, 1));
-            ADJ_HIP(hipMemcpyAsync(at(seg, i), c->d_state[0], fb, hipMemcpyDeviceToDevice, c->stream));
+            if (pss_status s = enqueue_steps(c, 1)) return s;
+            ADJ_HIP(hipMemcpyAsync(tape_at(tp, tp->seg, i), c->d_state[0], fb, hipMemcpyDeviceToDevice, c->stream));
         }
         for (int64_t i = len - 1; i >= 0; --i) {
             aa.Rin = Rcur;
             aa.Rout = Rnxt;
-            aa.phi1 = at(seg, i + 1);
-            aa.phi0 = at(seg, i);
+            aa.phi1 = tape_at(tp, tp->seg, i + 1);
+            aa.phi0 = tape_at(tp, tp->seg, i);
             aa.step = static_cast<uint32_t>(n0 + start + i);
             ADJ_HIP(pss::launch_adjcol(pss::MODE_ADJCOL, ny, aa, args(c)));
             ADJ_HIP(pss::launch_xrow(pss::MODE_ADJROW, nx, 2, ax));
@@ -1697,14 +1902,14 @@ pss_status pss_adjoint_model_b(pss_ctx* c, int64_t nsteps, int32_t ckpt_every, c
     }
     // g_0, and the gradient for the real initial field: N F^-1[g_0]
     aa.Rin = Rcur;
-    aa.Rout = G;
+    aa.Rout = tp->G;
     ADJ_HIP(pss::launch_adjcol(pss::MODE_ADJFIN, ny, aa, args(c)));
-    std::vector<double> gh(4);
-    ADJ_HIP(hipMemcpyAsync(gh.data(), acc, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    double gh[4];
+    ADJ_HIP(hipMemcpyAsync(gh, tp->acc, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     if (grad_phi0) {
         pss::LaunchArgs a1 = args(c);
-        a1.plan = plan_raw;
-        a1.bufs.S[0] = G;
+        a1.plan = tp->plan_raw;
+        a1.bufs.S[0] = tp->G;
         a1.bufs.sel = 0;
         a1.bufs.out = c->d_tmp;
         ADJ_HIP(pss::launch_update(pss::MODE_INV_OUT, c->lu, 1, a1));
@@ -1718,15 +1923,31 @@ pss_status pss_adjoint_model_b(pss_ctx* c, int64_t nsteps, int32_t ckpt_every, c
     const uint64_t fin = static_cast<uint64_t>(n0 + nsteps);
     ADJ_HIP(hipStreamSynchronize(c->stream));
     ADJ_HIP(hipMemcpy(c->d_step, &fin, sizeof(fin), hipMemcpyHostToDevice));
-    ADJ_HIP(hipMemcpy(c->d_state[0], fT, fb, hipMemcpyDeviceToDevice));
+    ADJ_HIP(hipMemcpy(c->d_state[0], tp->fT, fb, hipMemcpyDeviceToDevice));
+#undef ADJ_HIP
     c->steps_taken = n0 + nsteps;
     c->dirty = true;
-    release();
-#undef ADJ_TRY
-#undef ADJ_HIP
-    *loss = L;
+    ++c->state_gen;
     for (int i = 0; i < 4; ++i) grad[i] = gh[i];
     return PSS_OK;
+}
+
+pss_status pss_tape_destroy(pss_tape* tp) {
+    if (!tp) return PSS_OK;
+    tape_free(tp);
+    --tp->ctx->tapes;
+    delete tp;
+    return PSS_OK;
+}
+
+pss_status pss_adjoint_model_b(pss_ctx* c, int64_t nsteps, int32_t ckpt_every, const double* S_target,
+                               int32_t n_shells, double* loss, double* grad, float* grad_phi0, int32_t on_device) {
+    if (!grad) return fail(PSS_E_INVAL, "null argument");
+    pss_tape* tp = nullptr;
+    if (pss_status s = pss_adjoint_model_b_forward(c, nsteps, ckpt_every, S_target, n_shells, loss, &tp)) return s;
+    const pss_status s = pss_adjoint_model_b_backward(tp, grad, grad_phi0, on_device);
+    pss_tape_destroy(tp);
+    return s;
 }
 
 pss_status pss_batch_create(pss_batch** out, pss_ctx* const* lattices, int32_t n, const uint64_t* seeds) {
@@ -1746,6 +1967,8 @@ pss_status pss_batch_create(pss_batch** out, pss_ctx* const* lattices, int32_t n
     }
     auto* b = new pss_batch();
     b->mem.assign(lattices, lattices + n);
+    b->seen.assign(n, ~uint64_t{0});
+    for (int32_t i = 0; i < n; ++i) b->all.push_back(i);
     for (int32_t i = 0; i < n; ++i) {
         auto it = std::find_if(b->cls.begin(), b->cls.end(),
                                [&](const pss_batch::Class& cl) { return same_class(cl.rep, lattices[i]); });
@@ -1795,7 +2018,10 @@ pss_status pss_batch_create(pss_batch** out, pss_ctx* const* lattices, int32_t n
 pss_status pss_batch_destroy(pss_batch* b) {
     if (!b) return PSS_OK;
     if (b->stream) hipStreamSynchronize(b->stream);
-    for (pss_ctx* c : b->mem) --c->batches;
+    for (pss_ctx* c : b->mem) {
+        --c->batches;
+        if (c->after_batch == b->ev) c->after_batch = nullptr;  // its work is done
+    }
     free_batch(b);
     delete b;
     return PSS_OK;
@@ -1805,16 +2031,9 @@ pss_status pss_batch_step(pss_batch* b, int64_t nsteps) {
     if (!b) return fail(PSS_E_INVAL, "null batch");
     if (nsteps < 0) return fail(PSS_E_INVAL, "negative step count");
     if (nsteps == 0) return PSS_OK;
-    // channel arrays of every member must match its state; then order the
-    // batch stream after every member's stream
-    for (pss_ctx* c : b->mem) {
-        if (c->dirty)
-            if (pss_status s = prologue(c)) return s;
-        if (c->stream != b->stream) {
-            HIP_TRY(hipEventRecord(b->ev, c->stream));
-            HIP_TRY(hipStreamWaitEvent(b->stream, b->ev, 0));
-        }
-    }
+    // channel arrays of every member must match its state; the batch stream
+    // comes after every member's own work
+    if (pss_status s = batch_order_before(b, b->all)) return s;
     if (pss_status s = batch_refresh_plans(b)) return s;
     int64_t left = nsteps;
     while (left > 0) {
@@ -1825,10 +2044,10 @@ pss_status pss_batch_step(pss_batch* b, int64_t nsteps) {
         left -= k;
     }
     // later work on any member's stream comes after the batch
-    HIP_TRY(hipEventRecord(b->ev, b->stream));
+    if (pss_status s = batch_order_after(b, b->all)) return s;
     for (pss_ctx* c : b->mem) {
-        if (c->stream != b->stream) HIP_TRY(hipStreamWaitEvent(c->stream, b->ev, 0));
         c->steps_taken += nsteps;
+        ++c->state_gen;
     }
     return PSS_OK;
 }
@@ -1836,7 +2055,12 @@ pss_status pss_batch_step(pss_batch* b, int64_t nsteps) {
 pss_status pss_batch_sync(pss_batch* b) {
     if (!b) return fail(PSS_E_INVAL, "null batch");
     HIP_TRY(hipStreamSynchronize(b->stream));
-    return PSS_OK;
+    pss_status st = PSS_OK;
+    for (pss_ctx* c : b->mem) {
+        const pss_status s = take_nonfinite(c);
+        if (s && !st) st = s;  // report the first member, clear every flag
+    }
+    return st;
 }
 
 pss_status pss_batch_info(pss_batch* b, int32_t* n_classes, int32_t* class_of) {
@@ -1856,15 +2080,7 @@ pss_status pss_batch_time_kernel(pss_batch* b, int32_t cls, int32_t which, int32
     const auto& cl = b->cls[cls];
     pss_ctx* r = cl.rep;
     if (which == 1 && r->plan.nch == 0) return fail(PSS_E_INVAL, "class %d has no x kernel", cls);
-    for (int i : cl.idx) {
-        pss_ctx* c = b->mem[i];
-        if (c->dirty)
-            if (pss_status s = prologue(c)) return s;
-        if (c->stream != b->stream) {
-            HIP_TRY(hipEventRecord(b->ev, c->stream));
-            HIP_TRY(hipStreamWaitEvent(b->stream, b->ev, 0));
-        }
-    }
+    if (pss_status s = batch_order_before(b, cl.idx)) return s;
     if (pss_status s = batch_refresh_plans(b)) return s;
     pss::LaunchArgs a = which == 0 ? args(r) : xargs(r);
     a.stream = b->stream;
@@ -1893,7 +2109,11 @@ pss_status pss_batch_time_kernel(pss_batch* b, int32_t cls, int32_t which, int32
         if (pss_status s = pss_kernel_bytes(r, which, &one)) return s;
         *bytes = one * static_cast<double>(cl.idx.size());
     }
-    for (int i : cl.idx) b->mem[i]->dirty = true;  // repeated launches leave the channels stale
+    for (int i : cl.idx) {  // repeated launches leave the channels stale and change the states
+        b->mem[i]->dirty = true;
+        ++b->mem[i]->state_gen;
+    }
+    if (pss_status s = batch_order_after(b, cl.idx)) return s;
     return PSS_OK;
 }
 

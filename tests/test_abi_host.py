@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_2405_02410_amd as pss
@@ -152,3 +153,20 @@ def test_autotune_arguments():
     with pytest.raises(PssError) as e:
         lat.autotune(reps=0)
     assert e.value.name == "PSS_E_INVAL"
+
+
+def test_tape_and_prepare_arguments_without_device():
+    lib = pss.lib()
+    assert lib.pss_tape_destroy(None) == 0
+    grad = (ctypes.c_double * 4)()
+    assert lib.pss_adjoint_model_b_backward(None, grad, None, 0) == -1
+    assert lib.pss_step_prepare(None, 5) == -1
+    lat = _lat()
+    pss.model_b(lat)
+    with pytest.raises(PssError) as e:
+        lat.prepare(-1)
+    assert e.value.name == "PSS_E_INVAL"
+    with pytest.raises(PssError) as e:
+        lat.adjoint_forward(0, np.zeros(31))
+    assert e.value.name == "PSS_E_INVAL"
+

@@ -174,3 +174,25 @@ def test_full_ensemble_configuration_sampled():
         twin.step(25)
         assert np.array_equal(mem[i].spectrum(0), twin.spectrum(0)), i
     batch.close()
+
+
+def test_member_stream_is_fixed_while_a_batch_holds_it():
+    import torch
+    lats = []
+    for s in (1, 2):
+        lat = pss.Lattice((64, 64), dt=0.01, seed=s)
+        f, _ = pss.model_b(lat)
+        lat.init_uniform(f)
+        lats.append(lat)
+    b = pss.Batch(lats)
+    st = torch.cuda.Stream()
+    with pytest.raises(pss.PssError) as e:
+        lats[0].stream(st.cuda_stream)
+    assert e.value.name == "PSS_E_STATE"
+    b.step(3)
+    b.sync()
+    b.close()
+    lats[0].stream(st.cuda_stream)  # allowed once the batch is gone
+    lats[0].step(2)
+    lats[0].sync()
+    assert lats[0].step_index == 5

@@ -239,6 +239,73 @@ def test_model_b_1024_full_size():
     assert _rel(S, so) < 1e-4
 
 
+def test_model_b_1024_after_100_steps():
+    """The full-size workload lattice, pointwise against the FP64 oracle at step
+    100 (the stated 1e-4 bar), with the mass checked every 20 steps."""
+    import os
+    from oracle import spectral
+    spectral.WORKERS = os.cpu_count() or 1
+    try:
+        lat, m = _model_b_pair((1024, 1024), 100)
+        mass0 = lat.mass(0)
+        for _ in range(5):
+            lat.step(20)
+            m.step(20)
+            phi = lat.download(0)
+            assert abs(lat.mass(0) - mass0) <= 1e-6 * np.sum(np.abs(phi))
+        err = np.max(np.abs(lat.download(0) - m.real(0)[0]))
+        assert err <= 1e-4, err
+    finally:
+        spectral.WORKERS = 1
+
+
+def _multi_field(n, nf, seed, dt=0.005, D=0.004):
+    """nf coupled fields (3 or 4): each relaxes with its own implicit operator,
+    has a cubic self term and a product of all fields in its explicit terms,
+    so every field is a factor of a product of three or four fields."""
+    coef = [(-0.6, 1.0), (0.4, 0.7), (-0.2, 1.3), (0.3, 0.9)][:nf]
+    lat = pss.Lattice(n, dt=dt, seed=seed)
+    m = om.Model(_olat(n), dt, seed=seed)
+    fl = [lat.field(f"f{i}") for i in range(nf)]
+    fo = [m.add_field(f"f{i}") for i in range(nf)]
+    for i in range(nf):
+        c0, k2 = coef[i]
+        imp = [(-c0, 0), (-k2, 1)] if i % 2 == 0 else [(-c0, 1), (-k2, 2)]
+        lat.term(fl[i], [Mono(c, q2=q) for c, q in imp], [(fl[i], 1)], implicit=True)
+        m.add_term(fo[i], [OMono(c, q2=q) for c, q in imp], [(fo[i], 1)], implicit=True)
+        cub = [Mono(-1.0)] if i % 2 == 0 else [Mono(-1.0, q2=1)]
+        lat.term(fl[i], cub, [(fl[i], 3)])
+        m.add_term(fo[i], [OMono(mo.coef, q2=mo.q2) for mo in cub], [(fo[i], 3)])
+        others = [j for j in range(nf) if j != i]
+        prod = [(fl[j], 1) for j in others]
+        lat.term(fl[i], [Mono(0.3 - 0.1 * i)], prod)
+        m.add_term(fo[i], [OMono(0.3 - 0.1 * i)], [(fo[j], 1) for j in others])
+        lat.term(fl[i], [Mono(0.2, q2=1)], [(fl[(i + 1) % nf], 2)])
+        m.add_term(fo[i], [OMono(0.2, q2=1)], [(fo[(i + 1) % nf], 2)])
+        nz = [Mono(D)] if i % 2 == 0 else [Mono(D, q2=1)]
+        lat.noise(fl[i], nz)
+        m.set_noise(fo[i], [OMono(mo.coef, q2=mo.q2) for mo in nz])
+    for i in range(nf):
+        lat.init_uniform(fl[i], -0.2, 0.2)
+        m.init_uniform(fo[i], -0.2, 0.2)
+    return lat, m
+
+
+@pytest.mark.parametrize("n,nf", [((64, 64), 3), ((32, 64), 4), ((64, 32), 4), ((16, 16, 32), 3)])
+def test_three_and_four_coupled_fields(n, nf):
+    # reaches the kernels built for 4 register arrays (update) and for 3 and
+    # 4 factor fields (x kernel)
+    lat, m = _multi_field(n, nf, seed=13)
+    lat.step(25)
+    m.step(25)
+    for i in range(nf):
+        got = lat.download(i)
+        want = m.real(i)
+        if len(n) == 2:
+            want = want[0]
+        assert np.max(np.abs(got - want)) <= 2e-5 * max(1.0, np.max(np.abs(want))), i
+
+
 def test_two_field_products_2d():
     n, dt = (64, 64), 0.005
     a_, b_, k_, c_, g_, D_ = -1.0, 1.0, 1.0, -0.5, 0.3, 0.005
@@ -354,3 +421,41 @@ def test_launch_geometry_3d_is_bitwise(kw):
         lat.step(10)
         out.append(lat.spectrum(f))
     assert np.array_equal(out[0], out[1])
+
+
+def test_nonfinite_state_is_reported_once_by_sync():
+    lat, _ = _model_b_pair((64, 64), 0, seed=3, D=0.01)
+    f = 0
+    bad = inputs.random_field((64, 64), 5)
+    bad[7, 9] = np.nan
+    lat.upload(f, bad)
+    lat.step(3)
+    with pytest.raises(pss.PssError) as e:
+        lat.sync()
+    assert e.value.name == "PSS_E_NONFINITE"
+    lat.sync()  # reported once, then cleared
+    lat.upload(f, inputs.random_field((64, 64), 6))  # a finite state clears it too
+    lat.step(3)
+    lat.sync()
+    assert np.all(np.isfinite(lat.download(f)))
+
+
+def test_nonfinite_member_is_reported_by_the_batch():
+    lats = []
+    for s in (1, 2, 3):
+        lat = pss.Lattice((32, 32), dt=0.01, seed=s)
+        f, _ = pss.model_b(lat)
+        lat.init_uniform(f)
+        lats.append(lat)
+    bad = inputs.random_field((32, 32), 2)
+    bad[0, 0] = np.inf
+    lats[1].upload(0, bad)
+    b = pss.Batch(lats)
+    b.step(2)
+    with pytest.raises(pss.PssError) as e:
+        b.sync()
+    assert e.value.name == "PSS_E_NONFINITE"
+    b.step(1)
+    with pytest.raises(pss.PssError):  # the state stays non-finite
+        b.sync()
+    b.close()
