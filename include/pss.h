@@ -240,6 +240,20 @@ pss_status pss_mass(pss_ctx *ctx, int32_t field, double *mass);
 pss_status pss_structure_factor(pss_ctx *ctx, int32_t field, double *S, int64_t *counts,
                                 int32_t n_shells);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: tight serving or monitoring loops, harnesses that forbid it):
+ * the result of pss_structure_factor, computed without any device or host
+ * allocation.  The shell sums and counts live in a static device array of the
+ * library (32 KiB per GPU, held until the process ends) instead of buffers
+ * allocated on first use; n_shells above 2047 is PSS_E_UNSUPPORTED (every
+ * lattice of at most 4096 per axis fits).  The plan must already be built
+ * (PSS_E_STATE otherwise: building it allocates).  Writes S and counts as
+ * pss_structure_factor does; synchronous on the context's stream.  All calls
+ * on one GPU share the array: calls that overlap in time on one GPU (other
+ * threads, other streams) race and must be serialised by the caller. */
+pss_status pss_structure_factor_noalloc(pss_ctx *ctx, int32_t field, double *S, int64_t *counts,
+                                        int32_t n_shells);
+
 /* ---- utilities --------------------------------------------------------- */
 
 /* Philox4x32-10 words for counters (c0 + i, c1, c2, c3), i = 0..count-1, with

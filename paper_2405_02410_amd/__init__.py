@@ -96,6 +96,8 @@ _SIGS = {
                                      ctypes.c_int32],
     "pss_tape_destroy": [ctypes.c_void_p],
     "pss_step_prepare": [ctypes.c_void_p, ctypes.c_int64],
+    "pss_structure_factor_noalloc": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_int32],
     "pss_batch_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
                          ctypes.POINTER(ctypes.c_uint64)],
     "pss_batch_destroy": [ctypes.c_void_p],
@@ -305,6 +307,16 @@ class Lattice:
         v = ctypes.c_double()
         _check(lib().pss_mass(self._h, int(field), ctypes.byref(v)))
         return v.value
+
+    def structure_factor_noalloc(self, field):
+        """structure_factor through the allocation-free entry point (the plan
+        must be built)."""
+        ns = min(n for n in self.n) // 2 - 1
+        S = np.zeros(ns, dtype=np.float64)
+        cnt = np.zeros(ns, dtype=np.int64)
+        _check(lib().pss_structure_factor_noalloc(self._h, int(field), S.ctypes.data_as(ctypes.c_void_p),
+                                                  cnt.ctypes.data_as(ctypes.c_void_p), ns))
+        return S, cnt
 
     def structure_factor(self, field):
         ns = min(n for n in self.n) // 2 - 1

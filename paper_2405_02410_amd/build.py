@@ -53,6 +53,9 @@ def build(jobs=None, verbose=False):
     o = os.path.join(BUILD, "kern_common.o")
     cmds.append([hipcc, *HIPCC_FLAGS, "-DPSS_COMMON", "-c", src, "-o", o])
     objs.append(o)
+    o = os.path.join(BUILD, "noalloc.o")
+    cmds.append([hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, "pss_noalloc.hip"), "-o", o])
+    objs.append(o)
     o = os.path.join(BUILD, "runtime.o")
     cmds.append([hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, "pss_runtime.cpp"), "-o", o])
     objs.append(o)

@@ -164,6 +164,13 @@ inline size_t xrow_lds_bytes(int L, int P, int rb) {
     return sizeof(float2) * (fft_lds(L, P, rb / 2) + static_cast<size_t>(L));
 }
 
+// Allocation-free reductions (pss_noalloc.hip): the device address of the
+// file-scope scratch array on the current device, looked up once per device,
+// and a fill kernel that clears n 64-bit words of it
+constexpr int kScratchShells = 2048;
+hipError_t scratch_address(void** out);
+hipError_t launch_zero_words(hipStream_t s, unsigned long long* p, int n);
+
 // FP64 shell sums of (dV/N)|phi_hat|^2 over the packed state of one field
 hipError_t launch_shells(hipStream_t s, const float2* S, int nx, int ny, int nz, int tc, int ndim,
                          double scale, int nshell, double* sums, unsigned long long* counts);

@@ -1523,6 +1523,38 @@ pss_status pss_structure_factor(pss_ctx* c, int32_t field, double* S, int64_t* c
     return PSS_OK;
 }
 
+pss_status pss_structure_factor_noalloc(pss_ctx* c, int32_t field, double* S, int64_t* counts, int32_t n_shells) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (!S || !counts) return fail(PSS_E_INVAL, "null output");
+    if (!c->planned) return fail(PSS_E_STATE, "the plan is not built (building it allocates device memory)");
+    if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    if (pss_status s_bw = begin_work(c)) return s_bw;
+    const int nmin = c->ndim == 3 ? std::min(std::min(c->n[0], c->n[1]), c->n[2]) : std::min(c->n[0], c->n[1]);
+    const int ns = nmin / 2;  // shells j = 1 .. ns-1
+    if (n_shells != ns - 1) return fail(PSS_E_INVAL, "n_shells must be %d", ns - 1);
+    if (ns > pss::kScratchShells)
+        return fail(PSS_E_UNSUPPORTED, "%d shells exceed the %d of the static scratch", ns, pss::kScratchShells);
+    void* base = nullptr;
+    HIP_TRY(pss::scratch_address(&base));
+    double* sums = static_cast<double*>(base);
+    auto* cnt = reinterpret_cast<unsigned long long*>(sums + pss::kScratchShells);
+    // the previous call's contents are still there: clear what is summed into
+    HIP_TRY(pss::launch_zero_words(c->stream, reinterpret_cast<unsigned long long*>(sums), ns));
+    HIP_TRY(pss::launch_zero_words(c->stream, cnt, ns));
+    const double dV = c->dx[0] * c->dx[1] * (c->ndim == 3 ? c->dx[2] : 1.0);
+    HIP_TRY(pss::launch_shells(c->stream, c->d_state[field], c->n[0], c->n[1], c->ndim == 3 ? c->n[2] : 1, c->geo.tc,
+                               c->ndim, dV / static_cast<double>(c->sites()), ns, sums, cnt));
+    // shells 1 .. ns-1 straight into the caller's arrays, then averaged in place
+    static_assert(sizeof(int64_t) == sizeof(unsigned long long), "count width");
+    if (ns > 1) {
+        HIP_TRY(hipMemcpyAsync(S, sums + 1, sizeof(double) * (ns - 1), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipMemcpyAsync(counts, cnt + 1, sizeof(int64_t) * (ns - 1), hipMemcpyDeviceToHost, c->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int j = 0; j < ns - 1; ++j) S[j] = counts[j] ? S[j] / static_cast<double>(counts[j]) : 0.0;
+    return PSS_OK;
+}
+
 pss_status pss_util_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
                            int64_t count, uint32_t* out) {
     if (!out || count < 0) return fail(PSS_E_INVAL, "bad arguments");

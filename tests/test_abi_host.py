@@ -170,3 +170,14 @@ def test_tape_and_prepare_arguments_without_device():
         lat.adjoint_forward(0, np.zeros(31))
     assert e.value.name == "PSS_E_INVAL"
 
+
+def test_noalloc_reduction_needs_a_built_plan():
+    lat = _lat()
+    pss.model_b(lat)
+    with pytest.raises(PssError) as e:
+        lat.structure_factor_noalloc(0)
+    assert e.value.name == "PSS_E_STATE"
+    lib = pss.lib()
+    S = (ctypes.c_double * 31)()
+    cnt = (ctypes.c_int64 * 31)()
+    assert lib.pss_structure_factor_noalloc(None, 0, S, cnt, 31) == -1
