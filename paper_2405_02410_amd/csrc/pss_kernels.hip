@@ -13,11 +13,20 @@
 //
 // The spectral arrays use the packed half-spectrum layout described in
 // pss_plan.h: column 0 holds X(kx=0) + i X(kx=Nx/2).  Line transforms are the
-// register/LDS transforms of pss_fft.h: a forward transform gathers its input
-// at the digit-reversed positions and returns natural order (dit), an inverse
-// transform takes natural order and its output is scattered to the
-// digit-reversed positions (dif), so every per-mode computation sees natural
-// mode order.  A line is held by consecutive threads.
+// register/LDS transforms of pss_fft.h: a forward transform takes its input in
+// digit-reversed order and returns natural order (dit), an inverse transform
+// takes natural order and returns digit-reversed order (dif), so every
+// per-mode computation sees natural mode order.  A line is held by
+// consecutive threads.
+//
+// Position order.  The arrays that pass between the kernels of a step (the
+// de-aliased factors V and the product channels N, and their adjoint
+// counterparts) hold, along the update axis, position p = t + m*T the value
+// of the digit-reversed index D(t) + m*T.  The update kernel then reads and
+// writes them contiguously, and the x kernel (and the 3D y pass), whose work
+// does not depend on the coordinate along that axis, simply treat positions
+// as rows.  The state and the arrays of the transform modes (uploads,
+// downloads) stay in natural order; those gather or scatter at D(t) + m*T.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -540,7 +549,7 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
         float2 nxt[P];
         if (p.nch > 0) {
 #pragma unroll
-            for (int m = 0; m < P; ++m) nxt[m] = gload(bufs.N[0] + base + (dr + m * T) * tc);
+            for (int m = 0; m < P; ++m) nxt[m] = gload(bufs.N[0] + base + (t + m * T) * tc);
         }
         store_twiddles<L, P>(twl, twr, tid, nthr);
         // per-slot modes of the line (slot form on a packed line)
@@ -566,7 +575,7 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
             for (int m = 0; m < P; ++m) v[m] = nxt[m];
             if (ch + 1 < p.nch) {
 #pragma unroll
-                for (int m = 0; m < P; ++m) nxt[m] = gload(bufs.N[ch + 1] + base + (dr + m * T) * tc);
+                for (int m = 0; m < P; ++m) nxt[m] = gload(bufs.N[ch + 1] + base + (t + m * T) * tc);
             }
             FFT::template dit<-1>(v, ld, t, tw);
             exchange(v, true);
@@ -672,7 +681,7 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
         exchange(v, false);
         FFT::template dif<1>(v, ld, t, tw);
 #pragma unroll
-        for (int m = 0; m < P; ++m) gstore(bufs.V[g] + vbase + (dr + m * T) * vstride, v[m]);
+        for (int m = 0; m < P; ++m) gstore(bufs.V[g] + vbase + (t + m * T) * vstride, v[m]);
     }
 }
 
@@ -760,7 +769,7 @@ __global__ void __launch_bounds__(256) adjcol_kernel(AdjArgs aa, Geo geo, const 
     } else {
         float2 v[P];
 #pragma unroll
-        for (int m = 0; m < P; ++m) v[m] = aa.X[base + (dr + m * T) * tc];
+        for (int m = 0; m < P; ++m) v[m] = aa.X[base + (t + m * T) * tc];
         store_twiddles<L, P>(twl, twr, tid, nthr);
         __syncthreads();
         FFT::template dit<-1>(v, ld, t, tw);
@@ -838,11 +847,11 @@ __global__ void __launch_bounds__(256) adjcol_kernel(AdjArgs aa, Geo geo, const 
     exchange(wr, false);
     FFT::template dif<1>(wr, ld, t, tw);
 #pragma unroll
-    for (int m = 0; m < P; ++m) aa.W[base + (dr + m * T) * tc] = wr[m];
+    for (int m = 0; m < P; ++m) aa.W[base + (t + m * T) * tc] = wr[m];
     exchange(um, false);
     FFT::template dif<1>(um, ld, t, tw);
 #pragma unroll
-    for (int m = 0; m < P; ++m) aa.U[base + (dr + m * T) * tc] = um[m];
+    for (int m = 0; m < P; ++m) aa.U[base + (t + m * T) * tc] = um[m];
     if (aa.D > 0.f) part[2] /= 2.0 * aa.D;
     double out[4] = {part[0], 0.0, part[1], part[2]};
     block_atomic_add(out, aa.acc);

@@ -1603,6 +1603,11 @@ pss_status pss_time_kernel(pss_ctx* c, int32_t which, int32_t reps, double* ms, 
     if (pss_status s_bw = begin_work(c)) return s_bw;
     const int nk = c->ndim == 3 ? 4 : 2;
     if (which < 0 || which >= nk) return fail(PSS_E_INVAL, "kernel %d does not exist on this lattice", which);
+    // the x kernel and the y passes run only for models with real-space products
+    if ((which == 1 || which == 3) && c->plan.nch == 0)
+        return fail(PSS_E_INVAL, "kernel %d does not run on this model (no real-space products)", which);
+    if (which == 2 && c->plan.ng == 0)
+        return fail(PSS_E_INVAL, "kernel %d does not run on this model (no factor fields)", which);
     if (c->dirty)
         if (pss_status s = prologue(c)) return s;
     const int nf = static_cast<int>(c->fields.size());

@@ -87,3 +87,22 @@ def test_terminal_seed_is_the_loss_derivative():
     h = 1e-6
     fd = (adj.loss(lat, phi + h * d, S_star) - adj.loss(lat, phi - h * d, S_star)) / (2 * h)
     assert abs(np.real(np.sum(np.conj(g) * d)) - fd) <= 1e-6 * abs(fd)
+
+
+def test_stored_full_size_adjoint_matches_central_differences():
+    """tests/golden/adjoint_256.json (written by make_adjoint_256.py from the
+    oracle alone): at the adjoint workload's full size, 256^2 and 2000 steps,
+    the adjoint gradient in (a, b, k, D) agrees with FP64 central differences
+    of the loss (h = 1e-4 relative)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint_256.json")
+    with open(path) as f:
+        doc = json.load(f)
+    run = next(r for r in doc["runs"] if r["steps"] == doc["fd"]["steps"])
+    g = np.array(run["grad"])
+    fd = np.array(doc["fd"]["grad"])
+    assert np.all(np.abs(g - fd) <= 1e-4 * np.abs(fd)), (g, fd)
+    # coarsening moves the loss and the gradient up by orders of magnitude with the run length
+    losses = [r["loss"] for r in doc["runs"]]
+    assert all(b > 10 * a for a, b in zip(losses, losses[1:])), losses
