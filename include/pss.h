@@ -340,16 +340,20 @@ pss_status pss_tape_destroy(pss_tape *tape);
 /* ------------------------------------------------------------------ batches
  * Many independent 2D lattices advanced together.  The paper finds small
  * lattices overhead-bound on the GPU (its benchmarks: the CPU version wins
- * below 128^2, Sec. "Benchmarks"); a batch runs every lattice of one size
- * class in the same launches, so the per-launch cost is paid once per class
- * and the launches hold enough blocks to fill the chip.
+ * below 128^2, Sec. "Benchmarks"); a batch runs all its lattices in the same
+ * launches, so the per-launch cost is paid once and the launches hold enough
+ * blocks to fill the chip.
  *
  * Lattices with equal sizes, field count, factor and channel counts and launch
- * geometry form one class: per time step, one update launch and one x launch
- * each, with the lattice picked by blockIdx.y from a table of its plan,
- * buffers and step counter.  Every lattice keeps its own model, coefficients,
- * seed (noise keys), de-aliasing, state and step counter; a batch step gives,
- * bit for bit, the state that pss_step gives on that lattice alone. */
+ * geometry form one class.  Every class whose lattices have one field,
+ * operators without 1/|q| or i q_i monomials, the default 4 points per thread
+ * and lines of 64 to 1024 joins two fused launches per time step: one for the
+ * update phase and one for the x phase of all such classes, over a work list
+ * of (class, member, tile).  Any other class runs one update launch and one x
+ * launch of its own per step, with the lattice picked by blockIdx.y.  Every
+ * lattice keeps its own model, coefficients, seed (noise keys), de-aliasing,
+ * state and step counter; a batch step gives, bit for bit, the state that
+ * pss_step gives on that lattice alone. */
 
 /* Make a batch of n >= 1 distinct 2D lattices (3D lattices: PSS_E_UNSUPPORTED;
  * a lattice listed twice or a null entry: PSS_E_INVAL).  The lattices are
@@ -380,10 +384,17 @@ pss_status pss_batch_info(pss_batch *batch, int32_t *n_classes, int32_t *class_o
 /* Time `reps` back-to-back launches of one class's update kernel (which = 0)
  * or x kernel (which = 1) with HIP events on the batch stream: *ms per launch;
  * *bytes (may be NULL) the launch's algorithmic HBM bytes (the first member's
- * per-lattice figure times the class size).  Leaves the members' channel
- * arrays stale, so the next step rebuilds them; for timing only. */
+ * per-lattice figure times the class size).  cls = -1 times the fused launch
+ * of that phase (bytes summed over its classes; PSS_E_INVAL if the batch has
+ * none).  Leaves the members' channel arrays stale, so the next step rebuilds
+ * them; for timing only. */
 pss_status pss_batch_time_kernel(pss_batch *batch, int32_t cls, int32_t which, int32_t reps, double *ms,
                                  double *bytes);
+
+/* Kernel launches per time step of the batch (2 when every class is fused)
+ * and the number of classes in the fused launches; either pointer may be
+ * NULL. */
+pss_status pss_batch_launches(pss_batch *batch, int32_t *per_step, int32_t *fused_classes);
 
 const char *pss_last_error(void);
 

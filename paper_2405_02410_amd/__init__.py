@@ -104,6 +104,7 @@ _SIGS = {
     "pss_batch_step": [ctypes.c_void_p, ctypes.c_int64],
     "pss_batch_sync": [ctypes.c_void_p],
     "pss_batch_info": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+    "pss_batch_launches": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
     "pss_batch_time_kernel": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
 }
@@ -408,8 +409,9 @@ class Tape:
 
 
 class Batch:
-    """Independent 2D lattices advanced together (pss_batch_*): one update and
-    one x launch per size class and step.  Holds references to its lattices;
+    """Independent 2D lattices advanced together (pss_batch_*): one fused
+    update and one fused x launch per step for the classes that fit them, one
+    of each per step for any other size class.  Holds references to its lattices;
     close() (or garbage collection) frees the batch, not the lattices."""
 
     def __init__(self, lattices, seeds=None):
@@ -445,8 +447,15 @@ class Batch:
         _check(lib().pss_batch_info(self._h, ctypes.byref(nc), of))
         return nc.value, list(of)
 
+    def launches(self):
+        """(kernel launches per step, classes in the fused launches)."""
+        per, fused = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().pss_batch_launches(self._h, ctypes.byref(per), ctypes.byref(fused)))
+        return per.value, fused.value
+
     def time_kernel(self, cls, which=KERNEL_UPDATE, reps=100):
-        """(ms per launch, algorithmic bytes per launch) of one class's kernel."""
+        """(ms per launch, algorithmic bytes per launch) of one class's kernel,
+        or of the fused launch of that phase for cls = -1."""
         ms, b = ctypes.c_double(), ctypes.c_double()
         _check(lib().pss_batch_time_kernel(self._h, int(cls), int(which), int(reps), ctypes.byref(ms),
                                            ctypes.byref(b)))

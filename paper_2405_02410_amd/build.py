@@ -1,7 +1,8 @@
 """Build libpss.so for gfx950 in the package directory.
 
-The kernel source is compiled once per supported line length (8 .. 4096) and
-once for the shared utilities, in parallel, then linked with the host runtime.
+The kernel source is compiled once per supported line length (8 .. 4096),
+once for the fused batch kernels and once for the shared utilities, in
+parallel, then linked with the host runtime.
 Run as a script or call build(); both always recompile.
 """
 
@@ -53,6 +54,9 @@ def build(jobs=None, verbose=False):
     o = os.path.join(BUILD, "kern_common.o")
     cmds.append([hipcc, *HIPCC_FLAGS, "-DPSS_COMMON", "-c", src, "-o", o])
     objs.append(o)
+    o = os.path.join(BUILD, "kern_batch.o")
+    cmds.append([hipcc, *HIPCC_FLAGS, "-DPSS_BATCH", "-c", src, "-o", o])
+    objs.append(o)
     o = os.path.join(BUILD, "noalloc.o")
     cmds.append([hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, "pss_noalloc.hip"), "-o", o])
     objs.append(o)
@@ -61,7 +65,9 @@ def build(jobs=None, verbose=False):
     objs.append(o)
     jobs = jobs or min(16, os.cpu_count() or 4)
     # the longest compiles first
-    order = sorted(range(len(cmds)), key=lambda i: -LENGTHS[i] if i < len(LENGTHS) else 0)
+    # the longest compiles first: the fused batch kernels, then the longest lines
+    weight = [L for L in LENGTHS] + [0, 100000, 0, 0]
+    order = sorted(range(len(cmds)), key=lambda i: -weight[i])
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         futs = [ex.submit(_run, cmds[i]) for i in order]
         for f in futs:

@@ -120,6 +120,35 @@ struct LaunchArgs {
     int dim;             // 2 or 3
 };
 
+// Fused batch launches: one update-phase and one x-phase launch cover every
+// size class of a batch whose lattices fit the fused kernels (2D, one field,
+// 4 points per thread, 256-thread blocks, lines of 64 .. 1024).  Blocks are a
+// work list of (class, member, tile): class k owns blocks [start, start +
+// nmem * nblk), member-major.
+constexpr int kMaxBatchClasses = 8;
+struct BatchClass {
+    int L;      // line length of the phase (update: Ny; x: Nx)
+    int start;  // first block of the class
+    int nblk;   // blocks per member
+    int pad;
+    const Member* members;
+    const DevPlan* plans;
+    const float2* tw;  // twiddles of L
+    Geo geo;           // the class's launch geometry for this phase
+};
+struct BatchLaunch {
+    int ncls;      // classes in the launch
+    int total;     // blocks
+    int step_off;  // step within the replayed chunk (update phase)
+    int pad;
+    int64_t advance;  // x phase: counter advance of the chunk's last step (0: none)
+    BatchClass cls[kMaxBatchClasses];
+};
+// line lengths the fused kernels are built for
+inline bool batch_fused_len(int L) { return L >= 64 && L <= 1024 && (L & (L - 1)) == 0; }
+hipError_t launch_batch_update(hipStream_t s, const BatchLaunch& bl, size_t lds);
+hipError_t launch_batch_xrow(hipStream_t s, const BatchLaunch& bl, size_t lds);
+
 // largest points per thread a kernel is built for with `nregs` register
 // arrays of fields (1, 2 or 4 and more): 16, 8, 4, capped at L
 int max_points(int L, int nregs);

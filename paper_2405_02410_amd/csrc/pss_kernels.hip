@@ -124,24 +124,31 @@ __device__ __noinline__ float2 eval_general(const DevOp& op, float q2, float iqx
     return make_float2(re, im);
 }
 
-// sum_j poly[j] (q^2)^j up to the operator's degree
+// sum_j poly[j] (q^2)^j up to the operator's degree.  The coefficients are
+// read at fixed offsets (no load waits for the degree) and the terms above
+// the degree are skipped by a uniform branch; starting from r = 0 the first
+// kept term gives r = poly[deg] exactly, as a loop from the degree would.
 __device__ __forceinline__ float horner(const DevOp& op, float q2) {
     const int deg = op.deg;
-    float r = op.poly[deg];
-    for (int j = deg - 1; j >= 0; --j) r = fmaf(r, q2, op.poly[j]);
+    float r = 0.f;
+#pragma unroll
+    for (int j = PSS_MAXPOW; j >= 0; --j)
+        if (j <= deg) r = fmaf(r, q2, op.poly[j]);
     return r;
 }
-// the same for P modes at once: one loop per operator
+// the same for P modes at once
 template <int P>
 __device__ __forceinline__ void horner_p(const DevOp& op, const float (&q2)[P], float (&out)[P]) {
     const int deg = op.deg;
-    const float top = op.poly[deg];
 #pragma unroll
-    for (int m = 0; m < P; ++m) out[m] = top;
-    for (int j = deg - 1; j >= 0; --j) {
-        const float c = op.poly[j];
+    for (int m = 0; m < P; ++m) out[m] = 0.f;
 #pragma unroll
-        for (int m = 0; m < P; ++m) out[m] = fmaf(out[m], q2[m], c);
+    for (int j = PSS_MAXPOW; j >= 0; --j) {
+        if (j <= deg) {
+            const float c = op.poly[j];
+#pragma unroll
+            for (int m = 0; m < P; ++m) out[m] = fmaf(out[m], q2[m], c);
+        }
     }
 }
 
@@ -310,18 +317,20 @@ struct LineModes {
     uint32_t yx, yxn;  // linear-index parts of the fixed indices and of their negatives
     uint32_t yx0, yxN; // packed line: the same for kx = 0 and kx = -Nx/2 (negation keeps them)
 
-    // slot u (not a pair slot) -> w, q^2, lin, lneg
-    template <int L>
-    __device__ __forceinline__ void at(int u, int& w, float& q2, uint32_t& lin, uint32_t& lneg, bool& upper) const {
-        upper = packed && u > (L >> 1);
-        w = packed ? (upper ? L - u : u) : (u < (L >> 1) ? u : u - L);
-        const float ql = static_cast<float>(w) * qs;
-        q2 = fmaf(ql, ql, packed ? (upper ? qqN : qq0) : qq);
-        const uint32_t uw = static_cast<uint32_t>(w) & (L - 1), un = static_cast<uint32_t>(-w) & (L - 1);
-        lin = uw * lstride + (packed ? (upper ? yxN : yx0) : yx);
-        lneg = un * lstride + (packed ? (upper ? yxN : yx0) : yxn);
-    }
 };
+
+// slot u (not a pair slot) of a line -> w, q^2, lin, lneg.  The line's
+// description is taken by value so that it stays in registers.
+template <int L>
+__device__ __forceinline__ void slot_at(const LineModes lm, int u, float& q2, uint32_t& lin, uint32_t& lneg) {
+    const bool upper = lm.packed && u > (L >> 1);
+    const int w = lm.packed ? (upper ? L - u : u) : (u < (L >> 1) ? u : u - L);
+    const float ql = static_cast<float>(w) * lm.qs;
+    q2 = fmaf(ql, ql, lm.packed ? (upper ? lm.qqN : lm.qq0) : lm.qq);
+    const uint32_t uw = static_cast<uint32_t>(w) & (L - 1), un = static_cast<uint32_t>(-w) & (L - 1);
+    lin = uw * lm.lstride + (lm.packed ? (upper ? lm.yxN : lm.yx0) : lm.yx);
+    lneg = un * lm.lstride + (lm.packed ? (upper ? lm.yxN : lm.yx0) : lm.yxn);
+}
 
 template <int L, int DIM>
 __device__ __forceinline__ LineModes line_modes(const DevPlan& p, bool packed, int kx_l, int ky_l) {
@@ -395,7 +404,7 @@ __device__ __forceinline__ float2 pair_update_d(const DevPlan& p, int f, uint32_
 
 // mode q of slot u of a line, for the general-monomial operators
 template <int L, int DIM>
-__device__ __forceinline__ ModeQ slot_q(const DevPlan& p, const LineModes& lm, int u) {
+__device__ __forceinline__ ModeQ slot_q(const DevPlan& p, const LineModes lm, int u) {
     const bool upper = lm.packed && u > (L >> 1);
     const int w = lm.packed ? (upper ? L - u : u) : (u < (L >> 1) ? u : u - L);
     const int kx = lm.packed ? (upper ? -(p.n[0] >> 1) : 0) : lm.kx;
@@ -410,27 +419,40 @@ __device__ __forceinline__ void pair_accumulate(float2 (&acc)[NF][P], int target
     add_to(acc, target, P / 2, pair_op_d<DIM, GEN>(p, op, ky_l, L >> 1, L, v[P / 2]));
 }
 
-template <int L, int P, int NF, int MODE, int DIM, bool GEN>
-__global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ members,
-                                                      const DevPlan* __restrict__ plans,
-                                                      const DevPlan* __restrict__ plan_a, Bufs bufs_a, Geo geo,
-                                                      const uint64_t* __restrict__ step_ctr_a,
-                                                      int step_off, const float2* __restrict__ tw_g) {
+// One block of the update kernel: tile `blk` of lattice `mi`.  In the step
+// modes of several lattices (TABLE) the lattice's buffers, counter and flag
+// come from the member table and its plan from the plan array (both kernel
+// arguments, so the plan reads stay scalar loads).  A launch of one lattice
+// (and the transform modes) takes buffers, counter and flag from the
+// arguments: its data loads then wait for no table load.
+template <int L, int P, int NF, int MODE, int DIM, bool GEN, bool TABLE>
+__device__ __forceinline__ void update_block(int mi, int blk, const Member* __restrict__ members,
+                                             const DevPlan* __restrict__ plans, const DevPlan* __restrict__ plan_a,
+                                             const Bufs& bufs_a, const Geo& geo,
+                                             const uint64_t* __restrict__ step_ctr_a, uint32_t* __restrict__ flag_a,
+                                             int step_off, const float2* __restrict__ tw_g) {
     using FFT = LineFFT<L, P>;
     constexpr int T = FFT::T;
     extern __shared__ float2 smem[];
-    // step modes: lattice blockIdx.y of the member table and of the plan
-    // array (both kernel arguments, so the plan reads stay scalar loads); the
-    // transform modes act on the single lattice of the arguments (gridDim.y = 1)
-    constexpr bool TAB = MODE == MODE_STEP || MODE == MODE_PROLOGUE;
-    const int nb = gridDim.x;
-    const int lin_b = xcd_block(blockIdx.y * nb + blockIdx.x, nb * gridDim.y);
-    const int mi = lin_b / nb;
-    const int blk = lin_b - mi * nb;
+    constexpr bool TAB = (MODE == MODE_STEP || MODE == MODE_PROLOGUE) && TABLE;
     const Member* mem = members + mi;  // dereferenced in the step modes only
-    const DevPlan& p = TAB ? plans[mi] : *plan_a;
-    const Bufs& bufs = TAB ? mem->bufs : bufs_a;
-    const uint64_t* __restrict__ step_ctr = TAB ? mem->step_ctr : step_ctr_a;
+    // the lattice's plan, buffers and counter: from the tables or from the
+    // arguments (selected at compile time, so the unused source is never
+    // given an address)
+    const DevPlan* pp;
+    const Bufs* bp;
+    const uint64_t* step_ctr;
+    if constexpr (TAB) {
+        pp = plans + mi;
+        bp = &mem->bufs;
+        step_ctr = mem->step_ctr;
+    } else {
+        pp = plan_a;
+        bp = &bufs_a;
+        step_ctr = step_ctr_a;
+    }
+    const DevPlan& p = *pp;
+    const Bufs& bufs = *bp;
     const int tc = geo.tc, to = geo.to;
     const int ntile = geo.ntile;
     const int tid = threadIdx.x;
@@ -556,11 +578,7 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
         float q2[P];
         uint32_t lin[P], lneg[P];
 #pragma unroll
-        for (int m = 0; m < P; ++m) {
-            int w;
-            bool up;
-            lmode.at<L>(t + m * T, w, q2[m], lin[m], lneg[m], up);
-        }
+        for (int m = 0; m < P; ++m) slot_at<L>(lmode, t + m * T, q2[m], lin[m], lneg[m]);
         __syncthreads();  // twiddles in LDS
         float2 acc[NF][P];  // explicit contributions
 #pragma unroll
@@ -651,7 +669,13 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
             }
             if (!fin) bad |= 1u << f;  // a NaN or infinity in the new state
         }
-        if (bad) atomicOr(mem->flag, bad);
+        if (bad) {
+            if constexpr (TAB) {
+                atomicOr(mem->flag, bad);
+            } else {
+                atomicOr(flag_a, bad);
+            }
+        }
     }
 
     // de-aliased inverse transforms of every factor field (eq:cubicexampledealiased)
@@ -683,6 +707,21 @@ __global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ 
 #pragma unroll
         for (int m = 0; m < P; ++m) gstore(bufs.V[g] + vbase + (t + m * T) * vstride, v[m]);
     }
+}
+
+template <int L, int P, int NF, int MODE, int DIM, bool GEN, bool TABLE>
+__global__ void __launch_bounds__(256) update_kernel(const Member* __restrict__ members,
+                                                      const DevPlan* __restrict__ plans,
+                                                      const DevPlan* __restrict__ plan_a, Bufs bufs_a, Geo geo,
+                                                      const uint64_t* __restrict__ step_ctr_a,
+                                                      uint32_t* __restrict__ flag_a, int step_off,
+                                                      const float2* __restrict__ tw_g) {
+    // lattice blockIdx.y, XCD-ordered over the whole grid
+    const int nb = gridDim.x;
+    const int lin_b = xcd_block(blockIdx.y * nb + blockIdx.x, nb * gridDim.y);
+    const int mi = lin_b / nb;
+    update_block<L, P, NF, MODE, DIM, GEN, TABLE>(mi, lin_b - mi * nb, members, plans, plan_a, bufs_a, geo,
+                                                  step_ctr_a, flag_a, step_off, tw_g);
 }
 
 // ------------------------------------------------------ adjoint column kernel
@@ -996,29 +1035,36 @@ __global__ void __launch_bounds__(256) ypass_kernel(YArgs ya, Geo geo, const flo
 // (2 pr, 2 pr + 1) packed as one complex line held by T consecutive threads.
 // Packed-column arrays are read and written in whole tile blocks of RB*TC
 // contiguous elements.
-template <int L, int P, int NG, int MODE>
-__global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ members,
-                                                    const DevPlan* __restrict__ plans,
-                                                    const DevPlan* __restrict__ plan_a, Bufs bufs_a, Geo geo,
-                                                    const float2* __restrict__ tw_g, int64_t advance) {
+// One block of the x kernel: row block `blk` of lattice `mi` (as in the update kernel)
+template <int L, int P, int NG, int MODE, bool TABLE>
+__device__ __forceinline__ void xrow_block(int mi, int blk, const Member* __restrict__ members,
+                                           const DevPlan* __restrict__ plans, const DevPlan* __restrict__ plan_a,
+                                           const Bufs& bufs_a, const Geo& geo, const float2* __restrict__ tw_g,
+                                           int64_t advance, uint64_t* __restrict__ step_ctr_a) {
     using FFT = LineFFT<L, P>;
     constexpr int T = FFT::T;
     constexpr int NC = L / 2;  // packed columns
     extern __shared__ float2 smem[];
-    constexpr bool TAB = MODE == MODE_STEP;  // as in the update kernel
-    const int nb = gridDim.x;
-    const int lin_b = xcd_block(blockIdx.y * nb + blockIdx.x, nb * gridDim.y);
-    const int mi = lin_b / nb;
+    constexpr bool TAB = MODE == MODE_STEP && TABLE;  // as in the update kernel
     const Member* mem = members + mi;
-    const DevPlan& p = TAB ? plans[mi] : *plan_a;
-    const Bufs& bufs = TAB ? mem->bufs : bufs_a;
+    const DevPlan* pp;
+    const Bufs* bp;
+    if constexpr (TAB) {
+        pp = plans + mi;
+        bp = &mem->bufs;
+    } else {
+        pp = plan_a;
+        bp = &bufs_a;
+    }
+    const DevPlan& p = *pp;
+    const Bufs& bufs = *bp;
     const int tc = geo.tc, rb = geo.rb;
     const int ntile = NC / tc;
     const int tid = threadIdx.x;
     const int nthr = (rb >> 1) * T;
     const int pr = tid / T;  // pair within the block
     const int t = tid & (T - 1);
-    const int r0 = (lin_b - mi * nb) * rb;  // first row; row index = z*Ny + y
+    const int r0 = blk * rb;  // first row; row index = z*Ny + y
     const int ny = p.n[1];
     const int zr = r0 / ny;          // z of the block (0 in 2D)
     const int y0 = r0 - zr * ny;     // first y of the block
@@ -1164,7 +1210,13 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
 
     // MODE_STEP: the last step of a replayed chunk moves the member's step
     // counter on (no later kernel of the chunk reads it)
-    if (advance != 0 && r0 == 0 && tid == 0) *mem->step_ctr += static_cast<uint64_t>(advance);
+    if (advance != 0 && r0 == 0 && tid == 0) {
+        if constexpr (TAB) {
+            *mem->step_ctr += static_cast<uint64_t>(advance);
+        } else {
+            *step_ctr_a += static_cast<uint64_t>(advance);
+        }
+    }
     // real-space values of every factor field
     float2 z[NG][P];
 #pragma unroll
@@ -1210,6 +1262,19 @@ __global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ me
         FFT::template dif<-1>(w, ld, t, tw);
         store_rows(w, bufs.N[ch]);
     }
+}
+
+template <int L, int P, int NG, int MODE, bool TABLE>
+__global__ void __launch_bounds__(256) xrow_kernel(const Member* __restrict__ members,
+                                                    const DevPlan* __restrict__ plans,
+                                                    const DevPlan* __restrict__ plan_a, Bufs bufs_a, Geo geo,
+                                                    const float2* __restrict__ tw_g, int64_t advance,
+                                                    uint64_t* __restrict__ step_ctr_a) {
+    const int nb = gridDim.x;
+    const int lin_b = xcd_block(blockIdx.y * nb + blockIdx.x, nb * gridDim.y);
+    const int mi = lin_b / nb;
+    xrow_block<L, P, NG, MODE, TABLE>(mi, lin_b - mi * nb, members, plans, plan_a, bufs_a, geo, tw_g, advance,
+                                      step_ctr_a);
 }
 
 #if defined(PSS_COMMON)
@@ -1331,6 +1396,25 @@ __global__ void shells_kernel(const float2* __restrict__ S, int nx, int ny, int 
 // kernels of that length) and once with -DPSS_COMMON (utilities and the
 // length dispatch), so the instantiations build in parallel.
 #if defined(PSS_LINE_LEN)
+template <int L, int P, int NF, int DIM, bool TABLE>
+static hipError_t launch_update_tab(int mode, const LaunchArgs& a, dim3 grid, dim3 block, size_t lds) {
+#define PSS_UPD(M, G, NFV)                                                                                        \
+    hipLaunchKernelGGL((update_kernel<L, P, NFV, M, DIM, G, TABLE>), grid, block, lds, a.stream, a.members, a.plans, \
+                       a.plan, a.bufs, a.geo, a.step_ctr, a.flag, a.step_off, a.tw_u)
+    switch (mode) {
+        case MODE_STEP:
+            if (a.general)
+                PSS_UPD(MODE_STEP, true, NF);
+            else
+                PSS_UPD(MODE_STEP, false, NF);
+            break;
+        case MODE_PROLOGUE: PSS_UPD(MODE_PROLOGUE, false, NF); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef PSS_UPD
+    return hipGetLastError();
+}
+
 template <int L, int P, int NF, int DIM>
 static hipError_t launch_update_d(int mode, const LaunchArgs& a) {
     const int threads = a.geo.tc * a.geo.to * (L / P);
@@ -1338,26 +1422,19 @@ static hipError_t launch_update_d(int mode, const LaunchArgs& a) {
     const bool tab = mode == MODE_STEP || mode == MODE_PROLOGUE;
     if (tab && (!a.members || !a.plans || a.nmem < 1)) return hipErrorInvalidValue;
     dim3 grid(a.geo.nublk, tab ? a.nmem : 1), block(threads);
+    if (tab) {
+        // one lattice: buffers, counter and flag come from the arguments
+        if (a.nmem > 1) return launch_update_tab<L, P, NF, DIM, true>(mode, a, grid, block, lds);
+        return launch_update_tab<L, P, NF, DIM, false>(mode, a, grid, block, lds);
+    }
     switch (mode) {
-        case MODE_STEP:
-            if (a.general)
-                hipLaunchKernelGGL((update_kernel<L, P, NF, MODE_STEP, DIM, true>), grid, block, lds, a.stream,
-                                   a.members, a.plans, a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
-            else
-                hipLaunchKernelGGL((update_kernel<L, P, NF, MODE_STEP, DIM, false>), grid, block, lds, a.stream,
-                                   a.members, a.plans, a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
-            break;
-        case MODE_PROLOGUE:
-            hipLaunchKernelGGL((update_kernel<L, P, NF, MODE_PROLOGUE, DIM, false>), grid, block, lds, a.stream,
-                               a.members, a.plans, a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
-            break;
         case MODE_FWD_STORE:
-            hipLaunchKernelGGL((update_kernel<L, P, 1, MODE_FWD_STORE, DIM, false>), grid, block, lds, a.stream,
-                               a.members, a.plans, a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
+            hipLaunchKernelGGL((update_kernel<L, P, 1, MODE_FWD_STORE, DIM, false, false>), grid, block, lds, a.stream,
+                               a.members, a.plans, a.plan, a.bufs, a.geo, a.step_ctr, a.flag, a.step_off, a.tw_u);
             break;
         case MODE_INV_OUT:
-            hipLaunchKernelGGL((update_kernel<L, P, 1, MODE_INV_OUT, DIM, false>), grid, block, lds, a.stream,
-                               a.members, a.plans, a.plan, a.bufs, a.geo, a.step_ctr, a.step_off, a.tw_u);
+            hipLaunchKernelGGL((update_kernel<L, P, 1, MODE_INV_OUT, DIM, false, false>), grid, block, lds, a.stream,
+                               a.members, a.plans, a.plan, a.bufs, a.geo, a.step_ctr, a.flag, a.step_off, a.tw_u);
             break;
         default:
             return hipErrorInvalidValue;
@@ -1377,23 +1454,28 @@ static hipError_t launch_xrow_t(int mode, const LaunchArgs& a) {
     const bool tab = mode == MODE_STEP;
     if (tab && (!a.members || !a.plans || a.nmem < 1)) return hipErrorInvalidValue;
     dim3 grid(a.geo.nrowblk, tab ? a.nmem : 1), block(threads);
+    uint64_t* ctr = const_cast<uint64_t*>(a.step_ctr);
     switch (mode) {
         case MODE_STEP:
-            hipLaunchKernelGGL((xrow_kernel<L, P, NG, MODE_STEP>), grid, block, lds, a.stream, a.members, a.plans, a.plan,
-                               a.bufs, a.geo, a.tw_x, a.advance);
+            if (a.nmem > 1)
+                hipLaunchKernelGGL((xrow_kernel<L, P, NG, MODE_STEP, true>), grid, block, lds, a.stream, a.members,
+                                   a.plans, a.plan, a.bufs, a.geo, a.tw_x, a.advance, ctr);
+            else
+                hipLaunchKernelGGL((xrow_kernel<L, P, NG, MODE_STEP, false>), grid, block, lds, a.stream, a.members,
+                                   a.plans, a.plan, a.bufs, a.geo, a.tw_x, a.advance, ctr);
             break;
         case MODE_R2C_IN:
-            hipLaunchKernelGGL((xrow_kernel<L, P, 1, MODE_R2C_IN>), grid, block, lds, a.stream, a.members, a.plans, a.plan,
-                               a.bufs, a.geo, a.tw_x, int64_t{0});
+            hipLaunchKernelGGL((xrow_kernel<L, P, 1, MODE_R2C_IN, false>), grid, block, lds, a.stream, a.members,
+                               a.plans, a.plan, a.bufs, a.geo, a.tw_x, int64_t{0}, ctr);
             break;
         case MODE_C2R_OUT:
-            hipLaunchKernelGGL((xrow_kernel<L, P, 1, MODE_C2R_OUT>), grid, block, lds, a.stream, a.members, a.plans, a.plan,
-                               a.bufs, a.geo, a.tw_x, int64_t{0});
+            hipLaunchKernelGGL((xrow_kernel<L, P, 1, MODE_C2R_OUT, false>), grid, block, lds, a.stream, a.members,
+                               a.plans, a.plan, a.bufs, a.geo, a.tw_x, int64_t{0}, ctr);
             break;
         case MODE_ADJROW:
             if constexpr (NG == 2) {
-                hipLaunchKernelGGL((xrow_kernel<L, P, 2, MODE_ADJROW>), grid, block, lds, a.stream, a.members, a.plans,
-                                   a.plan, a.bufs, a.geo, a.tw_x, int64_t{0});
+                hipLaunchKernelGGL((xrow_kernel<L, P, 2, MODE_ADJROW, false>), grid, block, lds, a.stream, a.members,
+                                   a.plans, a.plan, a.bufs, a.geo, a.tw_x, int64_t{0}, ctr);
                 break;
             }
             return hipErrorInvalidValue;
@@ -1488,6 +1570,77 @@ hipError_t PSS_CAT(launch_xrow_L, PSS_LINE_LEN)(int mode, int ng, const LaunchAr
     return hipErrorInvalidValue;
 }
 #endif  // PSS_LINE_LEN
+
+#if defined(PSS_BATCH)
+// ------------------------------------------------------ fused batch launches
+// One launch per phase for a whole batch: block b (XCD-ordered) finds its
+// class in the work list, then its member and tile, and runs the block body
+// built for that class's line length.
+__device__ __forceinline__ int batch_class_of(const BatchLaunch& bl, int b) {
+    int k = 0;
+    for (int i = 1; i < bl.ncls; ++i)
+        if (b >= bl.cls[i].start) k = i;
+    return k;
+}
+
+__global__ void __launch_bounds__(256) batch_update_kernel(BatchLaunch bl) {
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const BatchClass& C = bl.cls[batch_class_of(bl, b)];
+    const int rel = b - C.start;
+    const int mi = rel / C.nblk;
+    const int blk = rel - mi * C.nblk;
+    const Bufs none{};
+#define PSS_BU(LL)                                                                                                 \
+    case LL:                                                                                                       \
+        update_block<LL, 4, 1, MODE_STEP, 2, false, true>(mi, blk, C.members, C.plans, nullptr, none, C.geo, nullptr, \
+                                                          nullptr, bl.step_off, C.tw);                             \
+        break;
+    switch (C.L) {
+        PSS_BU(64)
+        PSS_BU(128)
+        PSS_BU(256)
+        PSS_BU(512)
+        PSS_BU(1024)
+        default: break;
+    }
+#undef PSS_BU
+}
+
+__global__ void __launch_bounds__(256) batch_xrow_kernel(BatchLaunch bl) {
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const BatchClass& C = bl.cls[batch_class_of(bl, b)];
+    const int rel = b - C.start;
+    const int mi = rel / C.nblk;
+    const int blk = rel - mi * C.nblk;
+    const Bufs none{};
+#define PSS_BX(LL)                                                                                          \
+    case LL:                                                                                                \
+        xrow_block<LL, 4, 1, MODE_STEP, true>(mi, blk, C.members, C.plans, nullptr, none, C.geo, C.tw, bl.advance, \
+                                              nullptr);                                                     \
+        break;
+    switch (C.L) {
+        PSS_BX(64)
+        PSS_BX(128)
+        PSS_BX(256)
+        PSS_BX(512)
+        PSS_BX(1024)
+        default: break;
+    }
+#undef PSS_BX
+}
+
+hipError_t launch_batch_update(hipStream_t s, const BatchLaunch& bl, size_t lds) {
+    if (bl.ncls < 1 || bl.total < 1) return hipSuccess;
+    hipLaunchKernelGGL(batch_update_kernel, dim3(bl.total), dim3(256), lds, s, bl);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_xrow(hipStream_t s, const BatchLaunch& bl, size_t lds) {
+    if (bl.ncls < 1 || bl.total < 1) return hipSuccess;
+    hipLaunchKernelGGL(batch_xrow_kernel, dim3(bl.total), dim3(256), lds, s, bl);
+    return hipGetLastError();
+}
+#endif  // PSS_BATCH
 
 #if defined(PSS_COMMON)
 #define PSS_DECL_L(L)                                                               \

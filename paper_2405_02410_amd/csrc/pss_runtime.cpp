@@ -195,6 +195,12 @@ struct pss_batch {
     std::vector<uint64_t> seen;        // members' enq_gen when the batch last ordered itself after them
     std::vector<int> all;              // 0 .. n-1
     std::vector<Class> cls;
+    // fused launches: the classes that fit the fused kernels run in one
+    // update-phase and one x-phase launch per step (templates; the step
+    // offset and the counter advance are set per launch)
+    pss::BatchLaunch fu{}, fx{};
+    size_t fu_lds = 0, fx_lds = 0;
+    std::vector<char> in_fu, in_fx;    // per class
     uint64_t** d_ctrs = nullptr;       // step counter of every member
     hipStream_t stream = nullptr;      // the first member's stream
     hipEvent_t ev = nullptr;
@@ -947,13 +953,83 @@ pss_status batch_refresh_plans(pss_batch* b) {
     return PSS_OK;
 }
 
+// Work lists of the fused launches: every class whose lattices fit the fused
+// kernels (one field, operators without general monomials, 4 points per
+// thread, 256-thread update blocks, lines of 64 .. 1024).  The fused x launch
+// takes 256-thread blocks of 2048/Nx rows: rows per block only regroup the
+// same per-row arithmetic.
+void batch_plan_fused(pss_batch* b) {
+    b->fu = pss::BatchLaunch{};
+    b->fx = pss::BatchLaunch{};
+    b->fu_lds = b->fx_lds = 0;
+    b->in_fu.assign(b->cls.size(), 0);
+    b->in_fx.assign(b->cls.size(), 0);
+    for (size_t k = 0; k < b->cls.size(); ++k) {
+        auto& cl = b->cls[k];
+        pss_ctx* r = cl.rep;
+        const int nmem = static_cast<int>(cl.idx.size());
+        const bool plain = r->fields.size() == 1 && !r->plan.general;
+        if (plain && r->geo.pu == 4 && r->geo.to == 1 && r->geo.tc * (r->lu / 4) == 256 && pss::batch_fused_len(r->lu) &&
+            b->fu.ncls < pss::kMaxBatchClasses) {
+            pss::BatchClass& C = b->fu.cls[b->fu.ncls++];
+            C.L = r->lu;
+            C.start = b->fu.total;
+            C.nblk = r->geo.nublk;
+            C.members = cl.d_u;
+            C.plans = cl.d_plans;
+            C.tw = r->d_tw_u;
+            C.geo = r->geo;
+            b->fu.total += nmem * C.nblk;
+            b->fu_lds = std::max(b->fu_lds, pss::update_lds_bytes(r->lu, 4, r->geo.tc, 1));
+            b->in_fu[k] = 1;
+        }
+        const int nx = r->n[0], ny = r->n[1];
+        const int rbf = nx >= 64 ? 2048 / nx : 0;
+        if (plain && r->plan.nch > 0 && r->plan.ng <= 1 && r->geo.px == 4 && pss::batch_fused_len(nx) && rbf >= 2 &&
+            rbf <= ny && b->fx.ncls < pss::kMaxBatchClasses) {
+            pss::BatchClass& C = b->fx.cls[b->fx.ncls++];
+            C.L = nx;
+            C.start = b->fx.total;
+            C.nblk = ny / rbf;
+            C.members = cl.d_x;
+            C.plans = cl.d_plans;
+            C.tw = r->d_tw_x;
+            C.geo = r->geo;
+            C.geo.rb = rbf;
+            C.geo.rb_log2 = 0;
+            while ((1 << C.geo.rb_log2) < rbf) ++C.geo.rb_log2;
+            C.geo.nrowblk = ny / rbf;
+            b->fx.total += nmem * C.nblk;
+            b->fx_lds = std::max(b->fx_lds, pss::xrow_lds_bytes(nx, 4, rbf));
+            b->in_fx[k] = 1;
+        }
+    }
+}
+
+int batch_launches_per_step(const pss_batch* b) {
+    int n = (b->fu.ncls > 0) + (b->fx.ncls > 0);
+    for (size_t k = 0; k < b->cls.size(); ++k) {
+        if (!b->in_fu[k]) ++n;
+        if (!b->in_fx[k] && b->cls[k].rep->plan.nch > 0) ++n;
+    }
+    return n;
+}
+
 pss_status batch_enqueue(pss_batch* b, int64_t k) {
     // classes with an x kernel move their members' counters on in the last
     // step's x launch; the others need the counter kernel
     bool all_x = true;
     for (auto& cl : b->cls) all_x = all_x && cl.rep->plan.nch > 0;
     for (int64_t i = 0; i < k; ++i) {
-        for (auto& cl : b->cls) {
+        const int64_t adv = (all_x && i == k - 1) ? k : 0;
+        if (b->fu.ncls > 0) {
+            pss::BatchLaunch bl = b->fu;
+            bl.step_off = static_cast<int>(i);
+            HIP_TRY(pss::launch_batch_update(b->stream, bl, b->fu_lds));
+        }
+        for (size_t c = 0; c < b->cls.size(); ++c) {
+            if (b->in_fu[c]) continue;
+            auto& cl = b->cls[c];
             pss_ctx* r = cl.rep;
             pss::LaunchArgs a = args(r, static_cast<int>(i));
             a.stream = b->stream;
@@ -961,19 +1037,68 @@ pss_status batch_enqueue(pss_batch* b, int64_t k) {
             a.plans = cl.d_plans;
             a.nmem = static_cast<int>(cl.idx.size());
             HIP_TRY(pss::launch_update(pss::MODE_STEP, r->lu, static_cast<int>(r->fields.size()), a));
-            if (r->plan.nch > 0) {
-                pss::LaunchArgs ax = xargs(r);
-                ax.stream = b->stream;
-                ax.members = cl.d_x;
-                ax.plans = cl.d_plans;
-                ax.nmem = a.nmem;
-                ax.advance = (all_x && i == k - 1) ? k : 0;
-                HIP_TRY(pss::launch_xrow(pss::MODE_STEP, r->n[0], r->plan.ng, ax));
-            }
+        }
+        if (b->fx.ncls > 0) {
+            pss::BatchLaunch bl = b->fx;
+            bl.advance = adv;
+            HIP_TRY(pss::launch_batch_xrow(b->stream, bl, b->fx_lds));
+        }
+        for (size_t c = 0; c < b->cls.size(); ++c) {
+            auto& cl = b->cls[c];
+            pss_ctx* r = cl.rep;
+            if (b->in_fx[c] || r->plan.nch == 0) continue;
+            pss::LaunchArgs ax = xargs(r);
+            ax.stream = b->stream;
+            ax.members = cl.d_x;
+            ax.plans = cl.d_plans;
+            ax.nmem = static_cast<int>(cl.idx.size());
+            ax.advance = adv;
+            HIP_TRY(pss::launch_xrow(pss::MODE_STEP, r->n[0], r->plan.ng, ax));
         }
     }
     if (!all_x) HIP_TRY(pss::launch_advance_many(b->stream, b->d_ctrs, static_cast<int>(b->mem.size()), k));
     return PSS_OK;
+}
+
+// time `reps` back-to-back fused launches of one phase (HIP events on the batch stream)
+pss_status batch_time_fused(pss_batch* b, int32_t which, int32_t reps, double* ms, double* bytes) {
+    const pss::BatchLaunch& fl = which == 0 ? b->fu : b->fx;
+    if (fl.ncls == 0) return fail(PSS_E_INVAL, "the batch has no fused %s launch", which == 0 ? "update" : "x");
+    std::vector<int> members;
+    const std::vector<char>& in = which == 0 ? b->in_fu : b->in_fx;
+    double total = 0;
+    for (size_t k = 0; k < b->cls.size(); ++k) {
+        if (!in[k]) continue;
+        members.insert(members.end(), b->cls[k].idx.begin(), b->cls[k].idx.end());
+        double one = 0;
+        if (pss_status s = pss_kernel_bytes(b->cls[k].rep, which, &one)) return s;
+        total += one * static_cast<double>(b->cls[k].idx.size());
+    }
+    if (pss_status s = batch_order_before(b, members)) return s;
+    if (pss_status s = batch_refresh_plans(b)) return s;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, b->stream));
+    for (int r = 0; r < reps; ++r) {
+        if (which == 0)
+            HIP_TRY(pss::launch_batch_update(b->stream, b->fu, b->fu_lds));
+        else
+            HIP_TRY(pss::launch_batch_xrow(b->stream, b->fx, b->fx_lds));
+    }
+    HIP_TRY(hipEventRecord(e1, b->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float t = 0;
+    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *ms = static_cast<double>(t) / reps;
+    if (bytes) *bytes = total;
+    for (int i : members) {  // repeated launches leave the channels stale and change the states
+        b->mem[i]->dirty = true;
+        ++b->mem[i]->state_gen;
+    }
+    return batch_order_after(b, members);
 }
 
 pss_status batch_graph_for(pss_batch* b, int64_t k, hipGraphExec_t* out) {
@@ -2047,6 +2172,7 @@ pss_status pss_batch_create(pss_batch** out, pss_ctx* const* lattices, int32_t n
     if (e != hipSuccess)
         return bail(fail(e == hipErrorOutOfMemory ? PSS_E_NOMEM : PSS_E_HIP, "batch set-up: %s", hipGetErrorString(e)));
     b->stream = b->mem[0]->stream;
+    batch_plan_fused(b);
     for (pss_ctx* c : b->mem) ++c->batches;
     *out = b;
     return PSS_OK;
@@ -2100,6 +2226,13 @@ pss_status pss_batch_sync(pss_batch* b) {
     return st;
 }
 
+pss_status pss_batch_launches(pss_batch* b, int32_t* per_step, int32_t* fused_classes) {
+    if (!b) return fail(PSS_E_INVAL, "null batch");
+    if (per_step) *per_step = batch_launches_per_step(b);
+    if (fused_classes) *fused_classes = b->fu.ncls;
+    return PSS_OK;
+}
+
 pss_status pss_batch_info(pss_batch* b, int32_t* n_classes, int32_t* class_of) {
     if (!b) return fail(PSS_E_INVAL, "null batch");
     if (n_classes) *n_classes = static_cast<int32_t>(b->cls.size());
@@ -2112,8 +2245,9 @@ pss_status pss_batch_info(pss_batch* b, int32_t* n_classes, int32_t* class_of) {
 pss_status pss_batch_time_kernel(pss_batch* b, int32_t cls, int32_t which, int32_t reps, double* ms,
                                  double* bytes) {
     if (!b) return fail(PSS_E_INVAL, "null batch");
-    if (cls < 0 || cls >= static_cast<int32_t>(b->cls.size())) return fail(PSS_E_INVAL, "no class %d", cls);
     if ((which != 0 && which != 1) || reps < 1 || !ms) return fail(PSS_E_INVAL, "bad kernel timing request");
+    if (cls == -1) return batch_time_fused(b, which, reps, ms, bytes);
+    if (cls < 0 || cls >= static_cast<int32_t>(b->cls.size())) return fail(PSS_E_INVAL, "no class %d", cls);
     const auto& cl = b->cls[cls];
     pss_ctx* r = cl.rep;
     if (which == 1 && r->plan.nch == 0) return fail(PSS_E_INVAL, "class %d has no x kernel", cls);

@@ -65,6 +65,10 @@ def test_batch_is_bitwise_the_single_lattice_path():
     batch = pss.Batch(mem)
     nc, of = batch.classes()
     assert nc == 5 and of[:4] == [0, 0, 0, 0] and of[4] == of[5] != of[0]
+    # fused: updates of 64^2, 128^2 and 32x128; x passes of 64^2, 128^2 and
+    # 256x16.  On their own: the update of 256x16 (lines of 16), the x pass of
+    # 32x128 (rows of 32), both of the two-field class
+    assert batch.launches() == (6, 3)
     batch.step(7)
     batch.step(60)  # crosses a graph chunk
     batch.sync()
@@ -150,6 +154,9 @@ def test_batch_kernel_timing_and_bytes():
     assert ms > 0 and nbytes == 4 * single.kernel_bytes(pss.KERNEL_UPDATE)
     ms, nbytes = batch.time_kernel(0, pss.KERNEL_X, 20)
     assert ms > 0 and nbytes == 4 * single.kernel_bytes(pss.KERNEL_X)
+    for which in (pss.KERNEL_UPDATE, pss.KERNEL_X):  # the fused launches
+        ms, nbytes = batch.time_kernel(-1, which, 20)
+        assert ms > 0 and nbytes == 4 * single.kernel_bytes(which)
     # restore the states; the next batch step must rebuild the stale channels
     twins = [_model_b((128, 128), s) for s in range(4)]
     for lat, blob in zip(mem, blobs):
@@ -168,6 +175,7 @@ def test_full_ensemble_configuration_sampled():
     mem = [_model_b((s, s), 1000 + i) for i, s in enumerate(sizes)]
     batch = pss.Batch(mem)
     assert batch.classes()[0] == 3
+    assert batch.launches() == (2, 3)  # one fused launch per phase
     batch.step(25)
     for i in (0, 255, 256, 319, 320, 335):
         twin = _model_b((sizes[i], sizes[i]), 1000 + i)
