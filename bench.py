@@ -400,6 +400,8 @@ def main():
     ap.add_argument("--autotune", dest="autotune", action="store_true",
                     help="ensemble: pss_autotune's launch geometry per size instead of the default one (a class "
                          "whose tuned geometry does not fit the fused launches then runs launches of its own)")
+    ap.add_argument("--ens-steps", type=int, default=200,
+                    help="ensemble: steps per timed run of either form")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times with a plain device "
                          "copy (a known-size reference for hardware byte counters)")
@@ -415,7 +417,7 @@ def main():
         log("no GPU visible")
         sys.exit(1)
     torch.cuda.set_device(0)
-    ens_steps = 200  # per timed run; both forms replay whole step graphs
+    ens_steps = args.ens_steps  # per timed run; both forms replay whole step graphs
 
     if args.workload == "ensemble":
         e = ensemble(args, pss, torch, ens_steps)

@@ -13,7 +13,8 @@ Sec. "Writing models"), and the noise has Fourier variance 2 D_f(q)
 One step from phi^n to phi^{n+1} follows the six-step list after
 eq:timeupdate:
 
-1. (intermediate fields: none in this oracle model; every factor is a field)
+1. compute every intermediate (non-dynamic) field from the step-n state, in
+   the order the fields were declared (Sec. "Writing models");
 2. de-alias each factor field according to the highest-order term it enters
    (Sec. "De-aliasing");
 3. transform the de-aliased factors to real space and multiply;
@@ -31,6 +32,16 @@ Readings of points the paper leaves open:
 * An explicit term with a single factor of power 1 is linear; it needs neither
   de-aliasing nor a real-space round trip, so its Fourier value is the
   factor's own spectrum (the round trip is the identity).
+* Intermediate fields.  A field without a time derivative is defined by the
+  equation "psi + lhs = rhs" of Sec. "Writing models": its implicit terms
+  (linear in psi, written on the right-hand side like those of a dynamic
+  field, so L_psi is minus the lhs prefactor) and its explicit terms give
+      psi_hat = sum_t M_t N_t / (1 - L_psi(q)),
+  the same form as eq:timeupdate without a previous value, time step or
+  noise.  The paper's example psi + psi q^2 = -q^2 phi has L_psi = -q^2 and
+  gives psi_hat = -q^2 (1 + q^2)^-1 phi_hat.  An intermediate may use the
+  dynamic fields and the intermediates declared before it; it is evaluated
+  from the step-n state, so it enters the step like any explicit term.
 * Multi-field update order: all explicit terms are evaluated from the step-n
   state, then every field is advanced (Jacobi), as the list orders
   "calculate each N_ij" before "advance each field".
@@ -84,6 +95,7 @@ class Model:
         self.dealias = dealias
         self.mask_shape = shape
         self.names = []
+        self.dynamic = []
         self.terms = []
         self.noise = {}
         self.state = []
@@ -91,9 +103,12 @@ class Model:
         self._cache = None
 
     # -- construction ---------------------------------------------------
-    def add_field(self, name):
+    def add_field(self, name, dynamic=True):
+        """A dynamic field (state kept) or an intermediate one (dynamic=False,
+        recomputed from the state whenever it is needed)."""
         self.names.append(name)
-        self.state.append(np.zeros(self.lat.shape, dtype=np.complex128))
+        self.dynamic.append(bool(dynamic))
+        self.state.append(np.zeros(self.lat.shape, dtype=np.complex128) if dynamic else None)
         self._cache = None
         return len(self.names) - 1
 
@@ -106,11 +121,15 @@ class Model:
         return len(self.terms) - 1
 
     def set_noise(self, field, op):
+        if not self.dynamic[int(field)]:
+            raise ValueError("an intermediate field has no noise")
         self.noise[int(field)] = [m if isinstance(m, Mono) else Mono(*m) for m in op]
         self._cache = None
 
     # -- state ----------------------------------------------------------
     def set_real(self, field, values):
+        if not self.dynamic[field]:
+            raise ValueError("an intermediate field is defined by its equation")
         values = np.asarray(values, dtype=np.float64).reshape(self.lat.shape)
         self.state[field] = fftn(values.astype(np.complex128))
 
@@ -122,7 +141,23 @@ class Model:
         return vals
 
     def real(self, field):
-        return ifftn(self.state[field]).real
+        return ifftn(self.spectra()[field]).real
+
+    def spectra(self):
+        """Fourier values of every field at the current step: the state of
+        each dynamic field, and each intermediate field computed in declaration
+        order (step 1 of the list)."""
+        c = self._prepare()
+        spec = list(self.state)
+        for f, dyn in enumerate(self.dynamic):
+            if dyn:
+                continue
+            acc = np.zeros(self.lat.shape, dtype=np.complex128)
+            for i, t in enumerate(self.terms):
+                if t.target == f and not t.implicit:
+                    acc = acc + c["ops"][i] * self._term_hat(t, spec)
+            spec[f] = acc / c["denom"][f]
+        return spec
 
     # -- per-plan quantities (computed once, like a plan) ----------------
     def _prepare(self):
@@ -134,7 +169,21 @@ class Model:
         for t in self.terms:
             if t.implicit:
                 lam[t.target] = lam[t.target] + lat.operator(t.op)
-        denom = [1.0 - self.dt * l for l in lam]
+        # dynamic: 1 - dt L (eq:timeupdate); intermediate: 1 - L_psi
+        denom = [1.0 - (self.dt if self.dynamic[f] else 1.0) * lam[f] for f in range(nf)]
+        for f in range(nf):
+            if self.dynamic[f]:
+                continue
+            if np.any(denom[f] == 0):
+                raise ValueError("the equation of intermediate field %d is singular at some mode" % f)
+            for t in self.terms:
+                if t.target == f and not t.implicit:
+                    for g, _ in t.factors:
+                        if not self.dynamic[g] and g >= f:
+                            raise ValueError("an intermediate field may use only intermediates declared before it")
+        for f in self.noise:
+            if not self.dynamic[f]:
+                raise ValueError("an intermediate field has no noise")
         ops = [lat.operator(t.op) for t in self.terms]
         # highest order among the nonlinear terms that contain each field
         order = [0] * nf
@@ -176,32 +225,41 @@ class Model:
         return xi
 
     # -- one step ----------------------------------------------------------
-    def nonlinear_hat(self, t_index):
-        """Fourier transform of term t's product of de-aliased factors (steps 2-4)."""
+    def _term_hat(self, t, spec):
+        """Fourier transform of term t's product of de-aliased factors (steps
+        2-4), the factors' Fourier values taken from `spec`."""
         c = self._prepare()
-        t = self.terms[t_index]
         if t.is_direct:
-            return self.state[t.factors[0][0]]
+            return spec[t.factors[0][0]]
         prod = np.ones(self.lat.shape, dtype=np.float64)
         for g, p in t.factors:
-            spec = self.state[g]
+            sg = spec[g]
             if c["masks"][g] is not None:
-                spec = spec * c["masks"][g]
-            u = ifftn(spec).real
+                sg = sg * c["masks"][g]
+            u = ifftn(sg).real
             prod = prod * u ** p
         return fftn(prod.astype(np.complex128))
+
+    def nonlinear_hat(self, t_index):
+        """Fourier transform of term t's product of de-aliased factors at the
+        current step."""
+        return self._term_hat(self.terms[t_index], self.spectra())
 
     def step(self, nsteps=1):
         c = self._prepare()
         for _ in range(int(nsteps)):
             n = self.step_index
+            spec = self.spectra()
             rhs = [np.zeros(self.lat.shape, dtype=np.complex128) for _ in self.names]
             for i, t in enumerate(self.terms):
-                if t.implicit:
+                if t.implicit or not self.dynamic[t.target]:
                     continue
-                rhs[t.target] += c["ops"][i] * self.nonlinear_hat(i)
+                rhs[t.target] += c["ops"][i] * self._term_hat(t, spec)
             new = []
             for f in range(len(self.names)):
+                if not self.dynamic[f]:
+                    new.append(None)
+                    continue
                 acc = self.state[f] + self.dt * rhs[f]
                 if f in c["sigma"]:
                     acc = acc + c["sigma"][f] * self.noise_hat(f, n)
@@ -213,9 +271,10 @@ class Model:
     def copy(self):
         m = Model(self.lat, self.dt, self.seed, self.dealias, self.mask_shape)
         m.names = list(self.names)
+        m.dynamic = list(self.dynamic)
         m.terms = list(self.terms)
         m.noise = dict(self.noise)
-        m.state = [s.copy() for s in self.state]
+        m.state = [None if s is None else s.copy() for s in self.state]
         m.step_index = self.step_index
         return m
 
@@ -255,4 +314,30 @@ def two_field_3d(lattice, dt, a=-1.0, b=1.0, k=1.0, c=-0.5, g=0.3, D=0.005,
     if D:
         m.set_noise(phi, [Mono(D, q2=1)])
         m.set_noise(psi, [Mono(D)])
+    return m
+
+
+def kpz(lattice, dt, sigma=1.0, lam=1.0, D=0.01, seed=1, dealias=DEALIAS_TWO_THIRDS,
+        shape=SHAPE_RADIAL):
+    """KPZ interface growth (Sec. "What cuPSS calculates"):
+    d/dt phi = sigma lap phi + lam (grad phi)^2 + sqrt(2 D) eta.
+
+    The nonlinearity acts on gradients, not on phi, so it is written with one
+    intermediate field per lattice axis, g_i = d_i phi (i q_i phi_hat), and
+    the explicit terms lam g_i^2 (Sec. "Writing models").  Noise is not
+    conserved, D(q) = D.
+    """
+    m = Model(lattice, dt, seed=seed, dealias=dealias, shape=shape)
+    phi = m.add_field("phi")
+    m.add_term(phi, [Mono(-sigma, q2=1)], [(phi, 1)], implicit=True)
+    for i, n in enumerate((lattice.nx, lattice.ny, lattice.nz)):
+        if n == 1:
+            continue
+        iq = [0, 0, 0]
+        iq[i] = 1
+        g = m.add_field("d%s_phi" % "xyz"[i], dynamic=False)
+        m.add_term(g, [Mono(1.0, iq=iq)], [(phi, 1)])
+        m.add_term(phi, [Mono(lam)], [(g, 2)])
+    if D:
+        m.set_noise(phi, [Mono(D)])
     return m
