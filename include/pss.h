@@ -108,16 +108,28 @@ pss_status pss_lattice_destroy(pss_ctx *ctx);
 /* ---- model ------------------------------------------------------------- */
 
 /* Declare a field (Sec. "Writing models", createField).  dynamic = 1 for a
- * field with its own time derivative.  Intermediate fields defined by a
- * linear equation (dynamic = 0) return PSS_E_UNSUPPORTED.  Names must be
- * unique, 1..63 characters.  At most 4 fields.  *field_id receives the index
- * (0, 1, ...). */
+ * field with its own time derivative (at most 4); dynamic = 0 for an
+ * intermediate field (at most 4), defined by an equation without a time
+ * derivative, "psi + lhs = rhs" in the paper's notation: its implicit terms
+ * (operators on psi itself, written on the right-hand side like those of a
+ * dynamic field, so L_psi is minus the lhs prefactor) and its explicit terms
+ * give  psi_hat = sum_t M_t phi_t_hat / (1 - L_psi(q)).  The paper's example
+ * psi + psi q^2 = -q^2 phi is the implicit term -q^2 psi and the explicit
+ * term -q^2 phi.  Each explicit term of an intermediate field must be one
+ * dynamic field to the first power (PSS_E_UNSUPPORTED otherwise, also for an
+ * intermediate source).  Intermediate fields enter the terms of dynamic fields
+ * as factors of products (de-aliased like any factor) or as sources of linear
+ * terms; they are evaluated from the step-n state, as step 1 of the per-step
+ * list after eq:timeupdate.  Names must be unique over both kinds, 1..63
+ * characters.  *field_id receives the declaration index (0, 1, ...), which
+ * every other call takes and which keys the field's random numbers. */
 pss_status pss_field_declare(pss_ctx *ctx, const char *name, int32_t dynamic,
                              int32_t *field_id);
 
 /* Add a term  op(q) * prod_j field_j^power_j  to d/dt of target_field
  * (eq:basereal; the operator acts on the whole product, Sec. "Writing
- * models").  implicit = 1 requires exactly one factor, the target field to
+ * models"), or to the equation of an intermediate target (see
+ * pss_field_declare).  implicit = 1 requires exactly one factor, the target field to
  * the power 1 (implicit terms must be linear in their field); its operator is
  * added to L(q).  Explicit terms: 1 to 4 factors with powers 1..8; a single
  * factor of power 1 is applied directly in Fourier space, any other term is
@@ -171,13 +183,18 @@ pss_status pss_tuning_set(pss_ctx *ctx, const char *key, int64_t value);
 pss_status pss_tuning_get(pss_ctx *ctx, const char *key, int64_t *value);
 
 /* Check the model without touching the device: implicit terms, noise
- * operators, and stability Re(1 - dt L(q)) > 0 on every mode. */
+ * operators, stability Re(1 - dt L(q)) > 0 on every mode of every dynamic
+ * field, and |1 - L_psi(q)| > 1e-6 max(1, |L_psi(q)|) on every mode of every
+ * intermediate field (PSS_E_UNSTABLE otherwise). */
 pss_status pss_validate(pss_ctx *ctx);
 
 /* ---- state ------------------------------------------------------------- */
 
 /* Set field from a real-space float32 array (host, or device if on_device).
- * Synchronous: returns after the forward transform has completed. */
+ * Synchronous: returns after the forward transform has completed.  Dynamic
+ * fields only (PSS_E_INVAL for an intermediate field); the same holds for
+ * pss_field_init_uniform, pss_spectrum_download, pss_mass and the
+ * structure-factor calls. */
 pss_status pss_field_upload(pss_ctx *ctx, int32_t field, const float *real_xyz,
                             int32_t on_device);
 
@@ -187,7 +204,8 @@ pss_status pss_field_upload(pss_ctx *ctx, int32_t field, const float *real_xyz,
 pss_status pss_field_init_uniform(pss_ctx *ctx, int32_t field, double lo, double hi);
 
 /* Write the real-space field (inverse transform of the full state, no
- * de-aliasing) to a float32 array.  Synchronous. */
+ * de-aliasing) to a float32 array.  An intermediate field is computed on the
+ * device from the current state of the dynamic fields.  Synchronous. */
 pss_status pss_field_download(pss_ctx *ctx, int32_t field, float *real_xyz,
                               int32_t on_device);
 

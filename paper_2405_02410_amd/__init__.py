@@ -479,3 +479,23 @@ def model_b(lat, a=-1.0, b=1.0, k=1.0, D=0.01):
     if D:
         lat.noise(f, [Mono(D, q2=1)])
     return f, (t_imp, t_nl)
+
+
+def kpz(lat, sigma=1.0, lam=1.0, D=0.01):
+    """KPZ interface growth, Sec. "What cuPSS calculates":
+    d/dt phi = sigma lap phi + lam (grad phi)^2 + sqrt(2 D) eta, written with one
+    intermediate field per axis, g_i = d_i phi (i q_i phi), and explicit terms
+    lam g_i^2.  Returns the field id of phi and the ids of the gradient fields."""
+    f = lat.field("phi")
+    lat.term(f, [Mono(-sigma, q2=1)], [(f, 1)], implicit=True)
+    grads = []
+    for i in range(lat.ndim):
+        iq = [0, 0, 0]
+        iq[i] = 1
+        g = lat.field("d%s_phi" % "xyz"[i], dynamic=False)
+        lat.term(g, [Mono(1.0, iq=tuple(iq))], [(f, 1)])
+        lat.term(f, [Mono(lam)], [(g, 2)])
+        grads.append(g)
+    if D:
+        lat.noise(f, [Mono(D)])
+    return f, grads

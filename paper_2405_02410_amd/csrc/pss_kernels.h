@@ -21,6 +21,7 @@ enum {
     MODE_ADJROW = 8,     // x kernel: adjoint row pass (Model B), see AdjArgs
     MODE_ADJCOL = 9,     // adjoint column kernel: one reverse step
     MODE_ADJFIN = 10,    // adjoint column kernel: g_0 from the last reverse step
+    MODE_INTERM_OUT = 11,  // update kernel: inverse transform of intermediate `sel` into `out`
 };
 
 // Device arrays used by a launch (all in the packed half-spectrum layout

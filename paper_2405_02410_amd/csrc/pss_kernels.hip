@@ -223,7 +223,7 @@ __device__ __forceinline__ int line_lim(const DevMask& mk, int kx, int ky, int L
 __device__ __forceinline__ float2 noise_value(const DevPlan& p, int f, uint32_t step, uint32_t lin, uint32_t lneg,
                                               float D) {
     const uint32_t c = lin < lneg ? lin : lneg;
-    const uint4 w = philox4x32_10(make_uint4(c, step, static_cast<uint32_t>(f), 0u), p.key0, p.key1);
+    const uint4 w = philox4x32_10(make_uint4(c, step, static_cast<uint32_t>(p.fid[f]), 0u), p.key0, p.key1);
     const float2 g = box_muller(w.x, w.y);
     const float sd = __builtin_amdgcn_sqrtf(fmaxf(D, 0.f));
     if (lin == lneg) return make_float2(p.amp_self * sd * g.x, 0.f);
@@ -419,6 +419,64 @@ __device__ __forceinline__ void pair_accumulate(float2 (&acc)[NF][P], int target
     add_to(acc, target, P / 2, pair_op_d<DIM, GEN>(p, op, ky_l, L >> 1, L, v[P / 2]));
 }
 
+// Fourier value of an intermediate field at the slots of one line, from the
+// dynamic fields' values s there (Sec. "Writing models"):
+//   psi = sum_k op_k(q) phi_{src_k} / (1 - L_psi(q)).
+// On a packed line the pair slots come out in the same form as the state's:
+// (value of the kx = 0 mode, value of the kx = -Nx/2 mode), both real, since
+// every operator is real on those four self-conjugate modes.
+template <int L, int P, int NF, int DIM>
+__device__ __forceinline__ void interm_line(const DevPlan& p, const DevInterm& I, const float2 (&s)[NF][P],
+                                            const LineModes lm, int t, bool pair_lane, int ky_l, float2 (&v)[P]) {
+    constexpr int T = L / P;
+    ModeQ q[P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+        q[m] = slot_q<L, DIM>(p, lm, t + m * T);
+        v[m] = make_float2(0.f, 0.f);
+    }
+    for (int k = 0; k < I.nsrc; ++k) {
+        const int src = I.src[k];
+#pragma unroll
+        for (int m = 0; m < P; ++m) v[m] = cadd(v[m], cmul(eval_op<true>(I.op[k], q[m]), pick(s, src, m)));
+    }
+#pragma unroll
+    for (int m = 0; m < P; ++m) v[m] = cmul(v[m], cinv_implicit(1.f, eval_op<true>(I.den, q[m])));
+    if (pair_lane) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int mm = h ? P / 2 : 0;
+            int ky, kz;
+            pair_modes<DIM>(ky_l, h ? (L >> 1) : 0, L, ky, kz);
+            const ModeQ q0 = mode_q(p, 0, ky, kz), qn = mode_q(p, -(p.n[0] >> 1), ky, kz);
+            float re = 0.f, im = 0.f;
+            for (int k = 0; k < I.nsrc; ++k) {
+                const float2 a = pick(s, I.src[k], mm);
+                re = fmaf(eval_op<true>(I.op[k], q0).x, a.x, re);
+                im = fmaf(eval_op<true>(I.op[k], qn).x, a.y, im);
+            }
+            v[mm] = make_float2(re * cinv_implicit(1.f, eval_op<true>(I.den, q0)).x,
+                                im * cinv_implicit(1.f, eval_op<true>(I.den, qn)).x);
+        }
+    }
+}
+
+// the values of factor or linear-term source `src` at the slots of a line:
+// a dynamic field's own, or an intermediate's (only plans with the general
+// operator code have intermediates)
+template <int L, int P, int NF, int DIM, bool GEN>
+__device__ __forceinline__ void source_line(const DevPlan& p, int src, const float2 (&s)[NF][P], const LineModes lm,
+                                            int t, bool pair_lane, int ky_l, float2 (&v)[P]) {
+    if constexpr (GEN) {
+        if (src >= PSS_MAXF) {
+            interm_line<L, P, NF, DIM>(p, p.interm[src - PSS_MAXF], s, lm, t, pair_lane, ky_l, v);
+            return;
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < P; ++m) v[m] = pick(s, src, m);
+}
+
 // One block of the update kernel: tile `blk` of lattice `mi`.  In the step
 // modes of several lattices (TABLE) the lattice's buffers, counter and flag
 // come from the member table and its plan from the plan array (both kernel
@@ -547,7 +605,7 @@ __device__ __forceinline__ void update_block(int mi, int blk, const Member* __re
         return;
     }
 
-    // ---- MODE_STEP or MODE_PROLOGUE
+    // ---- MODE_STEP, MODE_PROLOGUE or MODE_INTERM_OUT
     const LineModes lmode = line_modes<L, DIM>(p, packed, kx_l, ky_l);
     float2 s[NF][P];  // state, then new state (slot form on a packed line)
 #pragma unroll
@@ -561,6 +619,19 @@ __device__ __forceinline__ void update_block(int mi, int blk, const Member* __re
         }
     }
 
+    if constexpr (MODE == MODE_INTERM_OUT) {
+        // an intermediate field from the current state, inverse-transformed
+        // along the line into `out` (natural order, as MODE_INV_OUT)
+        store_twiddles<L, P>(twl, twr, tid, nthr);
+        __syncthreads();
+        float2 v[P];
+        source_line<L, P, NF, DIM, GEN>(p, PSS_MAXF + bufs.sel, s, lmode, t, pair_lane, ky_l, v);
+        exchange(v, false);
+        FFT::template dif<1>(v, ld, t, tw);
+#pragma unroll
+        for (int m = 0; m < P; ++m) gstore(bufs.out + vbase + (dr + m * T) * vstride, v[m]);
+        return;
+    }
     if constexpr (MODE == MODE_PROLOGUE) {
         store_twiddles<L, P>(twl, twr, tid, nthr);
         __syncthreads();
@@ -615,9 +686,8 @@ __device__ __forceinline__ void update_block(int mi, int blk, const Member* __re
         // Fourier-space terms with a single linear factor
         for (int d = 0; d < p.nd; ++d) {
             const DevDirect& Dd = p.direct[d];
-            float2 src[P];
-#pragma unroll
-            for (int m = 0; m < P; ++m) src[m] = pick(s, Dd.src, m);
+            float2 src[P];  // from the step-n state (an intermediate: its step-n value)
+            source_line<L, P, NF, DIM, GEN>(p, Dd.src, s, lmode, t, pair_lane, ky_l, src);
             if constexpr (GEN) {
 #pragma unroll
                 for (int m = 0; m < P; ++m)
@@ -682,7 +752,10 @@ __device__ __forceinline__ void update_block(int mi, int blk, const Member* __re
     for (int g = 0; g < p.ng; ++g) {
         const DevMask& mk = p.mask[g];
         if (ct * tc >= mk.ncol) continue;  // whole tile masked: never read (block-uniform)
-        const int fg = p.gfield[g];
+        // the factor's Fourier values (a dynamic field's new state, or an
+        // intermediate computed from it)
+        float2 a[P];
+        source_line<L, P, NF, DIM, GEN>(p, p.gfield[g], s, lmode, t, pair_lane, ky_l, a);
         // the largest kept w^2 of this line (packed: of each half)
         const int lim = line_lim<DIM>(mk, lmode.packed ? 0 : kx_l, ky_l, L);
         const int limN = line_lim<DIM>(mk, -(nx >> 1), ky_l, L);
@@ -690,15 +763,14 @@ __device__ __forceinline__ void update_block(int mi, int blk, const Member* __re
 #pragma unroll
         for (int m = 0; m < P; ++m) {
             const int u = t + m * T;
-            const float2 a = pick(s, fg, m);
             const bool upper = packed && u > (L >> 1);
             const int w = packed ? (upper ? L - u : u) : (u < (L >> 1) ? u : u - L);
-            v[m] = w * w <= (upper ? limN : lim) ? a : make_float2(0.f, 0.f);
+            v[m] = w * w <= (upper ? limN : lim) ? a[m] : make_float2(0.f, 0.f);
         }
         if (pair_lane) {
             // slots 0 and L/2: kx = 0 (re) and kx = -Nx/2 (im) at w = 0, -L/2
             const int wh = (L >> 1) * (L >> 1);
-            const float2 a0 = pick(s, fg, 0), ah = pick(s, fg, P / 2);
+            const float2 a0 = a[0], ah = a[P / 2];
             v[0] = make_float2(0 <= lim ? a0.x : 0.f, 0 <= limN ? a0.y : 0.f);
             v[P / 2] = make_float2(wh <= lim ? ah.x : 0.f, wh <= limN ? ah.y : 0.f);
         }
@@ -1408,7 +1480,13 @@ static hipError_t launch_update_tab(int mode, const LaunchArgs& a, dim3 grid, di
             else
                 PSS_UPD(MODE_STEP, false, NF);
             break;
-        case MODE_PROLOGUE: PSS_UPD(MODE_PROLOGUE, false, NF); break;
+        case MODE_PROLOGUE:
+            if (a.general)
+                PSS_UPD(MODE_PROLOGUE, true, NF);
+            else
+                PSS_UPD(MODE_PROLOGUE, false, NF);
+            break;
+        case MODE_INTERM_OUT: PSS_UPD(MODE_INTERM_OUT, true, NF); break;
         default: return hipErrorInvalidValue;
     }
 #undef PSS_UPD
@@ -1419,8 +1497,9 @@ template <int L, int P, int NF, int DIM>
 static hipError_t launch_update_d(int mode, const LaunchArgs& a) {
     const int threads = a.geo.tc * a.geo.to * (L / P);
     const size_t lds = update_lds_bytes(L, P, a.geo.tc, a.geo.to);
-    const bool tab = mode == MODE_STEP || mode == MODE_PROLOGUE;
+    const bool tab = mode == MODE_STEP || mode == MODE_PROLOGUE || mode == MODE_INTERM_OUT;
     if (tab && (!a.members || !a.plans || a.nmem < 1)) return hipErrorInvalidValue;
+    if (mode == MODE_INTERM_OUT && a.nmem != 1) return hipErrorInvalidValue;
     dim3 grid(a.geo.nublk, tab ? a.nmem : 1), block(threads);
     if (tab) {
         // one lattice: buffers, counter and flag come from the arguments

@@ -29,6 +29,7 @@
 #define PSS_MAXPT 8   // products per channel
 #define PSS_MAXD 8    // Fourier-space (single linear factor) terms
 #define PSS_MAXPOW 8  // largest factor power / operator power
+#define PSS_MAXI 4    // intermediate (non-dynamic) fields
 
 namespace pss {
 
@@ -60,8 +61,20 @@ struct DevChannel {
 };
 
 struct DevDirect {
-    int32_t target, src;
+    int32_t target, src;  // src: dynamic field, or PSS_MAXF + intermediate
     DevOp op;
+};
+
+// An intermediate field (Sec. "Writing models": a field defined by an
+// equation without a time derivative), linear in the dynamic fields:
+//   psi = sum_k op_k(q) phi_{src_k} / (1 - L_psi(q)),
+// L_psi the sum of its implicit operators.  Factor slots and linear terms name
+// it as source PSS_MAXF + its index.
+struct DevInterm {
+    int32_t nsrc;
+    int32_t src[PSS_MAXF];  // dynamic field of each linear term
+    DevOp op[PSS_MAXF];
+    DevOp den;  // L_psi
 };
 
 struct DevMask {
@@ -88,13 +101,16 @@ struct DevPlan {
     float amp_self;    // sqrt(2 dt N / dV)
     uint32_t key0, key1;
     int32_t noisy[PSS_MAXF];
-    int32_t gfield[PSS_MAXF];  // factor slot -> field
+    int32_t fid[PSS_MAXF];     // declaration index of each dynamic field (its random-number key)
+    int32_t gfield[PSS_MAXF];  // factor slot -> dynamic field, or PSS_MAXF + intermediate
     DevMask mask[PSS_MAXF];    // per factor slot
     DevOp implicit_op[PSS_MAXF];
     DevOp noise_op[PSS_MAXF];
     DevDirect direct[PSS_MAXD];
     DevChannel ch[PSS_MAXCH];
-    int32_t general;  // some operator has 1/|q| or i q_i monomials (general list)
+    int32_t general;  // some operator has 1/|q| or i q_i monomials (general list), or ni > 0
+    int32_t ni;
+    DevInterm interm[PSS_MAXI];
 };
 
 }  // namespace pss

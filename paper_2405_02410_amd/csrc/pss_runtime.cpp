@@ -60,7 +60,8 @@ struct Term {
     std::vector<Mono> op;
     std::vector<std::pair<int, int>> factors;  // (field, power)
     // where its coefficients live in the compiled plan
-    int kind = 0;      // 0 implicit, 1 direct, 2 channel (single monomial), 3 channel (own operator)
+    int kind = 0;      // 0 implicit, 1 direct, 2 channel (single monomial), 3 channel (own operator),
+                       // 4 a term of an intermediate field's equation
     int slot = -1;     // field / direct / channel index
     int mono0 = -1;    // first monomial index inside the slot operator (kinds 0, 1, 3)
     int prod = -1;     // product index inside the channel (kind 2)
@@ -71,6 +72,11 @@ struct Field {
     bool noisy = false;
     std::vector<Mono> noise;
 };
+
+// Declared fields are numbered in declaration order.  Internally a dynamic
+// field is its index among the dynamic fields and an intermediate field is
+// PSS_MAXF + its index among the intermediates (the same codes the plan uses).
+bool is_interm(int code) { return code >= PSS_MAXF; }
 
 bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
 
@@ -136,8 +142,10 @@ struct pss_ctx {
     double dt = 0;
     uint64_t seed = 0;
     int rule = PSS_DEALIAS_TWO_THIRDS, shape = PSS_SHAPE_RADIAL;
-    std::vector<Field> fields;
-    std::vector<Term> terms;
+    std::vector<Field> fields;          // dynamic fields
+    std::vector<std::string> interms;   // intermediate fields (names)
+    std::vector<int> ids;               // declared field -> internal code
+    std::vector<Term> terms;            // fields named by internal code
 
     // device side
     bool planned = false;
@@ -230,6 +238,19 @@ struct pss_tape {
 
 namespace {
 
+int field_code(const pss_ctx* c, int32_t id) {
+    return id >= 0 && id < static_cast<int32_t>(c->ids.size()) ? c->ids[id] : -1;
+}
+
+// a declared field that must be dynamic -> its dynamic index
+pss_status dyn_field(const pss_ctx* c, int32_t id, int* f) {
+    const int code = field_code(c, id);
+    if (code < 0) return fail(PSS_E_INVAL, "bad field");
+    if (is_interm(code)) return fail(PSS_E_INVAL, "field %d is an intermediate field, defined by its equation", id);
+    *f = code;
+    return PSS_OK;
+}
+
 pss_status check_ctx(pss_ctx* c) {
     if (!c) return fail(PSS_E_INVAL, "null context");
     return PSS_OK;
@@ -299,10 +320,27 @@ void for_each_mode(const pss_ctx* c, F&& fn) {
 pss_status validate(pss_ctx* c) {
     const int nf = static_cast<int>(c->fields.size());
     if (nf == 0) return fail(PSS_E_STATE, "no fields declared");
-    std::vector<std::vector<Mono>> lam(nf);
-    for (const Term& t : c->terms)
-        if (t.implicit) lam[t.target].insert(lam[t.target].end(), t.op.begin(), t.op.end());
+    const int ni = static_cast<int>(c->interms.size());
+    std::vector<std::vector<Mono>> lam(nf), lam_i(ni);
+    for (const Term& t : c->terms) {
+        if (!t.implicit) continue;
+        auto& dst = is_interm(t.target) ? lam_i[t.target - PSS_MAXF] : lam[t.target];
+        dst.insert(dst.end(), t.op.begin(), t.op.end());
+    }
     pss_status st = PSS_OK;
+    // an intermediate field's equation must be solvable at every mode: psi =
+    // rhs / (1 - L_psi(q)) with 1 - L_psi bounded away from zero
+    for (int i = 0; i < ni && st == PSS_OK; ++i) {
+        for_each_mode(c, [&](const double* q, bool* nyq) {
+            if (st != PSS_OK) return;
+            double im = 0;
+            const double re = op_real_at(lam_i[i], q, nyq, &im);
+            const double d = std::hypot(1.0 - re, im), l = std::hypot(re, im);
+            if (!(d > 1e-6 * std::max(1.0, l)))
+                st = fail(PSS_E_UNSTABLE, "intermediate field '%s': 1 - L(q) = %g vanishes at q = (%g, %g, %g)",
+                          c->interms[i].c_str(), d, q[0], q[1], q[2]);
+        });
+    }
     for (int f = 0; f < nf && st == PSS_OK; ++f) {
         for_each_mode(c, [&](const double* q, bool* nyq) {
             if (st != PSS_OK) return;
@@ -396,14 +434,41 @@ pss_status build_plan(pss_ctx* c) {
         return ++op.n;
     };
 
+    for (size_t id = 0; id < c->ids.size(); ++id)
+        if (!is_interm(c->ids[id])) P.fid[c->ids[id]] = static_cast<int32_t>(id);
+    const int ni = static_cast<int>(c->interms.size());
+    P.ni = ni;
     for (int f = 0; f < nf; ++f) {
         P.noisy[f] = c->fields[f].noisy ? 1 : 0;
         for (const Mono& m : c->fields[f].noise)
             if (put_mono(P.noise_op[f], m) < 0) return fail(PSS_E_UNSUPPORTED, "too many noise monomials");
     }
     // factor slots: fields entering real-space products, with the highest order
-    std::vector<int> order(nf, 0);
+    // (indexed by internal code)
+    std::vector<int> order(PSS_MAXF + PSS_MAXI, 0);
     for (Term& t : c->terms) {
+        if (is_interm(t.target)) {
+            // psi = sum_k op_k phi_k / (1 - L_psi): implicit terms build L_psi,
+            // explicit ones (one dynamic factor to the first power) op_k
+            DevInterm& I = P.interm[t.target - PSS_MAXF];
+            t.kind = 4;
+            t.slot = t.target - PSS_MAXF;
+            if (t.implicit) {
+                for (const Mono& m : t.op)
+                    if (put_mono(I.den, m) < 0)
+                        return fail(PSS_E_UNSUPPORTED, "more than %d implicit monomials on a field", PSS_MAXM);
+                continue;
+            }
+            const int src = t.factors[0].first;
+            int k = 0;
+            while (k < I.nsrc && I.src[k] != src) ++k;
+            if (k == I.nsrc) I.src[I.nsrc++] = src;
+            for (const Mono& m : t.op)
+                if (put_mono(I.op[k], m) < 0)
+                    return fail(PSS_E_UNSUPPORTED, "more than %d monomials on one source of an intermediate field",
+                                PSS_MAXM);
+            continue;
+        }
         if (t.implicit) {
             t.kind = 0;
             t.slot = t.target;
@@ -428,21 +493,23 @@ pss_status build_plan(pss_ctx* c) {
         for (auto& fp : t.factors) ord += fp.second;
         for (auto& fp : t.factors) order[fp.first] = std::max(order[fp.first], ord);
     }
-    int gslot[PSS_MAXF];
+    int gslot[PSS_MAXF + PSS_MAXI];
     P.ng = 0;
-    for (int f = 0; f < nf; ++f) {
-        gslot[f] = -1;
-        if (order[f] > 0) {
-            gslot[f] = P.ng;
-            P.gfield[P.ng] = f;
-            P.mask[P.ng] = make_mask(c, c->rule, c->shape, order[f]);
+    for (int code = 0; code < PSS_MAXF + PSS_MAXI; ++code) {
+        gslot[code] = -1;
+        if (order[code] > 0) {
+            if (P.ng >= PSS_MAXF)
+                return fail(PSS_E_UNSUPPORTED, "at most %d distinct fields in real-space products", PSS_MAXF);
+            gslot[code] = P.ng;
+            P.gfield[P.ng] = code;
+            P.mask[P.ng] = make_mask(c, c->rule, c->shape, order[code]);
             ++P.ng;
         }
     }
     // channels; single-monomial terms with the same target and shape share one
     std::tuple<int, int, int, int, int, int> chan_key[PSS_MAXCH];
     for (Term& t : c->terms) {
-        if (t.implicit || t.kind == 1) continue;
+        if (t.implicit || t.kind == 1 || t.kind == 4) continue;
         const bool single = t.op.size() == 1;
         int ch = -1;
         if (single) {
@@ -493,11 +560,16 @@ pss_status build_plan(pss_ctx* c) {
     }
     for (int d = 0; d < P.nd; ++d) set_deg(P.direct[d].op);
     for (int k = 0; k < P.nch; ++k) set_deg(P.ch[k].op);
+    for (int i = 0; i < ni; ++i) {
+        set_deg(P.interm[i].den);
+        for (int k = 0; k < P.interm[i].nsrc; ++k) set_deg(P.interm[i].op[k]);
+    }
     // kernels without the general-monomial code unless some operator needs it
     P.general = 0;
     for (int f = 0; f < nf; ++f) P.general |= (P.implicit_op[f].n > 0) | (P.noise_op[f].n > 0);
     for (int d = 0; d < P.nd; ++d) P.general |= P.direct[d].op.n > 0;
     for (int k = 0; k < P.nch; ++k) P.general |= P.ch[k].op.n > 0;
+    P.general |= ni > 0;  // intermediates are evaluated by the general-operator code
     return PSS_OK;
 }
 
@@ -892,6 +964,27 @@ pss_status state_to_real(pss_ctx* c, int field) {
     return PSS_OK;
 }
 
+// intermediate field i, computed from the current state -> real-space array
+// on the device (d_real)
+pss_status interm_to_real(pss_ctx* c, int i) {
+    pss::LaunchArgs a = args(c);
+    a.bufs.sel = i;
+    a.bufs.out = c->d_tmp;
+    HIP_TRY(pss::launch_update(pss::MODE_INTERM_OUT, c->lu, static_cast<int>(c->fields.size()), a));
+    if (c->ndim == 3) {
+        pss::YArgs ya{};
+        ya.n = 1;
+        ya.src[0] = c->d_tmp;
+        ya.dst[0] = c->d_tmp;
+        ya.ncol[0] = c->n[0] / 2;
+        HIP_TRY(pss::launch_ypass(pss::MODE_YINV, c->n[1], ya, a));
+    }
+    a.bufs.in = c->d_tmp;
+    a.bufs.real_out = c->d_real;
+    HIP_TRY(pss::launch_xrow(pss::MODE_C2R_OUT, c->n[0], 1, a));
+    return PSS_OK;
+}
+
 pss_status graph_for(pss_ctx* c, int64_t k, hipGraphExec_t* out) {
     auto it = c->graphs.find(k);
     if (it != c->graphs.end()) {
@@ -920,6 +1013,7 @@ constexpr int64_t kGraphSteps = 50;
 
 bool same_class(const pss_ctx* a, const pss_ctx* b) {
     return a->n[0] == b->n[0] && a->n[1] == b->n[1] && a->fields.size() == b->fields.size() &&
+           a->interms.size() == b->interms.size() &&
            a->plan.ng == b->plan.ng && a->plan.nch == b->plan.nch && a->plan.general == b->plan.general &&
            std::memcmp(&a->geo, &b->geo, sizeof(pss::Geo)) == 0;
 }
@@ -1253,15 +1347,24 @@ pss_status pss_field_declare(pss_ctx* c, const char* name, int32_t dynamic, int3
     if (pss_status s = check_ctx(c)) return s;
     if (c->planned) return fail(PSS_E_STATE, "fields cannot be added after the plan is built");
     if (!name || !*name || std::strlen(name) > 63) return fail(PSS_E_INVAL, "field name must have 1..63 characters");
-    if (!dynamic)
-        return fail(PSS_E_UNSUPPORTED, "intermediate (non-dynamic) fields are not supported yet");
     for (const Field& f : c->fields)
         if (f.name == name) return fail(PSS_E_INVAL, "field '%s' already declared", name);
-    if (static_cast<int>(c->fields.size()) >= PSS_MAXF) return fail(PSS_E_UNSUPPORTED, "at most %d fields", PSS_MAXF);
-    Field f;
-    f.name = name;
-    c->fields.push_back(f);
-    if (field_id) *field_id = static_cast<int32_t>(c->fields.size() - 1);
+    for (const std::string& f : c->interms)
+        if (f == name) return fail(PSS_E_INVAL, "field '%s' already declared", name);
+    if (dynamic) {
+        if (static_cast<int>(c->fields.size()) >= PSS_MAXF)
+            return fail(PSS_E_UNSUPPORTED, "at most %d dynamic fields", PSS_MAXF);
+        Field f;
+        f.name = name;
+        c->fields.push_back(f);
+        c->ids.push_back(static_cast<int>(c->fields.size()) - 1);
+    } else {
+        if (static_cast<int>(c->interms.size()) >= PSS_MAXI)
+            return fail(PSS_E_UNSUPPORTED, "at most %d intermediate fields", PSS_MAXI);
+        c->interms.push_back(name);
+        c->ids.push_back(PSS_MAXF + static_cast<int>(c->interms.size()) - 1);
+    }
+    if (field_id) *field_id = static_cast<int32_t>(c->ids.size() - 1);
     return PSS_OK;
 }
 
@@ -1270,25 +1373,29 @@ pss_status pss_term_add(pss_ctx* c, int32_t target, int32_t implicit, const pss_
                         int32_t* term_id) {
     if (pss_status s = check_ctx(c)) return s;
     if (c->planned) return fail(PSS_E_STATE, "terms cannot be added after the plan is built");
-    const int nf = static_cast<int>(c->fields.size());
-    if (target < 0 || target >= nf) return fail(PSS_E_INVAL, "target field %d out of range", target);
+    const int tcode = field_code(c, target);
+    if (tcode < 0) return fail(PSS_E_INVAL, "target field %d out of range", target);
     if (pss_status s = check_ops(op, n_mono, false)) return s;
     if (n_factors < 1 || n_factors > 4 || !factor_fields || !factor_powers)
         return fail(PSS_E_INVAL, "a term needs 1..4 factors");
     if (static_cast<int>(c->terms.size()) >= PSS_MAXT) return fail(PSS_E_UNSUPPORTED, "at most %d terms", PSS_MAXT);
     Term t;
-    t.target = target;
+    t.target = tcode;
     t.implicit = implicit != 0;
     t.op = to_monos(op, n_mono);
     for (int i = 0; i < n_factors; ++i) {
-        if (factor_fields[i] < 0 || factor_fields[i] >= nf)
-            return fail(PSS_E_INVAL, "factor field %d out of range", factor_fields[i]);
+        const int code = field_code(c, factor_fields[i]);
+        if (code < 0) return fail(PSS_E_INVAL, "factor field %d out of range", factor_fields[i]);
         if (factor_powers[i] < 1 || factor_powers[i] > PSS_MAXPOW)
             return fail(PSS_E_INVAL, "factor powers must lie in [1, %d]", PSS_MAXPOW);
-        t.factors.push_back({factor_fields[i], factor_powers[i]});
+        t.factors.push_back({code, factor_powers[i]});
     }
     if (t.implicit && !(n_factors == 1 && factor_fields[0] == target && factor_powers[0] == 1))
         return fail(PSS_E_INVAL, "an implicit term must be linear in its own field (op * field)");
+    if (is_interm(tcode) && !t.implicit &&
+        !(n_factors == 1 && factor_powers[0] == 1 && !is_interm(t.factors[0].first)))
+        return fail(PSS_E_UNSUPPORTED,
+                    "an explicit term of an intermediate field must be one dynamic field to the first power");
     int total = 0;
     for (auto& fp : t.factors) total += fp.second;
     if (total > PSS_MAXPOW) return fail(PSS_E_INVAL, "total order above %d", PSS_MAXPOW);
@@ -1326,10 +1433,11 @@ pss_status pss_term_set_coef(pss_ctx* c, int32_t term_id, int32_t mono, double c
 
 pss_status pss_noise_set(pss_ctx* c, int32_t field, const pss_qmono* D, int32_t n_mono) {
     if (pss_status s = check_ctx(c)) return s;
-    if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    int fd = 0;
+    if (pss_status s = dyn_field(c, field, &fd)) return s;
     if (pss_status s = check_ops(D, n_mono, true)) return s;
     std::vector<Mono> nm = to_monos(D, n_mono);
-    Field& fl = c->fields[field];
+    Field& fl = c->fields[fd];
     if (!c->planned) {
         fl.noisy = true;
         fl.noise = nm;
@@ -1439,12 +1547,13 @@ pss_status pss_field_upload(pss_ctx* c, int32_t field, const float* real, int32_
     if (pss_status s = check_ctx(c)) return s;
     if (!real) return fail(PSS_E_INVAL, "null array");
     if (pss_status s = materialize(c)) return s;
-    if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    int fd = 0;
+    if (pss_status s = dyn_field(c, field, &fd)) return s;
     if (pss_status s_bw = begin_work(c)) return s_bw;
     const size_t bytes = sizeof(float) * static_cast<size_t>(c->sites());
     HIP_TRY(hipMemcpyAsync(c->d_real, real, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                            c->stream));
-    if (pss_status s = forward_to_state(c, field)) return s;
+    if (pss_status s = forward_to_state(c, fd)) return s;
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->dirty = true;
     ++c->state_gen;
@@ -1455,11 +1564,13 @@ pss_status pss_field_init_uniform(pss_ctx* c, int32_t field, double lo, double h
     if (pss_status s = check_ctx(c)) return s;
     if (!std::isfinite(lo) || !std::isfinite(hi)) return fail(PSS_E_INVAL, "non-finite bounds");
     if (pss_status s = materialize(c)) return s;
-    if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    int fd = 0;
+    if (pss_status s = dyn_field(c, field, &fd)) return s;
     if (pss_status s_bw = begin_work(c)) return s_bw;
+    // keyed by the declared field number, as the noise is
     HIP_TRY(pss::launch_init_uniform(c->stream, c->d_real, c->sites(), static_cast<uint32_t>(field),
                                      c->plan.key0, c->plan.key1, lo, hi));
-    if (pss_status s = forward_to_state(c, field)) return s;
+    if (pss_status s = forward_to_state(c, fd)) return s;
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->dirty = true;
     ++c->state_gen;
@@ -1470,9 +1581,14 @@ pss_status pss_field_download(pss_ctx* c, int32_t field, float* real, int32_t on
     if (pss_status s = check_ctx(c)) return s;
     if (!real) return fail(PSS_E_INVAL, "null array");
     if (pss_status s = materialize(c)) return s;
-    if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    const int code = field_code(c, field);
+    if (code < 0) return fail(PSS_E_INVAL, "bad field");
     if (pss_status s_bw = begin_work(c)) return s_bw;
-    if (pss_status s = state_to_real(c, field)) return s;
+    if (is_interm(code)) {
+        if (pss_status s = interm_to_real(c, code - PSS_MAXF)) return s;
+    } else if (pss_status s = state_to_real(c, code)) {
+        return s;
+    }
     const size_t bytes = sizeof(float) * static_cast<size_t>(c->sites());
     HIP_TRY(hipMemcpyAsync(real, c->d_real, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                            c->stream));
@@ -1484,10 +1600,11 @@ pss_status pss_spectrum_download(pss_ctx* c, int32_t field, float* half, int32_t
     if (pss_status s = check_ctx(c)) return s;
     if (!half) return fail(PSS_E_INVAL, "null array");
     if (pss_status s = materialize(c)) return s;
-    if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    int fd = 0;
+    if (pss_status s = dyn_field(c, field, &fd)) return s;
     if (pss_status s_bw = begin_work(c)) return s_bw;
     std::vector<float2> S(static_cast<size_t>(c->packed()));
-    HIP_TRY(hipMemcpyAsync(S.data(), c->d_state[field], sizeof(float2) * S.size(), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(S.data(), c->d_state[fd], sizeof(float2) * S.size(), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     const size_t nout = static_cast<size_t>(c->n[1]) * (c->ndim == 3 ? c->n[2] : 1) * (c->n[0] / 2 + 1) * 2;
     std::vector<float> h(nout);
@@ -1608,10 +1725,11 @@ pss_status pss_mass(pss_ctx* c, int32_t field, double* mass) {
     if (pss_status s = check_ctx(c)) return s;
     if (!mass) return fail(PSS_E_INVAL, "null output");
     if (pss_status s = materialize(c)) return s;
-    if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    int fd = 0;
+    if (pss_status s = dyn_field(c, field, &fd)) return s;
     if (pss_status s_bw = begin_work(c)) return s_bw;
     float2 v;
-    HIP_TRY(hipMemcpyAsync(&v, c->d_state[field], sizeof(v), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(&v, c->d_state[fd], sizeof(v), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     *mass = static_cast<double>(v.x);  // Re of phi_hat(0) + i phi_hat(Nx/2, 0)
     return PSS_OK;
@@ -1621,7 +1739,8 @@ pss_status pss_structure_factor(pss_ctx* c, int32_t field, double* S, int64_t* c
     if (pss_status s = check_ctx(c)) return s;
     if (!S || !counts) return fail(PSS_E_INVAL, "null output");
     if (pss_status s = materialize(c)) return s;
-    if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    int fd = 0;
+    if (pss_status s = dyn_field(c, field, &fd)) return s;
     if (pss_status s_bw = begin_work(c)) return s_bw;
     const int nmin = c->ndim == 3 ? std::min(std::min(c->n[0], c->n[1]), c->n[2]) : std::min(c->n[0], c->n[1]);
     const int ns = nmin / 2;  // shells j = 1 .. ns-1
@@ -1633,7 +1752,7 @@ pss_status pss_structure_factor(pss_ctx* c, int32_t field, double* S, int64_t* c
     HIP_TRY(hipMemsetAsync(c->d_shell_sum, 0, sizeof(double) * ns, c->stream));
     HIP_TRY(hipMemsetAsync(c->d_shell_cnt, 0, sizeof(unsigned long long) * ns, c->stream));
     const double dV = c->dx[0] * c->dx[1] * (c->ndim == 3 ? c->dx[2] : 1.0);
-    HIP_TRY(pss::launch_shells(c->stream, c->d_state[field], c->n[0], c->n[1], c->ndim == 3 ? c->n[2] : 1, c->geo.tc,
+    HIP_TRY(pss::launch_shells(c->stream, c->d_state[fd], c->n[0], c->n[1], c->ndim == 3 ? c->n[2] : 1, c->geo.tc,
                                c->ndim, dV / static_cast<double>(c->sites()), ns, c->d_shell_sum, c->d_shell_cnt));
     std::vector<double> sums(ns);
     std::vector<unsigned long long> cnt(ns);
@@ -1652,7 +1771,8 @@ pss_status pss_structure_factor_noalloc(pss_ctx* c, int32_t field, double* S, in
     if (pss_status s = check_ctx(c)) return s;
     if (!S || !counts) return fail(PSS_E_INVAL, "null output");
     if (!c->planned) return fail(PSS_E_STATE, "the plan is not built (building it allocates device memory)");
-    if (field < 0 || field >= static_cast<int>(c->fields.size())) return fail(PSS_E_INVAL, "bad field");
+    int fd = 0;
+    if (pss_status s = dyn_field(c, field, &fd)) return s;
     if (pss_status s_bw = begin_work(c)) return s_bw;
     const int nmin = c->ndim == 3 ? std::min(std::min(c->n[0], c->n[1]), c->n[2]) : std::min(c->n[0], c->n[1]);
     const int ns = nmin / 2;  // shells j = 1 .. ns-1
@@ -1667,7 +1787,7 @@ pss_status pss_structure_factor_noalloc(pss_ctx* c, int32_t field, double* S, in
     HIP_TRY(pss::launch_zero_words(c->stream, reinterpret_cast<unsigned long long*>(sums), ns));
     HIP_TRY(pss::launch_zero_words(c->stream, cnt, ns));
     const double dV = c->dx[0] * c->dx[1] * (c->ndim == 3 ? c->dx[2] : 1.0);
-    HIP_TRY(pss::launch_shells(c->stream, c->d_state[field], c->n[0], c->n[1], c->ndim == 3 ? c->n[2] : 1, c->geo.tc,
+    HIP_TRY(pss::launch_shells(c->stream, c->d_state[fd], c->n[0], c->n[1], c->ndim == 3 ? c->n[2] : 1, c->geo.tc,
                                c->ndim, dV / static_cast<double>(c->sites()), ns, sums, cnt));
     // shells 1 .. ns-1 straight into the caller's arrays, then averaged in place
     static_assert(sizeof(int64_t) == sizeof(unsigned long long), "count width");
@@ -1776,7 +1896,7 @@ pss_status pss_autotune(pss_ctx* c, int32_t reps, double* us_per_step) {
     std::lock_guard<std::mutex> lock(cache_mu);
     std::string key = std::to_string(c->ndim);
     for (int i = 0; i < c->ndim; ++i) key += "x" + std::to_string(c->n[i]);
-    key += "/f" + std::to_string(c->fields.size()) + "/t";
+    key += "/f" + std::to_string(c->fields.size()) + "/i" + std::to_string(c->interms.size()) + "/t";
     for (const Term& t : c->terms) {
         key += t.implicit ? "i" : "e";
         for (auto& fp : t.factors) key += std::to_string(fp.first) + "^" + std::to_string(fp.second);
@@ -1867,7 +1987,7 @@ pss_status pss_adjoint_model_b_forward(pss_ctx* c, int64_t nsteps, int32_t ckpt_
     // recognise Model B: one field; implicit -(a q^2 + k q^4); explicit -b q^2 F[phi^3]; noise D q^2
     double a = 0, b = 0, k = 0, D = 0;
     {
-        bool ok = c->fields.size() == 1 && c->terms.size() == 2;
+        bool ok = c->fields.size() == 1 && c->interms.empty() && c->terms.size() == 2;
         int nimp = 0, ncub = 0;
         for (const Term& t : c->terms) {
             if (!ok) break;

@@ -60,12 +60,71 @@ def test_implicit_term_must_be_linear_in_own_field():
 
 def test_duplicate_and_intermediate_fields():
     lat = _lat()
-    lat.field("phi")
+    f = lat.field("phi")
     with pytest.raises(PssError):
         lat.field("phi")
+    g = lat.field("psi", dynamic=False)
+    assert (f, g) == (0, 1)
+    with pytest.raises(PssError):
+        lat.field("psi")  # one namespace for both kinds
+    h = lat.field("chi")
+    assert h == 2
+    # an intermediate field has no noise
     with pytest.raises(PssError) as e:
-        lat.field("psi", dynamic=False)
+        lat.noise(g, [Mono(0.1)])
+    assert e.value.name == "PSS_E_INVAL"
+    # its explicit terms are one dynamic field to the first power
+    with pytest.raises(PssError) as e:
+        lat.term(g, [Mono(1.0)], [(f, 2)])
     assert e.value.name == "PSS_E_UNSUPPORTED"
+    with pytest.raises(PssError) as e:
+        lat.term(g, [Mono(1.0)], [(f, 1), (h, 1)])
+    assert e.value.name == "PSS_E_UNSUPPORTED"
+    lat.term(g, [Mono(1.0, iq=(1, 0, 0))], [(f, 1)])
+    lat.term(g, [Mono(-0.5, q2=1)], [(h, 1)])
+    # an intermediate may not be a source of another intermediate
+    k = lat.field("k", dynamic=False)
+    with pytest.raises(PssError) as e:
+        lat.term(k, [Mono(1.0)], [(g, 1)])
+    assert e.value.name == "PSS_E_UNSUPPORTED"
+    # its implicit terms are linear in itself
+    with pytest.raises(PssError):
+        lat.term(g, [Mono(1.0)], [(f, 1)], implicit=True)
+    lat.term(g, [Mono(-1.0, q2=1)], [(g, 1)], implicit=True)
+    # dynamic fields may use intermediates as factors and as linear sources
+    lat.term(f, [Mono(-1.0, q2=1)], [(f, 1)], implicit=True)
+    lat.term(h, [Mono(-1.0, q2=1)], [(h, 1)], implicit=True)
+    lat.term(f, [Mono(0.5)], [(g, 2)])
+    lat.term(h, [Mono(0.1)], [(g, 1)])
+    lat.validate()
+    for _ in range(2):
+        lat.field("x%d" % _, dynamic=False)
+    with pytest.raises(PssError) as e:
+        lat.field("one_too_many", dynamic=False)
+    assert e.value.name == "PSS_E_UNSUPPORTED"
+
+
+def test_singular_intermediate_rejected_on_host():
+    lat = _lat()
+    f = lat.field("phi")
+    g = lat.field("psi", dynamic=False)
+    lat.term(f, [Mono(-1.0, q2=1)], [(f, 1)], implicit=True)
+    lat.term(g, [Mono(1.0)], [(f, 1)])
+    # psi = psi + phi: 1 - L_psi = 0 at every mode
+    lat.term(g, [Mono(1.0)], [(g, 1)], implicit=True)
+    with pytest.raises(PssError) as e:
+        lat.validate()
+    assert e.value.name == "PSS_E_UNSTABLE"
+    # psi (1 - q^2 / q0^2) = ...: vanishes on the shell |q| = q0 = 2 pi * 8 / 64
+    lat2 = _lat()
+    f2 = lat2.field("phi")
+    g2 = lat2.field("psi", dynamic=False)
+    q0 = 2 * np.pi * 8 / 64
+    lat2.term(g2, [Mono(1.0 / q0 ** 2, q2=1)], [(g2, 1)], implicit=True)
+    lat2.term(g2, [Mono(1.0)], [(f2, 1)])
+    with pytest.raises(PssError) as e:
+        lat2.validate()
+    assert e.value.name == "PSS_E_UNSTABLE"
 
 
 def test_unstable_model_rejected_on_host():
