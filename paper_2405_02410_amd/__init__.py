@@ -19,7 +19,9 @@ from collections import namedtuple
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libpss.so")
+# PSS_LIB names another build of the same library (the host-sanitizer build
+# that the CPU interface tests run under); by default the in-tree libpss.so
+_LIB_PATH = os.environ.get("PSS_LIB") or os.path.join(_HERE, "libpss.so")
 
 PSS_OK = 0
 ERRORS = {

@@ -264,8 +264,8 @@ void* tape_alloc(pss_tape* tp, size_t bytes) {
 }
 
 void tape_free(pss_tape* tp) {
-    if (tp->ctx && tp->ctx->stream) hipStreamSynchronize(tp->ctx->stream);
-    for (void* p : tp->mem) hipFree(p);
+    if (tp->ctx && tp->ctx->stream) (void)hipStreamSynchronize(tp->ctx->stream);
+    for (void* p : tp->mem) (void)hipFree(p);
     tp->mem.clear();
 }
 
@@ -661,10 +661,10 @@ pss_status choose_geometry(pss_ctx* c) {
 }
 
 void free_device(pss_ctx* c) {
-    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
     auto rel = [](auto*& p) {
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
         p = nullptr;
     };
     for (auto*& p : c->d_state) rel(p);
@@ -685,7 +685,7 @@ void free_device(pss_ctx* c) {
     rel(c->d_shell_cnt);
     rel(c->d_member_u);
     rel(c->d_member_x);
-    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     c->stream = nullptr;
     c->own_stream = false;
     c->planned = false;
@@ -996,13 +996,13 @@ pss_status graph_for(pss_ctx* c, int64_t k, hipGraphExec_t* out) {
     pss_status st = enqueue_steps(c, k);
     hipError_t e = hipStreamEndCapture(c->stream, &g);
     if (st) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return st;
     }
     HIP_TRY(e);
     hipGraphExec_t ex = nullptr;
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     HIP_TRY(e);
     c->graphs[k] = ex;
     *out = ex;
@@ -1019,18 +1019,18 @@ bool same_class(const pss_ctx* a, const pss_ctx* b) {
 }
 
 void free_batch(pss_batch* b) {
-    for (auto& kv : b->graphs) hipGraphExecDestroy(kv.second);
+    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
     b->graphs.clear();
     for (auto& cl : b->cls) {
-        if (cl.d_u) hipFree(cl.d_u);
-        if (cl.d_x) hipFree(cl.d_x);
-        if (cl.d_plans) hipFree(cl.d_plans);
+        if (cl.d_u) (void)hipFree(cl.d_u);
+        if (cl.d_x) (void)hipFree(cl.d_x);
+        if (cl.d_plans) (void)hipFree(cl.d_plans);
         cl.d_u = cl.d_x = nullptr;
         cl.d_plans = nullptr;
     }
-    if (b->d_ctrs) hipFree(b->d_ctrs);
+    if (b->d_ctrs) (void)hipFree(b->d_ctrs);
     b->d_ctrs = nullptr;
-    if (b->ev) hipEventDestroy(b->ev);
+    if (b->ev) (void)hipEventDestroy(b->ev);
     b->ev = nullptr;
 }
 
@@ -1184,8 +1184,8 @@ pss_status batch_time_fused(pss_batch* b, int32_t which, int32_t reps, double* m
     HIP_TRY(hipEventSynchronize(e1));
     float t = 0;
     HIP_TRY(hipEventElapsedTime(&t, e0, e1));
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     *ms = static_cast<double>(t) / reps;
     if (bytes) *bytes = total;
     for (int i : members) {  // repeated launches leave the channels stale and change the states
@@ -1206,13 +1206,13 @@ pss_status batch_graph_for(pss_batch* b, int64_t k, hipGraphExec_t* out) {
     pss_status st = batch_enqueue(b, k);
     hipError_t e = hipStreamEndCapture(b->stream, &g);
     if (st) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return st;
     }
     HIP_TRY(e);
     hipGraphExec_t ex = nullptr;
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     HIP_TRY(e);
     b->graphs[k] = ex;
     *out = ex;
@@ -1492,11 +1492,11 @@ pss_status pss_stream_set(pss_ctx* c, void* stream) {
     if (c->tapes > 0) return fail(PSS_E_STATE, "an adjoint tape holds this lattice; destroy it first");
     if (c->planned && c->stream) HIP_TRY(hipStreamSynchronize(c->stream));
     if (c->own_stream && c->stream) {
-        hipStreamDestroy(c->stream);
+        (void)hipStreamDestroy(c->stream);
         c->own_stream = false;
         c->stream = nullptr;
     }
-    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
     c->stream = static_cast<hipStream_t>(stream);
     if (!c->stream && c->planned) {
@@ -1874,8 +1874,8 @@ pss_status pss_time_kernel(pss_ctx* c, int32_t which, int32_t reps, double* ms, 
     HIP_TRY(hipEventSynchronize(e1));
     float t = 0;
     HIP_TRY(hipEventElapsedTime(&t, e0, e1));
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     *ms = static_cast<double>(t) / reps;
     c->dirty = true;  // the channel arrays no longer match the state
     ++c->state_gen;   // repeated step launches changed the state
@@ -2300,7 +2300,7 @@ pss_status pss_batch_create(pss_batch** out, pss_ctx* const* lattices, int32_t n
 
 pss_status pss_batch_destroy(pss_batch* b) {
     if (!b) return PSS_OK;
-    if (b->stream) hipStreamSynchronize(b->stream);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
     for (pss_ctx* c : b->mem) {
         --c->batches;
         if (c->after_batch == b->ev) c->after_batch = nullptr;  // its work is done
@@ -2392,8 +2392,8 @@ pss_status pss_batch_time_kernel(pss_batch* b, int32_t cls, int32_t which, int32
     HIP_TRY(hipEventSynchronize(e1));
     float t = 0;
     HIP_TRY(hipEventElapsedTime(&t, e0, e1));
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     *ms = static_cast<double>(t) / reps;
     if (bytes) {
         double one = 0;
