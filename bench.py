@@ -194,9 +194,9 @@ def ensemble(args, pss, torch, steps):
     sites = sum(c * s * s for c, s in ENSEMBLE)
     batch = pss.Batch(lats)
     ncls = batch.classes()[0]
-    per_step, fused = batch.launches()
+    per_step, fused, resident = batch.launches()
     log(f"bench: ensemble of {len(lats)} lattices, {sites} sites, {ncls} classes, {per_step} launches per step "
-        f"({fused} classes fused)")
+        f"({fused} classes fused), {resident} LDS-resident classes (one launch per chunk of steps)")
     batch.step(steps)  # warm-up; builds the graphs of this chunk length
     batch.sync()
 
@@ -235,10 +235,20 @@ def ensemble(args, pss, torch, steps):
     plain = sites * plain_steps / pel
     log(f"bench: plain {1e6 * pel / plain_steps:.1f} us/step, {plain:.4e} site-steps/s")
 
-    # roofline of the launch with the largest share of the batched step: the
-    # fused launches when every class is fused, else each class's own
+    # roofline of the per-step launch with the largest share of the batched
+    # step: the fused launches when every other class is fused or resident,
+    # else each class's own; the resident launch (state on chip between
+    # steps, HBM only at its ends) is reported on its own
+    res = None
+    if resident:
+        ms_r, bytes_r = batch.time_kernel(-2, pss.KERNEL_UPDATE, ens_reps := max(50, args.kernel_reps // 10))
+        res_sites = sum(c * s * s for c, s in ENSEMBLE if s <= 128)
+        res = {"ms_per_step": ms_r, "steps_per_launch": ens_reps, "sites": res_sites,
+               "site_steps_per_s": res_sites / (ms_r * 1e-3), "hbm_bytes_per_step": bytes_r}
+        log(f"bench: resident launch: {ms_r * 1e3:.2f} us per step over {ens_reps} steps, "
+            f"{res_sites / (ms_r * 1e-3):.4e} site-steps/s")
     best = None
-    units = [(-1, w) for w in (pss.KERNEL_UPDATE, pss.KERNEL_X)] if fused == ncls else \
+    units = [(-1, w) for w in (pss.KERNEL_UPDATE, pss.KERNEL_X)] if fused + resident == ncls else \
         [(c, w) for c in range(ncls) for w in (pss.KERNEL_UPDATE, pss.KERNEL_X)]
     for cls, which in units:
         ms, nbytes = batch.time_kernel(cls, which, max(50, args.kernel_reps // 10))
@@ -255,7 +265,7 @@ def ensemble(args, pss, torch, steps):
                 "kernel": kname, "bytes_per_launch": nbytes, "us_per_launch": round(ms * 1e3, 3)}
     out = {"value": value, "unit": "site-steps/s", "steps": steps, "ms_per_step": 1e3 * el / steps,
            "members": len(lats), "sites": sites, "classes": ncls, "launches_per_step": per_step,
-           "fused_classes": fused,
+           "fused_classes": fused, "resident_classes": resident, "resident": res,
            "plain": {"value": plain, "steps": plain_steps, "ms_per_step": 1e3 * pel / plain_steps,
                      "form": "pss_step on each lattice in turn, each on its own stream"},
            "vs_plain": round(value / plain, 2), "roofline": roofline,

@@ -381,7 +381,19 @@ pss_status pss_tape_destroy(pss_tape *tape);
  * batch holding it is destroyed.  Members stay usable on their own (state I/O,
  * pss_step, pss_term_set_coef, pss_state_load); work on a member's stream is
  * ordered against the batch's steps.  The batch runs on the first lattice's
- * stream. */
+ * stream.
+ *
+ * Execution (the small-lattice overhead of Sec. "Benchmarks" is what it
+ * removes): members of equal sizes, field/factor/channel counts and launch
+ * geometry form a class.  A class of one-field lattices whose products use
+ * that field only, with Nx and Ny in {64, 128} and the default 4 points per
+ * thread, is LDS-resident: one launch per replayed chunk of steps, one block
+ * per member holding its whole lattice on chip (set PSS_BATCH_RESIDENT=0 in
+ * the environment before pss_batch_create to turn this off).  The other
+ * classes of one-field lattices with lines of 64..1024 share one update
+ * launch and one x launch per step over a work list of every class; any
+ * remaining class runs its own pair of launches per step.  Every form gives
+ * each member bit for bit the state that pss_step gives the lattice alone. */
 pss_status pss_batch_create(pss_batch **batch, pss_ctx *const *lattices, int32_t n, const uint64_t *seeds);
 
 /* Wait for the batch's work and free the batch (not its lattices). NULL is a no-op. */
@@ -404,15 +416,20 @@ pss_status pss_batch_info(pss_batch *batch, int32_t *n_classes, int32_t *class_o
  * *bytes (may be NULL) the launch's algorithmic HBM bytes (the first member's
  * per-lattice figure times the class size).  cls = -1 times the fused launch
  * of that phase (bytes summed over its classes; PSS_E_INVAL if the batch has
- * none).  Leaves the members' channel arrays stale, so the next step rebuilds
- * them; for timing only. */
+ * none).  cls = -2 times one launch of `reps` steps of every LDS-resident
+ * class: *ms per step, *bytes the launch's HBM bytes (state and channel array
+ * in and out once) per step; which is then ignored (0 or 1).  Leaves the
+ * members' channel arrays stale and moves their states on, so the next step
+ * rebuilds the channels; for timing only. */
 pss_status pss_batch_time_kernel(pss_batch *batch, int32_t cls, int32_t which, int32_t reps, double *ms,
                                  double *bytes);
 
-/* Kernel launches per time step of the batch (2 when every class is fused)
- * and the number of classes in the fused launches; either pointer may be
- * NULL. */
-pss_status pss_batch_launches(pss_batch *batch, int32_t *per_step, int32_t *fused_classes);
+/* Kernel launches per time step of the batch outside the LDS-resident
+ * classes (2 when every other class is fused), the number of classes in the
+ * fused launches, and the number of LDS-resident classes (one launch per
+ * replayed chunk of up to 50 steps each); any pointer may be NULL. */
+pss_status pss_batch_launches(pss_batch *batch, int32_t *per_step, int32_t *fused_classes,
+                              int32_t *resident_classes);
 
 const char *pss_last_error(void);
 

@@ -106,7 +106,8 @@ _SIGS = {
     "pss_batch_step": [ctypes.c_void_p, ctypes.c_int64],
     "pss_batch_sync": [ctypes.c_void_p],
     "pss_batch_info": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
-    "pss_batch_launches": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+    "pss_batch_launches": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                           ctypes.POINTER(ctypes.c_int32)],
     "pss_batch_time_kernel": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
 }
@@ -450,14 +451,17 @@ class Batch:
         return nc.value, list(of)
 
     def launches(self):
-        """(kernel launches per step, classes in the fused launches)."""
-        per, fused = ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().pss_batch_launches(self._h, ctypes.byref(per), ctypes.byref(fused)))
-        return per.value, fused.value
+        """(kernel launches per step outside the LDS-resident classes, classes
+        in the fused launches, LDS-resident classes)."""
+        per, fused, res = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().pss_batch_launches(self._h, ctypes.byref(per), ctypes.byref(fused), ctypes.byref(res)))
+        return per.value, fused.value, res.value
 
     def time_kernel(self, cls, which=KERNEL_UPDATE, reps=100):
         """(ms per launch, algorithmic bytes per launch) of one class's kernel,
-        or of the fused launch of that phase for cls = -1."""
+        of the fused launch of that phase for cls = -1, or (ms, HBM bytes) per
+        step of one launch of `reps` steps of the LDS-resident classes for
+        cls = -2."""
         ms, b = ctypes.c_double(), ctypes.c_double()
         _check(lib().pss_batch_time_kernel(self._h, int(cls), int(which), int(reps), ctypes.byref(ms),
                                            ctypes.byref(b)))

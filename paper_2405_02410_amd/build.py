@@ -23,6 +23,10 @@ HIPCC_FLAGS = [
     "-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fused only within one source expression, so a device
+    # function rounds the same wherever it is inlined: the batched, fused and
+    # LDS-resident kernels then give bit for bit the per-lattice results
+    "-ffp-contract=on",
 ]
 
 

@@ -147,6 +147,35 @@ struct BatchLaunch {
 };
 // line lengths the fused kernels are built for
 inline bool batch_fused_len(int L) { return L >= 64 && L <= 1024 && (L & (L - 1)) == 0; }
+
+// LDS-resident launch: lattices whose whole packed half spectrum and channel
+// array fit in one CU's LDS take many steps in one launch, one block per
+// member, with no HBM traffic between steps (2D, Nx and Ny in {64, 128}; one
+// field whose real-space products use that field only; 4 points per thread
+// in both phases, as the per-lattice kernels use them, so the arithmetic and
+// its rounding are the same).
+struct ResidentLaunch {
+    int lx, ly;   // lattice sizes
+    int nmem;     // members (blocks)
+    int nsteps;   // steps of the launch
+    int advance;  // 1: the launch moves the members' step counters on by nsteps
+    int pad;
+    const Member* members;  // update-kernel table: state S[0], channel N[0], counter, flag
+    const DevPlan* plans;
+    const float2* tw_x;  // twiddles of Nx and of Ny
+    const float2* tw_y;
+    Geo geo;  // tc, tc_log2: the global layout of S and N
+};
+__host__ __device__ constexpr int resident_threads(int lx, int ly) {
+    return (lx / 2) * (ly / 4) < 1024 ? (lx / 2) * (ly / 4) : 1024;
+}
+// LDS: padded channel/factor array, line scratch, packed-line exchange, twiddles
+inline size_t resident_lds_bytes(int lx, int ly) {
+    return sizeof(float2) * (static_cast<size_t>(lx / 2) * (ly + 1) + 4 * resident_threads(lx, ly) + 2 * ly + lx);
+}
+inline bool resident_shape(int lx, int ly) { return (lx == 64 || lx == 128) && (ly == 64 || ly == 128); }
+hipError_t resident_setup();
+hipError_t launch_batch_resident(hipStream_t s, const ResidentLaunch& rl);
 hipError_t launch_batch_update(hipStream_t s, const BatchLaunch& bl, size_t lds);
 hipError_t launch_batch_xrow(hipStream_t s, const BatchLaunch& bl, size_t lds);
 

@@ -1708,6 +1708,331 @@ __global__ void __launch_bounds__(256) batch_xrow_kernel(BatchLaunch bl) {
 #undef PSS_BX
 }
 
+// ------------------------------------------------- LDS-resident multi-step
+// One block holds a whole lattice: its state in registers (each thread keeps
+// the slots of its column lines), the channel and factor arrays in one LDS
+// array X[c][position] (column stride Ny + 1), which each phase overwrites in
+// place: the column phase reads a column's channel values and writes its
+// factor values, the row phase reads a row pair's factor values and writes
+// its channel values.  The two phases are the update kernel's and the x
+// kernel's line bodies with LDS in place of the packed-column arrays: the
+// same transforms (4 points per thread; every line fits in a wave, so only
+// the packed line's exchange and the phase changes take block barriers), the
+// same operations in the same order, and the same position order of the
+// exchanged arrays (the x phase works on positions as rows).  The launch
+// loads the state and the channel array, runs rl.nsteps steps, stores both
+// back and moves the member's step counter on.
+template <int LX, int LY>
+__global__ void __launch_bounds__(resident_threads(LX, LY)) resident_kernel(ResidentLaunch rl) {
+    constexpr int P = 4;
+    using FY = LineFFT<LY, P>;
+    using FX = LineFFT<LX, P>;
+    static_assert(!FY::kCross && !FX::kCross, "lines held by one wave");
+    constexpr int TY = FY::T, TX = FX::T;
+    constexpr int NC = LX / 2;                      // packed columns
+    constexpr int NTHR = resident_threads(LX, LY);
+    constexpr int CPR = NTHR / TY, RPR = NTHR / TX;  // column lines, row pairs per round
+    constexpr int CR = NC / CPR;                     // rounds of each phase
+    static_assert(CR * CPR == NC && CR * RPR == LY / 2, "whole rounds");
+    constexpr int XS = LY + 1;                       // column stride of X
+    constexpr int LPW = 64 / TY;                     // column lines per wave
+    extern __shared__ float2 smem[];
+    float2* const X = smem;
+    float2* const scr = X + NC * XS;                 // 4 NTHR: one line per thread group
+    float2* const xbuf = scr + 4 * NTHR;             // packed-line exchange (LY)
+    float2* const twy = xbuf + LY;
+    float2* const twx = twy + LY;
+    const int mi = xcd_block(blockIdx.x, gridDim.x);
+    const Member& mem = rl.members[mi];
+    const DevPlan& p = rl.plans[mi];
+    const int tid = threadIdx.x;
+    const int tc = rl.geo.tc, lt = rl.geo.tc_log2;
+    const int nx = p.n[0];
+    float2* __restrict__ Sg = mem.bufs.S[0];
+    float2* __restrict__ Ng = mem.bufs.N[0];
+
+    for (int i = tid; i < LY; i += NTHR) twy[i] = rl.tw_y[i];
+    for (int i = tid; i < LX; i += NTHR) twx[i] = rl.tw_x[i];
+    // column phase: line li of the round, thread t of the line
+    const int li = tid / TY, tcol = tid & (TY - 1);
+    const int dry = FY::drev(tcol);
+    LdsLine ldc;
+    ldc.wl = scr + li * LY;
+    ldc.blk0 = ldc.blk1 = nullptr;
+    ldc.par = 0;
+    // row phase: pair pi of the round, thread t of the pair
+    const int pi = tid / TX, trow = tid & (TX - 1);
+    const int drx = FX::drev(trow);
+    LdsLine ldr;
+    ldr.wl = scr + pi * LX;
+    ldr.blk0 = ldr.blk1 = nullptr;
+    ldr.par = 0;
+
+    // the state of this thread's column slots, and the channel array
+    float2 st[CR][P];
+#pragma unroll
+    for (int r = 0; r < CR; ++r) {
+        const int c = r * CPR + li;
+        const size_t base = (static_cast<size_t>(c >> lt) * LY << lt) + (c & (tc - 1));
+#pragma unroll
+        for (int m = 0; m < P; ++m) st[r][m] = gload(Sg + base + static_cast<size_t>(tcol + m * TY) * tc);
+    }
+    for (int i = tid; i < NC * LY; i += NTHR) {
+        const int ct = i / (LY * tc), rem = i - ct * (LY * tc);
+        const int y = rem >> lt, c = (ct << lt) + (rem & (tc - 1));
+        X[c * XS + y] = gload(Ng + i);
+    }
+    const uint32_t step0 = static_cast<uint32_t>(gload_u64(mem.step_ctr));
+    __syncthreads();
+
+    uint32_t bad = 0;
+    for (int sn = 0; sn < rl.nsteps; ++sn) {
+        const uint32_t step = step0 + static_cast<uint32_t>(sn);
+        // ---- column phase: forward y transform of the channel, update,
+        // de-aliased inverse y transform of the factor
+#pragma unroll
+        for (int r = 0; r < CR; ++r) {
+            const int c = r * CPR + li;
+            const bool blk_packed = r == 0;  // the round holding column 0 (block-uniform)
+            const bool packed = c == 0;
+            const bool pair_lane = packed && tcol == 0;
+            const int kx_l = c, ky_l = 0;
+            float2* const col = X + c * XS;
+            auto exchange = [&](float2 (&v)[P], bool forward) {
+                if (!blk_packed) return;
+                if (packed) {
+#pragma unroll
+                    for (int m = 0; m < P; ++m) xbuf[tcol + m * TY] = v[m];
+                }
+                __syncthreads();
+                if (packed) {
+#pragma unroll
+                    for (int m = 0; m < P; ++m) {
+                        const int u = tcol + m * TY;
+                        const float2 b = xbuf[(LY - u) & (LY - 1)];
+                        v[m] = forward ? to_slot<LY>(u, v[m], b) : from_slot<LY>(u, v[m], b);
+                    }
+                }
+                __syncthreads();
+            };
+            const LineModes lmode = line_modes<LY, 2>(p, packed, kx_l, ky_l);
+            float2(&s)[P] = st[r];
+            float q2[P];
+            uint32_t lin[P], lneg[P];
+#pragma unroll
+            for (int m = 0; m < P; ++m) slot_at<LY>(lmode, tcol + m * TY, q2[m], lin[m], lneg[m]);
+            float2 acc[1][P];
+#pragma unroll
+            for (int m = 0; m < P; ++m) acc[0][m] = make_float2(0.f, 0.f);
+            if (p.nch > 0) {
+                const DevChannel& C = p.ch[0];
+                float2 v[P];
+#pragma unroll
+                for (int m = 0; m < P; ++m) v[m] = col[tcol + m * TY];
+                FY::template dit<-1>(v, ldc, tcol, twy);
+                exchange(v, true);
+                float M[P];
+                horner_p(C.op, q2, M);
+#pragma unroll
+                for (int m = 0; m < P; ++m)
+                    if (!(pair_lane && (m == 0 || m == P / 2))) add_to(acc, C.target, m, cscale(v[m], M[m]));
+                if (pair_lane) pair_accumulate<2, false>(acc, C.target, v, p, C.op, ky_l, LY);
+            }
+            for (int d = 0; d < p.nd; ++d) {
+                const DevDirect& Dd = p.direct[d];
+                float2 src[P];
+#pragma unroll
+                for (int m = 0; m < P; ++m) src[m] = s[m];
+                float M[P];
+                horner_p(Dd.op, q2, M);
+#pragma unroll
+                for (int m = 0; m < P; ++m)
+                    if (!(pair_lane && (m == 0 || m == P / 2))) add_to(acc, Dd.target, m, cscale(src[m], M[m]));
+                if (pair_lane) pair_accumulate<2, false>(acc, Dd.target, src, p, Dd.op, ky_l, LY);
+            }
+            {
+                const bool noisy = p.noisy[0] != 0;
+                const float2 old0 = s[0], oldh = s[P / 2];
+                float Ar[P], Dn[P];
+                horner_p(p.implicit_op[0], q2, Ar);
+                if (noisy) horner_p(p.noise_op[0], q2, Dn);
+#pragma unroll
+                for (int m = 0; m < P; ++m) {
+                    float2 rr = cadd(s[m], cscale(acc[0][m], p.dt));
+                    if (noisy) rr = cadd(rr, noise_value(p, 0, step, lin[m], lneg[m], Dn[m]));
+                    s[m] = cscale(rr, __builtin_amdgcn_rcpf(fmaf(-p.dt, Ar[m], 1.f)));
+                }
+                if (pair_lane) {
+                    s[0] = pair_update_d<2, false>(p, 0, step, ky_l, 0, LY, old0, acc[0][0], noisy);
+                    s[P / 2] = pair_update_d<2, false>(p, 0, step, ky_l, LY >> 1, LY, oldh, acc[0][P / 2], noisy);
+                }
+                bool fin = true;
+#pragma unroll
+                for (int m = 0; m < P; ++m) fin = fin && __builtin_isfinite(s[m].x) && __builtin_isfinite(s[m].y);
+                if (!fin) bad |= 1u;
+            }
+            // de-aliased inverse transform of the factor (lines of a wave whose
+            // first column is past the kept ones are never read)
+            if (p.ng > 0 && (c / LPW) * LPW < p.mask[0].ncol) {
+                const DevMask& mk = p.mask[0];
+                const int lim = line_lim<2>(mk, packed ? 0 : kx_l, ky_l, LY);
+                const int limN = line_lim<2>(mk, -(nx >> 1), ky_l, LY);
+                float2 v[P];
+#pragma unroll
+                for (int m = 0; m < P; ++m) {
+                    const int u = tcol + m * TY;
+                    const bool upper = packed && u > (LY >> 1);
+                    const int w = packed ? (upper ? LY - u : u) : (u < (LY >> 1) ? u : u - LY);
+                    v[m] = w * w <= (upper ? limN : lim) ? s[m] : make_float2(0.f, 0.f);
+                }
+                if (pair_lane) {
+                    const int wh = (LY >> 1) * (LY >> 1);
+                    const float2 a0 = s[0], ah = s[P / 2];
+                    v[0] = make_float2(0 <= lim ? a0.x : 0.f, 0 <= limN ? a0.y : 0.f);
+                    v[P / 2] = make_float2(wh <= lim ? ah.x : 0.f, wh <= limN ? ah.y : 0.f);
+                }
+                exchange(v, false);
+                FY::template dif<1>(v, ldc, tcol, twy);
+#pragma unroll
+                for (int m = 0; m < P; ++m) col[tcol + m * TY] = v[m];
+            } else if (blk_packed) {
+                // the packed line's exchange barriers are block-wide
+                __syncthreads();
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+        // ---- row phase: inverse x transform of each row pair's factor
+        // values, the products, forward x transform into the channel values
+#pragma unroll
+        for (int r = 0; r < CR; ++r) {
+            const int p0 = 2 * (r * RPR + pi);  // first position of the pair
+            if (p.nch == 0) break;
+            const int ncol = p.mask[0].ncol;
+            float2 v[P];
+            {
+                float2 a[P], b[P];
+#pragma unroll
+                for (int m = 0; m < P; ++m) {
+                    const int k = drx + m * TX;
+                    const int kk = (k == NC) ? 0 : (k < NC ? k : LX - k);
+                    const int kc = kk < ncol ? kk : 0;
+                    a[m] = X[kc * XS + p0];
+                    b[m] = X[kc * XS + p0 + 1];
+                }
+#pragma unroll
+                for (int m = 0; m < P; ++m) {
+                    const int k = drx + m * TX;
+                    const int kk = (k == NC) ? 0 : (k < NC ? k : LX - k);
+                    const float2 zero = make_float2(0.f, 0.f);
+                    const float2 am = kk < ncol ? a[m] : zero, bm = kk < ncol ? b[m] : zero;
+                    float2 z;
+                    if (k == 0) {
+                        z = make_float2(am.x, bm.x);
+                    } else if (k == NC) {
+                        z = make_float2(am.y, bm.y);
+                    } else {
+                        z = k < NC ? make_float2(am.x - bm.y, am.y + bm.x) : make_float2(am.x + bm.y, bm.x - am.y);
+                    }
+                    v[m] = z;
+                }
+            }
+            FX::template dit<1>(v, ldr, trow, twx);
+            float2 z[P];
+#pragma unroll
+            for (int m = 0; m < P; ++m) z[m] = cscale(v[m], p.inv_n);
+            const DevChannel& C = p.ch[0];
+            float2 w[P];
+#pragma unroll
+            for (int m = 0; m < P; ++m) w[m] = make_float2(0.f, 0.f);
+            for (int k = 0; k < C.nprod; ++k) {
+                const DevProd& pd = C.prod[k];
+                uint32_t pw;
+                __builtin_memcpy(&pw, pd.pow, sizeof(pw));
+                const int pg = static_cast<int>(pw & 0xffu);
+#pragma unroll
+                for (int m = 0; m < P; ++m) {
+                    float a = pd.coef, b = pd.coef;
+                    for (int e = 0; e < pg; ++e) {
+                        a *= z[m].x;
+                        b *= z[m].y;
+                    }
+                    w[m].x += a;
+                    w[m].y += b;
+                }
+            }
+            FX::template dif<-1>(w, ldr, trow, twx);
+            // unpack the pair's two rows into the packed columns
+            float2* const W = ldr.wl;
+            wave_lds_sync();
+#pragma unroll
+            for (int m = 0; m < P; ++m) W[drx + m * TX] = w[m];
+            wave_lds_sync();
+#pragma unroll
+            for (int j = 0; j < NC / TX; ++j) {
+                const int c = trow + j * TX;
+#pragma unroll
+                for (int rr = 0; rr < 2; ++rr) {
+                    float2 o;
+                    if (c == 0) {
+                        const float2 a = W[0], b = W[NC];
+                        o = rr ? make_float2(a.y, b.y) : make_float2(a.x, b.x);
+                    } else {
+                        const float2 a = W[c], b = W[LX - c];
+                        o = rr ? make_float2(0.5f * (a.y + b.y), 0.5f * (b.x - a.x))
+                               : make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
+                    }
+                    X[c * XS + p0 + rr] = o;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // state and channel array back to HBM; the counter moves on
+#pragma unroll
+    for (int r = 0; r < CR; ++r) {
+        const int c = r * CPR + li;
+        const size_t base = (static_cast<size_t>(c >> lt) * LY << lt) + (c & (tc - 1));
+#pragma unroll
+        for (int m = 0; m < P; ++m) gstore(Sg + base + static_cast<size_t>(tcol + m * TY) * tc, st[r][m]);
+    }
+    for (int i = tid; i < NC * LY; i += NTHR) {
+        const int ct = i / (LY * tc), rem = i - ct * (LY * tc);
+        const int y = rem >> lt, c = (ct << lt) + (rem & (tc - 1));
+        gstore(Ng + i, X[c * XS + y]);
+    }
+    if (bad) atomicOr(mem.flag, bad);
+    if (rl.advance && tid == 0) *mem.step_ctr += static_cast<uint64_t>(rl.nsteps);
+}
+
+// allow the resident kernels their LDS (above the default dynamic limit)
+hipError_t resident_setup() {
+#define PSS_RES_ATTR(AX, AY)                                                                                     \
+    if (hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&resident_kernel<AX, AY>),              \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,                            \
+                                           static_cast<int>(resident_lds_bytes(AX, AY))))                        \
+        return e;
+    PSS_RES_ATTR(64, 64)
+    PSS_RES_ATTR(64, 128)
+    PSS_RES_ATTR(128, 64)
+    PSS_RES_ATTR(128, 128)
+#undef PSS_RES_ATTR
+    return hipSuccess;
+}
+
+hipError_t launch_batch_resident(hipStream_t s, const ResidentLaunch& rl) {
+    if (rl.nmem < 1 || rl.nsteps < 1) return hipSuccess;
+    const size_t lds = resident_lds_bytes(rl.lx, rl.ly);
+#define PSS_RES(AX, AY)                                                                                      if (rl.lx == AX && rl.ly == AY) {                                                                            hipLaunchKernelGGL((resident_kernel<AX, AY>), dim3(rl.nmem), dim3(resident_threads(AX, AY)), lds, s, rl);         return hipGetLastError();                                                                            }
+    PSS_RES(64, 64)
+    PSS_RES(64, 128)
+    PSS_RES(128, 64)
+    PSS_RES(128, 128)
+#undef PSS_RES
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_batch_update(hipStream_t s, const BatchLaunch& bl, size_t lds) {
     if (bl.ncls < 1 || bl.total < 1) return hipSuccess;
     hipLaunchKernelGGL(batch_update_kernel, dim3(bl.total), dim3(256), lds, s, bl);

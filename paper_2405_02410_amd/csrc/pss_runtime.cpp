@@ -14,6 +14,7 @@
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -209,6 +210,10 @@ struct pss_batch {
     pss::BatchLaunch fu{}, fx{};
     size_t fu_lds = 0, fx_lds = 0;
     std::vector<char> in_fu, in_fx;    // per class
+    // LDS-resident classes: one launch per replayed chunk of steps
+    std::vector<char> in_res;          // per class
+    std::vector<pss::ResidentLaunch> res;
+    bool resident = true;              // PSS_BATCH_RESIDENT=0 at creation turns the resident launches off
     uint64_t** d_ctrs = nullptr;       // step counter of every member
     hipStream_t stream = nullptr;      // the first member's stream
     hipEvent_t ev = nullptr;
@@ -1058,11 +1063,34 @@ void batch_plan_fused(pss_batch* b) {
     b->fu_lds = b->fx_lds = 0;
     b->in_fu.assign(b->cls.size(), 0);
     b->in_fx.assign(b->cls.size(), 0);
+    b->in_res.assign(b->cls.size(), 0);
+    b->res.clear();
+    int dev = 0, max_lds = 0;
+    const bool lds_ok = hipGetDevice(&dev) == hipSuccess &&
+                        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+                        pss::resident_setup() == hipSuccess;
     for (size_t k = 0; k < b->cls.size(); ++k) {
         auto& cl = b->cls[k];
         pss_ctx* r = cl.rep;
         const int nmem = static_cast<int>(cl.idx.size());
         const bool plain = r->fields.size() == 1 && !r->plan.general;
+        // whole lattices in LDS: one field whose products use only that field
+        if (plain && b->resident && lds_ok && pss::resident_shape(r->n[0], r->n[1]) && r->geo.pu == 4 &&
+            r->geo.px == 4 && r->geo.to == 1 && r->plan.nch <= 1 && r->plan.ng == r->plan.nch &&
+            static_cast<int>(pss::resident_lds_bytes(r->n[0], r->n[1])) <= max_lds) {
+            pss::ResidentLaunch rl{};
+            rl.lx = r->n[0];
+            rl.ly = r->n[1];
+            rl.nmem = nmem;
+            rl.members = cl.d_u;
+            rl.plans = cl.d_plans;
+            rl.tw_x = r->d_tw_x;
+            rl.tw_y = r->d_tw_u;
+            rl.geo = r->geo;
+            b->res.push_back(rl);
+            b->in_res[k] = 1;
+            continue;
+        }
         if (plain && r->geo.pu == 4 && r->geo.to == 1 && r->geo.tc * (r->lu / 4) == 256 && pss::batch_fused_len(r->lu) &&
             b->fu.ncls < pss::kMaxBatchClasses) {
             pss::BatchClass& C = b->fu.cls[b->fu.ncls++];
@@ -1103,6 +1131,7 @@ void batch_plan_fused(pss_batch* b) {
 int batch_launches_per_step(const pss_batch* b) {
     int n = (b->fu.ncls > 0) + (b->fx.ncls > 0);
     for (size_t k = 0; k < b->cls.size(); ++k) {
+        if (b->in_res[k]) continue;
         if (!b->in_fu[k]) ++n;
         if (!b->in_fx[k] && b->cls[k].rep->plan.nch > 0) ++n;
     }
@@ -1111,9 +1140,16 @@ int batch_launches_per_step(const pss_batch* b) {
 
 pss_status batch_enqueue(pss_batch* b, int64_t k) {
     // classes with an x kernel move their members' counters on in the last
-    // step's x launch; the others need the counter kernel
+    // step's x launch, resident classes in their own launch; otherwise the
+    // counter kernel moves every member's counter
     bool all_x = true;
-    for (auto& cl : b->cls) all_x = all_x && cl.rep->plan.nch > 0;
+    for (size_t c = 0; c < b->cls.size(); ++c) all_x = all_x && (b->in_res[c] || b->cls[c].rep->plan.nch > 0);
+    for (const pss::ResidentLaunch& rl0 : b->res) {
+        pss::ResidentLaunch rl = rl0;
+        rl.nsteps = static_cast<int>(k);
+        rl.advance = all_x ? 1 : 0;
+        HIP_TRY(pss::launch_batch_resident(b->stream, rl));
+    }
     for (int64_t i = 0; i < k; ++i) {
         const int64_t adv = (all_x && i == k - 1) ? k : 0;
         if (b->fu.ncls > 0) {
@@ -1122,7 +1158,7 @@ pss_status batch_enqueue(pss_batch* b, int64_t k) {
             HIP_TRY(pss::launch_batch_update(b->stream, bl, b->fu_lds));
         }
         for (size_t c = 0; c < b->cls.size(); ++c) {
-            if (b->in_fu[c]) continue;
+            if (b->in_fu[c] || b->in_res[c]) continue;
             auto& cl = b->cls[c];
             pss_ctx* r = cl.rep;
             pss::LaunchArgs a = args(r, static_cast<int>(i));
@@ -1140,7 +1176,7 @@ pss_status batch_enqueue(pss_batch* b, int64_t k) {
         for (size_t c = 0; c < b->cls.size(); ++c) {
             auto& cl = b->cls[c];
             pss_ctx* r = cl.rep;
-            if (b->in_fx[c] || r->plan.nch == 0) continue;
+            if (b->in_fx[c] || b->in_res[c] || r->plan.nch == 0) continue;
             pss::LaunchArgs ax = xargs(r);
             ax.stream = b->stream;
             ax.members = cl.d_x;
@@ -1189,6 +1225,45 @@ pss_status batch_time_fused(pss_batch* b, int32_t which, int32_t reps, double* m
     *ms = static_cast<double>(t) / reps;
     if (bytes) *bytes = total;
     for (int i : members) {  // repeated launches leave the channels stale and change the states
+        b->mem[i]->dirty = true;
+        ++b->mem[i]->state_gen;
+    }
+    return batch_order_after(b, members);
+}
+
+// time one launch of `reps` steps of every resident class (HIP events on the
+// batch stream): milliseconds and HBM bytes per step
+pss_status batch_time_resident(pss_batch* b, int32_t reps, double* ms, double* bytes) {
+    if (b->res.empty()) return fail(PSS_E_INVAL, "the batch has no LDS-resident class");
+    std::vector<int> members;
+    double total = 0;
+    for (size_t k = 0; k < b->cls.size(); ++k) {
+        if (!b->in_res[k]) continue;
+        members.insert(members.end(), b->cls[k].idx.begin(), b->cls[k].idx.end());
+        // state and channel array in and out once per launch
+        total += 16.0 * static_cast<double>(b->cls[k].rep->sites()) * static_cast<double>(b->cls[k].idx.size());
+    }
+    if (pss_status s = batch_order_before(b, members)) return s;
+    if (pss_status s = batch_refresh_plans(b)) return s;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, b->stream));
+    for (const pss::ResidentLaunch& rl0 : b->res) {
+        pss::ResidentLaunch rl = rl0;
+        rl.nsteps = reps;
+        rl.advance = 0;
+        HIP_TRY(pss::launch_batch_resident(b->stream, rl));
+    }
+    HIP_TRY(hipEventRecord(e1, b->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float t = 0;
+    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = static_cast<double>(t) / reps;
+    if (bytes) *bytes = total / reps;
+    for (int i : members) {  // the states moved on without their counters
         b->mem[i]->dirty = true;
         ++b->mem[i]->state_gen;
     }
@@ -2292,6 +2367,8 @@ pss_status pss_batch_create(pss_batch** out, pss_ctx* const* lattices, int32_t n
     if (e != hipSuccess)
         return bail(fail(e == hipErrorOutOfMemory ? PSS_E_NOMEM : PSS_E_HIP, "batch set-up: %s", hipGetErrorString(e)));
     b->stream = b->mem[0]->stream;
+    const char* env = std::getenv("PSS_BATCH_RESIDENT");
+    b->resident = !(env && std::strcmp(env, "0") == 0);
     batch_plan_fused(b);
     for (pss_ctx* c : b->mem) ++c->batches;
     *out = b;
@@ -2346,10 +2423,11 @@ pss_status pss_batch_sync(pss_batch* b) {
     return st;
 }
 
-pss_status pss_batch_launches(pss_batch* b, int32_t* per_step, int32_t* fused_classes) {
+pss_status pss_batch_launches(pss_batch* b, int32_t* per_step, int32_t* fused_classes, int32_t* resident_classes) {
     if (!b) return fail(PSS_E_INVAL, "null batch");
     if (per_step) *per_step = batch_launches_per_step(b);
     if (fused_classes) *fused_classes = b->fu.ncls;
+    if (resident_classes) *resident_classes = static_cast<int32_t>(b->res.size());
     return PSS_OK;
 }
 
@@ -2367,6 +2445,7 @@ pss_status pss_batch_time_kernel(pss_batch* b, int32_t cls, int32_t which, int32
     if (!b) return fail(PSS_E_INVAL, "null batch");
     if ((which != 0 && which != 1) || reps < 1 || !ms) return fail(PSS_E_INVAL, "bad kernel timing request");
     if (cls == -1) return batch_time_fused(b, which, reps, ms, bytes);
+    if (cls == -2) return batch_time_resident(b, reps, ms, bytes);
     if (cls < 0 || cls >= static_cast<int32_t>(b->cls.size())) return fail(PSS_E_INVAL, "no class %d", cls);
     const auto& cl = b->cls[cls];
     pss_ctx* r = cl.rep;

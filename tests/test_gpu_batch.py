@@ -65,10 +65,11 @@ def test_batch_is_bitwise_the_single_lattice_path():
     batch = pss.Batch(mem)
     nc, of = batch.classes()
     assert nc == 5 and of[:4] == [0, 0, 0, 0] and of[4] == of[5] != of[0]
-    # fused: updates of 64^2, 128^2 and 32x128; x passes of 64^2, 128^2 and
-    # 256x16.  On their own: the update of 256x16 (lines of 16), the x pass of
-    # 32x128 (rows of 32), both of the two-field class
-    assert batch.launches() == (6, 3)
+    # LDS-resident: the 64^2 and 128^2 Model B classes.  Fused: the update of
+    # 32x128 and the x pass of 256x16.  On their own: the update of 256x16
+    # (lines of 16), the x pass of 32x128 (rows of 32), both of the two-field
+    # class
+    assert batch.launches() == (6, 1, 2)
     batch.step(7)
     batch.step(60)  # crosses a graph chunk
     batch.sync()
@@ -146,8 +147,8 @@ def test_member_outlives_its_batch():
 
 
 def test_batch_kernel_timing_and_bytes():
-    mem = [_model_b((128, 128), s) for s in range(4)]
-    single = _model_b((128, 128), 9)
+    mem = [_model_b((256, 256), s) for s in range(4)]
+    single = _model_b((256, 256), 9)
     batch = pss.Batch(mem)
     blobs = [lat.save() for lat in mem]  # timing launches overwrite the state
     ms, nbytes = batch.time_kernel(0, pss.KERNEL_UPDATE, 20)
@@ -157,8 +158,10 @@ def test_batch_kernel_timing_and_bytes():
     for which in (pss.KERNEL_UPDATE, pss.KERNEL_X):  # the fused launches
         ms, nbytes = batch.time_kernel(-1, which, 20)
         assert ms > 0 and nbytes == 4 * single.kernel_bytes(which)
+    with pytest.raises(PssError):
+        batch.time_kernel(-2, pss.KERNEL_UPDATE, 5)  # no LDS-resident class
     # restore the states; the next batch step must rebuild the stale channels
-    twins = [_model_b((128, 128), s) for s in range(4)]
+    twins = [_model_b((256, 256), s) for s in range(4)]
     for lat, blob in zip(mem, blobs):
         lat.load(blob)
     batch.step(3)
@@ -166,6 +169,23 @@ def test_batch_kernel_timing_and_bytes():
         tw.step(3)
         assert np.array_equal(lat.spectrum(0), tw.spectrum(0))
     batch.close()
+    # the LDS-resident launch: per-step time and HBM bytes (state and channel
+    # array in and out once per launch of `reps` steps)
+    res = [_model_b((128, 128), s) for s in range(3)]
+    rb = pss.Batch(res)
+    blobs = [lat.save() for lat in res]
+    ms, nbytes = rb.time_kernel(-2, pss.KERNEL_UPDATE, 10)
+    assert ms > 0 and nbytes == 16 * 128 * 128 * 3 / 10
+    with pytest.raises(PssError):
+        rb.time_kernel(-1, pss.KERNEL_UPDATE, 5)  # no fused launch
+    for lat, blob in zip(res, blobs):
+        lat.load(blob)
+    rb.step(4)
+    twins = [_model_b((128, 128), s) for s in range(3)]
+    for lat, tw in zip(res, twins):
+        tw.step(4)
+        assert np.array_equal(lat.spectrum(0), tw.spectrum(0))
+    rb.close()
 
 
 def test_full_ensemble_configuration_sampled():
@@ -175,12 +195,78 @@ def test_full_ensemble_configuration_sampled():
     mem = [_model_b((s, s), 1000 + i) for i, s in enumerate(sizes)]
     batch = pss.Batch(mem)
     assert batch.classes()[0] == 3
-    assert batch.launches() == (2, 3)  # one fused launch per phase
+    # 128^2 LDS-resident; 256^2 and 512^2 in one fused launch per phase
+    assert batch.launches() == (2, 2, 1)
     batch.step(25)
     for i in (0, 255, 256, 319, 320, 335):
         twin = _model_b((sizes[i], sizes[i]), 1000 + i)
         twin.step(25)
         assert np.array_equal(mem[i].spectrum(0), twin.spectrum(0)), i
+    batch.close()
+
+
+@pytest.mark.parametrize("n", [(64, 64), (128, 128), (64, 128), (128, 64)])
+def test_resident_launch_is_bitwise_the_single_path(n, monkeypatch):
+    """Every lattice shape of the LDS-resident kernel, with and without noise,
+    and a member whose state went non-finite: equal bit for bit to the lattice
+    stepped alone and to the batch with the resident launch turned off; steps
+    that cross graph chunks, and a chunk of one step."""
+    def make():
+        return [_model_b(n, 40 + i, D=0.0 if i == 1 else 0.01) for i in range(3)]
+    mem, off, twins = make(), None, make()
+    batch = pss.Batch(mem)
+    assert batch.launches()[2] == 1
+    monkeypatch.setenv("PSS_BATCH_RESIDENT", "0")
+    off = make()
+    batch_off = pss.Batch(off)
+    assert batch_off.launches()[2] == 0
+    monkeypatch.delenv("PSS_BATCH_RESIDENT")
+    for k in (1, 60, 7):
+        batch.step(k)
+        batch_off.step(k)
+    batch.sync()
+    batch_off.sync()
+    for lat, lo, tw in zip(mem, off, twins):
+        tw.step(68)
+        assert lat.step_index == 68
+        assert np.array_equal(lat.spectrum(0), tw.spectrum(0))
+        assert np.array_equal(lo.spectrum(0), tw.spectrum(0))
+    # after the batch: the member's own steps continue from the right counter
+    mem[0].step(5)
+    twins[0].step(5)
+    assert np.array_equal(mem[0].spectrum(0), twins[0].spectrum(0))
+    batch.close()
+    batch_off.close()
+
+
+def test_resident_member_matches_the_oracle():
+    n, steps = (128, 128), 100
+    lat = _model_b(n, 77)
+    other = _model_b(n, 78)
+    batch = pss.Batch([lat, other])
+    assert batch.launches()[2] == 1
+    batch.step(steps)
+    batch.sync()
+    m = om.model_b(OLattice(n[0], n[1], 1), 0.01, a=-1.0, b=1.0, k=1.0, D=0.01, seed=77)
+    m.init_uniform(0, -0.1, 0.1)
+    m.step(steps)
+    want = m.real(0)[0]
+    assert np.max(np.abs(lat.download(0) - want)) <= 1e-4 * max(1.0, np.max(np.abs(want)))
+    batch.close()
+
+
+def test_resident_nonfinite_flag():
+    lat = _model_b((64, 64), 5)
+    other = _model_b((64, 64), 6)
+    bad = np.zeros((64, 64), dtype=np.float32)
+    bad[3, 7] = np.inf
+    lat.upload(0, bad)
+    batch = pss.Batch([lat, other])
+    assert batch.launches()[2] == 1
+    batch.step(2)
+    with pytest.raises(PssError) as e:
+        batch.sync()
+    assert e.value.name == "PSS_E_NONFINITE"
     batch.close()
 
 
