@@ -38,7 +38,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # this workload; its traffic figure is reported only while the kernel sources
 # and the launch geometry are the ones the counters were taken with.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_update_kernel_modelb_1024.txt")
-KERNEL_SOURCES = ("pss_kernels.hip", "pss_device.h", "pss_fft.h", "pss_kernels.h", "pss_plan.h")
+KERNEL_SOURCES = ("pss_kernels.hip", "pss_device.h", "pss_fft.h", "pss_fft_layout.h", "pss_kernels.h", "pss_plan.h")
 N = (1024, 1024)
 A, B, K, D, DT, SEED = -1.0, 1.0, 1.0, 0.01, 0.01, 1
 REPEATS = 5

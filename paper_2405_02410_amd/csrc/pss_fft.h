@@ -30,10 +30,15 @@
 // (each group writes only its own Ls elements) and, for lines wider than a
 // wave, two buffers for the block exchanges, used alternately (LdsLine::par):
 // a buffer is written again only after the next block barrier, which every
-// thread reaches after it has read the older exchange.
+// thread reaches after it has read the older exchange.  Each region holds
+// kReg = L + L/2^PSS_FFT_PAD elements: element e of an exchange sits at
+// e + (e >> PSS_FFT_PAD), one pad slot after every 2^PSS_FFT_PAD elements,
+// so that the strided exchange patterns spread over the LDS banks (lines of
+// 4096 stay unpadded, see pss_fft_layout.h).
 #pragma once
 
 #include "pss_device.h"
+#include "pss_fft_layout.h"
 
 namespace pss {
 
@@ -63,12 +68,14 @@ struct LdsLine {
     }
 };
 
-template <int L, int P>
+template <int L, int P, int PADS = kFftPad>
 struct LineFFT {
     static_assert((L & (L - 1)) == 0 && (P & (P - 1)) == 0 && P <= 16 && P <= L, "bad line shape");
     static constexpr int T = L / P;
-    static constexpr bool kCross = T > 64;           // the first exchange crosses waves
-    static constexpr int kLds = kCross ? 3 * L : L;  // LDS elements per line
+    static constexpr bool kCross = T > 64;                  // the first exchange crosses waves
+    static constexpr int kReg = fft_region(L, PADS);        // one exchange region
+    static constexpr int kLds = kCross ? 3 * kReg : kReg;  // LDS elements per line
+    static __device__ __forceinline__ int pad(int e) { return fft_padded(L, PADS) ? e + (e >> PADS) : e; }
 
     // stage s: sub-transform length, group size and radix
     struct Stages {
@@ -150,7 +157,7 @@ struct LineFFT {
 #pragma unroll
             for (int h = 0; h < PR; ++h)
 #pragma unroll
-                for (int k1 = 0; k1 < R; ++k1) buf[gb + k1 * Lr + g + h * G] = v[h + k1 * PR];
+                for (int k1 = 0; k1 < R; ++k1) buf[pad(gb + k1 * Lr + g + h * G)] = v[h + k1 * PR];
             if constexpr (cross) {
                 __syncthreads();
             } else {
@@ -158,7 +165,7 @@ struct LineFFT {
             }
             const int k1 = g / Gn, gp = g & (Gn - 1);
 #pragma unroll
-            for (int j = 0; j < P; ++j) v[j] = buf[gb + k1 * Lr + gp + j * Gn];
+            for (int j = 0; j < P; ++j) v[j] = buf[pad(gb + k1 * Lr + gp + j * Gn)];
             dif_stage<DIR, S + 1>(v, ld, t, tw);
         }
     }
@@ -179,7 +186,7 @@ struct LineFFT {
             const int k1 = g / Gn, gp = g & (Gn - 1);
             if constexpr (!cross) wave_lds_sync();
 #pragma unroll
-            for (int j = 0; j < P; ++j) buf[gb + k1 * Lr + gp + j * Gn] = v[j];
+            for (int j = 0; j < P; ++j) buf[pad(gb + k1 * Lr + gp + j * Gn)] = v[j];
             if constexpr (cross) {
                 __syncthreads();
             } else {
@@ -188,7 +195,7 @@ struct LineFFT {
 #pragma unroll
             for (int h = 0; h < PR; ++h)
 #pragma unroll
-                for (int kk = 0; kk < R; ++kk) v[h + kk * PR] = buf[gb + kk * Lr + g + h * G];
+                for (int kk = 0; kk < R; ++kk) v[h + kk * PR] = buf[pad(gb + kk * Lr + g + h * G)];
         }
 #pragma unroll
         for (int h = 0; h < PR; ++h) {
@@ -218,9 +225,5 @@ struct LineFFT {
     }
 };
 
-// LDS elements of the line transforms of `lines` lines (host and device)
-__host__ __device__ constexpr int fft_lds_elems(int L, int P, int lines) {
-    return lines * ((L / P > 64) ? 3 * L : L);
-}
 
 }  // namespace pss

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pss_fft_layout.h"
 #include "pss_plan.h"
 
 namespace pss {
@@ -171,7 +172,10 @@ __host__ __device__ constexpr int resident_threads(int lx, int ly) {
 }
 // LDS: padded channel/factor array, line scratch, packed-line exchange, twiddles
 inline size_t resident_lds_bytes(int lx, int ly) {
-    return sizeof(float2) * (static_cast<size_t>(lx / 2) * (ly + 1) + 4 * resident_threads(lx, ly) + 2 * ly + lx);
+    const int nthr = resident_threads(lx, ly);
+    const size_t scr_y = static_cast<size_t>(nthr / (ly / 4)) * fft_region(ly);
+    const size_t scr_x = static_cast<size_t>(nthr / (lx / 4)) * fft_region(lx);
+    return sizeof(float2) * (static_cast<size_t>(lx / 2) * (ly + 1) + (scr_y > scr_x ? scr_y : scr_x) + 2 * ly + lx);
 }
 inline bool resident_shape(int lx, int ly) { return (lx == 64 || lx == 128) && (ly == 64 || ly == 128); }
 hipError_t resident_setup();
@@ -195,6 +199,9 @@ hipError_t launch_adjseed(hipStream_t s, const float2* phi, float2* g, const flo
 
 // *ctrs[i] += k for i < n (the step counters of a batch)
 hipError_t launch_advance_many(hipStream_t s, uint64_t* const* ctrs, int n, int64_t k);
+// out[i] = the non-finite flag word after *ctrs[i] (the word after the step
+// counter), cleared atomically
+hipError_t launch_take_flags(hipStream_t s, uint64_t* const* ctrs, int n, uint32_t* out);
 hipError_t launch_init_uniform(hipStream_t s, float* out, int64_t n, uint32_t field, uint32_t key0, uint32_t key1,
                                double lo, double hi);
 hipError_t launch_philox(hipStream_t s, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
@@ -205,13 +212,13 @@ inline int field_slots(int n) { return n <= 1 ? 1 : (n == 2 ? 2 : 4); }
 // LDS elements of the line transforms of `lines` lines of length L held with
 // P points per thread: one in-wave region per line, plus two block-exchange
 // buffers per line when a line spans more than one wave (pss_fft.h)
-inline size_t fft_lds(int L, int P, int lines) {
-    return static_cast<size_t>(lines) * ((L / P > 64) ? 3 : 1) * static_cast<size_t>(L);
+inline size_t fft_lds(int L, int P, int lines, int pads = kFftPad) {
+    return static_cast<size_t>(fft_lds_elems(L, P, lines, pads));
 }
 // dynamic LDS of the update kernel: TC*TO line transforms, one exchange line
 // and the staged twiddle table (L entries), in that order
-inline size_t update_lds_bytes(int L, int P, int tc, int to) {
-    return sizeof(float2) * (fft_lds(L, P, tc * to) + 2 * static_cast<size_t>(L));
+inline size_t update_lds_bytes(int L, int P, int tc, int to, int pads = kFftPad) {
+    return sizeof(float2) * (fft_lds(L, P, tc * to, pads) + 2 * static_cast<size_t>(L));
 }
 // dynamic LDS of the y pass: TC*TZ line transforms, one exchange line per z
 // and the staged twiddle table (L entries), in that order

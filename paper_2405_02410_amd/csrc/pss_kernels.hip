@@ -483,13 +483,13 @@ __device__ __forceinline__ void source_line(const DevPlan& p, int src, const flo
 // arguments, so the plan reads stay scalar loads).  A launch of one lattice
 // (and the transform modes) takes buffers, counter and flag from the
 // arguments: its data loads then wait for no table load.
-template <int L, int P, int NF, int MODE, int DIM, bool GEN, bool TABLE>
+template <int L, int P, int NF, int MODE, int DIM, bool GEN, bool TABLE, int PADS = kFftPad>
 __device__ __forceinline__ void update_block(int mi, int blk, const Member* __restrict__ members,
                                              const DevPlan* __restrict__ plans, const DevPlan* __restrict__ plan_a,
                                              const Bufs& bufs_a, const Geo& geo,
                                              const uint64_t* __restrict__ step_ctr_a, uint32_t* __restrict__ flag_a,
                                              int step_off, const float2* __restrict__ tw_g) {
-    using FFT = LineFFT<L, P>;
+    using FFT = LineFFT<L, P, PADS>;
     constexpr int T = FFT::T;
     extern __shared__ float2 smem[];
     constexpr bool TAB = (MODE == MODE_STEP || MODE == MODE_PROLOGUE) && TABLE;
@@ -529,8 +529,8 @@ __device__ __forceinline__ void update_block(int mi, int blk, const Member* __re
     const size_t vstride = DIM == 2 ? static_cast<size_t>(tc) : static_cast<size_t>(ntile) * ny * tc;
     LdsLine ld;
     ld.wl = smem + li * FFT::kLds;
-    ld.blk0 = ld.wl + L;
-    ld.blk1 = ld.wl + 2 * L;
+    ld.blk0 = ld.wl + FFT::kReg;
+    ld.blk1 = ld.wl + 2 * FFT::kReg;
     ld.par = 0;
     float2* xbuf = smem + tc * to * FFT::kLds;  // packed-line exchange
     float2* twl = xbuf + L;
@@ -821,8 +821,8 @@ __global__ void __launch_bounds__(256) adjcol_kernel(AdjArgs aa, Geo geo, const 
     const size_t base = static_cast<size_t>(ct) * L * tc + cc;
     LdsLine ld;
     ld.wl = smem + cc * FFT::kLds;
-    ld.blk0 = ld.wl + L;
-    ld.blk1 = ld.wl + 2 * L;
+    ld.blk0 = ld.wl + FFT::kReg;
+    ld.blk1 = ld.wl + 2 * FFT::kReg;
     ld.par = 0;
     float2* xbuf = smem + tc * FFT::kLds;
     float2* twl = xbuf + L;
@@ -1036,8 +1036,8 @@ __global__ void __launch_bounds__(256) ypass_kernel(YArgs ya, Geo geo, const flo
     const int c = ct * tc + cc;
     LdsLine ld;
     ld.wl = smem + li * FFT::kLds;
-    ld.blk0 = ld.wl + L;
-    ld.blk1 = ld.wl + 2 * L;
+    ld.blk0 = ld.wl + FFT::kReg;
+    ld.blk1 = ld.wl + 2 * FFT::kReg;
     ld.par = 0;
     float2* xb = smem + tc * tz * FFT::kLds + lz * L;  // column-0 exchange, one line per z
     const int dr = FFT::drev(t);
@@ -1108,12 +1108,12 @@ __global__ void __launch_bounds__(256) ypass_kernel(YArgs ya, Geo geo, const flo
 // Packed-column arrays are read and written in whole tile blocks of RB*TC
 // contiguous elements.
 // One block of the x kernel: row block `blk` of lattice `mi` (as in the update kernel)
-template <int L, int P, int NG, int MODE, bool TABLE>
+template <int L, int P, int NG, int MODE, bool TABLE, int PADS = kFftPad>
 __device__ __forceinline__ void xrow_block(int mi, int blk, const Member* __restrict__ members,
                                            const DevPlan* __restrict__ plans, const DevPlan* __restrict__ plan_a,
                                            const Bufs& bufs_a, const Geo& geo, const float2* __restrict__ tw_g,
                                            int64_t advance, uint64_t* __restrict__ step_ctr_a) {
-    using FFT = LineFFT<L, P>;
+    using FFT = LineFFT<L, P, PADS>;
     constexpr int T = FFT::T;
     constexpr int NC = L / 2;  // packed columns
     extern __shared__ float2 smem[];
@@ -1143,8 +1143,8 @@ __device__ __forceinline__ void xrow_block(int mi, int blk, const Member* __rest
     const int lt = geo.tc_log2;
     LdsLine ld;
     ld.wl = smem + pr * FFT::kLds;
-    ld.blk0 = ld.wl + L;
-    ld.blk1 = ld.wl + 2 * L;
+    ld.blk0 = ld.wl + FFT::kReg;
+    ld.blk1 = ld.wl + 2 * FFT::kReg;
     ld.par = 0;
     const int dr = FFT::drev(t);
     // twiddles: loaded now, stored to LDS after each mode's first loads
@@ -1358,6 +1358,12 @@ __global__ void advance_kernel(uint64_t* step_ctr, int64_t k) {
 __global__ void advance_many_kernel(uint64_t* const* __restrict__ ctrs, int n, int64_t k) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) *ctrs[i] += static_cast<uint64_t>(k);
+}
+
+// read and clear the non-finite flag that follows each member's step counter
+__global__ void take_flags_kernel(uint64_t* const* __restrict__ ctrs, int n, uint32_t* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = atomicExch(reinterpret_cast<uint32_t*>(ctrs[i] + 1), 0u);
 }
 
 __global__ void init_uniform_kernel(float* __restrict__ out, int64_t n, uint32_t field, uint32_t key0,
@@ -1654,7 +1660,10 @@ hipError_t PSS_CAT(launch_xrow_L, PSS_LINE_LEN)(int mode, int ng, const LaunchAr
 // ------------------------------------------------------ fused batch launches
 // One launch per phase for a whole batch: block b (XCD-ordered) finds its
 // class in the work list, then its member and tile, and runs the block body
-// built for that class's line length.
+// built for that class's line length.  The update launch uses unpadded
+// transform exchanges: the pad's address arithmetic would raise the register
+// count of a kernel that holds every line length's body, and with it cut the
+// waves per SIMD from 4 to 3 (padding moves data only, never the results).
 __device__ __forceinline__ int batch_class_of(const BatchLaunch& bl, int b) {
     int k = 0;
     for (int i = 1; i < bl.ncls; ++i)
@@ -1671,7 +1680,8 @@ __global__ void __launch_bounds__(256) batch_update_kernel(BatchLaunch bl) {
     const Bufs none{};
 #define PSS_BU(LL)                                                                                                 \
     case LL:                                                                                                       \
-        update_block<LL, 4, 1, MODE_STEP, 2, false, true>(mi, blk, C.members, C.plans, nullptr, none, C.geo, nullptr, \
+        update_block<LL, 4, 1, MODE_STEP, 2, false, true, 0>(mi, blk, C.members, C.plans, nullptr, none, C.geo,       \
+                                                             nullptr,                                                 \
                                                           nullptr, bl.step_off, C.tw);                             \
         break;
     switch (C.L) {
@@ -1738,8 +1748,9 @@ __global__ void __launch_bounds__(resident_threads(LX, LY)) resident_kernel(Resi
     constexpr int LPW = 64 / TY;                     // column lines per wave
     extern __shared__ float2 smem[];
     float2* const X = smem;
-    float2* const scr = X + NC * XS;                 // 4 NTHR: one line per thread group
-    float2* const xbuf = scr + 4 * NTHR;             // packed-line exchange (LY)
+    float2* const scr = X + NC * XS;                 // one exchange region per line of a round
+    constexpr int SCR = CPR * FY::kReg > RPR * FX::kReg ? CPR * FY::kReg : RPR * FX::kReg;
+    float2* const xbuf = scr + SCR;                  // packed-line exchange (LY)
     float2* const twy = xbuf + LY;
     float2* const twx = twy + LY;
     const int mi = xcd_block(blockIdx.x, gridDim.x);
@@ -1757,14 +1768,14 @@ __global__ void __launch_bounds__(resident_threads(LX, LY)) resident_kernel(Resi
     const int li = tid / TY, tcol = tid & (TY - 1);
     const int dry = FY::drev(tcol);
     LdsLine ldc;
-    ldc.wl = scr + li * LY;
+    ldc.wl = scr + li * FY::kReg;
     ldc.blk0 = ldc.blk1 = nullptr;
     ldc.par = 0;
     // row phase: pair pi of the round, thread t of the pair
     const int pi = tid / TX, trow = tid & (TX - 1);
     const int drx = FX::drev(trow);
     LdsLine ldr;
-    ldr.wl = scr + pi * LX;
+    ldr.wl = scr + pi * FX::kReg;
     ldr.blk0 = ldr.blk1 = nullptr;
     ldr.par = 0;
 
@@ -2148,6 +2159,12 @@ hipError_t launch_advance(hipStream_t s, uint64_t* step_ctr, int64_t k) {
 hipError_t launch_advance_many(hipStream_t s, uint64_t* const* ctrs, int n, int64_t k) {
     if (n < 1) return hipSuccess;
     hipLaunchKernelGGL(advance_many_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ctrs, n, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_take_flags(hipStream_t s, uint64_t* const* ctrs, int n, uint32_t* out) {
+    if (n < 1) return hipSuccess;
+    hipLaunchKernelGGL(take_flags_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ctrs, n, out);
     return hipGetLastError();
 }
 

@@ -215,6 +215,7 @@ struct pss_batch {
     std::vector<pss::ResidentLaunch> res;
     bool resident = true;              // PSS_BATCH_RESIDENT=0 at creation turns the resident launches off
     uint64_t** d_ctrs = nullptr;       // step counter of every member
+    uint32_t* d_flags = nullptr;       // the members' non-finite flags, gathered by pss_batch_sync
     hipStream_t stream = nullptr;      // the first member's stream
     hipEvent_t ev = nullptr;
     std::map<int64_t, hipGraphExec_t> graphs;
@@ -1035,6 +1036,8 @@ void free_batch(pss_batch* b) {
     }
     if (b->d_ctrs) (void)hipFree(b->d_ctrs);
     b->d_ctrs = nullptr;
+    if (b->d_flags) (void)hipFree(b->d_flags);
+    b->d_flags = nullptr;
     if (b->ev) (void)hipEventDestroy(b->ev);
     b->ev = nullptr;
 }
@@ -1102,7 +1105,8 @@ void batch_plan_fused(pss_batch* b) {
             C.tw = r->d_tw_u;
             C.geo = r->geo;
             b->fu.total += nmem * C.nblk;
-            b->fu_lds = std::max(b->fu_lds, pss::update_lds_bytes(r->lu, 4, r->geo.tc, 1));
+            // the fused update kernel's transforms are unpadded (its register budget)
+            b->fu_lds = std::max(b->fu_lds, pss::update_lds_bytes(r->lu, 4, r->geo.tc, 1, 0));
             b->in_fu[k] = 1;
         }
         const int nx = r->n[0], ny = r->n[1];
@@ -2344,6 +2348,7 @@ pss_status pss_batch_create(pss_batch** out, pss_ctx* const* lattices, int32_t n
     std::vector<uint64_t*> ctrs;
     for (pss_ctx* c : b->mem) ctrs.push_back(c->d_step);
     hipError_t e = hipMalloc(&b->d_ctrs, sizeof(uint64_t*) * ctrs.size());
+    if (e == hipSuccess) e = hipMalloc(&b->d_flags, sizeof(uint32_t) * ctrs.size());
     if (e == hipSuccess) e = hipMemcpy(b->d_ctrs, ctrs.data(), sizeof(uint64_t*) * ctrs.size(), hipMemcpyHostToDevice);
     for (auto& cl : b->cls) {
         std::vector<pss::Member> tu, tx;
@@ -2415,12 +2420,18 @@ pss_status pss_batch_step(pss_batch* b, int64_t nsteps) {
 pss_status pss_batch_sync(pss_batch* b) {
     if (!b) return fail(PSS_E_INVAL, "null batch");
     HIP_TRY(hipStreamSynchronize(b->stream));
-    pss_status st = PSS_OK;
-    for (pss_ctx* c : b->mem) {
-        const pss_status s = take_nonfinite(c);
-        if (s && !st) st = s;  // report the first member, clear every flag
-    }
-    return st;
+    // every member's flag read and cleared by one kernel and one copy
+    const int n = static_cast<int>(b->mem.size());
+    std::vector<uint32_t> flags(n);
+    HIP_TRY(pss::launch_take_flags(b->stream, b->d_ctrs, n, b->d_flags));
+    HIP_TRY(hipMemcpyAsync(flags.data(), b->d_flags, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (int i = 0; i < n; ++i)
+        if (flags[i])  // report the first member; every flag is cleared
+            return fail(PSS_E_NONFINITE,
+                        "member %d: a non-finite value appeared in the state (field mask 0x%x) at or before step %lld",
+                        i, flags[i], static_cast<long long>(b->mem[i]->steps_taken));
+    return PSS_OK;
 }
 
 pss_status pss_batch_launches(pss_batch* b, int32_t* per_step, int32_t* fused_classes, int32_t* resident_classes) {
