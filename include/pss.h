@@ -1,7 +1,7 @@
 /*
  * pss.h -- C interface of the MI355X pseudo-spectral stochastic-PDE stepper.
  *
- * The library advances real fields phi_f on a periodic 2D or 3D lattice with
+ * The library advances real fields phi_f on a periodic 1D, 2D or 3D lattice with
  * the semi-implicit Euler-Maruyama scheme of cuPSS (arXiv 2405.02410,
  * eq:timeupdate and the six-step list that follows it):
  *
@@ -23,8 +23,9 @@
  *   thread-local message describing the most recent failure on the calling
  *   thread.
  * - Sizes are given as n[3] = {Nx, Ny, Nz} and dx[3] = {dx, dy, dz}; a 2D
- *   lattice ignores n[2] and dx[2].  Every N_i must be a power of two in
- *   [8, 4096]; other sizes return PSS_E_UNSUPPORTED.
+ *   lattice ignores n[2] and dx[2], a 1D lattice n[1], n[2], dx[1], dx[2].
+ *   Every N_i must be a power of two in [8, 4096]; other sizes return
+ *   PSS_E_UNSUPPORTED.
  * - Real-space arrays are float32, x fastest: index (z*Ny + y)*Nx + x.
  * - Fourier convention: forward transform unnormalised, inverse with 1/N.
  *   Mode indices are signed integers in FFT order with the Nyquist index read
@@ -95,10 +96,14 @@ typedef struct {
 /* ---- lattice ----------------------------------------------------------- */
 
 /* Create a lattice context (Sec. "Writing models", the system constructor).
- * ndim: 2 or 3.  n, dx: see conventions.  dt > 0.  Touches no device: the
- * device plan is built on the first upload, init or step.
+ * ndim: 1, 2 or 3.  n, dx: see conventions.  dt > 0.  Touches no device: the
+ * device plan is built on the first upload, init or step.  A 1D lattice (the
+ * line of the examples in Sec. "Callback functions" and "De-aliasing") is
+ * stepped by one block that holds the whole line; its state is the full
+ * complex spectrum of the line (pss_state_size), and it takes part in neither
+ * batches nor the adjoint (PSS_E_UNSUPPORTED there).
  * Errors: PSS_E_INVAL (null out, dt <= 0, dx <= 0), PSS_E_UNSUPPORTED (ndim
- * not 2 or 3, a size that is not a power of two in [8, 4096]). */
+ * not 1, 2 or 3, a size that is not a power of two in [8, 4096]). */
 pss_status pss_lattice_create(pss_ctx **out, int32_t ndim, const int64_t n[3],
                               const double dx[3], double dt);
 

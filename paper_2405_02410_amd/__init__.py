@@ -160,13 +160,13 @@ def _ptr(a):
 
 
 class Lattice:
-    """A periodic 2D or 3D lattice with fields, terms and noise (one context)."""
+    """A periodic 1D, 2D or 3D lattice with fields, terms and noise (one context)."""
 
     def __init__(self, n, dx=None, dt=0.01, seed=0, dealias=DEALIAS_TWO_THIRDS, shape=SHAPE_RADIAL):
         n = tuple(int(v) for v in n)
         self.ndim = len(n)
-        if self.ndim not in (2, 3):
-            raise PssError(-2, f"ndim must be 2 or 3 (got {self.ndim})")
+        if self.ndim not in (1, 2, 3):
+            raise PssError(-2, f"ndim must be 1, 2 or 3 (got {self.ndim})")
         dx = tuple(float(v) for v in (dx if dx is not None else (1.0,) * self.ndim))
         n3 = (ctypes.c_int64 * 3)(*(n + (1,) * (3 - self.ndim)))
         d3 = (ctypes.c_double * 3)(*(dx + (1.0,) * (3 - self.ndim)))

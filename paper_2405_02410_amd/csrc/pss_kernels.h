@@ -119,7 +119,8 @@ struct LaunchArgs {
     const float2* tw_u;  // twiddles of the update-axis length
     const float2* tw_x;  // twiddles of Nx
     const float2* tw_y;  // twiddles of Ny (3D y passes)
-    int dim;             // 2 or 3
+    int dim;             // 1, 2 or 3
+    int nsteps;          // 1D step launches: steps of the launch
 };
 
 // Fused batch launches: one update-phase and one x-phase launch cover every
@@ -188,6 +189,19 @@ hipError_t launch_batch_xrow(hipStream_t s, const BatchLaunch& bl, size_t lds);
 int max_points(int L, int nregs);
 
 hipError_t launch_update(int mode, int L, int nf, const LaunchArgs& a);
+
+// 1D lattices: one block holds the whole line (line1d_kernel).  Modes:
+// MODE_STEP (a.nsteps steps; a.advance != 0 moves the counter on by them),
+// MODE_FWD_STORE (real_in -> state sel), MODE_INV_OUT (state sel ->
+// real_out), MODE_INTERM_OUT (intermediate sel -> real_out).  The state of a
+// field is its full complex spectrum of N modes in natural order.
+hipError_t launch_line1d(int mode, int N, int nf, const LaunchArgs& a);
+// LDS of the 1D kernel: the line transform and the twiddle table
+inline size_t line1d_lds_bytes(int N) {
+    return sizeof(float2) * (static_cast<size_t>(fft_lds_elems(N, 4, 1)) + static_cast<size_t>(N));
+}
+// allow the 1D kernels of length N their LDS (above the default dynamic limit)
+hipError_t line1d_setup(int N);
 hipError_t launch_xrow(int mode, int L, int ng, const LaunchArgs& a);
 hipError_t launch_ypass(int mode, int L, const YArgs& ya, const LaunchArgs& a);
 hipError_t launch_advance(hipStream_t s, uint64_t* step_ctr, int64_t k);

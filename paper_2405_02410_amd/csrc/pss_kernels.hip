@@ -1387,7 +1387,8 @@ __global__ void philox_kernel(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3
 // Shell sums for the structure factor.  Thread i handles packed element i of
 // the 2D tiled layout [ctile][y][TC]; interior columns stand for the mode and
 // its conjugate partner (weight 2); column 0 is unpacked into kx = 0 and
-// kx = Nx/2 (weight 1 each) with the partner element at -y.
+// kx = Nx/2 (weight 1 each) with the partner element at -y.  In 1D element i
+// is mode i of the full spectrum (weight 1).
 __device__ __forceinline__ void shell_add(double* sums, unsigned int* cnt, int nshell, int kx, int ky, int kz,
                                           double v, unsigned int w) {
     const double kk = static_cast<double>(kx) * kx + static_cast<double>(ky) * ky + static_cast<double>(kz) * kz;
@@ -1409,10 +1410,15 @@ __global__ void shells_kernel(const float2* __restrict__ S, int nx, int ny, int 
     __syncthreads();
     const int ncols = nx / 2;
     const int ntile = ncols / tc;
-    const int64_t total = static_cast<int64_t>(ncols) * ny * nz;
+    const int64_t total = dim == 1 ? static_cast<int64_t>(nx) : static_cast<int64_t>(ncols) * ny * nz;
     auto mag = [](float2 v) { return static_cast<double>(v.x) * v.x + static_cast<double>(v.y) * v.y; };
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
          e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        if (dim == 1) {
+            const int k = static_cast<int>(e);
+            shell_add(lsum, lcnt, nshell, k < nx / 2 ? k : k - nx, 0, 0, scale * mag(S[e]), 1u);
+            continue;
+        }
         const int cc = static_cast<int>(e % tc);
         const int64_t r = e / tc;
         int c, y, z;
@@ -1470,6 +1476,195 @@ __global__ void shells_kernel(const float2* __restrict__ S, int nx, int ny, int 
 #endif  // PSS_COMMON
 
 // ------------------------------------------------------- launch dispatch
+// -------------------------------------------------------------- 1D lattices
+// One block holds the whole line of N sites: T = N/4 threads, 4 modes each.
+// A field's state is its full complex spectrum (Hermitian up to rounding) in
+// natural mode order; thread t keeps modes k = D(t) + m T, the order in which
+// the forward transform leaves them and the inverse transform takes them, so
+// a step needs no reordering.  Real space is the real part of the inverse
+// transform (as for every dimension).  A launch first forms the explicit
+// contributions of its first step from the state, then takes its steps in
+// registers, following the per-step list after eq:timeupdate: intermediate
+// and de-aliased factors from the state, inverse transforms, products,
+// forward transforms, noise, semi-implicit update.
+template <int N, int NF, bool GEN, int MODE>
+__global__ void __launch_bounds__(N / 4 < 64 ? 64 : N / 4)
+    line1d_kernel(const DevPlan* __restrict__ plan, Bufs bufs, uint64_t* __restrict__ step_ctr,
+                  uint32_t* __restrict__ flag, int nsteps, int advance, const float2* __restrict__ tw_g) {
+    constexpr int P = 4;
+    using FFT = LineFFT<N, P>;
+    constexpr int T = FFT::T;
+    extern __shared__ float2 smem[];
+    const DevPlan& p = *plan;
+    const int t = threadIdx.x;
+    LdsLine ld;
+    ld.wl = smem;
+    ld.blk0 = smem + FFT::kReg;
+    ld.blk1 = smem + 2 * FFT::kReg;
+    ld.par = 0;
+    float2* const twl = smem + FFT::kLds;
+    for (int i = t; i < N; i += T) twl[i] = tw_g[i];
+    __syncthreads();
+    const float2* tw = twl;
+    const int dr = FFT::drev(t);
+    // the modes of this thread: index k = dr + m T, signed kx, q, linear indices
+    ModeQ q[P];
+    float q2[P];
+    uint32_t lin[P], lneg[P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+        const int k = dr + m * T;
+        q[m] = mode_q(p, k < (N >> 1) ? k : k - N, 0, 0);
+        q2[m] = q[m].q2;
+        lin[m] = static_cast<uint32_t>(k);
+        lneg[m] = static_cast<uint32_t>((N - k) & (N - 1));
+    }
+
+    if constexpr (MODE == MODE_FWD_STORE) {
+        float2 v[P];
+#pragma unroll
+        for (int m = 0; m < P; ++m) v[m] = make_float2(bufs.real_in[t + m * T], 0.f);
+        FFT::template dif<-1>(v, ld, t, tw);
+#pragma unroll
+        for (int m = 0; m < P; ++m) gstore(bufs.S[bufs.sel] + dr + m * T, v[m]);
+        return;
+    }
+    if constexpr (MODE == MODE_INV_OUT) {
+        float2 v[P];
+#pragma unroll
+        for (int m = 0; m < P; ++m) v[m] = gload(bufs.S[bufs.sel] + dr + m * T);
+        FFT::template dit<1>(v, ld, t, tw);
+#pragma unroll
+        for (int m = 0; m < P; ++m) bufs.real_out[t + m * T] = v[m].x * p.inv_n;
+        return;
+    }
+
+    float2 s[NF][P];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int m = 0; m < P; ++m) s[f][m] = f < p.nf ? gload(bufs.S[f] + dr + m * T) : make_float2(0.f, 0.f);
+
+    // the Fourier values of source `src` (a dynamic field, or an intermediate
+    // psi = sum_k op_k phi_k / (1 - L_psi)) at this thread's modes
+    auto source = [&](int src, float2 (&v)[P]) {
+        if constexpr (GEN) {
+            if (src >= PSS_MAXF) {
+                const DevInterm& I = p.interm[src - PSS_MAXF];
+#pragma unroll
+                for (int m = 0; m < P; ++m) v[m] = make_float2(0.f, 0.f);
+                for (int k = 0; k < I.nsrc; ++k) {
+                    const int sk = I.src[k];
+#pragma unroll
+                    for (int m = 0; m < P; ++m) v[m] = cadd(v[m], cmul(eval_op<true>(I.op[k], q[m]), pick(s, sk, m)));
+                }
+#pragma unroll
+                for (int m = 0; m < P; ++m) v[m] = cmul(v[m], cinv_implicit(1.f, eval_op<true>(I.den, q[m])));
+                return;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < P; ++m) v[m] = pick(s, src, m);
+    };
+
+    if constexpr (MODE == MODE_INTERM_OUT) {
+        float2 v[P];
+        source(PSS_MAXF + bufs.sel, v);
+        FFT::template dit<1>(v, ld, t, tw);
+#pragma unroll
+        for (int m = 0; m < P; ++m) bufs.real_out[t + m * T] = v[m].x * p.inv_n;
+        return;
+    }
+
+    // MODE_STEP.  acc: the explicit contributions sum_ch M_ch(q) F[products]
+    float2 acc[NF][P];
+    auto channels = [&]() {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int m = 0; m < P; ++m) acc[f][m] = make_float2(0.f, 0.f);
+        if (p.nch == 0) return;
+        // real-space values of the de-aliased factors at x = t + m T
+        float u[PSS_MAXF][P];
+#pragma unroll
+        for (int g = 0; g < PSS_MAXF; ++g) {
+            if (g >= p.ng) break;
+            const DevMask& mk = p.mask[g];
+            float2 v[P];
+            source(p.gfield[g], v);
+#pragma unroll
+            for (int m = 0; m < P; ++m) {
+                const int k = dr + m * T;
+                if (!mask_keep(mk, k < (N >> 1) ? k : k - N, 0, 0)) v[m] = make_float2(0.f, 0.f);
+            }
+            FFT::template dit<1>(v, ld, t, tw);
+#pragma unroll
+            for (int m = 0; m < P; ++m) u[g][m] = v[m].x * p.inv_n;
+        }
+        for (int ch = 0; ch < p.nch; ++ch) {
+            const DevChannel& C = p.ch[ch];
+            float2 w[P];
+#pragma unroll
+            for (int m = 0; m < P; ++m) w[m] = make_float2(0.f, 0.f);
+            for (int k = 0; k < C.nprod; ++k) {
+                const DevProd& pd = C.prod[k];
+                uint32_t pw;
+                __builtin_memcpy(&pw, pd.pow, sizeof(pw));
+#pragma unroll
+                for (int m = 0; m < P; ++m) {
+                    float a = pd.coef;
+#pragma unroll
+                    for (int g = 0; g < PSS_MAXF; ++g) {
+                        const int pg = static_cast<int>((pw >> (8 * g)) & 0xffu);
+                        for (int e = 0; e < pg; ++e) a *= u[g][m];
+                    }
+                    w[m].x += a;
+                }
+            }
+            FFT::template dif<-1>(w, ld, t, tw);
+#pragma unroll
+            for (int m = 0; m < P; ++m) add_to(acc, C.target, m, cmul(eval_op<GEN>(C.op, q[m]), w[m]));
+        }
+    };
+
+    const uint32_t step0 = static_cast<uint32_t>(gload_u64(step_ctr));
+    uint32_t bad = 0;
+    channels();
+    for (int sn = 0; sn < nsteps; ++sn) {
+        const uint32_t step = step0 + static_cast<uint32_t>(sn);
+        // linear explicit terms from the step-n state
+        for (int d = 0; d < p.nd; ++d) {
+            const DevDirect& Dd = p.direct[d];
+            float2 src[P];
+            source(Dd.src, src);
+#pragma unroll
+            for (int m = 0; m < P; ++m) add_to(acc, Dd.target, m, cmul(eval_op<GEN>(Dd.op, q[m]), src[m]));
+        }
+        // semi-implicit update with the noise of this step
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if (f >= p.nf) continue;
+            const bool noisy = p.noisy[f] != 0;
+#pragma unroll
+            for (int m = 0; m < P; ++m) {
+                float2 r = cadd(s[f][m], cscale(acc[f][m], p.dt));
+                if (noisy) r = cadd(r, noise_mode<GEN>(p, f, step, lin[m], lneg[m], q[m]));
+                s[f][m] = cmul(r, cinv_implicit(p.dt, eval_op<GEN>(p.implicit_op[f], q[m])));
+                if (!(__builtin_isfinite(s[f][m].x) && __builtin_isfinite(s[f][m].y))) bad |= 1u << f;
+            }
+        }
+        if (sn + 1 < nsteps) channels();  // the next launch forms its first step's anew
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+        if (f < p.nf)
+#pragma unroll
+            for (int m = 0; m < P; ++m) gstore(bufs.S[f] + dr + m * T, s[f][m]);
+    if (bad) atomicOr(flag, bad);
+    __syncthreads();  // every thread has read the counter
+    if (advance && t == 0) *step_ctr += static_cast<uint64_t>(nsteps);
+}
+
 // This file is compiled once per line length with -DPSS_LINE_LEN=<L> (the
 // kernels of that length) and once with -DPSS_COMMON (utilities and the
 // length dispatch), so the instantiations build in parallel.
@@ -1590,6 +1785,53 @@ static hipError_t with_points(int want, F&& f) {
         if (want == L) return f(std::integral_constant<int, L>{});
     }
     return hipErrorInvalidValue;
+}
+
+template <int NF, bool GEN>
+static hipError_t launch_line1d_t(int mode, const LaunchArgs& a) {
+    constexpr int N = PSS_LINE_LEN;
+    const dim3 grid(1), block(N / 4);
+    const size_t lds = line1d_lds_bytes(N);
+    uint64_t* ctr = const_cast<uint64_t*>(a.step_ctr);
+#define PSS_L1(M)                                                                                                 \
+    hipLaunchKernelGGL((line1d_kernel<N, NF, GEN, M>), grid, block, lds, a.stream, a.plan, a.bufs, ctr, a.flag, \
+                       a.nsteps, a.advance != 0 ? 1 : 0, a.tw_x)
+    switch (mode) {
+        case MODE_STEP: PSS_L1(MODE_STEP); break;
+        case MODE_FWD_STORE: PSS_L1(MODE_FWD_STORE); break;
+        case MODE_INV_OUT: PSS_L1(MODE_INV_OUT); break;
+        case MODE_INTERM_OUT: PSS_L1(MODE_INTERM_OUT); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef PSS_L1
+    return hipGetLastError();
+}
+
+hipError_t PSS_CAT(launch_line1d_L, PSS_LINE_LEN)(int mode, int nf, const LaunchArgs& a) {
+    if (mode == MODE_FWD_STORE || mode == MODE_INV_OUT) return launch_line1d_t<1, false>(mode, a);
+    const bool gen = a.general || mode == MODE_INTERM_OUT;
+    if (nf <= 1) return gen ? launch_line1d_t<1, true>(mode, a) : launch_line1d_t<1, false>(mode, a);
+    if (nf == 2) return gen ? launch_line1d_t<2, true>(mode, a) : launch_line1d_t<2, false>(mode, a);
+    if (nf <= 4) return gen ? launch_line1d_t<4, true>(mode, a) : launch_line1d_t<4, false>(mode, a);
+    return hipErrorInvalidValue;
+}
+
+hipError_t PSS_CAT(line1d_setup_L, PSS_LINE_LEN)() {
+    constexpr int N = PSS_LINE_LEN;
+    const int lds = static_cast<int>(line1d_lds_bytes(N));
+#define PSS_L1A(NFV, G, M)                                                                                       \
+    if (hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&line1d_kernel<N, NFV, G, M>),          \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds))                     \
+        return e;
+#define PSS_L1B(M) PSS_L1A(1, false, M) PSS_L1A(1, true, M) PSS_L1A(2, false, M) PSS_L1A(2, true, M) \
+    PSS_L1A(4, false, M) PSS_L1A(4, true, M)
+    PSS_L1B(MODE_STEP)
+    PSS_L1B(MODE_INTERM_OUT)
+    PSS_L1A(1, false, MODE_FWD_STORE)
+    PSS_L1A(1, false, MODE_INV_OUT)
+#undef PSS_L1B
+#undef PSS_L1A
+    return hipSuccess;
 }
 
 hipError_t PSS_CAT(launch_update_L, PSS_LINE_LEN)(int mode, int nf, const LaunchArgs& a) {
@@ -2059,6 +2301,8 @@ hipError_t launch_batch_xrow(hipStream_t s, const BatchLaunch& bl, size_t lds) {
 
 #if defined(PSS_COMMON)
 #define PSS_DECL_L(L)                                                               \
+    hipError_t launch_line1d_L##L(int mode, int nf, const LaunchArgs& a);          \
+    hipError_t line1d_setup_L##L();                                                 \
     hipError_t launch_update_L##L(int mode, int nf, const LaunchArgs& a);          \
     hipError_t launch_ypass_L##L(int mode, const YArgs& ya, const LaunchArgs& a);  \
     hipError_t launch_xrow_L##L(int mode, int ng, const LaunchArgs& a);            \
@@ -2077,6 +2321,38 @@ PSS_DECL_L(4096)
 int max_points(int L, int nregs) {
     const int cap = nregs <= 1 ? 16 : (nregs == 2 ? 8 : 4);
     return cap < L ? cap : L;
+}
+
+hipError_t launch_line1d(int mode, int N, int nf, const LaunchArgs& a) {
+    switch (N) {
+        case 8: return launch_line1d_L8(mode, nf, a);
+        case 16: return launch_line1d_L16(mode, nf, a);
+        case 32: return launch_line1d_L32(mode, nf, a);
+        case 64: return launch_line1d_L64(mode, nf, a);
+        case 128: return launch_line1d_L128(mode, nf, a);
+        case 256: return launch_line1d_L256(mode, nf, a);
+        case 512: return launch_line1d_L512(mode, nf, a);
+        case 1024: return launch_line1d_L1024(mode, nf, a);
+        case 2048: return launch_line1d_L2048(mode, nf, a);
+        case 4096: return launch_line1d_L4096(mode, nf, a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t line1d_setup(int N) {
+    switch (N) {
+        case 8: return line1d_setup_L8();
+        case 16: return line1d_setup_L16();
+        case 32: return line1d_setup_L32();
+        case 64: return line1d_setup_L64();
+        case 128: return line1d_setup_L128();
+        case 256: return line1d_setup_L256();
+        case 512: return line1d_setup_L512();
+        case 1024: return line1d_setup_L1024();
+        case 2048: return line1d_setup_L2048();
+        case 4096: return line1d_setup_L4096();
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_update(int mode, int L, int nf, const LaunchArgs& a) {

@@ -183,7 +183,9 @@ struct pss_ctx {
     int64_t steps_taken = 0;
 
     int64_t sites() const { return static_cast<int64_t>(n[0]) * n[1] * n[2]; }
-    int64_t packed() const { return sites() / 2; }  // complex elements per spectral array
+    // complex elements per spectral array: the packed half spectrum in 2D and
+    // 3D, the full spectrum of the line in 1D
+    int64_t packed() const { return ndim == 1 ? sites() : sites() / 2; }
 };
 
 // A set of 2D lattices stepped together.  Lattices with the same sizes,
@@ -310,7 +312,8 @@ void for_each_mode(const pss_ctx* c, F&& fn) {
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < c->n[1]; ++y)
             for (int x = 0; x <= c->n[0] / 2; ++x) {
-                const int k[3] = {x == c->n[0] / 2 ? -x : x, y < c->n[1] / 2 ? y : y - c->n[1],
+                const int ny = c->n[1];
+                const int k[3] = {x == c->n[0] / 2 ? -x : x, ny == 1 ? 0 : (y < ny / 2 ? y : y - ny),
                                   nz == 1 ? 0 : (z < nz / 2 ? z : z - nz)};
                 double q[3];
                 bool nyq[3];
@@ -411,7 +414,8 @@ pss_status build_plan(pss_ctx* c) {
     P.n[2] = c->ndim == 3 ? c->n[2] : 1;
     P.nf = nf;
     for (int i = 0; i < 3; ++i) P.qs[i] = static_cast<float>(2 * M_PI / (P.n[i] * c->dx[i]));
-    if (c->ndim == 2) P.qs[2] = 0.f;
+    if (c->ndim <= 2) P.qs[2] = 0.f;
+    if (c->ndim == 1) P.qs[1] = 0.f;
     P.dt = static_cast<float>(c->dt);
     const double N = static_cast<double>(c->sites());
     const double dV = c->dx[0] * c->dx[1] * (c->ndim == 3 ? c->dx[2] : 1.0);
@@ -597,6 +601,20 @@ pss_status choose_geometry(pss_ctx* c) {
     pss::Geo& g = c->geo;
     g = pss::Geo{};
     g.nz = nz;
+    if (c->ndim == 1) {
+        // one block holds the line, 4 points per thread (no tunable geometry)
+        c->lu = nx;
+        g.tc = 1;
+        g.to = 1;
+        g.pu = g.px = 4;
+        g.ntile = 1;
+        g.nublk = 1;
+        g.nrowblk = 1;
+        g.rb = 2;
+        if (pss::line1d_lds_bytes(nx) > 160 * 1024)
+            return fail(PSS_E_UNSUPPORTED, "line needs more LDS than a workgroup has");
+        return PSS_OK;
+    }
     auto tuned = [&](const char* key, int def) {
         auto it = c->tune.find(key);
         return it == c->tune.end() ? def : static_cast<int>(it->second);
@@ -819,6 +837,7 @@ pss_status materialize(pss_ctx* c) {
     HIP_TRY(hipMalloc(&c->d_tw_y, sizeof(float2) * twy.size()));
     HIP_TRY(hipMemcpy(c->d_tw_y, twy.data(), sizeof(float2) * twy.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->d_plan, &c->plan, sizeof(pss::DevPlan), hipMemcpyHostToDevice));
+    if (c->ndim == 1) HIP_TRY(pss::line1d_setup(c->n[0]));
     HIP_TRY(hipMalloc(&c->d_member_u, sizeof(pss::Member)));
     HIP_TRY(hipMalloc(&c->d_member_x, sizeof(pss::Member)));
     const pss::Member mu = member_u(c), mx = member_x(c);
@@ -835,6 +854,10 @@ pss_status materialize(pss_ctx* c) {
 // update axis, then the real-space products).
 pss_status prologue(pss_ctx* c) {
     const int nf = static_cast<int>(c->fields.size());
+    if (c->ndim == 1) {  // a 1D launch forms its first step's products from the state itself
+        c->dirty = false;
+        return PSS_OK;
+    }
     pss::LaunchArgs a = args(c);
     HIP_TRY(pss::launch_update(pss::MODE_PROLOGUE, c->lu, nf, a));
     if (c->plan.nch > 0) {
@@ -911,6 +934,13 @@ pss_status clear_nonfinite(pss_ctx* c) {
 
 pss_status enqueue_steps(pss_ctx* c, int64_t k) {
     const int nf = static_cast<int>(c->fields.size());
+    if (c->ndim == 1) {  // one launch takes the whole chunk and moves the counter on
+        pss::LaunchArgs a = args(c);
+        a.nsteps = static_cast<int>(k);
+        a.advance = 1;
+        HIP_TRY(pss::launch_line1d(pss::MODE_STEP, c->n[0], nf, a));
+        return PSS_OK;
+    }
     // in 2D the last x kernel of the sequence moves the step counter on
     const bool x_advances = c->ndim == 2 && c->plan.nch > 0;
     for (int64_t i = 0; i < k; ++i) {
@@ -931,6 +961,12 @@ pss_status enqueue_steps(pss_ctx* c, int64_t k) {
 // real-space array on the device (d_real) -> Fourier state of `field`
 pss_status forward_to_state(pss_ctx* c, int field) {
     pss::LaunchArgs a = args(c);
+    if (c->ndim == 1) {
+        a.bufs.real_in = c->d_real;
+        a.bufs.sel = field;
+        HIP_TRY(pss::launch_line1d(pss::MODE_FWD_STORE, c->n[0], 1, a));
+        return PSS_OK;
+    }
     a.bufs.real_in = c->d_real;
     a.bufs.out = c->d_tmp;
     HIP_TRY(pss::launch_xrow(pss::MODE_R2C_IN, c->n[0], 1, a));
@@ -953,6 +989,12 @@ pss_status forward_to_state(pss_ctx* c, int field) {
 // Fourier state of `field` -> real-space array on the device (d_real)
 pss_status state_to_real(pss_ctx* c, int field) {
     pss::LaunchArgs a = args(c);
+    if (c->ndim == 1) {
+        a.bufs.sel = field;
+        a.bufs.real_out = c->d_real;
+        HIP_TRY(pss::launch_line1d(pss::MODE_INV_OUT, c->n[0], 1, a));
+        return PSS_OK;
+    }
     a.bufs.sel = field;
     a.bufs.out = c->d_tmp;
     HIP_TRY(pss::launch_update(pss::MODE_INV_OUT, c->lu, 1, a));
@@ -974,6 +1016,12 @@ pss_status state_to_real(pss_ctx* c, int field) {
 // on the device (d_real)
 pss_status interm_to_real(pss_ctx* c, int i) {
     pss::LaunchArgs a = args(c);
+    if (c->ndim == 1) {
+        a.bufs.sel = i;
+        a.bufs.real_out = c->d_real;
+        HIP_TRY(pss::launch_line1d(pss::MODE_INTERM_OUT, c->n[0], static_cast<int>(c->fields.size()), a));
+        return PSS_OK;
+    }
     a.bufs.sel = i;
     a.bufs.out = c->d_tmp;
     HIP_TRY(pss::launch_update(pss::MODE_INTERM_OUT, c->lu, static_cast<int>(c->fields.size()), a));
@@ -1391,7 +1439,7 @@ const char* pss_last_error(void) { return g_err.c_str(); }
 pss_status pss_lattice_create(pss_ctx** out, int32_t ndim, const int64_t n[3], const double dx[3], double dt) {
     if (!out || !n || !dx) return fail(PSS_E_INVAL, "null argument");
     *out = nullptr;
-    if (ndim != 2 && ndim != 3) return fail(PSS_E_UNSUPPORTED, "ndim must be 2 or 3 (got %d)", ndim);
+    if (ndim < 1 || ndim > 3) return fail(PSS_E_UNSUPPORTED, "ndim must be 1, 2 or 3 (got %d)", ndim);
     if (!(dt > 0) || !std::isfinite(dt)) return fail(PSS_E_INVAL, "dt must be positive");
     int64_t total = 1;
     for (int i = 0; i < ndim; ++i) {
@@ -1687,7 +1735,14 @@ pss_status pss_spectrum_download(pss_ctx* c, int32_t field, float* half, int32_t
     HIP_TRY(hipStreamSynchronize(c->stream));
     const size_t nout = static_cast<size_t>(c->n[1]) * (c->ndim == 3 ? c->n[2] : 1) * (c->n[0] / 2 + 1) * 2;
     std::vector<float> h(nout);
-    unpack_half(c, S, h.data());
+    if (c->ndim == 1) {  // modes 0 .. Nx/2 of the full spectrum
+        for (int k = 0; k <= c->n[0] / 2; ++k) {
+            h[2 * k] = S[k].x;
+            h[2 * k + 1] = S[k].y;
+        }
+    } else {
+        unpack_half(c, S, h.data());
+    }
     if (on_device) {
         HIP_TRY(hipMemcpy(half, h.data(), sizeof(float) * nout, hipMemcpyHostToDevice));
     } else {
@@ -1821,7 +1876,8 @@ pss_status pss_structure_factor(pss_ctx* c, int32_t field, double* S, int64_t* c
     int fd = 0;
     if (pss_status s = dyn_field(c, field, &fd)) return s;
     if (pss_status s_bw = begin_work(c)) return s_bw;
-    const int nmin = c->ndim == 3 ? std::min(std::min(c->n[0], c->n[1]), c->n[2]) : std::min(c->n[0], c->n[1]);
+    const int nmin = c->ndim == 3 ? std::min(std::min(c->n[0], c->n[1]), c->n[2])
+                                  : (c->ndim == 2 ? std::min(c->n[0], c->n[1]) : c->n[0]);
     const int ns = nmin / 2;  // shells j = 1 .. ns-1
     if (n_shells != ns - 1) return fail(PSS_E_INVAL, "n_shells must be %d", ns - 1);
     if (!c->d_shell_sum) {
@@ -1853,7 +1909,8 @@ pss_status pss_structure_factor_noalloc(pss_ctx* c, int32_t field, double* S, in
     int fd = 0;
     if (pss_status s = dyn_field(c, field, &fd)) return s;
     if (pss_status s_bw = begin_work(c)) return s_bw;
-    const int nmin = c->ndim == 3 ? std::min(std::min(c->n[0], c->n[1]), c->n[2]) : std::min(c->n[0], c->n[1]);
+    const int nmin = c->ndim == 3 ? std::min(std::min(c->n[0], c->n[1]), c->n[2])
+                                  : (c->ndim == 2 ? std::min(c->n[0], c->n[1]) : c->n[0]);
     const int ns = nmin / 2;  // shells j = 1 .. ns-1
     if (n_shells != ns - 1) return fail(PSS_E_INVAL, "n_shells must be %d", ns - 1);
     if (ns > pss::kScratchShells)
@@ -1891,7 +1948,7 @@ pss_status pss_util_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, u
 pss_status pss_kernels_per_step(pss_ctx* c, int32_t* count) {
     if (pss_status s = check_ctx(c)) return s;
     if (!count) return fail(PSS_E_INVAL, "null output");
-    *count = c->ndim == 3 ? 4 : 2;
+    *count = c->ndim == 3 ? 4 : (c->ndim == 2 ? 2 : 1);
     return PSS_OK;
 }
 
@@ -1909,8 +1966,12 @@ pss_status pss_kernel_bytes(pss_ctx* c, int32_t which, double* bytes) {
         vbytes += 8.0 * tiles * tc * lines;
     }
     const int nf = static_cast<int>(c->fields.size());
-    const int nk = c->ndim == 3 ? 4 : 2;
+    const int nk = c->ndim == 3 ? 4 : (c->ndim == 2 ? 2 : 1);
     if (which < 0 || which >= nk) return fail(PSS_E_INVAL, "kernel %d does not exist on this lattice", which);
+    if (c->ndim == 1) {  // a one-step launch: every state in and out once
+        *bytes = 2 * arr * nf;
+        return PSS_OK;
+    }
     switch (which) {
         case 0: *bytes = arr * (P.nch + 2 * nf) + vbytes; break;  // channels in, state in/out, factors out
         case 1: *bytes = vbytes + arr * P.nch; break;             // factors in, channels out
@@ -1925,7 +1986,7 @@ pss_status pss_time_kernel(pss_ctx* c, int32_t which, int32_t reps, double* ms, 
     if (!ms || reps < 1) return fail(PSS_E_INVAL, "bad arguments");
     if (pss_status s = materialize(c)) return s;
     if (pss_status s_bw = begin_work(c)) return s_bw;
-    const int nk = c->ndim == 3 ? 4 : 2;
+    const int nk = c->ndim == 3 ? 4 : (c->ndim == 2 ? 2 : 1);
     if (which < 0 || which >= nk) return fail(PSS_E_INVAL, "kernel %d does not exist on this lattice", which);
     // the x kernel and the y passes run only for models with real-space products
     if ((which == 1 || which == 3) && c->plan.nch == 0)
@@ -1941,7 +2002,12 @@ pss_status pss_time_kernel(pss_ctx* c, int32_t which, int32_t reps, double* ms, 
     pss::LaunchArgs a = args(c);
     const pss::LaunchArgs ax = xargs(c);
     HIP_TRY(hipEventRecord(e0, c->stream));
+    a.nsteps = 1;  // 1D: one-step launches that leave the counter
     for (int r = 0; r < reps; ++r) {
+        if (c->ndim == 1) {
+            HIP_TRY(pss::launch_line1d(pss::MODE_STEP, c->n[0], nf, a));
+            continue;
+        }
         switch (which) {
             case 0: HIP_TRY(pss::launch_update(pss::MODE_STEP, c->lu, nf, a)); break;
             case 1: HIP_TRY(pss::launch_xrow(pss::MODE_STEP, c->n[0], c->plan.ng, ax)); break;
@@ -1959,7 +2025,7 @@ pss_status pss_time_kernel(pss_ctx* c, int32_t which, int32_t reps, double* ms, 
     c->dirty = true;  // the channel arrays no longer match the state
     ++c->state_gen;   // repeated step launches changed the state
     static const char* names[4] = {"update_kernel", "xrow_kernel", "ypass_kernel(inverse)", "ypass_kernel(forward)"};
-    if (name) *name = names[which];
+    if (name) *name = c->ndim == 1 ? "line1d_kernel" : names[which];
     return PSS_OK;
 }
 
@@ -1968,6 +2034,10 @@ pss_status pss_autotune(pss_ctx* c, int32_t reps, double* us_per_step) {
     if (c->planned) return fail(PSS_E_STATE, "autotune before the plan is built (first upload, init or step)");
     if (reps < 1) return fail(PSS_E_INVAL, "reps must be >= 1");
     if (pss_status s = validate(c)) return s;
+    if (c->ndim == 1) {  // a 1D lattice has no launch geometry to choose
+        if (us_per_step) *us_per_step = 0.0;
+        return PSS_OK;
+    }
     using Tune = std::map<std::string, int64_t>;
     // one process-wide cache entry per lattice shape and term structure
     static std::map<std::string, std::pair<Tune, double>> cache;

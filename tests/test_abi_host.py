@@ -240,3 +240,18 @@ def test_noalloc_reduction_needs_a_built_plan():
     S = (ctypes.c_double * 31)()
     cnt = (ctypes.c_int64 * 31)()
     assert lib.pss_structure_factor_noalloc(None, 0, S, cnt, 31) == -1
+
+
+def test_one_dimensional_lattices_on_host():
+    lat = pss.Lattice((256,), dx=(0.5,), dt=0.01)
+    f, _ = pss.model_b(lat)
+    lat.validate()
+    assert lat.shape == (256,)
+    # KPZ in 1D has a single gradient intermediate
+    k = pss.Lattice((64,), dt=0.01)
+    f, grads = pss.kpz(k)
+    assert len(grads) == 1
+    k.validate()
+    with pytest.raises(PssError) as e:
+        pss.Lattice((100,), dt=0.01)
+    assert e.value.name == "PSS_E_UNSUPPORTED"
