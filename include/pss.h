@@ -160,6 +160,21 @@ pss_status pss_term_set_coef(pss_ctx *ctx, int32_t term_id, int32_t mono, double
 pss_status pss_noise_set(pss_ctx *ctx, int32_t field, const pss_qmono *D_of_q,
                          int32_t n_mono);
 
+/* Boundary frame (Sec. "Callback functions": a field held at fixed values on
+ * a band of sites, the buffer zone that imposes a boundary condition on a
+ * periodic lattice).  After the update of every step, the real space of
+ * dynamic field `field` (the real part of its inverse transform) takes
+ * values[i] at linear site sites[i] = (z*Ny + y)*Nx + x, i < n, and the
+ * field is transformed back; the next step starts from that state.  n = 0
+ * removes the field's frame.  Arrays are host memory, copied.  In 1D the
+ * frame is applied inside the step launch; in 2D and 3D it adds a pass
+ * through real space and a rebuild of the channel arrays after every step.
+ * Errors: PSS_E_INVAL (an intermediate field, a site off the lattice, a
+ * non-finite value), PSS_E_STATE (while a batch or an adjoint tape holds the
+ * lattice).  Lattices with frames take part in neither batches nor the
+ * adjoint (PSS_E_UNSUPPORTED there). */
+pss_status pss_frame_set(pss_ctx *ctx, int32_t field, const int64_t *sites, const float *values, int64_t n);
+
 /* 64-bit seed of the Philox4x32-10 noise (Salmon et al. SC'11).  The noise of
  * mode k of field f at step n is keyed by counter (c(k), n, f, 0) with key
  * (low, high) words of the seed, where c(k) = min(L(k), L(-k)) and L is the

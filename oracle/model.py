@@ -55,6 +55,12 @@ Readings of points the paper leaves open:
   and a self-conjugate mode takes sqrt(N) g1.  The Philox counter is
   (c(k), step, field, 0) with the 64-bit seed as key.
 * Real space is the real part of the inverse transform.
+* Boundary frames (Sec. "Callback functions": a field is held at fixed
+  values on a band of sites by setting its real-space values at the end of
+  every step).  Read as: after the update of a step, the field's real space
+  (the real part of its inverse transform) takes the frame values on the
+  frame sites and the field is transformed back; the next step starts from
+  that state.
 * Initial fields "uniform in [lo, hi)" take u0 of Philox counter
   (site, 0, field, 1) and set phi = float32(lo + (hi - lo) u0), i.e. the FP64
   value rounded once to binary32, so FP32 and FP64 runs start identically.
@@ -99,6 +105,7 @@ class Model:
         self.terms = []
         self.noise = {}
         self.state = []
+        self.frames = {}
         self.step_index = 0
         self._cache = None
 
@@ -119,6 +126,23 @@ class Model:
         self.terms.append(t)
         self._cache = None
         return len(self.terms) - 1
+
+    def set_frame(self, field, sites, values):
+        """Hold `field` at `values` on the linear site indices `sites` after
+        every step (a boundary frame)."""
+        if not self.dynamic[int(field)]:
+            raise ValueError("an intermediate field has no frame")
+        sites = np.asarray(sites, dtype=np.int64).reshape(-1)
+        values = np.asarray(values, dtype=np.float64).reshape(-1)
+        if sites.shape != values.shape or np.any(sites < 0) or np.any(sites >= self.lat.N):
+            raise ValueError("frame sites and values must match and lie on the lattice")
+        self.frames[int(field)] = (sites, values)
+
+    def _apply_frames(self):
+        for f, (sites, values) in self.frames.items():
+            x = ifftn(self.state[f]).real.reshape(-1)
+            x[sites] = values
+            self.state[f] = fftn(x.reshape(self.lat.shape).astype(np.complex128))
 
     def set_noise(self, field, op):
         if not self.dynamic[int(field)]:
@@ -265,6 +289,7 @@ class Model:
                     acc = acc + c["sigma"][f] * self.noise_hat(f, n)
                 new.append(acc / c["denom"][f])
             self.state = new
+            self._apply_frames()
             self.step_index += 1
 
     # -- convenience ------------------------------------------------------
@@ -274,6 +299,7 @@ class Model:
         m.dynamic = list(self.dynamic)
         m.terms = list(self.terms)
         m.noise = dict(self.noise)
+        m.frames = dict(self.frames)
         m.state = [None if s is None else s.copy() for s in self.state]
         m.step_index = self.step_index
         return m

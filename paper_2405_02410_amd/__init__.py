@@ -63,6 +63,7 @@ _SIGS = {
                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                      ctypes.POINTER(ctypes.c_int32)],
     "pss_term_set_coef": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double],
+    "pss_frame_set": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64],
     "pss_noise_set": [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(_QMono), ctypes.c_int32],
     "pss_seed_set": [ctypes.c_void_p, ctypes.c_uint64],
     "pss_dealias_set": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32],
@@ -215,6 +216,16 @@ class Lattice:
     def noise(self, field, op):
         arr, nm = _monos(op)
         _check(lib().pss_noise_set(self._h, int(field), arr, nm))
+
+    def frame(self, field, sites, values):
+        """Hold `field` at `values` on the linear real-space sites `sites`
+        after every step (a boundary frame); empty arrays remove it."""
+        st = np.ascontiguousarray(np.asarray(sites, dtype=np.int64).reshape(-1))
+        vs = np.ascontiguousarray(np.asarray(values, dtype=np.float32).reshape(-1))
+        if st.shape != vs.shape:
+            raise PssError(-1, "frame sites and values differ in length")
+        _check(lib().pss_frame_set(self._h, int(field), st.ctypes.data_as(ctypes.c_void_p),
+                                   vs.ctypes.data_as(ctypes.c_void_p), int(st.size)))
 
     def seed(self, seed):
         _check(lib().pss_seed_set(self._h, int(seed) & 0xFFFFFFFFFFFFFFFF))

@@ -196,9 +196,11 @@ hipError_t launch_update(int mode, int L, int nf, const LaunchArgs& a);
 // real_out), MODE_INTERM_OUT (intermediate sel -> real_out).  The state of a
 // field is its full complex spectrum of N modes in natural order.
 hipError_t launch_line1d(int mode, int N, int nf, const LaunchArgs& a);
-// LDS of the 1D kernel: the line transform and the twiddle table
+// LDS of the 1D kernel: the line transform, the twiddle table and a
+// real-space staging line for the boundary frames
 inline size_t line1d_lds_bytes(int N) {
-    return sizeof(float2) * (static_cast<size_t>(fft_lds_elems(N, 4, 1)) + static_cast<size_t>(N));
+    return sizeof(float2) * (static_cast<size_t>(fft_lds_elems(N, 4, 1)) + static_cast<size_t>(N)) +
+           sizeof(float) * static_cast<size_t>(N);
 }
 // allow the 1D kernels of length N their LDS (above the default dynamic limit)
 hipError_t line1d_setup(int N);
@@ -216,6 +218,8 @@ hipError_t launch_advance_many(hipStream_t s, uint64_t* const* ctrs, int n, int6
 // out[i] = the non-finite flag word after *ctrs[i] (the word after the step
 // counter), cleared atomically
 hipError_t launch_take_flags(hipStream_t s, uint64_t* const* ctrs, int n, uint32_t* out);
+// real[frame[i].x] = value bits frame[i].y, i < n (a boundary frame on a real-space array)
+hipError_t launch_apply_frame(hipStream_t s, float* real, const int2* frame, int n);
 hipError_t launch_init_uniform(hipStream_t s, float* out, int64_t n, uint32_t field, uint32_t key0, uint32_t key1,
                                double lo, double hi);
 hipError_t launch_philox(hipStream_t s, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,

@@ -1360,6 +1360,16 @@ __global__ void advance_many_kernel(uint64_t* const* __restrict__ ctrs, int n, i
     if (i < n) *ctrs[i] += static_cast<uint64_t>(k);
 }
 
+// a boundary frame on a real-space array: site frame[i].x takes the value
+// whose bits are frame[i].y
+__global__ void apply_frame_kernel(float* __restrict__ real, const int2* __restrict__ frame, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const int2 e = frame[i];
+        real[e.x] = __int_as_float(e.y);
+    }
+}
+
 // read and clear the non-finite flag that follows each member's step counter
 __global__ void take_flags_kernel(uint64_t* const* __restrict__ ctrs, int n, uint32_t* __restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1503,6 +1513,7 @@ __global__ void __launch_bounds__(N / 4 < 64 ? 64 : N / 4)
     ld.blk1 = smem + 2 * FFT::kReg;
     ld.par = 0;
     float2* const twl = smem + FFT::kLds;
+    float* const xst = reinterpret_cast<float*>(twl + N);  // real-space staging of the frames
     for (int i = t; i < N; i += T) twl[i] = tw_g[i];
     __syncthreads();
     const float2* tw = twl;
@@ -1650,9 +1661,39 @@ __global__ void __launch_bounds__(N / 4 < 64 ? 64 : N / 4)
                 float2 r = cadd(s[f][m], cscale(acc[f][m], p.dt));
                 if (noisy) r = cadd(r, noise_mode<GEN>(p, f, step, lin[m], lneg[m], q[m]));
                 s[f][m] = cmul(r, cinv_implicit(p.dt, eval_op<GEN>(p.implicit_op[f], q[m])));
-                if (!(__builtin_isfinite(s[f][m].x) && __builtin_isfinite(s[f][m].y))) bad |= 1u << f;
             }
         }
+        // boundary frames: the new state's real space takes the frame values
+        // on the frame sites (staged through LDS), then is transformed back
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if (f >= p.nf || p.nframe[f] == 0) continue;
+            float2 v[P];
+#pragma unroll
+            for (int m = 0; m < P; ++m) v[m] = s[f][m];
+            FFT::template dit<1>(v, ld, t, tw);
+#pragma unroll
+            for (int m = 0; m < P; ++m) xst[t + m * T] = v[m].x * p.inv_n;
+            __syncthreads();
+            const int2* __restrict__ fr = p.frame[f];
+            for (int i = t; i < p.nframe[f]; i += T) {
+                const int2 e = fr[i];
+                xst[e.x] = __int_as_float(e.y);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < P; ++m) v[m] = make_float2(xst[t + m * T], 0.f);
+            __syncthreads();  // the staging line is free again
+            FFT::template dif<-1>(v, ld, t, tw);
+#pragma unroll
+            for (int m = 0; m < P; ++m) s[f][m] = v[m];
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+            if (f < p.nf)
+#pragma unroll
+                for (int m = 0; m < P; ++m)
+                    if (!(__builtin_isfinite(s[f][m].x) && __builtin_isfinite(s[f][m].y))) bad |= 1u << f;
         if (sn + 1 < nsteps) channels();  // the next launch forms its first step's anew
     }
 #pragma unroll
@@ -2435,6 +2476,12 @@ hipError_t launch_advance(hipStream_t s, uint64_t* step_ctr, int64_t k) {
 hipError_t launch_advance_many(hipStream_t s, uint64_t* const* ctrs, int n, int64_t k) {
     if (n < 1) return hipSuccess;
     hipLaunchKernelGGL(advance_many_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ctrs, n, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_frame(hipStream_t s, float* real, const int2* frame, int n) {
+    if (n < 1) return hipSuccess;
+    hipLaunchKernelGGL(apply_frame_kernel, dim3((n + 255) / 256), dim3(256), 0, s, real, frame, n);
     return hipGetLastError();
 }
 

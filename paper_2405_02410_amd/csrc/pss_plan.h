@@ -21,6 +21,7 @@
 #pragma once
 
 #include <stdint.h>
+#include <hip/hip_runtime.h>
 
 #define PSS_MAXF 4    // fields
 #define PSS_MAXM 8    // monomials per operator
@@ -111,6 +112,10 @@ struct DevPlan {
     int32_t general;  // some operator has 1/|q| or i q_i monomials (general list), or ni > 0
     int32_t ni;
     DevInterm interm[PSS_MAXI];
+    // boundary frames: after every step field f takes value[i] at site[i] of
+    // real space (x fastest), i < nframe[f]; entries (site, value bits)
+    const int2* frame[PSS_MAXF];
+    int32_t nframe[PSS_MAXF];
 };
 
 }  // namespace pss

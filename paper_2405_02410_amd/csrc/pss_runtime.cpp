@@ -147,6 +147,7 @@ struct pss_ctx {
     std::vector<std::string> interms;   // intermediate fields (names)
     std::vector<int> ids;               // declared field -> internal code
     std::vector<Term> terms;            // fields named by internal code
+    std::vector<std::vector<int2>> frames;  // boundary frames per dynamic field: (site, value bits)
 
     // device side
     bool planned = false;
@@ -167,6 +168,7 @@ struct pss_ctx {
     float2* d_tmp = nullptr;
     float2* d_tmp2 = nullptr;
     float* d_real = nullptr;
+    int2* d_frame[PSS_MAXF] = {};  // device copies of the frames
     double* d_shell_sum = nullptr;
     unsigned long long* d_shell_cnt = nullptr;
     // one-entry member tables of the step kernels (update kernel, x kernel)
@@ -580,6 +582,11 @@ pss_status build_plan(pss_ctx* c) {
     for (int d = 0; d < P.nd; ++d) P.general |= P.direct[d].op.n > 0;
     for (int k = 0; k < P.nch; ++k) P.general |= P.ch[k].op.n > 0;
     P.general |= ni > 0;  // intermediates are evaluated by the general-operator code
+    for (int f = 0; f < nf; ++f) {  // boundary frames already on the device
+        P.frame[f] = c->d_frame[f];
+        P.nframe[f] = c->d_frame[f] && f < static_cast<int>(c->frames.size())
+                          ? static_cast<int32_t>(c->frames[f].size()) : 0;
+    }
     return PSS_OK;
 }
 
@@ -709,6 +716,7 @@ void free_device(pss_ctx* c) {
     rel(c->d_shell_cnt);
     rel(c->d_member_u);
     rel(c->d_member_x);
+    for (auto*& p : c->d_frame) rel(p);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     c->stream = nullptr;
     c->own_stream = false;
@@ -779,6 +787,30 @@ hipError_t y_forward_channels(pss_ctx* c) {
     return pss::launch_ypass(pss::MODE_YFWD, c->n[1], ya, args(c));
 }
 
+bool has_frames(const pss_ctx* c) {
+    for (const auto& fr : c->frames)
+        if (!fr.empty()) return true;
+    return false;
+}
+
+// copy every field's frame to the device and point the plan at it (the
+// caller uploads the plan)
+pss_status upload_frames(pss_ctx* c) {
+    for (int f = 0; f < PSS_MAXF; ++f) {
+        if (c->d_frame[f]) (void)hipFree(c->d_frame[f]);
+        c->d_frame[f] = nullptr;
+        c->plan.frame[f] = nullptr;
+        c->plan.nframe[f] = 0;
+        if (f >= static_cast<int>(c->frames.size()) || c->frames[f].empty()) continue;
+        const auto& fr = c->frames[f];
+        HIP_TRY(hipMalloc(&c->d_frame[f], sizeof(int2) * fr.size()));
+        HIP_TRY(hipMemcpy(c->d_frame[f], fr.data(), sizeof(int2) * fr.size(), hipMemcpyHostToDevice));
+        c->plan.frame[f] = c->d_frame[f];
+        c->plan.nframe[f] = static_cast<int32_t>(fr.size());
+    }
+    return PSS_OK;
+}
+
 pss_status upload_plan(pss_ctx* c) {
     HIP_TRY(hipStreamSynchronize(c->stream));
     HIP_TRY(hipMemcpy(c->d_plan, &c->plan, sizeof(pss::DevPlan), hipMemcpyHostToDevice));
@@ -836,6 +868,7 @@ pss_status materialize(pss_ctx* c) {
     const auto twy = twiddles(c->n[1]);
     HIP_TRY(hipMalloc(&c->d_tw_y, sizeof(float2) * twy.size()));
     HIP_TRY(hipMemcpy(c->d_tw_y, twy.data(), sizeof(float2) * twy.size(), hipMemcpyHostToDevice));
+    if (pss_status s = upload_frames(c)) return s;
     HIP_TRY(hipMemcpy(c->d_plan, &c->plan, sizeof(pss::DevPlan), hipMemcpyHostToDevice));
     if (c->ndim == 1) HIP_TRY(pss::line1d_setup(c->n[0]));
     HIP_TRY(hipMalloc(&c->d_member_u, sizeof(pss::Member)));
@@ -932,6 +965,9 @@ pss_status clear_nonfinite(pss_ctx* c) {
     return PSS_OK;
 }
 
+pss_status state_to_real(pss_ctx* c, int field);
+pss_status forward_to_state(pss_ctx* c, int field);
+
 pss_status enqueue_steps(pss_ctx* c, int64_t k) {
     const int nf = static_cast<int>(c->fields.size());
     if (c->ndim == 1) {  // one launch takes the whole chunk and moves the counter on
@@ -952,6 +988,18 @@ pss_status enqueue_steps(pss_ctx* c, int64_t k) {
             ax.advance = (x_advances && i == k - 1) ? k : 0;
             HIP_TRY(pss::launch_xrow(pss::MODE_STEP, c->n[0], c->plan.ng, ax));
             if (c->ndim == 3) HIP_TRY(y_forward_channels(c));
+        }
+        if (has_frames(c)) {
+            // boundary frames: each framed field through real space, then the
+            // factors and channels of the next step from the framed state
+            for (int f = 0; f < nf; ++f) {
+                if (f >= static_cast<int>(c->frames.size()) || c->frames[f].empty()) continue;
+                if (pss_status s = state_to_real(c, f)) return s;
+                HIP_TRY(pss::launch_apply_frame(c->stream, c->d_real, c->d_frame[f],
+                                                static_cast<int>(c->frames[f].size())));
+                if (pss_status s = forward_to_state(c, f)) return s;
+            }
+            if (pss_status s = prologue(c)) return s;
         }
     }
     if (!x_advances) HIP_TRY(pss::launch_advance(c->stream, c->d_step, k));
@@ -1589,6 +1637,35 @@ pss_status pss_noise_set(pss_ctx* c, int32_t field, const pss_qmono* D, int32_t 
     return upload_plan(c);
 }
 
+pss_status pss_frame_set(pss_ctx* c, int32_t field, const int64_t* sites, const float* values, int64_t n) {
+    if (pss_status s = check_ctx(c)) return s;
+    int fd = 0;
+    if (pss_status s = dyn_field(c, field, &fd)) return s;
+    if (n < 0 || (n > 0 && (!sites || !values))) return fail(PSS_E_INVAL, "bad frame arrays");
+    if (n > c->sites()) return fail(PSS_E_INVAL, "more frame sites than lattice sites");
+    if (c->batches > 0) return fail(PSS_E_STATE, "a batch holds this lattice (batched steps apply no frames)");
+    if (c->tapes > 0) return fail(PSS_E_STATE, "an adjoint tape holds this lattice");
+    std::vector<int2> fr(static_cast<size_t>(n));
+    for (int64_t i = 0; i < n; ++i) {
+        if (sites[i] < 0 || sites[i] >= c->sites()) return fail(PSS_E_INVAL, "frame site %lld off the lattice",
+                                                                  static_cast<long long>(sites[i]));
+        if (!std::isfinite(values[i])) return fail(PSS_E_INVAL, "non-finite frame value");
+        int bits;
+        std::memcpy(&bits, &values[i], sizeof(bits));
+        fr[static_cast<size_t>(i)] = make_int2(static_cast<int>(sites[i]), bits);
+    }
+    if (c->frames.size() < c->fields.size()) c->frames.resize(c->fields.size());
+    c->frames[fd] = std::move(fr);
+    if (!c->planned) return PSS_OK;
+    // on the device now; the step sequence changes in 2D and 3D
+    if (pss_status s = begin_work(c)) return s;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    if (pss_status s = upload_frames(c)) return s;
+    return upload_plan(c);
+}
+
 pss_status pss_seed_set(pss_ctx* c, uint64_t seed) {
     if (pss_status s = check_ctx(c)) return s;
     c->seed = seed;
@@ -2136,7 +2213,7 @@ pss_status pss_adjoint_model_b_forward(pss_ctx* c, int64_t nsteps, int32_t ckpt_
     // recognise Model B: one field; implicit -(a q^2 + k q^4); explicit -b q^2 F[phi^3]; noise D q^2
     double a = 0, b = 0, k = 0, D = 0;
     {
-        bool ok = c->fields.size() == 1 && c->interms.empty() && c->terms.size() == 2;
+        bool ok = c->fields.size() == 1 && c->interms.empty() && c->terms.size() == 2 && !has_frames(c);
         int nimp = 0, ncub = 0;
         for (const Term& t : c->terms) {
             if (!ok) break;
@@ -2388,6 +2465,8 @@ pss_status pss_batch_create(pss_batch** out, pss_ctx* const* lattices, int32_t n
     for (int32_t i = 0; i < n; ++i) {
         if (!lattices[i]) return fail(PSS_E_INVAL, "lattice %d is null", i);
         if (lattices[i]->ndim != 2) return fail(PSS_E_UNSUPPORTED, "lattice %d: batches hold 2D lattices only", i);
+        if (has_frames(lattices[i]))
+            return fail(PSS_E_UNSUPPORTED, "lattice %d has boundary frames, which batched steps do not apply", i);
         for (int32_t j = 0; j < i; ++j)
             if (lattices[j] == lattices[i]) return fail(PSS_E_INVAL, "lattice %d appears twice", i);
     }

@@ -255,3 +255,21 @@ def test_one_dimensional_lattices_on_host():
     with pytest.raises(PssError) as e:
         pss.Lattice((100,), dt=0.01)
     assert e.value.name == "PSS_E_UNSUPPORTED"
+
+
+def test_frame_arguments_on_host():
+    lat = _lat((16, 16))
+    f = lat.field("phi")
+    g = lat.field("psi", dynamic=False)
+    lat.term(g, [Mono(1.0, q2=1)], [(f, 1)])
+    lat.frame(f, [0, 255], [1.0, 2.0])
+    lat.frame(f, [], [])
+    with pytest.raises(PssError) as e:
+        lat.frame(g, [0], [1.0])
+    assert e.value.name == "PSS_E_INVAL"
+    with pytest.raises(PssError):
+        lat.frame(f, [256], [1.0])  # off the lattice
+    with pytest.raises(PssError):
+        lat.frame(f, [3], [float("nan")])
+    with pytest.raises(PssError):
+        lat.frame(f, [1, 2], [1.0])
