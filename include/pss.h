@@ -145,6 +145,13 @@ pss_status pss_term_add(pss_ctx *ctx, int32_t target_field, int32_t implicit,
                         const int32_t *factor_fields, const int32_t *factor_powers,
                         int32_t n_factors, int32_t *term_id);
 
+/* Read back term `term_id` as added: its target, implicit flag, operator
+ * (op receives *n_mono monomials; pass room for 8) and factors (room for 4);
+ * every pointer may be NULL.  pss_term_count gives the number of terms. */
+pss_status pss_term_info(pss_ctx *ctx, int32_t term_id, int32_t *target, int32_t *implicit, pss_qmono *op,
+                         int32_t *n_mono, int32_t *factor_fields, int32_t *factor_powers, int32_t *n_factors);
+pss_status pss_term_count(pss_ctx *ctx, int32_t *count);
+
 /* Change the coefficient of monomial `mono` of term `term_id`.  Allowed at
  * any time; takes effect at the next step (stream-ordered).  Re-checks
  * stability: PSS_E_UNSTABLE leaves the old value in place. */
@@ -159,6 +166,44 @@ pss_status pss_term_set_coef(pss_ctx *ctx, int32_t term_id, int32_t mono, double
  * returns PSS_E_STATE. */
 pss_status pss_noise_set(pss_ctx *ctx, int32_t field, const pss_qmono *D_of_q,
                          int32_t n_mono);
+
+/* ---- equation front end ------------------------------------------------ */
+
+/* Named parameter for equation strings (Sec. "Writing models",
+ * addParameter): a finite value, substituted when an equation or a noise
+ * prefactor that names it is added (later changes do not reach terms already
+ * added; pss_term_set_coef does).  Names follow the field-name rules. */
+pss_status pss_param_set(pss_ctx *ctx, const char *name, double value);
+pss_status pss_param_get(pss_ctx *ctx, const char *name, double *value);
+
+/* The declaration index of the field called `name` and whether it is dynamic
+ * (either pointer may be NULL); PSS_E_INVAL if there is none. */
+pss_status pss_field_find(pss_ctx *ctx, const char *name, int32_t *field_id, int32_t *dynamic);
+
+/* Add the terms of one equation written as in Sec. "Writing models":
+ *   "dt phi + (a*q^2 + k*q^4)*phi = -b*q^2*phi^3"   (dynamic field phi)
+ *   "psi + psi*q^2 = -q^2*phi"                        (intermediate field psi)
+ * "dt NAME" opens the equation of a dynamic field, a bare NAME that of an
+ * intermediate field (it must have been declared so).  After the field, the
+ * left-hand side may hold terms linear in it, each "operator * field"
+ * (implicit terms; moved to the right-hand side with the opposite sign); the
+ * right-hand side is a sum of products of numbers, parameters, fields with
+ * integer powers, the keywords q^2n ((-laplacian)^n), iqx, iqy, iqz (the
+ * derivatives) and "/q" (1/|q|), and parenthesised sums, each factor joined
+ * by '*' (Sec. "Reserved keywords").  Monomials with equal field factors are
+ * gathered into one term (up to 8 monomials a term).  *first_term and
+ * *n_terms (either may be NULL) receive the id of the first term added and
+ * the number added (ids are consecutive).  Errors: PSS_E_INVAL (syntax, an
+ * unknown name, a non-linear left-hand side, 'dt' on an intermediate field
+ * or its absence on a dynamic one; the message gives the position),
+ * PSS_E_UNSUPPORTED (a term without fields), and those of pss_term_add.  A
+ * failure in pss_term_add can leave earlier terms of the equation added. */
+pss_status pss_equation_add(pss_ctx *ctx, const char *equation, int32_t *first_term, int32_t *n_terms);
+
+/* Noise of `field` from a prefactor string, e.g. "D*q^2" (Sec. "Adding
+ * noise", addNoise): numbers, parameters, q^2n and /q only; then as
+ * pss_noise_set. */
+pss_status pss_noise_expr(pss_ctx *ctx, int32_t field, const char *expr);
 
 /* Boundary frame (Sec. "Callback functions": a field held at fixed values on
  * a band of sites, the buffer zone that imposes a boundary condition on a

@@ -64,6 +64,16 @@ _SIGS = {
                      ctypes.POINTER(ctypes.c_int32)],
     "pss_term_set_coef": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double],
     "pss_frame_set": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64],
+    "pss_param_set": [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_double],
+    "pss_param_get": [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double)],
+    "pss_field_find": [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+    "pss_equation_add": [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
+                         ctypes.POINTER(ctypes.c_int32)],
+    "pss_noise_expr": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p],
+    "pss_term_info": [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                      ctypes.POINTER(_QMono), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+    "pss_term_count": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)],
     "pss_noise_set": [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(_QMono), ctypes.c_int32],
     "pss_seed_set": [ctypes.c_void_p, ctypes.c_uint64],
     "pss_dealias_set": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32],
@@ -216,6 +226,45 @@ class Lattice:
     def noise(self, field, op):
         arr, nm = _monos(op)
         _check(lib().pss_noise_set(self._h, int(field), arr, nm))
+
+    # -- equation front end (Sec. "Writing models") -------------------
+    def param(self, name, value):
+        """Named parameter for equation strings (addParameter)."""
+        _check(lib().pss_param_set(self._h, name.encode(), float(value)))
+
+    def field_id(self, name):
+        """Declaration index of the field called `name`."""
+        fid = ctypes.c_int32()
+        _check(lib().pss_field_find(self._h, name.encode(), ctypes.byref(fid), None))
+        return fid.value
+
+    def equation(self, text):
+        """Add the terms of an equation string such as
+        "dt phi + (a*q^2 + k*q^4)*phi = -b*q^2*phi^3"; returns the ids of the
+        terms added."""
+        first, n = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().pss_equation_add(self._h, text.encode(), ctypes.byref(first), ctypes.byref(n)))
+        return list(range(first.value, first.value + n.value))
+
+    def noise_expr(self, field, expr):
+        """Noise of `field` from a prefactor string such as "D*q^2" (addNoise)."""
+        _check(lib().pss_noise_expr(self._h, int(field), expr.encode()))
+
+    def terms(self):
+        """Every term as added: (target, implicit, [Mono], [(field, power)])."""
+        n = ctypes.c_int32()
+        _check(lib().pss_term_count(self._h, ctypes.byref(n)))
+        out = []
+        for t in range(n.value):
+            tgt, imp, nm, nf = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            ops = (_QMono * 8)()
+            ff = (ctypes.c_int32 * 4)()
+            fp = (ctypes.c_int32 * 4)()
+            _check(lib().pss_term_info(self._h, t, ctypes.byref(tgt), ctypes.byref(imp), ops, ctypes.byref(nm),
+                                       ff, fp, ctypes.byref(nf)))
+            monos = [Mono(ops[i].coef, ops[i].q2_pow, ops[i].invq_pow, tuple(ops[i].iq_pow)) for i in range(nm.value)]
+            out.append((tgt.value, bool(imp.value), monos, [(ff[i], fp[i]) for i in range(nf.value)]))
+        return out
 
     def frame(self, field, sites, values):
         """Hold `field` at `values` on the linear real-space sites `sites`

@@ -67,10 +67,13 @@ def build(jobs=None, verbose=False):
     o = os.path.join(BUILD, "runtime.o")
     cmds.append([hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, "pss_runtime.cpp"), "-o", o])
     objs.append(o)
+    o = os.path.join(BUILD, "equation.o")
+    cmds.append([hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, "pss_equation.cpp"), "-o", o])
+    objs.append(o)
     jobs = jobs or min(16, os.cpu_count() or 4)
     # the longest compiles first
     # the longest compiles first: the fused batch kernels, then the longest lines
-    weight = [L for L in LENGTHS] + [0, 100000, 0, 0]
+    weight = [L for L in LENGTHS] + [0, 100000, 0, 0, 0]
     order = sorted(range(len(cmds)), key=lambda i: -weight[i])
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         futs = [ex.submit(_run, cmds[i]) for i in order]

@@ -1,7 +1,7 @@
 """Build a host-sanitizer variant of libpss.so for the CPU interface tests.
 
 The host runtime (pss_runtime.cpp: contexts, validation, plan compilation,
-graphs, batches, tapes) is compiled with g++ under AddressSanitizer and
+graphs, batches, tapes; pss_equation.cpp: the equation front end) is compiled with g++ under AddressSanitizer and
 UndefinedBehaviorSanitizer and linked with the kernel objects of the regular
 build (device code is not instrumented).  The result goes to
 _build/libpss_hostsan.so; load it by setting PSS_LIB to that path and
@@ -30,11 +30,14 @@ def build():
     objs = kernel_objects()
     if objs is None:
         raise RuntimeError("kernel objects missing: run paper_2405_02410_amd.build first")
-    rt = os.path.join(BUILD, "runtime_hostsan.o")
-    compile_cmd = ["g++", "-std=c++17", "-O1", "-g", "-fPIC", *SAN, "-D__HIP_PLATFORM_AMD__",
-                   "-I/opt/rocm/include", "-c", os.path.join(CSRC, "pss_runtime.cpp"), "-o", rt]
-    subprocess.run(compile_cmd, check=True)
-    link_cmd = ["g++", "-shared", *SAN, "-o", OUT + ".tmp", rt, *objs,
+    host = []
+    for src in ("pss_runtime.cpp", "pss_equation.cpp"):
+        o = os.path.join(BUILD, src.replace(".cpp", "_hostsan.o"))
+        compile_cmd = ["g++", "-std=c++17", "-O1", "-g", "-fPIC", *SAN, "-D__HIP_PLATFORM_AMD__",
+                       "-I/opt/rocm/include", "-c", os.path.join(CSRC, src), "-o", o]
+        subprocess.run(compile_cmd, check=True)
+        host.append(o)
+    link_cmd = ["g++", "-shared", *SAN, "-o", OUT + ".tmp", *host, *objs,
                 "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"]
     subprocess.run(link_cmd, check=True)
     os.replace(OUT + ".tmp", OUT)

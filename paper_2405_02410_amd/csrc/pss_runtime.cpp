@@ -24,21 +24,30 @@
 #include <vector>
 
 #include "../../include/pss.h"
+#include "pss_error.h"
 #include "pss_kernels.h"
 #include "pss_plan.h"
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-pss_status fail(pss_status code, const char* fmt, ...) {
+// the message pss_last_error returns (also set by the equation front end)
+pss_status pss_internal::set_error(pss_status code, const char* fmt, va_list ap) {
     char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
     vsnprintf(buf, sizeof(buf), fmt, ap);
-    va_end(ap);
     g_err = buf;
     return code;
+}
+
+namespace {
+
+pss_status fail(pss_status code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    const pss_status s = pss_internal::set_error(code, fmt, ap);
+    va_end(ap);
+    return s;
 }
 
 #define HIP_TRY(expr)                                                                        \
@@ -148,6 +157,7 @@ struct pss_ctx {
     std::vector<int> ids;               // declared field -> internal code
     std::vector<Term> terms;            // fields named by internal code
     std::vector<std::vector<int2>> frames;  // boundary frames per dynamic field: (site, value bits)
+    std::map<std::string, double> params;   // named parameters of the equation front end
 
     // device side
     bool planned = false;
@@ -1543,6 +1553,38 @@ pss_status pss_field_declare(pss_ctx* c, const char* name, int32_t dynamic, int3
     return PSS_OK;
 }
 
+pss_status pss_field_find(pss_ctx* c, const char* name, int32_t* field_id, int32_t* dynamic) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (!name) return fail(PSS_E_INVAL, "null name");
+    for (size_t id = 0; id < c->ids.size(); ++id) {
+        const int code = c->ids[id];
+        const std::string& nm = is_interm(code) ? c->interms[code - PSS_MAXF] : c->fields[code].name;
+        if (nm == name) {
+            if (field_id) *field_id = static_cast<int32_t>(id);
+            if (dynamic) *dynamic = is_interm(code) ? 0 : 1;
+            return PSS_OK;
+        }
+    }
+    return fail(PSS_E_INVAL, "no field named '%s'", name);
+}
+
+pss_status pss_param_set(pss_ctx* c, const char* name, double value) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (!name || !*name || std::strlen(name) > 63) return fail(PSS_E_INVAL, "parameter name must have 1..63 characters");
+    if (!std::isfinite(value)) return fail(PSS_E_INVAL, "non-finite parameter value");
+    c->params[name] = value;
+    return PSS_OK;
+}
+
+pss_status pss_param_get(pss_ctx* c, const char* name, double* value) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (!name || !value) return fail(PSS_E_INVAL, "null argument");
+    auto it = c->params.find(name);
+    if (it == c->params.end()) return fail(PSS_E_INVAL, "no parameter named '%s'", name);
+    *value = it->second;
+    return PSS_OK;
+}
+
 pss_status pss_term_add(pss_ctx* c, int32_t target, int32_t implicit, const pss_qmono* op, int32_t n_mono,
                         const int32_t* factor_fields, const int32_t* factor_powers, int32_t n_factors,
                         int32_t* term_id) {
@@ -1576,6 +1618,41 @@ pss_status pss_term_add(pss_ctx* c, int32_t target, int32_t implicit, const pss_
     if (total > PSS_MAXPOW) return fail(PSS_E_INVAL, "total order above %d", PSS_MAXPOW);
     c->terms.push_back(t);
     if (term_id) *term_id = static_cast<int32_t>(c->terms.size() - 1);
+    return PSS_OK;
+}
+
+pss_status pss_term_info(pss_ctx* c, int32_t term_id, int32_t* target, int32_t* implicit, pss_qmono* op,
+                         int32_t* n_mono, int32_t* factor_fields, int32_t* factor_powers, int32_t* n_factors) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (term_id < 0 || term_id >= static_cast<int>(c->terms.size())) return fail(PSS_E_INVAL, "bad term id");
+    const Term& t = c->terms[term_id];
+    auto declared = [&](int code) {
+        for (size_t id = 0; id < c->ids.size(); ++id)
+            if (c->ids[id] == code) return static_cast<int32_t>(id);
+        return int32_t{-1};
+    };
+    if (target) *target = declared(t.target);
+    if (implicit) *implicit = t.implicit ? 1 : 0;
+    if (n_mono) *n_mono = static_cast<int32_t>(t.op.size());
+    if (op)
+        for (size_t i = 0; i < t.op.size(); ++i) {
+            op[i].coef = t.op[i].coef;
+            op[i].q2_pow = t.op[i].q2;
+            op[i].invq_pow = t.op[i].invq;
+            for (int k = 0; k < 3; ++k) op[i].iq_pow[k] = t.op[i].iq[k];
+        }
+    if (n_factors) *n_factors = static_cast<int32_t>(t.factors.size());
+    for (size_t i = 0; i < t.factors.size(); ++i) {
+        if (factor_fields) factor_fields[i] = declared(t.factors[i].first);
+        if (factor_powers) factor_powers[i] = t.factors[i].second;
+    }
+    return PSS_OK;
+}
+
+pss_status pss_term_count(pss_ctx* c, int32_t* count) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (!count) return fail(PSS_E_INVAL, "null output");
+    *count = static_cast<int32_t>(c->terms.size());
     return PSS_OK;
 }
 

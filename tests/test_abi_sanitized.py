@@ -1,4 +1,5 @@
-"""The host interface tests (test_abi_host.py) again, in a child process, with
+"""The host interface tests (test_abi_host.py, test_equation_frontend.py)
+again, in a child process, with
 the host runtime built under AddressSanitizer and UndefinedBehaviorSanitizer
 (CPU only; device code is not instrumented).  Needs the kernel objects of the
 regular build."""
@@ -18,7 +19,8 @@ def test_host_interface_under_asan_and_ubsan():
         pytest.skip("kernel objects of the regular build are missing")
     hs.build()
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_abi_host.py")],
+                        os.path.join(ROOT, "tests", "test_abi_host.py"),
+                        os.path.join(ROOT, "tests", "test_equation_frontend.py")],
                        cwd=ROOT, env=hs.runtime_env(), capture_output=True, text=True, timeout=600)
     out = r.stdout + r.stderr
     assert r.returncode == 0, out[-4000:]

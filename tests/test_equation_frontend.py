@@ -1,0 +1,137 @@
+"""The equation-string front end (Sec. "Writing models" and "Reserved
+keywords"): equation strings become the same terms as the explicit C calls
+(host only; the terms are read back with pss_term_info).
+"""
+
+import numpy as np
+import pytest
+
+import paper_2405_02410_amd as pss
+from paper_2405_02410_amd import Mono, PssError
+
+
+def _lat(n=(64, 64)):
+    return pss.Lattice(n, dt=0.01)
+
+
+def _norm(terms):
+    """Terms with their monomials as sortable tuples."""
+    out = []
+    for tgt, imp, monos, fac in terms:
+        ms = sorted((round(m.coef, 12), m.q2, m.invq, tuple(m.iq)) for m in monos)
+        out.append((tgt, imp, ms, sorted(fac)))
+    return out
+
+
+def test_model_b_string_equals_the_explicit_terms():
+    a, b, k, D = -1.0, 1.0, 4.0, 0.01
+    ref = _lat()
+    f, _ = pss.model_b(ref, a=a, b=b, k=k, D=D)
+    lat = _lat()
+    for name, v in (("a", a), ("b", b), ("k", k), ("D", D)):
+        lat.param(name, v)
+    phi = lat.field("phi")
+    ids = lat.equation("dt phi + (a*q^2 + k*q^4)*phi = -b*q^2*phi^3")
+    assert ids == [0, 1]
+    lat.noise_expr(phi, "D*q^2")
+    assert _norm(lat.terms()) == _norm(ref.terms())
+    lat.validate()
+
+
+def test_the_papers_intermediate_and_laplacian_examples():
+    lat = _lat()
+    phi = lat.field("phi")
+    psi = lat.field("psi", dynamic=False)
+    lap = lat.field("lapphi", dynamic=False)
+    lat.equation("psi + psi*q^2 = -q^2*phi")
+    lat.equation("lapphi = -q^2*phi")
+    lat.equation("dt phi = psi*lapphi")
+    t = _norm(lat.terms())
+    # psi: implicit -q^2 (psi + psi q^2 = ...), explicit -q^2 phi
+    assert (psi, True, [(-1.0, 1, 0, (0, 0, 0))], [(psi, 1)]) in t
+    assert (psi, False, [(-1.0, 1, 0, (0, 0, 0))], [(phi, 1)]) in t
+    assert (lap, False, [(-1.0, 1, 0, (0, 0, 0))], [(phi, 1)]) in t
+    assert (phi, False, [(1.0, 0, 0, (0, 0, 0))], sorted([(psi, 1), (lap, 1)])) in t
+    lat.validate()
+
+
+def test_kpz_string_equals_the_helper():
+    ref = _lat()
+    pss.kpz(ref, sigma=1.3, lam=0.7, D=0.02)
+    lat = _lat()
+    lat.param("sigma", 1.3)
+    lat.param("lambda", 0.7)
+    phi = lat.field("phi")
+    lat.field("dx_phi", dynamic=False)
+    lat.field("dy_phi", dynamic=False)
+    lat.equation("dt phi + sigma*q^2*phi = 0")
+    lat.equation("dx_phi = iqx*phi")
+    lat.equation("dt phi = lambda*dx_phi^2")
+    lat.equation("dy_phi = iqy*phi")
+    lat.equation("dt phi = lambda*dy_phi^2")
+    lat.noise_expr(phi, "0.02")
+    assert _norm(lat.terms()) == _norm(ref.terms())
+
+
+def test_products_are_expanded_and_gathered():
+    lat = _lat()
+    lat.param("g", 0.5)
+    phi = lat.field("phi")
+    psi = lat.field("psi")
+    lat.equation("dt phi = -g*q^2*(phi + psi)^2 + iqx*iqy^2*phi*psi/q - 2*phi*psi/4")
+    t = {tuple(fac): sorted((round(m.coef, 12), m.q2, m.invq, tuple(m.iq)) for m in monos)
+         for _, _, monos, fac in lat.terms()}
+    assert t[((phi, 2),)] == [(-0.5, 1, 0, (0, 0, 0))]
+    assert t[((psi, 2),)] == [(-0.5, 1, 0, (0, 0, 0))]
+    assert t[((phi, 1), (psi, 1))] == sorted([(-1.0, 1, 0, (0, 0, 0)), (-0.5, 0, 0, (0, 0, 0)),
+                                                (1.0, 0, 1, (1, 2, 0))])
+
+
+@pytest.mark.parametrize("eq,code", [
+    ("dt phi + phi^3 = 0", "PSS_E_INVAL"),          # non-linear left-hand side
+    ("dt phi + psi = 0", "PSS_E_INVAL"),            # another field on the left
+    ("phi = -q^2*phi", "PSS_E_INVAL"),              # a dynamic field without dt
+    ("dt phi = q^3*phi", "PSS_E_INVAL"),            # q takes even powers
+    ("dt phi = qq*phi", "PSS_E_INVAL"),             # unknown name
+    ("dt phi = -q^2*phi^3 +", "PSS_E_INVAL"),       # dangling operator
+    ("dt phi = (q^2*phi", "PSS_E_INVAL"),           # missing parenthesis
+    ("dt phi = 1", "PSS_E_UNSUPPORTED"),            # a source term
+    ("dt phi = phi/phi", "PSS_E_INVAL"),            # division by a field
+    ("dt phi q^2*phi", "PSS_E_INVAL"),              # no '='
+])
+def test_bad_equations_are_refused(eq, code):
+    lat = _lat()
+    lat.field("phi")
+    lat.field("psi")
+    with pytest.raises(PssError) as e:
+        lat.equation(eq)
+    assert e.value.name == code, e.value
+
+
+def test_intermediate_equation_rules():
+    lat = _lat()
+    phi = lat.field("phi")
+    lat.field("psi", dynamic=False)
+    with pytest.raises(PssError):
+        lat.equation("dt psi = phi")  # dt on an intermediate field
+    with pytest.raises(PssError) as e:
+        lat.equation("psi = phi^2")  # intermediates are linear in the dynamic fields
+    assert e.value.name == "PSS_E_UNSUPPORTED"
+    lat.equation("psi = 2*phi - iqx*phi")
+    with pytest.raises(PssError):
+        lat.noise_expr(phi, "phi*q^2")  # a noise prefactor holds no fields
+
+
+def test_noise_strings():
+    lat = _lat()
+    lat.param("D", 0.3)
+    phi = lat.field("phi")
+    lat.equation("dt phi + q^2*phi = 0")
+    lat.noise_expr(phi, "D*q^2 + 0.1/q")
+    lat.validate()
+    bad = _lat()
+    f = bad.field("phi")
+    bad.equation("dt phi + q^2*phi = 0")
+    bad.noise_expr(f, "-0.1*q^2")  # negative D(q): refused when validated
+    with pytest.raises(PssError):
+        bad.validate()
