@@ -318,8 +318,12 @@ pss_status pss_mass(pss_ctx *ctx, int32_t field, double *mass);
 
 /* Shell-averaged structure factor S_j = mean over modes with
  * round(|k|) = j of (dV/N)|phi_hat(k)|^2, j = 1 .. n_shells, n_shells =
- * min_i(N_i)/2 - 1; counts[j-1] receives the shell population.  FP64
- * accumulation on the device.  Synchronous. */
+ * min_i(N_i)/2 - 1 (Sec. "Example", the coarsening observable); counts[j-1]
+ * receives the shell population.  The FP64 terms are summed exactly on the
+ * device (each rounded once to 2^-62 of its shell's largest term, then added
+ * as integers), so the result does not depend on the order of the device's
+ * atomics and repeats bit for bit.  A shell with a NaN term is NaN; one with
+ * an infinite term and no NaN is +inf.  Synchronous. */
 pss_status pss_structure_factor(pss_ctx *ctx, int32_t field, double *S, int64_t *counts,
                                 int32_t n_shells);
 
@@ -327,7 +331,7 @@ pss_status pss_structure_factor(pss_ctx *ctx, int32_t field, double *S, int64_t 
  * hipMalloc: tight serving or monitoring loops, harnesses that forbid it):
  * the result of pss_structure_factor, computed without any device or host
  * allocation.  The shell sums and counts live in a static device array of the
- * library (32 KiB per GPU, held until the process ends) instead of buffers
+ * library (64 KiB per GPU, held until the process ends) instead of buffers
  * allocated on first use; n_shells above 2047 is PSS_E_UNSUPPORTED (every
  * lattice of at most 4096 per axis fits).  The plan must already be built
  * (PSS_E_STATE otherwise: building it allocates).  Writes S and counts as
@@ -393,7 +397,8 @@ pss_status pss_kernels_per_step(pss_ctx *ctx, int32_t *count);
  * where m is the de-aliasing mask and the noise of each step is regenerated
  * from its Philox counter (it does not depend on the coefficients other than
  * through D).  Outputs: *loss; grad[4] = dL/d(a, b, k, D) (FP64 sums of FP32
- * terms; dL/dD = 0 when D = 0); grad_phi0 (may be NULL; else Nx*Ny floats,
+ * terms, taken in a fixed order: the same run gives the same bits;
+ * dL/dD = 0 when D = 0); grad_phi0 (may be NULL; else Nx*Ny floats,
  * host or device memory per on_device) = dL/dphi_0(x) for the real initial
  * field.  The lattice is left at step n0 + nsteps with the forward final
  * state.  Device workspace: (ceil(nsteps/ckpt_every) + min(ckpt_every,

@@ -35,7 +35,7 @@ struct Bufs {
     float2* out;
     const float* real_in;
     float* real_out;
-    double* acc;  // adjoint row pass: FP64 accumulator of sum_x u^3 w
+    double* acc;  // adjoint row pass: one FP64 slot per block of sum_x u^3 w
     int sel;
 };
 
@@ -44,12 +44,14 @@ struct Bufs {
 // column kernel.  All spectral arrays are packed, in the 2D state layout.
 //   g_{n+1} = first ? G : Rin + b m F_y[X] / N    (X: x-forward of 3 u^2 w, row pass)
 //   r_n = g_{n+1} / A                             -> Rout
-//   acc[0] -= <r, dt q^2 phi1>, acc[2] -= <r, dt q^4 phi1>, acc[3] += <r, eta_n>/(2D)
+//   dL/da -= <r, dt q^2 phi1>, dL/dk -= <r, dt q^4 phi1>, dL/dD += <r, eta_n>/(2D)
 //   W = F_y^-1[-dt q^2 r_n],  U = F_y^-1[m phi0]
 // The row pass (x kernel, MODE_ADJROW) forms w = N F^-1[-dt q^2 r_n] and
-// u_n in real space and adds <r, -dt q^2 F[u_n^3]> = sum_x u^3 w to acc[1].
-// with <x, y> = Re sum over all modes of conj(x) y.  MODE_ADJFIN stops after
-// g_{n+1} and stores it in Rout.
+// u_n in real space and adds <r, -dt q^2 F[u_n^3]> = sum_x u^3 w to dL/db,
+// with <x, y> = Re sum over all modes of conj(x) y.  Each block adds its part
+// of a sum into slots of its own (the same blocks every step), which the host
+// sums in a fixed order after the sweep.  MODE_ADJFIN stops after g_{n+1} and
+// stores it in Rout.
 struct AdjArgs {
     const DevPlan* plan;  // forward plan: masks, noise operator, q scales, keys
     const float2* G;
@@ -60,7 +62,7 @@ struct AdjArgs {
     float2* Rout;
     float2* W;
     float2* U;
-    double* acc;          // [4]: dL/da, dL/db (row pass), dL/dk, dL/dD
+    double* acc;          // [3 * blocks]: per block dL/da, dL/dk, dL/dD
     float a, b, k, D;
     uint32_t step;        // n: the noise counter of the forward step
     int first;
@@ -255,9 +257,14 @@ constexpr int kScratchShells = 2048;
 hipError_t scratch_address(void** out);
 hipError_t launch_zero_words(hipStream_t s, unsigned long long* p, int n);
 
-// FP64 shell sums of (dV/N)|phi_hat|^2 over the packed state of one field
+// Shell means of (dV/N)|phi_hat|^2 over the packed state of one field, from
+// exact fixed-point sums (the result does not depend on the order of the
+// atomics).  acc holds kShellWords * nshell zeroed 64-bit words; on return
+// acc[j] holds the mean of shell j as a double and acc[2 * nshell + j] its
+// population.
+constexpr int kShellWords = 4;
 hipError_t launch_shells(hipStream_t s, const float2* S, int nx, int ny, int nz, int tc, int ndim,
-                         double scale, int nshell, double* sums, unsigned long long* counts);
+                         double scale, int nshell, unsigned long long* acc);
 
 
 }  // namespace pss

@@ -61,22 +61,38 @@ __device__ __forceinline__ const float2* store_twiddles(float2* dst, const float
     return dst;
 }
 
-// FP64 atomic add of NV per-thread values into dst[0..NV): one atomic per
-// wave after a shuffle reduction when the block is whole waves, else one per
-// thread (tiny lattices)
+// Sum of NV per-thread FP64 values over the block in a fixed order (a
+// shuffle tree inside each wave, then the waves in index order), added by
+// thread 0 into this block's own slot[0..NV).  Launches with the same grid
+// add into the same slots in stream order, so the slots, and a fixed-order
+// sum over them, do not depend on how the blocks are scheduled.  Every thread
+// of the block calls it; the block is whole waves or a part of one.
 template <int NV>
-__device__ __forceinline__ void block_atomic_add(double (&v)[NV], double* dst) {
-    if ((blockDim.x & 63) == 0) {
+__device__ __forceinline__ void block_sum_to_slot(double (&v)[NV], double* __restrict__ slot) {
+    __shared__ double red[64 * NV];
+    const int nt = blockDim.x, tid = threadIdx.x;
+    const bool waves = (nt & 63) == 0;
+    if (waves) {
 #pragma unroll
         for (int i = 0; i < NV; ++i)
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o, 64);
-        if ((threadIdx.x & 63) == 0)
+        if ((tid & 63) == 0)
 #pragma unroll
-            for (int i = 0; i < NV; ++i) atomicAdd(dst + i, v[i]);
+            for (int i = 0; i < NV; ++i) red[(tid >> 6) * NV + i] = v[i];
     } else {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) atomicAdd(dst + i, v[i]);
+        for (int i = 0; i < NV; ++i) red[tid * NV + i] = v[i];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const int n = waves ? nt >> 6 : nt;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            double acc = 0.0;
+            for (int w = 0; w < n; ++w) acc += red[w * NV + i];
+            slot[i] += acc;
+        }
     }
 }
 
@@ -964,8 +980,7 @@ __global__ void __launch_bounds__(256) adjcol_kernel(AdjArgs aa, Geo geo, const 
 #pragma unroll
     for (int m = 0; m < P; ++m) aa.U[base + (t + m * T) * tc] = um[m];
     if (aa.D > 0.f) part[2] /= 2.0 * aa.D;
-    double out[4] = {part[0], 0.0, part[1], part[2]};
-    block_atomic_add(out, aa.acc);
+    block_sum_to_slot(part, aa.acc + static_cast<size_t>(blockIdx.x) * 3);
 }
 
 #if defined(PSS_COMMON)
@@ -1276,7 +1291,7 @@ __device__ __forceinline__ void xrow_block(int mi, int blk, const Member* __rest
         }
         FFT::template dif<-1>(u, ld, t, tw);
         store_rows(u, bufs.N[0]);
-        block_atomic_add(part, bufs.acc);
+        block_sum_to_slot(part, bufs.acc + blockIdx.x);
         return;
     }
 
@@ -1398,90 +1413,167 @@ __global__ void philox_kernel(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3
 // the 2D tiled layout [ctile][y][TC]; interior columns stand for the mode and
 // its conjugate partner (weight 2); column 0 is unpacked into kx = 0 and
 // kx = Nx/2 (weight 1 each) with the partner element at -y.  In 1D element i
-// is mode i of the full spectrum (weight 1).
-__device__ __forceinline__ void shell_add(double* sums, unsigned int* cnt, int nshell, int kx, int ky, int kz,
-                                          double v, unsigned int w) {
-    const double kk = static_cast<double>(kx) * kx + static_cast<double>(ky) * ky + static_cast<double>(kz) * kz;
-    const int j = static_cast<int>(rint(sqrt(kk)));
-    if (j >= 1 && j < nshell) {
-        atomicAdd(&sums[j], v * w);
-        atomicAdd(&cnt[j], w);
+// is mode i of the full spectrum (weight 1).  shell_terms calls
+// emit(j, t) for every term t = w * scale * |phi_hat|^2 of shell j.
+//
+// The sums are exact, so they do not depend on the order in which the
+// threads and blocks add: a first pass takes the largest binary exponent E_j
+// of the terms of each shell (a max, order-free), a second adds every term
+// as the integer round(t * 2^(61 - e_j)) (e_j = E_j - 1023, so each is below
+// 2^62) into a 128-bit accumulator (64-bit atomics with carry; integer sums
+// are associative), and a last pass turns the integer back into a double.
+// Each term is rounded once, to 2^-62 of the shell's largest term.
+template <typename F>
+__device__ __forceinline__ void shell_terms(const float2* __restrict__ S, int64_t e, int nx, int ny, int nz, int tc,
+                                            int dim, int nshell, double scale, F&& emit) {
+    auto mag = [](float2 v) { return static_cast<double>(v.x) * v.x + static_cast<double>(v.y) * v.y; };
+    auto add = [&](int kx, int ky, int kz, double v, int w) {
+        const double kk = static_cast<double>(kx) * kx + static_cast<double>(ky) * ky + static_cast<double>(kz) * kz;
+        const int j = static_cast<int>(rint(sqrt(kk)));
+        if (j >= 1 && j < nshell) emit(j, scale * v * w, static_cast<unsigned int>(w));
+    };
+    if (dim == 1) {
+        const int k = static_cast<int>(e);
+        add(k < nx / 2 ? k : k - nx, 0, 0, mag(S[e]), 1);
+        return;
+    }
+    const int ncols = nx / 2;
+    const int ntile = ncols / tc;
+    const int cc = static_cast<int>(e % tc);
+    const int64_t r = e / tc;
+    int c, y, z;
+    if (dim == 2) {
+        y = static_cast<int>(r % ny);
+        c = static_cast<int>(r / ny) * tc + cc;
+        z = 0;
+    } else {
+        z = static_cast<int>(r % nz);
+        const int64_t r2 = r / nz;
+        c = static_cast<int>(r2 % ntile) * tc + cc;
+        y = static_cast<int>(r2 / ntile);
+    }
+    const int ky = y < ny / 2 ? y : y - ny;
+    const int kz = nz == 1 ? 0 : (z < nz / 2 ? z : z - nz);
+    const float2 a = S[e];
+    if (c > 0) {
+        add(c, ky, kz, mag(a), 2);
+        return;
+    }
+    // column 0: slot form along the update axis on packed lines
+    const bool packed = dim == 2 || y == 0 || y == ny / 2;
+    if (!packed) {
+        if (y < ny / 2)
+            add(0, y, kz, mag(a), 2);
+        else
+            add(-(nx / 2), ny - y, kz, mag(a), 2);
+        return;
+    }
+    const int L = dim == 2 ? ny : nz;
+    const int u = dim == 2 ? y : z;
+    const int ky0 = dim == 2 ? 0 : ky;
+    auto at = [&](int w) { return dim == 2 ? make_int2(w, 0) : make_int2(ky0, w); };  // (ky, kz) of index w
+    if (u == 0 || u == L / 2) {
+        const int w = u == 0 ? 0 : -(L / 2);
+        const int2 yz = at(w);
+        add(0, yz.x, yz.y, static_cast<double>(a.x) * a.x, 1);
+        add(-(nx / 2), yz.x, yz.y, static_cast<double>(a.y) * a.y, 1);
+    } else if (u < L / 2) {
+        const int2 yz = at(u);
+        add(0, yz.x, yz.y, mag(a), 2);
+    } else {
+        const int2 yz = at(L - u);
+        add(-(nx / 2), yz.x, yz.y, mag(a), 2);
     }
 }
 
-__global__ void shells_kernel(const float2* __restrict__ S, int nx, int ny, int nz, int tc, int dim, double scale,
-                              int nshell, double* __restrict__ gsum, unsigned long long* __restrict__ gcnt) {
-    extern __shared__ double lsum[];
-    unsigned int* lcnt = reinterpret_cast<unsigned int*>(lsum + nshell);
+// order key of a term: twice its biased exponent, +1 for a NaN (so that a
+// NaN wins over an infinity, as it would in a plain sum)
+__device__ __forceinline__ unsigned int shell_key(double t) {
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(t));
+    const unsigned int E = static_cast<unsigned int>((b >> 52) & 0x7ffull);
+    const bool nan = E == 0x7ffu && (b & 0xfffffffffffffull) != 0ull;
+    return 2u * E + (nan ? 1u : 0u);
+}
+
+__device__ __forceinline__ int64_t shell_total(int nx, int ny, int nz, int dim) {
+    return dim == 1 ? static_cast<int64_t>(nx) : static_cast<int64_t>(nx / 2) * ny * nz;
+}
+
+// pass 1: key[j] = max over the terms of shell j
+__global__ void shell_keys_kernel(const float2* __restrict__ S, int nx, int ny, int nz, int tc, int dim, double scale,
+                                  int nshell, unsigned int* __restrict__ gkey) {
+    extern __shared__ unsigned int lkey[];
+    for (int i = threadIdx.x; i < nshell; i += blockDim.x) lkey[i] = 0u;
+    __syncthreads();
+    const int64_t total = shell_total(nx, ny, nz, dim);
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        shell_terms(S, e, nx, ny, nz, tc, dim, nshell, scale,
+                    [&](int j, double t, unsigned int) { atomicMax(&lkey[j], shell_key(t)); });
+    __syncthreads();
+    for (int i = threadIdx.x; i < nshell; i += blockDim.x)
+        if (lkey[i]) atomicMax(&gkey[i], lkey[i]);
+}
+
+// 128-bit add of (hi, lo) into (*h, *l) with 64-bit atomics
+__device__ __forceinline__ void add128(unsigned long long* h, unsigned long long* l, unsigned long long hi,
+                                       unsigned long long lo) {
+    const unsigned long long old = atomicAdd(l, lo);
+    hi += old + lo < old ? 1ull : 0ull;
+    if (hi) atomicAdd(h, hi);
+}
+
+// pass 2: the exact fixed-point sums and the shell populations
+__global__ void shell_sums_kernel(const float2* __restrict__ S, int nx, int ny, int nz, int tc, int dim, double scale,
+                                  int nshell, const unsigned int* __restrict__ gkey, unsigned long long* __restrict__ ghi,
+                                  unsigned long long* __restrict__ glo, unsigned long long* __restrict__ gcnt) {
+    extern __shared__ unsigned long long lacc[];
+    unsigned long long* lhi = lacc;
+    unsigned long long* llo = lacc + nshell;
+    unsigned int* lcnt = reinterpret_cast<unsigned int*>(lacc + 2 * nshell);
+    unsigned int* lkey = lcnt + nshell;
     for (int i = threadIdx.x; i < nshell; i += blockDim.x) {
-        lsum[i] = 0.0;
+        lhi[i] = 0ull;
+        llo[i] = 0ull;
         lcnt[i] = 0u;
+        lkey[i] = gkey[i];
     }
     __syncthreads();
-    const int ncols = nx / 2;
-    const int ntile = ncols / tc;
-    const int64_t total = dim == 1 ? static_cast<int64_t>(nx) : static_cast<int64_t>(ncols) * ny * nz;
-    auto mag = [](float2 v) { return static_cast<double>(v.x) * v.x + static_cast<double>(v.y) * v.y; };
+    const int64_t total = shell_total(nx, ny, nz, dim);
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
-         e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        if (dim == 1) {
-            const int k = static_cast<int>(e);
-            shell_add(lsum, lcnt, nshell, k < nx / 2 ? k : k - nx, 0, 0, scale * mag(S[e]), 1u);
-            continue;
-        }
-        const int cc = static_cast<int>(e % tc);
-        const int64_t r = e / tc;
-        int c, y, z;
-        if (dim == 2) {
-            y = static_cast<int>(r % ny);
-            c = static_cast<int>(r / ny) * tc + cc;
-            z = 0;
-        } else {
-            z = static_cast<int>(r % nz);
-            const int64_t r2 = r / nz;
-            c = static_cast<int>(r2 % ntile) * tc + cc;
-            y = static_cast<int>(r2 / ntile);
-        }
-        const int ky = y < ny / 2 ? y : y - ny;
-        const int kz = nz == 1 ? 0 : (z < nz / 2 ? z : z - nz);
-        const float2 a = S[e];
-        if (c > 0) {
-            shell_add(lsum, lcnt, nshell, c, ky, kz, scale * mag(a), 2u);
-            continue;
-        }
-        // column 0: slot form along the update axis on packed lines
-        const bool packed = dim == 2 || y == 0 || y == ny / 2;
-        if (!packed) {
-            if (y < ny / 2)
-                shell_add(lsum, lcnt, nshell, 0, y, kz, scale * mag(a), 2u);
-            else
-                shell_add(lsum, lcnt, nshell, -(nx / 2), ny - y, kz, scale * mag(a), 2u);
-            continue;
-        }
-        const int L = dim == 2 ? ny : nz;
-        const int u = dim == 2 ? y : z;
-        const int ky0 = dim == 2 ? 0 : ky;
-        auto at = [&](int w) { return dim == 2 ? make_int2(w, 0) : make_int2(ky0, w); };  // (ky, kz) of index w
-        if (u == 0 || u == L / 2) {
-            const int w = u == 0 ? 0 : -(L / 2);
-            const int2 yz = at(w);
-            shell_add(lsum, lcnt, nshell, 0, yz.x, yz.y, scale * static_cast<double>(a.x) * a.x, 1u);
-            shell_add(lsum, lcnt, nshell, -(nx / 2), yz.x, yz.y, scale * static_cast<double>(a.y) * a.y, 1u);
-        } else if (u < L / 2) {
-            const int2 yz = at(u);
-            shell_add(lsum, lcnt, nshell, 0, yz.x, yz.y, scale * mag(a), 2u);
-        } else {
-            const int2 yz = at(L - u);
-            shell_add(lsum, lcnt, nshell, -(nx / 2), yz.x, yz.y, scale * mag(a), 2u);
-        }
-    }
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        shell_terms(S, e, nx, ny, nz, tc, dim, nshell, scale, [&](int j, double t, unsigned int w) {
+            atomicAdd(&lcnt[j], w);
+            const int E = static_cast<int>(lkey[j] >> 1);
+            if (E == 0x7ff || t == 0.0) return;  // a non-finite shell is settled by its key
+            add128(&lhi[j], &llo[j], 0ull, __double2ull_rn(ldexp(t, 1084 - E)));
+        });
     __syncthreads();
     for (int i = threadIdx.x; i < nshell; i += blockDim.x) {
         if (lcnt[i]) {
-            atomicAdd(&gsum[i], lsum[i]);
+            add128(&ghi[i], &glo[i], lhi[i], llo[i]);
             atomicAdd(&gcnt[i], static_cast<unsigned long long>(lcnt[i]));
         }
     }
+}
+
+// pass 3: shell means S_j = sum_j / count_j, written over hi[j] as doubles
+__global__ void shell_means_kernel(int nshell, const unsigned int* __restrict__ gkey,
+                                   unsigned long long* __restrict__ ghi, const unsigned long long* __restrict__ glo,
+                                   const unsigned long long* __restrict__ gcnt) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nshell) return;
+    const unsigned int key = gkey[j];
+    const int E = static_cast<int>(key >> 1);
+    double v;
+    if (E == 0x7ff) {
+        v = (key & 1u) ? __longlong_as_double(0x7ff8000000000000ll) : __longlong_as_double(0x7ff0000000000000ll);
+    } else {
+        const double m = static_cast<double>(ghi[j]) * 18446744073709551616.0 + static_cast<double>(glo[j]);
+        v = ldexp(m, E - 1084);
+    }
+    const unsigned long long n = gcnt[j];
+    ghi[j] = static_cast<unsigned long long>(__double_as_longlong(n ? v / static_cast<double>(n) : 0.0));
 }
 #endif  // PSS_COMMON
 
@@ -1794,6 +1886,7 @@ static hipError_t launch_xrow_t(int mode, const LaunchArgs& a) {
                                a.plans, a.plan, a.bufs, a.geo, a.tw_x, int64_t{0}, ctr);
             break;
         case MODE_ADJROW:
+            if ((threads & 63) != 0 && threads > 64) return hipErrorInvalidValue;  // block_sum_to_slot's shapes
             if constexpr (NG == 2) {
                 hipLaunchKernelGGL((xrow_kernel<L, P, 2, MODE_ADJROW, false>), grid, block, lds, a.stream, a.members,
                                    a.plans, a.plan, a.bufs, a.geo, a.tw_x, int64_t{0}, ctr);
@@ -1913,6 +2006,7 @@ hipError_t PSS_CAT(launch_adjcol_L, PSS_LINE_LEN)(int mode, const AdjArgs& aa, c
         const size_t lds = update_lds_bytes(L, P, a.geo.tc, 1);
         dim3 grid(a.geo.nublk), block(threads);
         if (a.dim != 2 || a.geo.to != 1) return hipErrorInvalidValue;
+        if ((threads & 63) != 0 && threads > 64) return hipErrorInvalidValue;  // block_sum_to_slot's shapes
         if (mode == MODE_ADJCOL) {
             hipLaunchKernelGGL((adjcol_kernel<L, P, MODE_ADJCOL>), grid, block, lds, a.stream, aa, a.geo, a.tw_u);
         } else if (mode == MODE_ADJFIN) {
@@ -2500,10 +2594,18 @@ hipError_t launch_init_uniform(hipStream_t s, float* out, int64_t n, uint32_t fi
 }
 
 hipError_t launch_shells(hipStream_t s, const float2* S, int nx, int ny, int nz, int tc, int ndim, double scale,
-                         int nshell, double* sums, unsigned long long* counts) {
-    const size_t lds = nshell * (sizeof(double) + sizeof(unsigned int));
-    hipLaunchKernelGGL(shells_kernel, dim3(256), dim3(256), lds, s, S, nx, ny, nz, tc, ndim, scale, nshell, sums,
-                       counts);
+                         int nshell, unsigned long long* acc) {
+    if (nshell < 1) return hipSuccess;
+    unsigned long long* hi = acc;
+    unsigned long long* lo = acc + nshell;
+    unsigned long long* cnt = acc + 2 * nshell;
+    auto* key = reinterpret_cast<unsigned int*>(acc + 3 * nshell);
+    hipLaunchKernelGGL(shell_keys_kernel, dim3(256), dim3(256), sizeof(unsigned int) * nshell, s, S, nx, ny, nz, tc,
+                       ndim, scale, nshell, key);
+    const size_t lds = nshell * (2 * sizeof(unsigned long long) + 2 * sizeof(unsigned int));
+    hipLaunchKernelGGL(shell_sums_kernel, dim3(256), dim3(256), lds, s, S, nx, ny, nz, tc, ndim, scale, nshell, key,
+                       hi, lo, cnt);
+    hipLaunchKernelGGL(shell_means_kernel, dim3((nshell + 255) / 256), dim3(256), 0, s, nshell, key, hi, lo, cnt);
     return hipGetLastError();
 }
 

@@ -1,6 +1,6 @@
 // Device scratch of the allocation-free reductions.
 //
-// pss_structure_factor allocates its FP64 shell sums and counts on first use
+// pss_structure_factor allocates its shell accumulators on first use
 // (hipMalloc).  Callers that cannot allocate device memory use
 // pss_structure_factor_noalloc, whose partial results live in the file-scope
 // array below instead.  Every GPU that the library runs on holds its own copy
@@ -18,9 +18,9 @@
 
 namespace pss {
 
-// room for the sums (double) and counts (unsigned long long) of
-// kScratchShells shells: 32 KiB
-static __device__ __align__(256) unsigned char scratch[kScratchShells * (sizeof(double) + sizeof(unsigned long long))];
+// room for the accumulators of kScratchShells shells (kShellWords 64-bit
+// words each: 128-bit sum, count, exponent key): 64 KiB
+static __device__ __align__(256) unsigned long long scratch[kScratchShells * kShellWords];
 
 namespace {
 constexpr int kMaxDevices = 64;

@@ -179,8 +179,7 @@ struct pss_ctx {
     float2* d_tmp2 = nullptr;
     float* d_real = nullptr;
     int2* d_frame[PSS_MAXF] = {};  // device copies of the frames
-    double* d_shell_sum = nullptr;
-    unsigned long long* d_shell_cnt = nullptr;
+    unsigned long long* d_shell_acc = nullptr;  // shell accumulators (kShellWords per shell)
     // one-entry member tables of the step kernels (update kernel, x kernel)
     pss::Member* d_member_u = nullptr;
     pss::Member* d_member_x = nullptr;
@@ -250,7 +249,8 @@ struct pss_tape {
     char* ck = nullptr;
     char* seg = nullptr;
     float2 *fT = nullptr, *G = nullptr, *R0 = nullptr, *R1 = nullptr, *X = nullptr, *W = nullptr, *U = nullptr;
-    double* acc = nullptr;
+    double* acc = nullptr;  // per-block FP64 slots of the gradient sums
+    size_t nacc = 0;
     float* coef = nullptr;
     pss::DevPlan* plan_row = nullptr;
     pss::DevPlan* plan_raw = nullptr;
@@ -722,8 +722,7 @@ void free_device(pss_ctx* c) {
     rel(c->d_tmp);
     rel(c->d_tmp2);
     rel(c->d_real);
-    rel(c->d_shell_sum);
-    rel(c->d_shell_cnt);
+    rel(c->d_shell_acc);
     rel(c->d_member_u);
     rel(c->d_member_x);
     for (auto*& p : c->d_frame) rel(p);
@@ -2034,25 +2033,19 @@ pss_status pss_structure_factor(pss_ctx* c, int32_t field, double* S, int64_t* c
                                   : (c->ndim == 2 ? std::min(c->n[0], c->n[1]) : c->n[0]);
     const int ns = nmin / 2;  // shells j = 1 .. ns-1
     if (n_shells != ns - 1) return fail(PSS_E_INVAL, "n_shells must be %d", ns - 1);
-    if (!c->d_shell_sum) {
-        HIP_TRY(hipMalloc(&c->d_shell_sum, sizeof(double) * ns));
-        HIP_TRY(hipMalloc(&c->d_shell_cnt, sizeof(unsigned long long) * ns));
-    }
-    HIP_TRY(hipMemsetAsync(c->d_shell_sum, 0, sizeof(double) * ns, c->stream));
-    HIP_TRY(hipMemsetAsync(c->d_shell_cnt, 0, sizeof(unsigned long long) * ns, c->stream));
+    if (!c->d_shell_acc) HIP_TRY(hipMalloc(&c->d_shell_acc, sizeof(unsigned long long) * pss::kShellWords * ns));
+    HIP_TRY(hipMemsetAsync(c->d_shell_acc, 0, sizeof(unsigned long long) * pss::kShellWords * ns, c->stream));
     const double dV = c->dx[0] * c->dx[1] * (c->ndim == 3 ? c->dx[2] : 1.0);
     HIP_TRY(pss::launch_shells(c->stream, c->d_state[fd], c->n[0], c->n[1], c->ndim == 3 ? c->n[2] : 1, c->geo.tc,
-                               c->ndim, dV / static_cast<double>(c->sites()), ns, c->d_shell_sum, c->d_shell_cnt));
-    std::vector<double> sums(ns);
-    std::vector<unsigned long long> cnt(ns);
-    HIP_TRY(hipMemcpyAsync(sums.data(), c->d_shell_sum, sizeof(double) * ns, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipMemcpyAsync(cnt.data(), c->d_shell_cnt, sizeof(unsigned long long) * ns, hipMemcpyDeviceToHost,
-                           c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    for (int j = 1; j < ns; ++j) {
-        counts[j - 1] = static_cast<int64_t>(cnt[j]);
-        S[j - 1] = cnt[j] ? sums[j] / static_cast<double>(cnt[j]) : 0.0;
+                               c->ndim, dV / static_cast<double>(c->sites()), ns, c->d_shell_acc));
+    // shells 1 .. ns-1: the means, then the populations
+    static_assert(sizeof(int64_t) == sizeof(unsigned long long), "count width");
+    if (ns > 1) {
+        HIP_TRY(hipMemcpyAsync(S, c->d_shell_acc + 1, sizeof(double) * (ns - 1), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipMemcpyAsync(counts, c->d_shell_acc + 2 * ns + 1, sizeof(int64_t) * (ns - 1), hipMemcpyDeviceToHost,
+                               c->stream));
     }
+    HIP_TRY(hipStreamSynchronize(c->stream));
     return PSS_OK;
 }
 
@@ -2071,22 +2064,19 @@ pss_status pss_structure_factor_noalloc(pss_ctx* c, int32_t field, double* S, in
         return fail(PSS_E_UNSUPPORTED, "%d shells exceed the %d of the static scratch", ns, pss::kScratchShells);
     void* base = nullptr;
     HIP_TRY(pss::scratch_address(&base));
-    double* sums = static_cast<double*>(base);
-    auto* cnt = reinterpret_cast<unsigned long long*>(sums + pss::kScratchShells);
+    auto* acc = static_cast<unsigned long long*>(base);
     // the previous call's contents are still there: clear what is summed into
-    HIP_TRY(pss::launch_zero_words(c->stream, reinterpret_cast<unsigned long long*>(sums), ns));
-    HIP_TRY(pss::launch_zero_words(c->stream, cnt, ns));
+    HIP_TRY(pss::launch_zero_words(c->stream, acc, pss::kShellWords * ns));
     const double dV = c->dx[0] * c->dx[1] * (c->ndim == 3 ? c->dx[2] : 1.0);
     HIP_TRY(pss::launch_shells(c->stream, c->d_state[fd], c->n[0], c->n[1], c->ndim == 3 ? c->n[2] : 1, c->geo.tc,
-                               c->ndim, dV / static_cast<double>(c->sites()), ns, sums, cnt));
-    // shells 1 .. ns-1 straight into the caller's arrays, then averaged in place
+                               c->ndim, dV / static_cast<double>(c->sites()), ns, acc));
+    // shells 1 .. ns-1 straight into the caller's arrays
     static_assert(sizeof(int64_t) == sizeof(unsigned long long), "count width");
     if (ns > 1) {
-        HIP_TRY(hipMemcpyAsync(S, sums + 1, sizeof(double) * (ns - 1), hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(hipMemcpyAsync(counts, cnt + 1, sizeof(int64_t) * (ns - 1), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipMemcpyAsync(S, acc + 1, sizeof(double) * (ns - 1), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipMemcpyAsync(counts, acc + 2 * ns + 1, sizeof(int64_t) * (ns - 1), hipMemcpyDeviceToHost, c->stream));
     }
     HIP_TRY(hipStreamSynchronize(c->stream));
-    for (int j = 0; j < ns - 1; ++j) S[j] = counts[j] ? S[j] / static_cast<double>(counts[j]) : 0.0;
     return PSS_OK;
 }
 
@@ -2352,7 +2342,8 @@ pss_status pss_adjoint_model_b_forward(pss_ctx* c, int64_t nsteps, int32_t ckpt_
     tp->X = static_cast<float2*>(tape_alloc(tp, fb));
     tp->W = static_cast<float2*>(tape_alloc(tp, fb));
     tp->U = static_cast<float2*>(tape_alloc(tp, fb));
-    tp->acc = static_cast<double*>(tape_alloc(tp, 4 * sizeof(double)));
+    tp->nacc = 3 * static_cast<size_t>(c->geo.nublk) + static_cast<size_t>(c->geo.nrowblk);
+    tp->acc = static_cast<double*>(tape_alloc(tp, tp->nacc * sizeof(double)));
     tp->coef = static_cast<float*>(tape_alloc(tp, sizeof(float) * ns));
     tp->plan_row = static_cast<pss::DevPlan*>(tape_alloc(tp, sizeof(pss::DevPlan)));
     tp->plan_raw = static_cast<pss::DevPlan*>(tape_alloc(tp, sizeof(pss::DevPlan)));
@@ -2434,7 +2425,7 @@ pss_status pss_adjoint_model_b_backward(pss_tape* tp, double* grad, float* grad_
     } while (0)
     tp->done = true;
     ADJ_HIP(pss::launch_adjseed(c->stream, tp->fT, tp->G, tp->coef, tp->ns, nx, ny, c->geo.tc));
-    ADJ_HIP(hipMemsetAsync(tp->acc, 0, 4 * sizeof(double), c->stream));
+    ADJ_HIP(hipMemsetAsync(tp->acc, 0, tp->nacc * sizeof(double), c->stream));
 
     // reverse sweep: recompute each segment from its checkpoint, then step back
     pss::AdjArgs aa{};
@@ -2457,7 +2448,7 @@ pss_status pss_adjoint_model_b_backward(pss_tape* tp, double* grad, float* grad_
     ax.bufs.V[0] = tp->U;
     ax.bufs.V[1] = tp->W;
     ax.bufs.N[0] = tp->X;
-    ax.bufs.acc = tp->acc + 1;
+    ax.bufs.acc = tp->acc + 3 * static_cast<size_t>(c->geo.nublk);
     const int64_t n0 = tp->n0, nsteps = tp->nsteps;
     for (int64_t sgi = tp->nck - 1; sgi >= 0; --sgi) {
         const int64_t start = sgi * tp->ckpt;
@@ -2489,8 +2480,8 @@ pss_status pss_adjoint_model_b_backward(pss_tape* tp, double* grad, float* grad_
     aa.Rin = Rcur;
     aa.Rout = tp->G;
     ADJ_HIP(pss::launch_adjcol(pss::MODE_ADJFIN, ny, aa, args(c)));
-    double gh[4];
-    ADJ_HIP(hipMemcpyAsync(gh, tp->acc, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    std::vector<double> slots(tp->nacc);
+    ADJ_HIP(hipMemcpyAsync(slots.data(), tp->acc, tp->nacc * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     if (grad_phi0) {
         pss::LaunchArgs a1 = args(c);
         a1.plan = tp->plan_raw;
@@ -2513,6 +2504,16 @@ pss_status pss_adjoint_model_b_backward(pss_tape* tp, double* grad, float* grad_
     c->steps_taken = n0 + nsteps;
     c->dirty = true;
     ++c->state_gen;
+    // the per-block slots in block order: dL/da, dL/dk, dL/dD from the
+    // column blocks, dL/db from the row blocks
+    double gh[4] = {0.0, 0.0, 0.0, 0.0};
+    const size_t ncol = static_cast<size_t>(c->geo.nublk);
+    for (size_t bk = 0; bk < ncol; ++bk) {
+        gh[0] += slots[3 * bk];
+        gh[2] += slots[3 * bk + 1];
+        gh[3] += slots[3 * bk + 2];
+    }
+    for (size_t bk = 3 * ncol; bk < tp->nacc; ++bk) gh[1] += slots[bk];
     for (int i = 0; i < 4; ++i) grad[i] = gh[i];
     return PSS_OK;
 }
