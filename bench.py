@@ -11,7 +11,8 @@ training-system workloads measured against their plain forms:
 * "ensemble": 256 x 128^2 + 64 x 256^2 + 16 x 512^2 independent lattices in
   one batch, against the same lattices stepped one lattice per launch;
 * "adjoint": the gradient of a structure-factor loss through 2000 steps of
-  256^2 Model B (checkpoints every 45), against the forward run alone.
+  256^2 Model B (checkpoints every 45), against the forward run alone;
+* "model_h": 2D Model H at 1024^2 (the paper's second benchmark model).
 
 Timing: the step graphs are built before any timed region (pss_step_prepare);
 the lattice runs on a torch stream, and HIP events recorded on that stream
@@ -19,7 +20,7 @@ bracket each timed run of K steps, with a device synchronisation on both
 sides; `value` is the median of 5 such runs.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-       [--workload modelb1024|ensemble|adjoint|3d] [--no-extras]
+       [--workload modelb1024|ensemble|adjoint|3d|modelh] [--no-extras]
 """
 
 import argparse
@@ -383,6 +384,59 @@ def three_d(args, pss, torch):
     }
 
 
+def model_h(args, pss, torch, cpu_steps=0):
+    """2D Model H 1024^2 FP32 (pss.model_h: a=-1 b=1 k=1, M=1, eta=0.5,
+    conserved noise 0.01 q^2 on phi, dt=0.01): three dynamic fields, two
+    gradient intermediates, eight product channels over five factor slots."""
+    n, dt = (1024, 1024), 0.01
+    stream = torch.cuda.Stream()
+    lat = pss.Lattice(n, dt=dt, seed=SEED)
+    lat.stream(stream.cuda_stream)
+    (phi, vx, vy), _ = pss.model_h(lat, a=A, b=B, k=K, M=1.0, eta=0.5, D=D)
+    lat.init_uniform(phi, -0.4, 0.4)
+    steps = min(args.steps, 500)
+    warm = min(args.warmup, 50)
+    lat.prepare(warm)
+    lat.prepare(steps)
+    lat.step(warm)
+    lat.sync()
+    times = timed_runs(torch, stream, lambda: lat.step(steps))
+    el = statistics.median(times)
+    sites = n[0] * n[1]
+    names = ("update_kernel", "xrow_kernel")
+    best = None
+    for w in range(lat.kernels_per_step()):
+        ms, _ = lat.time_kernel(w, max(10, args.kernel_reps // 10))
+        nb = lat.kernel_bytes(w)
+        log(f"bench: model h {names[w]} {ms * 1e3:.1f} us/launch, {nb / 1e6:.1f} MB -> "
+            f"{nb / (ms * 1e-3) / 1e9:.0f} GB/s")
+        if best is None or ms > best[0]:
+            best = (ms, nb, names[w])
+    ms, nb, kname = best
+    achieved = nb / (ms * 1e-3) / 1e9
+    log(f"bench: model h {1e6 * el / steps:.1f} us/step, {sites * steps / el:.4e} site-steps/s")
+    cpu = None
+    if cpu_steps > 0:
+        from oracle import model as om
+        from oracle.spectral import Lattice as OLattice
+        m = om.model_h(OLattice(n[0], n[1], 1), dt, a=A, b=B, k=K, M=1.0, eta=0.5, D=D, seed=SEED)
+        m.init_uniform(0, -0.4, 0.4)
+        m.step(1)
+        t0 = time.perf_counter()
+        m.step(cpu_steps)
+        cel = time.perf_counter() - t0
+        cpu = {"value": sites * cpu_steps / cel, "unit": "site-steps/s", "cores": os.cpu_count(),
+               "kind": "oracle", "sample": f"{cpu_steps} steps of the 1024x1024 Model H workload after 1 warm-up step"}
+    return {
+        "value": sites * steps / el, "unit": "site-steps/s", "steps": steps, "warmup": warm,
+        "ms_per_step": 1e3 * el / steps, "geometry": lat.geometry(),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
+                     "bytes_per_launch": nb, "us_per_launch": round(ms * 1e3, 3)},
+        "cpu_baseline": cpu,
+    }
+
+
 def line(workload, value, steps, warmup, ms_per_step, extra):
     out = {"metric": "site-steps/s", "value": value, "unit": "site-steps/s", "n_gpus": 1,
            "steps": steps, "warmup": warmup, "ms_per_step": ms_per_step,
@@ -402,11 +456,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="default workload: leave out the ensemble and adjoint measurements")
-    ap.add_argument("--workload", choices=("modelb1024", "ensemble", "adjoint", "3d"), default="modelb1024",
+    ap.add_argument("--workload", choices=("modelb1024", "ensemble", "adjoint", "3d", "modelh"),
+                    default="modelb1024",
                     help="modelb1024: one 1024^2 lattice, with the ensemble and adjoint measurements "
                          "(default); ensemble: 256x128^2 + 64x256^2 + 16x512^2 independent lattices in one "
                          "batch, also timed one lattice per launch; adjoint: gradient of the structure-factor "
-                         "loss through 2000 steps at 256^2; 3d: the two-field 256^3 system")
+                         "loss through 2000 steps at 256^2; 3d: the two-field 256^3 system; modelh: 2D "
+                         "Model H at 1024^2")
     ap.add_argument("--autotune", dest="autotune", action="store_true",
                     help="ensemble: pss_autotune's launch geometry per size instead of the default one (a class "
                          "whose tuned geometry does not fit the fused launches then runs launches of its own)")
@@ -453,6 +509,15 @@ def main():
     if args.workload == "3d":
         print(json.dumps(three_d(args, pss, torch)), flush=True)
         return
+    if args.workload == "modelh":
+        h = model_h(args, pss, torch, cpu_steps=0 if args.no_cpu else 3)
+        cfg = {"workload": "2D Model H 1024x1024 FP32: phi advected by an incompressible viscous flow driven by "
+                           "its interfaces, a=-1 b=1 k=1 M=1 eta=0.5, conserved noise D=0.01 q^2 on phi, "
+                           "dt=0.01, 2/3 radial de-aliasing, uniform[-0.4,0.4] initial phi",
+               "lattice": [1024, 1024], "parallelism": "single GPU", "geometry": h["geometry"]}
+        print(json.dumps(line(cfg, h["value"], h["steps"], h["warmup"], h["ms_per_step"],
+                              {"roofline": h["roofline"], "cpu_baseline": h["cpu_baseline"]})), flush=True)
+        return
 
     m = modelb1024(args, pss, torch)
     extras = {}
@@ -461,6 +526,9 @@ def main():
         extras["ensemble"] = ensemble(args, pss, torch, ens_steps)
         log("bench: adjoint workload")
         extras["adjoint"] = adjoint(args, pss, torch)
+        log("bench: model h workload")
+        h = model_h(args, pss, torch)
+        extras["model_h"] = {k: h[k] for k in ("value", "unit", "steps", "ms_per_step", "roofline")}
 
     if args.copy_mib > 0:
         nbytes = args.copy_mib << 20

@@ -30,7 +30,7 @@ enum {
 struct Bufs {
     float2* S[PSS_MAXF];   // state per field
     float2* N[PSS_MAXCH];  // product channels (x kernel writes, update kernel reads)
-    float2* V[PSS_MAXF];   // de-aliased inverse transforms per factor slot
+    float2* V[PSS_MAXG];   // de-aliased inverse transforms per factor slot
     const float2* in;
     float2* out;
     const float* real_in;

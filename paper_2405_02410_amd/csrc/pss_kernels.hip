@@ -1304,10 +1304,16 @@ __device__ __forceinline__ void xrow_block(int mi, int blk, const Member* __rest
             *step_ctr_a += static_cast<uint64_t>(advance);
         }
     }
-    // real-space values of every factor field
+    // real-space values of every factor field (the variant with room for
+    // more than four holds zeros in the slots beyond the plan's)
     float2 z[NG][P];
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
+        if (NG > 4 && g >= p.ng) {
+#pragma unroll
+            for (int m = 0; m < P; ++m) z[g][m] = make_float2(0.f, 0.f);
+            continue;
+        }
         float2 v[P];
         build_z(v, bufs.V[g], p.mask[g].ncol);
         if (g == 0) {
@@ -1326,16 +1332,16 @@ __device__ __forceinline__ void xrow_block(int mi, int blk, const Member* __rest
         for (int m = 0; m < P; ++m) w[m] = make_float2(0.f, 0.f);
         for (int k = 0; k < C.nprod; ++k) {
             const DevProd& pd = C.prod[k];
-            // the factor powers read as one 32-bit word (a scalar load)
-            static_assert(sizeof(pd.pow) == 4, "four factor slots");
-            uint32_t pw;
+            // the factor powers read as one 64-bit word (a scalar load)
+            static_assert(sizeof(pd.pow) == 8, "eight factor slots");
+            uint64_t pw;
             __builtin_memcpy(&pw, pd.pow, sizeof(pw));
 #pragma unroll
             for (int m = 0; m < P; ++m) {
                 float a = pd.coef, b = pd.coef;
 #pragma unroll
                 for (int g = 0; g < NG; ++g) {
-                    const int pg = static_cast<int>((pw >> (8 * g)) & 0xffu);
+                    const int pg = static_cast<int>((pw >> (8 * g)) & 0xffull);
                     for (int e = 0; e < pg; ++e) {
                         a *= z[g][m].x;
                         b *= z[g][m].y;
@@ -1688,9 +1694,9 @@ __global__ void __launch_bounds__(N / 4 < 64 ? 64 : N / 4)
             for (int m = 0; m < P; ++m) acc[f][m] = make_float2(0.f, 0.f);
         if (p.nch == 0) return;
         // real-space values of the de-aliased factors at x = t + m T
-        float u[PSS_MAXF][P];
+        float u[PSS_MAXG][P];
 #pragma unroll
-        for (int g = 0; g < PSS_MAXF; ++g) {
+        for (int g = 0; g < PSS_MAXG; ++g) {
             if (g >= p.ng) break;
             const DevMask& mk = p.mask[g];
             float2 v[P];
@@ -1711,14 +1717,15 @@ __global__ void __launch_bounds__(N / 4 < 64 ? 64 : N / 4)
             for (int m = 0; m < P; ++m) w[m] = make_float2(0.f, 0.f);
             for (int k = 0; k < C.nprod; ++k) {
                 const DevProd& pd = C.prod[k];
-                uint32_t pw;
+                uint64_t pw;
                 __builtin_memcpy(&pw, pd.pow, sizeof(pw));
 #pragma unroll
                 for (int m = 0; m < P; ++m) {
                     float a = pd.coef;
 #pragma unroll
-                    for (int g = 0; g < PSS_MAXF; ++g) {
-                        const int pg = static_cast<int>((pw >> (8 * g)) & 0xffu);
+                    for (int g = 0; g < PSS_MAXG; ++g) {
+                        if (g >= p.ng) break;
+                        const int pg = static_cast<int>((pw >> (8 * g)) & 0xffull);
                         for (int e = 0; e < pg; ++e) a *= u[g][m];
                     }
                     w[m].x += a;
@@ -2029,6 +2036,11 @@ hipError_t PSS_CAT(launch_xrow_L, PSS_LINE_LEN)(int mode, int ng, const LaunchAr
         return with_points<L, 4>(px, [&](auto P) { return launch_xrow_t<L, decltype(P)::value, 3>(mode, a); });
     if (ng == 4)
         return with_points<L, 4>(px, [&](auto P) { return launch_xrow_t<L, decltype(P)::value, 4>(mode, a); });
+    if (mode != MODE_STEP) return hipErrorInvalidValue;
+    // five to eight factor slots (multi-field flow models): one variant with
+    // room for eight, 4 points per thread
+    if (ng <= PSS_MAXG)
+        return with_points<L, 4>(px, [&](auto P) { return launch_xrow_t<L, decltype(P)::value, PSS_MAXG>(mode, a); });
     return hipErrorInvalidValue;
 }
 #endif  // PSS_LINE_LEN
@@ -2335,9 +2347,7 @@ __global__ void __launch_bounds__(resident_threads(LX, LY)) resident_kernel(Resi
             for (int m = 0; m < P; ++m) w[m] = make_float2(0.f, 0.f);
             for (int k = 0; k < C.nprod; ++k) {
                 const DevProd& pd = C.prod[k];
-                uint32_t pw;
-                __builtin_memcpy(&pw, pd.pow, sizeof(pw));
-                const int pg = static_cast<int>(pw & 0xffu);
+                const int pg = static_cast<int>(pd.pow[0]);
 #pragma unroll
                 for (int m = 0; m < P; ++m) {
                     float a = pd.coef, b = pd.coef;

@@ -31,6 +31,7 @@
 #define PSS_MAXD 8    // Fourier-space (single linear factor) terms
 #define PSS_MAXPOW 8  // largest factor power / operator power
 #define PSS_MAXI 4    // intermediate (non-dynamic) fields
+#define PSS_MAXG 8    // factor slots: distinct fields in real-space products
 
 namespace pss {
 
@@ -51,7 +52,7 @@ struct DevOp {
 
 struct DevProd {
     float coef;
-    int8_t pow[PSS_MAXF];  // power of each factor slot
+    int8_t pow[PSS_MAXG];  // power of each factor slot (read as one 64-bit word)
 };
 
 struct DevChannel {
@@ -103,8 +104,8 @@ struct DevPlan {
     uint32_t key0, key1;
     int32_t noisy[PSS_MAXF];
     int32_t fid[PSS_MAXF];     // declaration index of each dynamic field (its random-number key)
-    int32_t gfield[PSS_MAXF];  // factor slot -> dynamic field, or PSS_MAXF + intermediate
-    DevMask mask[PSS_MAXF];    // per factor slot
+    int32_t gfield[PSS_MAXG];  // factor slot -> dynamic field, or PSS_MAXF + intermediate
+    DevMask mask[PSS_MAXG];    // per factor slot
     DevOp implicit_op[PSS_MAXF];
     DevOp noise_op[PSS_MAXF];
     DevDirect direct[PSS_MAXD];

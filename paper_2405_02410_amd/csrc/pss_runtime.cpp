@@ -520,8 +520,8 @@ pss_status build_plan(pss_ctx* c) {
     for (int code = 0; code < PSS_MAXF + PSS_MAXI; ++code) {
         gslot[code] = -1;
         if (order[code] > 0) {
-            if (P.ng >= PSS_MAXF)
-                return fail(PSS_E_UNSUPPORTED, "at most %d distinct fields in real-space products", PSS_MAXF);
+            if (P.ng >= PSS_MAXG)
+                return fail(PSS_E_UNSUPPORTED, "at most %d distinct fields in real-space products", PSS_MAXG);
             gslot[code] = P.ng;
             P.gfield[P.ng] = code;
             P.mask[P.ng] = make_mask(c, c->rule, c->shape, order[code]);

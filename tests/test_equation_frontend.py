@@ -135,3 +135,27 @@ def test_noise_strings():
     bad.noise_expr(f, "-0.1*q^2")  # negative D(q): refused when validated
     with pytest.raises(PssError):
         bad.validate()
+
+
+def test_model_h_strings_equal_the_helper():
+    # the projected stress of Model H written out as equation strings
+    lat = _lat()
+    for name, v in (("a", -1.0), ("b", 1.0), ("k", 0.8), ("M", 1.2), ("eta", 0.5), ("D", 0.01)):
+        lat.param(name, v)
+    phi = lat.field("phi")
+    lat.field("vx")
+    lat.field("vy")
+    lat.field("dx_phi", dynamic=False)
+    lat.field("dy_phi", dynamic=False)
+    lat.equation("dx_phi = iqx*phi")
+    lat.equation("dy_phi = iqy*phi")
+    lat.equation("dt phi + M*(a*q^2 + k*q^4)*phi = -M*b*q^2*phi^3 - vx*dx_phi - vy*dy_phi")
+    lat.equation("dt vx + eta*q^2*vx = -k*(iqx + iqx^3/q^2)*dx_phi^2"
+                 " - k*(iqy + 2*iqx^2*iqy/q^2)*dx_phi*dy_phi - k*iqx*iqy^2/q^2*dy_phi^2")
+    lat.equation("dt vy + eta*q^2*vy = -k*iqx^2*iqy/q^2*dx_phi^2"
+                 " - k*(iqx + 2*iqx*iqy^2/q^2)*dx_phi*dy_phi - k*(iqy + iqy^3/q^2)*dy_phi^2")
+    lat.noise_expr(phi, "D*q^2")
+    ref = _lat()
+    pss.model_h(ref, a=-1.0, b=1.0, k=0.8, M=1.2, eta=0.5, D=0.01)
+    assert sorted(_norm(lat.terms())) == sorted(_norm(ref.terms()))
+    lat.validate()
