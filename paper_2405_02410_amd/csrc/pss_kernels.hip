@@ -99,6 +99,7 @@ __device__ __forceinline__ void block_sum_to_slot(double (&v)[NV], double* __res
 // ----------------------------------------------------------------- modes
 struct ModeQ {
     float q2;
+    float invq;  // 1/|q| (0 at q = 0)
     float iq[3];
 };
 
@@ -114,13 +115,14 @@ __device__ __forceinline__ ModeQ mode_q(const DevPlan& p, int kx, int ky, int kz
     m.iq[0] = (kx == -(p.n[0] >> 1)) ? 0.f : qx;
     m.iq[1] = (ky == -(p.n[1] >> 1)) ? 0.f : qy;
     m.iq[2] = (p.n[2] > 1 && kz == -(p.n[2] >> 1)) ? 0.f : qz;
+    m.invq = m.q2 > 0.f ? 1.f / sqrtf(m.q2) : 0.f;
     return m;
 }
 
-// monomials with 1/|q| or i q_i factors (rare): kept out of line so the common
-// pure-q^2 path stays a short Horner loop
-__device__ __noinline__ float2 eval_general(const DevOp& op, float q2, float iqx, float iqy, float iqz) {
-    const float invq = q2 > 0.f ? 1.f / sqrtf(q2) : 0.f;
+// monomials with 1/|q| or i q_i factors, evaluated only by the kernel
+// variants built for plans that have them
+__device__ __forceinline__ float2 eval_general(const DevOp& op, const ModeQ& q) {
+    const float q2 = q.q2, invq = q.invq, iqx = q.iq[0], iqy = q.iq[1], iqz = q.iq[2];
     float re = 0.f, im = 0.f;
     for (int i = 0; i < op.n; ++i) {
         const DevMono mo = op.m[i];
@@ -177,7 +179,7 @@ __device__ __forceinline__ float2 eval_op(const DevOp& op, const ModeQ& q) {
     const float re = horner(op, q.q2);
     if constexpr (GEN) {
         if (op.n != 0) {
-            const float2 g = eval_general(op, q.q2, q.iq[0], q.iq[1], q.iq[2]);
+            const float2 g = eval_general(op, q);
             return make_float2(re + g.x, g.y);
         }
     }
@@ -265,21 +267,37 @@ __device__ __forceinline__ void mode_lin(const DevPlan& p, int kx, int ky, int k
     lneg = lin_index(p, (nx - ux) & (nx - 1), (ny - uy) & (ny - 1), (nz - uz) & (nz - 1));
 }
 
-// select element F of a register array with a runtime index (unrolled)
+// Element f of a register array, f a runtime (block-uniform) field index.
+// Written with bit masks rather than a chain of conditional copies: the
+// compiler folds such a chain back into an indexed access, which moves the
+// whole array to scratch memory.
 template <int NF, int P>
 __device__ __forceinline__ float2 pick(const float2 (&a)[NF][P], int f, int m) {
-    float2 r = a[0][m];
+    if constexpr (NF == 1) return a[0][m];
+    uint32_t rx = 0u, ry = 0u;
 #pragma unroll
-    for (int i = 1; i < NF; ++i)
-        if (f == i) r = a[i][m];
-    return r;
+    for (int i = 0; i < NF; ++i) {
+        const uint32_t mk = f == i ? 0xffffffffu : 0u;
+        rx |= __float_as_uint(a[i][m].x) & mk;
+        ry |= __float_as_uint(a[i][m].y) & mk;
+    }
+    return make_float2(__uint_as_float(rx), __uint_as_float(ry));
 }
 
+// a[f][m] += v, f a runtime field index: every element takes v or +0 (bit
+// masks, for the reason given at pick)
 template <int NF, int P>
 __device__ __forceinline__ void add_to(float2 (&a)[NF][P], int f, int m, float2 v) {
+    if constexpr (NF == 1) {
+        if (f == 0) a[0][m] = cadd(a[0][m], v);
+        return;
+    }
 #pragma unroll
-    for (int i = 0; i < NF; ++i)
-        if (f == i) a[i][m] = cadd(a[i][m], v);
+    for (int i = 0; i < NF; ++i) {
+        const uint32_t mk = f == i ? 0xffffffffu : 0u;
+        a[i][m].x += __uint_as_float(__float_as_uint(v.x) & mk);
+        a[i][m].y += __uint_as_float(__float_as_uint(v.y) & mk);
+    }
 }
 
 // ------------------------------------------------------------ update kernel
@@ -666,6 +684,12 @@ __device__ __forceinline__ void update_block(int mi, int blk, const Member* __re
         uint32_t lin[P], lneg[P];
 #pragma unroll
         for (int m = 0; m < P; ++m) slot_at<L>(lmode, t + m * T, q2[m], lin[m], lneg[m]);
+        // general operators: the mode vectors of the slots, once per line
+        ModeQ qv[GEN ? P : 1];
+        if constexpr (GEN) {
+#pragma unroll
+            for (int m = 0; m < P; ++m) qv[m] = slot_q<L, DIM>(p, lmode, t + m * T);
+        }
         __syncthreads();  // twiddles in LDS
         float2 acc[NF][P];  // explicit contributions
 #pragma unroll
@@ -684,20 +708,27 @@ __device__ __forceinline__ void update_block(int mi, int blk, const Member* __re
             }
             FFT::template dit<-1>(v, ld, t, tw);
             exchange(v, true);
-            if constexpr (GEN) {
+            // each output: its operator times the transform, into its field
+            // (one field: one output, so the loop is left out)
+            const int nout = NF == 1 ? 1 : C.nout;
+            for (int o = 0; o < nout; ++o) {
+                const DevOp& op = C.op[o];
+                const int tg = C.target[o];
+                if constexpr (GEN) {
 #pragma unroll
-                for (int m = 0; m < P; ++m)
-                    if (!(pair_lane && (m == 0 || m == P / 2)))
-                        add_to(acc, C.target, m, cmul(eval_op<GEN>(C.op, slot_q<L, DIM>(p, lmode, t + m * T)), v[m]));
-            } else {
-                float M[P];
-                horner_p(C.op, q2, M);
+                    for (int m = 0; m < P; ++m)
+                        if (!(pair_lane && (m == 0 || m == P / 2)))
+                            add_to(acc, tg, m, cmul(eval_op<GEN>(op, qv[m]), v[m]));
+                } else {
+                    float M[P];
+                    horner_p(op, q2, M);
 #pragma unroll
-                for (int m = 0; m < P; ++m)
-                    if (!(pair_lane && (m == 0 || m == P / 2))) add_to(acc, C.target, m, cscale(v[m], M[m]));
+                    for (int m = 0; m < P; ++m)
+                        if (!(pair_lane && (m == 0 || m == P / 2))) add_to(acc, tg, m, cscale(v[m], M[m]));
+                }
+                // slots 0 and L/2 of a packed line: two real modes (operators are real on them)
+                if (pair_lane) pair_accumulate<DIM, GEN>(acc, tg, v, p, op, ky_l, L);
             }
-            // slots 0 and L/2 of a packed line: two real modes (operators are real on them)
-            if (pair_lane) pair_accumulate<DIM, GEN>(acc, C.target, v, p, C.op, ky_l, L);
         }
         // Fourier-space terms with a single linear factor
         for (int d = 0; d < p.nd; ++d) {
@@ -708,7 +739,7 @@ __device__ __forceinline__ void update_block(int mi, int blk, const Member* __re
 #pragma unroll
                 for (int m = 0; m < P; ++m)
                     if (!(pair_lane && (m == 0 || m == P / 2)))
-                        add_to(acc, Dd.target, m, cmul(eval_op<GEN>(Dd.op, slot_q<L, DIM>(p, lmode, t + m * T)), src[m]));
+                        add_to(acc, Dd.target, m, cmul(eval_op<GEN>(Dd.op, qv[m]), src[m]));
             } else {
                 float M[P];
                 horner_p(Dd.op, q2, M);
@@ -734,7 +765,7 @@ __device__ __forceinline__ void update_block(int mi, int blk, const Member* __re
             for (int m = 0; m < P; ++m) {
                 float2 r = cadd(s[f][m], cscale(acc[f][m], p.dt));
                 if constexpr (GEN) {
-                    const ModeQ q = slot_q<L, DIM>(p, lmode, t + m * T);
+                    const ModeQ& q = qv[m];
                     if (noisy) r = cadd(r, noise_mode<GEN>(p, f, step, lin[m], lneg[m], q));
                     s[f][m] = cmul(r, cinv_implicit(p.dt, eval_op<GEN>(p.implicit_op[f], q)));
                 } else {
@@ -1732,8 +1763,9 @@ __global__ void __launch_bounds__(N / 4 < 64 ? 64 : N / 4)
                 }
             }
             FFT::template dif<-1>(w, ld, t, tw);
+            for (int o = 0; o < C.nout; ++o)
 #pragma unroll
-            for (int m = 0; m < P; ++m) add_to(acc, C.target, m, cmul(eval_op<GEN>(C.op, q[m]), w[m]));
+                for (int m = 0; m < P; ++m) add_to(acc, C.target[o], m, cmul(eval_op<GEN>(C.op[o], q[m]), w[m]));
         }
     };
 
@@ -2232,11 +2264,11 @@ __global__ void __launch_bounds__(resident_threads(LX, LY)) resident_kernel(Resi
                 FY::template dit<-1>(v, ldc, tcol, twy);
                 exchange(v, true);
                 float M[P];
-                horner_p(C.op, q2, M);
+                horner_p(C.op[0], q2, M);
 #pragma unroll
                 for (int m = 0; m < P; ++m)
-                    if (!(pair_lane && (m == 0 || m == P / 2))) add_to(acc, C.target, m, cscale(v[m], M[m]));
-                if (pair_lane) pair_accumulate<2, false>(acc, C.target, v, p, C.op, ky_l, LY);
+                    if (!(pair_lane && (m == 0 || m == P / 2))) add_to(acc, C.target[0], m, cscale(v[m], M[m]));
+                if (pair_lane) pair_accumulate<2, false>(acc, C.target[0], v, p, C.op[0], ky_l, LY);
             }
             for (int d = 0; d < p.nd; ++d) {
                 const DevDirect& Dd = p.direct[d];

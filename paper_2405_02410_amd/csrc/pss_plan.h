@@ -32,6 +32,7 @@
 #define PSS_MAXPOW 8  // largest factor power / operator power
 #define PSS_MAXI 4    // intermediate (non-dynamic) fields
 #define PSS_MAXG 8    // factor slots: distinct fields in real-space products
+#define PSS_MAXO 3    // outputs (target field, operator) of one product channel
 
 namespace pss {
 
@@ -55,10 +56,15 @@ struct DevProd {
     int8_t pow[PSS_MAXG];  // power of each factor slot (read as one 64-bit word)
 };
 
+// A real-space product channel: F[sum_p coef_p prod_g u_g^pow] is formed once
+// and feeds nout field updates, output o adding op[o](q) times it to field
+// target[o] (distinct targets; e.g. the stress products of a flow model feed
+// every velocity component).
 struct DevChannel {
-    int32_t target;  // field whose update receives M(q) * F[sum_p coef_p prod_g u_g^pow]
     int32_t nprod;
-    DevOp op;
+    int32_t nout;
+    int32_t target[PSS_MAXO];
+    DevOp op[PSS_MAXO];
     DevProd prod[PSS_MAXPT];
 };
 

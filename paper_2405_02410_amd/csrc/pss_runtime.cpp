@@ -529,35 +529,35 @@ pss_status build_plan(pss_ctx* c) {
         }
     }
     // channels; single-monomial terms with the same target and shape share one
-    std::tuple<int, int, int, int, int, int> chan_key[PSS_MAXCH];
+    std::vector<DevChannel> chs;
+    std::vector<std::tuple<int, int, int, int, int, int>> chan_key;
     for (Term& t : c->terms) {
         if (t.implicit || t.kind == 1 || t.kind == 4) continue;
         const bool single = t.op.size() == 1;
+        const auto key = single ? std::make_tuple(t.target, t.op[0].q2, t.op[0].invq, t.op[0].iq[0], t.op[0].iq[1],
+                                                  t.op[0].iq[2])
+                                : std::make_tuple(-1, 0, 0, 0, 0, 0);
         int ch = -1;
         if (single) {
-            for (int k = 0; k < P.nch; ++k)
-                if (chan_key[k] == std::make_tuple(t.target, t.op[0].q2, t.op[0].invq, t.op[0].iq[0], t.op[0].iq[1],
-                                                   t.op[0].iq[2]) &&
-                    P.ch[k].nprod < PSS_MAXPT)
-                    ch = k;
+            for (size_t k = 0; k < chs.size(); ++k)
+                if (chan_key[k] == key && chs[k].nprod < PSS_MAXPT) ch = static_cast<int>(k);
         }
         if (ch < 0) {
-            if (P.nch >= PSS_MAXCH) return fail(PSS_E_UNSUPPORTED, "more than %d product channels", PSS_MAXCH);
-            ch = P.nch++;
-            chan_key[ch] = single ? std::make_tuple(t.target, t.op[0].q2, t.op[0].invq, t.op[0].iq[0], t.op[0].iq[1],
-                                                    t.op[0].iq[2])
-                                  : std::make_tuple(-1, 0, 0, 0, 0, 0);
-            DevChannel& C = P.ch[ch];
-            C.target = t.target;
+            ch = static_cast<int>(chs.size());
+            chs.push_back(DevChannel{});
+            chan_key.push_back(key);
+            DevChannel& C = chs.back();
+            C.nout = 1;
+            C.target[0] = t.target;
             if (single) {
                 Mono unit = t.op[0];
                 unit.coef = 1.0;
-                put_mono(C.op, unit);
+                put_mono(C.op[0], unit);
             } else {
-                for (const Mono& m : t.op) put_mono(C.op, m);
+                for (const Mono& m : t.op) put_mono(C.op[0], m);
             }
         }
-        DevChannel& C = P.ch[ch];
+        DevChannel& C = chs[ch];
         DevProd& pd = C.prod[C.nprod];
         pd.coef = single ? static_cast<float>(t.op[0].coef) : 1.f;
         for (auto& fp : t.factors) pd.pow[gslot[fp.first]] += static_cast<int8_t>(fp.second);
@@ -566,6 +566,60 @@ pss_status build_plan(pss_ctx* c) {
         t.prod = C.nprod;
         t.mono0 = 0;
         ++C.nprod;
+    }
+    // channels forming the same products (up to one common factor r) for
+    // different fields share one transform: the later one becomes another
+    // output of the earlier, its operator scaled by r
+    {
+        auto same_products = [](const DevChannel& x, const DevChannel& y, double* r) {
+            if (x.nprod != y.nprod || x.nprod == 0 || x.prod[0].coef == 0.f) return false;
+            for (int i = 0; i < x.nprod; ++i) {
+                if (std::memcmp(x.prod[i].pow, y.prod[i].pow, sizeof(x.prod[i].pow)) != 0) return false;
+                // y_i / x_i == y_0 / x_0, exactly (products of two floats are exact in double)
+                if (static_cast<double>(y.prod[i].coef) * x.prod[0].coef !=
+                    static_cast<double>(x.prod[i].coef) * y.prod[0].coef)
+                    return false;
+            }
+            *r = static_cast<double>(y.prod[0].coef) / x.prod[0].coef;
+            return true;
+        };
+        auto scaled = [](const DevOp& op, double r) {
+            DevOp o = op;
+            for (int j = 0; j <= PSS_MAXPOW; ++j) o.poly[j] = static_cast<float>(r * op.poly[j]);
+            for (int i = 0; i < op.n; ++i) o.m[i].coef = static_cast<float>(r * op.m[i].coef);
+            return o;
+        };
+        auto has_target = [](const DevChannel& x, int f) {
+            for (int o = 0; o < x.nout; ++o)
+                if (x.target[o] == f) return true;
+            return false;
+        };
+        std::vector<int> remap(chs.size());
+        std::vector<DevChannel> merged;
+        for (size_t k = 0; k < chs.size(); ++k) {
+            int into = -1;
+            double r = 1.0;
+            for (size_t j = 0; j < merged.size() && into < 0; ++j)
+                if (merged[j].nout < PSS_MAXO && !has_target(merged[j], chs[k].target[0]) &&
+                    same_products(merged[j], chs[k], &r))
+                    into = static_cast<int>(j);
+            if (into >= 0) {
+                DevChannel& D = merged[into];
+                D.target[D.nout] = chs[k].target[0];
+                D.op[D.nout] = r == 1.0 ? chs[k].op[0] : scaled(chs[k].op[0], r);
+                ++D.nout;
+                remap[k] = into;
+            } else {
+                remap[k] = static_cast<int>(merged.size());
+                merged.push_back(chs[k]);
+            }
+        }
+        if (merged.size() > PSS_MAXCH)
+            return fail(PSS_E_UNSUPPORTED, "%zu product channels (at most %d)", merged.size(), PSS_MAXCH);
+        P.nch = static_cast<int32_t>(merged.size());
+        for (size_t k = 0; k < merged.size(); ++k) P.ch[k] = merged[k];
+        for (Term& t : c->terms)
+            if (t.kind == 2 || t.kind == 3) t.slot = remap[t.slot];
     }
     // Horner degree of every operator
     auto set_deg = [](DevOp& op) {
@@ -581,7 +635,8 @@ pss_status build_plan(pss_ctx* c) {
         set_deg(P.noise_op[f]);
     }
     for (int d = 0; d < P.nd; ++d) set_deg(P.direct[d].op);
-    for (int k = 0; k < P.nch; ++k) set_deg(P.ch[k].op);
+    for (int k = 0; k < P.nch; ++k)
+        for (int o = 0; o < P.ch[k].nout; ++o) set_deg(P.ch[k].op[o]);
     for (int i = 0; i < ni; ++i) {
         set_deg(P.interm[i].den);
         for (int k = 0; k < P.interm[i].nsrc; ++k) set_deg(P.interm[i].op[k]);
@@ -590,7 +645,8 @@ pss_status build_plan(pss_ctx* c) {
     P.general = 0;
     for (int f = 0; f < nf; ++f) P.general |= (P.implicit_op[f].n > 0) | (P.noise_op[f].n > 0);
     for (int d = 0; d < P.nd; ++d) P.general |= P.direct[d].op.n > 0;
-    for (int k = 0; k < P.nch; ++k) P.general |= P.ch[k].op.n > 0;
+    for (int k = 0; k < P.nch; ++k)
+        for (int o = 0; o < P.ch[k].nout; ++o) P.general |= P.ch[k].op[o].n > 0;
     P.general |= ni > 0;  // intermediates are evaluated by the general-operator code
     for (int f = 0; f < nf; ++f) {  // boundary frames already on the device
         P.frame[f] = c->d_frame[f];
