@@ -678,7 +678,6 @@ __device__ __forceinline__ void update_block(int mi, int blk, const Member* __re
 #pragma unroll
             for (int m = 0; m < P; ++m) nxt[m] = gload(bufs.N[0] + base + (t + m * T) * tc);
         }
-        store_twiddles<L, P>(twl, twr, tid, nthr);
         // per-slot modes of the line (slot form on a packed line)
         float q2[P];
         uint32_t lin[P], lneg[P];
@@ -690,6 +689,24 @@ __device__ __forceinline__ void update_block(int mi, int blk, const Member* __re
 #pragma unroll
             for (int m = 0; m < P; ++m) qv[m] = slot_q<L, DIM>(p, lmode, t + m * T);
         }
+        // the step's noise depends on the step and the modes only: formed
+        // here, while the loads above are still in flight
+        float2 eta[GEN ? 1 : NF][P];
+        if constexpr (!GEN) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                if (f < nf && p.noisy[f] != 0) {
+                    float Dn[P];
+                    horner_p(p.noise_op[f], q2, Dn);
+#pragma unroll
+                    for (int m = 0; m < P; ++m) eta[f][m] = noise_value(p, f, step, lin[m], lneg[m], Dn[m]);
+                } else {
+#pragma unroll
+                    for (int m = 0; m < P; ++m) eta[f][m] = make_float2(0.f, 0.f);
+                }
+            }
+        }
+        store_twiddles<L, P>(twl, twr, tid, nthr);  // waits for the twiddle loads
         __syncthreads();  // twiddles in LDS
         float2 acc[NF][P];  // explicit contributions
 #pragma unroll
@@ -756,11 +773,8 @@ __device__ __forceinline__ void update_block(int mi, int blk, const Member* __re
             if (f >= nf) continue;
             const bool noisy = p.noisy[f] != 0;
             const float2 old0 = s[f][0], oldh = s[f][P / 2];
-            float Ar[P], Dn[P];
-            if constexpr (!GEN) {
-                horner_p(p.implicit_op[f], q2, Ar);
-                if (noisy) horner_p(p.noise_op[f], q2, Dn);
-            }
+            float Ar[P];
+            if constexpr (!GEN) horner_p(p.implicit_op[f], q2, Ar);
 #pragma unroll
             for (int m = 0; m < P; ++m) {
                 float2 r = cadd(s[f][m], cscale(acc[f][m], p.dt));
@@ -769,7 +783,7 @@ __device__ __forceinline__ void update_block(int mi, int blk, const Member* __re
                     if (noisy) r = cadd(r, noise_mode<GEN>(p, f, step, lin[m], lneg[m], q));
                     s[f][m] = cmul(r, cinv_implicit(p.dt, eval_op<GEN>(p.implicit_op[f], q)));
                 } else {
-                    if (noisy) r = cadd(r, noise_value(p, f, step, lin[m], lneg[m], Dn[m]));
+                    if (noisy) r = cadd(r, eta[f][m]);
                     s[f][m] = cscale(r, __builtin_amdgcn_rcpf(fmaf(-p.dt, Ar[m], 1.f)));
                 }
             }
