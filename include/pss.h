@@ -309,6 +309,30 @@ pss_status pss_step_index(pss_ctx *ctx, int64_t *out);
  * Uploads, uniform initialisation and state loads also clear it. */
 pss_status pss_sync(pss_ctx *ctx);
 
+/* Let caller-owned device memory (for example a torch tensor) hold the
+ * Fourier state of dynamic field `field` instead of memory the library
+ * allocates.  device_ptr: device memory on the context's device, 8-byte
+ * aligned, at least pss_field_state_bytes(field) bytes (`bytes` is the size
+ * the caller has); the caller keeps it alive until the lattice is destroyed,
+ * and the library never frees it.  Call before the plan is built (the first
+ * call that needs the device): PSS_E_STATE afterwards; PSS_E_INVAL for a null,
+ * misaligned or short buffer or an intermediate field, and, when the plan is
+ * built, for memory that is not device memory.  Building the plan clears it to
+ * zero, as it does the library's own.  Layout: the library's packed spectral
+ * layout of the field, byte for byte the field's block of pss_state_save.  The
+ * library reads and writes it on the context's stream; a caller that writes
+ * it directly must then call pss_state_changed. */
+pss_status pss_field_bind(pss_ctx *ctx, int32_t field, void *device_ptr, size_t bytes);
+
+/* Bytes of one dynamic field's Fourier state (8 bytes per stored complex
+ * mode: (Nx/2) Ny Nz in 2D and 3D, Nx in 1D). */
+pss_status pss_field_state_bytes(pss_ctx *ctx, int32_t field, size_t *bytes);
+
+/* Tell the library that the state changed outside its calls (memory bound
+ * with pss_field_bind written by the caller): the next step rebuilds its
+ * real-space products from the state. */
+pss_status pss_state_changed(pss_ctx *ctx);
+
 /* Bytes needed by pss_state_save. */
 pss_status pss_state_size(pss_ctx *ctx, size_t *bytes);
 

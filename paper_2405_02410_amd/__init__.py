@@ -87,6 +87,9 @@ _SIGS = {
     "pss_step_index": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)],
     "pss_sync": [ctypes.c_void_p],
     "pss_state_size": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "pss_field_bind": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t],
+    "pss_field_state_bytes": [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
+    "pss_state_changed": [ctypes.c_void_p],
     "pss_state_save": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t],
     "pss_state_load": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t],
     "pss_mass": [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
@@ -190,6 +193,7 @@ class Lattice:
         self.shape = tuple(reversed(n))  # numpy order (z, y, x)
         self.sites = int(np.prod(n))
         self.names = []
+        self._bound = []  # tensors that hold field states (kept alive with the lattice)
         _check(lib().pss_seed_set(self._h, int(seed) & 0xFFFFFFFFFFFFFFFF))
         _check(lib().pss_dealias_set(self._h, int(dealias), int(shape)))
 
@@ -338,6 +342,26 @@ class Lattice:
         a = np.empty(self.shape[:-1] + (nh, 2), dtype=np.float32)
         _check(lib().pss_spectrum_download(self._h, int(field), a.ctypes.data_as(ctypes.c_void_p), 0))
         return a[..., 0] + 1j * a[..., 1]
+
+    def state_bytes(self, field):
+        """Bytes of the field's Fourier state (pss_field_state_bytes)."""
+        v = ctypes.c_size_t()
+        _check(lib().pss_field_state_bytes(self._h, int(field), ctypes.byref(v)))
+        return v.value
+
+    def bind(self, field, tensor):
+        """Let a contiguous torch CUDA tensor of at least state_bytes(field)
+        bytes hold the field's Fourier state (pss_field_bind); before the first
+        call that builds the plan.  The lattice keeps a reference to it."""
+        if not getattr(tensor, "is_cuda", False) or not tensor.is_contiguous():
+            raise ValueError("bind takes a contiguous CUDA tensor")
+        nbytes = tensor.numel() * tensor.element_size()
+        _check(lib().pss_field_bind(self._h, int(field), ctypes.c_void_p(tensor.data_ptr()), nbytes))
+        self._bound.append(tensor)
+
+    def state_changed(self):
+        """After writing a bound state tensor directly (pss_state_changed)."""
+        _check(lib().pss_state_changed(self._h))
 
     def step(self, n=1):
         _check(lib().pss_step(self._h, int(n)))

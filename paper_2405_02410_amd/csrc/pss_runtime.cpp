@@ -175,6 +175,8 @@ struct pss_ctx {
     // d_chan: channel inputs of the update kernel; d_chan_x: x-kernel outputs
     // (the same arrays in 2D; in 3D the forward y pass maps one to the other)
     std::vector<float2*> d_state, d_chan, d_chan_x, d_v;
+    void* bound[PSS_MAXF] = {};       // caller-owned state memory per dynamic field (pss_field_bind)
+    size_t bound_bytes[PSS_MAXF] = {};
     float2* d_tmp = nullptr;
     float2* d_tmp2 = nullptr;
     float* d_real = nullptr;
@@ -764,7 +766,12 @@ void free_device(pss_ctx* c) {
         if (p) (void)hipFree(p);
         p = nullptr;
     };
-    for (auto*& p : c->d_state) rel(p);
+    for (size_t f = 0; f < c->d_state.size(); ++f) {
+        if (f < PSS_MAXF && c->d_state[f] == c->bound[f])
+            c->d_state[f] = nullptr;  // the caller's memory: not ours to free
+        else
+            rel(c->d_state[f]);
+    }
     for (size_t k = 0; k < c->d_chan_x.size(); ++k)
         if (c->d_chan_x[k] != c->d_chan[k]) rel(c->d_chan_x[k]);
     c->d_chan_x.clear();
@@ -898,8 +905,18 @@ pss_status materialize(pss_ctx* c) {
     c->d_state.assign(nf, nullptr);
     c->d_chan.assign(c->plan.nch, nullptr);
     c->d_v.assign(c->plan.ng, nullptr);
-    for (auto*& p : c->d_state) {
-        HIP_TRY(hipMalloc(&p, bytes));
+    for (int f = 0; f < nf; ++f) {
+        float2*& p = c->d_state[f];
+        if (c->bound[f]) {
+            // caller-owned memory (pss_field_bind): it must be device memory
+            hipPointerAttribute_t at{};
+            HIP_TRY(hipPointerGetAttributes(&at, c->bound[f]));
+            if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+                return fail(PSS_E_INVAL, "the memory bound to field %d is not device memory", f);
+            p = static_cast<float2*>(c->bound[f]);
+        } else {
+            HIP_TRY(hipMalloc(&p, bytes));
+        }
         HIP_TRY(hipMemset(p, 0, bytes));
     }
     for (auto*& p : c->d_chan) {
@@ -2014,6 +2031,37 @@ pss_status pss_state_size(pss_ctx* c, size_t* bytes) {
     if (pss_status s = check_ctx(c)) return s;
     if (!bytes) return fail(PSS_E_INVAL, "null output");
     *bytes = sizeof(SaveHeader) + c->fields.size() * sizeof(float2) * static_cast<size_t>(c->packed());
+    return PSS_OK;
+}
+
+pss_status pss_field_state_bytes(pss_ctx* c, int32_t field, size_t* bytes) {
+    if (pss_status s = check_ctx(c)) return s;
+    if (!bytes) return fail(PSS_E_INVAL, "null output");
+    int fd = 0;
+    if (pss_status s = dyn_field(c, field, &fd)) return s;
+    *bytes = sizeof(float2) * static_cast<size_t>(c->packed());
+    return PSS_OK;
+}
+
+pss_status pss_field_bind(pss_ctx* c, int32_t field, void* device_ptr, size_t bytes) {
+    if (pss_status s = check_ctx(c)) return s;
+    int fd = 0;
+    if (pss_status s = dyn_field(c, field, &fd)) return s;
+    if (c->planned) return fail(PSS_E_STATE, "bind before the plan is built (the state is already allocated)");
+    if (!device_ptr) return fail(PSS_E_INVAL, "null memory");
+    if (reinterpret_cast<uintptr_t>(device_ptr) % alignof(float2) != 0)
+        return fail(PSS_E_INVAL, "memory must be %zu-byte aligned", alignof(float2));
+    const size_t need = sizeof(float2) * static_cast<size_t>(c->packed());
+    if (bytes < need) return fail(PSS_E_INVAL, "the state of field %d needs %zu bytes (got %zu)", field, need, bytes);
+    c->bound[fd] = device_ptr;
+    c->bound_bytes[fd] = bytes;
+    return PSS_OK;
+}
+
+pss_status pss_state_changed(pss_ctx* c) {
+    if (pss_status s = check_ctx(c)) return s;
+    c->dirty = true;
+    ++c->state_gen;
     return PSS_OK;
 }
 

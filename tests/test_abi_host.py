@@ -273,3 +273,28 @@ def test_frame_arguments_on_host():
         lat.frame(f, [3], [float("nan")])
     with pytest.raises(PssError):
         lat.frame(f, [1, 2], [1.0])
+
+
+def test_field_bind_arguments_on_host():
+    # binding is host bookkeeping until the plan is built: every argument
+    # check runs without a device (the device-memory check comes with the plan)
+    lib = pss.lib()
+    lat = pss.Lattice((64, 32), dt=0.01)
+    f, _ = pss.model_b(lat)
+    psi = lat.field("psi", dynamic=False)
+    lat.term(psi, [Mono(1.0, q2=1)], [(f, 1)])
+    need = lat.state_bytes(f)
+    assert need == 8 * 32 * 32  # (Nx/2) Ny complex modes
+    assert pss.Lattice((64,), dt=0.01).field("u") == 0
+    one = pss.Lattice((64,), dt=0.01)
+    g = one.field("u")
+    assert one.state_bytes(g) == 8 * 64  # 1D: the full spectrum
+    fake = ctypes.c_void_p(0x10000)  # never dereferenced on the host
+    for args, word in (((f, None, need), b"null"), ((f, ctypes.c_void_p(0x10004), need), b"aligned"),
+                       ((f, fake, need - 8), b"needs"), ((psi, fake, need), b""), ((7, fake, need), b"")):
+        assert lib.pss_field_bind(lat._h, args[0], args[1], args[2]) == -1
+        assert word in lib.pss_last_error()
+    assert lib.pss_field_bind(lat._h, f, fake, need) == 0
+    assert lib.pss_state_changed(lat._h) == 0
+    with pytest.raises(ValueError):
+        lat.bind(f, np.zeros(need // 4, dtype=np.float32))  # a host array is refused by the binding
