@@ -139,7 +139,7 @@ pss_status pss_field_declare(pss_ctx *ctx, const char *name, int32_t dynamic,
  * added to L(q).  Explicit terms: 1 to 4 factors with powers 1..8; a single
  * factor of power 1 is applied directly in Fourier space, any other term is
  * formed in real space from de-aliased factors.  At most 8 monomials per
- * operator, 16 terms in total.  When the plan is built, the real-space terms
+ * operator, 32 terms in total.  When the plan is built, the real-space terms
  * become product channels: terms of one target with the same single-monomial
  * operator shape share a channel, and a channel whose products equal
  * another's up to a common factor for a different target is folded into it

@@ -369,40 +369,41 @@ def kpz(lattice, dt, sigma=1.0, lam=1.0, D=0.01, seed=1, dealias=DEALIAS_TWO_THI
     return m
 
 
-def model_h_force_ops(k):
+def model_h_force_ops(k, ndim=2):
     """Operators of the projected Korteweg force of model_h, per velocity
     component and stress product: {(component, (i, j)): [Mono, ...]} for the
-    products g_x^2, g_x g_y and g_y^2 (g = grad phi).
+    products g_i g_j, i <= j (g = grad phi), in 2 or 3 dimensions.
 
     The force -k d_j(g_i g_j) is projected with P_ci = delta_ci + (iq_c)(iq_i)/q^2
     (the Fourier form of the pressure's Poisson equation), so component c
-    receives -k sum_ij P_ci (i q_j) F[g_i g_j]; g_x g_y stands for the pairs
-    (x, y) and (y, x).
+    receives -k sum_ij P_ci (i q_j) F[g_i g_j]; g_i g_j with i != j stands for
+    the pairs (i, j) and (j, i).
     """
     ops = {}
-    for c in (0, 1):
-        for i, j in ((0, 0), (0, 1), (1, 1)):
-            monos = []
-            pairs = [(i, j)] if i == j else [(i, j), (j, i)]
-            for a, bb in pairs:
-                # delta_ca (i q_b)
-                if a == c:
+    for c in range(ndim):
+        for i in range(ndim):
+            for j in range(i, ndim):
+                monos = []
+                pairs = [(i, j)] if i == j else [(i, j), (j, i)]
+                for a, bb in pairs:
+                    # delta_ca (i q_b)
+                    if a == c:
+                        iq = [0, 0, 0]
+                        iq[bb] += 1
+                        monos.append(Mono(-k, iq=iq))
+                    # (i q_c)(i q_a)(i q_b) / q^2
                     iq = [0, 0, 0]
+                    iq[c] += 1
+                    iq[a] += 1
                     iq[bb] += 1
-                    monos.append(Mono(-k, iq=iq))
-                # (i q_c)(i q_a)(i q_b) / q^2
-                iq = [0, 0, 0]
-                iq[c] += 1
-                iq[a] += 1
-                iq[bb] += 1
-                monos.append(Mono(-k, invq=2, iq=iq))
-            ops[(c, (i, j))] = monos
+                    monos.append(Mono(-k, invq=2, iq=iq))
+                ops[(c, (i, j))] = monos
     return ops
 
 
 def model_h(lattice, dt, a=-1.0, b=1.0, k=1.0, M=1.0, eta=1.0, D=0.0, seed=1,
             dealias=DEALIAS_TWO_THIRDS, shape=SHAPE_RADIAL):
-    """Model H in 2D (the paper's second benchmark, Sec. "Benchmarking";
+    """Model H in 2D or 3D (the paper's second benchmark, Sec. "Benchmarking";
     Hohenberg and Halperin's model H): a conserved order parameter advected by
     an incompressible Stokes flow that its interfaces drive,
 
@@ -417,39 +418,38 @@ def model_h(lattice, dt, a=-1.0, b=1.0, k=1.0, M=1.0, eta=1.0, D=0.0, seed=1,
       projection f_hat -> P(q) f_hat, P_ij = delta_ij - q_i q_j / q^2,
       which is linear in f and becomes part of each term's operator;
     * -phi grad mu differs from -k d_j(g_i g_j), g = grad phi, by a
-      gradient, which P removes, so the force terms are the three stress
-      products g_x^2, g_x g_y, g_y^2 with the operators of model_h_force_ops;
-    * g_x, g_y are intermediate fields (i q_x phi_hat, i q_y phi_hat);
-    * advection -v . grad phi = -(v_x g_x + v_y g_y) (equal to -div(v phi)
-      for a solenoidal v).
+      gradient, which P removes, so the force terms are the stress products
+      g_i g_j (i <= j) with the operators of model_h_force_ops;
+    * g_i are intermediate fields (i q_i phi_hat);
+    * advection -v . grad phi = -sum_i v_i g_i (equal to -div(v phi) for a
+      solenoidal v).
     Readings: the convective term (v . grad) v is left out (the viscous,
     low-Reynolds form of model H), and the velocity has no noise (per-field
-    noise cannot be projected).  Fields: phi, v_x, v_y (dynamic), dx_phi,
-    dy_phi (intermediate), in that order.
+    noise cannot be projected).  Fields: phi, the velocity components (dynamic)
+    and the gradient components (intermediate), in that order.
     """
-    if lattice.nz != 1:
-        raise ValueError("model_h is two-dimensional")
+    ndim = 3 if lattice.nz != 1 else 2
     m = Model(lattice, dt, seed=seed, dealias=dealias, shape=shape)
     phi = m.add_field("phi")
-    vx = m.add_field("vx")
-    vy = m.add_field("vy")
-    gx = m.add_field("dx_phi", dynamic=False)
-    gy = m.add_field("dy_phi", dynamic=False)
-    m.add_term(gx, [Mono(1.0, iq=(1, 0, 0))], [(phi, 1)])
-    m.add_term(gy, [Mono(1.0, iq=(0, 1, 0))], [(phi, 1)])
+    v = [m.add_field("v" + "xyz"[i]) for i in range(ndim)]
+    g = [m.add_field("d%s_phi" % "xyz"[i], dynamic=False) for i in range(ndim)]
+    for i in range(ndim):
+        iq = [0, 0, 0]
+        iq[i] = 1
+        m.add_term(g[i], [Mono(1.0, iq=iq)], [(phi, 1)])
     # order parameter: M lap mu, advection
     m.add_term(phi, [Mono(-M * a, q2=1), Mono(-M * k, q2=2)], [(phi, 1)], implicit=True)
     m.add_term(phi, [Mono(-M * b, q2=1)], [(phi, 3)])
-    m.add_term(phi, [Mono(-1.0)], [(vx, 1), (gx, 1)])
-    m.add_term(phi, [Mono(-1.0)], [(vy, 1), (gy, 1)])
+    for i in range(ndim):
+        m.add_term(phi, [Mono(-1.0)], [(v[i], 1), (g[i], 1)])
     # flow: viscosity, projected stress
-    ops = model_h_force_ops(k)
-    g = (gx, gy)
-    for c, v in ((0, vx), (1, vy)):
-        m.add_term(v, [Mono(-eta, q2=1)], [(v, 1)], implicit=True)
-        for i, j in ((0, 0), (0, 1), (1, 1)):
-            fac = [(g[i], 2)] if i == j else [(g[i], 1), (g[j], 1)]
-            m.add_term(v, ops[(c, (i, j))], fac)
+    ops = model_h_force_ops(k, ndim)
+    for c in range(ndim):
+        m.add_term(v[c], [Mono(-eta, q2=1)], [(v[c], 1)], implicit=True)
+        for i in range(ndim):
+            for j in range(i, ndim):
+                fac = [(g[i], 2)] if i == j else [(g[i], 1), (g[j], 1)]
+                m.add_term(v[c], ops[(c, (i, j))], fac)
     if D:
         m.set_noise(phi, [Mono(D, q2=1)])
     return m

@@ -592,52 +592,51 @@ def kpz(lat, sigma=1.0, lam=1.0, D=0.01):
 
 
 def model_h(lat, a=-1.0, b=1.0, k=1.0, M=1.0, eta=1.0, D=0.0):
-    """2D Model H (the paper's second benchmark, Sec. "Benchmarking"): a
-    conserved order parameter advected by an incompressible viscous flow that
-    its interfaces drive,
+    """Model H in 2D or 3D (the paper's second benchmark, Sec. "Benchmarking"):
+    a conserved order parameter advected by an incompressible viscous flow
+    that its interfaces drive,
         d/dt phi = -v.grad phi + M lap mu,   mu = a phi + b phi^3 - k lap phi,
         d/dt v = eta lap v - grad p - phi grad mu,   div v = 0,
     with conserved noise D q^2 on phi.  The pressure is the projection
     P_ij = delta_ij + (i q_i)(i q_j)/q^2 folded into the operators of the
     force terms, the force written as -k d_j(g_i g_j), g = grad phi (it
     differs from -phi grad mu by a gradient, which the projection removes).
-    Returns (phi, vx, vy) and the ids of the gradient fields (gx, gy)."""
-    if lat.ndim != 2:
-        raise ValueError("model_h is two-dimensional")
+    Returns (phi, v_x, v_y[, v_z]) and the ids of the gradient fields."""
+    nd = lat.ndim
+    if nd not in (2, 3):
+        raise ValueError("model_h is two- or three-dimensional")
     phi = lat.field("phi")
-    vx = lat.field("vx")
-    vy = lat.field("vy")
-    gx = lat.field("dx_phi", dynamic=False)
-    gy = lat.field("dy_phi", dynamic=False)
-    lat.term(gx, [Mono(1.0, iq=(1, 0, 0))], [(phi, 1)])
-    lat.term(gy, [Mono(1.0, iq=(0, 1, 0))], [(phi, 1)])
+    v = [lat.field("v" + "xyz"[i]) for i in range(nd)]
+    g = [lat.field("d%s_phi" % "xyz"[i], dynamic=False) for i in range(nd)]
+    for i in range(nd):
+        iq = [0, 0, 0]
+        iq[i] = 1
+        lat.term(g[i], [Mono(1.0, iq=tuple(iq))], [(phi, 1)])
     lat.term(phi, [Mono(-M * a, q2=1), Mono(-M * k, q2=2)], [(phi, 1)], implicit=True)
     lat.term(phi, [Mono(-M * b, q2=1)], [(phi, 3)])
-    lat.term(phi, [Mono(-1.0)], [(vx, 1), (gx, 1)])
-    lat.term(phi, [Mono(-1.0)], [(vy, 1), (gy, 1)])
-    g = (gx, gy)
-    for c, v in ((0, vx), (1, vy)):
-        lat.term(v, [Mono(-eta, q2=1)], [(v, 1)], implicit=True)
-        for i, j in ((0, 0), (0, 1), (1, 1)):
-            # -k sum over (i, j) and (j, i) of P_ci (i q_j): delta_ci (i q_j)
-            # + (i q_c)(i q_i)(i q_j)/q^2
-            monos = []
-            for p_, r_ in ([(i, j)] if i == j else [(i, j), (j, i)]):
-                if p_ == c:
+    for i in range(nd):
+        lat.term(phi, [Mono(-1.0)], [(v[i], 1), (g[i], 1)])
+    for c in range(nd):
+        lat.term(v[c], [Mono(-eta, q2=1)], [(v[c], 1)], implicit=True)
+        for i in range(nd):
+            for j in range(i, nd):
+                # -k sum over (i, j) and (j, i) of P_ci (i q_j): delta_ci (i q_j)
+                # + (i q_c)(i q_i)(i q_j)/q^2
+                merged = {}
+                for p_, r_ in ([(i, j)] if i == j else [(i, j), (j, i)]):
+                    if p_ == c:
+                        iq = [0, 0, 0]
+                        iq[r_] += 1
+                        key = (0, 0, tuple(iq))
+                        merged[key] = merged.get(key, 0.0) - k
                     iq = [0, 0, 0]
+                    iq[c] += 1
+                    iq[p_] += 1
                     iq[r_] += 1
-                    monos.append(Mono(-k, iq=tuple(iq)))
-                iq = [0, 0, 0]
-                iq[c] += 1
-                iq[p_] += 1
-                iq[r_] += 1
-                monos.append(Mono(-k, invq=2, iq=tuple(iq)))
-            merged = {}
-            for mo in monos:  # equal monomials (the two orders of a mixed pair) add up
-                key = (mo.q2, mo.invq, mo.iq)
-                merged[key] = merged.get(key, 0.0) + mo.coef
-            monos = [Mono(cf, q2=q2, invq=iv, iq=iq) for (q2, iv, iq), cf in merged.items()]
-            lat.term(v, monos, [(g[i], 2)] if i == j else [(g[i], 1), (g[j], 1)])
+                    key = (0, 2, tuple(iq))  # equal monomials (the two orders of a mixed pair) add up
+                    merged[key] = merged.get(key, 0.0) - k
+                monos = [Mono(cf, q2=q2, invq=iv, iq=iq) for (q2, iv, iq), cf in merged.items()]
+                lat.term(v[c], monos, [(g[i], 2)] if i == j else [(g[i], 1), (g[j], 1)])
     if D:
         lat.noise(phi, [Mono(D, q2=1)])
-    return (phi, vx, vy), (gx, gy)
+    return (phi, *v), tuple(g)

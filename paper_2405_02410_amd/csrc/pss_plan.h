@@ -25,7 +25,7 @@
 
 #define PSS_MAXF 4    // fields
 #define PSS_MAXM 8    // monomials per operator
-#define PSS_MAXT 16   // terms
+#define PSS_MAXT 32   // terms
 #define PSS_MAXCH 8   // real-space product channels
 #define PSS_MAXPT 8   // products per channel
 #define PSS_MAXD 8    // Fourier-space (single linear factor) terms

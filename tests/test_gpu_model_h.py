@@ -1,6 +1,7 @@
-"""GPU parity of 2D Model H (pss.model_h: order parameter, two velocity
-components, two gradient intermediates, eight product channels over five
-factor slots) against the FP64 oracle, through the C interface.
+"""GPU parity of Model H (pss.model_h; 2D: order parameter, two velocity
+components, two gradient intermediates, five product channels over five
+factor slots; 3D: three of each, eight channels over seven slots) against the
+FP64 oracle, through the C interface.
 
 Tolerance: every field within 1e-4 of its largest magnitude (and of 1 for
 the order parameter) after the stated steps, FP32 against FP64, the bar of
@@ -112,3 +113,44 @@ def test_model_h_restart_and_chunking_bitwise():
         b.step(k)
     for fid in ids:
         assert np.array_equal(a.spectrum(fid), b.spectrum(fid))
+
+
+@pytest.mark.parametrize("n,steps", [((16, 16, 16), 60), ((32, 16, 8), 40), ((32, 32, 32), 30)])
+def test_model_h_3d_matches_oracle(n, steps):
+    # four dynamic fields, three gradient intermediates, seven factor slots;
+    # the six stress products each feed all three velocity components
+    print(f"model h 3d n={n} steps={steps}", flush=True)
+    lat = pss.Lattice(n, dt=0.01, seed=7)
+    ids, grads = pss.model_h(lat, D=0.01, **PARAMS)
+    m = om.model_h(OLattice(*n), 0.01, D=0.01, seed=7, **PARAMS)
+    lat.init_uniform(ids[0], -0.4, 0.4)
+    m.init_uniform(0, -0.4, 0.4)
+    lat.step(steps)
+    m.step(steps)
+    for i, fid in enumerate(tuple(ids) + tuple(grads)):
+        ok, err = _close(lat.download(fid), m.real(i), floor=1.0 if i == 0 else 0.0)
+        assert ok, (i, err)
+    assert np.max(np.abs(m.real(1))) > 1e-4
+
+
+def test_model_h_3d_invariants():
+    n, steps = (64, 64, 64), 20
+    print(f"model h 3d n={n} steps={steps}", flush=True)
+    lat = pss.Lattice(n, dt=0.01, seed=5)
+    ids, _ = pss.model_h(lat, D=0.02, **PARAMS)
+    lat.init_uniform(ids[0], -0.4, 0.4)
+    mass0 = lat.mass(ids[0])
+    lat.step(steps)
+    phi = lat.download(ids[0])
+    assert np.all(np.isfinite(phi))
+    assert abs(lat.mass(ids[0]) - mass0) <= 1e-6 * np.sum(np.abs(phi))
+    sp = [lat.spectrum(v).astype(np.complex128) for v in ids[1:]]  # (z, y, kx)
+    kx = np.arange(n[0] // 2 + 1)[None, None, :]
+    ky = np.where(np.arange(n[1]) < n[1] // 2, np.arange(n[1]), np.arange(n[1]) - n[1])[None, :, None]
+    kz = np.where(np.arange(n[2]) < n[2] // 2, np.arange(n[2]), np.arange(n[2]) - n[2])[:, None, None]
+    q = [2 * np.pi * kx / n[0], 2 * np.pi * ky / n[1], 2 * np.pi * kz / n[2]]
+    keep = (kx != n[0] // 2) & (ky != -(n[1] // 2)) & (kz != -(n[2] // 2))
+    div = sum(1j * q[c] * sp[c] for c in range(3))
+    scale = np.max(np.sqrt(q[0] ** 2 + q[1] ** 2 + q[2] ** 2) * sum(np.abs(s) for s in sp))
+    assert scale > 0
+    assert np.max(np.abs(div[np.broadcast_to(keep, div.shape)])) <= 1e-5 * scale

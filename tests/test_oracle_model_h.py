@@ -15,7 +15,8 @@ something other than itself:
 * a profile that depends on x only drives no flow and follows the Model B
   oracle exactly;
 * the mean of phi is conserved and the flow stays solenoidal under noise;
-* with no noise the free energy plus the kinetic energy does not grow.
+* with no noise the free energy plus the kinetic energy does not grow;
+* in 3D: the same projection, one-step, flat-profile and invariant checks.
 """
 
 import numpy as np
@@ -149,3 +150,80 @@ def test_energy_does_not_grow_without_noise():
         if prev is not None:
             assert e <= prev + 1e-12 * abs(prev)
         prev = e
+
+
+# -- three dimensions ---------------------------------------------------------
+
+def _off_nyquist3(lat):
+    keep = np.ones(lat.shape, dtype=bool)
+    for i, n in enumerate((lat.nx, lat.ny, lat.nz)):
+        keep &= lat.k_int[i] != -(n // 2)
+    return keep
+
+
+def test_projected_stress_is_solenoidal_3d():
+    lat = Lattice(16, 8, 12, dx=0.7, dy=1.3, dz=0.9)
+    ops = om.model_h_force_ops(1.3, ndim=3)
+    assert len(ops) == 18
+    keep = _off_nyquist3(lat) & (lat.q2 > 0)
+    for i in range(3):
+        for j in range(i, 3):
+            div = sum(lat.iq[c] * lat.operator(ops[(c, (i, j))]) for c in range(3))
+            scale = max(np.max(np.abs(lat.iq[c] * lat.operator(ops[(c, (i, j))]))) for c in range(3))
+            assert scale > 1.0
+            assert np.max(np.abs(div[keep])) <= 1e-12 * scale, (i, j)
+
+
+def test_one_step_flow_is_the_projected_phi_grad_mu_3d():
+    n, dt = 16, 0.02
+    a, b, k, M, eta = -0.7, 1.2, 0.8, 0.9, 1.4
+    lat = Lattice(n, n, n, dx=0.8, dy=0.8, dz=0.8)
+    rng = np.random.default_rng(8)
+    spec = np.zeros(lat.shape, dtype=np.complex128)
+    sel = np.broadcast_to((np.abs(lat.k_int[0]) <= 1) & (np.abs(lat.k_int[1]) <= 1) & (np.abs(lat.k_int[2]) <= 1),
+                          lat.shape)
+    spec[sel] = rng.normal(size=sel.sum()) + 1j * rng.normal(size=sel.sum())
+    phi0 = ifftn(spec).real
+    phi0 = 0.6 * phi0 / np.max(np.abs(phi0))
+    m = om.model_h(lat, dt, a=a, b=b, k=k, M=M, eta=eta, D=0.0)
+    m.set_real(0, phi0)
+    m.step(1)
+    ph = fftn(phi0.astype(np.complex128))
+    mu = a * phi0 + b * phi0 ** 3 + k * ifftn(lat.q2 * ph).real
+    muh = fftn(mu.astype(np.complex128))
+    q = [np.broadcast_to(lat.q[i], lat.shape) for i in range(3)]
+    f = [fftn((-phi0 * ifftn(1j * q[i] * muh).real).astype(np.complex128)) for i in range(3)]
+    qf = sum(q[i] * f[i] for i in range(3)) / np.where(lat.q2 > 0, lat.q2, 1.0)
+    for i in range(3):
+        want = dt * np.where(lat.q2 > 0, f[i] - q[i] * qf, 0.0) / (1.0 + dt * eta * lat.q2)
+        got = m.state[1 + i]
+        assert np.max(np.abs(want)) > 1e-4
+        assert np.max(np.abs(got - want)) <= 1e-10 * np.max(np.abs(want)), i
+
+
+def test_flat_profile_drives_no_flow_3d():
+    lat = Lattice(32, 8, 8)
+    prof = np.random.default_rng(3).uniform(-0.5, 0.5, size=32)
+    m = om.model_h(lat, 0.01, D=0.0)
+    mb = om.model_b(lat, 0.01, D=0.0)
+    phi0 = np.broadcast_to(prof[None, None, :], lat.shape)
+    m.set_real(0, phi0)
+    mb.set_real(0, phi0)
+    m.step(30)
+    mb.step(30)
+    for c in (1, 2, 3):
+        assert np.max(np.abs(m.real(c))) <= 1e-13
+    assert np.max(np.abs(m.real(0) - mb.real(0))) <= 1e-12
+
+
+def test_mass_and_divergence_3d():
+    lat = Lattice(16, 16, 8)
+    m = om.model_h(lat, 0.01, D=0.02, seed=4)
+    m.init_uniform(0, -0.4, 0.5)
+    mass0 = m.state[0][0, 0, 0].real
+    m.step(30)
+    assert abs(m.state[0][0, 0, 0].real - mass0) <= 1e-10 * np.sum(np.abs(m.real(0)))
+    div = sum(lat.iq[c] * m.state[1 + c] for c in range(3))
+    vmax = np.max(np.sqrt(lat.q2) * sum(np.abs(m.state[1 + c]) for c in range(3)))
+    assert vmax > 0
+    assert np.max(np.abs(div[_off_nyquist3(lat)])) <= 1e-12 * vmax
