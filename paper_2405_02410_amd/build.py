@@ -71,7 +71,6 @@ def build(jobs=None, verbose=False):
     cmds.append([hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, "pss_equation.cpp"), "-o", o])
     objs.append(o)
     jobs = jobs or min(16, os.cpu_count() or 4)
-    # the longest compiles first
     # the longest compiles first: the fused batch kernels, then the longest lines
     weight = [L for L in LENGTHS] + [0, 100000, 0, 0, 0]
     order = sorted(range(len(cmds)), key=lambda i: -weight[i])
