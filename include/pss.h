@@ -101,9 +101,14 @@ typedef struct {
  * line of the examples in Sec. "Callback functions" and "De-aliasing") is
  * stepped by one block that holds the whole line; its state is the full
  * complex spectrum of the line (pss_state_size), and it takes part in neither
- * batches nor the adjoint (PSS_E_UNSUPPORTED there).
+ * batches nor the adjoint (PSS_E_UNSUPPORTED there).  A 1D line may also
+ * have an even length 2^a 3^b 5^c (Sec. "Benchmarking": sizes other than
+ * powers of two are allowed, at a lower speed); such a line keeps its spectra
+ * in LDS, which bounds N times the field and factor counts (PSS_E_UNSUPPORTED
+ * when the plan is built, with the bytes it would need).
  * Errors: PSS_E_INVAL (null out, dt <= 0, dx <= 0), PSS_E_UNSUPPORTED (ndim
- * not 1, 2 or 3, a size that is not a power of two in [8, 4096]). */
+ * not 1, 2 or 3, a size that is not a power of two in [8, 4096], or in 1D not
+ * an even 2^a 3^b 5^c in [8, 4096]). */
 pss_status pss_lattice_create(pss_ctx **out, int32_t ndim, const int64_t n[3],
                               const double dx[3], double dt);
 

@@ -123,6 +123,7 @@ struct LaunchArgs {
     const float2* tw_y;  // twiddles of Ny (3D y passes)
     int dim;             // 1, 2 or 3
     int nsteps;          // 1D step launches: steps of the launch
+    int ng;              // factor slots of the plan (1D lines of mixed-radix length size their LDS by it)
 };
 
 // Fused batch launches: one update-phase and one x-phase launch cover every
@@ -206,6 +207,41 @@ inline size_t line1d_lds_bytes(int N) {
 }
 // allow the 1D kernels of length N their LDS (above the default dynamic limit)
 hipError_t line1d_setup(int N);
+
+// 1D lines of mixed-radix length N = 2^a 3^b 5^c, a >= 1, not a power of two
+// (launch_line1d sends them to their own kernel): the radices of the
+// self-sorting passes, 4 first, then 2, 3 and 5.  False if N does not factor
+// so or is not even.
+struct MrPlan {
+    int n;
+    int nst;
+    int radix[24];
+};
+inline bool mr_plan(int N, MrPlan* mr) {
+    if (N < 2 || (N & 1)) return false;
+    mr->n = N;
+    mr->nst = 0;
+    int n = N;
+    while (n % 4 == 0 && n > 4) {
+        mr->radix[mr->nst++] = 4;
+        n /= 4;
+    }
+    for (int r : {4, 2, 3, 5})
+        while (n % r == 0) {
+            if (mr->nst >= 24) return false;
+            mr->radix[mr->nst++] = r;
+            n /= r;
+        }
+    return n == 1;
+}
+// LDS of the mixed-radix 1D kernel: twiddle table, two transform buffers,
+// NF states and NF contribution arrays (complex), ng real factor lines
+inline size_t line1d_mr_lds_bytes(int N, int NF, int ng) {
+    return sizeof(float2) * static_cast<size_t>(N) * (3 + 2 * static_cast<size_t>(NF)) +
+           sizeof(float) * static_cast<size_t>(N) * static_cast<size_t>(ng > 0 ? ng : 1);
+}
+hipError_t launch_line1d_mr(int mode, int N, int nf, int ng, const LaunchArgs& a);
+hipError_t line1d_mr_setup();
 hipError_t launch_xrow(int mode, int L, int ng, const LaunchArgs& a);
 hipError_t launch_ypass(int mode, int L, const YArgs& ya, const LaunchArgs& a);
 hipError_t launch_advance(hipStream_t s, uint64_t* step_ctr, int64_t k);

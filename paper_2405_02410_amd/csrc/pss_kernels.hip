@@ -1626,6 +1626,290 @@ __global__ void shell_means_kernel(int nshell, const unsigned int* __restrict__ 
     const unsigned long long n = gcnt[j];
     ghi[j] = static_cast<unsigned long long>(__double_as_longlong(n ? v / static_cast<double>(n) : 0.0));
 }
+
+// ------------------------------------------- 1D lines of mixed-radix length
+// Lines whose length N = 2^a 3^b 5^c (a >= 1) is not a power of two.  One
+// block per lattice keeps the spectra in LDS and transforms them with
+// self-sorting (Stockham) passes of radix 4, 2, 3 and 5 (Van Loan, Sec. 1.7):
+// a pass of radix r over the current length n = m r and s interleaved
+// transforms maps x to
+//   y[q + s (r p + j)] = w_n^(j p) sum_l x[q + s (p + l m)] w_r^(j l),
+// p < m, q < s, j < r, w_n = exp(-+2 pi i / n), and the next pass takes n = m,
+// s = s r, until the result stands in natural order.  The step is the one of
+// the power-of-two 1D kernel, mode by mode over the whole line.
+
+// (cos, sin)(2 pi k / r) for r in {2, 3, 4, 5}
+__device__ __forceinline__ float2 small_root(int r, int k) {
+    // the fifth roots: cos and sin of 72 and 144 degrees
+    constexpr float c1 = 0.309016994374947424f, s1 = 0.951056516295153572f;
+    constexpr float c2 = -0.809016994374947424f, s2 = 0.587785252292473129f;
+    constexpr float h3 = 0.866025403784438647f;  // sin(120 degrees)
+    switch (r) {
+        case 2: return k == 0 ? make_float2(1.f, 0.f) : make_float2(-1.f, 0.f);
+        case 3: return k == 0 ? make_float2(1.f, 0.f) : (k == 1 ? make_float2(-0.5f, h3) : make_float2(-0.5f, -h3));
+        case 4:
+            return k == 0 ? make_float2(1.f, 0.f)
+                          : (k == 1 ? make_float2(0.f, 1.f) : (k == 2 ? make_float2(-1.f, 0.f) : make_float2(0.f, -1.f)));
+        default:
+            switch (k) {
+                case 0: return make_float2(1.f, 0.f);
+                case 1: return make_float2(c1, s1);
+                case 2: return make_float2(c2, s2);
+                case 3: return make_float2(c2, -s2);
+                default: return make_float2(c1, -s1);
+            }
+    }
+}
+
+// Transform of the N values in x (LDS) with sign -1 (forward) or +1 (inverse,
+// unnormalised); y is LDS scratch of N values.  Returns the buffer holding the
+// result.  Every thread of the block calls it; it ends with a barrier.
+__device__ float2* mr_transform(float2* x, float2* y, const float2* __restrict__ tw, const MrPlan& mr, int sign) {
+    const int N = mr.n;
+    int n = N, s = 1;
+    for (int st = 0; st < mr.nst; ++st) {
+        const int r = mr.radix[st];
+        const int m = n / r;
+        for (int idx = threadIdx.x; idx < m * s; idx += blockDim.x) {
+            const int q = idx % s, p = idx / s;
+            float2 a[5];
+            for (int l = 0; l < r; ++l) a[l] = x[q + s * (p + l * m)];
+            for (int j = 0; j < r; ++j) {
+                float2 b = make_float2(0.f, 0.f);
+                for (int l = 0; l < r; ++l) {
+                    float2 w = small_root(r, (j * l) % r);
+                    w.y *= static_cast<float>(sign);
+                    b = cadd(b, cmul(a[l], w));
+                }
+                float2 w = tw[(j * p * s) % N];  // exp(-2 pi i j p s / N) = w_n^(j p)
+                if (sign > 0) w.y = -w.y;
+                y[q + s * (r * p + j)] = cmul(b, w);
+            }
+        }
+        __syncthreads();
+        float2* t = x;
+        x = y;
+        y = t;
+        n = m;
+        s *= r;
+    }
+    return x;
+}
+
+template <int NF, bool GEN, int MODE>
+__global__ void __launch_bounds__(256)
+    line1d_mr_kernel(const DevPlan* __restrict__ plan, Bufs bufs, uint64_t* __restrict__ step_ctr,
+                     uint32_t* __restrict__ flag, int nsteps, int advance, const float2* __restrict__ tw_g, MrPlan mr) {
+    extern __shared__ float2 smem[];
+    const DevPlan& p = *plan;
+    const int N = mr.n;
+    const int t = threadIdx.x, T = blockDim.x;
+    float2* const tw = smem;         // exp(-2 pi i k / N)
+    float2* const A = smem + N;      // transform buffers
+    float2* const B = smem + 2 * N;
+    float2* const S = smem + 3 * N;  // states [NF][N]
+    float2* const acc = S + NF * N;  // explicit contributions [NF][N]
+    float* const u = reinterpret_cast<float*>(acc + NF * N);  // de-aliased factors [ng][N]
+    for (int i = t; i < N; i += T) tw[i] = tw_g[i];
+    auto kq = [&](int k) { return mode_q(p, k < (N >> 1) ? k : k - N, 0, 0); };
+
+    if constexpr (MODE == MODE_FWD_STORE) {
+        for (int i = t; i < N; i += T) A[i] = make_float2(bufs.real_in[i], 0.f);
+        __syncthreads();
+        const float2* r = mr_transform(A, B, tw, mr, -1);
+        for (int k = t; k < N; k += T) gstore(bufs.S[bufs.sel] + k, r[k]);
+        return;
+    }
+    if constexpr (MODE == MODE_INV_OUT) {
+        for (int k = t; k < N; k += T) A[k] = gload(bufs.S[bufs.sel] + k);
+        __syncthreads();
+        const float2* r = mr_transform(A, B, tw, mr, 1);
+        for (int i = t; i < N; i += T) bufs.real_out[i] = r[i].x * p.inv_n;
+        return;
+    }
+
+    const int nf = p.nf;
+    for (int f = 0; f < nf; ++f)
+        for (int k = t; k < N; k += T) S[f * N + k] = gload(bufs.S[f] + k);
+    __syncthreads();
+    // Fourier value of source src (a dynamic field, or an intermediate
+    // psi = sum_j op_j phi_j / (1 - L_psi)) at mode k of the current state
+    auto source = [&](int src, int k, const ModeQ& q) -> float2 {
+        if constexpr (GEN) {
+            if (src >= PSS_MAXF) {
+                const DevInterm& I = p.interm[src - PSS_MAXF];
+                float2 v = make_float2(0.f, 0.f);
+                for (int j = 0; j < I.nsrc; ++j) v = cadd(v, cmul(eval_op<true>(I.op[j], q), S[I.src[j] * N + k]));
+                return cmul(v, cinv_implicit(1.f, eval_op<true>(I.den, q)));
+            }
+        }
+        return S[src * N + k];
+    };
+
+    if constexpr (MODE == MODE_INTERM_OUT) {
+        for (int k = t; k < N; k += T) A[k] = source(PSS_MAXF + bufs.sel, k, kq(k));
+        __syncthreads();
+        const float2* r = mr_transform(A, B, tw, mr, 1);
+        for (int i = t; i < N; i += T) bufs.real_out[i] = r[i].x * p.inv_n;
+        return;
+    }
+
+    // MODE_STEP: acc = sum_ch M_ch(q) F[products] from the current state
+    auto channels = [&]() {
+        for (int i = t; i < nf * N; i += T) acc[i] = make_float2(0.f, 0.f);
+        if (p.nch == 0) {
+            __syncthreads();
+            return;
+        }
+        for (int g = 0; g < p.ng; ++g) {
+            const DevMask& mk = p.mask[g];
+            for (int k = t; k < N; k += T)
+                A[k] = mask_keep(mk, k < (N >> 1) ? k : k - N, 0, 0) ? source(p.gfield[g], k, kq(k))
+                                                                     : make_float2(0.f, 0.f);
+            __syncthreads();
+            const float2* r = mr_transform(A, B, tw, mr, 1);
+            for (int i = t; i < N; i += T) u[g * N + i] = r[i].x * p.inv_n;
+            __syncthreads();
+        }
+        for (int ch = 0; ch < p.nch; ++ch) {
+            const DevChannel& C = p.ch[ch];
+            for (int i = t; i < N; i += T) {
+                float w = 0.f;
+                for (int k = 0; k < C.nprod; ++k) {
+                    const DevProd& pd = C.prod[k];
+                    float a = pd.coef;
+                    for (int g = 0; g < p.ng; ++g)
+                        for (int e = 0; e < pd.pow[g]; ++e) a *= u[g * N + i];
+                    w += a;
+                }
+                A[i] = make_float2(w, 0.f);
+            }
+            __syncthreads();
+            const float2* r = mr_transform(A, B, tw, mr, -1);
+            for (int k = t; k < N; k += T) {
+                const ModeQ q = kq(k);
+                for (int o = 0; o < C.nout; ++o) {
+                    float2& d = acc[C.target[o] * N + k];
+                    d = cadd(d, cmul(eval_op<GEN>(C.op[o], q), r[k]));
+                }
+            }
+            __syncthreads();
+        }
+    };
+
+    const uint32_t step0 = static_cast<uint32_t>(gload_u64(step_ctr));
+    uint32_t bad = 0;
+    channels();
+    for (int sn = 0; sn < nsteps; ++sn) {
+        const uint32_t step = step0 + static_cast<uint32_t>(sn);
+        // linear explicit terms from the step-n state, then the semi-implicit
+        // update with the noise of this step (each mode by one thread)
+        for (int k = t; k < N; k += T) {
+            const ModeQ q = kq(k);
+            for (int d = 0; d < p.nd; ++d) {
+                const DevDirect& Dd = p.direct[d];
+                float2& a = acc[Dd.target * N + k];
+                a = cadd(a, cmul(eval_op<GEN>(Dd.op, q), source(Dd.src, k, q)));
+            }
+        }
+        __syncthreads();  // the intermediates of the direct terms read every field's step-n state
+        for (int k = t; k < N; k += T) {
+            const ModeQ q = kq(k);
+            const uint32_t lin = static_cast<uint32_t>(k), lneg = static_cast<uint32_t>((N - k) % N);
+            for (int f = 0; f < nf; ++f) {
+                float2 r = cadd(S[f * N + k], cscale(acc[f * N + k], p.dt));
+                if (p.noisy[f] != 0) r = cadd(r, noise_mode<GEN>(p, f, step, lin, lneg, q));
+                r = cmul(r, cinv_implicit(p.dt, eval_op<GEN>(p.implicit_op[f], q)));
+                S[f * N + k] = r;
+                if (!(__builtin_isfinite(r.x) && __builtin_isfinite(r.y))) bad |= 1u << f;
+            }
+        }
+        __syncthreads();
+        // boundary frames: the new state's real space takes the frame values
+        // on the frame sites, then is transformed back
+        for (int f = 0; f < nf; ++f) {
+            if (p.nframe[f] == 0) continue;
+            for (int k = t; k < N; k += T) A[k] = S[f * N + k];
+            __syncthreads();
+            float2* r = mr_transform(A, B, tw, mr, 1);
+            float2* o = r == A ? B : A;
+            for (int i = t; i < N; i += T) o[i] = make_float2(r[i].x * p.inv_n, 0.f);
+            __syncthreads();
+            const int2* __restrict__ fr = p.frame[f];
+            for (int i = t; i < p.nframe[f]; i += T) o[fr[i].x] = make_float2(__int_as_float(fr[i].y), 0.f);
+            __syncthreads();
+            const float2* z = mr_transform(o, r, tw, mr, -1);
+            for (int k = t; k < N; k += T) S[f * N + k] = z[k];
+            __syncthreads();
+        }
+        if (sn + 1 < nsteps) channels();
+    }
+    for (int f = 0; f < nf; ++f)
+        for (int k = t; k < N; k += T) gstore(bufs.S[f] + k, S[f * N + k]);
+    if (bad) atomicOr(flag, bad);
+    __syncthreads();  // every thread has read the counter
+    if (advance && t == 0) *step_ctr += static_cast<uint64_t>(nsteps);
+}
+
+hipError_t launch_line1d_mr(int mode, int N, int nf, int ng, const LaunchArgs& a) {
+    MrPlan mr{};
+    if (!mr_plan(N, &mr)) return hipErrorInvalidValue;
+    const int NF = nf <= 1 ? 1 : (nf == 2 ? 2 : 4);
+    const size_t lds = line1d_mr_lds_bytes(mr.n, NF, ng);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    const dim3 grid(1), block(256);
+    uint64_t* ctr = const_cast<uint64_t*>(a.step_ctr);
+    const bool gen = a.general || mode == MODE_INTERM_OUT;
+#define PSS_MR(NFV, G, M)                                                                                   \
+    hipLaunchKernelGGL((line1d_mr_kernel<NFV, G, M>), grid, block, lds, a.stream, a.plan, a.bufs, ctr, a.flag, \
+                       a.nsteps, a.advance != 0 ? 1 : 0, a.tw_x, mr)
+#define PSS_MRF(M)                       \
+    do {                                 \
+        if (NF == 1) {                   \
+            if (gen)                     \
+                PSS_MR(1, true, M);      \
+            else                         \
+                PSS_MR(1, false, M);     \
+        } else if (NF == 2) {            \
+            if (gen)                     \
+                PSS_MR(2, true, M);      \
+            else                         \
+                PSS_MR(2, false, M);     \
+        } else {                         \
+            if (gen)                     \
+                PSS_MR(4, true, M);      \
+            else                         \
+                PSS_MR(4, false, M);     \
+        }                                \
+    } while (0)
+    switch (mode) {
+        case MODE_STEP: PSS_MRF(MODE_STEP); break;
+        case MODE_INTERM_OUT: PSS_MRF(MODE_INTERM_OUT); break;
+        case MODE_FWD_STORE: PSS_MR(1, false, MODE_FWD_STORE); break;
+        case MODE_INV_OUT: PSS_MR(1, false, MODE_INV_OUT); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef PSS_MRF
+#undef PSS_MR
+    return hipGetLastError();
+}
+
+hipError_t line1d_mr_setup() {
+    const int lds = 160 * 1024;
+#define PSS_MRA(NFV, G, M)                                                                                     \
+    if (hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&line1d_mr_kernel<NFV, G, M>),        \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds))                   \
+        return e;
+#define PSS_MRB(M) PSS_MRA(1, false, M) PSS_MRA(1, true, M) PSS_MRA(2, false, M) PSS_MRA(2, true, M) \
+    PSS_MRA(4, false, M) PSS_MRA(4, true, M)
+    PSS_MRB(MODE_STEP)
+    PSS_MRB(MODE_INTERM_OUT)
+    PSS_MRA(1, false, MODE_FWD_STORE)
+    PSS_MRA(1, false, MODE_INV_OUT)
+#undef PSS_MRB
+#undef PSS_MRA
+    return hipSuccess;
+}
 #endif  // PSS_COMMON
 
 // ------------------------------------------------------- launch dispatch
@@ -2526,7 +2810,7 @@ hipError_t launch_line1d(int mode, int N, int nf, const LaunchArgs& a) {
         case 1024: return launch_line1d_L1024(mode, nf, a);
         case 2048: return launch_line1d_L2048(mode, nf, a);
         case 4096: return launch_line1d_L4096(mode, nf, a);
-        default: return hipErrorInvalidValue;
+        default: return launch_line1d_mr(mode, N, nf, a.ng, a);
     }
 }
 
@@ -2542,7 +2826,7 @@ hipError_t line1d_setup(int N) {
         case 1024: return line1d_setup_L1024();
         case 2048: return line1d_setup_L2048();
         case 4096: return line1d_setup_L4096();
-        default: return hipErrorInvalidValue;
+        default: return line1d_mr_setup();
     }
 }
 

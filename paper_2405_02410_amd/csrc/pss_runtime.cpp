@@ -686,8 +686,18 @@ pss_status choose_geometry(pss_ctx* c) {
         g.nublk = 1;
         g.nrowblk = 1;
         g.rb = 2;
-        if (pss::line1d_lds_bytes(nx) > 160 * 1024)
-            return fail(PSS_E_UNSUPPORTED, "line needs more LDS than a workgroup has");
+        if (is_pow2(nx)) {
+            if (pss::line1d_lds_bytes(nx) > 160 * 1024)
+                return fail(PSS_E_UNSUPPORTED, "line needs more LDS than a workgroup has");
+        } else {
+            // mixed-radix lines keep their spectra in LDS
+            const int NF = nf <= 1 ? 1 : (nf == 2 ? 2 : 4);
+            const size_t lds = pss::line1d_mr_lds_bytes(nx, NF, c->plan.ng);
+            if (lds > 160 * 1024)
+                return fail(PSS_E_UNSUPPORTED,
+                            "a line of %d sites with %d fields and %d factor fields needs %zu bytes of LDS "
+                            "(160 KiB at most)", nx, nf, c->plan.ng, lds);
+        }
         return PSS_OK;
     }
     auto tuned = [&](const char* key, int def) {
@@ -816,6 +826,7 @@ pss::LaunchArgs args(pss_ctx* c, int step_off = 0) {
     a.tw_x = c->d_tw_x;
     a.tw_y = c->d_tw_y;
     a.dim = c->ndim;
+    a.ng = c->plan.ng;
     return a;
 }
 
@@ -1574,9 +1585,14 @@ pss_status pss_lattice_create(pss_ctx** out, int32_t ndim, const int64_t n[3], c
     int64_t total = 1;
     for (int i = 0; i < ndim; ++i) {
         if (!(dx[i] > 0) || !std::isfinite(dx[i])) return fail(PSS_E_INVAL, "dx[%d] must be positive", i);
-        if (!is_pow2(n[i]) || n[i] < 8 || n[i] > 4096)
-            return fail(PSS_E_UNSUPPORTED, "n[%d] = %lld is not a power of two in [8, 4096]", i,
-                        static_cast<long long>(n[i]));
+        // 1D lines may also have a mixed-radix length 2^a 3^b 5^c (a >= 1)
+        pss::MrPlan mr{};
+        const bool mixed = ndim == 1 && n[i] >= 8 && n[i] <= 4096 && pss::mr_plan(static_cast<int>(n[i]), &mr);
+        if ((!is_pow2(n[i]) && !mixed) || n[i] < 8 || n[i] > 4096)
+            return fail(PSS_E_UNSUPPORTED,
+                        ndim == 1 ? "n[%d] = %lld is not an even 2^a 3^b 5^c in [8, 4096]"
+                                  : "n[%d] = %lld is not a power of two in [8, 4096]",
+                        i, static_cast<long long>(n[i]));
         total *= n[i];
     }
     if (total > (int64_t(1) << 31)) return fail(PSS_E_UNSUPPORTED, "more than 2^31 sites");

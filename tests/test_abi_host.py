@@ -252,8 +252,9 @@ def test_one_dimensional_lattices_on_host():
     f, grads = pss.kpz(k)
     assert len(grads) == 1
     k.validate()
+    pss.Lattice((100,), dt=0.01)  # 2^2 5^2: a mixed-radix line
     with pytest.raises(PssError) as e:
-        pss.Lattice((100,), dt=0.01)
+        pss.Lattice((98,), dt=0.01)  # a factor 7
     assert e.value.name == "PSS_E_UNSUPPORTED"
 
 
@@ -298,3 +299,18 @@ def test_field_bind_arguments_on_host():
     assert lib.pss_state_changed(lat._h) == 0
     with pytest.raises(ValueError):
         lat.bind(f, np.zeros(need // 4, dtype=np.float32))  # a host array is refused by the binding
+
+
+def test_mixed_radix_lengths_on_host():
+    # 1D lines may be any even 2^a 3^b 5^c in [8, 4096]; 2D and 3D stay powers of two
+    for n in (12, 96, 120, 160, 250, 1000, 3072, 4000):
+        lat = pss.Lattice((n,), dt=0.01)
+        f, _ = pss.model_b(lat)
+        lat.validate()
+    for n in (98, 63, 6, 4098, 14 * 3):
+        with pytest.raises(PssError) as e:
+            pss.Lattice((n,), dt=0.01)
+        assert e.value.name == "PSS_E_UNSUPPORTED", n
+    with pytest.raises(PssError) as e:
+        pss.Lattice((96, 64), dt=0.01)
+    assert e.value.name == "PSS_E_UNSUPPORTED"
