@@ -1463,8 +1463,9 @@ __global__ void philox_kernel(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3
 // Shell sums for the structure factor.  Thread i handles packed element i of
 // the 2D tiled layout [ctile][y][TC]; interior columns stand for the mode and
 // its conjugate partner (weight 2); column 0 is unpacked into kx = 0 and
-// kx = Nx/2 (weight 1 each) with the partner element at -y.  In 1D element i
-// is mode i of the full spectrum (weight 1).  shell_terms calls
+// kx = Nx/2 (weight 1 each) with the partner element at -y.  With dim = 1 the
+// array is a full spectrum, element ky Nx + kx for mode (kx, ky) (weight 1):
+// 1D lines and mixed-radix 2D lattices.  shell_terms calls
 // emit(j, t) for every term t = w * scale * |phi_hat|^2 of shell j.
 //
 // The sums are exact, so they do not depend on the order in which the
@@ -1484,8 +1485,10 @@ __device__ __forceinline__ void shell_terms(const float2* __restrict__ S, int64_
         if (j >= 1 && j < nshell) emit(j, scale * v * w, static_cast<unsigned int>(w));
     };
     if (dim == 1) {
-        const int k = static_cast<int>(e);
-        add(k < nx / 2 ? k : k - nx, 0, 0, mag(S[e]), 1);
+        // a full complex spectrum (1D lines, mixed-radix 2D lattices): mode
+        // (kx, ky) at ky Nx + kx, each mode once
+        const int kx = static_cast<int>(e % nx), ky = static_cast<int>(e / nx);
+        add(kx < nx / 2 ? kx : kx - nx, ny == 1 ? 0 : (ky < ny / 2 ? ky : ky - ny), 0, mag(S[e]), 1);
         return;
     }
     const int ncols = nx / 2;
@@ -1547,7 +1550,7 @@ __device__ __forceinline__ unsigned int shell_key(double t) {
 }
 
 __device__ __forceinline__ int64_t shell_total(int nx, int ny, int nz, int dim) {
-    return dim == 1 ? static_cast<int64_t>(nx) : static_cast<int64_t>(nx / 2) * ny * nz;
+    return dim == 1 ? static_cast<int64_t>(nx) * ny : static_cast<int64_t>(nx / 2) * ny * nz;
 }
 
 // pass 1: key[j] = max over the terms of shell j
@@ -1908,6 +1911,288 @@ hipError_t line1d_mr_setup() {
     PSS_MRA(1, false, MODE_INV_OUT)
 #undef PSS_MRB
 #undef PSS_MRA
+    return hipSuccess;
+}
+
+// ------------------------------------ 2D lattices of mixed-radix lengths
+// Nx, Ny even 2^a 3^b 5^c, at least one not a power of two.  The state of a
+// field is its full complex spectrum, mode (kx, ky) at ky Nx + kx (natural
+// order on both axes); real space is the real part of the inverse transform,
+// as everywhere.  A step is two launches, as on the power-of-two path: the
+// column kernel (one block per kx: forward y transforms of the channels, the
+// update, the de-aliased factors' inverse y transforms) and the row kernel
+// (one block per y: inverse x transforms of the factors, the real-space
+// products, their forward x transforms), each line in LDS and transformed
+// with the self-sorting passes above.
+
+template <int NF, bool GEN, int MODE>
+__global__ void __launch_bounds__(256)
+    mr2_col_kernel(const DevPlan* __restrict__ plan, Bufs bufs, const uint64_t* __restrict__ step_ctr,
+                   uint32_t* __restrict__ flag, int step_off, const float2* __restrict__ tw_g, MrPlan my) {
+    extern __shared__ float2 smem[];
+    const DevPlan& p = *plan;
+    const int Nx = p.n[0], Ny = my.n;
+    const int kx = blockIdx.x;
+    const int kxs = kx < (Nx >> 1) ? kx : kx - Nx;
+    const int t = threadIdx.x, T = blockDim.x;
+    float2* const tw = smem;
+    float2* const A = smem + Ny;
+    float2* const B = smem + 2 * Ny;
+    float2* const S = smem + 3 * Ny;  // [NF][Ny]
+    float2* const acc = S + NF * Ny;  // [NF][Ny]
+    for (int i = t; i < Ny; i += T) tw[i] = tw_g[i];
+    auto at = [&](int ky) { return static_cast<size_t>(ky) * Nx + kx; };
+    auto kq = [&](int ky) { return mode_q(p, kxs, ky < (Ny >> 1) ? ky : ky - Ny, 0); };
+
+    if constexpr (MODE == MODE_FWD_STORE) {
+        for (int ky = t; ky < Ny; ky += T) A[ky] = gload(bufs.in + at(ky));
+        __syncthreads();
+        const float2* r = mr_transform(A, B, tw, my, -1);
+        for (int ky = t; ky < Ny; ky += T) gstore(bufs.S[bufs.sel] + at(ky), r[ky]);
+        return;
+    }
+    if constexpr (MODE == MODE_INV_OUT) {
+        for (int ky = t; ky < Ny; ky += T) A[ky] = gload(bufs.S[bufs.sel] + at(ky));
+        __syncthreads();
+        const float2* r = mr_transform(A, B, tw, my, 1);
+        for (int y = t; y < Ny; y += T) gstore(bufs.out + at(y), r[y]);
+        return;
+    }
+
+    const int nf = p.nf;
+    for (int f = 0; f < nf; ++f)
+        for (int ky = t; ky < Ny; ky += T) S[f * Ny + ky] = gload(bufs.S[f] + at(ky));
+    __syncthreads();
+    auto source = [&](int src, int ky, const ModeQ& q) -> float2 {
+        if constexpr (GEN) {
+            if (src >= PSS_MAXF) {
+                const DevInterm& I = p.interm[src - PSS_MAXF];
+                float2 v = make_float2(0.f, 0.f);
+                for (int j = 0; j < I.nsrc; ++j) v = cadd(v, cmul(eval_op<true>(I.op[j], q), S[I.src[j] * Ny + ky]));
+                return cmul(v, cinv_implicit(1.f, eval_op<true>(I.den, q)));
+            }
+        }
+        return S[src * Ny + ky];
+    };
+
+    if constexpr (MODE == MODE_INTERM_OUT) {
+        for (int ky = t; ky < Ny; ky += T) A[ky] = source(PSS_MAXF + bufs.sel, ky, kq(ky));
+        __syncthreads();
+        const float2* r = mr_transform(A, B, tw, my, 1);
+        for (int y = t; y < Ny; y += T) gstore(bufs.out + at(y), r[y]);
+        return;
+    }
+
+    if constexpr (MODE == MODE_STEP) {
+        const uint32_t step = static_cast<uint32_t>(gload_u64(step_ctr)) + static_cast<uint32_t>(step_off);
+        for (int i = t; i < nf * Ny; i += T) acc[i] = make_float2(0.f, 0.f);
+        // channels: forward y transform of the x-transformed products, M(q) per mode
+        for (int ch = 0; ch < p.nch; ++ch) {
+            const DevChannel& C = p.ch[ch];
+            for (int y = t; y < Ny; y += T) A[y] = gload(bufs.N[ch] + at(y));
+            __syncthreads();
+            const float2* r = mr_transform(A, B, tw, my, -1);
+            for (int ky = t; ky < Ny; ky += T) {
+                const ModeQ q = kq(ky);
+                for (int o = 0; o < C.nout; ++o) {
+                    float2& d = acc[C.target[o] * Ny + ky];
+                    d = cadd(d, cmul(eval_op<GEN>(C.op[o], q), r[ky]));
+                }
+            }
+            __syncthreads();
+        }
+        // linear explicit terms, then the semi-implicit update with the noise
+        for (int ky = t; ky < Ny; ky += T) {
+            const ModeQ q = kq(ky);
+            for (int d = 0; d < p.nd; ++d) {
+                const DevDirect& Dd = p.direct[d];
+                float2& a = acc[Dd.target * Ny + ky];
+                a = cadd(a, cmul(eval_op<GEN>(Dd.op, q), source(Dd.src, ky, q)));
+            }
+        }
+        __syncthreads();
+        uint32_t bad = 0;
+        for (int ky = t; ky < Ny; ky += T) {
+            const ModeQ q = kq(ky);
+            const uint32_t lin = static_cast<uint32_t>(at(ky));
+            const uint32_t lneg =
+                static_cast<uint32_t>(static_cast<size_t>((Ny - ky) % Ny) * Nx + static_cast<size_t>((Nx - kx) % Nx));
+            for (int f = 0; f < nf; ++f) {
+                float2 r = cadd(S[f * Ny + ky], cscale(acc[f * Ny + ky], p.dt));
+                if (p.noisy[f] != 0) r = cadd(r, noise_mode<GEN>(p, f, step, lin, lneg, q));
+                r = cmul(r, cinv_implicit(p.dt, eval_op<GEN>(p.implicit_op[f], q)));
+                S[f * Ny + ky] = r;
+                gstore(bufs.S[f] + at(ky), r);
+                if (!(__builtin_isfinite(r.x) && __builtin_isfinite(r.y))) bad |= 1u << f;
+            }
+        }
+        if (bad) atomicOr(flag, bad);
+        __syncthreads();
+    }
+
+    // MODE_STEP and MODE_PROLOGUE: inverse y transforms of the de-aliased
+    // factors from the (new) state
+    for (int g = 0; g < p.ng; ++g) {
+        const DevMask& mk = p.mask[g];
+        for (int ky = t; ky < Ny; ky += T)
+            A[ky] = mask_keep(mk, kxs, ky < (Ny >> 1) ? ky : ky - Ny, 0) ? source(p.gfield[g], ky, kq(ky))
+                                                                        : make_float2(0.f, 0.f);
+        __syncthreads();
+        const float2* r = mr_transform(A, B, tw, my, 1);
+        for (int y = t; y < Ny; y += T) gstore(bufs.V[g] + at(y), r[y]);
+        __syncthreads();
+    }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256)
+    mr2_row_kernel(const DevPlan* __restrict__ plan, Bufs bufs, const float2* __restrict__ tw_g, MrPlan mx,
+                   int64_t advance, uint64_t* __restrict__ step_ctr) {
+    extern __shared__ float2 smem[];
+    const DevPlan& p = *plan;
+    const int Nx = mx.n;
+    const size_t row = static_cast<size_t>(blockIdx.x) * Nx;
+    const int t = threadIdx.x, T = blockDim.x;
+    float2* const tw = smem;
+    float2* const A = smem + Nx;
+    float2* const B = smem + 2 * Nx;
+    float* const u = reinterpret_cast<float*>(smem + 3 * Nx);  // [ng][Nx]
+    for (int i = t; i < Nx; i += T) tw[i] = tw_g[i];
+
+    if constexpr (MODE == MODE_R2C_IN) {
+        for (int x = t; x < Nx; x += T) A[x] = make_float2(bufs.real_in[row + x], 0.f);
+        __syncthreads();
+        const float2* r = mr_transform(A, B, tw, mx, -1);
+        for (int k = t; k < Nx; k += T) gstore(bufs.out + row + k, r[k]);
+        return;
+    }
+    if constexpr (MODE == MODE_C2R_OUT) {
+        for (int k = t; k < Nx; k += T) A[k] = gload(bufs.in + row + k);
+        __syncthreads();
+        const float2* r = mr_transform(A, B, tw, mx, 1);
+        for (int x = t; x < Nx; x += T) bufs.real_out[row + x] = r[x].x * p.inv_n;
+        return;
+    }
+    // MODE_STEP: factors to real space, products, forward x transforms
+    for (int g = 0; g < p.ng; ++g) {
+        for (int k = t; k < Nx; k += T) A[k] = gload(bufs.V[g] + row + k);
+        __syncthreads();
+        const float2* r = mr_transform(A, B, tw, mx, 1);
+        for (int x = t; x < Nx; x += T) u[g * Nx + x] = r[x].x * p.inv_n;
+        __syncthreads();
+    }
+    for (int ch = 0; ch < p.nch; ++ch) {
+        const DevChannel& C = p.ch[ch];
+        for (int x = t; x < Nx; x += T) {
+            float w = 0.f;
+            for (int k = 0; k < C.nprod; ++k) {
+                const DevProd& pd = C.prod[k];
+                float a = pd.coef;
+                for (int g = 0; g < p.ng; ++g)
+                    for (int e = 0; e < pd.pow[g]; ++e) a *= u[g * Nx + x];
+                w += a;
+            }
+            A[x] = make_float2(w, 0.f);
+        }
+        __syncthreads();
+        const float2* r = mr_transform(A, B, tw, mx, -1);
+        for (int k = t; k < Nx; k += T) gstore(bufs.N[ch] + row + k, r[k]);
+        __syncthreads();
+    }
+    if (advance != 0 && blockIdx.x == 0 && t == 0) *step_ctr += static_cast<uint64_t>(advance);
+}
+
+hipError_t launch_mr2_col(int mode, int nf, const LaunchArgs& a) {
+    MrPlan my{};
+    if (!mr_plan(a.ny, &my)) return hipErrorInvalidValue;
+    const int NF = nf <= 1 ? 1 : (nf == 2 ? 2 : 4);
+    const size_t lds = mr2_col_lds_bytes(my.n, NF);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    const dim3 grid(a.nx), block(256);
+    const bool gen = a.general || mode == MODE_INTERM_OUT;
+#define PSS_C2(NFV, G, M)                                                                                    \
+    hipLaunchKernelGGL((mr2_col_kernel<NFV, G, M>), grid, block, lds, a.stream, a.plan, a.bufs, a.step_ctr,  \
+                       a.flag, a.step_off, a.tw_u, my)
+#define PSS_C2F(M)                       \
+    do {                                 \
+        if (NF == 1) {                   \
+            if (gen)                     \
+                PSS_C2(1, true, M);      \
+            else                         \
+                PSS_C2(1, false, M);     \
+        } else if (NF == 2) {            \
+            if (gen)                     \
+                PSS_C2(2, true, M);      \
+            else                         \
+                PSS_C2(2, false, M);     \
+        } else {                         \
+            if (gen)                     \
+                PSS_C2(4, true, M);      \
+            else                         \
+                PSS_C2(4, false, M);     \
+        }                                \
+    } while (0)
+    switch (mode) {
+        case MODE_STEP: PSS_C2F(MODE_STEP); break;
+        case MODE_PROLOGUE: PSS_C2F(MODE_PROLOGUE); break;
+        case MODE_INTERM_OUT: PSS_C2F(MODE_INTERM_OUT); break;
+        case MODE_FWD_STORE: PSS_C2(1, false, MODE_FWD_STORE); break;
+        case MODE_INV_OUT: PSS_C2(1, false, MODE_INV_OUT); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef PSS_C2F
+#undef PSS_C2
+    return hipGetLastError();
+}
+
+hipError_t launch_mr2_row(int mode, const LaunchArgs& a) {
+    MrPlan mx{};
+    if (!mr_plan(a.nx, &mx)) return hipErrorInvalidValue;
+    const size_t lds = mr2_row_lds_bytes(mx.n, a.ng);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    const dim3 grid(a.ny), block(256);
+    uint64_t* ctr = const_cast<uint64_t*>(a.step_ctr);
+    switch (mode) {
+        case MODE_STEP:
+            hipLaunchKernelGGL(mr2_row_kernel<MODE_STEP>, grid, block, lds, a.stream, a.plan, a.bufs, a.tw_x, mx,
+                               a.advance, ctr);
+            break;
+        case MODE_R2C_IN:
+            hipLaunchKernelGGL(mr2_row_kernel<MODE_R2C_IN>, grid, block, lds, a.stream, a.plan, a.bufs, a.tw_x, mx,
+                               int64_t{0}, ctr);
+            break;
+        case MODE_C2R_OUT:
+            hipLaunchKernelGGL(mr2_row_kernel<MODE_C2R_OUT>, grid, block, lds, a.stream, a.plan, a.bufs, a.tw_x, mx,
+                               int64_t{0}, ctr);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t mr2_setup() {
+    const int lds = 160 * 1024;
+#define PSS_C2A(NFV, G, M)                                                                                     \
+    if (hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mr2_col_kernel<NFV, G, M>),          \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds))                   \
+        return e;
+#define PSS_C2B(M) PSS_C2A(1, false, M) PSS_C2A(1, true, M) PSS_C2A(2, false, M) PSS_C2A(2, true, M) \
+    PSS_C2A(4, false, M) PSS_C2A(4, true, M)
+    PSS_C2B(MODE_STEP)
+    PSS_C2B(MODE_PROLOGUE)
+    PSS_C2B(MODE_INTERM_OUT)
+    PSS_C2A(1, false, MODE_FWD_STORE)
+    PSS_C2A(1, false, MODE_INV_OUT)
+#undef PSS_C2B
+#undef PSS_C2A
+#define PSS_R2A(M)                                                                                             \
+    if (hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mr2_row_kernel<M>),                  \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds))                   \
+        return e;
+    PSS_R2A(MODE_STEP)
+    PSS_R2A(MODE_R2C_IN)
+    PSS_R2A(MODE_C2R_OUT)
+#undef PSS_R2A
     return hipSuccess;
 }
 #endif  // PSS_COMMON

@@ -147,6 +147,7 @@ std::vector<float2> twiddles(int L) {
 
 struct pss_ctx {
     int ndim = 2;
+    bool mixed = false;  // 2D sizes that are not both powers of two: full spectra, mixed-radix kernels
     int n[3] = {1, 1, 1};
     double dx[3] = {1, 1, 1};
     double dt = 0;
@@ -198,7 +199,7 @@ struct pss_ctx {
     int64_t sites() const { return static_cast<int64_t>(n[0]) * n[1] * n[2]; }
     // complex elements per spectral array: the packed half spectrum in 2D and
     // 3D, the full spectrum of the line in 1D
-    int64_t packed() const { return ndim == 1 ? sites() : sites() / 2; }
+    int64_t packed() const { return ndim == 1 || mixed ? sites() : sites() / 2; }
 };
 
 // A set of 2D lattices stepped together.  Lattices with the same sizes,
@@ -700,6 +701,22 @@ pss_status choose_geometry(pss_ctx* c) {
         }
         return PSS_OK;
     }
+    if (c->mixed) {
+        // one block per line on both passes, spectra in LDS (no tunable geometry)
+        c->lu = ny;
+        g.tc = 1;
+        g.to = 1;
+        g.pu = g.px = 4;
+        g.ntile = ncols;
+        g.nublk = nx;
+        g.nrowblk = ny;
+        g.rb = 2;
+        const int NF = nf <= 1 ? 1 : (nf == 2 ? 2 : 4);
+        const size_t lc = pss::mr2_col_lds_bytes(ny, NF), lr = pss::mr2_row_lds_bytes(nx, c->plan.ng);
+        if (lc > 160 * 1024 || lr > 160 * 1024)
+            return fail(PSS_E_UNSUPPORTED, "lattice needs more LDS than a workgroup has (%zu, %zu bytes)", lc, lr);
+        return PSS_OK;
+    }
     auto tuned = [&](const char* key, int def) {
         auto it = c->tune.find(key);
         return it == c->tune.end() ? def : static_cast<int>(it->second);
@@ -827,6 +844,8 @@ pss::LaunchArgs args(pss_ctx* c, int step_off = 0) {
     a.tw_y = c->d_tw_y;
     a.dim = c->ndim;
     a.ng = c->plan.ng;
+    a.nx = c->n[0];
+    a.ny = c->n[1];
     return a;
 }
 
@@ -964,6 +983,7 @@ pss_status materialize(pss_ctx* c) {
     if (pss_status s = upload_frames(c)) return s;
     HIP_TRY(hipMemcpy(c->d_plan, &c->plan, sizeof(pss::DevPlan), hipMemcpyHostToDevice));
     if (c->ndim == 1) HIP_TRY(pss::line1d_setup(c->n[0]));
+    if (c->mixed) HIP_TRY(pss::mr2_setup());
     HIP_TRY(hipMalloc(&c->d_member_u, sizeof(pss::Member)));
     HIP_TRY(hipMalloc(&c->d_member_x, sizeof(pss::Member)));
     const pss::Member mu = member_u(c), mx = member_x(c);
@@ -985,6 +1005,12 @@ pss_status prologue(pss_ctx* c) {
         return PSS_OK;
     }
     pss::LaunchArgs a = args(c);
+    if (c->mixed) {
+        HIP_TRY(pss::launch_mr2_col(pss::MODE_PROLOGUE, nf, a));
+        if (c->plan.nch > 0) HIP_TRY(pss::launch_mr2_row(pss::MODE_STEP, a));
+        c->dirty = false;
+        return PSS_OK;
+    }
     HIP_TRY(pss::launch_update(pss::MODE_PROLOGUE, c->lu, nf, a));
     if (c->plan.nch > 0) {
         if (c->ndim == 3) HIP_TRY(y_inverse_factors(c));
@@ -1074,13 +1100,21 @@ pss_status enqueue_steps(pss_ctx* c, int64_t k) {
     const bool x_advances = c->ndim == 2 && c->plan.nch > 0;
     for (int64_t i = 0; i < k; ++i) {
         pss::LaunchArgs a = args(c, static_cast<int>(i));
-        HIP_TRY(pss::launch_update(pss::MODE_STEP, c->lu, nf, a));
-        if (c->plan.nch > 0) {
-            if (c->ndim == 3) HIP_TRY(y_inverse_factors(c));
-            pss::LaunchArgs ax = xargs(c);
-            ax.advance = (x_advances && i == k - 1) ? k : 0;
-            HIP_TRY(pss::launch_xrow(pss::MODE_STEP, c->n[0], c->plan.ng, ax));
-            if (c->ndim == 3) HIP_TRY(y_forward_channels(c));
+        if (c->mixed) {
+            HIP_TRY(pss::launch_mr2_col(pss::MODE_STEP, nf, a));
+            if (c->plan.nch > 0) {
+                a.advance = (x_advances && i == k - 1) ? k : 0;
+                HIP_TRY(pss::launch_mr2_row(pss::MODE_STEP, a));
+            }
+        } else {
+            HIP_TRY(pss::launch_update(pss::MODE_STEP, c->lu, nf, a));
+            if (c->plan.nch > 0) {
+                if (c->ndim == 3) HIP_TRY(y_inverse_factors(c));
+                pss::LaunchArgs ax = xargs(c);
+                ax.advance = (x_advances && i == k - 1) ? k : 0;
+                HIP_TRY(pss::launch_xrow(pss::MODE_STEP, c->n[0], c->plan.ng, ax));
+                if (c->ndim == 3) HIP_TRY(y_forward_channels(c));
+            }
         }
         if (has_frames(c)) {
             // boundary frames: each framed field through real space, then the
@@ -1106,6 +1140,15 @@ pss_status forward_to_state(pss_ctx* c, int field) {
         a.bufs.real_in = c->d_real;
         a.bufs.sel = field;
         HIP_TRY(pss::launch_line1d(pss::MODE_FWD_STORE, c->n[0], 1, a));
+        return PSS_OK;
+    }
+    if (c->mixed) {
+        a.bufs.real_in = c->d_real;
+        a.bufs.out = c->d_tmp;
+        HIP_TRY(pss::launch_mr2_row(pss::MODE_R2C_IN, a));
+        a.bufs.in = c->d_tmp;
+        a.bufs.sel = field;
+        HIP_TRY(pss::launch_mr2_col(pss::MODE_FWD_STORE, 1, a));
         return PSS_OK;
     }
     a.bufs.real_in = c->d_real;
@@ -1136,6 +1179,15 @@ pss_status state_to_real(pss_ctx* c, int field) {
         HIP_TRY(pss::launch_line1d(pss::MODE_INV_OUT, c->n[0], 1, a));
         return PSS_OK;
     }
+    if (c->mixed) {
+        a.bufs.sel = field;
+        a.bufs.out = c->d_tmp;
+        HIP_TRY(pss::launch_mr2_col(pss::MODE_INV_OUT, 1, a));
+        a.bufs.in = c->d_tmp;
+        a.bufs.real_out = c->d_real;
+        HIP_TRY(pss::launch_mr2_row(pss::MODE_C2R_OUT, a));
+        return PSS_OK;
+    }
     a.bufs.sel = field;
     a.bufs.out = c->d_tmp;
     HIP_TRY(pss::launch_update(pss::MODE_INV_OUT, c->lu, 1, a));
@@ -1161,6 +1213,15 @@ pss_status interm_to_real(pss_ctx* c, int i) {
         a.bufs.sel = i;
         a.bufs.real_out = c->d_real;
         HIP_TRY(pss::launch_line1d(pss::MODE_INTERM_OUT, c->n[0], static_cast<int>(c->fields.size()), a));
+        return PSS_OK;
+    }
+    if (c->mixed) {
+        a.bufs.sel = i;
+        a.bufs.out = c->d_tmp;
+        HIP_TRY(pss::launch_mr2_col(pss::MODE_INTERM_OUT, static_cast<int>(c->fields.size()), a));
+        a.bufs.in = c->d_tmp;
+        a.bufs.real_out = c->d_real;
+        HIP_TRY(pss::launch_mr2_row(pss::MODE_C2R_OUT, a));
         return PSS_OK;
     }
     a.bufs.sel = i;
@@ -1585,12 +1646,12 @@ pss_status pss_lattice_create(pss_ctx** out, int32_t ndim, const int64_t n[3], c
     int64_t total = 1;
     for (int i = 0; i < ndim; ++i) {
         if (!(dx[i] > 0) || !std::isfinite(dx[i])) return fail(PSS_E_INVAL, "dx[%d] must be positive", i);
-        // 1D lines may also have a mixed-radix length 2^a 3^b 5^c (a >= 1)
+        // 1D and 2D sizes may also be mixed-radix lengths 2^a 3^b 5^c (a >= 1)
         pss::MrPlan mr{};
-        const bool mixed = ndim == 1 && n[i] >= 8 && n[i] <= 4096 && pss::mr_plan(static_cast<int>(n[i]), &mr);
+        const bool mixed = ndim <= 2 && n[i] >= 8 && n[i] <= 4096 && pss::mr_plan(static_cast<int>(n[i]), &mr);
         if ((!is_pow2(n[i]) && !mixed) || n[i] < 8 || n[i] > 4096)
             return fail(PSS_E_UNSUPPORTED,
-                        ndim == 1 ? "n[%d] = %lld is not an even 2^a 3^b 5^c in [8, 4096]"
+                        ndim <= 2 ? "n[%d] = %lld is not an even 2^a 3^b 5^c in [8, 4096]"
                                   : "n[%d] = %lld is not a power of two in [8, 4096]",
                         i, static_cast<long long>(n[i]));
         total *= n[i];
@@ -1602,6 +1663,7 @@ pss_status pss_lattice_create(pss_ctx** out, int32_t ndim, const int64_t n[3], c
         c->n[i] = static_cast<int>(n[i]);
         c->dx[i] = dx[i];
     }
+    c->mixed = ndim == 2 && (!is_pow2(n[0]) || !is_pow2(n[1]));
     c->dt = dt;
     *out = c;
     return PSS_OK;
@@ -1982,6 +2044,14 @@ pss_status pss_spectrum_download(pss_ctx* c, int32_t field, float* half, int32_t
             h[2 * k] = S[k].x;
             h[2 * k + 1] = S[k].y;
         }
+    } else if (c->mixed) {  // columns kx = 0 .. Nx/2 of the full 2D spectrum
+        const int nx = c->n[0], nh = nx / 2 + 1;
+        for (int y = 0; y < c->n[1]; ++y)
+            for (int k = 0; k < nh; ++k) {
+                const float2 v = S[static_cast<size_t>(y) * nx + k];
+                h[2 * (static_cast<size_t>(y) * nh + k)] = v.x;
+                h[2 * (static_cast<size_t>(y) * nh + k) + 1] = v.y;
+            }
     } else {
         unpack_half(c, S, h.data());
     }
@@ -2157,7 +2227,7 @@ pss_status pss_structure_factor(pss_ctx* c, int32_t field, double* S, int64_t* c
     HIP_TRY(hipMemsetAsync(c->d_shell_acc, 0, sizeof(unsigned long long) * pss::kShellWords * ns, c->stream));
     const double dV = c->dx[0] * c->dx[1] * (c->ndim == 3 ? c->dx[2] : 1.0);
     HIP_TRY(pss::launch_shells(c->stream, c->d_state[fd], c->n[0], c->n[1], c->ndim == 3 ? c->n[2] : 1, c->geo.tc,
-                               c->ndim, dV / static_cast<double>(c->sites()), ns, c->d_shell_acc));
+                               c->mixed ? 1 : c->ndim, dV / static_cast<double>(c->sites()), ns, c->d_shell_acc));
     // shells 1 .. ns-1: the means, then the populations
     static_assert(sizeof(int64_t) == sizeof(unsigned long long), "count width");
     if (ns > 1) {
@@ -2189,7 +2259,7 @@ pss_status pss_structure_factor_noalloc(pss_ctx* c, int32_t field, double* S, in
     HIP_TRY(pss::launch_zero_words(c->stream, acc, pss::kShellWords * ns));
     const double dV = c->dx[0] * c->dx[1] * (c->ndim == 3 ? c->dx[2] : 1.0);
     HIP_TRY(pss::launch_shells(c->stream, c->d_state[fd], c->n[0], c->n[1], c->ndim == 3 ? c->n[2] : 1, c->geo.tc,
-                               c->ndim, dV / static_cast<double>(c->sites()), ns, acc));
+                               c->mixed ? 1 : c->ndim, dV / static_cast<double>(c->sites()), ns, acc));
     // shells 1 .. ns-1 straight into the caller's arrays
     static_assert(sizeof(int64_t) == sizeof(unsigned long long), "count width");
     if (ns > 1) {
@@ -2236,6 +2306,10 @@ pss_status pss_kernel_bytes(pss_ctx* c, int32_t which, double* bytes) {
         *bytes = 2 * arr * nf;
         return PSS_OK;
     }
+    if (c->mixed) {  // full arrays: channels in, state in/out, factors out; factors in, channels out
+        *bytes = which == 0 ? arr * (P.nch + 2 * nf + P.ng) : arr * (P.ng + P.nch);
+        return PSS_OK;
+    }
     switch (which) {
         case 0: *bytes = arr * (P.nch + 2 * nf) + vbytes; break;  // channels in, state in/out, factors out
         case 1: *bytes = vbytes + arr * P.nch; break;             // factors in, channels out
@@ -2248,6 +2322,7 @@ pss_status pss_kernel_bytes(pss_ctx* c, int32_t which, double* bytes) {
 pss_status pss_time_kernel(pss_ctx* c, int32_t which, int32_t reps, double* ms, const char** name) {
     if (pss_status s = check_ctx(c)) return s;
     if (!ms || reps < 1) return fail(PSS_E_INVAL, "bad arguments");
+    if (c->mixed) return fail(PSS_E_UNSUPPORTED, "kernel timing covers the power-of-two lattices");
     if (pss_status s = materialize(c)) return s;
     if (pss_status s_bw = begin_work(c)) return s_bw;
     const int nk = c->ndim == 3 ? 4 : (c->ndim == 2 ? 2 : 1);
@@ -2298,7 +2373,7 @@ pss_status pss_autotune(pss_ctx* c, int32_t reps, double* us_per_step) {
     if (c->planned) return fail(PSS_E_STATE, "autotune before the plan is built (first upload, init or step)");
     if (reps < 1) return fail(PSS_E_INVAL, "reps must be >= 1");
     if (pss_status s = validate(c)) return s;
-    if (c->ndim == 1) {  // a 1D lattice has no launch geometry to choose
+    if (c->ndim == 1 || c->mixed) {  // one block per line: no launch geometry to choose
         if (us_per_step) *us_per_step = 0.0;
         return PSS_OK;
     }
@@ -2395,7 +2470,8 @@ pss_status pss_adjoint_model_b_forward(pss_ctx* c, int64_t nsteps, int32_t ckpt_
     if (pss_status s = check_ctx(c)) return s;
     if (nsteps < 1 || ckpt_every < 1) return fail(PSS_E_INVAL, "need nsteps >= 1 and ckpt_every >= 1");
     if (!S_target || !loss) return fail(PSS_E_INVAL, "null argument");
-    if (c->ndim != 2) return fail(PSS_E_UNSUPPORTED, "the adjoint is implemented for 2D lattices");
+    if (c->ndim != 2 || c->mixed)
+        return fail(PSS_E_UNSUPPORTED, "the adjoint is implemented for 2D lattices of power-of-two sizes");
     if (c->tapes > 0) return fail(PSS_E_STATE, "this lattice already holds an adjoint tape");
     // recognise Model B: one field; implicit -(a q^2 + k q^4); explicit -b q^2 F[phi^3]; noise D q^2
     double a = 0, b = 0, k = 0, D = 0;
@@ -2662,7 +2738,8 @@ pss_status pss_batch_create(pss_batch** out, pss_ctx* const* lattices, int32_t n
     if (!lattices || n < 1) return fail(PSS_E_INVAL, "a batch needs at least one lattice");
     for (int32_t i = 0; i < n; ++i) {
         if (!lattices[i]) return fail(PSS_E_INVAL, "lattice %d is null", i);
-        if (lattices[i]->ndim != 2) return fail(PSS_E_UNSUPPORTED, "lattice %d: batches hold 2D lattices only", i);
+        if (lattices[i]->ndim != 2 || lattices[i]->mixed)
+            return fail(PSS_E_UNSUPPORTED, "lattice %d: batches hold 2D lattices of power-of-two sizes only", i);
         if (has_frames(lattices[i]))
             return fail(PSS_E_UNSUPPORTED, "lattice %d has boundary frames, which batched steps do not apply", i);
         for (int32_t j = 0; j < i; ++j)

@@ -302,7 +302,7 @@ def test_field_bind_arguments_on_host():
 
 
 def test_mixed_radix_lengths_on_host():
-    # 1D lines may be any even 2^a 3^b 5^c in [8, 4096]; 2D and 3D stay powers of two
+    # 1D lines may be any even 2^a 3^b 5^c in [8, 4096]
     for n in (12, 96, 120, 160, 250, 1000, 3072, 4000):
         lat = pss.Lattice((n,), dt=0.01)
         f, _ = pss.model_b(lat)
@@ -311,6 +311,12 @@ def test_mixed_radix_lengths_on_host():
         with pytest.raises(PssError) as e:
             pss.Lattice((n,), dt=0.01)
         assert e.value.name == "PSS_E_UNSUPPORTED", n
-    with pytest.raises(PssError) as e:
-        pss.Lattice((96, 64), dt=0.01)
-    assert e.value.name == "PSS_E_UNSUPPORTED"
+    # 2D: even 2^a 3^b 5^c sizes on either axis; 3D stays powers of two
+    for n in ((96, 64), (64, 96), (120, 90), (1000, 12)):
+        lat = pss.Lattice(n, dt=0.01)
+        pss.model_b(lat)
+        lat.validate()
+    for n in ((98, 64), (63, 64), (96, 64, 64)):
+        with pytest.raises(PssError) as e:
+            pss.Lattice(n, dt=0.01)
+        assert e.value.name == "PSS_E_UNSUPPORTED", n
