@@ -101,18 +101,17 @@ typedef struct {
  * line of the examples in Sec. "Callback functions" and "De-aliasing") is
  * stepped by one block that holds the whole line; its state is the full
  * complex spectrum of the line (pss_state_size), and it takes part in neither
- * batches nor the adjoint (PSS_E_UNSUPPORTED there).  In 1D and 2D a size
- * may also be an even 2^a 3^b 5^c (Sec. "Benchmarking": sizes other than
- * powers of two are allowed, at a lower speed).  Such lattices run on a
- * generic path: the state of a field is its full complex spectrum (mode
- * (kx, ky) at ky Nx + kx; pss_state_size and pss_field_state_bytes count it),
+ * batches nor the adjoint (PSS_E_UNSUPPORTED there).  A size may also be an
+ * even 2^a 3^b 5^c (Sec. "Benchmarking": sizes other than powers of two are
+ * allowed, at a lower speed).  Such lattices run on a generic path: the
+ * state of a field is its full complex spectrum (mode (kx, ky, kz) at
+ * (kz Ny + ky) Nx + kx; pss_state_size and pss_field_state_bytes count it),
  * each line is transformed in LDS, which bounds the line length times the
  * field and factor counts (PSS_E_UNSUPPORTED when the plan is built, with the
- * bytes it would need), and a 2D one takes part in neither batches, the
- * adjoint nor pss_time_kernel (PSS_E_UNSUPPORTED).
+ * bytes it would need), and a 2D or 3D one takes part in neither batches,
+ * the adjoint nor pss_time_kernel (PSS_E_UNSUPPORTED).
  * Errors: PSS_E_INVAL (null out, dt <= 0, dx <= 0), PSS_E_UNSUPPORTED (ndim
- * not 1, 2 or 3, a size outside [8, 4096], in 3D not a power of two, in 1D
- * and 2D not an even 2^a 3^b 5^c). */
+ * not 1, 2 or 3, a size outside [8, 4096] or not an even 2^a 3^b 5^c). */
 pss_status pss_lattice_create(pss_ctx **out, int32_t ndim, const int64_t n[3],
                               const double dx[3], double dt);
 
@@ -334,7 +333,7 @@ pss_status pss_sync(pss_ctx *ctx);
 pss_status pss_field_bind(pss_ctx *ctx, int32_t field, void *device_ptr, size_t bytes);
 
 /* Bytes of one dynamic field's Fourier state (8 bytes per stored complex
- * mode: (Nx/2) Ny Nz in 2D and 3D, Nx in 1D, Nx Ny for a 2D lattice of
+ * mode: (Nx/2) Ny Nz in 2D and 3D, Nx in 1D, Nx Ny Nz for a lattice of
  * mixed-radix sizes). */
 pss_status pss_field_state_bytes(pss_ctx *ctx, int32_t field, size_t *bytes);
 

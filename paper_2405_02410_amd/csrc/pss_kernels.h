@@ -124,7 +124,7 @@ struct LaunchArgs {
     int dim;             // 1, 2 or 3
     int nsteps;          // 1D step launches: steps of the launch
     int ng;              // factor slots of the plan (1D lines of mixed-radix length size their LDS by it)
-    int nx, ny;          // lattice sizes (the mixed-radix 2D launches)
+    int nx, ny, nz;      // lattice sizes (the mixed-radix launches)
 };
 
 // Fused batch launches: one update-phase and one x-phase launch cover every
@@ -244,8 +244,8 @@ inline size_t line1d_mr_lds_bytes(int N, int NF, int ng) {
 hipError_t launch_line1d_mr(int mode, int N, int nf, int ng, const LaunchArgs& a);
 hipError_t line1d_mr_setup();
 
-// 2D lattices of mixed-radix sizes (even 2^a 3^b 5^c, not both powers of
-// two): full complex spectra, mode (kx, ky) at ky Nx + kx.  Column launch
+// 2D and 3D lattices of mixed-radix sizes (even 2^a 3^b 5^c, not all powers
+// of two): full complex spectra, mode (kx, ky, kz) at (kz Ny + ky) Nx + kx.  Column launch
 // (one block per kx): MODE_STEP (channels N[ch] in (y, kx) form -> update ->
 // factors V[g] in (y, kx) form), MODE_PROLOGUE (factors from the state),
 // MODE_FWD_STORE (in, (y, kx) -> state sel), MODE_INV_OUT (state sel -> out,
@@ -259,8 +259,12 @@ inline size_t mr2_row_lds_bytes(int Nx, int ng) {
     return sizeof(float2) * static_cast<size_t>(Nx) * 3 +
            sizeof(float) * static_cast<size_t>(Nx) * static_cast<size_t>(ng > 0 ? ng : 1);
 }
+// In 3D the column launch runs along z (one block per (kx, ky)), the row
+// launch covers Ny Nz rows, and launch_mr3_ypass transforms the arrays of ya
+// along y (sign -1 forward, +1 inverse), one block per (kx, z).
 hipError_t launch_mr2_col(int mode, int nf, const LaunchArgs& a);
 hipError_t launch_mr2_row(int mode, const LaunchArgs& a);
+hipError_t launch_mr3_ypass(int sign, const YArgs& ya, const LaunchArgs& a);
 hipError_t mr2_setup();
 hipError_t launch_xrow(int mode, int L, int ng, const LaunchArgs& a);
 hipError_t launch_ypass(int mode, int L, const YArgs& ya, const LaunchArgs& a);

@@ -1464,8 +1464,8 @@ __global__ void philox_kernel(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3
 // the 2D tiled layout [ctile][y][TC]; interior columns stand for the mode and
 // its conjugate partner (weight 2); column 0 is unpacked into kx = 0 and
 // kx = Nx/2 (weight 1 each) with the partner element at -y.  With dim = 1 the
-// array is a full spectrum, element ky Nx + kx for mode (kx, ky) (weight 1):
-// 1D lines and mixed-radix 2D lattices.  shell_terms calls
+// array is a full spectrum, element (kz Ny + ky) Nx + kx for mode (kx, ky, kz)
+// (weight 1): 1D lines and mixed-radix 2D and 3D lattices.  shell_terms calls
 // emit(j, t) for every term t = w * scale * |phi_hat|^2 of shell j.
 //
 // The sums are exact, so they do not depend on the order in which the
@@ -1485,10 +1485,12 @@ __device__ __forceinline__ void shell_terms(const float2* __restrict__ S, int64_
         if (j >= 1 && j < nshell) emit(j, scale * v * w, static_cast<unsigned int>(w));
     };
     if (dim == 1) {
-        // a full complex spectrum (1D lines, mixed-radix 2D lattices): mode
-        // (kx, ky) at ky Nx + kx, each mode once
-        const int kx = static_cast<int>(e % nx), ky = static_cast<int>(e / nx);
-        add(kx < nx / 2 ? kx : kx - nx, ny == 1 ? 0 : (ky < ny / 2 ? ky : ky - ny), 0, mag(S[e]), 1);
+        // a full complex spectrum (1D lines, mixed-radix 2D and 3D
+        // lattices): each mode once
+        const int kx = static_cast<int>(e % nx), ky = static_cast<int>((e / nx) % ny),
+                  kz = static_cast<int>(e / (static_cast<int64_t>(nx) * ny));
+        add(kx < nx / 2 ? kx : kx - nx, ny == 1 ? 0 : (ky < ny / 2 ? ky : ky - ny),
+            nz == 1 ? 0 : (kz < nz / 2 ? kz : kz - nz), mag(S[e]), 1);
         return;
     }
     const int ncols = nx / 2;
@@ -1550,7 +1552,7 @@ __device__ __forceinline__ unsigned int shell_key(double t) {
 }
 
 __device__ __forceinline__ int64_t shell_total(int nx, int ny, int nz, int dim) {
-    return dim == 1 ? static_cast<int64_t>(nx) * ny : static_cast<int64_t>(nx / 2) * ny * nz;
+    return dim == 1 ? static_cast<int64_t>(nx) * ny * nz : static_cast<int64_t>(nx / 2) * ny * nz;
 }
 
 // pass 1: key[j] = max over the terms of shell j
@@ -1914,16 +1916,17 @@ hipError_t line1d_mr_setup() {
     return hipSuccess;
 }
 
-// ------------------------------------ 2D lattices of mixed-radix lengths
-// Nx, Ny even 2^a 3^b 5^c, at least one not a power of two.  The state of a
-// field is its full complex spectrum, mode (kx, ky) at ky Nx + kx (natural
-// order on both axes); real space is the real part of the inverse transform,
-// as everywhere.  A step is two launches, as on the power-of-two path: the
-// column kernel (one block per kx: forward y transforms of the channels, the
-// update, the de-aliased factors' inverse y transforms) and the row kernel
-// (one block per y: inverse x transforms of the factors, the real-space
-// products, their forward x transforms), each line in LDS and transformed
-// with the self-sorting passes above.
+// ------------------------------- 2D and 3D lattices of mixed-radix sizes
+// Every size an even 2^a 3^b 5^c, at least one not a power of two.  The state
+// of a field is its full complex spectrum, mode (kx, ky, kz) at
+// (kz Ny + ky) Nx + kx (natural order on every axis); real space is the real
+// part of the inverse transform, as everywhere.  A step is launched as on the
+// power-of-two path: the column kernel (one block per line along the last
+// axis: forward transforms of the channels, the update, the de-aliased
+// factors' inverse transforms), in 3D a y pass, the row kernel (one block per
+// x row: inverse x transforms of the factors, the real-space products, their
+// forward x transforms), in 3D a y pass back; each line in LDS and
+// transformed with the self-sorting passes above.
 
 template <int NF, bool GEN, int MODE>
 __global__ void __launch_bounds__(256)
@@ -1931,18 +1934,26 @@ __global__ void __launch_bounds__(256)
                    uint32_t* __restrict__ flag, int step_off, const float2* __restrict__ tw_g, MrPlan my) {
     extern __shared__ float2 smem[];
     const DevPlan& p = *plan;
-    const int Nx = p.n[0], Ny = my.n;
-    const int kx = blockIdx.x;
+    // the line runs along the last axis: y in 2D (block = kx), z in 3D
+    // (block = (kx, ky)); "ky" below is the index along the line
+    const int Nx = p.n[0], Ny = my.n, N1 = p.n[1];
+    const bool d3 = p.n[2] > 1;
+    const int kx = d3 ? static_cast<int>(blockIdx.x % Nx) : static_cast<int>(blockIdx.x);
+    const int ko = d3 ? static_cast<int>(blockIdx.x / Nx) : 0;  // ky of a 3D line
     const int kxs = kx < (Nx >> 1) ? kx : kx - Nx;
+    const int kos = ko < (N1 >> 1) ? ko : ko - N1;
+    const size_t base = d3 ? static_cast<size_t>(ko) * Nx + kx : static_cast<size_t>(kx);
+    const size_t su = d3 ? static_cast<size_t>(Nx) * N1 : static_cast<size_t>(Nx);
     const int t = threadIdx.x, T = blockDim.x;
     float2* const tw = smem;
     float2* const A = smem + Ny;
     float2* const B = smem + 2 * Ny;
-    float2* const S = smem + 3 * Ny;  // [NF][Ny]
-    float2* const acc = S + NF * Ny;  // [NF][Ny]
+    float2* const S = smem + 3 * Ny;  // [NF][line]
+    float2* const acc = S + NF * Ny;  // [NF][line]
     for (int i = t; i < Ny; i += T) tw[i] = tw_g[i];
-    auto at = [&](int ky) { return static_cast<size_t>(ky) * Nx + kx; };
-    auto kq = [&](int ky) { return mode_q(p, kxs, ky < (Ny >> 1) ? ky : ky - Ny, 0); };
+    auto at = [&](int ky) { return base + static_cast<size_t>(ky) * su; };
+    auto ws = [&](int ky) { return ky < (Ny >> 1) ? ky : ky - Ny; };
+    auto kq = [&](int ky) { return d3 ? mode_q(p, kxs, kos, ws(ky)) : mode_q(p, kxs, ws(ky), 0); };
 
     if constexpr (MODE == MODE_FWD_STORE) {
         for (int ky = t; ky < Ny; ky += T) A[ky] = gload(bufs.in + at(ky));
@@ -2015,8 +2026,9 @@ __global__ void __launch_bounds__(256)
         for (int ky = t; ky < Ny; ky += T) {
             const ModeQ q = kq(ky);
             const uint32_t lin = static_cast<uint32_t>(at(ky));
-            const uint32_t lneg =
-                static_cast<uint32_t>(static_cast<size_t>((Ny - ky) % Ny) * Nx + static_cast<size_t>((Nx - kx) % Nx));
+            const size_t neg_line = d3 ? static_cast<size_t>((Ny - ky) % Ny) * N1 + static_cast<size_t>((N1 - ko) % N1)
+                                       : static_cast<size_t>((Ny - ky) % Ny);
+            const uint32_t lneg = static_cast<uint32_t>(neg_line * Nx + static_cast<size_t>((Nx - kx) % Nx));
             for (int f = 0; f < nf; ++f) {
                 float2 r = cadd(S[f * Ny + ky], cscale(acc[f * Ny + ky], p.dt));
                 if (p.noisy[f] != 0) r = cadd(r, noise_mode<GEN>(p, f, step, lin, lneg, q));
@@ -2035,8 +2047,9 @@ __global__ void __launch_bounds__(256)
     for (int g = 0; g < p.ng; ++g) {
         const DevMask& mk = p.mask[g];
         for (int ky = t; ky < Ny; ky += T)
-            A[ky] = mask_keep(mk, kxs, ky < (Ny >> 1) ? ky : ky - Ny, 0) ? source(p.gfield[g], ky, kq(ky))
-                                                                        : make_float2(0.f, 0.f);
+            A[ky] = (d3 ? mask_keep(mk, kxs, kos, ws(ky)) : mask_keep(mk, kxs, ws(ky), 0))
+                        ? source(p.gfield[g], ky, kq(ky))
+                        : make_float2(0.f, 0.f);
         __syncthreads();
         const float2* r = mr_transform(A, B, tw, my, 1);
         for (int y = t; y < Ny; y += T) gstore(bufs.V[g] + at(y), r[y]);
@@ -2102,13 +2115,45 @@ __global__ void __launch_bounds__(256)
     if (advance != 0 && blockIdx.x == 0 && t == 0) *step_ctr += static_cast<uint64_t>(advance);
 }
 
+// 3D: transforms along y of the arrays of ya (in place allowed: a line is
+// read whole before it is written), one block per (kx, z) line
+__global__ void __launch_bounds__(256)
+    mr3_ypass_kernel(const DevPlan* __restrict__ plan, YArgs ya, const float2* __restrict__ tw_g, MrPlan my, int sign) {
+    extern __shared__ float2 smem[];
+    const DevPlan& p = *plan;
+    const int Nx = p.n[0], Ny = my.n;
+    const int kx = static_cast<int>(blockIdx.x % Nx), z = static_cast<int>(blockIdx.x / Nx);
+    const size_t base = static_cast<size_t>(z) * Nx * Ny + kx;
+    const int t = threadIdx.x, T = blockDim.x;
+    float2* const tw = smem;
+    float2* const A = smem + Ny;
+    float2* const B = smem + 2 * Ny;
+    for (int i = t; i < Ny; i += T) tw[i] = tw_g[i];
+    for (int i = 0; i < ya.n; ++i) {
+        for (int y = t; y < Ny; y += T) A[y] = gload(ya.src[i] + base + static_cast<size_t>(y) * Nx);
+        __syncthreads();
+        const float2* r = mr_transform(A, B, tw, my, sign);
+        for (int y = t; y < Ny; y += T) gstore(ya.dst[i] + base + static_cast<size_t>(y) * Nx, r[y]);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_mr3_ypass(int sign, const YArgs& ya, const LaunchArgs& a) {
+    MrPlan my{};
+    if (!mr_plan(a.ny, &my) || a.dim != 3) return hipErrorInvalidValue;
+    if (ya.n <= 0) return hipSuccess;
+    const size_t lds = sizeof(float2) * 3 * static_cast<size_t>(my.n);
+    hipLaunchKernelGGL(mr3_ypass_kernel, dim3(a.nx * a.nz), dim3(256), lds, a.stream, a.plan, ya, a.tw_y, my, sign);
+    return hipGetLastError();
+}
+
 hipError_t launch_mr2_col(int mode, int nf, const LaunchArgs& a) {
     MrPlan my{};
-    if (!mr_plan(a.ny, &my)) return hipErrorInvalidValue;
+    if (!mr_plan(a.dim == 3 ? a.nz : a.ny, &my)) return hipErrorInvalidValue;
     const int NF = nf <= 1 ? 1 : (nf == 2 ? 2 : 4);
     const size_t lds = mr2_col_lds_bytes(my.n, NF);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    const dim3 grid(a.nx), block(256);
+    const dim3 grid(a.dim == 3 ? a.nx * a.ny : a.nx), block(256);
     const bool gen = a.general || mode == MODE_INTERM_OUT;
 #define PSS_C2(NFV, G, M)                                                                                    \
     hipLaunchKernelGGL((mr2_col_kernel<NFV, G, M>), grid, block, lds, a.stream, a.plan, a.bufs, a.step_ctr,  \
@@ -2150,7 +2195,7 @@ hipError_t launch_mr2_row(int mode, const LaunchArgs& a) {
     if (!mr_plan(a.nx, &mx)) return hipErrorInvalidValue;
     const size_t lds = mr2_row_lds_bytes(mx.n, a.ng);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    const dim3 grid(a.ny), block(256);
+    const dim3 grid(a.ny * (a.dim == 3 ? a.nz : 1)), block(256);
     uint64_t* ctr = const_cast<uint64_t*>(a.step_ctr);
     switch (mode) {
         case MODE_STEP:
@@ -2193,7 +2238,8 @@ hipError_t mr2_setup() {
     PSS_R2A(MODE_R2C_IN)
     PSS_R2A(MODE_C2R_OUT)
 #undef PSS_R2A
-    return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&mr3_ypass_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 #endif  // PSS_COMMON
 

@@ -702,17 +702,17 @@ pss_status choose_geometry(pss_ctx* c) {
         return PSS_OK;
     }
     if (c->mixed) {
-        // one block per line on both passes, spectra in LDS (no tunable geometry)
-        c->lu = ny;
+        // one block per line on every pass, spectra in LDS (no tunable geometry)
+        c->lu = c->ndim == 3 ? nz : ny;
         g.tc = 1;
         g.to = 1;
         g.pu = g.px = 4;
         g.ntile = ncols;
-        g.nublk = nx;
-        g.nrowblk = ny;
+        g.nublk = c->ndim == 3 ? nx * ny : nx;
+        g.nrowblk = ny * nz;
         g.rb = 2;
         const int NF = nf <= 1 ? 1 : (nf == 2 ? 2 : 4);
-        const size_t lc = pss::mr2_col_lds_bytes(ny, NF), lr = pss::mr2_row_lds_bytes(nx, c->plan.ng);
+        const size_t lc = pss::mr2_col_lds_bytes(c->lu, NF), lr = pss::mr2_row_lds_bytes(nx, c->plan.ng);
         if (lc > 160 * 1024 || lr > 160 * 1024)
             return fail(PSS_E_UNSUPPORTED, "lattice needs more LDS than a workgroup has (%zu, %zu bytes)", lc, lr);
         return PSS_OK;
@@ -846,6 +846,7 @@ pss::LaunchArgs args(pss_ctx* c, int step_off = 0) {
     a.ng = c->plan.ng;
     a.nx = c->n[0];
     a.ny = c->n[1];
+    a.nz = c->n[2];
     return a;
 }
 
@@ -887,6 +888,18 @@ hipError_t y_forward_channels(pss_ctx* c) {
         ya.ncol[k] = c->n[0] / 2;
     }
     return pss::launch_ypass(pss::MODE_YFWD, c->n[1], ya, args(c));
+}
+
+// 3D mixed-radix lattices: y transforms (sign -1 forward, +1 inverse) of n
+// arrays in place
+hipError_t mr_ypass(pss_ctx* c, int sign, float2* const* arrs, int n) {
+    pss::YArgs ya{};
+    ya.n = n;
+    for (int i = 0; i < n; ++i) {
+        ya.src[i] = arrs[i];
+        ya.dst[i] = arrs[i];
+    }
+    return pss::launch_mr3_ypass(sign, ya, args(c));
 }
 
 bool has_frames(const pss_ctx* c) {
@@ -954,7 +967,7 @@ pss_status materialize(pss_ctx* c) {
         HIP_TRY(hipMemset(p, 0, bytes));
     }
     c->d_chan_x = c->d_chan;
-    if (c->ndim == 3) {
+    if (c->ndim == 3 && !c->mixed) {
         for (auto*& p : c->d_chan_x) {
             HIP_TRY(hipMalloc(&p, bytes));
             HIP_TRY(hipMemset(p, 0, bytes));
@@ -1007,7 +1020,11 @@ pss_status prologue(pss_ctx* c) {
     pss::LaunchArgs a = args(c);
     if (c->mixed) {
         HIP_TRY(pss::launch_mr2_col(pss::MODE_PROLOGUE, nf, a));
-        if (c->plan.nch > 0) HIP_TRY(pss::launch_mr2_row(pss::MODE_STEP, a));
+        if (c->plan.nch > 0) {
+            if (c->ndim == 3) HIP_TRY(mr_ypass(c, 1, c->d_v.data(), c->plan.ng));
+            HIP_TRY(pss::launch_mr2_row(pss::MODE_STEP, a));
+            if (c->ndim == 3) HIP_TRY(mr_ypass(c, -1, c->d_chan.data(), c->plan.nch));
+        }
         c->dirty = false;
         return PSS_OK;
     }
@@ -1103,8 +1120,10 @@ pss_status enqueue_steps(pss_ctx* c, int64_t k) {
         if (c->mixed) {
             HIP_TRY(pss::launch_mr2_col(pss::MODE_STEP, nf, a));
             if (c->plan.nch > 0) {
+                if (c->ndim == 3) HIP_TRY(mr_ypass(c, 1, c->d_v.data(), c->plan.ng));
                 a.advance = (x_advances && i == k - 1) ? k : 0;
                 HIP_TRY(pss::launch_mr2_row(pss::MODE_STEP, a));
+                if (c->ndim == 3) HIP_TRY(mr_ypass(c, -1, c->d_chan.data(), c->plan.nch));
             }
         } else {
             HIP_TRY(pss::launch_update(pss::MODE_STEP, c->lu, nf, a));
@@ -1146,6 +1165,7 @@ pss_status forward_to_state(pss_ctx* c, int field) {
         a.bufs.real_in = c->d_real;
         a.bufs.out = c->d_tmp;
         HIP_TRY(pss::launch_mr2_row(pss::MODE_R2C_IN, a));
+        if (c->ndim == 3) HIP_TRY(mr_ypass(c, -1, &c->d_tmp, 1));
         a.bufs.in = c->d_tmp;
         a.bufs.sel = field;
         HIP_TRY(pss::launch_mr2_col(pss::MODE_FWD_STORE, 1, a));
@@ -1183,6 +1203,7 @@ pss_status state_to_real(pss_ctx* c, int field) {
         a.bufs.sel = field;
         a.bufs.out = c->d_tmp;
         HIP_TRY(pss::launch_mr2_col(pss::MODE_INV_OUT, 1, a));
+        if (c->ndim == 3) HIP_TRY(mr_ypass(c, 1, &c->d_tmp, 1));
         a.bufs.in = c->d_tmp;
         a.bufs.real_out = c->d_real;
         HIP_TRY(pss::launch_mr2_row(pss::MODE_C2R_OUT, a));
@@ -1219,6 +1240,7 @@ pss_status interm_to_real(pss_ctx* c, int i) {
         a.bufs.sel = i;
         a.bufs.out = c->d_tmp;
         HIP_TRY(pss::launch_mr2_col(pss::MODE_INTERM_OUT, static_cast<int>(c->fields.size()), a));
+        if (c->ndim == 3) HIP_TRY(mr_ypass(c, 1, &c->d_tmp, 1));
         a.bufs.in = c->d_tmp;
         a.bufs.real_out = c->d_real;
         HIP_TRY(pss::launch_mr2_row(pss::MODE_C2R_OUT, a));
@@ -1646,14 +1668,12 @@ pss_status pss_lattice_create(pss_ctx** out, int32_t ndim, const int64_t n[3], c
     int64_t total = 1;
     for (int i = 0; i < ndim; ++i) {
         if (!(dx[i] > 0) || !std::isfinite(dx[i])) return fail(PSS_E_INVAL, "dx[%d] must be positive", i);
-        // 1D and 2D sizes may also be mixed-radix lengths 2^a 3^b 5^c (a >= 1)
+        // sizes are powers of two or mixed-radix lengths 2^a 3^b 5^c (a >= 1)
         pss::MrPlan mr{};
-        const bool mixed = ndim <= 2 && n[i] >= 8 && n[i] <= 4096 && pss::mr_plan(static_cast<int>(n[i]), &mr);
+        const bool mixed = n[i] >= 8 && n[i] <= 4096 && pss::mr_plan(static_cast<int>(n[i]), &mr);
         if ((!is_pow2(n[i]) && !mixed) || n[i] < 8 || n[i] > 4096)
-            return fail(PSS_E_UNSUPPORTED,
-                        ndim <= 2 ? "n[%d] = %lld is not an even 2^a 3^b 5^c in [8, 4096]"
-                                  : "n[%d] = %lld is not a power of two in [8, 4096]",
-                        i, static_cast<long long>(n[i]));
+            return fail(PSS_E_UNSUPPORTED, "n[%d] = %lld is not an even 2^a 3^b 5^c in [8, 4096]", i,
+                        static_cast<long long>(n[i]));
         total *= n[i];
     }
     if (total > (int64_t(1) << 31)) return fail(PSS_E_UNSUPPORTED, "more than 2^31 sites");
@@ -1663,7 +1683,7 @@ pss_status pss_lattice_create(pss_ctx** out, int32_t ndim, const int64_t n[3], c
         c->n[i] = static_cast<int>(n[i]);
         c->dx[i] = dx[i];
     }
-    c->mixed = ndim == 2 && (!is_pow2(n[0]) || !is_pow2(n[1]));
+    c->mixed = ndim >= 2 && (!is_pow2(n[0]) || !is_pow2(n[1]) || (ndim == 3 && !is_pow2(n[2])));
     c->dt = dt;
     *out = c;
     return PSS_OK;
@@ -2044,13 +2064,14 @@ pss_status pss_spectrum_download(pss_ctx* c, int32_t field, float* half, int32_t
             h[2 * k] = S[k].x;
             h[2 * k + 1] = S[k].y;
         }
-    } else if (c->mixed) {  // columns kx = 0 .. Nx/2 of the full 2D spectrum
+    } else if (c->mixed) {  // kx = 0 .. Nx/2 of the full spectrum, every (ky, kz)
         const int nx = c->n[0], nh = nx / 2 + 1;
-        for (int y = 0; y < c->n[1]; ++y)
+        const size_t rows = static_cast<size_t>(c->n[1]) * (c->ndim == 3 ? c->n[2] : 1);
+        for (size_t y = 0; y < rows; ++y)
             for (int k = 0; k < nh; ++k) {
-                const float2 v = S[static_cast<size_t>(y) * nx + k];
-                h[2 * (static_cast<size_t>(y) * nh + k)] = v.x;
-                h[2 * (static_cast<size_t>(y) * nh + k) + 1] = v.y;
+                const float2 v = S[y * nx + k];
+                h[2 * (y * nh + k)] = v.x;
+                h[2 * (y * nh + k) + 1] = v.y;
             }
     } else {
         unpack_half(c, S, h.data());

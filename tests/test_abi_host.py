@@ -311,12 +311,16 @@ def test_mixed_radix_lengths_on_host():
         with pytest.raises(PssError) as e:
             pss.Lattice((n,), dt=0.01)
         assert e.value.name == "PSS_E_UNSUPPORTED", n
-    # 2D: even 2^a 3^b 5^c sizes on either axis; 3D stays powers of two
+    # 2D and 3D: even 2^a 3^b 5^c sizes on any axis
     for n in ((96, 64), (64, 96), (120, 90), (1000, 12)):
         lat = pss.Lattice(n, dt=0.01)
         pss.model_b(lat)
         lat.validate()
-    for n in ((98, 64), (63, 64), (96, 64, 64)):
+    for n in ((24, 16, 10), (64, 64, 96)):
+        lat = pss.Lattice(n, dt=0.01)
+        pss.model_b(lat)
+        lat.validate()
+    for n in ((98, 64), (63, 64), (96, 64, 14)):
         with pytest.raises(PssError) as e:
             pss.Lattice(n, dt=0.01)
         assert e.value.name == "PSS_E_UNSUPPORTED", n
