@@ -12,7 +12,8 @@ training-system workloads measured against their plain forms:
   one batch, against the same lattices stepped one lattice per launch;
 * "adjoint": the gradient of a structure-factor loss through 2000 steps of
   256^2 Model B (checkpoints every 45), against the forward run alone;
-* "model_h": 2D Model H at 1024^2 (the paper's second benchmark model).
+* "model_h": 2D Model H at 1024^2 (the paper's second benchmark model);
+* "mixed_radix": 2D Model B at 960^2, a size that is not a power of two.
 
 Timing: the step graphs are built before any timed region (pss_step_prepare);
 the lattice runs on a torch stream, and HIP events recorded on that stream
@@ -437,6 +438,34 @@ def model_h(args, pss, torch, cpu_steps=0):
     }
 
 
+def mixed_radix(args, pss, torch):
+    """2D Model B at 960x960 (960 = 2^6 3 5: the generic mixed-radix path,
+    full spectra and one block per line) with the workload's coefficients;
+    HBM bytes per step from pss_kernel_bytes of its two launches."""
+    n = (960, 960)
+    stream = torch.cuda.Stream()
+    lat = pss.Lattice(n, dt=DT, seed=SEED)
+    lat.stream(stream.cuda_stream)
+    f, _ = pss.model_b(lat, a=A, b=B, k=K, D=D)
+    lat.init_uniform(f, -0.1, 0.1)
+    steps = min(args.steps, 200)
+    warm = min(args.warmup, 20)
+    lat.prepare(warm)
+    lat.prepare(steps)
+    lat.step(warm)
+    lat.sync()
+    times = timed_runs(torch, stream, lambda: lat.step(steps))
+    el = statistics.median(times)
+    sites = n[0] * n[1]
+    step_bytes = lat.kernel_bytes(0) + lat.kernel_bytes(1)
+    ms = 1e3 * el / steps
+    log(f"bench: mixed-radix 960^2 {1e3 * ms:.1f} us/step, {sites * steps / el:.4e} site-steps/s, "
+        f"{step_bytes / (ms * 1e-3) / 1e9:.0f} GB/s over the step")
+    return {"value": sites * steps / el, "unit": "site-steps/s", "steps": steps, "ms_per_step": ms,
+            "lattice": list(n), "step_bytes": step_bytes,
+            "step_GBs": round(step_bytes / (ms * 1e-3) / 1e9, 1)}
+
+
 def line(workload, value, steps, warmup, ms_per_step, extra):
     out = {"metric": "site-steps/s", "value": value, "unit": "site-steps/s", "n_gpus": 1,
            "steps": steps, "warmup": warmup, "ms_per_step": ms_per_step,
@@ -529,6 +558,8 @@ def main():
         log("bench: model h workload")
         h = model_h(args, pss, torch)
         extras["model_h"] = {k: h[k] for k in ("value", "unit", "steps", "ms_per_step", "roofline")}
+        log("bench: mixed-radix workload")
+        extras["mixed_radix"] = mixed_radix(args, pss, torch)
 
     if args.copy_mib > 0:
         nbytes = args.copy_mib << 20
