@@ -290,3 +290,38 @@ def test_member_stream_is_fixed_while_a_batch_holds_it():
     lats[0].step(2)
     lats[0].sync()
     assert lats[0].step_index == 5
+
+
+def test_batch_of_multi_field_models_is_bitwise_the_single_path():
+    # Model H members (three fields, general operators, shared channels) and
+    # a two-field member run in per-class launches: each member gets bit for
+    # bit what pss_step gives it alone
+    def mh(seed):
+        lat = pss.Lattice((64, 64), dt=0.01, seed=seed)
+        ids, _ = pss.model_h(lat, D=0.01)
+        lat.init_uniform(ids[0], -0.4, 0.4)
+        return lat, ids
+
+    def two(seed):
+        lat = pss.Lattice((128, 64), dt=0.01, seed=seed)
+        a = lat.field("a")
+        b = lat.field("b")
+        lat.term(a, [Mono(-0.5), Mono(-1.0, q2=1)], [(a, 1)], implicit=True)
+        lat.term(b, [Mono(-0.2, q2=1)], [(b, 1)], implicit=True)
+        lat.term(a, [Mono(-1.0)], [(a, 3)])
+        lat.term(b, [Mono(0.3)], [(a, 1), (b, 1)])
+        lat.noise(a, [Mono(0.004)])
+        for f in (a, b):
+            lat.init_uniform(f, -0.3, 0.3)
+        return lat, (a, b)
+
+    members = [mh(3), mh(5), two(7), mh(9)]
+    alone = [mh(3), mh(5), two(7), mh(9)]
+    batch = pss.Batch([m for m, _ in members])
+    batch.step(40)
+    batch.sync()
+    for (m, ids), (r, _) in zip(members, alone):
+        r.step(40)
+        for f in ids:
+            assert np.array_equal(m.spectrum(f), r.spectrum(f))
+    batch.close()
