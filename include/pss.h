@@ -255,7 +255,10 @@ pss_status pss_stream_set(pss_ctx *ctx, void *hip_stream);
  * Keys: "tc" (packed columns per tile; also the array layout), "to" (3D:
  * y lines per update block), "tz" (3D: z lines per y-pass block), "rb" (rows
  * per x-kernel block), "pu", "px", "py" (points per thread of the update,
- * x and y kernels: 4, 8 or 16).  value <= 0 restores the default.  Invalid
+ * x and y kernels: 4, 8 or 16).  On a lattice with a size that is not a
+ * power of two (2D, 3D) only "tc" (lines per column-kernel block) and "py"
+ * (3D: lines per y-pass block) apply, each a divisor of Nx up to 64 whose
+ * block fits the LDS.  value <= 0 restores the default.  Invalid
  * combinations are reported as PSS_E_UNSUPPORTED when the plan is built. */
 pss_status pss_tuning_set(pss_ctx *ctx, const char *key, int64_t value);
 

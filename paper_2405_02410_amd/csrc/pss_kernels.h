@@ -246,22 +246,29 @@ hipError_t line1d_mr_setup();
 
 // 2D and 3D lattices of mixed-radix sizes (even 2^a 3^b 5^c, not all powers
 // of two): full complex spectra, mode (kx, ky, kz) at (kz Ny + ky) Nx + kx.  Column launch
-// (one block per kx): MODE_STEP (channels N[ch] in (y, kx) form -> update ->
+// (geo.tc neighbouring lines per block): MODE_STEP (channels N[ch] in (y, kx) form -> update ->
 // factors V[g] in (y, kx) form), MODE_PROLOGUE (factors from the state),
 // MODE_FWD_STORE (in, (y, kx) -> state sel), MODE_INV_OUT (state sel -> out,
 // (y, kx)), MODE_INTERM_OUT (intermediate sel -> out).  Row launch (one block
 // per y): MODE_STEP (V -> products -> N; a.advance moves the counter on),
 // MODE_R2C_IN (real_in -> out), MODE_C2R_OUT (in -> real_out, normalised).
-inline size_t mr2_col_lds_bytes(int Ny, int NF) {
-    return sizeof(float2) * static_cast<size_t>(Ny) * (3 + 2 * static_cast<size_t>(NF));
+// column launch: the twiddles of a line, then two transform buffers, NF
+// states and NF contribution arrays of tc lines each; the y pass: the
+// twiddles and two buffers of tc lines
+inline size_t mr2_col_lds_bytes(int L, int NF, int tc) {
+    return sizeof(float2) * static_cast<size_t>(L) * (1 + static_cast<size_t>(tc) * (2 + 2 * static_cast<size_t>(NF)));
+}
+inline size_t mr3_ypass_lds_bytes(int Ny, int tc) {
+    return sizeof(float2) * static_cast<size_t>(Ny) * (1 + 2 * static_cast<size_t>(tc));
 }
 inline size_t mr2_row_lds_bytes(int Nx, int ng) {
     return sizeof(float2) * static_cast<size_t>(Nx) * 3 +
            sizeof(float) * static_cast<size_t>(Nx) * static_cast<size_t>(ng > 0 ? ng : 1);
 }
-// In 3D the column launch runs along z (one block per (kx, ky)), the row
-// launch covers Ny Nz rows, and launch_mr3_ypass transforms the arrays of ya
-// along y (sign -1 forward, +1 inverse), one block per (kx, z).
+// In 3D the column launch runs along z (geo.tc lines of neighbouring kx per
+// block), the row launch covers Ny Nz rows, and launch_mr3_ypass transforms
+// the arrays of ya along y (sign -1 forward, +1 inverse), geo.py lines of
+// neighbouring kx per block.
 hipError_t launch_mr2_col(int mode, int nf, const LaunchArgs& a);
 hipError_t launch_mr2_row(int mode, const LaunchArgs& a);
 hipError_t launch_mr3_ypass(int sign, const YArgs& ya, const LaunchArgs& a);

@@ -1666,30 +1666,57 @@ __device__ __forceinline__ float2 small_root(int r, int k) {
     }
 }
 
-// Transform of the N values in x (LDS) with sign -1 (forward) or +1 (inverse,
-// unnormalised); y is LDS scratch of N values.  Returns the buffer holding the
-// result.  Every thread of the block calls it; it ends with a barrier.
-__device__ float2* mr_transform(float2* x, float2* y, const float2* __restrict__ tw, const MrPlan& mr, int sign) {
+// One self-sorting pass of radix R over nl lines of N values (line l at
+// x + l N), sign sg = -1 (forward) or +1 (inverse): the radix-R transforms of
+// the current length n = m R, then the twiddles w_n^(j p).
+template <int R>
+__device__ __forceinline__ void mr_pass(const float2* __restrict__ x, float2* __restrict__ y,
+                                        const float2* __restrict__ tw, int N, int m, int s, int nl, float sg) {
+    const int per = m * s;
+    for (int idx = threadIdx.x; idx < nl * per; idx += blockDim.x) {
+        const int line = idx / per, rem = idx - line * per;
+        const int q = rem % s, p = rem / s;
+        const float2* xl = x + static_cast<size_t>(line) * N;
+        float2* yl = y + static_cast<size_t>(line) * N;
+        float2 a[R];
+#pragma unroll
+        for (int l = 0; l < R; ++l) a[l] = xl[q + s * (p + l * m)];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            float2 b = a[0];
+#pragma unroll
+            for (int l = 1; l < R; ++l) {
+                float2 w = small_root(R, (j * l) % R);
+                w.y *= sg;
+                b = cadd(b, cmul(a[l], w));
+            }
+            if (j > 0) {
+                float2 w = tw[(j * p * s) % N];  // exp(-2 pi i j p s / N) = w_n^(j p)
+                if (sg > 0.f) w.y = -w.y;
+                b = cmul(b, w);
+            }
+            yl[q + s * (R * p + j)] = b;
+        }
+    }
+}
+
+// Transform of nl lines of N values in x (LDS; line l at x + l N) with sign
+// -1 (forward) or +1 (inverse, unnormalised); y is LDS scratch of the same
+// size.  Returns the buffer holding the result.  Every thread of the block
+// calls it; it ends with a barrier.
+__device__ float2* mr_transform(float2* x, float2* y, const float2* __restrict__ tw, const MrPlan& mr, int sign,
+                                int nl = 1) {
     const int N = mr.n;
+    const float sg = static_cast<float>(sign);
     int n = N, s = 1;
     for (int st = 0; st < mr.nst; ++st) {
         const int r = mr.radix[st];
         const int m = n / r;
-        for (int idx = threadIdx.x; idx < m * s; idx += blockDim.x) {
-            const int q = idx % s, p = idx / s;
-            float2 a[5];
-            for (int l = 0; l < r; ++l) a[l] = x[q + s * (p + l * m)];
-            for (int j = 0; j < r; ++j) {
-                float2 b = make_float2(0.f, 0.f);
-                for (int l = 0; l < r; ++l) {
-                    float2 w = small_root(r, (j * l) % r);
-                    w.y *= static_cast<float>(sign);
-                    b = cadd(b, cmul(a[l], w));
-                }
-                float2 w = tw[(j * p * s) % N];  // exp(-2 pi i j p s / N) = w_n^(j p)
-                if (sign > 0) w.y = -w.y;
-                y[q + s * (r * p + j)] = cmul(b, w);
-            }
+        switch (r) {
+            case 4: mr_pass<4>(x, y, tw, N, m, s, nl, sg); break;
+            case 2: mr_pass<2>(x, y, tw, N, m, s, nl, sg); break;
+            case 3: mr_pass<3>(x, y, tw, N, m, s, nl, sg); break;
+            default: mr_pass<5>(x, y, tw, N, m, s, nl, sg); break;
         }
         __syncthreads();
         float2* t = x;
@@ -1931,128 +1958,148 @@ hipError_t line1d_mr_setup() {
 template <int NF, bool GEN, int MODE>
 __global__ void __launch_bounds__(256)
     mr2_col_kernel(const DevPlan* __restrict__ plan, Bufs bufs, const uint64_t* __restrict__ step_ctr,
-                   uint32_t* __restrict__ flag, int step_off, const float2* __restrict__ tw_g, MrPlan my) {
+                   uint32_t* __restrict__ flag, int step_off, const float2* __restrict__ tw_g, MrPlan my, int tc) {
     extern __shared__ float2 smem[];
     const DevPlan& p = *plan;
-    // the line runs along the last axis: y in 2D (block = kx), z in 3D
-    // (block = (kx, ky)); "ky" below is the index along the line
-    const int Nx = p.n[0], Ny = my.n, N1 = p.n[1];
+    // tc neighbouring lines along the last axis: y in 2D (block = kx0 ..
+    // kx0 + tc - 1), z in 3D (the same kx range at one ky); "ky" below is the
+    // index along a line.  LDS holds line c of an array at c L.
+    const int Nx = p.n[0], L = my.n, N1 = p.n[1];
     const bool d3 = p.n[2] > 1;
-    const int kx = d3 ? static_cast<int>(blockIdx.x % Nx) : static_cast<int>(blockIdx.x);
-    const int ko = d3 ? static_cast<int>(blockIdx.x / Nx) : 0;  // ky of a 3D line
-    const int kxs = kx < (Nx >> 1) ? kx : kx - Nx;
+    const int nxb = Nx / tc;
+    const int kx0 = static_cast<int>(blockIdx.x % nxb) * tc;
+    const int ko = d3 ? static_cast<int>(blockIdx.x / nxb) : 0;  // ky of 3D lines
     const int kos = ko < (N1 >> 1) ? ko : ko - N1;
-    const size_t base = d3 ? static_cast<size_t>(ko) * Nx + kx : static_cast<size_t>(kx);
+    const size_t base = d3 ? static_cast<size_t>(ko) * Nx + kx0 : static_cast<size_t>(kx0);
     const size_t su = d3 ? static_cast<size_t>(Nx) * N1 : static_cast<size_t>(Nx);
     const int t = threadIdx.x, T = blockDim.x;
+    const int n = tc * L;  // elements of one array in LDS
     float2* const tw = smem;
-    float2* const A = smem + Ny;
-    float2* const B = smem + 2 * Ny;
-    float2* const S = smem + 3 * Ny;  // [NF][line]
-    float2* const acc = S + NF * Ny;  // [NF][line]
-    for (int i = t; i < Ny; i += T) tw[i] = tw_g[i];
-    auto at = [&](int ky) { return base + static_cast<size_t>(ky) * su; };
-    auto ws = [&](int ky) { return ky < (Ny >> 1) ? ky : ky - Ny; };
-    auto kq = [&](int ky) { return d3 ? mode_q(p, kxs, kos, ws(ky)) : mode_q(p, kxs, ws(ky), 0); };
+    float2* const A = smem + L;
+    float2* const B = A + n;
+    float2* const S = B + n;          // [NF][tc][L]
+    float2* const acc = S + NF * n;   // [NF][tc][L]
+    for (int i = t; i < L; i += T) tw[i] = tw_g[i];
+    // global element of line c at position w; loads and stores run with the
+    // line index fastest, so a wave touches neighbouring kx
+    auto at = [&](int c, int w) { return base + c + static_cast<size_t>(w) * su; };
+    auto gin = [&](const float2* __restrict__ src, float2* dst) {
+        for (int i = t; i < n; i += T) {
+            const int c = i % tc, w = i / tc;
+            dst[c * L + w] = gload(src + at(c, w));
+        }
+    };
+    auto gout = [&](const float2* src, float2* __restrict__ dst) {
+        for (int i = t; i < n; i += T) {
+            const int c = i % tc, w = i / tc;
+            gstore(dst + at(c, w), src[c * L + w]);
+        }
+    };
+    auto ws = [&](int w) { return w < (L >> 1) ? w : w - L; };
+    auto kxs = [&](int c) { const int kx = kx0 + c; return kx < (Nx >> 1) ? kx : kx - Nx; };
+    auto kq = [&](int c, int w) { return d3 ? mode_q(p, kxs(c), kos, ws(w)) : mode_q(p, kxs(c), ws(w), 0); };
 
     if constexpr (MODE == MODE_FWD_STORE) {
-        for (int ky = t; ky < Ny; ky += T) A[ky] = gload(bufs.in + at(ky));
+        gin(bufs.in, A);
         __syncthreads();
-        const float2* r = mr_transform(A, B, tw, my, -1);
-        for (int ky = t; ky < Ny; ky += T) gstore(bufs.S[bufs.sel] + at(ky), r[ky]);
+        const float2* r = mr_transform(A, B, tw, my, -1, tc);
+        gout(r, bufs.S[bufs.sel]);
         return;
     }
     if constexpr (MODE == MODE_INV_OUT) {
-        for (int ky = t; ky < Ny; ky += T) A[ky] = gload(bufs.S[bufs.sel] + at(ky));
+        gin(bufs.S[bufs.sel], A);
         __syncthreads();
-        const float2* r = mr_transform(A, B, tw, my, 1);
-        for (int y = t; y < Ny; y += T) gstore(bufs.out + at(y), r[y]);
+        const float2* r = mr_transform(A, B, tw, my, 1, tc);
+        gout(r, bufs.out);
         return;
     }
 
     const int nf = p.nf;
-    for (int f = 0; f < nf; ++f)
-        for (int ky = t; ky < Ny; ky += T) S[f * Ny + ky] = gload(bufs.S[f] + at(ky));
+    for (int f = 0; f < nf; ++f) gin(bufs.S[f], S + f * n);
     __syncthreads();
-    auto source = [&](int src, int ky, const ModeQ& q) -> float2 {
+    // Fourier value of source src at LDS element i (line i / L, position i % L)
+    auto source = [&](int src, int i, const ModeQ& q) -> float2 {
         if constexpr (GEN) {
             if (src >= PSS_MAXF) {
                 const DevInterm& I = p.interm[src - PSS_MAXF];
                 float2 v = make_float2(0.f, 0.f);
-                for (int j = 0; j < I.nsrc; ++j) v = cadd(v, cmul(eval_op<true>(I.op[j], q), S[I.src[j] * Ny + ky]));
+                for (int j = 0; j < I.nsrc; ++j) v = cadd(v, cmul(eval_op<true>(I.op[j], q), S[I.src[j] * n + i]));
                 return cmul(v, cinv_implicit(1.f, eval_op<true>(I.den, q)));
             }
         }
-        return S[src * Ny + ky];
+        return S[src * n + i];
     };
 
     if constexpr (MODE == MODE_INTERM_OUT) {
-        for (int ky = t; ky < Ny; ky += T) A[ky] = source(PSS_MAXF + bufs.sel, ky, kq(ky));
+        for (int i = t; i < n; i += T) A[i] = source(PSS_MAXF + bufs.sel, i, kq(i / L, i % L));
         __syncthreads();
-        const float2* r = mr_transform(A, B, tw, my, 1);
-        for (int y = t; y < Ny; y += T) gstore(bufs.out + at(y), r[y]);
+        const float2* r = mr_transform(A, B, tw, my, 1, tc);
+        gout(r, bufs.out);
         return;
     }
 
     if constexpr (MODE == MODE_STEP) {
         const uint32_t step = static_cast<uint32_t>(gload_u64(step_ctr)) + static_cast<uint32_t>(step_off);
-        for (int i = t; i < nf * Ny; i += T) acc[i] = make_float2(0.f, 0.f);
-        // channels: forward y transform of the x-transformed products, M(q) per mode
+        for (int i = t; i < nf * n; i += T) acc[i] = make_float2(0.f, 0.f);
+        // channels: forward transforms of the products, M(q) per mode
         for (int ch = 0; ch < p.nch; ++ch) {
             const DevChannel& C = p.ch[ch];
-            for (int y = t; y < Ny; y += T) A[y] = gload(bufs.N[ch] + at(y));
+            gin(bufs.N[ch], A);
             __syncthreads();
-            const float2* r = mr_transform(A, B, tw, my, -1);
-            for (int ky = t; ky < Ny; ky += T) {
-                const ModeQ q = kq(ky);
+            const float2* r = mr_transform(A, B, tw, my, -1, tc);
+            for (int i = t; i < n; i += T) {
+                const ModeQ q = kq(i / L, i % L);
                 for (int o = 0; o < C.nout; ++o) {
-                    float2& d = acc[C.target[o] * Ny + ky];
-                    d = cadd(d, cmul(eval_op<GEN>(C.op[o], q), r[ky]));
+                    float2& d = acc[C.target[o] * n + i];
+                    d = cadd(d, cmul(eval_op<GEN>(C.op[o], q), r[i]));
                 }
             }
             __syncthreads();
         }
         // linear explicit terms, then the semi-implicit update with the noise
-        for (int ky = t; ky < Ny; ky += T) {
-            const ModeQ q = kq(ky);
+        for (int i = t; i < n; i += T) {
+            const ModeQ q = kq(i / L, i % L);
             for (int d = 0; d < p.nd; ++d) {
                 const DevDirect& Dd = p.direct[d];
-                float2& a = acc[Dd.target * Ny + ky];
-                a = cadd(a, cmul(eval_op<GEN>(Dd.op, q), source(Dd.src, ky, q)));
+                float2& a = acc[Dd.target * n + i];
+                a = cadd(a, cmul(eval_op<GEN>(Dd.op, q), source(Dd.src, i, q)));
             }
         }
         __syncthreads();
         uint32_t bad = 0;
-        for (int ky = t; ky < Ny; ky += T) {
-            const ModeQ q = kq(ky);
-            const uint32_t lin = static_cast<uint32_t>(at(ky));
-            const size_t neg_line = d3 ? static_cast<size_t>((Ny - ky) % Ny) * N1 + static_cast<size_t>((N1 - ko) % N1)
-                                       : static_cast<size_t>((Ny - ky) % Ny);
+        for (int i = t; i < n; i += T) {
+            const int c = i / L, w = i % L, kx = kx0 + c;
+            const ModeQ q = kq(c, w);
+            const uint32_t lin = static_cast<uint32_t>(at(c, w));
+            const size_t neg_line = d3 ? static_cast<size_t>((L - w) % L) * N1 + static_cast<size_t>((N1 - ko) % N1)
+                                       : static_cast<size_t>((L - w) % L);
             const uint32_t lneg = static_cast<uint32_t>(neg_line * Nx + static_cast<size_t>((Nx - kx) % Nx));
             for (int f = 0; f < nf; ++f) {
-                float2 r = cadd(S[f * Ny + ky], cscale(acc[f * Ny + ky], p.dt));
+                float2 r = cadd(S[f * n + i], cscale(acc[f * n + i], p.dt));
                 if (p.noisy[f] != 0) r = cadd(r, noise_mode<GEN>(p, f, step, lin, lneg, q));
                 r = cmul(r, cinv_implicit(p.dt, eval_op<GEN>(p.implicit_op[f], q)));
-                S[f * Ny + ky] = r;
-                gstore(bufs.S[f] + at(ky), r);
+                S[f * n + i] = r;
                 if (!(__builtin_isfinite(r.x) && __builtin_isfinite(r.y))) bad |= 1u << f;
             }
         }
         if (bad) atomicOr(flag, bad);
         __syncthreads();
+        for (int f = 0; f < nf; ++f) gout(S + f * n, bufs.S[f]);
     }
 
-    // MODE_STEP and MODE_PROLOGUE: inverse y transforms of the de-aliased
+    // MODE_STEP and MODE_PROLOGUE: inverse transforms of the de-aliased
     // factors from the (new) state
     for (int g = 0; g < p.ng; ++g) {
         const DevMask& mk = p.mask[g];
-        for (int ky = t; ky < Ny; ky += T)
-            A[ky] = (d3 ? mask_keep(mk, kxs, kos, ws(ky)) : mask_keep(mk, kxs, ws(ky), 0))
-                        ? source(p.gfield[g], ky, kq(ky))
-                        : make_float2(0.f, 0.f);
+        for (int i = t; i < n; i += T) {
+            const int c = i / L, w = i % L;
+            A[i] = (d3 ? mask_keep(mk, kxs(c), kos, ws(w)) : mask_keep(mk, kxs(c), ws(w), 0))
+                       ? source(p.gfield[g], i, kq(c, w))
+                       : make_float2(0.f, 0.f);
+        }
         __syncthreads();
-        const float2* r = mr_transform(A, B, tw, my, 1);
-        for (int y = t; y < Ny; y += T) gstore(bufs.V[g] + at(y), r[y]);
+        const float2* r = mr_transform(A, B, tw, my, 1, tc);
+        gout(r, bufs.V[g]);
         __syncthreads();
     }
 }
@@ -2118,22 +2165,31 @@ __global__ void __launch_bounds__(256)
 // 3D: transforms along y of the arrays of ya (in place allowed: a line is
 // read whole before it is written), one block per (kx, z) line
 __global__ void __launch_bounds__(256)
-    mr3_ypass_kernel(const DevPlan* __restrict__ plan, YArgs ya, const float2* __restrict__ tw_g, MrPlan my, int sign) {
+    mr3_ypass_kernel(const DevPlan* __restrict__ plan, YArgs ya, const float2* __restrict__ tw_g, MrPlan my, int sign,
+                     int tc) {
     extern __shared__ float2 smem[];
     const DevPlan& p = *plan;
     const int Nx = p.n[0], Ny = my.n;
-    const int kx = static_cast<int>(blockIdx.x % Nx), z = static_cast<int>(blockIdx.x / Nx);
-    const size_t base = static_cast<size_t>(z) * Nx * Ny + kx;
+    const int nxb = Nx / tc;
+    const int kx0 = static_cast<int>(blockIdx.x % nxb) * tc, z = static_cast<int>(blockIdx.x / nxb);
+    const size_t base = static_cast<size_t>(z) * Nx * Ny + kx0;
     const int t = threadIdx.x, T = blockDim.x;
+    const int n = tc * Ny;
     float2* const tw = smem;
     float2* const A = smem + Ny;
-    float2* const B = smem + 2 * Ny;
+    float2* const B = A + n;
     for (int i = t; i < Ny; i += T) tw[i] = tw_g[i];
-    for (int i = 0; i < ya.n; ++i) {
-        for (int y = t; y < Ny; y += T) A[y] = gload(ya.src[i] + base + static_cast<size_t>(y) * Nx);
+    for (int a = 0; a < ya.n; ++a) {
+        for (int i = t; i < n; i += T) {
+            const int c = i % tc, y = i / tc;
+            A[c * Ny + y] = gload(ya.src[a] + base + c + static_cast<size_t>(y) * Nx);
+        }
         __syncthreads();
-        const float2* r = mr_transform(A, B, tw, my, sign);
-        for (int y = t; y < Ny; y += T) gstore(ya.dst[i] + base + static_cast<size_t>(y) * Nx, r[y]);
+        const float2* r = mr_transform(A, B, tw, my, sign, tc);
+        for (int i = t; i < n; i += T) {
+            const int c = i % tc, y = i / tc;
+            gstore(ya.dst[a] + base + c + static_cast<size_t>(y) * Nx, r[c * Ny + y]);
+        }
         __syncthreads();
     }
 }
@@ -2142,8 +2198,12 @@ hipError_t launch_mr3_ypass(int sign, const YArgs& ya, const LaunchArgs& a) {
     MrPlan my{};
     if (!mr_plan(a.ny, &my) || a.dim != 3) return hipErrorInvalidValue;
     if (ya.n <= 0) return hipSuccess;
-    const size_t lds = sizeof(float2) * 3 * static_cast<size_t>(my.n);
-    hipLaunchKernelGGL(mr3_ypass_kernel, dim3(a.nx * a.nz), dim3(256), lds, a.stream, a.plan, ya, a.tw_y, my, sign);
+    const int tc = a.geo.py;  // neighbouring y lines per block
+    if (tc < 1 || a.nx % tc != 0) return hipErrorInvalidValue;
+    const size_t lds = mr3_ypass_lds_bytes(my.n, tc);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(mr3_ypass_kernel, dim3((a.nx / tc) * a.nz), dim3(256), lds, a.stream, a.plan, ya, a.tw_y, my,
+                       sign, tc);
     return hipGetLastError();
 }
 
@@ -2151,13 +2211,15 @@ hipError_t launch_mr2_col(int mode, int nf, const LaunchArgs& a) {
     MrPlan my{};
     if (!mr_plan(a.dim == 3 ? a.nz : a.ny, &my)) return hipErrorInvalidValue;
     const int NF = nf <= 1 ? 1 : (nf == 2 ? 2 : 4);
-    const size_t lds = mr2_col_lds_bytes(my.n, NF);
+    const int tc = a.geo.tc;  // neighbouring lines per block
+    if (tc < 1 || a.nx % tc != 0) return hipErrorInvalidValue;
+    const size_t lds = mr2_col_lds_bytes(my.n, NF, tc);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    const dim3 grid(a.dim == 3 ? a.nx * a.ny : a.nx), block(256);
+    const dim3 grid((a.nx / tc) * (a.dim == 3 ? a.ny : 1)), block(256);
     const bool gen = a.general || mode == MODE_INTERM_OUT;
 #define PSS_C2(NFV, G, M)                                                                                    \
     hipLaunchKernelGGL((mr2_col_kernel<NFV, G, M>), grid, block, lds, a.stream, a.plan, a.bufs, a.step_ctr,  \
-                       a.flag, a.step_off, a.tw_u, my)
+                       a.flag, a.step_off, a.tw_u, my, tc)
 #define PSS_C2F(M)                       \
     do {                                 \
         if (NF == 1) {                   \

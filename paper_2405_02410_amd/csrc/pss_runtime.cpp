@@ -667,7 +667,8 @@ int pick_pow2(int want, int lo, int hi) {
 
 // Launch geometry.  Defaults come from the sizes; pss_tuning_set can force any
 // of tc, to, tz, rb (powers of two) and pu, px, py (points per thread: 4, 8 or
-// 16) before the plan is built.
+// 16) before the plan is built; on mixed-radix lattices tc and py are lines
+// per column / y-pass block.
 pss_status choose_geometry(pss_ctx* c) {
     const int nf = static_cast<int>(c->fields.size());
     const int ng = std::max(1, c->plan.ng);
@@ -702,19 +703,41 @@ pss_status choose_geometry(pss_ctx* c) {
         return PSS_OK;
     }
     if (c->mixed) {
-        // one block per line on every pass, spectra in LDS (no tunable geometry)
+        // spectra in LDS, one block per x row; the column launch (and the 3D
+        // y pass) takes tc lines of neighbouring kx per block, so that its
+        // strided global accesses read and write tc neighbouring elements
+        // together: the largest of 8, 4, 2, 1 that divides Nx and fits
         c->lu = c->ndim == 3 ? nz : ny;
-        g.tc = 1;
+        const int NF = nf <= 1 ? 1 : (nf == 2 ? 2 : 4);
+        auto pick_tc = [&](auto bytes) {
+            for (int tc : {8, 4, 2, 1})
+                if (nx % tc == 0 && bytes(tc) <= 160 * 1024) return tc;
+            return 0;
+        };
+        g.tc = pick_tc([&](int tc) { return pss::mr2_col_lds_bytes(c->lu, NF, tc); });
+        g.py = c->ndim == 3 ? pick_tc([&](int tc) { return pss::mr3_ypass_lds_bytes(ny, tc); }) : 1;
+        // pss_tuning_set may force either (a divisor of Nx that fits)
+        auto forced = [&](const char* key, int& v, auto bytes) {
+            auto it = c->tune.find(key);
+            if (it == c->tune.end()) return true;
+            const int64_t w = it->second;
+            if (w < 1 || w > 64 || nx % w != 0 || bytes(static_cast<int>(w)) > 160 * 1024) return false;
+            v = static_cast<int>(w);
+            return true;
+        };
+        if (!forced("tc", g.tc, [&](int tc) { return pss::mr2_col_lds_bytes(c->lu, NF, tc); }) ||
+            (c->ndim == 3 && !forced("py", g.py, [&](int tc) { return pss::mr3_ypass_lds_bytes(ny, tc); })))
+            return fail(PSS_E_UNSUPPORTED, "forced tc / py must divide Nx and fit the LDS");
         g.to = 1;
         g.pu = g.px = 4;
         g.ntile = ncols;
-        g.nublk = c->ndim == 3 ? nx * ny : nx;
+        g.nublk = (nx / std::max(g.tc, 1)) * (c->ndim == 3 ? ny : 1);
         g.nrowblk = ny * nz;
         g.rb = 2;
-        const int NF = nf <= 1 ? 1 : (nf == 2 ? 2 : 4);
-        const size_t lc = pss::mr2_col_lds_bytes(c->lu, NF), lr = pss::mr2_row_lds_bytes(nx, c->plan.ng);
-        if (lc > 160 * 1024 || lr > 160 * 1024)
-            return fail(PSS_E_UNSUPPORTED, "lattice needs more LDS than a workgroup has (%zu, %zu bytes)", lc, lr);
+        const size_t lr = pss::mr2_row_lds_bytes(nx, c->plan.ng);
+        if (g.tc == 0 || g.py == 0 || lr > 160 * 1024)
+            return fail(PSS_E_UNSUPPORTED, "lattice needs more LDS than a workgroup has (%zu, %zu bytes)",
+                        pss::mr2_col_lds_bytes(c->lu, NF, 1), lr);
         return PSS_OK;
     }
     auto tuned = [&](const char* key, int def) {
