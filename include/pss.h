@@ -300,7 +300,15 @@ pss_status pss_spectrum_download(pss_ctx *ctx, int32_t field, float *half_spectr
 
 /* Advance nsteps time steps (eq:timeupdate).  nsteps = 0 is a no-op.
  * Asynchronous on the context stream; replays captured HIP graphs of the
- * step sequence. */
+ * step sequence.
+ * Debug mode: a lattice created while the environment variable
+ * PSS_DEBUG_SYNC is set (and not "0") enqueues the same kernels one step at
+ * a time without graphs, synchronises the stream after every kernel, and
+ * returns PSS_E_HIP or PSS_E_NONFINITE from pss_step itself, naming the
+ * kernel and the step; its workspaces start filled with NaN so that a read
+ * before a write would reach the state.  Results are bitwise those of the
+ * graph path.  After such an error the state is undefined and the step
+ * index counts the completed steps.  Batches and tapes are not affected. */
 pss_status pss_step(pss_ctx *ctx, int64_t nsteps);
 
 /* Build the plan (if needed) and capture and instantiate the HIP graphs that
@@ -407,7 +415,12 @@ pss_status pss_time_kernel(pss_ctx *ctx, int32_t which, int32_t reps, double *ms
  * copy of the model with `reps` back-to-back launches per kernel (HIP
  * events), and keep the fastest as if set by pss_tuning_set.  Keys the
  * caller already set are kept.  The choice is cached for the process per
- * lattice shape, term structure and forced keys.  *us_per_step (may be NULL)
+ * device, lattice shape, term structure and forced keys.  If the environment
+ * variable PSS_TUNE_CACHE names a file, a choice missing from the process
+ * cache is looked up there first, and a new one is appended to it as the
+ * text line "<key> <us per step> <k>=<v> ..." (the last line of a key wins;
+ * lines that do not parse are skipped; PSS_E_INVAL if the file cannot be
+ * written, with the choice still applied).  *us_per_step (may be NULL)
  * receives the summed kernel time of one step at the choice.  Tiling keys
  * leave results bitwise unchanged; points per thread change the FFT radix
  * and so the FP32 rounding.  PSS_E_STATE after the plan is built. */

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cctype>
 #include <cmath>
 #include <complex>
 #include <cstdarg>
@@ -195,6 +196,10 @@ struct pss_ctx {
     std::map<int64_t, hipGraphExec_t> graphs;
     std::map<std::string, int64_t> tune;  // launch-geometry overrides
     int64_t steps_taken = 0;
+    // PSS_DEBUG_SYNC set (and not "0") when the lattice was created: steps run
+    // eagerly instead of as graphs, the stream is synchronised and checked
+    // after every kernel, and the workspaces start filled with NaN
+    bool debug_sync = false;
 
     int64_t sites() const { return static_cast<int64_t>(n[0]) * n[1] * n[2]; }
     // complex elements per spectral array: the packed half spectrum in 2D and
@@ -847,6 +852,22 @@ void free_device(pss_ctx* c) {
 
 uint32_t* flag_of(pss_ctx* c) { return c->d_step ? reinterpret_cast<uint32_t*>(c->d_step + 1) : nullptr; }
 
+// Debug mode only: wait for the kernel just enqueued and report, by kernel
+// and step, a launch or execution error or the first non-finite state value.
+pss_status debug_check(pss_ctx* c, const char* kernel, int64_t step) {
+    if (!c->debug_sync) return PSS_OK;
+    const hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess)
+        return fail(PSS_E_HIP, "%s (step %lld): %s", kernel, static_cast<long long>(step), hipGetErrorString(e));
+    uint32_t f = 0;
+    HIP_TRY(hipMemcpy(&f, flag_of(c), sizeof(f), hipMemcpyDeviceToHost));
+    if (!f) return PSS_OK;
+    const uint32_t zero = 0;
+    HIP_TRY(hipMemcpy(flag_of(c), &zero, sizeof(zero), hipMemcpyHostToDevice));
+    return fail(PSS_E_NONFINITE, "a non-finite value appeared in the state (field mask 0x%x) in %s of step %lld", f,
+                kernel, static_cast<long long>(step));
+}
+
 pss::LaunchArgs args(pss_ctx* c, int step_off = 0) {
     pss::LaunchArgs a{};
     a.stream = c->stream;
@@ -985,24 +1006,32 @@ pss_status materialize(pss_ctx* c) {
         }
         HIP_TRY(hipMemset(p, 0, bytes));
     }
+    // workspaces: zeros, or all-ones bytes (a NaN in every float) in debug
+    // mode, so that a read before the first write reaches the state as NaN
+    const int fill = c->debug_sync ? 0xFF : 0;
     for (auto*& p : c->d_chan) {
         HIP_TRY(hipMalloc(&p, bytes));
-        HIP_TRY(hipMemset(p, 0, bytes));
+        HIP_TRY(hipMemset(p, fill, bytes));
     }
     c->d_chan_x = c->d_chan;
     if (c->ndim == 3 && !c->mixed) {
         for (auto*& p : c->d_chan_x) {
             HIP_TRY(hipMalloc(&p, bytes));
-            HIP_TRY(hipMemset(p, 0, bytes));
+            HIP_TRY(hipMemset(p, fill, bytes));
         }
     }
     for (auto*& p : c->d_v) {
         HIP_TRY(hipMalloc(&p, bytes));
-        HIP_TRY(hipMemset(p, 0, bytes));
+        HIP_TRY(hipMemset(p, fill, bytes));
     }
     HIP_TRY(hipMalloc(&c->d_tmp, bytes));
     HIP_TRY(hipMalloc(&c->d_tmp2, bytes));
     HIP_TRY(hipMalloc(&c->d_real, sizeof(float) * static_cast<size_t>(c->sites())));
+    if (c->debug_sync) {
+        HIP_TRY(hipMemset(c->d_tmp, fill, bytes));
+        HIP_TRY(hipMemset(c->d_tmp2, fill, bytes));
+        HIP_TRY(hipMemset(c->d_real, fill, sizeof(float) * static_cast<size_t>(c->sites())));
+    }
     HIP_TRY(hipMalloc(&c->d_plan, sizeof(pss::DevPlan)));
     // the step counter and, in the next word, the non-finite flag
     HIP_TRY(hipMalloc(&c->d_step, 2 * sizeof(uint64_t)));
@@ -1134,30 +1163,38 @@ pss_status enqueue_steps(pss_ctx* c, int64_t k) {
         a.nsteps = static_cast<int>(k);
         a.advance = 1;
         HIP_TRY(pss::launch_line1d(pss::MODE_STEP, c->n[0], nf, a));
-        return PSS_OK;
+        return debug_check(c, "line1d_kernel", c->steps_taken);
     }
     // in 2D the last x kernel of the sequence moves the step counter on
     const bool x_advances = c->ndim == 2 && c->plan.nch > 0;
     for (int64_t i = 0; i < k; ++i) {
         pss::LaunchArgs a = args(c, static_cast<int>(i));
+        const int64_t at = c->steps_taken + i;
+#define PSS_CHECKED(launch, name)                                 \
+    do {                                                          \
+        HIP_TRY(launch);                                          \
+        if (pss_status s_ = debug_check(c, name, at)) return s_;  \
+    } while (0)
         if (c->mixed) {
-            HIP_TRY(pss::launch_mr2_col(pss::MODE_STEP, nf, a));
+            PSS_CHECKED(pss::launch_mr2_col(pss::MODE_STEP, nf, a), "mr2_col_kernel");
             if (c->plan.nch > 0) {
-                if (c->ndim == 3) HIP_TRY(mr_ypass(c, 1, c->d_v.data(), c->plan.ng));
+                if (c->ndim == 3) PSS_CHECKED(mr_ypass(c, 1, c->d_v.data(), c->plan.ng), "mr3_ypass_kernel(inverse)");
                 a.advance = (x_advances && i == k - 1) ? k : 0;
-                HIP_TRY(pss::launch_mr2_row(pss::MODE_STEP, a));
-                if (c->ndim == 3) HIP_TRY(mr_ypass(c, -1, c->d_chan.data(), c->plan.nch));
+                PSS_CHECKED(pss::launch_mr2_row(pss::MODE_STEP, a), "mr2_row_kernel");
+                if (c->ndim == 3)
+                    PSS_CHECKED(mr_ypass(c, -1, c->d_chan.data(), c->plan.nch), "mr3_ypass_kernel(forward)");
             }
         } else {
-            HIP_TRY(pss::launch_update(pss::MODE_STEP, c->lu, nf, a));
+            PSS_CHECKED(pss::launch_update(pss::MODE_STEP, c->lu, nf, a), "update_kernel");
             if (c->plan.nch > 0) {
-                if (c->ndim == 3) HIP_TRY(y_inverse_factors(c));
+                if (c->ndim == 3) PSS_CHECKED(y_inverse_factors(c), "ypass_kernel(inverse)");
                 pss::LaunchArgs ax = xargs(c);
                 ax.advance = (x_advances && i == k - 1) ? k : 0;
-                HIP_TRY(pss::launch_xrow(pss::MODE_STEP, c->n[0], c->plan.ng, ax));
-                if (c->ndim == 3) HIP_TRY(y_forward_channels(c));
+                PSS_CHECKED(pss::launch_xrow(pss::MODE_STEP, c->n[0], c->plan.ng, ax), "xrow_kernel");
+                if (c->ndim == 3) PSS_CHECKED(y_forward_channels(c), "ypass_kernel(forward)");
             }
         }
+#undef PSS_CHECKED
         if (has_frames(c)) {
             // boundary frames: each framed field through real space, then the
             // factors and channels of the next step from the framed state
@@ -1169,6 +1206,7 @@ pss_status enqueue_steps(pss_ctx* c, int64_t k) {
                 if (pss_status s = forward_to_state(c, f)) return s;
             }
             if (pss_status s = prologue(c)) return s;
+            if (pss_status s = debug_check(c, "frames and products", at)) return s;
         }
     }
     if (!x_advances) HIP_TRY(pss::launch_advance(c->stream, c->d_step, k));
@@ -1708,6 +1746,8 @@ pss_status pss_lattice_create(pss_ctx** out, int32_t ndim, const int64_t n[3], c
     }
     c->mixed = ndim >= 2 && (!is_pow2(n[0]) || !is_pow2(n[1]) || (ndim == 3 && !is_pow2(n[2])));
     c->dt = dt;
+    const char* dbg = std::getenv("PSS_DEBUG_SYNC");
+    c->debug_sync = dbg && *dbg && std::strcmp(dbg, "0") != 0;
     *out = c;
     return PSS_OK;
 }
@@ -2113,8 +2153,22 @@ pss_status pss_step(pss_ctx* c, int64_t nsteps) {
     if (nsteps == 0) return PSS_OK;
     if (pss_status s = materialize(c)) return s;
     if (pss_status s_bw = begin_work(c)) return s_bw;
-    if (c->dirty)
+    if (c->dirty) {
         if (pss_status s = prologue(c)) return s;
+        if (pss_status s = debug_check(c, "products of the state", c->steps_taken)) return s;
+    }
+    if (c->debug_sync) {
+        // the same kernels, enqueued one by one and checked after each
+        for (int64_t i = 0; i < nsteps; ++i) {
+            if (pss_status s = enqueue_steps(c, 1)) {
+                ++c->state_gen;
+                return s;
+            }
+            ++c->steps_taken;
+        }
+        ++c->state_gen;
+        return PSS_OK;
+    }
     int64_t left = nsteps;
     while (left > 0) {
         const int64_t k = std::min(left, kGraphSteps);
@@ -2422,11 +2476,15 @@ pss_status pss_autotune(pss_ctx* c, int32_t reps, double* us_per_step) {
         return PSS_OK;
     }
     using Tune = std::map<std::string, int64_t>;
-    // one process-wide cache entry per lattice shape and term structure
+    // one process-wide cache entry per device, lattice shape and term structure
     static std::map<std::string, std::pair<Tune, double>> cache;
     static std::mutex cache_mu;
     std::lock_guard<std::mutex> lock(cache_mu);
-    std::string key = std::to_string(c->ndim);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop{};
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    std::string key = std::string("v1/") + prop.gcnArchName + "/" + std::to_string(c->ndim);
     for (int i = 0; i < c->ndim; ++i) key += "x" + std::to_string(c->n[i]);
     key += "/f" + std::to_string(c->fields.size()) + "/i" + std::to_string(c->interms.size()) + "/t";
     for (const Term& t : c->terms) {
@@ -2435,6 +2493,42 @@ pss_status pss_autotune(pss_ctx* c, int32_t reps, double* us_per_step) {
         key += ",";
     }
     for (const auto& kv : c->tune) key += kv.first + "=" + std::to_string(kv.second);  // forced keys stay
+    for (char& ch : key)
+        if (std::isspace(static_cast<unsigned char>(ch))) ch = '_';
+    // PSS_TUNE_CACHE names a text file that keeps the choices across
+    // processes: one line per entry, "<key> <us per step> <k>=<v> ...", the
+    // last line of a key wins; lines that do not parse are skipped
+    const char* cache_file = std::getenv("PSS_TUNE_CACHE");
+    if (cache_file && *cache_file && !cache.count(key)) {
+        if (FILE* fp = std::fopen(cache_file, "r")) {
+            char line[1024];
+            while (std::fgets(line, sizeof line, fp)) {
+                char* save = nullptr;
+                const char* k = strtok_r(line, " \t\r\n", &save);
+                const char* us = strtok_r(nullptr, " \t\r\n", &save);
+                if (!k || !us || key != k) continue;
+                char* end = nullptr;
+                const double t = std::strtod(us, &end);
+                if (*end || !(t > 0) || !std::isfinite(t)) continue;
+                Tune tn;
+                bool ok = true;
+                while (const char* kv = strtok_r(nullptr, " \t\r\n", &save)) {
+                    const char* eq = std::strchr(kv, '=');
+                    const std::string name = eq ? std::string(kv, eq) : std::string();
+                    const long long v = eq ? std::strtoll(eq + 1, &end, 10) : 0;
+                    if (!eq || *end || v < 1 || v > 4096 ||
+                        (name != "tc" && name != "to" && name != "tz" && name != "rb" && name != "pu" &&
+                         name != "px" && name != "py")) {
+                        ok = false;
+                        break;
+                    }
+                    tn[name] = v;
+                }
+                if (ok) cache[key] = {tn, t};
+            }
+            std::fclose(fp);
+        }
+    }
     auto hit = cache.find(key);
     if (hit != cache.end()) {
         c->tune = hit->second.first;
@@ -2504,6 +2598,18 @@ pss_status pss_autotune(pss_ctx* c, int32_t reps, double* us_per_step) {
     c->tune = best;
     cache[key] = {best, tbest * 1e3};
     if (us_per_step) *us_per_step = tbest * 1e3;
+    if (cache_file && *cache_file) {
+        std::string line = key;
+        char us[64];
+        std::snprintf(us, sizeof us, " %.17g", tbest * 1e3);
+        line += us;
+        for (const auto& kv : best) line += " " + kv.first + "=" + std::to_string(kv.second);
+        line += "\n";
+        FILE* fp = std::fopen(cache_file, "a");
+        const bool ok = fp && std::fwrite(line.data(), 1, line.size(), fp) == line.size();
+        if (fp && std::fclose(fp) != 0) return fail(PSS_E_INVAL, "PSS_TUNE_CACHE: cannot write %s", cache_file);
+        if (!ok) return fail(PSS_E_INVAL, "PSS_TUNE_CACHE: cannot append to %s", cache_file);
+    }
     return PSS_OK;
 }
 
