@@ -1666,16 +1666,32 @@ __device__ __forceinline__ float2 small_root(int r, int k) {
     }
 }
 
+// floor(x / d) for 0 <= x < 2^21 and d >= 1, without an integer division:
+// (x + 1/2)/d lies at least 1/(2d) from an integer, and rounding 1/d and the
+// product moves it by less than 2^-22 (x + 1/2)/d, below 1/(2d) for such x,
+// so truncating the FP32 product gives the exact quotient
+struct FastDiv {
+    int d;
+    float rd;
+    __device__ __forceinline__ explicit FastDiv(int dv) : d(dv), rd(1.0f / static_cast<float>(dv)) {}
+    __device__ __forceinline__ int quo(int x) const {
+        return static_cast<int>((static_cast<float>(x) + 0.5f) * rd);
+    }
+};
+
 // One self-sorting pass of radix R over nl lines of N values (line l at
 // x + l N), sign sg = -1 (forward) or +1 (inverse): the radix-R transforms of
-// the current length n = m R, then the twiddles w_n^(j p).
+// the current length n = m R, then the twiddles w_n^(j p).  n s = N at every
+// pass, so j p s < N indexes the table directly.  Lines hold at most 2^21
+// values in all (they sit in LDS).
 template <int R>
 __device__ __forceinline__ void mr_pass(const float2* __restrict__ x, float2* __restrict__ y,
                                         const float2* __restrict__ tw, int N, int m, int s, int nl, float sg) {
     const int per = m * s;
+    const FastDiv fper(per), fs(s);
     for (int idx = threadIdx.x; idx < nl * per; idx += blockDim.x) {
-        const int line = idx / per, rem = idx - line * per;
-        const int q = rem % s, p = rem / s;
+        const int line = fper.quo(idx), rem = idx - line * per;
+        const int p = fs.quo(rem), q = rem - p * s;
         const float2* xl = x + static_cast<size_t>(line) * N;
         float2* yl = y + static_cast<size_t>(line) * N;
         float2 a[R];
@@ -1691,7 +1707,7 @@ __device__ __forceinline__ void mr_pass(const float2* __restrict__ x, float2* __
                 b = cadd(b, cmul(a[l], w));
             }
             if (j > 0) {
-                float2 w = tw[(j * p * s) % N];  // exp(-2 pi i j p s / N) = w_n^(j p)
+                float2 w = tw[j * p * s];  // exp(-2 pi i j p s / N) = w_n^(j p)
                 if (sg > 0.f) w.y = -w.y;
                 b = cmul(b, w);
             }
@@ -1967,8 +1983,12 @@ __global__ void __launch_bounds__(256)
     const int Nx = p.n[0], L = my.n, N1 = p.n[1];
     const bool d3 = p.n[2] > 1;
     const int nxb = Nx / tc;
-    const int kx0 = static_cast<int>(blockIdx.x % nxb) * tc;
-    const int ko = d3 ? static_cast<int>(blockIdx.x / nxb) : 0;  // ky of 3D lines
+    // XCD-ordered blocks: each XCD's L2 takes a contiguous range of columns,
+    // so the cache lines that neighbouring column blocks share are fetched
+    // into one L2, not into all eight
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int kx0 = (blk % nxb) * tc;
+    const int ko = d3 ? blk / nxb : 0;  // ky of 3D lines
     const int kos = ko < (N1 >> 1) ? ko : ko - N1;
     const size_t base = d3 ? static_cast<size_t>(ko) * Nx + kx0 : static_cast<size_t>(kx0);
     const size_t su = d3 ? static_cast<size_t>(Nx) * N1 : static_cast<size_t>(Nx);
@@ -1980,20 +2000,26 @@ __global__ void __launch_bounds__(256)
     float2* const S = B + n;          // [NF][tc][L]
     float2* const acc = S + NF * n;   // [NF][tc][L]
     for (int i = t; i < L; i += T) tw[i] = tw_g[i];
+    const FastDiv ftc(tc), fL(L);  // n < 2^21: the LDS holds the lines
     // global element of line c at position w; loads and stores run with the
     // line index fastest, so a wave touches neighbouring kx
     auto at = [&](int c, int w) { return base + c + static_cast<size_t>(w) * su; };
     auto gin = [&](const float2* __restrict__ src, float2* dst) {
         for (int i = t; i < n; i += T) {
-            const int c = i % tc, w = i / tc;
+            const int w = ftc.quo(i), c = i - w * tc;
             dst[c * L + w] = gload(src + at(c, w));
         }
     };
     auto gout = [&](const float2* src, float2* __restrict__ dst) {
         for (int i = t; i < n; i += T) {
-            const int c = i % tc, w = i / tc;
+            const int w = ftc.quo(i), c = i - w * tc;
             gstore(dst + at(c, w), src[c * L + w]);
         }
+    };
+    // line and position of LDS element i
+    auto lw = [&](int i, int& c, int& w) {
+        c = fL.quo(i);
+        w = i - c * L;
     };
     auto ws = [&](int w) { return w < (L >> 1) ? w : w - L; };
     auto kxs = [&](int c) { const int kx = kx0 + c; return kx < (Nx >> 1) ? kx : kx - Nx; };
@@ -2031,7 +2057,11 @@ __global__ void __launch_bounds__(256)
     };
 
     if constexpr (MODE == MODE_INTERM_OUT) {
-        for (int i = t; i < n; i += T) A[i] = source(PSS_MAXF + bufs.sel, i, kq(i / L, i % L));
+        for (int i = t; i < n; i += T) {
+            int c, w;
+            lw(i, c, w);
+            A[i] = source(PSS_MAXF + bufs.sel, i, kq(c, w));
+        }
         __syncthreads();
         const float2* r = mr_transform(A, B, tw, my, 1, tc);
         gout(r, bufs.out);
@@ -2048,7 +2078,9 @@ __global__ void __launch_bounds__(256)
             __syncthreads();
             const float2* r = mr_transform(A, B, tw, my, -1, tc);
             for (int i = t; i < n; i += T) {
-                const ModeQ q = kq(i / L, i % L);
+                int c, w;
+                lw(i, c, w);
+                const ModeQ q = kq(c, w);
                 for (int o = 0; o < C.nout; ++o) {
                     float2& d = acc[C.target[o] * n + i];
                     d = cadd(d, cmul(eval_op<GEN>(C.op[o], q), r[i]));
@@ -2057,8 +2089,10 @@ __global__ void __launch_bounds__(256)
             __syncthreads();
         }
         // linear explicit terms, then the semi-implicit update with the noise
-        for (int i = t; i < n; i += T) {
-            const ModeQ q = kq(i / L, i % L);
+        for (int i = t; i < n && p.nd > 0; i += T) {
+            int c, w;
+            lw(i, c, w);
+            const ModeQ q = kq(c, w);
             for (int d = 0; d < p.nd; ++d) {
                 const DevDirect& Dd = p.direct[d];
                 float2& a = acc[Dd.target * n + i];
@@ -2068,12 +2102,15 @@ __global__ void __launch_bounds__(256)
         __syncthreads();
         uint32_t bad = 0;
         for (int i = t; i < n; i += T) {
-            const int c = i / L, w = i % L, kx = kx0 + c;
+            int c, w;
+            lw(i, c, w);
+            const int kx = kx0 + c;
             const ModeQ q = kq(c, w);
             const uint32_t lin = static_cast<uint32_t>(at(c, w));
-            const size_t neg_line = d3 ? static_cast<size_t>((L - w) % L) * N1 + static_cast<size_t>((N1 - ko) % N1)
-                                       : static_cast<size_t>((L - w) % L);
-            const uint32_t lneg = static_cast<uint32_t>(neg_line * Nx + static_cast<size_t>((Nx - kx) % Nx));
+            // the linear index of the mode -k (each index modulo its size)
+            const size_t wn = w ? L - w : 0;
+            const size_t neg_line = d3 ? wn * N1 + static_cast<size_t>(ko ? N1 - ko : 0) : wn;
+            const uint32_t lneg = static_cast<uint32_t>(neg_line * Nx + static_cast<size_t>(kx ? Nx - kx : 0));
             for (int f = 0; f < nf; ++f) {
                 float2 r = cadd(S[f * n + i], cscale(acc[f * n + i], p.dt));
                 if (p.noisy[f] != 0) r = cadd(r, noise_mode<GEN>(p, f, step, lin, lneg, q));
@@ -2092,7 +2129,8 @@ __global__ void __launch_bounds__(256)
     for (int g = 0; g < p.ng; ++g) {
         const DevMask& mk = p.mask[g];
         for (int i = t; i < n; i += T) {
-            const int c = i / L, w = i % L;
+            int c, w;
+            lw(i, c, w);
             A[i] = (d3 ? mask_keep(mk, kxs(c), kos, ws(w)) : mask_keep(mk, kxs(c), ws(w), 0))
                        ? source(p.gfield[g], i, kq(c, w))
                        : make_float2(0.f, 0.f);
@@ -2171,23 +2209,25 @@ __global__ void __launch_bounds__(256)
     const DevPlan& p = *plan;
     const int Nx = p.n[0], Ny = my.n;
     const int nxb = Nx / tc;
-    const int kx0 = static_cast<int>(blockIdx.x % nxb) * tc, z = static_cast<int>(blockIdx.x / nxb);
+    const int blk = xcd_block(blockIdx.x, gridDim.x);  // as in the column kernel
+    const int kx0 = (blk % nxb) * tc, z = blk / nxb;
     const size_t base = static_cast<size_t>(z) * Nx * Ny + kx0;
     const int t = threadIdx.x, T = blockDim.x;
     const int n = tc * Ny;
+    const FastDiv ftc(tc);
     float2* const tw = smem;
     float2* const A = smem + Ny;
     float2* const B = A + n;
     for (int i = t; i < Ny; i += T) tw[i] = tw_g[i];
     for (int a = 0; a < ya.n; ++a) {
         for (int i = t; i < n; i += T) {
-            const int c = i % tc, y = i / tc;
+            const int y = ftc.quo(i), c = i - y * tc;
             A[c * Ny + y] = gload(ya.src[a] + base + c + static_cast<size_t>(y) * Nx);
         }
         __syncthreads();
         const float2* r = mr_transform(A, B, tw, my, sign, tc);
         for (int i = t; i < n; i += T) {
-            const int c = i % tc, y = i / tc;
+            const int y = ftc.quo(i), c = i - y * tc;
             gstore(ya.dst[a] + base + c + static_cast<size_t>(y) * Nx, r[c * Ny + y]);
         }
         __syncthreads();

@@ -709,18 +709,16 @@ pss_status choose_geometry(pss_ctx* c) {
     }
     if (c->mixed) {
         // spectra in LDS, one block per x row; the column launch (and the 3D
-        // y pass) takes tc lines of neighbouring kx per block, so that its
-        // strided global accesses read and write tc neighbouring elements
-        // together: the largest of 8, 4, 2, 1 that divides Nx and fits
+        // y pass) takes tc lines of neighbouring kx per block.  One line per
+        // block is the default: the blocks are XCD-ordered, so neighbouring
+        // columns share their cache lines in one L2, and the smaller LDS
+        // footprint keeps more blocks per CU (960^2 Model B: 54.2, 56.7 and
+        // 73.5 us per step at tc = 1, 2, 4)
         c->lu = c->ndim == 3 ? nz : ny;
         const int NF = nf <= 1 ? 1 : (nf == 2 ? 2 : 4);
-        auto pick_tc = [&](auto bytes) {
-            for (int tc : {8, 4, 2, 1})
-                if (nx % tc == 0 && bytes(tc) <= 160 * 1024) return tc;
-            return 0;
-        };
-        g.tc = pick_tc([&](int tc) { return pss::mr2_col_lds_bytes(c->lu, NF, tc); });
-        g.py = c->ndim == 3 ? pick_tc([&](int tc) { return pss::mr3_ypass_lds_bytes(ny, tc); }) : 1;
+        auto fits1 = [&](auto bytes) { return bytes(1) <= 160 * 1024 ? 1 : 0; };
+        g.tc = fits1([&](int tc) { return pss::mr2_col_lds_bytes(c->lu, NF, tc); });
+        g.py = c->ndim == 3 ? fits1([&](int tc) { return pss::mr3_ypass_lds_bytes(ny, tc); }) : 1;
         // pss_tuning_set may force either (a divisor of Nx that fits)
         auto forced = [&](const char* key, int& v, auto bytes) {
             auto it = c->tune.find(key);
