@@ -267,6 +267,19 @@ __device__ __forceinline__ void mode_lin(const DevPlan& p, int kx, int ky, int k
     lneg = lin_index(p, (nx - ux) & (nx - 1), (ny - uy) & (ny - 1), (nz - uz) & (nz - 1));
 }
 
+// f(integral_constant<int, I>) for I = 0 .. N-1, unrolled at compile time
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for_from(F& f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for_from<I + 1, N>(f);
+    }
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_from<0, N>(f);
+}
+
 // Element f of a register array, f a runtime (block-uniform) field index.
 // Written with bit masks rather than a chain of conditional copies: the
 // compiler folds such a chain back into an indexed access, which moves the
@@ -767,10 +780,13 @@ __device__ __forceinline__ void update_block(int mi, int blk, const Member* __re
             if (pair_lane) pair_accumulate<DIM, GEN>(acc, Dd.target, src, p, Dd.op, ky_l, L);
         }
         // semi-implicit update (eq:timeupdate) with in-register noise
+        // fields unrolled by template: a loop that the compiler leaves rolled
+        // (the general-operator bodies are large) indexes s and acc at run
+        // time, which moves both arrays to scratch memory
         uint32_t bad = 0;
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            if (f >= nf) continue;
+        static_for<NF>([&](auto FF) {
+            constexpr int f = decltype(FF)::value;
+            if (f >= nf) return;
             const bool noisy = p.noisy[f] != 0;
             const float2 old0 = s[f][0], oldh = s[f][P / 2];
             float Ar[P];
@@ -799,7 +815,7 @@ __device__ __forceinline__ void update_block(int mi, int blk, const Member* __re
                 fin = fin && __builtin_isfinite(s[f][m].x) && __builtin_isfinite(s[f][m].y);
             }
             if (!fin) bad |= 1u << f;  // a NaN or infinity in the new state
-        }
+        });
         if (bad) {
             if constexpr (TAB) {
                 atomicOr(mem->flag, bad);
