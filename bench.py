@@ -485,13 +485,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="default workload: leave out the ensemble and adjoint measurements")
-    ap.add_argument("--workload", choices=("modelb1024", "ensemble", "adjoint", "3d", "modelh"),
+    ap.add_argument("--workload", choices=("modelb1024", "ensemble", "adjoint", "3d", "modelh", "mixed"),
                     default="modelb1024",
                     help="modelb1024: one 1024^2 lattice, with the ensemble and adjoint measurements "
                          "(default); ensemble: 256x128^2 + 64x256^2 + 16x512^2 independent lattices in one "
                          "batch, also timed one lattice per launch; adjoint: gradient of the structure-factor "
                          "loss through 2000 steps at 256^2; 3d: the two-field 256^3 system; modelh: 2D "
-                         "Model H at 1024^2")
+                         "Model H at 1024^2; mixed: 2D Model B at 960^2 (mixed-radix sizes)")
     ap.add_argument("--autotune", dest="autotune", action="store_true",
                     help="ensemble: pss_autotune's launch geometry per size instead of the default one (a class "
                          "whose tuned geometry does not fit the fused launches then runs launches of its own)")
@@ -546,6 +546,16 @@ def main():
                "lattice": [1024, 1024], "parallelism": "single GPU", "geometry": h["geometry"]}
         print(json.dumps(line(cfg, h["value"], h["steps"], h["warmup"], h["ms_per_step"],
                               {"roofline": h["roofline"], "cpu_baseline": h["cpu_baseline"]})), flush=True)
+        return
+
+    if args.workload == "mixed":
+        x = mixed_radix(args, pss, torch)
+        cfg = {"workload": "2D Model B 960x960 FP32 (960 = 2^6 3 5: full spectra, radix-4/2/3/5 passes), a=-1 "
+                           "b=1 k=1, conserved noise D=0.01 q^2, dt=0.01, 2/3 radial de-aliasing",
+               "lattice": x["lattice"], "parallelism": "single GPU"}
+        print(json.dumps(line(cfg, x["value"], x["steps"], min(args.warmup, 20), x["ms_per_step"],
+                              {"step_bytes": x["step_bytes"], "step_GBs": x["step_GBs"], "roofline": None,
+                               "cpu_baseline": None})), flush=True)
         return
 
     m = modelb1024(args, pss, torch)
