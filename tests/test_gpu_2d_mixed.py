@@ -110,3 +110,31 @@ def test_chunking_is_bitwise_and_refusals():
     with pytest.raises(PssError) as e:
         pss.Batch([a, b])
     assert e.value.name == "PSS_E_UNSUPPORTED"
+
+
+def test_lines_per_block_are_bitwise_and_checked():
+    # pss_tuning_set "tc": neighbouring column lines per block only regroup
+    # the same per-line arithmetic
+    n = (120, 96)
+
+    def run(tc):
+        lat = pss.Lattice(n, dt=0.01, seed=8)
+        f, _ = pss.model_b(lat, D=0.02)
+        if tc:
+            lat.tune(tc=tc)
+        lat.init_uniform(f, -0.2, 0.2)
+        lat.step(40)
+        return lat.geometry()["tc"], lat.spectrum(f)
+
+    tc0, ref = run(None)
+    assert tc0 == 1
+    for tc in (2, 3, 8):
+        got_tc, sp = run(tc)
+        assert got_tc == tc
+        assert np.array_equal(sp, ref), tc
+    lat = pss.Lattice(n, dt=0.01, seed=8)
+    pss.model_b(lat)
+    lat.tune(tc=7)  # not a divisor of Nx
+    with pytest.raises(PssError) as e:
+        lat.init_uniform(0, -0.1, 0.1)
+    assert e.value.name == "PSS_E_UNSUPPORTED"

@@ -95,3 +95,26 @@ def test_model_h_matches_oracle():
     m.step(steps)
     for i, fid in enumerate(tuple(ids) + tuple(grads)):
         assert _close(lat.download(fid), m.real(i), floor=1.0 if i == 0 else 0.0), i
+
+
+def test_lines_per_block_are_bitwise():
+    # "tc" (z lines per column block) and "py" (y lines per y-pass block)
+    # regroup the same per-line arithmetic
+    n = (24, 20, 12)
+
+    def run(**kw):
+        lat = pss.Lattice(n, dt=0.01, seed=9)
+        f, _ = pss.model_b(lat, D=0.02)
+        if kw:
+            lat.tune(**kw)
+        lat.init_uniform(f, -0.2, 0.2)
+        lat.step(20)
+        g = lat.geometry()
+        return (g["tc"], g["py"]), lat.spectrum(f)
+
+    g0, ref = run()
+    assert g0 == (1, 1)
+    for kw in (dict(tc=2), dict(py=4), dict(tc=3, py=6), dict(tc=8, py=2)):
+        g, sp = run(**kw)
+        assert g == (kw.get("tc", 1), kw.get("py", 1))
+        assert np.array_equal(sp, ref), kw
