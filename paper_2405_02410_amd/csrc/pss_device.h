@@ -151,6 +151,17 @@ __device__ __forceinline__ void gstore(float2* p, float2 v) {
     *q = __builtin_bit_cast(double, v);
 }
 __device__ __forceinline__ uint64_t gload_u64(const uint64_t* p) { return *(const pss_gu64*)(p); }
+// two neighbouring float2 in one 16-byte load (p 16-byte aligned).  Loaded
+// as four floats: the same load typed as two doubles and split by bit casts
+// compiled here to overlapping destination registers for loads in flight,
+// which dropped the second element (caught by the parity tests)
+typedef float pss_fvec4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) pss_fvec4 pss_gfvec4;
+__device__ __forceinline__ void gload_pair(const float2* p, float2& a, float2& b) {
+    const pss_fvec4 v = *(const pss_gfvec4*)(p);
+    a = make_float2(v.x, v.y);
+    b = make_float2(v.z, v.w);
+}
 
 // ------------------------------------------------------------ block order
 // The hardware hands out the blocks of a grid round-robin over the 8 XCDs

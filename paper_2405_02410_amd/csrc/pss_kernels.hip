@@ -1238,14 +1238,27 @@ __device__ __forceinline__ void xrow_block(int mi, int blk, const Member* __rest
         // all loads first, without control flow between them; a dropped
         // column reads column 0 and then counts as zero
         float2 a[P], b[P];
+        if (tc == 1) {
+            // one-column tiles: the pair's two rows are neighbours, and the
+            // row pair starts at an even row, so one aligned 16-byte load
+            // takes both (half the address work of two 8-byte loads)
 #pragma unroll
-        for (int m = 0; m < P; ++m) {
-            const int k = dr + m * T;
-            const int kk = (k == NC) ? 0 : (k < NC ? k : L - k);
-            const int kc = kk < ncol ? kk : 0;
-            const size_t off = row0 + (kc >> lt) * tstride + (kc & (tc - 1));
-            a[m] = gload(src + off);
-            b[m] = gload(src + off + tc);
+            for (int m = 0; m < P; ++m) {
+                const int k = dr + m * T;
+                const int kk = (k == NC) ? 0 : (k < NC ? k : L - k);
+                const int kc = kk < ncol ? kk : 0;
+                gload_pair(src + row0 + kc * tstride, a[m], b[m]);
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < P; ++m) {
+                const int k = dr + m * T;
+                const int kk = (k == NC) ? 0 : (k < NC ? k : L - k);
+                const int kc = kk < ncol ? kk : 0;
+                const size_t off = row0 + (kc >> lt) * tstride + (kc & (tc - 1));
+                a[m] = gload(src + off);
+                b[m] = gload(src + off + tc);
+            }
         }
 #pragma unroll
         for (int m = 0; m < P; ++m) {
