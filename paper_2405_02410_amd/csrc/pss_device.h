@@ -151,6 +151,19 @@ __device__ __forceinline__ void gstore(float2* p, float2 v) {
     *q = __builtin_bit_cast(double, v);
 }
 __device__ __forceinline__ uint64_t gload_u64(const uint64_t* p) { return *(const pss_gu64*)(p); }
+// A store marked non-temporal (NT): the line is not kept dirty in this XCD's
+// L2, so the kernel's end has less to write back.  The step kernels of one
+// lattice store this way (the next kernel reads the array from other XCDs);
+// batched launches measured faster with plain stores.
+template <bool NT>
+__device__ __forceinline__ void gstore_sel(float2* p, float2 v) {
+    pss_gdouble* q = (pss_gdouble*)(p);
+    if constexpr (NT) {
+        __builtin_nontemporal_store(__builtin_bit_cast(double, v), q);
+    } else {
+        *q = __builtin_bit_cast(double, v);
+    }
+}
 // two neighbouring float2 in one 16-byte load (p 16-byte aligned).  Loaded
 // as four floats: the same load typed as two doubles and split by bit casts
 // compiled here to overlapping destination registers for loads in flight,

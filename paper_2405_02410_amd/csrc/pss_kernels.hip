@@ -811,7 +811,7 @@ __device__ __forceinline__ void update_block(int mi, int blk, const Member* __re
             bool fin = true;
 #pragma unroll
             for (int m = 0; m < P; ++m) {
-                gstore(bufs.S[f] + base + (t + m * T) * tc, s[f][m]);
+                gstore_sel<!TABLE>(bufs.S[f] + base + (t + m * T) * tc, s[f][m]);
                 fin = fin && __builtin_isfinite(s[f][m].x) && __builtin_isfinite(s[f][m].y);
             }
             if (!fin) bad |= 1u << f;  // a NaN or infinity in the new state
@@ -854,7 +854,7 @@ __device__ __forceinline__ void update_block(int mi, int blk, const Member* __re
         exchange(v, false);
         FFT::template dif<1>(v, ld, t, tw);
 #pragma unroll
-        for (int m = 0; m < P; ++m) gstore(bufs.V[g] + vbase + (t + m * T) * vstride, v[m]);
+        for (int m = 0; m < P; ++m) gstore_sel<!TABLE>(bufs.V[g] + vbase + (t + m * T) * vstride, v[m]);
     }
 }
 
@@ -1307,7 +1307,7 @@ __device__ __forceinline__ void xrow_block(int mi, int blk, const Member* __rest
                 o = (r & 1) ? make_float2(0.5f * (a.y + b.y), 0.5f * (b.x - a.x))
                             : make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
             }
-            gstore(dst + ((sbase + static_cast<size_t>(tl) * ny + r) << lt) + cc, o);
+            gstore_sel<!TABLE>(dst + ((sbase + static_cast<size_t>(tl) * ny + r) << lt) + cc, o);
         }
     };
 
