@@ -466,6 +466,49 @@ def mixed_radix(args, pss, torch):
             "step_GBs": round(step_bytes / (ms * 1e-3) / 1e9, 1)}
 
 
+def features(args, pss, torch):
+    """Step rates of the other model forms at fixed sizes, each timed like the
+    main workload (HIP events on the lattice stream, median of REPEATS runs):
+    1D Model B lines of 4096 (radix 4) and 3000 (2^3 3 5^3, mixed radix)
+    points, one block each; 2D Model B at 1024^2 with a boundary frame of 4
+    columns held at 0.2 (each step also transforms the framed field to real
+    space and back); 2D KPZ at 1024^2 (two gradient intermediates)."""
+    out = {}
+
+    def timed(name, lat, steps, warm):
+        stream = torch.cuda.Stream()
+        lat.stream(stream.cuda_stream)
+        lat.prepare(warm)
+        lat.prepare(steps)
+        lat.step(warm)
+        lat.sync()
+        times = timed_runs(torch, stream, lambda: lat.step(steps))
+        el = statistics.median(times)
+        sites = 1
+        for v in lat.n:
+            sites *= v
+        out[name] = {"lattice": list(lat.n), "steps": steps, "us_per_step": round(1e6 * el / steps, 3),
+                     "site_steps_per_s": sites * steps / el}
+        log(f"bench: {name} {1e6 * el / steps:.2f} us/step, {sites * steps / el:.4e} site-steps/s")
+
+    for n in (4096, 3000):
+        lat = pss.Lattice((n,), dt=DT, seed=SEED)
+        f, _ = pss.model_b(lat, a=A, b=B, k=K, D=D)
+        lat.init_uniform(f, -0.1, 0.1)
+        timed(f"line_{n}", lat, 2000, 200)
+    lat = pss.Lattice(N, dt=DT, seed=SEED)
+    f, _ = pss.model_b(lat, a=A, b=B, k=K, D=D)
+    lat.init_uniform(f, -0.1, 0.1)
+    sites = [y * N[0] + x for y in range(N[1]) for x in range(4)]
+    lat.frame(f, sites, [0.2] * len(sites))
+    timed("frame_1024", lat, 500, 50)
+    lat = pss.Lattice(N, dt=DT, seed=SEED)
+    f, _ = pss.kpz(lat, sigma=1.0, lam=1.0, D=D)
+    lat.init_uniform(f, -0.1, 0.1)
+    timed("kpz_1024", lat, 500, 50)
+    return out
+
+
 def line(workload, value, steps, warmup, ms_per_step, extra):
     out = {"metric": "site-steps/s", "value": value, "unit": "site-steps/s", "n_gpus": 1,
            "steps": steps, "warmup": warmup, "ms_per_step": ms_per_step,
@@ -485,13 +528,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="default workload: leave out the ensemble and adjoint measurements")
-    ap.add_argument("--workload", choices=("modelb1024", "ensemble", "adjoint", "3d", "modelh", "mixed"),
+    ap.add_argument("--workload", choices=("modelb1024", "ensemble", "adjoint", "3d", "modelh", "mixed", "features"),
                     default="modelb1024",
                     help="modelb1024: one 1024^2 lattice, with the ensemble and adjoint measurements "
                          "(default); ensemble: 256x128^2 + 64x256^2 + 16x512^2 independent lattices in one "
                          "batch, also timed one lattice per launch; adjoint: gradient of the structure-factor "
                          "loss through 2000 steps at 256^2; 3d: the two-field 256^3 system; modelh: 2D "
-                         "Model H at 1024^2; mixed: 2D Model B at 960^2 (mixed-radix sizes)")
+                         "Model H at 1024^2; mixed: 2D Model B at 960^2 (mixed-radix sizes); features: 1D lines, "
+                         "a framed 1024^2 lattice and 2D KPZ")
     ap.add_argument("--autotune", dest="autotune", action="store_true",
                     help="ensemble: pss_autotune's launch geometry per size instead of the default one (a class "
                          "whose tuned geometry does not fit the fused launches then runs launches of its own)")
@@ -548,6 +592,15 @@ def main():
                               {"roofline": h["roofline"], "cpu_baseline": h["cpu_baseline"]})), flush=True)
         return
 
+    if args.workload == "features":
+        x = features(args, pss, torch)
+        cfg = {"workload": "1D Model B lines of 4096 and 3000 points; 2D Model B 1024^2 with a 4-column frame; "
+                           "2D KPZ 1024^2 (sigma=1, lam=1, D=0.01); coefficients of the main workload",
+               "parallelism": "single GPU"}
+        first = x["line_4096"]
+        print(json.dumps(line(cfg, first["site_steps_per_s"], first["steps"], 200, first["us_per_step"] * 1e-3,
+                              {"features": x, "roofline": None, "cpu_baseline": None})), flush=True)
+        return
     if args.workload == "mixed":
         x = mixed_radix(args, pss, torch)
         cfg = {"workload": "2D Model B 960x960 FP32 (960 = 2^6 3 5: full spectra, radix-4/2/3/5 passes), a=-1 "
