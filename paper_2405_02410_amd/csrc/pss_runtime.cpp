@@ -1163,8 +1163,13 @@ pss_status enqueue_steps(pss_ctx* c, int64_t k) {
         HIP_TRY(pss::launch_line1d(pss::MODE_STEP, c->n[0], nf, a));
         return debug_check(c, "line1d_kernel", c->steps_taken);
     }
+    // A framed lattice rebuilds every step's factors and products from the
+    // framed state (the prologue after the frames), so its steps run only the
+    // update launch: the product launches of the unframed state would be
+    // overwritten unread.
+    const bool framed = has_frames(c);
     // in 2D the last x kernel of the sequence moves the step counter on
-    const bool x_advances = c->ndim == 2 && c->plan.nch > 0;
+    const bool x_advances = c->ndim == 2 && c->plan.nch > 0 && !framed;
     for (int64_t i = 0; i < k; ++i) {
         pss::LaunchArgs a = args(c, static_cast<int>(i));
         const int64_t at = c->steps_taken + i;
@@ -1175,7 +1180,7 @@ pss_status enqueue_steps(pss_ctx* c, int64_t k) {
     } while (0)
         if (c->mixed) {
             PSS_CHECKED(pss::launch_mr2_col(pss::MODE_STEP, nf, a), "mr2_col_kernel");
-            if (c->plan.nch > 0) {
+            if (c->plan.nch > 0 && !framed) {
                 if (c->ndim == 3) PSS_CHECKED(mr_ypass(c, 1, c->d_v.data(), c->plan.ng), "mr3_ypass_kernel(inverse)");
                 a.advance = (x_advances && i == k - 1) ? k : 0;
                 PSS_CHECKED(pss::launch_mr2_row(pss::MODE_STEP, a), "mr2_row_kernel");
@@ -1184,7 +1189,7 @@ pss_status enqueue_steps(pss_ctx* c, int64_t k) {
             }
         } else {
             PSS_CHECKED(pss::launch_update(pss::MODE_STEP, c->lu, nf, a), "update_kernel");
-            if (c->plan.nch > 0) {
+            if (c->plan.nch > 0 && !framed) {
                 if (c->ndim == 3) PSS_CHECKED(y_inverse_factors(c), "ypass_kernel(inverse)");
                 pss::LaunchArgs ax = xargs(c);
                 ax.advance = (x_advances && i == k - 1) ? k : 0;
@@ -1193,7 +1198,7 @@ pss_status enqueue_steps(pss_ctx* c, int64_t k) {
             }
         }
 #undef PSS_CHECKED
-        if (has_frames(c)) {
+        if (framed) {
             // boundary frames: each framed field through real space, then the
             // factors and channels of the next step from the framed state
             for (int f = 0; f < nf; ++f) {
