@@ -117,3 +117,26 @@ def test_framed_lattices_stay_out_of_batches_and_the_adjoint():
         lat.frame(f, [0], [1.0])
     assert e.value.name == "PSS_E_STATE"
     b.close()
+
+
+@pytest.mark.parametrize("n", [(64, 32), (16, 16, 16)])
+def test_framed_steps_chunk_bitwise(n):
+    # a framed step runs the update launch, the frame and the rebuilt
+    # products; the step counter then moves on once per chunk
+    nx = n[0]
+    sites = np.array([i for i in range(int(np.prod(n))) if (i % nx) < 2])
+    values = np.full(sites.size, -0.3, dtype=np.float32)
+
+    def mk():
+        lat = pss.Lattice(n, dt=0.01, seed=13)
+        f, _ = pss.model_b(lat, D=0.02)
+        lat.init_uniform(f, -0.1, 0.1)
+        lat.frame(f, sites, values)
+        return lat
+
+    a, b = mk(), mk()
+    a.step(75)
+    for k in (10, 50, 15):
+        b.step(k)
+    assert a.step_index == b.step_index == 75
+    assert np.array_equal(a.spectrum(0), b.spectrum(0))
